@@ -1,0 +1,281 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each pin is independent of the oracle's own arithmetic: closed forms written
+from the state parameters (not from the covariance matrix), exact invariants of
+a probability distribution, the paper's own sequential algorithm (Sec. II,
+fixed outcomes as in Sec. III "Runtime"), and mpmath at high precision.
+A mutation test (at the end) plants plausible mistakes in a copy of the oracle
+and checks that every mutant fails at least one pin.
+"""
+import itertools
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import gbs_inputs as gi
+import oracle
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def _pat(*v):
+    return np.array(v, dtype=np.int8)
+
+
+# --------------------------------------------------------------------------
+# pins, written so they can run against any build of the oracle library
+# --------------------------------------------------------------------------
+
+def pin_vacuum(lib=None):
+    """Vacuum: no clicks with probability 1, any click pattern exactly 0."""
+    cov = 0.5 * np.eye(10)
+    for route in (oracle.formP, oracle.formS):
+        assert route(cov, _pat(0, 0, 0, 0, 0), lib_path=lib).p == 1.0
+        assert route(cov, _pat(-1, 0, -1, 0, -1), lib_path=lib).p == 1.0
+        for pat in ([1, 0, 0, 0, 0], [1, 1, -1, 0, 1], [1, 1, 1, 1, 1]):
+            assert route(cov, np.array(pat, np.int8), lib_path=lib).p == 0.0
+
+
+def pin_single_mode(lib=None):
+    """Squeezed (thermal) single mode: P(no click) = 1/sqrt(det sigma_Q) with the
+    closed form det = (nbar+1/2)^2 + (nbar+1/2) cosh 2r + 1/4, which is cosh^2 r
+    for a pure squeezed vacuum (q_k of Eq. (prob) at zero mean)."""
+    for r, phi, nbar in [(0.6, 0.0, 0.0), (0.3, 1.1, 0.0), (1.2, 2.0, 0.0),
+                         (0.0, 0.0, 0.7), (0.5, 0.4, 0.3)]:
+        cov = gi.single_mode_covariance(r, phi, nbar)
+        det = (nbar + 0.5) ** 2 + (nbar + 0.5) * np.cosh(2 * r) + 0.25
+        pvac = 1.0 / np.sqrt(det)
+        for route in (oracle.formP, oracle.formS):
+            assert route(cov, _pat(0), lib_path=lib).p == pytest.approx(pvac, rel=1e-15)
+            assert route(cov, _pat(1), lib_path=lib).p == pytest.approx(1 - pvac, rel=1e-14)
+    # pure squeezed vacuum: P(click) = 1 - 1/cosh r
+    for r in (0.1, 0.6, 0.92, 1.5):
+        cov = gi.single_mode_covariance(r)
+        assert oracle.formP(cov, _pat(1), lib_path=lib).p == pytest.approx(1 - 1 / np.cosh(r), rel=1e-14)
+
+
+def pin_thermal(lib=None):
+    """Thermal state: P(vac) = 1/(1 + nbar) per mode, independent modes."""
+    nb = np.array([0.2, 1.5, 0.05])
+    cov = gi.thermal_covariance(nb)
+    q = 1.0 / (1.0 + nb)
+    assert oracle.formP(cov, _pat(0, 0, 0), lib_path=lib).p == pytest.approx(np.prod(q), rel=1e-15)
+    assert oracle.formS(cov, _pat(1, 0, 1), lib_path=lib).p == pytest.approx(
+        (1 - q[0]) * q[1] * (1 - q[2]), rel=1e-14)
+
+
+def _product_closed_form(params, pattern):
+    p = 1.0
+    for (r, phi, nbar), v in zip(params, pattern):
+        det = (nbar + 0.5) ** 2 + (nbar + 0.5) * np.cosh(2 * r) + 0.25
+        q = 1.0 / np.sqrt(det)
+        if v == 1:
+            p *= 1 - q
+        elif v == 0:
+            p *= q
+    return p
+
+
+def pin_product(lib=None, m=7, seed=3):
+    """Product states factorise: p = prod_C (1 - q_i) prod_N q_j."""
+    rng = np.random.default_rng(seed)
+    params = [(rng.uniform(0.1, 1.0), rng.uniform(0, np.pi), rng.uniform(0, 0.5)) for _ in range(m)]
+    cov = gi.direct_sum([gi.single_mode_covariance(*p) for p in params])
+    for _ in range(6):
+        pat = rng.integers(-1, 2, size=m).astype(np.int8)
+        want = _product_closed_form(params, pat)
+        for route in (oracle.formP, oracle.formS):
+            assert route(cov, pat, lib_path=lib).p == pytest.approx(want, rel=1e-13, abs=1e-300)
+
+
+def pin_tmsv(lib=None):
+    """Two-mode squeezed vacuum: photon numbers are perfectly correlated, so
+    P(click, no click) = 0, P(no click, no click) = 1/cosh^2 r,
+    P(click, click) = 1 - 1/cosh^2 r, and one mode alone is thermal with
+    nbar = sinh^2 r, P(click) = tanh^2 r."""
+    for r in (0.3, 0.7, 1.1):
+        cov = gi.tmsv_covariance(r)
+        for route in (oracle.formP, oracle.formS):
+            # the FP64 input is a TMSV only to ~1e-16, so "0" is ~1e-16
+            assert abs(route(cov, _pat(1, 0), lib_path=lib).p) < 1e-15
+            assert abs(route(cov, _pat(0, 1), lib_path=lib).p) < 1e-15
+            assert route(cov, _pat(0, 0), lib_path=lib).p == pytest.approx(1 / np.cosh(r) ** 2, rel=1e-14)
+            assert route(cov, _pat(1, 1), lib_path=lib).p == pytest.approx(1 - 1 / np.cosh(r) ** 2, rel=1e-14)
+            assert route(cov, _pat(1, -1), lib_path=lib).p == pytest.approx(np.tanh(r) ** 2, rel=1e-14)
+
+
+def pin_normalisation(lib=None, m=8, seed=1):
+    """The 2^m click patterns of a state form a distribution: they sum to 1."""
+    cov = gi.state_config1(seed) if m == 8 else gi.gbs_covariance(
+        gi.haar_unitary(m, np.random.default_rng(seed)),
+        np.random.default_rng(seed + 100).uniform(0.3, 1.0, m))
+    tot = 0.0
+    for bits in itertools.product((0, 1), repeat=m):
+        p = oracle.formP(cov, np.array(bits, np.int8), lib_path=lib).p
+        assert p >= -1e-15
+        tot += p
+    assert tot == pytest.approx(1.0, abs=1e-13)
+
+
+def pin_paper_algorithm(lib=None, seed=5):
+    """The paper's sequential update rule (Sec. II) with fixed outcomes gives
+    the same pattern probability as the subset sum."""
+    rng = np.random.default_rng(seed)
+    m = 5
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.3, 1.0, m))
+    for pat in ([1, 1, 1, 1, 1], [1, 0, 1, -1, 0], [0, 1, -1, 1, 1], [-1, -1, 1, 0, 1]):
+        pat = np.array(pat, np.int8)
+        want = float(oracle.prob_sequential(cov, pat, dps=40))
+        for route in (oracle.formP, oracle.formS):
+            assert route(cov, pat, lib_path=lib).p == pytest.approx(want, rel=1e-13)
+
+
+PINS = [pin_vacuum, pin_single_mode, pin_thermal, pin_product, pin_tmsv,
+        pin_normalisation, pin_paper_algorithm]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=lambda f: f.__name__)
+def test_pin(pin, oracle_lib):
+    pin()
+
+
+# --------------------------------------------------------------------------
+# further invariants and cross-route checks
+# --------------------------------------------------------------------------
+
+def test_normalisation_m10(oracle_lib):
+    pin_normalisation(m=10, seed=7)
+
+
+def test_marginal_consistency(oracle_lib):
+    """p(C, N; j unobserved) = p(C + j, N) + p(C, N + j) (the POVM elements of
+    one mode sum to the identity)."""
+    rng = np.random.default_rng(11)
+    cov = gi.gbs_covariance(gi.haar_unitary(9, rng), rng.uniform(0.3, 1.0, 9))
+    for _ in range(8):
+        pat = rng.integers(-1, 2, size=9).astype(np.int8)
+        j = int(rng.integers(9))
+        pat[j] = -1
+        a = pat.copy(); a[j] = 1
+        b = pat.copy(); b[j] = 0
+        lhs = oracle.formP(cov, pat)
+        rhs = oracle.formP(cov, a).p + oracle.formP(cov, b).p
+        assert lhs.p == pytest.approx(rhs, rel=1e-13)
+
+
+def test_permutation_invariance(oracle_lib):
+    """Relabelling modes (both quadratures together) leaves p unchanged."""
+    rng = np.random.default_rng(12)
+    m = 8
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.3, 1.0, m))
+    pat = np.array([1, 1, 0, -1, 1, 0, 1, -1], np.int8)
+    perm = rng.permutation(m)
+    q = np.empty(2 * m, np.int64)
+    q[0::2] = 2 * perm
+    q[1::2] = 2 * perm + 1
+    cov2 = np.ascontiguousarray(cov[np.ix_(q, q)])
+    pat2 = pat[perm]
+    assert oracle.formP(cov2, pat2).p == pytest.approx(oracle.formP(cov, pat).p, rel=1e-14)
+    assert oracle.formS(cov2, pat2).p == pytest.approx(oracle.formS(cov, pat).p, rel=1e-14)
+
+
+def test_routes_agree_mpmath(oracle_lib):
+    """Definition (binary128), conditioned route, mpmath definition, mpmath
+    Torontonian form and the paper's algorithm agree."""
+    cov = gi.state_config1()
+    for pat in ([1] * 8, [1, 0, 1, 1, 0, -1, 1, 0], [0, 0, 1, -1, -1, 1, 0, 1]):
+        pat = np.array(pat, np.int8)
+        a = oracle.formP(cov, pat)
+        b = oracle.formS(cov, pat)
+        c = oracle.prob_mp(cov, pat, dps=50)
+        d = oracle.prob_torontonian_mp(cov, pat, dps=50)
+        e = oracle.prob_sequential(cov, pat, dps=50)
+        ref = float(c)
+        assert abs(float(d - c)) < 1e-40
+        assert abs(float(e - c)) < 1e-40
+        # binary128 with cancellation ratio R: error ~ R * 1e-33
+        assert abs((a.p + a.p_lo) - ref) <= 1e-28 * abs(ref) * a.cancel_ratio
+        assert abs((b.p + b.p_lo) - ref) <= 1e-28 * abs(ref) * b.cancel_ratio
+
+
+def test_product_state_many_clicks(oracle_lib):
+    """A product state with 14 clicks: heavy cancellation (R ~ 1e7+), closed
+    form known, so binary128 accuracy is pinned at a size where FP64 fails."""
+    rng = np.random.default_rng(21)
+    m = 14
+    params = [(rng.uniform(0.2, 0.5), rng.uniform(0, np.pi), 0.0) for _ in range(m)]
+    cov = gi.direct_sum([gi.single_mode_covariance(*p) for p in params])
+    pat = np.ones(m, np.int8)
+    want = _product_closed_form(params, pat)
+    res = oracle.formS(cov, pat)
+    assert res.cancel_ratio > 1e6
+    assert res.p == pytest.approx(want, rel=1e-12)
+
+
+def test_tmsv_pairs_many_clicks(oracle_lib):
+    """Six independent two-mode squeezed pairs, all 12 modes clicked:
+    p = prod_k (1 - 1/cosh^2 r_k)."""
+    rs = [0.3, 0.45, 0.6, 0.75, 0.9, 1.05]
+    cov = np.zeros((24, 24))
+    for k, r in enumerate(rs):
+        cov[4 * k:4 * k + 4, 4 * k:4 * k + 4] = gi.tmsv_covariance(r)
+    want = np.prod([1 - 1 / np.cosh(r) ** 2 for r in rs])
+    res = oracle.formS(cov, np.ones(12, np.int8))
+    assert res.p == pytest.approx(want, rel=1e-12)
+
+
+def test_errors(oracle_lib):
+    cov = 0.5 * np.eye(4)
+    with pytest.raises(oracle.OracleError):
+        oracle.formP(cov, np.array([1, 2], np.int8))
+    bad = cov.copy()
+    bad[0, 0] = -3.0
+    with pytest.raises(oracle.OracleError):
+        oracle.formP(bad, np.array([1, 1], np.int8))
+    nan = cov.copy()
+    nan[1, 0] = np.nan
+    with pytest.raises(oracle.OracleError):
+        oracle.formS(nan, np.array([1, 1], np.int8))
+
+
+# --------------------------------------------------------------------------
+# planted mistakes: each mutant of the oracle must fail at least one pin
+# --------------------------------------------------------------------------
+
+MUTANTS = {
+    "sign_dropped": (r"if \(__builtin_popcountll\(mask\) & 1\) s -= t; else s \+= t;", "s += t;"),
+    "sign_dropped_S": (r"if \(k & 1\) s -= t; else s \+= t;", "s += t;"),
+    "no_half_identity": (r"if \(ga == gb\) v \+= \(qf\)0\.5;", ""),
+    "wrong_quadrature_index": (r"int ga = 2 \* modes\[a / 2\] \+ \(a & 1\);", "int ga = 2 * modes[a / 2];"),
+    "det_power_minus_one": (r"prod /= ljj;", "prod /= s;"),
+    "schur_sign": (r"sig_c\[a \* dc \+ b\] -= v;", "sig_c[a * dc + b] += v;"),
+    "forgot_no_click_modes": (r"modes\[k\+\+\] = nidx\[ni\+\+\];", "ni++;"),
+    "transposed_cross_block": (r"qf v = sigq\(cov, m, 2 \* nidx\[i / 2\] \+ \(i & 1\), gc\);",
+                               "qf v = sigq(cov, m, 2 * nidx[i / 2] + 1 - (i & 1), gc);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "tor_oracle.c")).read()
+    pat, rep = MUTANTS[name]
+    mutated, k = re.subn(pat, rep, src)
+    assert k >= 1, f"mutation {name} did not apply"
+    path = tmp_path / "mut.c"
+    path.write_text(mutated)
+    so = str(tmp_path / f"libmut_{name}.so")
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-std=c11", str(path), "-o", so,
+                    "-lquadmath", "-lm"], check=True)
+    failed = []
+    for pin in PINS:
+        try:
+            pin(lib=so)
+        except (AssertionError, oracle.OracleError):
+            failed.append(pin.__name__)
+    assert failed, f"mutant {name} passed every pin"
