@@ -1,0 +1,166 @@
+"""Benchmark: large single Torontonians on an 800-mode GBS state.
+
+One step = one call of tor_probability (the whole hot path: sigma_Q, reduction
+of the click pattern to Sigma_C, the subset-tree kernels, the double-double
+reduction and the final assembly) for a marginal click pattern with n clicks
+(default n = 28, 2^28 subset terms) of the 800-mode state (Haar U,
+r_i ~ U[0.3, 0.9], seed 50), double-double terms (the precision tier that meets
+the 1e-8 target at these sizes).
+
+Printed: one JSON line with the subset-determinant rate, the roofline of the
+dominant (wave-tier) kernel from HIP events on the library's stream, and the
+CPU oracle timed on a bounded sample of the same sum.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 28]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 subset-dets/sec + % FP64 peak at n=20–28; p50/p99 query latency"
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak (256 CU x 128 flop/clk x 2.4 GHz)
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic flop count of the double-double subset tree (FMA = 2 flops),
+# from the operation counts of the dd primitives (csrc/dd.hpp).
+# ---------------------------------------------------------------------------
+F_TWO_SUM, F_FAST_TWO_SUM, F_TWO_PROD = 6, 3, 3
+F_DD_ADD = 2 * F_TWO_SUM + 1 + F_FAST_TWO_SUM + 1 + F_FAST_TWO_SUM          # 20
+F_DD_MUL = F_TWO_PROD + 1 + 2 + 1 + F_FAST_TWO_SUM                          # 10
+F_DD_SUB_DOT2 = 2 * F_TWO_PROD + 2 * 3 + 2 * F_TWO_SUM + 6 + F_TWO_SUM      # 36
+F_DD_DET2 = 2 * F_TWO_PROD + 3 + 2 + F_TWO_SUM + 4 + F_TWO_SUM              # 27
+F_DD_RSQRT = 2 + 2 * F_TWO_PROD + 4 + 2 + 2 + F_FAST_TWO_SUM                # 19
+
+
+def E(r):
+    return r * (2 * r + 1)
+
+
+def dd_node_flops(r):
+    """Flops to expand one r-mode node (r >= 2) into its include child and to
+    combine T, A; r == 1: a leaf pivot."""
+    if r == 1:
+        return F_DD_DET2 + F_DD_RSQRT + F_DD_ADD + 1
+    piv = 2 * F_DD_RSQRT + 3 * F_DD_MUL + (F_DD_MUL + F_DD_ADD)
+    cols = 2 * (r - 1) * (3 * F_DD_MUL + F_DD_ADD)
+    ents = E(r - 1) * F_DD_SUB_DOT2
+    comb = F_DD_MUL + F_DD_ADD + 2
+    return piv + cols + ents + comb
+
+
+def tree_flops(n, top=None):
+    """Flops of the full subset tree of n modes; with top = J only the part
+    below the nodes of J modes (what one wave-tier task does), per task."""
+    r0 = n if top is None else top
+    # a node with r modes has 2^(r0 - r) copies below the start
+    return sum((2 ** (r0 - r)) * dd_node_flops(r) for r in range(1, r0 + 1))
+
+
+def cpu_baseline(cov, pattern, n, seconds_target=15.0):
+    """Time the binary128 oracle on a strided sample of the same subset sum."""
+    import oracle
+    threads = oracle.num_threads()
+    count = 2048
+    # grow the sample until it takes ~1 s, then size it for the target
+    while True:
+        stride = max(1, (2 ** n) // count) | 1
+        t = time.perf_counter()
+        oracle.formS_range(cov, pattern, 0, stride, count)
+        dt = time.perf_counter() - t
+        if dt > 1.0 or count >= 2 ** n:
+            break
+        count *= 4
+    count = int(min(2 ** n, count * max(1.0, seconds_target / dt)))
+    stride = max(1, (2 ** n) // count) | 1
+    t = time.perf_counter()
+    oracle.formS_range(cov, pattern, 0, stride, count)
+    dt = time.perf_counter() - t
+    return {"value": count / dt, "unit": "subset-dets/s", "cores": threads, "kind": "oracle",
+            "sample": f"{count} of the 2^{n} subsets (masks 0, {stride}, 2*{stride}, ... mod 2^{n}) of the "
+                      f"same n={n} sum, binary128 Cholesky per subset, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=28)
+    ap.add_argument("--prec", default="dd", choices=["dd", "f64"])
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the subset sum would shard by prefix bits with one 24-byte exchange per GPU)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import gbs_inputs as gi
+    import paper_1810_00900_amd as tg
+
+    n = args.n
+    cov = gi.state_m800(50)
+    pattern = gi.config5_pattern(n)
+    ctx = tg.Context(0)
+    ctx.set_option(tg.OPT_TIMING, 1)
+    for _ in range(args.warmup):
+        r = ctx.probability(cov, pattern, prec=args.prec, tol=1e-8)
+    ctx.reset_stats()
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = ctx.probability(cov, pattern, prec=args.prec, tol=1e-8)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.stats()
+    ms_per_step = wall / args.steps * 1e3
+    subsets = 2.0 ** n * args.steps
+    value = subsets / wall
+
+    J = min(n, 9)
+    ntasks = 2 ** (n - J)
+    wave_ms = st["wave_ms"] / max(st["wave_launches"], 1)
+    wave_flops = tree_flops(n, top=J) * ntasks
+    achieved = wave_flops / (wave_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "subset-dets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64-dd" if args.prec == "dd" else "f64",
+        "data": "synthetic (seeded Haar-random 800-mode GBS state)",
+        "config": {"workload": f"large single Torontonian: m=800 modes (Haar U, r~U[0.3,0.9], seed 50), "
+                               f"marginal click pattern with n={n} (2^{n} subsets)",
+                   "m": 800, "n": n, "precision": args.prec, "task_modes": J},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": f"wave_kernel<dd,{J}>" if args.prec == "dd" else f"wave_kernel<double,{J}>",
+                     "kernel_ms": wave_ms,
+                     "algorithmic_flops_per_launch": wave_flops},
+        "phases_ms_per_step": {"expand": st["expand_ms"] / args.steps, "wave": st["wave_ms"] / args.steps,
+                               "reduce": st["reduce_ms"] / args.steps},
+        "result": {"p": r.p, "cancel_ratio": r.cancel_ratio, "rel_err_bound": r.rel_err_bound,
+                   "prec_used": r.prec_used},
+    }
+    ctx.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cov, pattern, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,161 @@
+/*
+ * tor.h -- C ABI of the MI355X (gfx950) library for exact threshold-detector
+ * Gaussian boson sampling probabilities.
+ *
+ * Method (arXiv:1810.00900, Sec. II "The Algorithm"): the POVM element of a
+ * click, I - |0><0|, is a difference of two Gaussian operators, so by
+ * linearity the probability of a click pattern is a signed sum, over the
+ * subsets Y of the clicked modes C, of Gaussian vacuum probabilities
+ *
+ *     p(C, N) = sum_{Y subset of C} (-1)^{|Y|} det(sigma_Q[Y u N])^{-1/2}
+ *             = P_vac(N) * sum_{Y subset of C} (-1)^{|Y|} det(Sigma_C[Y])^{-1/2},
+ *
+ * where sigma_Q = sigma + I/2 (hbar = 1), N are the no-click modes, P_vac(N) =
+ * det(sigma_Q[N])^{-1/2} is the q_k of Eq. (prob) at zero mean, and Sigma_C is
+ * sigma_Q[C] conditioned on vacuum at N (the Schur complement of Eq.
+ * MatrixUpdate applied for every mode of N).  Equivalently
+ * p = P_vac(N) det(Sigma_C)^{-1/2} Tor(O), O = I - Sigma_C^{-1}, with the
+ * Torontonian Tor(O) = sum_{Z subset of C} (-1)^{n-|Z|} det(I - O_Z)^{-1/2}.
+ *
+ * Conventions shared by every entry point:
+ *   cov      host pointer, 2m x 2m, row-major binary64, quadratures interleaved
+ *            per mode (x1, p1, x2, p2, ...) as in the paper's quadrature vector
+ *            (Sec. II, Eq. 1), hbar = 1 (vacuum = I/2; the paper's hbar = 2
+ *            covariance is V = 2 cov), zero mean.  Must be finite and symmetric
+ *            to 1e-12 relative; only the lower triangle enters the arithmetic.
+ *   pattern  host pointer, int8[m]: 1 = click, 0 = no click, -1 = unobserved
+ *            (traced out).  At most TOR_MAX_CLICKS entries may be 1.
+ *   sigma_Q  formed as sigma + I/2 exactly (double-double), so the result is
+ *            that of the binary64 input matrix.
+ *
+ * Precision: the 2^n-term alternating sum cancels heavily (the cancellation
+ * ratio R = sum|terms| / |sum| reaches 1e10-1e20 at n = 16-28 on 800-mode
+ * states), and the paper reports quad precision was needed (Sec. III,
+ * "Memory").  The sum is always accumulated in double-double.  The per-subset
+ * factorisation runs in binary64 (TOR_PREC_F64) or in double-double
+ * (TOR_PREC_DD); TOR_PREC_AUTO runs binary64 first and repeats in
+ * double-double when the a-priori bound exceeds tol.
+ *
+ * Status codes: 0 = TOR_OK; TOR_WARN_PRECISION (1): result delivered but its
+ * error bound exceeds tol; negative values are errors and leave *out
+ * unspecified.  tor_last_error() returns a thread-local message for the last
+ * failing call on the calling thread.
+ *
+ * Ownership: the caller owns every buffer passed in; the library copies
+ * inputs before returning.  tor_ctx and tor_state objects are library-owned and
+ * freed by their destroy calls; a state must not outlive its context.  A
+ * context is not thread-safe: use one per thread or lock externally.
+ */
+#ifndef TOR_H
+#define TOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tor_status;
+#define TOR_OK 0
+#define TOR_WARN_PRECISION 1
+#define TOR_EINVAL (-1)  /* bad argument (null pointer, bad pattern value, not symmetric, NaN) */
+#define TOR_ENOTPD (-2)  /* a pivot of sigma_Q was not positive: not a physical covariance */
+#define TOR_ETOOBIG (-3) /* more than TOR_MAX_CLICKS clicks, or m too large */
+#define TOR_ENOMEM (-4)  /* device or host allocation failed */
+#define TOR_EDEVICE (-5) /* HIP runtime error (message in tor_last_error) */
+#define TOR_EAGAIN (-6)  /* not ready / not admitted yet */
+
+#define TOR_MAX_CLICKS 32
+
+typedef enum { TOR_PREC_AUTO = 0, TOR_PREC_F64 = 1, TOR_PREC_DD = 2 } tor_prec;
+
+typedef struct tor_ctx tor_ctx;
+typedef struct tor_state tor_state;
+
+typedef struct {
+    double p;             /* click-pattern probability p(C, N) (binary64 rounding of p_hi + p_lo) */
+    double p_lo;          /* low word: p + p_lo is the double-double result */
+    double log_p;         /* natural log of p (-inf if p <= 0) */
+    double tor;           /* Torontonian Tor(I - Sigma_C^-1) = det(Sigma_C)^{1/2} * T */
+    double T;             /* subset sum over Sigma_C (= p / P_vac(N)) */
+    double T_lo;          /* low word of T */
+    double abs_sum;       /* sum of |terms| over Sigma_C */
+    double cancel_ratio;  /* abs_sum / |T| */
+    double rel_err_bound; /* a-priori relative error bound of p */
+    double log_pvac_n;    /* log P_vac(N) */
+    int32_t n_clicks;     /* |C| */
+    int32_t prec_used;    /* TOR_PREC_F64 or TOR_PREC_DD */
+    int32_t status;       /* per-result status (TOR_OK or TOR_WARN_PRECISION) */
+    int32_t reserved;
+} tor_result;
+
+/* Per-context cumulative kernel statistics (HIP events on the context's
+ * stream; recorded only while timing is enabled). */
+typedef struct {
+    double wave_ms;       /* total time of the wave-tier kernel launches */
+    double expand_ms;     /* total time of the HBM-tier expansion launches */
+    double reduce_ms;     /* total time of the reduction launches */
+    int64_t wave_launches;
+    int64_t expand_launches;
+    int64_t reduce_launches;
+    double subsets;       /* number of subset terms evaluated (2^n per sum) */
+} tor_stats;
+
+/* Options settable on a context (tor_ctx_set_option). */
+typedef enum {
+    TOR_OPT_TIMING = 0,     /* 1: record HIP events around every launch (default 0) */
+    TOR_OPT_TASK_MODES = 1, /* modes per wave-tier task, 1..9 (default 9) */
+    TOR_OPT_WAVE_GRID = 2,  /* cap on wave-tier workgroups per launch (default 65536) */
+    TOR_OPT_MEM_BUDGET = 3  /* device bytes the context may hold (default 64 GiB) */
+} tor_option;
+
+/* Create a context on HIP device `device` (its own stream, default priority).
+ * *out receives the context.  Errors: TOR_EINVAL, TOR_EDEVICE, TOR_ENOMEM. */
+tor_status tor_ctx_create(int device, tor_ctx **out);
+void tor_ctx_destroy(tor_ctx *ctx);
+
+/* Run the context's work on `stream` (a hipStream_t of the context's device,
+ * e.g. a torch stream's handle); NULL restores the context's own stream. */
+tor_status tor_ctx_set_stream(tor_ctx *ctx, void *stream);
+tor_status tor_ctx_set_option(tor_ctx *ctx, tor_option opt, int64_t value);
+tor_status tor_ctx_get_stats(const tor_ctx *ctx, tor_stats *out);
+tor_status tor_ctx_reset_stats(tor_ctx *ctx);
+
+/* Thread-local message of the last error on this thread ("" if none). */
+const char *tor_last_error(void);
+
+/* Probability of one click pattern of the zero-mean Gaussian state `cov`
+ * (m modes).  Sec. II of the paper (signed sum of Eq. (prob) vacuum terms;
+ * no-click modes conditioned with Eq. MatrixUpdate).  tol is the relative
+ * error target for TOR_PREC_AUTO and for the TOR_WARN_PRECISION flag.
+ * Errors: TOR_EINVAL, TOR_ENOTPD, TOR_ETOOBIG, TOR_ENOMEM, TOR_EDEVICE. */
+tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int8_t *pattern, tor_prec prec,
+                           double tol, tor_result *out);
+
+/* The subset sum alone for a given SPD matrix Sigma (2n x 2n row-major,
+ * interleaved, host): T = sum_{Y subset of [n]} (-1)^{|Y|} det(Sigma[Y])^{-1/2}.
+ * sigma_lo may be NULL; otherwise Sigma = sigma_hi + sigma_lo entrywise
+ * (double-double input).  out->p = T, out->log_pvac_n = 0.  n <= 32. */
+tor_status tor_subset_sum(tor_ctx *ctx, const double *sigma_hi, const double *sigma_lo, int32_t n, tor_prec prec,
+                          double tol, tor_result *out);
+
+/* A state: validated covariance kept on the host (and sigma_Q formed once)
+ * for many queries.  cov as above. */
+tor_status tor_state_create(tor_ctx *ctx, const double *cov, int32_t m, tor_state **out);
+void tor_state_destroy(tor_state *st);
+
+/* nq queries on one state, patterns = nq x m int8 (row per query), results in
+ * out[nq].  All queries' subset trees are evaluated in shared launches, each
+ * with its own fixed reduction order, so every result is bitwise identical to
+ * the same query run alone.  Per-query failures are reported in
+ * out[i].status; the call returns the first error, or TOR_OK /
+ * TOR_WARN_PRECISION. */
+tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *patterns, tor_prec prec,
+                     double tol, tor_result *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOR_H */

@@ -1,0 +1,266 @@
+"""Python binding of libtorgbs (include/tor.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module converts
+numpy arrays to pointers, calls the C ABI and turns results into dataclasses.
+PyTorch is used only to hand a stream (``torch.cuda.Stream``) to a context.
+
+The library must have been built (``python -m paper_1810_00900_amd.build`` or
+``__graft_entry__.build()``); importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtorgbs.so")
+
+TOR_OK = 0
+TOR_WARN_PRECISION = 1
+TOR_EINVAL = -1
+TOR_ENOTPD = -2
+TOR_ETOOBIG = -3
+TOR_ENOMEM = -4
+TOR_EDEVICE = -5
+TOR_EAGAIN = -6
+
+PREC_AUTO, PREC_F64, PREC_DD = 0, 1, 2
+_PREC = {"auto": PREC_AUTO, "f64": PREC_F64, "dd": PREC_DD,
+         PREC_AUTO: PREC_AUTO, PREC_F64: PREC_F64, PREC_DD: PREC_DD}
+
+OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET = 0, 1, 2, 3
+
+_STATUS_NAMES = {0: "TOR_OK", 1: "TOR_WARN_PRECISION", -1: "TOR_EINVAL", -2: "TOR_ENOTPD",
+                 -3: "TOR_ETOOBIG", -4: "TOR_ENOMEM", -5: "TOR_EDEVICE", -6: "TOR_EAGAIN"}
+
+
+class TorError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _CResult(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_double), ("p_lo", ctypes.c_double), ("log_p", ctypes.c_double),
+                ("tor", ctypes.c_double), ("T", ctypes.c_double), ("T_lo", ctypes.c_double),
+                ("abs_sum", ctypes.c_double), ("cancel_ratio", ctypes.c_double),
+                ("rel_err_bound", ctypes.c_double), ("log_pvac_n", ctypes.c_double),
+                ("n_clicks", ctypes.c_int32), ("prec_used", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _CStats(ctypes.Structure):
+    _fields_ = [("wave_ms", ctypes.c_double), ("expand_ms", ctypes.c_double),
+                ("reduce_ms", ctypes.c_double), ("wave_launches", ctypes.c_int64),
+                ("expand_launches", ctypes.c_int64), ("reduce_launches", ctypes.c_int64),
+                ("subsets", ctypes.c_double)]
+
+
+@dataclass
+class Result:
+    p: float
+    p_lo: float
+    log_p: float
+    tor: float
+    T: float
+    T_lo: float
+    abs_sum: float
+    cancel_ratio: float
+    rel_err_bound: float
+    log_pvac_n: float
+    n_clicks: int
+    prec_used: int
+    status: int
+
+    @classmethod
+    def _from(cls, r: _CResult) -> "Result":
+        return cls(*(getattr(r, f) for f, _ in _CResult._fields_[:-1]))
+
+
+_lib = None
+
+
+def lib():
+    """Load libtorgbs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1810_00900_amd.build")
+    # PyTorch ships its own HIP runtime (same soname, libamdhip64.so.7).  Load
+    # torch first so that the library binds to that already-loaded runtime and
+    # one process holds a single HIP runtime: torch's streams and device
+    # tensors are then valid in the library, and torch can still initialise.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    i8p = ctypes.POINTER(ctypes.c_int8)
+    sig = {
+        "tor_ctx_create": ([ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int32),
+        "tor_ctx_destroy": ([vp], None),
+        "tor_ctx_set_stream": ([vp, vp], ctypes.c_int32),
+        "tor_ctx_set_option": ([vp, ctypes.c_int, ctypes.c_int64], ctypes.c_int32),
+        "tor_ctx_get_stats": ([vp, ctypes.POINTER(_CStats)], ctypes.c_int32),
+        "tor_ctx_reset_stats": ([vp], ctypes.c_int32),
+        "tor_last_error": ([], ctypes.c_char_p),
+        "tor_probability": ([vp, dp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
+                             ctypes.POINTER(_CResult)], ctypes.c_int32),
+        "tor_subset_sum": ([vp, dp, dp, ctypes.c_int32, ctypes.c_int, ctypes.c_double,
+                            ctypes.POINTER(_CResult)], ctypes.c_int32),
+        "tor_state_create": ([vp, dp, ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int32),
+        "tor_state_destroy": ([vp], None),
+        "tor_batch": ([vp, vp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
+                       ctypes.POINTER(_CResult)], ctypes.c_int32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().tor_last_error().decode()
+
+
+def _check(status: int, allow_warn: bool = True) -> int:
+    if status < 0 or (status == TOR_WARN_PRECISION and not allow_warn):
+        raise TorError(status, last_error())
+    return status
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i8(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int8)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i8ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+
+
+class Context:
+    """A library context on one HIP device (tor_ctx)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().tor_ctx_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self._stream_ref = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tor_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream=None):
+        """Run on a torch.cuda.Stream (or a raw hipStream_t int); None = own stream."""
+        raw = None
+        if stream is not None:
+            raw = getattr(stream, "cuda_stream", stream)
+        self._stream_ref = stream
+        _check(lib().tor_ctx_set_stream(self._h, ctypes.c_void_p(raw)))
+
+    def set_option(self, opt: int, value: int):
+        _check(lib().tor_ctx_set_option(self._h, int(opt), int(value)))
+
+    def stats(self) -> dict:
+        s = _CStats()
+        _check(lib().tor_ctx_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in _CStats._fields_}
+
+    def reset_stats(self):
+        _check(lib().tor_ctx_reset_stats(self._h))
+
+    def probability(self, cov, pattern, prec="auto", tol: float = 1e-10) -> Result:
+        cov = _f64(cov)
+        pattern = _i8(pattern)
+        m = pattern.shape[0]
+        if cov.shape != (2 * m, 2 * m):
+            raise ValueError("cov must be 2m x 2m for a pattern of length m")
+        r = _CResult()
+        _check(lib().tor_probability(self._h, _dptr(cov), m, _i8ptr(pattern), _PREC[prec], float(tol),
+                                     ctypes.byref(r)))
+        return Result._from(r)
+
+    def subset_sum(self, sigma, sigma_lo=None, prec="dd", tol: float = 1e-10) -> Result:
+        sigma = _f64(sigma)
+        n = sigma.shape[0] // 2
+        lo = None if sigma_lo is None else _f64(sigma_lo)
+        r = _CResult()
+        _check(lib().tor_subset_sum(self._h, _dptr(sigma), None if lo is None else _dptr(lo), n, _PREC[prec],
+                                    float(tol), ctypes.byref(r)))
+        return Result._from(r)
+
+    def state(self, cov) -> "State":
+        return State(self, cov)
+
+    def batch(self, state: "State", patterns, prec="auto", tol: float = 1e-10):
+        patterns = _i8(patterns)
+        if patterns.ndim != 2 or patterns.shape[1] != state.m:
+            raise ValueError("patterns must be nq x m")
+        nq = patterns.shape[0]
+        out = (_CResult * max(nq, 1))()
+        st = lib().tor_batch(self._h, state.handle, nq, _i8ptr(patterns), _PREC[prec], float(tol), out)
+        res = [Result._from(out[i]) for i in range(nq)]
+        if st < 0 and all(r.status < 0 for r in res):
+            raise TorError(st, last_error())
+        return res, st
+
+
+class State:
+    """A validated covariance kept by the library (tor_state)."""
+
+    def __init__(self, ctx: Context, cov):
+        cov = _f64(cov)
+        self.m = cov.shape[0] // 2
+        h = ctypes.c_void_p()
+        _check(lib().tor_state_create(ctx.handle, _dptr(cov), self.m, ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tor_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

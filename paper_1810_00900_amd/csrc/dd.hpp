@@ -1,0 +1,172 @@
+// Double-double ("dd") arithmetic on IEEE binary64, host and device.
+//
+// A dd value is an unevaluated sum hi + lo with |lo| <= ulp(hi)/2, giving about
+// 106 significant bits.  The error-free transformations are Knuth's TwoSum,
+// Dekker's FastTwoSum and the FMA-based TwoProd; addition follows the
+// "accurate" double-word sum and multiplication the double-word product analysed
+// by Joldes, Muller and Popescu (ACM TOMS 44(4), 2017), relative error <= 3u^2
+// and <= 5u^2 (u = 2^-53).  Every routine here is written from those
+// published algorithms.
+//
+// This file MUST be compiled with floating-point contraction disabled
+// (-ffp-contract=off): TwoSum and FastTwoSum are exact only if each operation
+// rounds on its own.  FMAs are written explicitly where an algorithm needs one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+#define DD_FN __host__ __device__ __forceinline__
+#else
+#define DD_FN inline
+#endif
+
+#pragma clang fp contract(off)
+
+struct __align__(16) dd {
+    double hi, lo;
+};
+
+DD_FN dd dd_make(double h, double l) { dd r; r.hi = h; r.lo = l; return r; }
+DD_FN dd dd_from(double x) { return dd_make(x, 0.0); }
+
+// s + e == a + b exactly (any a, b).
+DD_FN void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// s + e == a + b exactly, requires exponent(a) >= exponent(b) (e.g. |a| >= |b|).
+DD_FN void fast_two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    e = b - (s - a);
+}
+
+// p + e == a * b exactly (barring underflow), using one FMA.
+DD_FN void two_prod(double a, double b, double &p, double &e) {
+    p = a * b;
+    e = fma(a, b, -p);
+}
+
+DD_FN dd dd_neg(dd a) { return dd_make(-a.hi, -a.lo); }
+
+// Accurate double-word + double-word.
+DD_FN dd dd_add(dd x, dd y) {
+    double sh, sl, th, tl;
+    two_sum(x.hi, y.hi, sh, sl);
+    two_sum(x.lo, y.lo, th, tl);
+    sl += th;
+    double vh, vl;
+    fast_two_sum(sh, sl, vh, vl);
+    vl += tl;
+    dd r;
+    fast_two_sum(vh, vl, r.hi, r.lo);
+    return r;
+}
+
+DD_FN dd dd_sub(dd x, dd y) { return dd_add(x, dd_neg(y)); }
+
+// double-word * double
+DD_FN dd dd_mul_d(dd x, double y) {
+    double p, e;
+    two_prod(x.hi, y, p, e);
+    e = fma(x.lo, y, e);
+    dd r;
+    fast_two_sum(p, e, r.hi, r.lo);
+    return r;
+}
+
+// double-word * double-word
+DD_FN dd dd_mul(dd x, dd y) {
+    double p, e;
+    two_prod(x.hi, y.hi, p, e);
+    double t = x.lo * y.hi;
+    t = fma(x.hi, y.lo, t);
+    e += t;
+    dd r;
+    fast_two_sum(p, e, r.hi, r.lo);
+    return r;
+}
+
+// x - a1*b1 - a2*b2 in one pass.  The two leading products are split exactly
+// (TwoProd), the leading sum is formed with TwoSums, and all second-order
+// terms are gathered in one binary64 sum; the absolute error is a small
+// multiple of u^2 (|x| + |a1 b1| + |a2 b2|), the backward error of a
+// dd-precision rank-2 update.
+DD_FN dd dd_sub_dot2(dd x, dd a1, dd b1, dd a2, dd b2) {
+    double p1, e1, p2, e2;
+    two_prod(a1.hi, b1.hi, p1, e1);
+    two_prod(a2.hi, b2.hi, p2, e2);
+    double c1 = fma(a1.hi, b1.lo, a1.lo * b1.hi);
+    double c2 = fma(a2.hi, b2.lo, a2.lo * b2.hi);
+    double s, t1, t2;
+    two_sum(x.hi, -p1, s, t1);
+    two_sum(s, -p2, s, t2);
+    double low = ((x.lo + t1) + t2) - ((e1 + e2) + (c1 + c2));
+    dd r;
+    two_sum(s, low, r.hi, r.lo);
+    return r;
+}
+
+// a*c - b*b (determinant of a symmetric 2x2 block [[a, b], [b, c]]).
+DD_FN dd dd_det2(dd a, dd b, dd c) {
+    double p1, e1, p2, e2;
+    two_prod(a.hi, c.hi, p1, e1);
+    two_prod(b.hi, b.hi, p2, e2);
+    double c1 = fma(a.hi, c.lo, a.lo * c.hi);
+    double c2 = 2.0 * (b.hi * b.lo);
+    double s, t;
+    two_sum(p1, -p2, s, t);
+    double low = (t + e1 + c1) - (e2 + c2);
+    dd r;
+    two_sum(s, low, r.hi, r.lo);
+    return r;
+}
+
+// 1/sqrt(x) for x > 0: a binary64 seed refined by one Newton step
+// y = y0 + y0 (1 - x y0^2) / 2 whose residual is formed in double-word
+// precision; the seed's relative error e becomes ~1.5 e^2 + O(u^2).
+// Non-positive or non-finite x propagates NaN/inf.
+DD_FN dd dd_rsqrt(dd x) {
+    double y0 = 1.0 / sqrt(x.hi);
+    double p, e;
+    two_prod(y0, y0, p, e);           // y0^2 = p + e exactly
+    double h, l;
+    two_prod(x.hi, p, h, l);
+    l = fma(x.hi, e, l);
+    l = fma(x.lo, p, l);              // x*y0^2 = h + l (to ~u^2)
+    double r = (1.0 - h) - l;         // 1 - h is exact since h ~ 1
+    double corr = 0.5 * (y0 * r);
+    dd out;
+    fast_two_sum(y0, corr, out.hi, out.lo);
+    return out;
+}
+
+// binary64 helpers with the same call shape, for the binary64-term tier
+DD_FN double sub_dot2(double x, double a1, double b1, double a2, double b2) {
+    return fma(-a2, b2, fma(-a1, b1, x));
+}
+DD_FN dd sub_dot2(dd x, dd a1, dd b1, dd a2, dd b2) { return dd_sub_dot2(x, a1, b1, a2, b2); }
+DD_FN double det2(double a, double b, double c) { return fma(a, c, -b * b); }
+DD_FN dd det2(dd a, dd b, dd c) { return dd_det2(a, b, c); }
+DD_FN double rsqrt_s(double x) { return 1.0 / sqrt(x); }
+DD_FN dd rsqrt_s(dd x) { return dd_rsqrt(x); }
+DD_FN double mul_s(double a, double b) { return a * b; }
+DD_FN dd mul_s(dd a, dd b) { return dd_mul(a, b); }
+DD_FN dd to_dd(double a) { return dd_from(a); }
+DD_FN dd to_dd(dd a) { return a; }
+// scalar from a dd (hi, lo) pair: binary64 tier rounds to hi + lo
+template <class S> DD_FN S from_pair(double h, double l);
+template <> DD_FN double from_pair<double>(double h, double l) { return h + l; }
+template <> DD_FN dd from_pair<dd>(double h, double l) {
+    dd r;
+    two_sum(h, l, r.hi, r.lo);
+    return r;
+}
+// T-recursion step: t0 - q * t1 with dd accumulation
+DD_FN dd dd_sub_mul(dd t0, double q, dd t1) { return dd_sub(t0, dd_mul_d(t1, q)); }
+DD_FN dd dd_sub_mul(dd t0, dd q, dd t1) { return dd_sub(t0, dd_mul(t1, q)); }
+DD_FN double hi_of(double a) { return a; }
+DD_FN double hi_of(dd a) { return a.hi; }
