@@ -82,8 +82,10 @@ struct tor_ctx {
     int device = 0;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
-    DevBuf pool, descA, descB, partA, partB;
+    DevBuf pool, descA, descB, partA, partB, jobs;
     Partial *host_res = nullptr;
+    size_t host_res_cap = 0;
+    std::vector<unsigned char> host_jobs, host_stage;
     bool timing = false;
     int task_modes = 9;
     int wave_grid = 65536;
@@ -259,89 +261,280 @@ double elapsed(hipEvent_t a, hipEvent_t b) {
     return (double)ms;
 }
 
-// Subset sum T, A of the packed (row-major lower) double-double matrix of n
-// modes, on the GPU.  Tree plan: the top n - J levels are expanded in HBM (one
-// launch per level), the remaining J modes of each of the 2^(n-J) nodes by the
-// wave tier.
-tor_status gpu_subset_sum(tor_ctx *ctx, const std::vector<dd> &packed, int n, bool use_dd, dd &T, double &A) {
-    if (n == 0) {
-        T = dd_from(1.0);
-        A = 1.0;
-        return TOR_OK;
-    }
-    const int J = std::min(n, ctx->task_modes);
-    const int G = n - J;
-    const long long ntasks = 1LL << G;
-    const size_t es = use_dd ? sizeof(dd) : sizeof(double);
-    // pool layout: root, then the include children of every HBM level
-    std::vector<unsigned long long> child_base(G + 1);
+// One subset sum to evaluate on the GPU: the packed (row-major lower)
+// double-double matrix of n modes.
+struct SumIn {
+    const std::vector<dd> *packed = nullptr;
+    int n = 0;
+};
+struct SumOut {
+    dd T = {1.0, 0.0};
+    double A = 1.0;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Device bytes one subset sum of n modes needs (pool + descriptors + partials).
+size_t sum_bytes(int n, int task_modes, size_t es) {
+    if (n == 0) return 0;
+    const int J = std::min(n, task_modes), G = n - J;
     unsigned long long total = (unsigned long long)E(n);
-    for (int d = 0; d < G; d++) {
-        child_base[d] = total;
-        total += (1ULL << d) * (unsigned long long)E(n - d - 1);
+    for (int d = 0; d < G; d++) total += (1ULL << d) * (unsigned long long)E(n - d - 1);
+    const size_t nt = (size_t)1 << G;
+    return total * es + 2 * nt * sizeof(NodeDesc) + nt * sizeof(Partial) + (nt / 512 + 8) * sizeof(Partial) +
+           1024;
+}
+
+// Evaluate a group of subset sums in shared launches.  The top n - J levels of
+// every tree are expanded in HBM (one launch per depth, all trees that reach it),
+// then one wave-tier launch per distinct J, then the per-tree reduction stages,
+// then one gather of the results.  The work and the reduction order of each
+// tree do not depend on the other trees in the group.
+tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vector<int> &idx, bool use_dd,
+                     std::vector<SumOut> &out) {
+    const size_t es = use_dd ? sizeof(dd) : sizeof(double);
+    struct Plan {
+        int q, n, J, G;
+        long long nt;
+        unsigned long long root_off;
+        std::vector<unsigned long long> child_base;
+        long long desc_off;
+    };
+    std::vector<Plan> P;
+    unsigned long long roots = 0;
+    long long desc_total = 0;
+    int Gmax = 0;
+    for (int q : idx) {
+        Plan p;
+        p.q = q;
+        p.n = in[q].n;
+        p.J = std::min(p.n, ctx->task_modes);
+        p.G = p.n - p.J;
+        p.nt = 1LL << p.G;
+        p.root_off = roots;
+        roots += (unsigned long long)E(p.n);
+        p.desc_off = desc_total;
+        desc_total += p.nt;
+        Gmax = std::max(Gmax, p.G);
+        P.push_back(std::move(p));
     }
-    const size_t pool_bytes = total * es;
-    const size_t desc_bytes = (size_t)ntasks * sizeof(NodeDesc);
-    const size_t part_bytes = (size_t)ntasks * sizeof(Partial);
-    if (pool_bytes + 2 * desc_bytes + 2 * part_bytes > ctx->mem_budget)
-        return fail(TOR_ENOMEM, "n = %d needs %.2f GB of device memory (budget %.2f GB)", n,
-                    (pool_bytes + 2.0 * desc_bytes + 2.0 * part_bytes) / 1e9, ctx->mem_budget / 1e9);
-    if (ctx->pool.ensure(pool_bytes) != hipSuccess || ctx->descA.ensure(desc_bytes) != hipSuccess ||
-        ctx->descB.ensure(desc_bytes) != hipSuccess || ctx->partA.ensure(part_bytes) != hipSuccess ||
-        ctx->partB.ensure(part_bytes / 256 + 4 * sizeof(Partial)) != hipSuccess)
-        return fail(TOR_ENOMEM, "device allocation of %.2f GB failed", pool_bytes / 1e9);
-    hipStream_t st = ctx->stream;
-    // upload the root
-    const size_t ne = (size_t)E(n);
-    std::vector<unsigned char> stage(ne * es);
-    for (int a = 0; a < 2 * n; a++)
-        for (int b = 0; b <= a; b++) {
-            dd v = packed[(size_t)pidx(a, b)];
-            if (use_dd) {
-                ((dd *)stage.data())[pidx(a, b)] = v;
-            } else {
-                ((double *)stage.data())[pidx(a, b)] = v.hi + v.lo;
-            }
+    if (P.empty()) return TOR_OK;
+    unsigned long long pool_total = roots;
+    for (auto &p : P) {
+        p.child_base.resize(p.G);
+        for (int d = 0; d < p.G; d++) {
+            p.child_base[d] = pool_total;
+            pool_total += (1ULL << d) * (unsigned long long)E(p.n - d - 1);
         }
-    HIP_TRY(hipMemcpyAsync(ctx->pool.p, stage.data(), ne * es, hipMemcpyHostToDevice, st));
-    NodeDesc root{0ULL, 1.0, 0.0, 1.0};
-    HIP_TRY(hipMemcpyAsync(ctx->descA.p, &root, sizeof root, hipMemcpyHostToDevice, st));
-    NodeDesc *cur = (NodeDesc *)ctx->descA.p, *nxt = (NodeDesc *)ctx->descB.p;
+    }
+    // reduction stages: stage outputs laid out one after another in partB
+    struct RStage {
+        std::vector<ReduceJob> jobs;
+        long long blocks = 0;
+    };
+    std::vector<RStage> stages;
+    std::vector<const Partial *> final_src(P.size(), nullptr);
+    std::vector<long long> cnt(P.size());
+    std::vector<long long> src_off(P.size());  // element offset of the current stage input
+    std::vector<int> src_buf(P.size(), 0);       // 0 = partA, 1 = partB
+    long long partB_used = 0;
+    for (size_t i = 0; i < P.size(); i++) {
+        cnt[i] = P[i].nt;
+        src_off[i] = P[i].desc_off;
+    }
+    // sizes first (pointers filled after allocation)
+    struct RPlan {
+        size_t i;
+        long long in_off, out_off, count;
+        int in_buf;
+    };
+    std::vector<std::vector<RPlan>> rplans;
+    for (;;) {
+        std::vector<RPlan> st;
+        for (size_t i = 0; i < P.size(); i++) {
+            if (cnt[i] <= 1) continue;
+            long long nb = (cnt[i] + TOR_REDUCE_CHUNK - 1) / TOR_REDUCE_CHUNK;
+            st.push_back({i, src_off[i], partB_used, cnt[i], src_buf[i]});
+            src_off[i] = partB_used;
+            src_buf[i] = 1;
+            partB_used += nb;
+            cnt[i] = nb;
+        }
+        if (st.empty()) break;
+        rplans.push_back(std::move(st));
+    }
+    const size_t pool_bytes = pool_total * es;
+    const size_t desc_bytes = (size_t)desc_total * sizeof(NodeDesc);
+    const size_t partA_bytes = (size_t)desc_total * sizeof(Partial);
+    const size_t partB_bytes = (size_t)(partB_used + 1) * sizeof(Partial);
+    // job buffer layout
+    size_t nexp = 0;
+    for (int d = 0; d < Gmax; d++)
+        for (auto &p : P)
+            if (p.G > d) nexp++;
+    size_t nred = 0;
+    for (auto &st : rplans) nred += st.size();
+    const size_t off_roots = 0;
+    const size_t off_exp = align_up(off_roots + P.size() * sizeof(NodeDesc), 64);
+    const size_t off_wave = align_up(off_exp + nexp * sizeof(ExpandJob), 64);
+    const size_t off_red = align_up(off_wave + P.size() * sizeof(WaveJob), 64);
+    const size_t off_gsrc = align_up(off_red + nred * sizeof(ReduceJob), 64);
+    const size_t off_res = align_up(off_gsrc + P.size() * sizeof(Partial *), 64);
+    const size_t job_bytes = off_res + P.size() * sizeof(Partial);
+    if (pool_bytes + 2 * desc_bytes + partA_bytes + partB_bytes + job_bytes > ctx->mem_budget)
+        return fail(TOR_ENOMEM, "subset sums need %.2f GB of device memory (budget %.2f GB)",
+                    (pool_bytes + 2.0 * desc_bytes + partA_bytes + partB_bytes) / 1e9, ctx->mem_budget / 1e9);
+    if (ctx->pool.ensure(pool_bytes) != hipSuccess || ctx->descA.ensure(desc_bytes) != hipSuccess ||
+        ctx->descB.ensure(desc_bytes) != hipSuccess || ctx->partA.ensure(partA_bytes) != hipSuccess ||
+        ctx->partB.ensure(partB_bytes) != hipSuccess || ctx->jobs.ensure(job_bytes) != hipSuccess)
+        return fail(TOR_ENOMEM, "device allocation of %.2f GB failed", pool_bytes / 1e9);
+    if (ctx->host_jobs.size() < job_bytes) ctx->host_jobs.resize(job_bytes);
+    unsigned char *hj = ctx->host_jobs.data();
+    unsigned char *dj = (unsigned char *)ctx->jobs.p;
+    NodeDesc *descA = (NodeDesc *)ctx->descA.p, *descB = (NodeDesc *)ctx->descB.p;
+    Partial *partA = (Partial *)ctx->partA.p, *partB = (Partial *)ctx->partB.p;
+    auto level_ptr = [&](const Plan &p, size_t pi, int d) -> NodeDesc * {
+        if (d == 0) return (NodeDesc *)(dj + off_roots) + pi;
+        return ((d & 1) ? descB : descA) + p.desc_off;
+    };
+    // root descriptors
+    for (size_t i = 0; i < P.size(); i++) {
+        NodeDesc r{P[i].root_off, 1.0, 0.0, 1.0};
+        std::memcpy(hj + off_roots + i * sizeof(NodeDesc), &r, sizeof r);
+    }
+    // expansion jobs, grouped by depth
+    std::vector<std::pair<size_t, int>> exp_launch;  // (first job index, count) per depth
+    size_t ej = 0;
+    for (int d = 0; d < Gmax; d++) {
+        size_t first = ej;
+        for (size_t i = 0; i < P.size(); i++) {
+            const Plan &p = P[i];
+            if (p.G <= d) continue;
+            ExpandJob job{level_ptr(p, i, d), level_ptr(p, i, d + 1), p.child_base[d], p.n - d, 0};
+            std::memcpy(hj + off_exp + ej * sizeof(ExpandJob), &job, sizeof job);
+            ej++;
+        }
+        exp_launch.push_back({first, (int)(ej - first)});
+    }
+    // wave jobs grouped by J (descending J, then query order)
+    std::vector<size_t> order(P.size());
+    for (size_t i = 0; i < P.size(); i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return P[a].J > P[b].J; });
+    struct WGroup {
+        int J;
+        size_t first;
+        int count;
+        long long total;
+    };
+    std::vector<WGroup> wgroups;
+    for (size_t k = 0; k < order.size(); k++) {
+        const size_t i = order[k];
+        const Plan &p = P[i];
+        if (wgroups.empty() || wgroups.back().J != p.J) wgroups.push_back({p.J, k, 0, 0});
+        WGroup &g = wgroups.back();
+        WaveJob job{level_ptr(p, i, p.G), partA + p.desc_off, g.total};
+        std::memcpy(hj + off_wave + k * sizeof(WaveJob), &job, sizeof job);
+        g.count++;
+        g.total += p.nt;
+    }
+    // reduction jobs
+    std::vector<std::pair<size_t, std::pair<int, long long>>> red_launch;
+    size_t rj = 0;
+    for (auto &st : rplans) {
+        size_t first = rj;
+        long long blocks = 0;
+        for (auto &r : st) {
+            ReduceJob job{(r.in_buf ? partB : partA) + r.in_off, partB + r.out_off, r.count, blocks};
+            std::memcpy(hj + off_red + rj * sizeof(ReduceJob), &job, sizeof job);
+            blocks += (r.count + TOR_REDUCE_CHUNK - 1) / TOR_REDUCE_CHUNK;
+            rj++;
+        }
+        red_launch.push_back({first, {(int)(rj - first), blocks}});
+    }
+    // gather sources: the last stage output of each tree
+    for (size_t i = 0; i < P.size(); i++) {
+        const Partial *src = src_buf[i] ? partB + src_off[i] : partA + src_off[i];
+        std::memcpy(hj + off_gsrc + i * sizeof(Partial *), &src, sizeof src);
+    }
+    // upload the roots and the job tables
+    hipStream_t st = ctx->stream;
+    std::vector<unsigned char> &stage = ctx->host_stage;
+    if (stage.size() < roots * es) stage.resize(roots * es);
+    for (auto &p : P) {
+        const std::vector<dd> &pk = *in[p.q].packed;
+        for (long long e = 0; e < E(p.n); e++) {
+            if (use_dd) ((dd *)stage.data())[p.root_off + e] = pk[(size_t)e];
+            else ((double *)stage.data())[p.root_off + e] = pk[(size_t)e].hi + pk[(size_t)e].lo;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->pool.p, stage.data(), roots * es, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dj, hj, off_res, hipMemcpyHostToDevice, st));
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[0], st));
-    for (int d = 0; d < G; d++) {
-        HIP_TRY(tor_launch_expand(use_dd, cur, 1LL << d, n - d, ctx->pool.p, child_base[d], nxt, 1 << 20, st));
-        std::swap(cur, nxt);
+    for (int d = 0; d < Gmax; d++) {
+        auto [first, count] = exp_launch[d];
+        HIP_TRY(tor_launch_expand(use_dd, (const ExpandJob *)(dj + off_exp) + first, count, d, ctx->pool.p, 1 << 20,
+                                  st));
     }
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[1], st));
-    HIP_TRY(tor_launch_wave(use_dd, J, cur, ntasks, ctx->pool.p, (Partial *)ctx->partA.p, ctx->wave_grid, st));
+    for (auto &g : wgroups)
+        HIP_TRY(tor_launch_wave(use_dd, g.J, (const WaveJob *)(dj + off_wave) + g.first, g.count, g.total,
+                                ctx->pool.p, ctx->wave_grid, st));
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[2], st));
-    Partial *pin = (Partial *)ctx->partA.p, *pout = (Partial *)ctx->partB.p;
-    long long cnt = ntasks;
-    int nred = 0;
-    while (cnt > 1) {
-        const long long chunk = 1024;
-        HIP_TRY(tor_launch_reduce(pin, cnt, chunk, pout, st));
-        cnt = (cnt + chunk - 1) / chunk;
-        std::swap(pin, pout);
-        nred++;
-    }
+    for (auto &rl : red_launch)
+        HIP_TRY(tor_launch_reduce((const ReduceJob *)(dj + off_red) + rl.first, rl.second.first, rl.second.second,
+                                  st));
+    HIP_TRY(tor_launch_gather((const Partial *const *)(dj + off_gsrc), (int)P.size(), (Partial *)(dj + off_res),
+                              st));
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[3], st));
-    HIP_TRY(hipMemcpyAsync(ctx->host_res, pin, sizeof(Partial), hipMemcpyDeviceToHost, st));
+    if (ctx->host_res_cap < P.size()) {
+        if (ctx->host_res) (void)hipHostFree(ctx->host_res);
+        ctx->host_res = nullptr;
+        ctx->host_res_cap = 0;
+        if (hipHostMalloc((void **)&ctx->host_res, sizeof(Partial) * P.size(), hipHostMallocDefault) != hipSuccess)
+            return fail(TOR_ENOMEM, "pinned allocation failed");
+        ctx->host_res_cap = P.size();
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->host_res, dj + off_res, sizeof(Partial) * P.size(), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    T = dd_make(ctx->host_res->t_hi, ctx->host_res->t_lo);
-    A = ctx->host_res->a;
     if (ctx->timing) {
         ctx->stats.expand_ms += elapsed(ctx->ev[0], ctx->ev[1]);
         ctx->stats.wave_ms += elapsed(ctx->ev[1], ctx->ev[2]);
         ctx->stats.reduce_ms += elapsed(ctx->ev[2], ctx->ev[3]);
     }
-    ctx->stats.expand_launches += G;
-    ctx->stats.wave_launches += 1;
-    ctx->stats.reduce_launches += nred;
-    ctx->stats.subsets += std::ldexp(1.0, n);
-    if (!std::isfinite(T.hi) || !std::isfinite(A))
-        return fail(TOR_ENOTPD, "a Schur pivot was not positive (non-physical or near-singular covariance)");
+    ctx->stats.expand_launches += Gmax;
+    ctx->stats.wave_launches += (int64_t)wgroups.size();
+    ctx->stats.reduce_launches += (int64_t)red_launch.size() + 1;
+    for (size_t i = 0; i < P.size(); i++) {
+        SumOut &o = out[P[i].q];
+        o.T = dd_make(ctx->host_res[i].t_hi, ctx->host_res[i].t_lo);
+        o.A = ctx->host_res[i].a;
+        ctx->stats.subsets += std::ldexp(1.0, P[i].n);
+    }
     return TOR_OK;
+}
+
+// Evaluate subset sums in groups that fit the memory budget.
+tor_status gpu_sums(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vector<int> &which, bool use_dd,
+                    std::vector<SumOut> &out) {
+    const size_t es = use_dd ? sizeof(dd) : sizeof(double);
+    std::vector<int> group;
+    size_t bytes = 0;
+    for (int q : which) {
+        if (in[q].n == 0) {
+            out[q] = SumOut{};
+            continue;
+        }
+        size_t b = sum_bytes(in[q].n, ctx->task_modes, es);
+        if (!group.empty() && (bytes + b > ctx->mem_budget / 2 || group.size() >= 65536)) {
+            tor_status s = gpu_group(ctx, in, group, use_dd, out);
+            if (s) return s;
+            group.clear();
+            bytes = 0;
+        }
+        group.push_back(q);
+        bytes += b;
+    }
+    return gpu_group(ctx, in, group, use_dd, out);
 }
 
 void pack_lower(const std::vector<dd> &full, int n, std::vector<dd> &packed) {
@@ -351,52 +544,101 @@ void pack_lower(const std::vector<dd> &full, int n, std::vector<dd> &packed) {
         for (int b = 0; b <= a; b++) packed[(size_t)pidx(a, b)] = full[(size_t)a * d + b];
 }
 
-// Full evaluation from Sigma_C: PD check and log det on the host, the subset
-// sum on the GPU with the requested precision policy, and the final fields.
-tor_status evaluate(tor_ctx *ctx, const std::vector<dd> &sig, int n, dd pvac, double log_pvac, tor_prec prec,
-                    double tol, tor_result *out) {
-    if (!out) return fail(TOR_EINVAL, "out is NULL");
+// A query reduced to its conditioned matrix, ready for the GPU.
+struct Prepared {
+    std::vector<dd> packed;
+    int n = 0;
+    dd pvac = {1.0, 0.0};
+    double log_pvac = 0.0;
+    double log_det = 0.0;
+    tor_status status = TOR_OK;
+    std::string err;
+};
+
+// PD check and log det of Sigma_C on the host; packs Sigma_C.
+tor_status prepare(const std::vector<dd> &sig, int n, dd pvac, double log_pvac, Prepared &p) {
+    p.n = n;
+    p.pvac = pvac;
+    p.log_pvac = log_pvac;
+    std::vector<dd> chol = sig, rinv;
+    if (n > 0 && !dd_cholesky(chol, 2 * n, rinv, &p.log_det))
+        return fail(TOR_ENOTPD, "Sigma_C is not positive definite");
+    pack_lower(sig, n, p.packed);
+    return TOR_OK;
+}
+
+double bound_of(int used, int n, dd T, double A) {
+    double R = A / std::fabs(T.hi);
+    return kBoundC * std::max(n, 1) * (used == TOR_PREC_DD ? kUDD : kUF64) * R;
+}
+
+void finalize(const Prepared &p, const SumOut &s, int used, double tol, tor_result *out) {
+    const dd T = s.T;
+    const double A = s.A;
+    dd pr = dd_mul(p.pvac, T);
+    std::memset(out, 0, sizeof *out);
+    out->p = pr.hi + pr.lo;
+    out->p_lo = pr.lo - (out->p - pr.hi);
+    out->log_p = out->p > 0 ? p.log_pvac + std::log(T.hi) + std::log1p(T.lo / T.hi) : -INFINITY;
+    out->T = T.hi;
+    out->T_lo = T.lo;
+    out->tor = std::exp(0.5 * p.log_det) * (T.hi + T.lo);
+    out->abs_sum = A;
+    out->cancel_ratio = A / std::fabs(T.hi);
+    out->rel_err_bound = bound_of(used, p.n, T, A);
+    out->log_pvac_n = p.log_pvac;
+    out->n_clicks = p.n;
+    out->prec_used = used;
+    out->status = out->rel_err_bound <= tol ? TOR_OK : TOR_WARN_PRECISION;
+}
+
+// Evaluate prepared queries with the precision policy; results in out[i].
+// Queries whose preparation failed keep their error status.
+tor_status evaluate_many(tor_ctx *ctx, std::vector<Prepared> &qs, tor_prec prec, double tol, tor_result *out) {
     if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD)
         return fail(TOR_EINVAL, "bad precision %d", (int)prec);
     if (!(tol > 0.0)) tol = 1e-10;
-    std::vector<dd> chol = sig, rinv;
-    double log_det = 0.0;
-    if (n > 0 && !dd_cholesky(chol, 2 * n, rinv, &log_det))
-        return fail(TOR_ENOTPD, "Sigma_C is not positive definite");
-    std::vector<dd> packed;
-    pack_lower(sig, n, packed);
-    dd T;
-    double A;
-    int used = prec == TOR_PREC_DD ? TOR_PREC_DD : TOR_PREC_F64;
-    tor_status s = gpu_subset_sum(ctx, packed, n, used == TOR_PREC_DD, T, A);
-    if (s < 0) return s;
-    auto bound_of = [&](int pu, dd t, double a) {
-        double R = a / std::fabs(t.hi);
-        return kBoundC * std::max(n, 1) * (pu == TOR_PREC_DD ? kUDD : kUF64) * R;
-    };
-    double bound = bound_of(used, T, A);
-    if (prec == TOR_PREC_AUTO && !(bound <= tol) && n > 0) {
-        used = TOR_PREC_DD;
-        s = gpu_subset_sum(ctx, packed, n, true, T, A);
-        if (s < 0) return s;
-        bound = bound_of(used, T, A);
+    std::vector<SumIn> in(qs.size());
+    std::vector<int> ok;
+    for (size_t i = 0; i < qs.size(); i++) {
+        in[i].packed = &qs[i].packed;
+        in[i].n = qs[i].n;
+        if (qs[i].status == TOR_OK) ok.push_back((int)i);
     }
-    dd p = dd_mul(pvac, T);
-    std::memset(out, 0, sizeof *out);
-    out->p = p.hi + p.lo;
-    out->p_lo = p.lo - (out->p - p.hi);
-    out->log_p = out->p > 0 ? log_pvac + std::log(T.hi) + std::log1p(T.lo / T.hi) : -INFINITY;
-    out->T = T.hi;
-    out->T_lo = T.lo;
-    out->tor = std::exp(0.5 * log_det) * (T.hi + T.lo);
-    out->abs_sum = A;
-    out->cancel_ratio = A / std::fabs(T.hi);
-    out->rel_err_bound = bound;
-    out->log_pvac_n = log_pvac;
-    out->n_clicks = n;
-    out->prec_used = used;
-    out->status = bound <= tol ? TOR_OK : TOR_WARN_PRECISION;
-    return out->status;
+    std::vector<SumOut> res(qs.size());
+    std::vector<int> used(qs.size(), prec == TOR_PREC_DD ? TOR_PREC_DD : TOR_PREC_F64);
+    tor_status s = gpu_sums(ctx, in, ok, prec == TOR_PREC_DD, res);
+    if (s < 0) return s;
+    if (prec == TOR_PREC_AUTO) {
+        std::vector<int> redo;
+        for (int i : ok)
+            if (qs[i].n > 0 && !(bound_of(TOR_PREC_F64, qs[i].n, res[i].T, res[i].A) <= tol)) redo.push_back(i);
+        if (!redo.empty()) {
+            s = gpu_sums(ctx, in, redo, true, res);
+            if (s < 0) return s;
+            for (int i : redo) used[i] = TOR_PREC_DD;
+        }
+    }
+    tor_status first = TOR_OK;
+    for (size_t i = 0; i < qs.size(); i++) {
+        if (qs[i].status != TOR_OK) {
+            std::memset(&out[i], 0, sizeof out[i]);
+            out[i].status = qs[i].status;
+            if (first >= 0) first = qs[i].status;
+            continue;
+        }
+        if (!std::isfinite(res[i].T.hi) || !std::isfinite(res[i].A)) {
+            std::memset(&out[i], 0, sizeof out[i]);
+            out[i].status = TOR_ENOTPD;
+            if (first >= 0) {
+                first = fail(TOR_ENOTPD, "a Schur pivot was not positive (non-physical or near-singular covariance)");
+            }
+            continue;
+        }
+        finalize(qs[i], res[i], used[i], tol, &out[i]);
+        if (out[i].status == TOR_WARN_PRECISION && first == TOR_OK) first = TOR_WARN_PRECISION;
+    }
+    return first;
 }
 
 }  // namespace
@@ -422,11 +664,12 @@ tor_status tor_ctx_create(int device, tor_ctx **out) {
         return fail(TOR_EDEVICE, "hipStreamCreate failed");
     }
     c->stream = c->own_stream;
-    if (hipHostMalloc((void **)&c->host_res, sizeof(Partial) * 4, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->host_res, sizeof(Partial) * 64, hipHostMallocDefault) != hipSuccess) {
         (void)hipStreamDestroy(c->own_stream);
         delete c;
         return fail(TOR_ENOMEM, "pinned allocation failed");
     }
+    c->host_res_cap = 64;
     for (auto &e : c->ev) (void)hipEventCreate(&e);
     *out = c;
     return TOR_OK;
@@ -441,6 +684,7 @@ void tor_ctx_destroy(tor_ctx *c) {
     c->descB.release();
     c->partA.release();
     c->partB.release();
+    c->jobs.release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->host_res) (void)hipHostFree(c->host_res);
@@ -498,7 +742,11 @@ tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int
     double log_pvac;
     s = reduce_pattern(cov, m, pattern, sig, n, pvac, log_pvac);
     if (s) return s;
-    return evaluate(ctx, sig, n, pvac, log_pvac, prec, tol, out);
+    if (!out) return fail(TOR_EINVAL, "out is NULL");
+    std::vector<Prepared> qs(1);
+    s = prepare(sig, n, pvac, log_pvac, qs[0]);
+    if (s) return s;
+    return evaluate_many(ctx, qs, prec, tol, out);
 }
 
 tor_status tor_subset_sum(tor_ctx *ctx, const double *sigma_hi, const double *sigma_lo, int32_t n, tor_prec prec,
@@ -523,7 +771,11 @@ tor_status tor_subset_sum(tor_ctx *ctx, const double *sigma_hi, const double *si
                 return fail(TOR_EINVAL, "Sigma is not symmetric at (%d, %d)", i, j);
             sig[(size_t)j * d + i] = sig[(size_t)i * d + j];
         }
-    return evaluate(ctx, sig, n, dd_from(1.0), 0.0, prec, tol, out);
+    if (!out) return fail(TOR_EINVAL, "out is NULL");
+    std::vector<Prepared> qs(1);
+    tor_status s = prepare(sig, n, dd_from(1.0), 0.0, qs[0]);
+    if (s) return s;
+    return evaluate_many(ctx, qs, prec, tol, out);
 }
 
 tor_status tor_state_create(tor_ctx *ctx, const double *cov, int32_t m, tor_state **out) {
@@ -553,23 +805,20 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
     if (st->ctx != ctx) return fail(TOR_EINVAL, "state belongs to another context");
     if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
     HIP_TRY(hipSetDevice(ctx->device));
-    tor_status first = TOR_OK;
+    std::vector<Prepared> qs((size_t)nq);
     for (int q = 0; q < nq; q++) {
         std::vector<dd> sig;
         int n = 0;
         dd pvac;
         double log_pvac;
         tor_status s = reduce_pattern(st->cov.data(), st->m, patterns + (size_t)q * st->m, sig, n, pvac, log_pvac);
-        if (s == TOR_OK) s = evaluate(ctx, sig, n, pvac, log_pvac, prec, tol, &out[q]);
-        if (s < 0) {
-            std::memset(&out[q], 0, sizeof out[q]);
-            out[q].status = s;
-            if (first >= 0) first = s;
-        } else if (s == TOR_WARN_PRECISION && first == TOR_OK) {
-            first = s;
+        if (s == TOR_OK) s = prepare(sig, n, pvac, log_pvac, qs[q]);
+        if (s != TOR_OK) {
+            qs[q].status = s;
+            qs[q].n = 0;
         }
     }
-    return first;
+    return evaluate_many(ctx, qs, prec, tol, out);
 }
 
 }  // extern "C"

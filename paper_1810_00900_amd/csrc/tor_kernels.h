@@ -20,15 +20,41 @@ struct Partial {
     double t_hi, t_lo, a, pad;
 };
 
-#ifdef __cplusplus
-extern "C" {
-#endif
-hipError_t tor_launch_wave(int is_dd, int J, const NodeDesc *tasks, long long ntasks, const void *pool,
-                           Partial *out, int grid_cap, hipStream_t st);
-hipError_t tor_launch_expand(int is_dd, const NodeDesc *par, long long npar, int r, void *pool,
-                             unsigned long long child_base, NodeDesc *chi, int grid_cap, hipStream_t st);
-hipError_t tor_launch_reduce(const Partial *in, long long n, long long chunk, Partial *out, hipStream_t st);
-int tor_wave_lds_bytes(int is_dd, int J);
-#ifdef __cplusplus
-}
-#endif
+// Work lists of the batched launches.  Several queries (each its own subset
+// tree) share one launch; each job is one query's share, and a block finds its
+// job from its flat index, so the work done for a query never depends on the
+// other queries in the launch.
+
+// expansion of level d of one query: 2^d parent nodes with r modes
+struct ExpandJob {
+    const NodeDesc *par;
+    NodeDesc *chi;
+    unsigned long long child_base;
+    int r;
+    int pad;
+};
+
+// wave-tier tasks of one query: tasks[0 .. count) -> out[0 .. count); the
+// flat task index of tasks[0] is `begin` (jobs sorted by begin)
+struct WaveJob {
+    const NodeDesc *tasks;
+    Partial *out;
+    long long begin;
+};
+
+// one reduction stage of one query: in[0 .. count) -> out[0 .. ceil(count/chunk))
+struct ReduceJob {
+    const Partial *in;
+    Partial *out;
+    long long count;
+    long long block_begin;
+};
+
+#define TOR_REDUCE_CHUNK 1024
+
+hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
+                           int grid_cap, hipStream_t st);
+hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
+                             hipStream_t st);
+hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_blocks, hipStream_t st);
+hipError_t tor_launch_gather(const Partial *const *src, int n, Partial *dst, hipStream_t st);

@@ -213,9 +213,21 @@ template <class S, int J, int K> struct WaveLevel {
     }
 };
 
+// index of the last job whose begin <= t (jobs sorted by begin, jobs[0].begin == 0)
+template <class Job>
+__device__ __forceinline__ int find_job(const Job *jobs, int njobs, long long t) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <class S, int J>
-__global__ __launch_bounds__(64) void wave_kernel(const NodeDesc *__restrict__ tasks, long long ntasks,
-                                                  const S *__restrict__ pool, Partial *__restrict__ out) {
+__global__ __launch_bounds__(64) void wave_kernel(const WaveJob *__restrict__ jobs, int njobs, long long total,
+                                                  const S *__restrict__ pool) {
     using C = WaveCfg<S, J>;
     __shared__ S mat[C::MAT];
     __shared__ S vbuf[C::VMAX];
@@ -224,8 +236,10 @@ __global__ __launch_bounds__(64) void wave_kernel(const NodeDesc *__restrict__ t
     __shared__ dd coef[C::NL];
     __shared__ double acoef[C::NL];
     const int lane = threadIdx.x;
-    for (long long t = blockIdx.x; t < ntasks; t += gridDim.x) {
-        NodeDesc d = tasks[t];
+    for (long long t = blockIdx.x; t < total; t += gridDim.x) {
+        const int j = find_job(jobs, njobs, t);
+        const long long lt = t - jobs[j].begin;
+        NodeDesc d = jobs[j].tasks[lt];
         const S *root = pool + d.off;
         for (int e = lane; e < E(J); e += 64) mat[e] = root[e];
         if (lane == 0) {
@@ -255,7 +269,7 @@ __global__ __launch_bounds__(64) void wave_kernel(const NodeDesc *__restrict__ t
             p.t_lo = T.lo;
             p.a = A;
             p.pad = 0.0;
-            out[t] = p;
+            jobs[j].out[lt] = p;
         }
         __syncthreads();
     }
@@ -264,25 +278,26 @@ __global__ __launch_bounds__(64) void wave_kernel(const NodeDesc *__restrict__ t
 // ---------------------------------------------------------------- HBM tier
 
 template <class S>
-__global__ __launch_bounds__(256) void expand_kernel(const NodeDesc *__restrict__ par, long long npar, int r,
-                                                     S *__restrict__ pool, unsigned long long child_base,
-                                                     NodeDesc *__restrict__ chi) {
+__global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict__ jobs, int log2npar,
+                                                     long long total, S *__restrict__ pool) {
     __shared__ S v[2][2 * TOR_MAX_N];
-    const int R = 2 * r, RC = R - 2, EC = E(r - 1);
-    for (long long i = blockIdx.x; i < npar; i += gridDim.x) {
-        NodeDesc d = par[i];
+    for (long long f = blockIdx.x; f < total; f += gridDim.x) {
+        const ExpandJob job = jobs[f >> log2npar];
+        const long long i = f & ((1LL << log2npar) - 1);
+        const int r = job.r, R = 2 * r, RC = R - 2, EC = E(r - 1);
+        NodeDesc d = job.par[i];
         const S *base = pool + d.off;
         Pivot<S> pv = make_pivot(base[pidx(R - 2, R - 2)], base[pidx(R - 1, R - 2)], base[pidx(R - 1, R - 1)]);
-        unsigned long long coff = child_base + (unsigned long long)i * (unsigned long long)EC;
+        unsigned long long coff = job.child_base + (unsigned long long)i * (unsigned long long)EC;
         if (threadIdx.x == 0) {
-            chi[2 * i] = d;
+            job.chi[2 * i] = d;
             NodeDesc c;
             c.off = coff;
             dd cf = dd_neg(coef_mul(dd_make(d.coef_hi, d.coef_lo), pv.q));
             c.coef_hi = cf.hi;
             c.coef_lo = cf.lo;
             c.acoef = d.acoef * hi_of(pv.q);
-            chi[2 * i + 1] = c;
+            job.chi[2 * i + 1] = c;
         }
         for (int c = threadIdx.x; c < RC; c += blockDim.x) {
             S m0 = base[pidx(R - 2, c)];
@@ -302,121 +317,117 @@ __global__ __launch_bounds__(256) void expand_kernel(const NodeDesc *__restrict_
 
 // ---------------------------------------------------------------- reduction
 
-// Stage 1: block b sums partials [b*chunk, min((b+1)*chunk, n)) in a fixed
-// order (thread-strided sequential sums, then a fixed LDS tree).
-__global__ __launch_bounds__(256) void reduce_kernel(const Partial *__restrict__ in, long long n, long long chunk,
-                                                     Partial *__restrict__ out) {
+// One reduction stage: block b of a job sums in[b*chunk, min((b+1)*chunk, count))
+// in a fixed order (thread-strided sequential sums, then a fixed LDS tree).
+__global__ __launch_bounds__(256) void reduce_kernel(const ReduceJob *__restrict__ jobs, int njobs,
+                                                     long long total_blocks) {
     __shared__ dd sT[256];
     __shared__ double sA[256];
-    long long lo = (long long)blockIdx.x * chunk;
-    long long hi = lo + chunk < n ? lo + chunk : n;
-    dd T = dd_from(0.0);
-    double A = 0.0;
-    for (long long k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-        Partial p = in[k];
-        T = dd_add(T, dd_make(p.t_hi, p.t_lo));
-        A += p.a;
-    }
-    sT[threadIdx.x] = T;
-    sA[threadIdx.x] = A;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            sT[threadIdx.x] = dd_add(sT[threadIdx.x], sT[threadIdx.x + s]);
-            sA[threadIdx.x] = sA[threadIdx.x] + sA[threadIdx.x + s];
+    for (long long gb = blockIdx.x; gb < total_blocks; gb += gridDim.x) {
+        int lo_j = 0, hi_j = njobs - 1;
+        while (lo_j < hi_j) {
+            int mid = (lo_j + hi_j + 1) >> 1;
+            if (jobs[mid].block_begin <= gb) lo_j = mid;
+            else hi_j = mid - 1;
+        }
+        const ReduceJob job = jobs[lo_j];
+        const long long b = gb - job.block_begin;
+        long long lo = b * TOR_REDUCE_CHUNK;
+        long long hi = lo + TOR_REDUCE_CHUNK < job.count ? lo + TOR_REDUCE_CHUNK : job.count;
+        dd T = dd_from(0.0);
+        double A = 0.0;
+        for (long long k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+            Partial p = job.in[k];
+            T = dd_add(T, dd_make(p.t_hi, p.t_lo));
+            A += p.a;
+        }
+        sT[threadIdx.x] = T;
+        sA[threadIdx.x] = A;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) {
+                sT[threadIdx.x] = dd_add(sT[threadIdx.x], sT[threadIdx.x + s]);
+                sA[threadIdx.x] = sA[threadIdx.x] + sA[threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            Partial p;
+            p.t_hi = sT[0].hi;
+            p.t_lo = sT[0].lo;
+            p.a = sA[0];
+            p.pad = 0.0;
+            job.out[b] = p;
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        Partial p;
-        p.t_hi = sT[0].hi;
-        p.t_lo = sT[0].lo;
-        p.a = sA[0];
-        p.pad = 0.0;
-        out[blockIdx.x] = p;
-    }
+}
+
+__global__ void gather_kernel(const Partial *const *__restrict__ src, int n, Partial *__restrict__ dst) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = *src[i];
 }
 
 // ---------------------------------------------------------------- launchers
 
 template <class S, int J>
-static hipError_t launch_wave_J(const NodeDesc *tasks, long long ntasks, const void *pool, Partial *out,
-                                int grid_cap, hipStream_t st) {
-    long long g = ntasks < grid_cap ? ntasks : grid_cap;
-    if (g < 1) g = 1;
-    hipLaunchKernelGGL((wave_kernel<S, J>), dim3((unsigned)g), dim3(64), 0, st, tasks, ntasks,
-                       (const S *)pool, out);
+static hipError_t launch_wave_J(const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
+                                hipStream_t st) {
+    long long g = total < grid_cap ? total : grid_cap;
+    if (g < 1) return hipSuccess;
+    hipLaunchKernelGGL((wave_kernel<S, J>), dim3((unsigned)g), dim3(64), 0, st, jobs, njobs, total,
+                       (const S *)pool);
     return hipGetLastError();
 }
 
 template <class S>
-static hipError_t launch_wave_S(int J, const NodeDesc *tasks, long long ntasks, const void *pool, Partial *out,
+static hipError_t launch_wave_S(int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
                                 int grid_cap, hipStream_t st) {
     switch (J) {
-    case 1: return launch_wave_J<S, 1>(tasks, ntasks, pool, out, grid_cap, st);
-    case 2: return launch_wave_J<S, 2>(tasks, ntasks, pool, out, grid_cap, st);
-    case 3: return launch_wave_J<S, 3>(tasks, ntasks, pool, out, grid_cap, st);
-    case 4: return launch_wave_J<S, 4>(tasks, ntasks, pool, out, grid_cap, st);
-    case 5: return launch_wave_J<S, 5>(tasks, ntasks, pool, out, grid_cap, st);
-    case 6: return launch_wave_J<S, 6>(tasks, ntasks, pool, out, grid_cap, st);
-    case 7: return launch_wave_J<S, 7>(tasks, ntasks, pool, out, grid_cap, st);
-    case 8: return launch_wave_J<S, 8>(tasks, ntasks, pool, out, grid_cap, st);
-    case 9: return launch_wave_J<S, 9>(tasks, ntasks, pool, out, grid_cap, st);
+    case 1: return launch_wave_J<S, 1>(jobs, njobs, total, pool, grid_cap, st);
+    case 2: return launch_wave_J<S, 2>(jobs, njobs, total, pool, grid_cap, st);
+    case 3: return launch_wave_J<S, 3>(jobs, njobs, total, pool, grid_cap, st);
+    case 4: return launch_wave_J<S, 4>(jobs, njobs, total, pool, grid_cap, st);
+    case 5: return launch_wave_J<S, 5>(jobs, njobs, total, pool, grid_cap, st);
+    case 6: return launch_wave_J<S, 6>(jobs, njobs, total, pool, grid_cap, st);
+    case 7: return launch_wave_J<S, 7>(jobs, njobs, total, pool, grid_cap, st);
+    case 8: return launch_wave_J<S, 8>(jobs, njobs, total, pool, grid_cap, st);
+    case 9: return launch_wave_J<S, 9>(jobs, njobs, total, pool, grid_cap, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace tor
 
-extern "C" {
-
-hipError_t tor_launch_wave(int is_dd, int J, const NodeDesc *tasks, long long ntasks, const void *pool,
-                           Partial *out, int grid_cap, hipStream_t st) {
-    return is_dd ? tor::launch_wave_S<dd>(J, tasks, ntasks, pool, out, grid_cap, st)
-                 : tor::launch_wave_S<double>(J, tasks, ntasks, pool, out, grid_cap, st);
+hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
+                           int grid_cap, hipStream_t st) {
+    return is_dd ? tor::launch_wave_S<dd>(J, jobs, njobs, total, pool, grid_cap, st)
+                 : tor::launch_wave_S<double>(J, jobs, njobs, total, pool, grid_cap, st);
 }
 
-hipError_t tor_launch_expand(int is_dd, const NodeDesc *par, long long npar, int r, void *pool,
-                             unsigned long long child_base, NodeDesc *chi, int grid_cap, hipStream_t st) {
-    long long g = npar < grid_cap ? npar : grid_cap;
-    if (g < 1) g = 1;
-    if (r < 2 || r > TOR_MAX_N) return hipErrorInvalidValue;
+hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
+                             hipStream_t st) {
+    long long total = (long long)njobs << log2npar;
+    long long g = total < grid_cap ? total : grid_cap;
+    if (g < 1) return hipSuccess;
     if (is_dd)
-        hipLaunchKernelGGL(tor::expand_kernel<dd>, dim3((unsigned)g), dim3(256), 0, st, par, npar, r, (dd *)pool,
-                           child_base, chi);
+        hipLaunchKernelGGL(tor::expand_kernel<dd>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
+                           (dd *)pool);
     else
-        hipLaunchKernelGGL(tor::expand_kernel<double>, dim3((unsigned)g), dim3(256), 0, st, par, npar, r,
-                           (double *)pool, child_base, chi);
+        hipLaunchKernelGGL(tor::expand_kernel<double>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
+                           (double *)pool);
     return hipGetLastError();
 }
 
-hipError_t tor_launch_reduce(const Partial *in, long long n, long long chunk, Partial *out, hipStream_t st) {
-    long long nb = (n + chunk - 1) / chunk;
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(tor::reduce_kernel, dim3((unsigned)nb), dim3(256), 0, st, in, n, chunk, out);
+hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_blocks, hipStream_t st) {
+    long long g = total_blocks < (1LL << 20) ? total_blocks : (1LL << 20);
+    if (g < 1) return hipSuccess;
+    hipLaunchKernelGGL(tor::reduce_kernel, dim3((unsigned)g), dim3(256), 0, st, jobs, njobs, total_blocks);
     return hipGetLastError();
 }
 
-int tor_wave_lds_bytes(int is_dd, int J) {
-    // reported for tuning/diagnostics; mirrors WaveCfg
-    int bytes = 0;
-    auto f = [&](auto tag) {
-        using S = decltype(tag);
-        switch (J) {
-#define TOR_CASE(JJ)                                                                              \
-    case JJ: {                                                                                    \
-        using C = tor::WaveCfg<S, JJ>;                                                            \
-        bytes = (int)(sizeof(S) * (C::MAT + C::VMAX) + sizeof(tor::Pivot<S>) * C::NPIV +          \
-                      C::NL * (sizeof(int) + sizeof(dd) + sizeof(double)));                       \
-    } break;
-            TOR_CASE(1) TOR_CASE(2) TOR_CASE(3) TOR_CASE(4) TOR_CASE(5) TOR_CASE(6) TOR_CASE(7) TOR_CASE(8)
-            TOR_CASE(9)
-#undef TOR_CASE
-        default: bytes = -1;
-        }
-    };
-    if (is_dd) f(dd{}); else f(0.0);
-    return bytes;
+hipError_t tor_launch_gather(const Partial *const *src, int n, Partial *dst, hipStream_t st) {
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(tor::gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, n, dst);
+    return hipGetLastError();
 }
-
-}  // extern "C"

@@ -303,6 +303,31 @@ def test_batch_matches_single(ctx, cov800):
         assert (r.p, r.p_lo) == (s.p, s.p_lo)
 
 
+def test_batch_mixed_sizes_and_errors(ctx, cov800):
+    """A batch mixing tree sizes (n = 0..20, J < 9 and J = 9 trees), an
+    invalid pattern and duplicates: every valid result equals the same query
+    run alone, bitwise; the invalid one reports its own status."""
+    st = ctx.state(cov800)
+    rng = np.random.default_rng(9)
+    ns = [0, 1, 2, 5, 8, 9, 10, 13, 17, 20, 3, 9]
+    pats = [gi.marginal_pattern(800, gi.random_click_set(800, n, rng)) for n in ns]
+    bad = pats[3].copy()
+    bad[7] = 5
+    pats.insert(4, bad)
+    pats.append(pats[7].copy())
+    res, status = ctx.batch(st, np.stack(pats), prec="auto", tol=1e-10)
+    assert status == tg.TOR_EINVAL
+    assert res[4].status == tg.TOR_EINVAL
+    for i, (p, r) in enumerate(zip(pats, res)):
+        if i == 4:
+            continue
+        s = ctx.probability(cov800, p, prec="auto", tol=1e-10)
+        assert (r.p, r.p_lo, r.abs_sum, r.prec_used) == (s.p, s.p_lo, s.abs_sum, s.prec_used), i
+        o = oracle.prob(cov800, p) if r.n_clicks <= 14 else None
+        if o is not None:
+            assert _rel(_gpu_p(r), _orc_p(o)) <= 1e-10
+
+
 # ---------------------------------------------------------------- errors
 
 def test_errors(ctx):
