@@ -154,6 +154,50 @@ void tor_state_destroy(tor_state *st);
 tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *patterns, tor_prec prec,
                      double tol, tor_result *out);
 
+/* ------------------------------------------------------------------------
+ * Exact chain-rule sampling (the paper's mode-by-mode sampler, Sec. II: each
+ * mode's coin is flipped with the conditional no-click probability given the
+ * outcomes so far; here that probability is a ratio of two subset sums).
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t chains_started;   /* chains consumed to produce the samples (deterministic) */
+    int64_t chains_accepted;  /* = samples produced */
+    int64_t chains_evaluated; /* chains the GPU ran (whole launches) */
+    int64_t chains_capped;    /* chains stopped because the clicks exceeded TOR_CHAIN_CLICKS */
+    double seconds;           /* wall time of the call */
+    double subsets;           /* subset terms evaluated over the consumed chains */
+} gbs_stats;
+
+#define TOR_CHAIN_CLICKS 15   /* largest click count a chain may carry */
+
+/* Draw n_samples threshold-detector samples of the zero-mean Gaussian state
+ * `cov` (m modes, conventions above).  Modes are measured in ascending order;
+ * chain c draws its coin at mode j from Philox4x32-10 with key = seed and
+ * counter (c, j), so the output depends only on (cov, n_post, seed).  With
+ * n_post >= 0 only chains with exactly n_post clicks are accepted (exact
+ * rejection with early stopping: the accepted samples follow the
+ * distribution conditioned on n_post clicks); with n_post < 0 every chain is
+ * accepted.  Samples are the first accepted chains in chain order.
+ * samples: host, n_samples x m bytes (0/1).  stats may be NULL.
+ * Per-mode probabilities use binary64 matrices (K_j = sigma_Q[0..j]^-1 formed
+ * in double-double and rounded once) and double-double sums.
+ * Errors: TOR_EINVAL, TOR_ETOOBIG (n_post > TOR_CHAIN_CLICKS or m > 1024),
+ * TOR_EAGAIN (no sample after 2^31 chains), TOR_ENOMEM, TOR_EDEVICE. */
+tor_status gbs_sample(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,
+                      int32_t n_samples, uint8_t *samples, gbs_stats *stats);
+
+/* Replay chains chain_begin .. chain_begin + nchains - 1 of gbs_sample with
+ * the same (cov, n_post, seed) and report, per chain and mode, the click
+ * probability used (NaN after the chain stopped), the uniform draw and the
+ * outcome, and per chain its status (1 accepted, 0 rejected, 2 capped).  Any
+ * output pointer may be NULL.  Arrays are host, nchains x m (row per chain).
+ * A chain is resumable from (seed, chain index): the coins are a pure
+ * function of the counter. */
+tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,
+                     int64_t chain_begin, int32_t nchains, double *p_click, double *uniform, uint8_t *outcome,
+                     int8_t *status);
+
 #ifdef __cplusplus
 }
 #endif

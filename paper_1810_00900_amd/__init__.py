@@ -59,6 +59,12 @@ class _CStats(ctypes.Structure):
                 ("subsets", ctypes.c_double)]
 
 
+class _CGbsStats(ctypes.Structure):
+    _fields_ = [("chains_started", ctypes.c_int64), ("chains_accepted", ctypes.c_int64),
+                ("chains_evaluated", ctypes.c_int64), ("chains_capped", ctypes.c_int64),
+                ("seconds", ctypes.c_double), ("subsets", ctypes.c_double)]
+
+
 @dataclass
 class Result:
     p: float
@@ -118,6 +124,10 @@ def lib():
         "tor_state_destroy": ([vp], None),
         "tor_batch": ([vp, vp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
                        ctypes.POINTER(_CResult)], ctypes.c_int32),
+        "gbs_sample": ([vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                        ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(_CGbsStats)], ctypes.c_int32),
+        "gbs_trace": ([vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
+                       dp, dp, ctypes.POINTER(ctypes.c_uint8), i8p], ctypes.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -222,6 +232,30 @@ class Context:
         _check(lib().tor_subset_sum(self._h, _dptr(sigma), None if lo is None else _dptr(lo), n, _PREC[prec],
                                     float(tol), ctypes.byref(r)))
         return Result._from(r)
+
+    def gbs_sample(self, cov, n_post: int, seed: int, n_samples: int):
+        """Exact chain-rule threshold samples (gbs_sample); returns
+        (samples uint8[n_samples, m], stats dict)."""
+        cov = _f64(cov)
+        m = cov.shape[0] // 2
+        out = np.zeros((n_samples, m), dtype=np.uint8)
+        st = _CGbsStats()
+        _check(lib().gbs_sample(self._h, _dptr(cov), m, int(n_post), int(seed) & (2**64 - 1), int(n_samples),
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(st)))
+        return out, {f: getattr(st, f) for f, _ in _CGbsStats._fields_}
+
+    def gbs_trace(self, cov, n_post: int, seed: int, chain_begin: int, nchains: int):
+        """Replay chains of gbs_sample: (p_click, uniform, outcome, status)."""
+        cov = _f64(cov)
+        m = cov.shape[0] // 2
+        pc = np.zeros((nchains, m))
+        un = np.zeros((nchains, m))
+        oc = np.zeros((nchains, m), dtype=np.uint8)
+        stt = np.zeros(nchains, dtype=np.int8)
+        _check(lib().gbs_trace(self._h, _dptr(cov), m, int(n_post), int(seed) & (2**64 - 1), int(chain_begin),
+                               int(nchains), _dptr(pc), _dptr(un), oc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                               _i8ptr(stt)))
+        return pc, un, oc, stt
 
     def state(self, cov) -> "State":
         return State(self, cov)

@@ -1,0 +1,257 @@
+// Exact chain-rule sampling of threshold-detector GBS on the GPU.
+//
+// A sample is drawn mode by mode in ascending order (the paper's algorithm
+// measures one mode at a time, Sec. II; any order is exact).  At mode j, with
+// clicked set C and no-click set N among the modes before j, the probability of
+// no click is p(C, N + j) / p(C, N).  Because every mode before j is in C or N,
+// the vacuum-conditioned matrix of C + {j} is the inverse of
+// G = K_j[C + j], K_j = (sigma_Q[0..j])^-1 (a Jacobi complementary-minor
+// identity), and the subset sum over Sigma = G^-1 equals +-det(G)^{1/2} times the
+// same sum over G.  Deciding j first in the tree over G splits it into
+// X0 = T(G[C]) and X1 = q_j T(G / G_jj); then P(no click at j) = X0 / X1.  So a
+// chain carries only its click list; the K_j are shared by all chains.
+//
+// One 64-lane workgroup runs one chain at a time: per mode it gathers G into
+// LDS, evaluates the split subset tree (the wave tier; modes above 9 by a loop
+// over the top decisions with rank-2 Schur updates in LDS), draws the coin from
+// Philox4x32-10 keyed by (seed, chain, mode), and stops early when the
+// postselection on n clicks can no longer be met.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dd.hpp"
+#include "tor_kernels.h"
+#include "tor_tree.hpp"
+
+#pragma clang fp contract(off)
+
+namespace tor {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
+// multiply-xor round with multipliers 0xD2511F53, 0xCD9E8D57 and Weyl key
+// increments 0x9E3779B9, 0xBB67AE85.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k.x += 0x9E3779B9u;
+            k.y += 0xBB67AE85u;
+        }
+        const unsigned lo0 = c.x * 0xD2511F53u, hi0 = __umulhi(c.x, 0xD2511F53u);
+        const unsigned lo1 = c.z * 0xCD9E8D57u, hi1 = __umulhi(c.z, 0xCD9E8D57u);
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    }
+    return c;
+}
+
+// uniform in [0, 1) with 53 random bits from the first two output words
+__device__ __forceinline__ double philox_uniform(unsigned long long seed, long long chain, int step) {
+    uint4 x = philox4x32_10(make_uint4((unsigned)chain, (unsigned)((unsigned long long)chain >> 32),
+                                       (unsigned)step, 0u),
+                            make_uint2((unsigned)seed, (unsigned)(seed >> 32)));
+    unsigned long long b = ((unsigned long long)x.x << 21) | (unsigned long long)(x.y >> 11);
+    return (double)b * 0x1.0p-53;
+}
+
+// Root split of a TL-mode tree for J <= 3 (one leaf): X0 = T(exclude last),
+// X1s = -q T(include last).
+template <class S, int R>
+__device__ __forceinline__ void leaf_split(const S *M, dd &X0, dd &X1s) {
+    if constexpr (R == 1) {
+        S q = rsqrt_s(det2(M[0], M[1], M[2]));
+        X0 = dd_from(1.0);
+        X1s = dd_neg(to_dd(q));
+    } else {
+        constexpr int p0 = 2 * R - 2, p1 = 2 * R - 1, RC = 2 * R - 2;
+        double A0;
+        Leaf<S, R - 1>::run(M, X0, A0);
+        Pivot<S> pv = make_pivot(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)]);
+        S v1[RC], v2[RC];
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+            S m0 = M[pidx(p0, c)];
+            v1[c] = mul_s(m0, pv.s1);
+            v2[c] = mul_s(sub_mul(M[pidx(p1, c)], pv.l, m0), pv.s2);
+        }
+        S Cm[E(R - 1)];
+#pragma unroll
+        for (int a = 0; a < RC; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) Cm[pidx(a, b)] = sub_dot2(M[pidx(a, b)], v1[a], v1[b], v2[a], v2[b]);
+        dd T1;
+        double A1;
+        Leaf<S, R - 1>::run(Cm, T1, A1);
+        X1s = dd_neg(coef_mul(T1, pv.q));
+    }
+}
+
+// Include-child of an r-mode node in LDS (cooperative rank-2 Schur update of
+// the last mode); returns q.  in and out must not overlap.
+template <class S>
+__device__ __forceinline__ S wave_schur_last(const S *in, int r, S *out, S *vt, int lane) {
+    const int R = 2 * r, RC = R - 2, EC = E(r - 1);
+    Pivot<S> pv = make_pivot(in[pidx(R - 2, R - 2)], in[pidx(R - 1, R - 2)], in[pidx(R - 1, R - 1)]);
+    for (int c = lane; c < RC; c += 64) {
+        S m0 = in[pidx(R - 2, c)];
+        vt[c] = mul_s(m0, pv.s1);
+        vt[RC + c] = mul_s(sub_mul(in[pidx(R - 1, c)], pv.l, m0), pv.s2);
+    }
+    __syncthreads();
+    for (int e = lane; e < EC; e += 64) {
+        int a, b;
+        unpack(e, a, b);
+        out[e] = sub_dot2(in[e], vt[a], vt[b], vt[RC + a], vt[RC + b]);
+    }
+    __syncthreads();
+    return pv.q;
+}
+
+template <class S, int J> struct ChainStep {
+    // tree of the k = J modes already gathered into the wave LDS (k <= 9)
+    static __device__ __forceinline__ void run(unsigned char *raw, int lane, dd &X0, dd &X1s) {
+        using C = WaveCfg<S, J>;
+        WaveSmem<S, J> &sm = *reinterpret_cast<WaveSmem<S, J> *>(raw);
+        if constexpr (C::TW == 0) {
+            X0 = dd_from(0.0);
+            X1s = dd_from(0.0);
+            if (lane == 0) {
+                S M[E(J)];
+#pragma unroll
+                for (int e = 0; e < E(J); ++e) M[e] = sm.mat[e];
+                leaf_split<S, J>(M, X0, X1s);
+            }
+            __syncthreads();
+        } else {
+            dd T;
+            double A;
+            wave_tree<S, J>(sm, dd_from(1.0), 1.0, lane, T, A);
+            X0 = (lane & 1) ? dd_from(0.0) : T;
+            X1s = (lane & 1) ? T : dd_from(0.0);
+            __syncthreads();
+        }
+    }
+};
+
+template <class S> struct ChainLds {
+    static constexpr size_t wave_bytes = sizeof(WaveSmem<S, 9>);
+};
+
+template <class S>
+__global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
+    __shared__ __align__(16) unsigned char raw[ChainLds<S>::wave_bytes];
+    __shared__ S gbuf[3][E(TOR_CHAIN_MAX)];
+    __shared__ S vt[4 * TOR_CHAIN_MAX];
+    __shared__ int Cl[TOR_CHAIN_MAX + 1];
+    const int lane = threadIdx.x;
+    S *wmat = reinterpret_cast<WaveSmem<S, 9> *>(raw)->mat;  // mat[] is the first member for every J
+    for (int ci = blockIdx.x; ci < P.nchains; ci += gridDim.x) {
+        const long long chain = P.chain_begin + ci;
+        int nc = 0;
+        signed char st = 1;
+        double nsub = 0.0;
+        int j = 0;
+        for (; j < P.m; ++j) {
+            if (P.n_post >= 0 && (nc > P.n_post || nc + (P.m - j) < P.n_post)) {
+                st = 0;
+                break;
+            }
+            if (nc + 1 > TOR_CHAIN_MAX) {
+                st = 2;
+                break;
+            }
+            const int k = nc + 1;
+            const int D = 2 * j + 2;
+            const double *Kj = P.K + P.koff[j];
+            S *G = k <= 9 ? wmat : gbuf[0];
+            for (int e = lane; e < E(k); e += 64) {
+                int a, b;
+                unpack(e, a, b);
+                const int ma = (a >> 1) < nc ? Cl[a >> 1] : j;
+                const int mb = (b >> 1) < nc ? Cl[b >> 1] : j;
+                G[e] = (S)from_pair<S>(Kj[(2 * ma + (a & 1)) * D + 2 * mb + (b & 1)], 0.0);
+            }
+            __syncthreads();
+            dd X0 = dd_from(0.0), X1s = dd_from(0.0);
+            if (k <= 9) {
+                switch (k) {
+                case 1: ChainStep<S, 1>::run(raw, lane, X0, X1s); break;
+                case 2: ChainStep<S, 2>::run(raw, lane, X0, X1s); break;
+                case 3: ChainStep<S, 3>::run(raw, lane, X0, X1s); break;
+                case 4: ChainStep<S, 4>::run(raw, lane, X0, X1s); break;
+                case 5: ChainStep<S, 5>::run(raw, lane, X0, X1s); break;
+                case 6: ChainStep<S, 6>::run(raw, lane, X0, X1s); break;
+                case 7: ChainStep<S, 7>::run(raw, lane, X0, X1s); break;
+                case 8: ChainStep<S, 8>::run(raw, lane, X0, X1s); break;
+                default: ChainStep<S, 9>::run(raw, lane, X0, X1s); break;
+                }
+            } else {
+                // decisions on the top u = k - 9 modes (bit b: mode k-1-b; bit 0 is mode j)
+                const int u = k - 9;
+                WaveSmem<S, 9> &sm = *reinterpret_cast<WaveSmem<S, 9> *>(raw);
+                for (int p = 0; p < (1 << u); ++p) {
+                    const S *cur = gbuf[0];
+                    int r = k, nb = 1;
+                    dd c = dd_from(1.0);
+                    double a = 1.0;
+                    for (int b = 0; b < u; ++b, --r) {
+                        if ((p >> b) & 1) {
+                            S *o = gbuf[nb];
+                            S q = wave_schur_last<S>(cur, r, o, vt, lane);
+                            c = dd_neg(coef_mul(c, q));
+                            a *= hi_of(q);
+                            cur = o;
+                            nb = 3 - nb;
+                        }
+                    }
+                    for (int e = lane; e < E(9); e += 64) sm.mat[e] = cur[e];
+                    __syncthreads();
+                    dd T;
+                    double A;
+                    wave_tree<S, 9>(sm, c, a, lane, T, A);
+                    if (p & 1) X1s = dd_add(X1s, T);
+                    else X0 = dd_add(X0, T);
+                    __syncthreads();
+                }
+            }
+            double dummy0 = 0.0, dummy1 = 0.0;
+            wave_reduce(X0, dummy0);
+            wave_reduce(X1s, dummy1);
+            nsub += (double)(1 << k);
+            // P(no click) = X0 / X1 with X1 = -X1s; all lanes hold the same sums
+            const double x0 = X0.hi + X0.lo, x1 = -(X1s.hi + X1s.lo);
+            const double pclick = 1.0 - x0 / x1;
+            const double uni = philox_uniform(P.seed, chain, j);
+            const bool click = uni < pclick;
+            if (lane == 0) {
+                const size_t o = (size_t)ci * (size_t)P.m + (size_t)j;
+                P.outcome[o] = click ? 1 : 0;
+                if (P.trace_p) P.trace_p[o] = pclick;
+                if (P.trace_u) P.trace_u[o] = uni;
+                if (click) Cl[nc] = j;
+            }
+            __syncthreads();
+            if (click) nc++;
+        }
+        if (st == 1 && P.n_post >= 0 && nc != P.n_post) st = 0;
+        for (int jj = j + lane; jj < P.m; jj += 64) {
+            const size_t o = (size_t)ci * (size_t)P.m + (size_t)jj;
+            P.outcome[o] = 0;
+            if (P.trace_p) P.trace_p[o] = __builtin_nan("");
+            if (P.trace_u) P.trace_u[o] = __builtin_nan("");
+        }
+        if (lane == 0) {
+            P.status[ci] = st;
+            if (P.subsets) P.subsets[ci] = nsub;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace tor
+
+hipError_t tor_launch_chains(const ChainParams &P, int grid_cap, hipStream_t st) {
+    int g = P.nchains < grid_cap ? P.nchains : grid_cap;
+    if (g < 1) return hipSuccess;
+    hipLaunchKernelGGL(tor::chain_kernel<double>, dim3((unsigned)g), dim3(64), 0, st, P);
+    return hipGetLastError();
+}

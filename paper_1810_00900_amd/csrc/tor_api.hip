@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -83,6 +84,7 @@ struct tor_ctx {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     DevBuf pool, descA, descB, partA, partB, jobs;
+    DevBuf kbuf, koff, c_out, c_status, c_tp, c_tu, c_sub;
     Partial *host_res = nullptr;
     size_t host_res_cap = 0;
     std::vector<unsigned char> host_jobs, host_stage;
@@ -685,6 +687,7 @@ void tor_ctx_destroy(tor_ctx *c) {
     c->partA.release();
     c->partB.release();
     c->jobs.release();
+    for (DevBuf *b : {&c->kbuf, &c->koff, &c->c_out, &c->c_status, &c->c_tp, &c->c_tu, &c->c_sub}) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->host_res) (void)hipHostFree(c->host_res);
@@ -819,6 +822,181 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
         }
     }
     return evaluate_many(ctx, qs, prec, tol, out);
+}
+
+// ------------------------------------------------------------------ sampler
+
+}  // extern "C"
+
+namespace {
+
+// K_j = (sigma_Q[modes 0..j])^-1 for every j, from one double-double Cholesky
+// sigma_Q = L L^T: with M = L^-1 (lower triangular) the leading block of M is
+// the inverse factor of the leading block, so K_j[a][b] = sum_{t <= 2j+1}
+// M[t][a] M[t][b], accumulated row pair by row pair.  Rounded to binary64.
+tor_status build_k_tables(const double *cov, int m, std::vector<double> &K, std::vector<unsigned long long> &koff) {
+    const int d = 2 * m;
+    std::vector<dd> L((size_t)d * d), rinv;
+    for (int a = 0; a < d; a++)
+        for (int b = 0; b <= a; b++) {
+            dd v = sigq(cov, m, a, b);
+            L[(size_t)a * d + b] = v;
+            L[(size_t)b * d + a] = v;
+        }
+    if (!dd_cholesky(L, d, rinv, nullptr)) return fail(TOR_ENOTPD, "sigma_Q is not positive definite");
+    std::vector<dd> Mi((size_t)d * d, dd_from(0.0));
+    for (int c = 0; c < d; c++) {
+        Mi[(size_t)c * d + c] = rinv[c];
+        for (int i = c + 1; i < d; i++) {
+            dd acc = dd_from(0.0);
+            for (int t = c; t < i; t++) acc = dd_add(acc, dd_mul(L[(size_t)i * d + t], Mi[(size_t)t * d + c]));
+            Mi[(size_t)i * d + c] = dd_neg(dd_mul(acc, rinv[i]));
+        }
+    }
+    koff.assign(m + 1, 0);
+    for (int j = 0; j < m; j++) koff[j + 1] = koff[j] + (unsigned long long)(2 * j + 2) * (2 * j + 2);
+    K.assign(koff[m], 0.0);
+    std::vector<dd> acc((size_t)d * d, dd_from(0.0));
+    for (int j = 0; j < m; j++) {
+        const int D = 2 * j + 2;
+        for (int t = 2 * j; t < D; t++)
+            for (int a = 0; a <= t; a++)
+                for (int b = 0; b <= a; b++)
+                    acc[(size_t)a * d + b] =
+                        dd_add(acc[(size_t)a * d + b], dd_mul(Mi[(size_t)t * d + a], Mi[(size_t)t * d + b]));
+        double *Kj = K.data() + koff[j];
+        for (int a = 0; a < D; a++)
+            for (int b = 0; b <= a; b++) {
+                dd v = acc[(size_t)a * d + b];
+                Kj[(size_t)a * D + b] = Kj[(size_t)b * D + a] = v.hi + v.lo;
+            }
+    }
+    return TOR_OK;
+}
+
+tor_status upload_chain_tables(tor_ctx *ctx, const double *cov, int m) {
+    std::vector<double> K;
+    std::vector<unsigned long long> koff;
+    tor_status s = build_k_tables(cov, m, K, koff);
+    if (s) return s;
+    if (ctx->kbuf.ensure(K.size() * sizeof(double)) != hipSuccess ||
+        ctx->koff.ensure(koff.size() * sizeof(unsigned long long)) != hipSuccess)
+        return fail(TOR_ENOMEM, "device allocation of the K tables failed");
+    HIP_TRY(hipMemcpyAsync(ctx->kbuf.p, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->koff.p, koff.data(), koff.size() * sizeof(unsigned long long),
+                           hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return TOR_OK;
+}
+
+tor_status check_sampler_args(const double *cov, int m, int n_post) {
+    tor_status s = validate_cov(cov, m);
+    if (s) return s;
+    if (m > 1024) return fail(TOR_ETOOBIG, "m = %d > 1024 for the sampler", m);
+    if (n_post > TOR_CHAIN_CLICKS) return fail(TOR_ETOOBIG, "n_post = %d > %d", n_post, TOR_CHAIN_CLICKS);
+    if (n_post > m) return fail(TOR_EINVAL, "n_post > m");
+    return TOR_OK;
+}
+
+tor_status run_chains(tor_ctx *ctx, int m, int n_post, uint64_t seed, long long begin, int nchains, bool trace) {
+    const size_t nm = (size_t)nchains * (size_t)m;
+    if (ctx->c_out.ensure(nm) != hipSuccess || ctx->c_status.ensure((size_t)nchains) != hipSuccess ||
+        ctx->c_sub.ensure((size_t)nchains * sizeof(double)) != hipSuccess ||
+        (trace && (ctx->c_tp.ensure(nm * sizeof(double)) != hipSuccess ||
+                   ctx->c_tu.ensure(nm * sizeof(double)) != hipSuccess)))
+        return fail(TOR_ENOMEM, "device allocation for %d chains failed", nchains);
+    ChainParams P;
+    P.K = (const double *)ctx->kbuf.p;
+    P.koff = (const unsigned long long *)ctx->koff.p;
+    P.m = m;
+    P.n_post = n_post;
+    P.seed = seed;
+    P.chain_begin = begin;
+    P.nchains = nchains;
+    P.outcome = (unsigned char *)ctx->c_out.p;
+    P.status = (signed char *)ctx->c_status.p;
+    P.trace_p = trace ? (double *)ctx->c_tp.p : nullptr;
+    P.trace_u = trace ? (double *)ctx->c_tu.p : nullptr;
+    P.subsets = (double *)ctx->c_sub.p;
+    HIP_TRY(tor_launch_chains(P, 256 * 8, ctx->stream));
+    return TOR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tor_status gbs_sample(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,
+                      int32_t n_samples, uint8_t *samples, gbs_stats *stats) {
+    if (!ctx) return fail(TOR_EINVAL, "ctx is NULL");
+    if (n_samples < 0 || (n_samples > 0 && !samples)) return fail(TOR_EINVAL, "bad samples buffer");
+    tor_status s = check_sampler_args(cov, m, n_post);
+    if (s) return s;
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto t0 = std::chrono::steady_clock::now();
+    s = upload_chain_tables(ctx, cov, m);
+    if (s) return s;
+    const int NB = 16384;
+    std::vector<unsigned char> out((size_t)NB * m);
+    std::vector<signed char> st(NB);
+    std::vector<double> sub(NB);
+    long long begin = 0, consumed = 0, evaluated = 0, capped = 0;
+    double subsets = 0.0;
+    int got = 0;
+    while (got < n_samples) {
+        if (begin >= (1LL << 31)) return fail(TOR_EAGAIN, "no %d accepted samples within 2^31 chains", n_samples);
+        s = run_chains(ctx, m, n_post, seed, begin, NB, false);
+        if (s) return s;
+        HIP_TRY(hipMemcpyAsync(out.data(), ctx->c_out.p, out.size(), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(st.data(), ctx->c_status.p, st.size(), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(sub.data(), ctx->c_sub.p, sub.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        evaluated += NB;
+        for (int i = 0; i < NB && got < n_samples; i++) {
+            consumed++;
+            subsets += sub[i];
+            if (st[i] == 2) capped++;
+            if (st[i] == 1) {
+                std::memcpy(samples + (size_t)got * m, out.data() + (size_t)i * m, (size_t)m);
+                got++;
+            }
+        }
+        begin += NB;
+    }
+    if (stats) {
+        stats->chains_started = consumed;
+        stats->chains_accepted = got;
+        stats->chains_evaluated = evaluated;
+        stats->chains_capped = capped;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->subsets = subsets;
+    }
+    return TOR_OK;
+}
+
+tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,
+                     int64_t chain_begin, int32_t nchains, double *p_click, double *uniform, uint8_t *outcome,
+                     int8_t *status) {
+    if (!ctx) return fail(TOR_EINVAL, "ctx is NULL");
+    if (nchains < 0 || chain_begin < 0) return fail(TOR_EINVAL, "bad chain range");
+    tor_status s = check_sampler_args(cov, m, n_post);
+    if (s) return s;
+    if (nchains == 0) return TOR_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    s = upload_chain_tables(ctx, cov, m);
+    if (s) return s;
+    s = run_chains(ctx, m, n_post, seed, chain_begin, nchains, true);
+    if (s) return s;
+    const size_t nm = (size_t)nchains * m;
+    if (p_click)
+        HIP_TRY(hipMemcpyAsync(p_click, ctx->c_tp.p, nm * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (uniform)
+        HIP_TRY(hipMemcpyAsync(uniform, ctx->c_tu.p, nm * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (outcome) HIP_TRY(hipMemcpyAsync(outcome, ctx->c_out.p, nm, hipMemcpyDeviceToHost, ctx->stream));
+    if (status) HIP_TRY(hipMemcpyAsync(status, ctx->c_status.p, (size_t)nchains, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return TOR_OK;
 }
 
 }  // extern "C"

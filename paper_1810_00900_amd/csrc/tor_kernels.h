@@ -58,3 +58,23 @@ hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int lo
                              hipStream_t st);
 hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_blocks, hipStream_t st);
 hipError_t tor_launch_gather(const Partial *const *src, int n, Partial *dst, hipStream_t st);
+
+// ---- chain-rule sampler
+#define TOR_CHAIN_MAX 16  // largest tree per step (clicks so far + 1)
+
+struct ChainParams {
+    const double *K;                 // K_j, full row-major (2j+2)^2, concatenated
+    const unsigned long long *koff;  // offset of K_j in K
+    int m;
+    int n_post;                      // < 0: no postselection
+    unsigned long long seed;
+    long long chain_begin;
+    int nchains;
+    unsigned char *outcome;          // nchains x m (0/1; 0 after a stop)
+    signed char *status;             // nchains: 1 accepted, 0 rejected, 2 exceeded the tree cap
+    double *trace_p;                 // optional nchains x m: P(click) (NaN where not evaluated)
+    double *trace_u;                 // optional nchains x m: uniform draw
+    double *subsets;                 // optional nchains: subset terms evaluated
+};
+
+hipError_t tor_launch_chains(const ChainParams &P, int grid_cap, hipStream_t st);

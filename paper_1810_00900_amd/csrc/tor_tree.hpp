@@ -1,0 +1,246 @@
+// Device building blocks of the subset tree, shared by the probability
+// kernels (tor_kernels.hip) and the chain-rule sampler (gbs_sampler.hip).
+//
+// A node holds the symmetric matrix M of its r undecided modes in packed
+// row-major lower storage (E(r) = r(2r+1) scalars; mode k is rows 2k, 2k+1).
+// Deciding the node's last mode: the exclude child is the leading block of M
+// (a prefix of the same array); the include child is the Schur complement of
+// the last mode's 2x2 pivot block, the vacuum-conditioning update Eq.
+// MatrixUpdate of arXiv:1810.00900, with factor q = det(pivot)^-1/2 (the q_k of
+// Eq. (prob) at zero mean), and T(M) = T(exclude) - q T(include).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dd.hpp"
+#include "tor_kernels.h"
+
+#pragma clang fp contract(off)
+
+namespace tor {
+
+__host__ __device__ constexpr int E(int r) { return r * (2 * r + 1); }
+__host__ __device__ constexpr int pidx(int a, int b) { return a * (a + 1) / 2 + b; }
+
+// packed lower-triangle index -> (row, column)
+__device__ __forceinline__ void unpack(int e, int &a, int &b) {
+    int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    if ((r + 1) * (r + 2) / 2 <= e) r++;
+    if (r * (r + 1) / 2 > e) r--;
+    a = r;
+    b = e - r * (r + 1) / 2;
+}
+
+template <class S> __device__ __forceinline__ S szero();
+template <> __device__ __forceinline__ double szero<double>() { return 0.0; }
+template <> __device__ __forceinline__ dd szero<dd>() { return dd_make(0.0, 0.0); }
+
+__device__ __forceinline__ double sub_mul(double x, double a, double b) { return fma(-a, b, x); }
+__device__ __forceinline__ dd sub_mul(dd x, dd a, dd b) { return dd_sub(x, dd_mul(a, b)); }
+
+// Pivot quantities of the last mode of an r-mode node:
+//   alpha = M[p0,p0], beta = M[p1,p0], gamma = M[p1,p1]
+//   s1 = alpha^-1/2, l = beta/alpha, D2 = gamma - l beta, s2 = D2^-1/2,
+//   q = s1 s2 = det(pivot)^-1/2.
+// With v1(c) = M[p0,c] s1 and v2(c) = (M[p1,c] - l M[p0,c]) s2 the Schur
+// complement is M[a,b] - v1(a) v1(b) - v2(a) v2(b).
+template <class S> struct Pivot {
+    S s1, l, s2, q;
+};
+
+template <class S>
+__device__ __forceinline__ Pivot<S> make_pivot(S al, S be, S ga) {
+    Pivot<S> p;
+    p.s1 = rsqrt_s(al);
+    p.l = mul_s(be, mul_s(p.s1, p.s1));
+    S d2 = sub_mul(ga, p.l, be);
+    p.s2 = rsqrt_s(d2);
+    p.q = mul_s(p.s1, p.s2);
+    return p;
+}
+
+__device__ __forceinline__ dd coef_mul(dd c, double q) { return dd_mul_d(c, q); }
+__device__ __forceinline__ dd coef_mul(dd c, dd q) { return dd_mul(c, q); }
+
+// ---------------------------------------------------------------- leaf tier
+
+template <class S, int R> struct Leaf {
+    static __device__ __forceinline__ void run(const S *M, dd &T, double &A) {
+        constexpr int p0 = 2 * R - 2, p1 = 2 * R - 1, RC = 2 * R - 2;
+        dd T0;
+        double A0;
+        Leaf<S, R - 1>::run(M, T0, A0);  // exclude: the prefix of M
+        Pivot<S> pv = make_pivot(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)]);
+        S v1[RC], v2[RC];
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+            S m0 = M[pidx(p0, c)];
+            v1[c] = mul_s(m0, pv.s1);
+            v2[c] = mul_s(sub_mul(M[pidx(p1, c)], pv.l, m0), pv.s2);
+        }
+        S C[E(R - 1)];
+#pragma unroll
+        for (int a = 0; a < RC; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b)
+                C[pidx(a, b)] = sub_dot2(M[pidx(a, b)], v1[a], v1[b], v2[a], v2[b]);
+        dd T1;
+        double A1;
+        Leaf<S, R - 1>::run(C, T1, A1);
+        T = dd_sub_mul(T0, pv.q, T1);
+        A = A0 + hi_of(pv.q) * A1;
+    }
+};
+
+template <class S> struct Leaf<S, 1> {
+    static __device__ __forceinline__ void run(const S *M, dd &T, double &A) {
+        S q = rsqrt_s(det2(M[0], M[1], M[2]));
+        T = dd_sub(dd_from(1.0), to_dd(q));
+        A = 1.0 + hi_of(q);
+    }
+};
+
+template <class S> struct Leaf<S, 0> {
+    static __device__ __forceinline__ void run(const S *, dd &T, double &A) {
+        T = dd_from(1.0);
+        A = 1.0;
+    }
+};
+
+// ---------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double shfl_xor_d(double x, int m) { return __shfl_xor(x, m, 64); }
+
+// fixed butterfly over the 64 lanes; every lane ends with the same value
+__device__ __forceinline__ void wave_reduce(dd &T, double &A) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        dd o = dd_make(shfl_xor_d(T.hi, m), shfl_xor_d(T.lo, m));
+        double oa = shfl_xor_d(A, m);
+        // order the operands by lane so both partners compute the same sum
+        bool low = (threadIdx.x & m) == 0;
+        T = low ? dd_add(T, o) : dd_add(o, T);
+        A = low ? A + oa : oa + A;
+    }
+}
+
+// ---------------------------------------------------------------- wave tier
+
+template <class S, int J> struct WaveCfg {
+    static constexpr int TL = J < 3 ? J : 3;
+    static constexpr int TW = J - TL;
+    static constexpr int NL = 1 << TW;  // leaves (<= 64)
+    // LDS slot offsets: slot base for include children created at level k
+    static constexpr int soff(int k) {
+        int o = E(J);
+        for (int kk = 0; kk < k; ++kk) o += (1 << kk) * E(J - kk - 1);
+        return o;
+    }
+    static constexpr int MAT = soff(TW);
+    static constexpr int vmax() {
+        int m = 1;
+        for (int k = 0; k < TW; ++k) {
+            int v = (1 << k) * 2 * (2 * (J - k) - 2);
+            if (v > m) m = v;
+        }
+        return m;
+    }
+    static constexpr int VMAX = vmax();
+    static constexpr int NPIV = NL / 2 > 0 ? NL / 2 : 1;
+};
+
+template <class S, int J, int K> struct WaveLevel {
+    using C = WaveCfg<S, J>;
+    static __device__ __forceinline__ void run(S *mat, S *vbuf, Pivot<S> *piv, int *loc, dd *coef,
+                                               double *acoef, int lane) {
+        if constexpr (K < C::TW) {
+            constexpr int r = J - K, R = 2 * r, NK = 1 << K, RC = R - 2, EC = E(r - 1);
+            // phase 0: pivot of each node, coefficients and slots of the include children
+            if (lane < NK) {
+                const S *base = mat + loc[lane];
+                Pivot<S> pv = make_pivot(base[pidx(R - 2, R - 2)], base[pidx(R - 1, R - 2)],
+                                         base[pidx(R - 1, R - 1)]);
+                piv[lane] = pv;
+                coef[NK + lane] = dd_neg(coef_mul(coef[lane], pv.q));
+                acoef[NK + lane] = acoef[lane] * hi_of(pv.q);
+                loc[NK + lane] = C::soff(K) + lane * EC;
+            }
+            __syncthreads();
+            // phase 1: the two scaled pivot columns of every node
+            for (int it = lane; it < NK * RC; it += 64) {
+                int i = it / RC, c = it - i * RC;
+                const S *base = mat + loc[i];
+                Pivot<S> pv = piv[i];
+                S m0 = base[pidx(R - 2, c)];
+                vbuf[i * 2 * RC + c] = mul_s(m0, pv.s1);
+                vbuf[i * 2 * RC + RC + c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
+            }
+            __syncthreads();
+            // phase 2: rank-2 updates into the include children's slots
+            for (int it = lane; it < NK * EC; it += 64) {
+                int i = it / EC, e = it - i * EC;
+                int a, b;
+                unpack(e, a, b);
+                const S *base = mat + loc[i];
+                const S *v = vbuf + i * 2 * RC;
+                mat[C::soff(K) + i * EC + e] = sub_dot2(base[e], v[a], v[b], v[RC + a], v[RC + b]);
+            }
+            __syncthreads();
+            WaveLevel<S, J, K + 1>::run(mat, vbuf, piv, loc, coef, acoef, lane);
+        }
+    }
+};
+
+// index of the last job whose begin <= t (jobs sorted by begin, jobs[0].begin == 0)
+template <class Job>
+__device__ __forceinline__ int find_job(const Job *jobs, int njobs, long long t) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// LDS working set of the wave tier for a J-mode node.
+template <class S, int J> struct WaveSmem {
+    using C = WaveCfg<S, J>;
+    S mat[C::MAT];
+    S vbuf[C::VMAX];
+    Pivot<S> piv[C::NPIV];
+    int loc[C::NL];
+    dd coef[C::NL];
+    double acoef[C::NL];
+};
+
+// Subset tree of the J-mode node stored in sm.mat[0 .. E(J)) with path
+// coefficient (c, a): the wave expands J - TL levels in LDS, then lane l < NL
+// finishes leaf l in registers.  Returns this lane's share (T, A) (zero for
+// lanes >= NL).  Leaf index bit 0 is the decision on the node's last mode
+// (1 = included) when J > TL.  Must be called by all 64 lanes.
+template <class S, int J>
+__device__ __forceinline__ void wave_tree(WaveSmem<S, J> &sm, dd c, double a, int lane, dd &T, double &A) {
+    using C = WaveCfg<S, J>;
+    if (lane == 0) {
+        sm.loc[0] = 0;
+        sm.coef[0] = c;
+        sm.acoef[0] = a;
+    }
+    __syncthreads();
+    WaveLevel<S, J, 0>::run(sm.mat, sm.vbuf, sm.piv, sm.loc, sm.coef, sm.acoef, lane);
+    T = dd_from(0.0);
+    A = 0.0;
+    if (lane < C::NL) {
+        S M[E(C::TL)];
+        const S *base = sm.mat + sm.loc[lane];
+#pragma unroll
+        for (int e = 0; e < E(C::TL); ++e) M[e] = base[e];
+        dd Tl;
+        double Al;
+        Leaf<S, C::TL>::run(M, Tl, Al);
+        T = dd_mul(sm.coef[lane], Tl);
+        A = sm.acoef[lane] * Al;
+    }
+}
+
+}  // namespace tor
