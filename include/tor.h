@@ -198,6 +198,55 @@ tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post,
                      int64_t chain_begin, int32_t nchains, double *p_click, double *uniform, uint8_t *outcome,
                      int8_t *status);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of probability queries.
+ *
+ * Each worker owns a stream and device buffers.  A free worker takes the
+ * oldest pending queries that fit its memory budget (at most max_batch) and
+ * evaluates them as one fused batch (see tor_batch); queries submitted while
+ * batches are on the GPU are admitted into the next free worker's batch, so
+ * the batches of different workers overlap on the device.  Every result is
+ * bitwise identical to the same query evaluated alone.  Thread-safe: any
+ * thread may submit, poll or wait.
+ * ------------------------------------------------------------------------ */
+
+typedef struct tor_server tor_server;
+
+typedef struct {
+    int32_t workers;         /* concurrent batches (each its own stream); default 2, at most 16 */
+    int32_t max_pending;     /* admission: queries waiting; further submits get TOR_EAGAIN (default 65536) */
+    size_t mem_budget_bytes; /* device bytes per batch (admission by memory; default 16 GiB) */
+    tor_prec prec;           /* precision policy of every query (TOR_PREC_DD recommended) */
+    double tol;              /* relative error target; <= 0 means 1e-10 */
+    int32_t max_batch;       /* queries per fused batch (default 4096) */
+} tor_server_opts;
+
+typedef struct {
+    int64_t submitted;
+    int64_t completed;
+    int64_t batches;
+    int64_t max_batch_seen;
+    int64_t pending;
+} tor_server_stats;
+
+/* Start a server on ctx's device (opts may be NULL for defaults).  The server
+ * must be stopped before ctx is destroyed. */
+tor_status tor_server_start(tor_ctx *ctx, const tor_server_opts *opts, tor_server **out);
+/* Queue one query on state st (st must outlive the query).  The pattern is
+ * reduced to its conditioned matrix before returning.  *ticket identifies the
+ * result.  TOR_EAGAIN: not admitted (queue full); other errors as
+ * tor_probability. */
+tor_status tor_submit(tor_server *srv, const tor_state *st, const int8_t *pattern, uint64_t *ticket);
+/* TOR_EAGAIN while the query is pending; otherwise fills *out (and the
+ * submit-to-completion latency in seconds, if latency_s is not NULL), releases
+ * the ticket and returns the result's status. */
+tor_status tor_poll(tor_server *srv, uint64_t ticket, tor_result *out, double *latency_s);
+/* As tor_poll but blocks until the result is ready. */
+tor_status tor_wait(tor_server *srv, uint64_t ticket, tor_result *out, double *latency_s);
+tor_status tor_server_get_stats(tor_server *srv, tor_server_stats *out);
+/* Finish every pending query, then stop the workers and free the server. */
+tor_status tor_server_stop(tor_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

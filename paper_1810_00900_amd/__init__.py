@@ -65,6 +65,17 @@ class _CGbsStats(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("subsets", ctypes.c_double)]
 
 
+class _CServerOpts(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("max_pending", ctypes.c_int32),
+                ("mem_budget_bytes", ctypes.c_size_t), ("prec", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_batch", ctypes.c_int32)]
+
+
+class _CServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("max_batch_seen", ctypes.c_int64), ("pending", ctypes.c_int64)]
+
+
 @dataclass
 class Result:
     p: float
@@ -124,6 +135,12 @@ def lib():
         "tor_state_destroy": ([vp], None),
         "tor_batch": ([vp, vp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
                        ctypes.POINTER(_CResult)], ctypes.c_int32),
+        "tor_server_start": ([vp, ctypes.POINTER(_CServerOpts), ctypes.POINTER(vp)], ctypes.c_int32),
+        "tor_submit": ([vp, vp, i8p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+        "tor_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(_CResult), dp], ctypes.c_int32),
+        "tor_wait": ([vp, ctypes.c_uint64, ctypes.POINTER(_CResult), dp], ctypes.c_int32),
+        "tor_server_get_stats": ([vp, ctypes.POINTER(_CServerStats)], ctypes.c_int32),
+        "tor_server_stop": ([vp], ctypes.c_int32),
         "gbs_sample": ([vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                         ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(_CGbsStats)], ctypes.c_int32),
         "gbs_trace": ([vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
@@ -298,3 +315,56 @@ class State:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Continuous-batching server (tor_server_*): submit from any thread, poll or
+    wait for results; each result carries the submit-to-completion latency."""
+
+    def __init__(self, ctx: Context, workers=2, max_pending=1 << 16, mem_budget_bytes=16 << 30, prec="dd",
+                 tol=1e-10, max_batch=4096):
+        o = _CServerOpts(int(workers), int(max_pending), int(mem_budget_bytes), _PREC[prec], float(tol),
+                         int(max_batch))
+        h = ctypes.c_void_p()
+        _check(lib().tor_server_start(ctx.handle, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+
+    def submit(self, state: State, pattern) -> int:
+        """Returns a ticket, or raises TorError (status TOR_EAGAIN when not admitted)."""
+        pattern = _i8(pattern)
+        t = ctypes.c_uint64()
+        _check(lib().tor_submit(self._h, state.handle, _i8ptr(pattern), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """(Result, latency_s) if done, else None."""
+        r = _CResult()
+        lat = ctypes.c_double()
+        st = lib().tor_poll(self._h, ticket, ctypes.byref(r), ctypes.byref(lat))
+        if st == TOR_EAGAIN:
+            return None
+        _check(st)
+        return Result._from(r), lat.value
+
+    def wait(self, ticket: int):
+        r = _CResult()
+        lat = ctypes.c_double()
+        _check(lib().tor_wait(self._h, ticket, ctypes.byref(r), ctypes.byref(lat)))
+        return Result._from(r), lat.value
+
+    def stats(self) -> dict:
+        s = _CServerStats()
+        _check(lib().tor_server_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in _CServerStats._fields_}
+
+    def stop(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().tor_server_stop(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()

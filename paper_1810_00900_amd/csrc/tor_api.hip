@@ -6,6 +6,12 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -558,12 +564,34 @@ struct Prepared {
 };
 
 // PD check and log det of Sigma_C on the host; packs Sigma_C.
+// PD check and log det of Sigma_C by a binary64 Cholesky (log det only feeds
+// the reported Torontonian; the subset tree itself stops with a non-positive
+// pivot on the GPU as well).
+bool f64_cholesky_logdet(const std::vector<dd> &A, int d, double *log_det) {
+    std::vector<double> L((size_t)d * d);
+    double ld = 0.0;
+    for (int j = 0; j < d; j++) {
+        double s = A[(size_t)j * d + j].hi + A[(size_t)j * d + j].lo;
+        for (int t = 0; t < j; t++) s -= L[(size_t)j * d + t] * L[(size_t)j * d + t];
+        if (!(s > 0.0)) return false;
+        const double l = std::sqrt(s);
+        L[(size_t)j * d + j] = l;
+        ld += std::log(s);
+        for (int i = j + 1; i < d; i++) {
+            double v = A[(size_t)i * d + j].hi + A[(size_t)i * d + j].lo;
+            for (int t = 0; t < j; t++) v -= L[(size_t)i * d + t] * L[(size_t)j * d + t];
+            L[(size_t)i * d + j] = v / l;
+        }
+    }
+    *log_det = ld;
+    return true;
+}
+
 tor_status prepare(const std::vector<dd> &sig, int n, dd pvac, double log_pvac, Prepared &p) {
     p.n = n;
     p.pvac = pvac;
     p.log_pvac = log_pvac;
-    std::vector<dd> chol = sig, rinv;
-    if (n > 0 && !dd_cholesky(chol, 2 * n, rinv, &p.log_det))
+    if (n > 0 && !f64_cholesky_logdet(sig, 2 * n, &p.log_det))
         return fail(TOR_ENOTPD, "Sigma_C is not positive definite");
     pack_lower(sig, n, p.packed);
     return TOR_OK;
@@ -609,15 +637,22 @@ tor_status evaluate_many(tor_ctx *ctx, std::vector<Prepared> &qs, tor_prec prec,
     }
     std::vector<SumOut> res(qs.size());
     std::vector<int> used(qs.size(), prec == TOR_PREC_DD ? TOR_PREC_DD : TOR_PREC_F64);
+    auto fail_all = [&](tor_status e) {
+        for (size_t i = 0; i < qs.size(); i++) {
+            std::memset(&out[i], 0, sizeof out[i]);
+            out[i].status = e;
+        }
+        return e;
+    };
     tor_status s = gpu_sums(ctx, in, ok, prec == TOR_PREC_DD, res);
-    if (s < 0) return s;
+    if (s < 0) return fail_all(s);
     if (prec == TOR_PREC_AUTO) {
         std::vector<int> redo;
         for (int i : ok)
             if (qs[i].n > 0 && !(bound_of(TOR_PREC_F64, qs[i].n, res[i].T, res[i].A) <= tol)) redo.push_back(i);
         if (!redo.empty()) {
             s = gpu_sums(ctx, in, redo, true, res);
-            if (s < 0) return s;
+            if (s < 0) return fail_all(s);
             for (int i : redo) used[i] = TOR_PREC_DD;
         }
     }
@@ -996,6 +1031,218 @@ tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post,
     if (outcome) HIP_TRY(hipMemcpyAsync(outcome, ctx->c_out.p, nm, hipMemcpyDeviceToHost, ctx->stream));
     if (status) HIP_TRY(hipMemcpyAsync(status, ctx->c_status.p, (size_t)nchains, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return TOR_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ server
+//
+// Continuous batching: each worker owns a context (its own stream and device
+// buffers).  A free worker takes the oldest pending requests that fit its
+// memory budget (and the batch cap), evaluates them as one fused batch, and
+// publishes the results; requests that arrive meanwhile wait for the next free
+// worker, so batches of different workers overlap on the device.  Every result
+// is bitwise the same as the query evaluated alone (see tor_batch).
+
+namespace {
+
+struct ServerReq {
+    Prepared prep;
+    std::chrono::steady_clock::time_point t_submit, t_done;
+    tor_result res;
+    bool done = false;
+};
+
+}  // namespace
+
+struct tor_server {
+    tor_ctx *parent = nullptr;
+    tor_server_opts opts{};
+    std::vector<tor_ctx *> wctx;
+    std::vector<std::thread> threads;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> pending;
+    std::unordered_map<uint64_t, std::unique_ptr<ServerReq>> reqs;
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    tor_server_stats stats{};
+};
+
+namespace {
+
+void server_worker(tor_server *S, int w) {
+    tor_ctx *ctx = S->wctx[w];
+    (void)hipSetDevice(ctx->device);
+    const size_t es = S->opts.prec == TOR_PREC_F64 ? sizeof(double) : sizeof(dd);
+    for (;;) {
+        std::vector<uint64_t> take;
+        std::vector<Prepared> batch;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [&] { return S->stopping || !S->pending.empty(); });
+            if (S->pending.empty()) return;  // stopping and drained
+            size_t bytes = 0;
+            while (!S->pending.empty() && (int)take.size() < S->opts.max_batch) {
+                uint64_t t = S->pending.front();
+                ServerReq &r = *S->reqs[t];
+                size_t b = sum_bytes(r.prep.n, ctx->task_modes, es);
+                if (!take.empty() && bytes + b > S->opts.mem_budget_bytes) break;
+                bytes += b;
+                take.push_back(t);
+                batch.push_back(std::move(r.prep));
+                S->pending.pop_front();
+            }
+        }
+        std::vector<tor_result> out(batch.size());
+        (void)evaluate_many(ctx, batch, S->opts.prec, S->opts.tol, out.data());
+        auto now = std::chrono::steady_clock::now();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (size_t i = 0; i < take.size(); i++) {
+                ServerReq &r = *S->reqs[take[i]];
+                r.res = out[i];
+                r.t_done = now;
+                r.done = true;
+            }
+            S->stats.batches += 1;
+            S->stats.completed += (int64_t)take.size();
+            S->stats.max_batch_seen = std::max<int64_t>(S->stats.max_batch_seen, (int64_t)take.size());
+        }
+        S->cv_done.notify_all();
+    }
+}
+
+tor_status take_result(tor_server *S, uint64_t ticket, tor_result *out, double *latency_s) {
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(TOR_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    ServerReq &r = *it->second;
+    if (out) *out = r.res;
+    if (latency_s) *latency_s = std::chrono::duration<double>(r.t_done - r.t_submit).count();
+    tor_status st = r.res.status;
+    S->reqs.erase(it);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+tor_status tor_server_start(tor_ctx *ctx, const tor_server_opts *opts, tor_server **out) {
+    if (!ctx || !out) return fail(TOR_EINVAL, "NULL argument");
+    *out = nullptr;
+    tor_server_opts o;
+    o.workers = 2;
+    o.max_pending = 1 << 16;
+    o.mem_budget_bytes = (size_t)16 << 30;
+    o.prec = TOR_PREC_DD;
+    o.tol = 1e-10;
+    o.max_batch = 4096;
+    if (opts) {
+        if (opts->workers > 0) o.workers = opts->workers;
+        if (opts->max_pending > 0) o.max_pending = opts->max_pending;
+        if (opts->mem_budget_bytes > 0) o.mem_budget_bytes = opts->mem_budget_bytes;
+        o.prec = opts->prec;
+        if (opts->tol > 0) o.tol = opts->tol;
+        if (opts->max_batch > 0) o.max_batch = opts->max_batch;
+    }
+    if (o.workers > 16) return fail(TOR_EINVAL, "at most 16 workers");
+    if (o.prec != TOR_PREC_AUTO && o.prec != TOR_PREC_F64 && o.prec != TOR_PREC_DD)
+        return fail(TOR_EINVAL, "bad precision");
+    tor_server *S = new (std::nothrow) tor_server();
+    if (!S) return fail(TOR_ENOMEM, "host allocation failed");
+    S->parent = ctx;
+    S->opts = o;
+    for (int w = 0; w < o.workers; w++) {
+        tor_ctx *c = nullptr;
+        tor_status st = tor_ctx_create(ctx->device, &c);
+        if (st) {
+            for (tor_ctx *x : S->wctx) tor_ctx_destroy(x);
+            delete S;
+            return st;
+        }
+        c->task_modes = ctx->task_modes;
+        c->wave_grid = ctx->wave_grid;
+        c->mem_budget = std::max(ctx->mem_budget, o.mem_budget_bytes);
+        S->wctx.push_back(c);
+    }
+    for (int w = 0; w < o.workers; w++) S->threads.emplace_back(server_worker, S, w);
+    *out = S;
+    return TOR_OK;
+}
+
+tor_status tor_submit(tor_server *S, const tor_state *st, const int8_t *pattern, uint64_t *ticket) {
+    if (!S || !st || !pattern || !ticket) return fail(TOR_EINVAL, "NULL argument");
+    auto t0 = std::chrono::steady_clock::now();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stopping) return fail(TOR_EINVAL, "server is stopping");
+        if ((int)S->pending.size() >= S->opts.max_pending) return fail(TOR_EAGAIN, "queue full");
+    }
+    std::unique_ptr<ServerReq> r(new (std::nothrow) ServerReq());
+    if (!r) return fail(TOR_ENOMEM, "host allocation failed");
+    r->t_submit = t0;
+    std::vector<dd> sig;
+    int n = 0;
+    dd pvac;
+    double log_pvac;
+    tor_status s = reduce_pattern(st->cov.data(), st->m, pattern, sig, n, pvac, log_pvac);
+    if (s == TOR_OK) s = prepare(sig, n, pvac, log_pvac, r->prep);
+    if (s) return s;
+    const size_t es = S->opts.prec == TOR_PREC_F64 ? sizeof(double) : sizeof(dd);
+    if (sum_bytes(n, S->wctx[0]->task_modes, es) > S->wctx[0]->mem_budget)
+        return fail(TOR_ENOMEM, "query with %d clicks exceeds the device memory budget", n);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if ((int)S->pending.size() >= S->opts.max_pending) return fail(TOR_EAGAIN, "queue full");
+        uint64_t t = S->next_ticket++;
+        S->reqs.emplace(t, std::move(r));
+        S->pending.push_back(t);
+        S->stats.submitted += 1;
+        *ticket = t;
+    }
+    S->cv_work.notify_one();
+    return TOR_OK;
+}
+
+tor_status tor_poll(tor_server *S, uint64_t ticket, tor_result *out, double *latency_s) {
+    if (!S) return fail(TOR_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(TOR_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!it->second->done) return TOR_EAGAIN;
+    return take_result(S, ticket, out, latency_s);
+}
+
+tor_status tor_wait(tor_server *S, uint64_t ticket, tor_result *out, double *latency_s) {
+    if (!S) return fail(TOR_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(TOR_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    ServerReq *r = it->second.get();
+    S->cv_done.wait(lk, [&] { return r->done; });
+    return take_result(S, ticket, out, latency_s);
+}
+
+tor_status tor_server_get_stats(tor_server *S, tor_server_stats *out) {
+    if (!S || !out) return fail(TOR_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->stats;
+    out->pending = (int64_t)S->pending.size();
+    return TOR_OK;
+}
+
+tor_status tor_server_stop(tor_server *S) {
+    if (!S) return fail(TOR_EINVAL, "NULL argument");
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stopping = true;
+    }
+    S->cv_work.notify_all();
+    for (auto &t : S->threads) t.join();
+    for (tor_ctx *c : S->wctx) tor_ctx_destroy(c);
+    delete S;
     return TOR_OK;
 }
 
