@@ -90,23 +90,44 @@ DD_FN dd dd_mul(dd x, dd y) {
     return r;
 }
 
-// x - a1*b1 - a2*b2 in one pass.  The two leading products are split exactly
-// (TwoProd), the leading sum is formed with TwoSums, and all second-order
-// terms are gathered in one binary64 sum; the absolute error is a small
-// multiple of u^2 (|x| + |a1 b1| + |a2 b2|), the backward error of a
-// dd-precision rank-2 update.
+// x - a1*b1 - a2*b2 in one pass.  The leading products are split exactly
+// (p + e == a.hi*b.hi via FMA), the cross terms a.hi*b.lo + a.lo*b.hi are
+// folded into e with two more FMAs, the leading sum x.hi - p1 - p2 is formed
+// error-free with two TwoSums, and every second-order term is gathered in one
+// binary64 sum.  The absolute error is a small multiple of
+// u^2 (|x| + |a1 b1| + |a2 b2|): the backward error of a double-double rank-2
+// update, which is what the Schur-complement analysis needs (the final
+// FastTwoSum may round once more when the leading sum cancels completely, an
+// error of the same order).
 DD_FN dd dd_sub_dot2(dd x, dd a1, dd b1, dd a2, dd b2) {
-    double p1, e1, p2, e2;
-    two_prod(a1.hi, b1.hi, p1, e1);
-    two_prod(a2.hi, b2.hi, p2, e2);
-    double c1 = fma(a1.hi, b1.lo, a1.lo * b1.hi);
-    double c2 = fma(a2.hi, b2.lo, a2.lo * b2.hi);
+    const double p1 = a1.hi * b1.hi;
+    double c1 = fma(a1.hi, b1.hi, -p1);
+    c1 = fma(a1.hi, b1.lo, c1);
+    c1 = fma(a1.lo, b1.hi, c1);
+    const double p2 = a2.hi * b2.hi;
+    double c2 = fma(a2.hi, b2.hi, -p2);
+    c2 = fma(a2.hi, b2.lo, c2);
+    c2 = fma(a2.lo, b2.hi, c2);
     double s, t1, t2;
     two_sum(x.hi, -p1, s, t1);
     two_sum(s, -p2, s, t2);
-    double low = ((x.lo + t1) + t2) - ((e1 + e2) + (c1 + c2));
+    const double low = ((x.lo + t1) + t2) - (c1 + c2);
     dd r;
-    two_sum(s, low, r.hi, r.lo);
+    fast_two_sum(s, low, r.hi, r.lo);
+    return r;
+}
+
+// x - a*b, the one-term form of dd_sub_dot2 (same error behaviour).
+DD_FN dd dd_sub_mul1(dd x, dd a, dd b) {
+    const double p = a.hi * b.hi;
+    double c = fma(a.hi, b.hi, -p);
+    c = fma(a.hi, b.lo, c);
+    c = fma(a.lo, b.hi, c);
+    double s, t;
+    two_sum(x.hi, -p, s, t);
+    const double low = (x.lo + t) - c;
+    dd r;
+    fast_two_sum(s, low, r.hi, r.lo);
     return r;
 }
 
@@ -125,12 +146,30 @@ DD_FN dd dd_det2(dd a, dd b, dd c) {
     return r;
 }
 
+// Binary64 reciprocal square root accurate to about one ulp for positive
+// normal x: the hardware estimate (v_rsq_f64 on the device) refined by two
+// Newton steps y <- y + y (1 - x y^2) / 2, each of which squares the relative
+// error until binary64 rounding dominates.  On the host the estimate is
+// 1/sqrt(x).
+DD_FN double rsqrt_f64(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(x);
+    double r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+    r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+    return y;
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
+
 // 1/sqrt(x) for x > 0: a binary64 seed refined by one Newton step
 // y = y0 + y0 (1 - x y0^2) / 2 whose residual is formed in double-word
 // precision; the seed's relative error e becomes ~1.5 e^2 + O(u^2).
 // Non-positive or non-finite x propagates NaN/inf.
 DD_FN dd dd_rsqrt(dd x) {
-    double y0 = 1.0 / sqrt(x.hi);
+    double y0 = rsqrt_f64(x.hi);
     double p, e;
     two_prod(y0, y0, p, e);           // y0^2 = p + e exactly
     double h, l;
@@ -151,7 +190,7 @@ DD_FN double sub_dot2(double x, double a1, double b1, double a2, double b2) {
 DD_FN dd sub_dot2(dd x, dd a1, dd b1, dd a2, dd b2) { return dd_sub_dot2(x, a1, b1, a2, b2); }
 DD_FN double det2(double a, double b, double c) { return fma(a, c, -b * b); }
 DD_FN dd det2(dd a, dd b, dd c) { return dd_det2(a, b, c); }
-DD_FN double rsqrt_s(double x) { return 1.0 / sqrt(x); }
+DD_FN double rsqrt_s(double x) { return rsqrt_f64(x); }
 DD_FN dd rsqrt_s(dd x) { return dd_rsqrt(x); }
 DD_FN double mul_s(double a, double b) { return a * b; }
 DD_FN dd mul_s(dd a, dd b) { return dd_mul(a, b); }

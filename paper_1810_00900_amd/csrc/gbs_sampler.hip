@@ -143,7 +143,9 @@ __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
     __shared__ S vt[4 * TOR_CHAIN_MAX];
     __shared__ int Cl[TOR_CHAIN_MAX + 1];
     const int lane = threadIdx.x;
-    S *wmat = reinterpret_cast<WaveSmem<S, 9> *>(raw)->mat;  // mat[] is the first member for every J
+    // ab[] then mat[] sit at the same offsets in WaveSmem<S, J> for every J
+    S *wmat = reinterpret_cast<WaveSmem<S, 9> *>(raw)->mat;
+    wave_tree_init(reinterpret_cast<WaveSmem<S, 9> *>(raw)->ab, lane);
     for (int ci = blockIdx.x; ci < P.nchains; ci += gridDim.x) {
         const long long chain = P.chain_begin + ci;
         int nc = 0;

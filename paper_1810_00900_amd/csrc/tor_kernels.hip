@@ -47,6 +47,7 @@ __global__ __launch_bounds__(64) void wave_kernel(const WaveJob *__restrict__ jo
                                                   const S *__restrict__ pool) {
     __shared__ WaveSmem<S, J> sm;
     const int lane = threadIdx.x;
+    wave_tree_init(sm.ab, lane);
     for (long long t = blockIdx.x; t < total; t += gridDim.x) {
         const int j = find_job(jobs, njobs, t);
         const long long lt = t - jobs[j].begin;

@@ -35,7 +35,7 @@ template <> __device__ __forceinline__ double szero<double>() { return 0.0; }
 template <> __device__ __forceinline__ dd szero<dd>() { return dd_make(0.0, 0.0); }
 
 __device__ __forceinline__ double sub_mul(double x, double a, double b) { return fma(-a, b, x); }
-__device__ __forceinline__ dd sub_mul(dd x, dd a, dd b) { return dd_sub(x, dd_mul(a, b)); }
+__device__ __forceinline__ dd sub_mul(dd x, dd a, dd b) { return dd_sub_mul1(x, a, b); }
 
 // Pivot quantities of the last mode of an r-mode node:
 //   alpha = M[p0,p0], beta = M[p1,p0], gamma = M[p1,p1]
@@ -126,33 +126,40 @@ __device__ __forceinline__ void wave_reduce(dd &T, double &A) {
 // ---------------------------------------------------------------- wave tier
 
 template <class S, int J> struct WaveCfg {
-    static constexpr int TL = J < 3 ? J : 3;
-    static constexpr int TW = J - TL;
-    static constexpr int NL = 1 << TW;  // leaves (<= 64)
+    static constexpr int TL = J < 3 ? J : 3;    // leaf modes (per lane, registers)
+    static constexpr int TW = J - TL;           // levels above the leaves
+    static constexpr int TWC = TW > 0 ? TW - 1 : 0;  // levels expanded cooperatively in LDS
+    static constexpr int NN = 1 << TWC;         // nodes after the cooperative levels
+    static constexpr int NL = 1 << TW;          // leaves (<= 64), one per lane
     // LDS slot offsets: slot base for include children created at level k
     static constexpr int soff(int k) {
         int o = E(J);
         for (int kk = 0; kk < k; ++kk) o += (1 << kk) * E(J - kk - 1);
         return o;
     }
-    static constexpr int MAT = soff(TW);
+    static constexpr int MAT = soff(TWC);
     static constexpr int vmax() {
         int m = 1;
-        for (int k = 0; k < TW; ++k) {
+        for (int k = 0; k < TWC; ++k) {
             int v = (1 << k) * 2 * (2 * (J - k) - 2);
             if (v > m) m = v;
         }
         return m;
     }
     static constexpr int VMAX = vmax();
-    static constexpr int NPIV = NL / 2 > 0 ? NL / 2 : 1;
+    static constexpr int NPIV = NN / 2 > 0 ? NN / 2 : 1;
 };
+
+// (row, column) of packed index e, for every e < E(8) (the largest child of
+// a 9-mode node); identical for every node size since packed storage of a
+// smaller matrix is a prefix.
+#define TOR_AB_N 136
 
 template <class S, int J, int K> struct WaveLevel {
     using C = WaveCfg<S, J>;
-    static __device__ __forceinline__ void run(S *mat, S *vbuf, Pivot<S> *piv, int *loc, dd *coef,
-                                               double *acoef, int lane) {
-        if constexpr (K < C::TW) {
+    static __device__ __forceinline__ void run(const unsigned short *ab, S *mat, S *vbuf, Pivot<S> *piv, int *loc,
+                                               dd *coef, double *acoef, int lane) {
+        if constexpr (K < C::TWC) {
             constexpr int r = J - K, R = 2 * r, NK = 1 << K, RC = R - 2, EC = E(r - 1);
             // phase 0: pivot of each node, coefficients and slots of the include children
             if (lane < NK) {
@@ -176,16 +183,17 @@ template <class S, int J, int K> struct WaveLevel {
             }
             __syncthreads();
             // phase 2: rank-2 updates into the include children's slots
+#pragma unroll 2
             for (int it = lane; it < NK * EC; it += 64) {
                 int i = it / EC, e = it - i * EC;
-                int a, b;
-                unpack(e, a, b);
+                const unsigned short w = ab[e];
+                const int a = w & 0xff, b = w >> 8;
                 const S *base = mat + loc[i];
                 const S *v = vbuf + i * 2 * RC;
                 mat[C::soff(K) + i * EC + e] = sub_dot2(base[e], v[a], v[b], v[RC + a], v[RC + b]);
             }
             __syncthreads();
-            WaveLevel<S, J, K + 1>::run(mat, vbuf, piv, loc, coef, acoef, lane);
+            WaveLevel<S, J, K + 1>::run(ab, mat, vbuf, piv, loc, coef, acoef, lane);
         }
     }
 };
@@ -202,22 +210,37 @@ __device__ __forceinline__ int find_job(const Job *jobs, int njobs, long long t)
     return lo;
 }
 
-// LDS working set of the wave tier for a J-mode node.
+// LDS working set of the wave tier for a J-mode node.  The index table comes
+// first and mat second, at the same offsets for every J.
 template <class S, int J> struct WaveSmem {
     using C = WaveCfg<S, J>;
+    unsigned short ab[TOR_AB_N];
     S mat[C::MAT];
     S vbuf[C::VMAX];
     Pivot<S> piv[C::NPIV];
-    int loc[C::NL];
-    dd coef[C::NL];
-    double acoef[C::NL];
+    int loc[C::NN];
+    dd coef[C::NN];
+    double acoef[C::NN];
 };
 
+// Fill the packed-index table (once per workgroup, before the first tree).
+__device__ __forceinline__ void wave_tree_init(unsigned short *ab, int lane) {
+    for (int e = lane; e < TOR_AB_N; e += 64) {
+        int a, b;
+        unpack(e, a, b);
+        ab[e] = (unsigned short)(a | (b << 8));
+    }
+    __syncthreads();
+}
+
 // Subset tree of the J-mode node stored in sm.mat[0 .. E(J)) with path
-// coefficient (c, a): the wave expands J - TL levels in LDS, then lane l < NL
-// finishes leaf l in registers.  Returns this lane's share (T, A) (zero for
-// lanes >= NL).  Leaf index bit 0 is the decision on the node's last mode
-// (1 = included) when J > TL.  Must be called by all 64 lanes.
+// coefficient (c, a).  The wave expands all but the last of the J - TL levels
+// above the leaves breadth-first in LDS; lane l < NL then takes node
+// l mod NN, decides its last mode itself (l >= NN: include, a rank-2 Schur
+// update in registers; else exclude, the same code with zero update vectors)
+// and finishes the TL-mode leaf in registers.  Returns this lane's share
+// (T, A) (zero for lanes >= NL).  Lane bit 0 is the decision on the node's last
+// mode (1 = included) when J > TL.  Must be called by all 64 lanes.
 template <class S, int J>
 __device__ __forceinline__ void wave_tree(WaveSmem<S, J> &sm, dd c, double a, int lane, dd &T, double &A) {
     using C = WaveCfg<S, J>;
@@ -227,19 +250,57 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J> &sm, dd c, double a, in
         sm.acoef[0] = a;
     }
     __syncthreads();
-    WaveLevel<S, J, 0>::run(sm.mat, sm.vbuf, sm.piv, sm.loc, sm.coef, sm.acoef, lane);
+    WaveLevel<S, J, 0>::run(sm.ab, sm.mat, sm.vbuf, sm.piv, sm.loc, sm.coef, sm.acoef, lane);
     T = dd_from(0.0);
     A = 0.0;
-    if (lane < C::NL) {
-        S M[E(C::TL)];
-        const S *base = sm.mat + sm.loc[lane];
+    if constexpr (C::TW == 0) {
+        if (lane == 0) {
+            S M[E(C::TL)];
 #pragma unroll
-        for (int e = 0; e < E(C::TL); ++e) M[e] = base[e];
-        dd Tl;
-        double Al;
-        Leaf<S, C::TL>::run(M, Tl, Al);
-        T = dd_mul(sm.coef[lane], Tl);
-        A = sm.acoef[lane] * Al;
+            for (int e = 0; e < E(C::TL); ++e) M[e] = sm.mat[e];
+            dd Tl;
+            double Al;
+            Leaf<S, C::TL>::run(M, Tl, Al);
+            T = dd_mul(c, Tl);
+            A = a * Al;
+        }
+    } else {
+        if (lane < C::NL) {
+            constexpr int R1 = C::TL + 1, p0 = 2 * R1 - 2, p1 = 2 * R1 - 1, RC = 2 * R1 - 2;
+            const int i = lane & (C::NN - 1);
+            const bool inc = lane >= C::NN;
+            const S *base = sm.mat + sm.loc[i];
+            S M[E(R1)];
+#pragma unroll
+            for (int e = 0; e < E(R1); ++e) M[e] = base[e];
+            Pivot<S> pv = make_pivot(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)]);
+            const S zero = from_pair<S>(0.0, 0.0);
+            S v1[RC], v2[RC];
+#pragma unroll
+            for (int cc = 0; cc < RC; ++cc) {
+                S m0 = M[pidx(p0, cc)];
+                S x1 = mul_s(m0, pv.s1);
+                S x2 = mul_s(sub_mul(M[pidx(p1, cc)], pv.l, m0), pv.s2);
+                v1[cc] = inc ? x1 : zero;
+                v2[cc] = inc ? x2 : zero;
+            }
+            S Ml[E(C::TL)];
+#pragma unroll
+            for (int x = 0; x < RC; ++x)
+#pragma unroll
+                for (int y = 0; y <= x; ++y) Ml[pidx(x, y)] = sub_dot2(M[pidx(x, y)], v1[x], v1[y], v2[x], v2[y]);
+            dd cl = sm.coef[i];
+            double al = sm.acoef[i];
+            if (inc) {
+                cl = dd_neg(coef_mul(cl, pv.q));
+                al *= hi_of(pv.q);
+            }
+            dd Tl;
+            double Al;
+            Leaf<S, C::TL>::run(Ml, Tl, Al);
+            T = dd_mul(cl, Tl);
+            A = al * Al;
+        }
     }
 }
 
