@@ -205,7 +205,7 @@ template <> DD_FN dd from_pair<dd>(double h, double l) {
     return r;
 }
 // T-recursion step: t0 - q * t1 with dd accumulation
-DD_FN dd dd_sub_mul(dd t0, double q, dd t1) { return dd_sub(t0, dd_mul_d(t1, q)); }
-DD_FN dd dd_sub_mul(dd t0, dd q, dd t1) { return dd_sub(t0, dd_mul(t1, q)); }
+DD_FN dd dd_sub_mul(dd t0, double q, dd t1) { return dd_sub_mul1(t0, t1, dd_from(q)); }
+DD_FN dd dd_sub_mul(dd t0, dd q, dd t1) { return dd_sub_mul1(t0, t1, q); }
 DD_FN double hi_of(double a) { return a; }
 DD_FN double hi_of(dd a) { return a.hi; }

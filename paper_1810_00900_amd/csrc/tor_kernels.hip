@@ -72,11 +72,25 @@ __global__ __launch_bounds__(64) void wave_kernel(const WaveJob *__restrict__ jo
 
 // ---------------------------------------------------------------- HBM tier
 
+// Wave-scope ordering of LDS accesses: writes by some lanes become visible to
+// later reads by other lanes of the same wave (LDS operations of one wave
+// execute in order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave per parent node (four per 256-thread workgroup): the include child
+// (rank-2 Schur update of the last mode) goes to the pool, the exclude child
+// keeps the parent's offset.  Waves run independently (no workgroup barrier).
 template <class S>
 __global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict__ jobs, int log2npar,
                                                      long long total, S *__restrict__ pool) {
-    __shared__ S v[2][2 * TOR_MAX_N];
-    for (long long f = blockIdx.x; f < total; f += gridDim.x) {
+    __shared__ S vs[4][2][2 * TOR_MAX_N];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    S *v0 = vs[w][0], *v1 = vs[w][1];
+    for (long long f = (long long)blockIdx.x * 4 + w; f < total; f += (long long)gridDim.x * 4) {
         const ExpandJob job = jobs[f >> log2npar];
         const long long i = f & ((1LL << log2npar) - 1);
         const int r = job.r, R = 2 * r, RC = R - 2, EC = E(r - 1);
@@ -84,7 +98,7 @@ __global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict
         const S *base = pool + d.off;
         Pivot<S> pv = make_pivot(base[pidx(R - 2, R - 2)], base[pidx(R - 1, R - 2)], base[pidx(R - 1, R - 1)]);
         unsigned long long coff = job.child_base + (unsigned long long)i * (unsigned long long)EC;
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             job.chi[2 * i] = d;
             NodeDesc c;
             c.off = coff;
@@ -94,19 +108,19 @@ __global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict
             c.acoef = d.acoef * hi_of(pv.q);
             job.chi[2 * i + 1] = c;
         }
-        for (int c = threadIdx.x; c < RC; c += blockDim.x) {
+        for (int c = lane; c < RC; c += 64) {
             S m0 = base[pidx(R - 2, c)];
-            v[0][c] = mul_s(m0, pv.s1);
-            v[1][c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
+            v0[c] = mul_s(m0, pv.s1);
+            v1[c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
         }
-        __syncthreads();
+        wave_sync();
         S *outp = pool + coff;
-        for (int e = threadIdx.x; e < EC; e += blockDim.x) {
+        for (int e = lane; e < EC; e += 64) {
             int a, b;
             unpack(e, a, b);
-            outp[e] = sub_dot2(base[e], v[0][a], v[0][b], v[1][a], v[1][b]);
+            outp[e] = sub_dot2(base[e], v0[a], v0[b], v1[a], v1[b]);
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -203,7 +217,8 @@ hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, lon
 hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
                              hipStream_t st) {
     long long total = (long long)njobs << log2npar;
-    long long g = total < grid_cap ? total : grid_cap;
+    long long blocks = (total + 3) / 4;
+    long long g = blocks < grid_cap ? blocks : grid_cap;
     if (g < 1) return hipSuccess;
     if (is_dd)
         hipLaunchKernelGGL(tor::expand_kernel<dd>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,

@@ -49,12 +49,15 @@ template <class S> struct Pivot {
 
 template <class S>
 __device__ __forceinline__ Pivot<S> make_pivot(S al, S be, S ga) {
+    // q = det^-1/2 and s1 = alpha^-1/2 are independent (shorter dependency
+    // chain); s2 = (gamma - beta^2/alpha)^-1/2 = q alpha^{1/2} = q alpha s1.
     Pivot<S> p;
+    const S det = det2(al, be, ga);
     p.s1 = rsqrt_s(al);
-    p.l = mul_s(be, mul_s(p.s1, p.s1));
-    S d2 = sub_mul(ga, p.l, be);
-    p.s2 = rsqrt_s(d2);
-    p.q = mul_s(p.s1, p.s2);
+    p.q = rsqrt_s(det);
+    const S s1sq = mul_s(p.s1, p.s1);
+    p.l = mul_s(be, s1sq);
+    p.s2 = mul_s(p.q, mul_s(al, p.s1));
     return p;
 }
 
