@@ -86,6 +86,130 @@ def cpu_baseline(cov, pattern, n, seconds_target=15.0):
                       f"same n={n} sum, binary128 Cholesky per subset, {dt:.1f} s"}
 
 
+KERNEL_SOURCES = ["paper_1810_00900_amd/csrc/dd.hpp", "paper_1810_00900_amd/csrc/tor_tree.hpp",
+                  "paper_1810_00900_amd/csrc/tor_kernels.hip", "paper_1810_00900_amd/csrc/tor_kernels.h"]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the wave-tier kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE measurement (profiles/), scaled by the
+    copy-kernel calibration; None when the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_wave_kernel_dd9_m800_n28.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    if d.get("sources_sha256") != h.hexdigest() or d.get("kernel") != kernel:
+        return None
+    return d["traffic_bytes_per_launch"]
+
+
+def copy_calibration():
+    """A plain 1 GiB device copy, profiled with the same counters to scale
+    FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 8}))
+
+
+def per_n_rates(ctx, cov, prec, ns=(20, 24, 28), reps=3):
+    """subset-dets/s of single Torontonians at several n (whole calls)."""
+    import gbs_inputs as gi
+    out = {}
+    for n in ns:
+        pat = gi.config5_pattern(n)
+        ctx.probability(cov, pat, prec=prec, tol=1e-8)
+        t = time.perf_counter()
+        for _ in range(reps):
+            ctx.probability(cov, pat, prec=prec, tol=1e-8)
+        dt = (time.perf_counter() - t) / reps
+        out[str(n)] = {"subset_dets_per_s": 2.0 ** n / dt, "ms": dt * 1e3}
+    return out
+
+
+def sampler_bench(ctx, n_samples=1000):
+    """The postselected sampling workload: m = 100, Haar U, r = 0.6, 12 clicks."""
+    import gbs_inputs as gi
+    cov = gi.state_config2()
+    samples, st = ctx.gbs_sample(cov, 12, 2, n_samples)
+    assert (samples.sum(axis=1) == 12).all()
+    return {"workload": "m=100, Haar U, r=0.6, postselected on 12 clicks, seed 2",
+            "samples": n_samples, "seconds": st["seconds"], "samples_per_s": n_samples / st["seconds"],
+            "chains": st["chains_started"], "acceptance": st["chains_accepted"] / st["chains_started"],
+            "subset_dets_per_s": st["subsets"] / st["seconds"], "precision": "f64 terms, dd sums"}
+
+
+def serving_bench(ctx, nq=10000, workers=2):
+    """10^4 marginal-pattern queries (n ~ U{8..24}) on four 800-mode states:
+    closed-loop saturation, then Poisson arrivals at 0.5x and 0.8x of it, for
+    the continuous-batching server and for one query per launch."""
+    import numpy as np
+
+    import gbs_inputs as gi
+    import paper_1810_00900_amd as tg
+    covs = [gi.state_m800(s) for s in (30, 31, 32, 33)]
+    qs = gi.config3_queries(nq)
+    sts = [ctx.state(c) for c in covs]
+    rng = np.random.default_rng(35)
+
+    def pct(lat):
+        return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+
+    def served(rate):
+        srv = tg.Server(ctx, workers=workers, prec="dd", tol=1e-10, max_batch=4096)
+        arr = np.cumsum(rng.exponential(1.0 / rate, nq)) if rate else None
+        t0 = time.perf_counter()
+        tickets = []
+        for k, (s, n, p) in enumerate(qs):
+            if arr is not None:
+                while time.perf_counter() - t0 < arr[k]:
+                    pass
+            tickets.append(srv.submit(sts[s], p))
+        res = [srv.wait(t) for t in tickets]
+        T = time.perf_counter() - t0
+        st = srv.stats()
+        srv.stop()
+        lat = np.array([x[1] for x in res])
+        out = {"queries_per_s": nq / T, "batches": st["batches"], "max_batch": st["max_batch_seen"]}
+        out.update(pct(lat))
+        return out
+
+    def single(rate):
+        arr = np.cumsum(rng.exponential(1.0 / rate, nq)) if rate else np.zeros(nq)
+        t0 = time.perf_counter()
+        lat = np.empty(nq)
+        for k, (s, n, p) in enumerate(qs):
+            if rate:
+                while time.perf_counter() - t0 < arr[k]:
+                    pass
+            ctx.probability(covs[s], p, prec="dd", tol=1e-10)
+            lat[k] = time.perf_counter() - t0 - arr[k]
+        T = time.perf_counter() - t0
+        out = {"queries_per_s": nq / T}
+        out.update(pct(lat))
+        return out
+
+    sat = served(None)
+    X = sat["queries_per_s"]
+    res = {"workload": "10^4 queries, n ~ U{8..24}, marginal click sets, 4 states m=800 (seeds 30-33), "
+                       "queries seed 34, dd terms, tol 1e-10",
+           "served_closed_loop": sat, "one_per_launch_closed_loop": single(None)}
+    for f in (0.5, 0.8):
+        res[f"served_poisson_{f}x"] = served(f * X)
+        res[f"one_per_launch_poisson_{f}x"] = single(f * X)
+    res["poisson_rates_qps"] = {"0.5x": 0.5 * X, "0.8x": 0.8 * X}
+    res["subsets_total"] = float(sum(2.0 ** n for _, n, _ in qs))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,7 +218,12 @@ def main():
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--prec", default="dd", choices=["dd", "f64"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip per-n, sampler and serving measurements")
+    ap.add_argument("--copy-calibration", action="store_true", help="only run the 1 GiB copy used to scale counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the subset sum would shard by prefix bits with one 24-byte exchange per GPU)",
@@ -129,6 +258,7 @@ def main():
     ntasks = 2 ** (n - J)
     wave_ms = st["wave_ms"] / max(st["wave_launches"], 1)
     wave_flops = tree_flops(n, top=J) * ntasks
+    kname = f"wave_kernel<dd,{J}>" if args.prec == "dd" else f"wave_kernel<double,{J}>"
     achieved = wave_flops / (wave_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -147,8 +277,9 @@ def main():
                                f"marginal click pattern with n={n} (2^{n} subsets)",
                    "m": 800, "n": n, "precision": args.prec, "task_modes": J},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": f"wave_kernel<dd,{J}>" if args.prec == "dd" else f"wave_kernel<double,{J}>",
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": (measured_traffic(kname) if n == 28 else None),
+                     "kernel": kname,
                      "kernel_ms": wave_ms,
                      "algorithmic_flops_per_launch": wave_flops},
         "phases_ms_per_step": {"expand": st["expand_ms"] / args.steps, "wave": st["wave_ms"] / args.steps,
@@ -156,6 +287,11 @@ def main():
         "result": {"p": r.p, "cancel_ratio": r.cancel_ratio, "rel_err_bound": r.rel_err_bound,
                    "prec_used": r.prec_used},
     }
+    if not args.no_extras:
+        out["per_n"] = per_n_rates(ctx, cov, args.prec)
+        out["per_n_f64_terms"] = per_n_rates(ctx, cov, "f64")
+        out["sampler"] = sampler_bench(ctx)
+        out["serving"] = serving_bench(ctx)
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cov, pattern, n)

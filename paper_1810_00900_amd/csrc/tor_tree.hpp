@@ -185,15 +185,40 @@ template <class S, int J, int K> struct WaveLevel {
                 vbuf[i * 2 * RC + RC + c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
             }
             __syncthreads();
-            // phase 2: rank-2 updates into the include children's slots
-#pragma unroll 2
-            for (int it = lane; it < NK * EC; it += 64) {
-                int i = it / EC, e = it - i * EC;
-                const unsigned short w = ab[e];
-                const int a = w & 0xff, b = w >> 8;
-                const S *base = mat + loc[i];
-                const S *v = vbuf + i * 2 * RC;
-                mat[C::soff(K) + i * EC + e] = sub_dot2(base[e], v[a], v[b], v[RC + a], v[RC + b]);
+            // phase 2: rank-2 updates into the include children's slots.  Each
+            // lane's entries are taken in chunks: all loads of a chunk first,
+            // then the independent updates (computed unconditionally so that
+            // their dependency chains interleave), then the stores.
+            {
+                constexpr int TOT = NK * EC, JJ = (TOT + 63) / 64;
+                constexpr int NCH = (JJ + 3) / 4, CH = (JJ + NCH - 1) / NCH;
+#pragma unroll
+                for (int j0 = 0; j0 < JJ; j0 += CH) {
+                    S x[CH], p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
+                    int dst[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        const int it0 = lane + 64 * (j0 + u);
+                        const bool ok = (j0 + u < JJ) && it0 < TOT;
+                        const int it = ok ? it0 : 0;
+                        const int i = it / EC, e = it - i * EC;
+                        const unsigned short w = ab[e];
+                        const int a = w & 0xff, b = w >> 8;
+                        const S *base = mat + loc[i];
+                        const S *v = vbuf + i * 2 * RC;
+                        x[u] = base[e];
+                        p1[u] = v[a];
+                        q1[u] = v[b];
+                        p2[u] = v[RC + a];
+                        q2[u] = v[RC + b];
+                        dst[u] = ok ? C::soff(K) + i * EC + e : -1;
+                    }
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) r[u] = sub_dot2(x[u], p1[u], q1[u], p2[u], q2[u]);
+#pragma unroll
+                    for (int u = 0; u < CH; ++u)
+                        if (dst[u] >= 0) mat[dst[u]] = r[u];
+                }
             }
             __syncthreads();
             WaveLevel<S, J, K + 1>::run(ab, mat, vbuf, piv, loc, coef, acoef, lane);
