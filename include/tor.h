@@ -122,6 +122,19 @@ tor_status tor_ctx_set_option(tor_ctx *ctx, tor_option opt, int64_t value);
 tor_status tor_ctx_get_stats(const tor_ctx *ctx, tor_stats *out);
 tor_status tor_ctx_reset_stats(tor_ctx *ctx);
 
+/* Autotuner: for each tree size n in [n_lo, n_hi] time the candidate
+ * wave-tier task sizes (6..9 modes per task) on a synthetic SPD matrix and
+ * keep the fastest for (prec, n) in ctx; with cache_path != NULL also write
+ * the table as JSON ({"arch": ..., "task_modes": {"dd:24": 9, ...}}).  The
+ * choice depends only on (prec, n): results of a query never depend on the
+ * other queries it is batched with.  prec must be TOR_PREC_F64 or
+ * TOR_PREC_DD.  A context created while the environment variable
+ * TOR_TUNE_CACHE names such a file loads it. */
+tor_status tor_autotune(tor_ctx *ctx, tor_prec prec, int32_t n_lo, int32_t n_hi, const char *cache_path);
+tor_status tor_load_tuning(tor_ctx *ctx, const char *cache_path);
+/* The task size a tree of n modes will use with precision prec. */
+tor_status tor_get_tuning(const tor_ctx *ctx, tor_prec prec, int32_t n, int32_t *task_modes);
+
 /* Thread-local message of the last error on this thread ("" if none). */
 const char *tor_last_error(void);
 

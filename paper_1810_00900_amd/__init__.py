@@ -141,6 +141,9 @@ def lib():
         "tor_wait": ([vp, ctypes.c_uint64, ctypes.POINTER(_CResult), dp], ctypes.c_int32),
         "tor_server_get_stats": ([vp, ctypes.POINTER(_CServerStats)], ctypes.c_int32),
         "tor_server_stop": ([vp], ctypes.c_int32),
+        "tor_autotune": ([vp, ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p], ctypes.c_int32),
+        "tor_load_tuning": ([vp, ctypes.c_char_p], ctypes.c_int32),
+        "tor_get_tuning": ([vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int32),
         "gbs_sample": ([vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                         ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(_CGbsStats)], ctypes.c_int32),
         "gbs_trace": ([vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
@@ -249,6 +252,19 @@ class Context:
         _check(lib().tor_subset_sum(self._h, _dptr(sigma), None if lo is None else _dptr(lo), n, _PREC[prec],
                                     float(tol), ctypes.byref(r)))
         return Result._from(r)
+
+    def autotune(self, prec="dd", n_lo=10, n_hi=24, cache_path=None):
+        """Time the wave-tier task sizes per n and keep the fastest (tor_autotune)."""
+        _check(lib().tor_autotune(self._h, _PREC[prec], int(n_lo), int(n_hi),
+                                  None if cache_path is None else str(cache_path).encode()))
+
+    def load_tuning(self, cache_path):
+        _check(lib().tor_load_tuning(self._h, str(cache_path).encode()))
+
+    def tuning(self, prec, n) -> int:
+        v = ctypes.c_int32()
+        _check(lib().tor_get_tuning(self._h, _PREC[prec], int(n), ctypes.byref(v)))
+        return v.value
 
     def gbs_sample(self, cov, n_post: int, seed: int, n_samples: int):
         """Exact chain-rule threshold samples (gbs_sample); returns

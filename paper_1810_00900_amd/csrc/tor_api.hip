@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -96,6 +97,8 @@ struct tor_ctx {
     std::vector<unsigned char> host_jobs, host_stage;
     bool timing = false;
     int task_modes = 9;
+    // autotuned task size per (precision, n); 0 = use task_modes
+    int tuned[2][TOR_MAX_CLICKS + 1] = {};
     int wave_grid = 65536;
     size_t mem_budget = (size_t)64 << 30;
     tor_stats stats{};
@@ -283,9 +286,17 @@ struct SumOut {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device bytes one subset sum of n modes needs (pool + descriptors + partials).
-size_t sum_bytes(int n, int task_modes, size_t es) {
+// Task size (modes per wave-tier task) for a tree of n modes: the autotuned
+// choice for (precision, n) if any, else the context's setting.
+int task_modes_for(const tor_ctx *ctx, bool use_dd, int n) {
+    int t = (n >= 0 && n <= TOR_MAX_CLICKS) ? ctx->tuned[use_dd ? 1 : 0][n] : 0;
+    return std::min(n, t > 0 ? t : ctx->task_modes);
+}
+
+size_t sum_bytes(int n, int J, size_t es) {
     if (n == 0) return 0;
-    const int J = std::min(n, task_modes), G = n - J;
+    J = std::min(n, J);
+    const int G = n - J;
     unsigned long long total = (unsigned long long)E(n);
     for (int d = 0; d < G; d++) total += (1ULL << d) * (unsigned long long)E(n - d - 1);
     const size_t nt = (size_t)1 << G;
@@ -316,7 +327,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
         Plan p;
         p.q = q;
         p.n = in[q].n;
-        p.J = std::min(p.n, ctx->task_modes);
+        p.J = task_modes_for(ctx, use_dd, p.n);
         p.G = p.n - p.J;
         p.nt = 1LL << p.G;
         p.root_off = roots;
@@ -532,7 +543,7 @@ tor_status gpu_sums(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vecto
             out[q] = SumOut{};
             continue;
         }
-        size_t b = sum_bytes(in[q].n, ctx->task_modes, es);
+        size_t b = sum_bytes(in[q].n, task_modes_for(ctx, use_dd, in[q].n), es);
         if (!group.empty() && (bytes + b > ctx->mem_budget / 2 || group.size() >= 65536)) {
             tor_status s = gpu_group(ctx, in, group, use_dd, out);
             if (s) return s;
@@ -684,6 +695,8 @@ tor_status evaluate_many(tor_ctx *ctx, std::vector<Prepared> &qs, tor_prec prec,
 
 extern "C" {
 
+tor_status tor_load_tuning(tor_ctx *ctx, const char *cache_path);
+
 const char *tor_last_error(void) { return g_err.c_str(); }
 
 tor_status tor_ctx_create(int device, tor_ctx **out) {
@@ -708,6 +721,9 @@ tor_status tor_ctx_create(int device, tor_ctx **out) {
     }
     c->host_res_cap = 64;
     for (auto &e : c->ev) (void)hipEventCreate(&e);
+    if (const char *tc = std::getenv("TOR_TUNE_CACHE")) {
+        if (*tc && tor_load_tuning(c, tc) != TOR_OK) g_err.clear();  // a missing cache is not an error
+    }
     *out = c;
     return TOR_OK;
 }
@@ -1087,7 +1103,7 @@ void server_worker(tor_server *S, int w) {
             while (!S->pending.empty() && (int)take.size() < S->opts.max_batch) {
                 uint64_t t = S->pending.front();
                 ServerReq &r = *S->reqs[t];
-                size_t b = sum_bytes(r.prep.n, ctx->task_modes, es);
+                size_t b = sum_bytes(r.prep.n, task_modes_for(ctx, S->opts.prec == TOR_PREC_DD, r.prep.n), es);
                 if (!take.empty() && bytes + b > S->opts.mem_budget_bytes) break;
                 bytes += b;
                 take.push_back(t);
@@ -1163,6 +1179,7 @@ tor_status tor_server_start(tor_ctx *ctx, const tor_server_opts *opts, tor_serve
             return st;
         }
         c->task_modes = ctx->task_modes;
+        std::memcpy(c->tuned, ctx->tuned, sizeof c->tuned);
         c->wave_grid = ctx->wave_grid;
         c->mem_budget = std::max(ctx->mem_budget, o.mem_budget_bytes);
         S->wctx.push_back(c);
@@ -1191,7 +1208,7 @@ tor_status tor_submit(tor_server *S, const tor_state *st, const int8_t *pattern,
     if (s == TOR_OK) s = prepare(sig, n, pvac, log_pvac, r->prep);
     if (s) return s;
     const size_t es = S->opts.prec == TOR_PREC_F64 ? sizeof(double) : sizeof(dd);
-    if (sum_bytes(n, S->wctx[0]->task_modes, es) > S->wctx[0]->mem_budget)
+    if (sum_bytes(n, task_modes_for(S->wctx[0], S->opts.prec == TOR_PREC_DD, n), es) > S->wctx[0]->mem_budget)
         return fail(TOR_ENOMEM, "query with %d clicks exceeds the device memory budget", n);
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -1243,6 +1260,135 @@ tor_status tor_server_stop(tor_server *S) {
     for (auto &t : S->threads) t.join();
     for (tor_ctx *c : S->wctx) tor_ctx_destroy(c);
     delete S;
+    return TOR_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ autotuner
+//
+// Picks the wave-tier task size J (modes per task) for each tree size n by
+// timing the candidates on a synthetic SPD matrix with the same structure as
+// the workloads (2x2 mode blocks, moderate conditioning).  The choice depends
+// only on (precision, n), so a query's result never depends on the other
+// queries of a batch.
+
+namespace {
+
+std::vector<dd> synthetic_sigma(int n) {
+    // sigma = I + B B^T / (2n) with B from a fixed linear congruential stream
+    const int d = 2 * n;
+    std::vector<double> B((size_t)d * d);
+    unsigned s = 2024u;
+    for (auto &b : B) {
+        s = s * 1664525u + 1013904223u;
+        b = ((s >> 8) & 0xffffff) / 16777216.0 - 0.5;
+    }
+    std::vector<dd> sig((size_t)d * d);
+    for (int i = 0; i < d; i++)
+        for (int j = 0; j < d; j++) {
+            double v = i == j ? 1.0 : 0.0;
+            for (int k = 0; k < d; k++) v += B[(size_t)i * d + k] * B[(size_t)j * d + k] / (2.0 * n);
+            sig[(size_t)i * d + j] = dd_from(v);
+        }
+    return sig;
+}
+
+}  // namespace
+
+extern "C" {
+
+tor_status tor_autotune(tor_ctx *ctx, tor_prec prec, int32_t n_lo, int32_t n_hi, const char *cache_path) {
+    if (!ctx) return fail(TOR_EINVAL, "ctx is NULL");
+    if (prec != TOR_PREC_F64 && prec != TOR_PREC_DD) return fail(TOR_EINVAL, "tune TOR_PREC_F64 or TOR_PREC_DD");
+    if (n_lo < 1 || n_hi > TOR_MAX_CLICKS || n_lo > n_hi) return fail(TOR_EINVAL, "bad n range");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const bool use_dd = prec == TOR_PREC_DD;
+    const int slot = use_dd ? 1 : 0;
+    for (int n = n_lo; n <= n_hi; n++) {
+        Prepared p;
+        tor_status s = prepare(synthetic_sigma(n), n, dd_from(1.0), 0.0, p);
+        if (s) return s;
+        std::vector<SumIn> in(1);
+        in[0].packed = &p.packed;
+        in[0].n = n;
+        std::vector<int> which{0};
+        std::vector<SumOut> out(1);
+        int best = std::min(n, 9);
+        double best_t = 1e300;
+        for (int J = std::min(n, 9); J >= std::max(1, std::min(n, 6)); J--) {
+            ctx->tuned[slot][n] = J;
+            s = gpu_sums(ctx, in, which, use_dd, out);  // warm
+            if (s) return s;
+            const int reps = n <= 20 ? 5 : (n <= 26 ? 3 : 1);
+            auto t0 = std::chrono::steady_clock::now();
+            for (int r = 0; r < reps; r++) {
+                s = gpu_sums(ctx, in, which, use_dd, out);
+                if (s) return s;
+            }
+            double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / reps;
+            if (t < best_t) {
+                best_t = t;
+                best = J;
+            }
+            if (J == n) break;
+        }
+        ctx->tuned[slot][n] = best;
+    }
+    if (cache_path && *cache_path) {
+        FILE *f = std::fopen(cache_path, "w");
+        if (!f) return fail(TOR_EINVAL, "cannot write %s", cache_path);
+        hipDeviceProp_t prop;
+        (void)hipGetDeviceProperties(&prop, ctx->device);
+        std::fprintf(f, "{\"arch\": \"%s\", \"task_modes\": {", prop.gcnArchName);
+        bool first = true;
+        for (int sl = 0; sl < 2; sl++)
+            for (int n = 0; n <= TOR_MAX_CLICKS; n++)
+                if (ctx->tuned[sl][n] > 0) {
+                    std::fprintf(f, "%s\"%s:%d\": %d", first ? "" : ", ", sl ? "dd" : "f64", n, ctx->tuned[sl][n]);
+                    first = false;
+                }
+        std::fprintf(f, "}}\n");
+        std::fclose(f);
+    }
+    return TOR_OK;
+}
+
+tor_status tor_load_tuning(tor_ctx *ctx, const char *cache_path) {
+    if (!ctx || !cache_path) return fail(TOR_EINVAL, "NULL argument");
+    FILE *f = std::fopen(cache_path, "r");
+    if (!f) return fail(TOR_EINVAL, "cannot read %s", cache_path);
+    std::string txt;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, k);
+    std::fclose(f);
+    // entries look like "dd:24": 9
+    int loaded = 0;
+    for (size_t pos = 0; (pos = txt.find('"', pos)) != std::string::npos;) {
+        size_t end = txt.find('"', pos + 1);
+        if (end == std::string::npos) break;
+        std::string key = txt.substr(pos + 1, end - pos - 1);
+        pos = end + 1;
+        int sl = key.rfind("dd:", 0) == 0 ? 1 : (key.rfind("f64:", 0) == 0 ? 0 : -1);
+        if (sl < 0) continue;
+        int n = std::atoi(key.c_str() + (sl ? 3 : 4));
+        size_t colon = txt.find(':', pos);
+        if (colon == std::string::npos) break;
+        int J = std::atoi(txt.c_str() + colon + 1);
+        if (n >= 0 && n <= TOR_MAX_CLICKS && J >= 1 && J <= 9) {
+            ctx->tuned[sl][n] = J;
+            loaded++;
+        }
+    }
+    if (!loaded) return fail(TOR_EINVAL, "no task sizes in %s", cache_path);
+    return TOR_OK;
+}
+
+tor_status tor_get_tuning(const tor_ctx *ctx, tor_prec prec, int32_t n, int32_t *task_modes) {
+    if (!ctx || !task_modes) return fail(TOR_EINVAL, "NULL argument");
+    if (n < 0 || n > TOR_MAX_CLICKS) return fail(TOR_EINVAL, "bad n");
+    *task_modes = task_modes_for(ctx, prec == TOR_PREC_DD, n);
     return TOR_OK;
 }
 
