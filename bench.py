@@ -62,6 +62,13 @@ def tree_flops(n, top=None):
     return sum((2 ** (r0 - r)) * dd_node_flops(r) for r in range(1, r0 + 1))
 
 
+def wave_kernel_name(prec, J):
+    """Name of the wave-tier kernel that runs J-mode tasks (as rocprofv3 lists
+    it, template arguments shortened)."""
+    s = "dd" if prec == "dd" else "double"
+    return f"wave_kernel_top<{s},{J}>" if J > 9 else f"wave_kernel<{s},{J}>"
+
+
 def cpu_baseline(cov, pattern, n, seconds_target=15.0):
     """Time the binary128 oracle on a strided sample of the same subset sum."""
     import oracle
@@ -95,7 +102,8 @@ def measured_traffic(kernel):
     rocprofv3 FETCH_SIZE/WRITE_SIZE measurement (profiles/), scaled by the
     copy-kernel calibration; None when the kernel sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_wave_kernel_dd9_m800_n28.json")
+    slug = kernel.replace("<", "_").replace(",", "").replace(">", "").replace("double", "f64")
+    path = os.path.join(ROOT, "profiles", f"traffic_{slug}_m800_n28.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -254,11 +262,11 @@ def main():
     subsets = 2.0 ** n * args.steps
     value = subsets / wall
 
-    J = min(n, 9)
+    J = ctx.tuning(args.prec, n)
     ntasks = 2 ** (n - J)
     wave_ms = st["wave_ms"] / max(st["wave_launches"], 1)
     wave_flops = tree_flops(n, top=J) * ntasks
-    kname = f"wave_kernel<dd,{J}>" if args.prec == "dd" else f"wave_kernel<double,{J}>"
+    kname = wave_kernel_name(args.prec, J)
     achieved = wave_flops / (wave_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,

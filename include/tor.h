@@ -105,7 +105,8 @@ typedef struct {
 /* Options settable on a context (tor_ctx_set_option). */
 typedef enum {
     TOR_OPT_TIMING = 0,     /* 1: record HIP events around every launch (default 0) */
-    TOR_OPT_TASK_MODES = 1, /* modes per wave-tier task, 1..9 (default 9) */
+    TOR_OPT_TASK_MODES = 1, /* modes per wave-tier task, 1..11, both precisions
+                             (default 10 for dd terms, 11 for binary64 terms) */
     TOR_OPT_WAVE_GRID = 2,  /* cap on wave-tier workgroups per launch (default 65536) */
     TOR_OPT_MEM_BUDGET = 3  /* device bytes the context may hold (default 64 GiB) */
 } tor_option;
@@ -123,7 +124,7 @@ tor_status tor_ctx_get_stats(const tor_ctx *ctx, tor_stats *out);
 tor_status tor_ctx_reset_stats(tor_ctx *ctx);
 
 /* Autotuner: for each tree size n in [n_lo, n_hi] time the candidate
- * wave-tier task sizes (6..9 modes per task) on a synthetic SPD matrix and
+ * wave-tier task sizes (6..11 modes per task) on a synthetic SPD matrix and
  * keep the fastest for (prec, n) in ctx; with cache_path != NULL also write
  * the table as JSON ({"arch": ..., "task_modes": {"dd:24": 9, ...}}).  The
  * choice depends only on (prec, n): results of a query never depend on the

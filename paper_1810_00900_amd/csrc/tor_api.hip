@@ -96,7 +96,9 @@ struct tor_ctx {
     size_t host_res_cap = 0;
     std::vector<unsigned char> host_jobs, host_stage;
     bool timing = false;
-    int task_modes = 9;
+    // wave-tier task size per precision [f64, dd] unless tuned: measured best
+    // on MI355X for the large trees (n >= 24)
+    int task_modes[2] = {11, 10};
     // autotuned task size per (precision, n); 0 = use task_modes
     int tuned[2][TOR_MAX_CLICKS + 1] = {};
     int wave_grid = 65536;
@@ -290,7 +292,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // choice for (precision, n) if any, else the context's setting.
 int task_modes_for(const tor_ctx *ctx, bool use_dd, int n) {
     int t = (n >= 0 && n <= TOR_MAX_CLICKS) ? ctx->tuned[use_dd ? 1 : 0][n] : 0;
-    return std::min(n, t > 0 ? t : ctx->task_modes);
+    return std::min(n, t > 0 ? t : ctx->task_modes[use_dd ? 1 : 0]);
 }
 
 size_t sum_bytes(int n, int J, size_t es) {
@@ -757,8 +759,8 @@ tor_status tor_ctx_set_option(tor_ctx *c, tor_option opt, int64_t v) {
     switch (opt) {
     case TOR_OPT_TIMING: c->timing = v != 0; return TOR_OK;
     case TOR_OPT_TASK_MODES:
-        if (v < 1 || v > 9) return fail(TOR_EINVAL, "task modes must be in 1..9");
-        c->task_modes = (int)v;
+        if (v < 1 || v > TOR_TASK_MAX) return fail(TOR_EINVAL, "task modes must be in 1..%d", TOR_TASK_MAX);
+        c->task_modes[0] = c->task_modes[1] = (int)v;
         return TOR_OK;
     case TOR_OPT_WAVE_GRID:
         if (v < 1 || v > (1LL << 30)) return fail(TOR_EINVAL, "bad wave grid cap");
@@ -1178,7 +1180,8 @@ tor_status tor_server_start(tor_ctx *ctx, const tor_server_opts *opts, tor_serve
             delete S;
             return st;
         }
-        c->task_modes = ctx->task_modes;
+        c->task_modes[0] = ctx->task_modes[0];
+        c->task_modes[1] = ctx->task_modes[1];
         std::memcpy(c->tuned, ctx->tuned, sizeof c->tuned);
         c->wave_grid = ctx->wave_grid;
         c->mem_budget = std::max(ctx->mem_budget, o.mem_budget_bytes);
@@ -1314,9 +1317,9 @@ tor_status tor_autotune(tor_ctx *ctx, tor_prec prec, int32_t n_lo, int32_t n_hi,
         in[0].n = n;
         std::vector<int> which{0};
         std::vector<SumOut> out(1);
-        int best = std::min(n, 9);
+        int best = std::min(n, TOR_TASK_MAX);
         double best_t = 1e300;
-        for (int J = std::min(n, 9); J >= std::max(1, std::min(n, 6)); J--) {
+        for (int J = std::min(n, TOR_TASK_MAX); J >= std::max(1, std::min(n, 6)); J--) {
             ctx->tuned[slot][n] = J;
             s = gpu_sums(ctx, in, which, use_dd, out);  // warm
             if (s) return s;
@@ -1376,7 +1379,7 @@ tor_status tor_load_tuning(tor_ctx *ctx, const char *cache_path) {
         size_t colon = txt.find(':', pos);
         if (colon == std::string::npos) break;
         int J = std::atoi(txt.c_str() + colon + 1);
-        if (n >= 0 && n <= TOR_MAX_CLICKS && J >= 1 && J <= 9) {
+        if (n >= 0 && n <= TOR_MAX_CLICKS && J >= 1 && J <= TOR_TASK_MAX) {
             ctx->tuned[sl][n] = J;
             loaded++;
         }

@@ -4,6 +4,9 @@
 #include <stdint.h>
 
 #define TOR_MAX_N 32
+// largest wave-tier task (modes per task): nine-mode trees, plus 10- and
+// 11-mode tasks that take their top one or two decisions in LDS first
+#define TOR_TASK_MAX 11
 
 // A node of the subset tree: its packed matrix starts at pool + off (in
 // scalars; the node uses the leading r-mode prefix), and the signed product of

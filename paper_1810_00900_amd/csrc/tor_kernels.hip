@@ -42,9 +42,16 @@
 
 namespace tor {
 
+// Waves per SIMD the wave tier asks the register allocator for: two where two
+// workgroups' LDS fit a quarter of the CU's 160 KiB (one wave per workgroup),
+// so that a second wave can hide the first one's latency; else one.
+template <class S, int J> struct WaveOcc {
+    static constexpr int value = sizeof(WaveSmem<S, J>) + 512 <= 20480 ? 2 : 1;
+};
+
 template <class S, int J>
-__global__ __launch_bounds__(64) void wave_kernel(const WaveJob *__restrict__ jobs, int njobs, long long total,
-                                                  const S *__restrict__ pool) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, J>::value))) void wave_kernel(
+    const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool) {
     __shared__ WaveSmem<S, J> sm;
     const int lane = threadIdx.x;
     wave_tree_init(sm.ab, lane);
@@ -57,6 +64,106 @@ __global__ __launch_bounds__(64) void wave_kernel(const WaveJob *__restrict__ jo
         dd T;
         double A;
         wave_tree<S, J>(sm, dd_make(d.coef_hi, d.coef_lo), d.acoef, lane, T, A);
+        wave_reduce(T, A);
+        if (lane == 0) {
+            Partial p;
+            p.t_hi = T.hi;
+            p.t_lo = T.lo;
+            p.a = A;
+            p.pad = 0.0;
+            jobs[j].out[lt] = p;
+        }
+        __syncthreads();
+    }
+}
+
+// Tasks of 10 or 11 modes: the top one or two decisions are taken in LDS,
+// depth first, above the nine-mode tree.  At a 10-mode node the pivot columns
+// of its last mode are set aside, the exclude child (the leading nine-mode
+// block, in place) is summed by the nine-mode tree, then the include child is
+// formed in place over that block (the HBM tier's update) and summed the same
+// way.  An 11-mode task sums its exclude child (the leading 10-mode block) so,
+// then rebuilds its include child from the task's matrix, still in HBM, and
+// sums that.  Each top level saves one HBM level for a few hundred bytes of LDS.
+template <class S> struct TopSmem {
+    WaveSmem<S, 9> w;
+    S vtop[2][2 * (2 * TOR_TASK_MAX - 2)];
+};
+
+// pivot of the last mode of the r-mode node m[] and its two scaled columns
+template <class S, int r>
+__device__ __forceinline__ Pivot<S> top_columns(const S *m, S *v, int lane) {
+    constexpr int R = 2 * r, RC = R - 2;
+    // every lane forms the pivot (same value everywhere, no LDS round trip)
+    const Pivot<S> pv = make_pivot(m[pidx(R - 2, R - 2)], m[pidx(R - 1, R - 2)], m[pidx(R - 1, R - 1)]);
+    for (int c = lane; c < RC; c += 64) {
+        S m0 = m[pidx(R - 2, c)];
+        v[c] = mul_s(m0, pv.s1);
+        v[RC + c] = mul_s(sub_mul(m[pidx(R - 1, c)], pv.l, m0), pv.s2);
+    }
+    return pv;
+}
+
+// dst[e] = src[e] - v1(a) v1(b) - v2(a) v2(b) for the (r-1)-mode child, e < E(r-1)
+template <class S, int r>
+__device__ __forceinline__ void top_update(const S *src, S *dst, const S *v, int lane) {
+    constexpr int RC = 2 * r - 2;
+    for (int e = lane; e < E(r - 1); e += 64) {
+        int a, b;
+        unpack(e, a, b);
+        dst[e] = sub_dot2(src[e], v[a], v[b], v[RC + a], v[RC + b]);
+    }
+}
+
+// the 10-mode node in sm.w.mat[0 .. E(10)); adds this lane's share to (T, A)
+template <class S>
+__device__ __forceinline__ void top10(TopSmem<S> &sm, dd c, double a, int lane, dd &T, double &A) {
+    S *v = sm.vtop[0];
+    const Pivot<S> pv = top_columns<S, 10>(sm.w.mat, v, lane);
+    __syncthreads();
+    dd t;
+    double x;
+    wave_tree<S, 9>(sm.w, c, a, lane, t, x);
+    T = dd_add(T, t);
+    A += x;
+    __syncthreads();
+    top_update<S, 10>(sm.w.mat, sm.w.mat, v, lane);
+    __syncthreads();
+    wave_tree<S, 9>(sm.w, dd_neg(coef_mul(c, pv.q)), a * hi_of(pv.q), lane, t, x);
+    T = dd_add(T, t);
+    A += x;
+}
+
+template <class S, int J>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9>::value))) void wave_kernel_top(
+    const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool) {
+    static_assert(J == 10 || J == 11, "top levels: one or two");
+    static_assert(WaveCfg<S, 9>::MAT >= E(J), "the task's matrix must fit the nine-mode working set");
+    __shared__ TopSmem<S> sm;
+    const int lane = threadIdx.x;
+    wave_tree_init(sm.w.ab, lane);
+    for (long long t = blockIdx.x; t < total; t += gridDim.x) {
+        const int j = find_job(jobs, njobs, t);
+        const long long lt = t - jobs[j].begin;
+        NodeDesc d = jobs[j].tasks[lt];
+        const S *root = pool + d.off;
+        for (int e = lane; e < E(J); e += 64) sm.w.mat[e] = root[e];
+        __syncthreads();
+        const dd c0 = dd_make(d.coef_hi, d.coef_lo);
+        dd T = dd_from(0.0);
+        double A = 0.0;
+        if constexpr (J == 10) {
+            top10(sm, c0, d.acoef, lane, T, A);
+        } else {
+            S *v = sm.vtop[1];
+            const Pivot<S> pv = top_columns<S, 11>(sm.w.mat, v, lane);
+            __syncthreads();
+            top10(sm, c0, d.acoef, lane, T, A);
+            __syncthreads();
+            top_update<S, 11>(root, sm.w.mat, v, lane);
+            __syncthreads();
+            top10(sm, dd_neg(coef_mul(c0, pv.q)), d.acoef * hi_of(pv.q), lane, T, A);
+        }
         wave_reduce(T, A);
         if (lane == 0) {
             Partial p;
@@ -189,6 +296,16 @@ static hipError_t launch_wave_J(const WaveJob *jobs, int njobs, long long total,
     return hipGetLastError();
 }
 
+template <class S, int J>
+static hipError_t launch_wave_top(const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
+                                  hipStream_t st) {
+    long long g = total < grid_cap ? total : grid_cap;
+    if (g < 1) return hipSuccess;
+    hipLaunchKernelGGL((wave_kernel_top<S, J>), dim3((unsigned)g), dim3(64), 0, st, jobs, njobs, total,
+                       (const S *)pool);
+    return hipGetLastError();
+}
+
 template <class S>
 static hipError_t launch_wave_S(int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
                                 int grid_cap, hipStream_t st) {
@@ -202,6 +319,8 @@ static hipError_t launch_wave_S(int J, const WaveJob *jobs, int njobs, long long
     case 7: return launch_wave_J<S, 7>(jobs, njobs, total, pool, grid_cap, st);
     case 8: return launch_wave_J<S, 8>(jobs, njobs, total, pool, grid_cap, st);
     case 9: return launch_wave_J<S, 9>(jobs, njobs, total, pool, grid_cap, st);
+    case 10: return launch_wave_top<S, 10>(jobs, njobs, total, pool, grid_cap, st);
+    case 11: return launch_wave_top<S, 11>(jobs, njobs, total, pool, grid_cap, st);
     default: return hipErrorInvalidValue;
     }
 }

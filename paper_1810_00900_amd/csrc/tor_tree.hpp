@@ -188,7 +188,9 @@ template <class S, int J, int K> struct WaveLevel {
             // phase 2: rank-2 updates into the include children's slots.  Each
             // lane's entries are taken in chunks: all loads of a chunk first,
             // then the independent updates (computed unconditionally so that
-            // their dependency chains interleave), then the stores.
+            // their dependency chains interleave), then the stores.  A lane
+            // past the end stores into piv[] (dead until the next level's
+            // phase 0), so the whole phase is one branch-free block.
             {
                 constexpr int TOT = NK * EC, JJ = (TOT + 63) / 64;
                 constexpr int NCH = (JJ + 3) / 4, CH = (JJ + NCH - 1) / NCH;
@@ -216,8 +218,10 @@ template <class S, int J, int K> struct WaveLevel {
 #pragma unroll
                     for (int u = 0; u < CH; ++u) r[u] = sub_dot2(x[u], p1[u], q1[u], p2[u], q2[u]);
 #pragma unroll
-                    for (int u = 0; u < CH; ++u)
-                        if (dst[u] >= 0) mat[dst[u]] = r[u];
+                    for (int u = 0; u < CH; ++u) {
+                        S *dp = dst[u] >= 0 ? mat + dst[u] : reinterpret_cast<S *>(piv);
+                        *dp = r[u];
+                    }
                 }
             }
             __syncthreads();

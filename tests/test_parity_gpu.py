@@ -276,12 +276,48 @@ def test_tmsv_pairs_28(ctx):
 def test_tiling_independent(ctx, cov800):
     pat = gi.config5_pattern(16)
     vals = []
-    for j in (3, 5, 7, 9):
-        ctx.set_option(tg.OPT_TASK_MODES, j)
-        vals.append(_gpu_p(ctx.probability(cov800, pat, prec="dd")))
-    ctx.set_option(tg.OPT_TASK_MODES, 9)
+    c = tg.Context(0)
+    for j in (3, 5, 7, 9, 10, 11):
+        c.set_option(tg.OPT_TASK_MODES, j)
+        vals.append(_gpu_p(c.probability(cov800, pat, prec="dd")))
+    c.close()
     for v in vals[1:]:
         assert _rel(v, vals[0]) <= 1e-13
+
+
+@pytest.mark.parametrize("J,n", [(10, 10), (10, 12), (10, 16), (11, 11), (11, 12), (11, 16)])
+def test_top_level_tasks_vs_oracle(ctx, cov800, J, n):
+    """10- and 11-mode wave tasks (top one or two decisions in LDS, then
+    nine-mode trees): n = J is one task with no HBM level, larger n span
+    2^(n-J) tasks."""
+    pat = gi.config5_pattern(n)
+    o = oracle.formS(cov800, pat)
+    c = tg.Context(0)
+    try:
+        c.set_option(tg.OPT_TASK_MODES, J)
+        r = c.probability(cov800, pat, prec="dd")
+        c.set_option(tg.OPT_TASK_MODES, 9)
+        r9 = c.probability(cov800, pat, prec="dd")
+    finally:
+        c.close()
+    err = _rel(_gpu_p(r), _orc_p(o))
+    assert err <= 1e-10
+    assert err <= r.rel_err_bound
+    assert _rel(_gpu_p(r), _gpu_p(r9)) <= 1e-13
+    assert r.abs_sum == pytest.approx(r9.abs_sum, rel=1e-13)
+
+
+@pytest.mark.parametrize("J", [10, 11])
+def test_top_level_tasks_f64(ctx, cov800, J):
+    pat = gi.config5_pattern(14)
+    o = oracle.formS(cov800, pat)
+    c = tg.Context(0)
+    try:
+        c.set_option(tg.OPT_TASK_MODES, J)
+        r = c.probability(cov800, pat, prec="f64")
+    finally:
+        c.close()
+    assert _rel(_gpu_p(r), _orc_p(o)) <= r.rel_err_bound
 
 
 def test_deterministic(ctx, cov800):

@@ -60,7 +60,8 @@ def test_alone_vs_mix_identical(ctx, setup):
 def test_memory_admission_splits_batches(ctx, setup):
     covs, states, qs = setup
     pats = [gi.config5_pattern(12, seed=s) for s in range(20)]
-    with tg.Server(ctx, workers=1, prec="dd", mem_budget_bytes=64 << 10) as srv:
+    # one n = 12 query needs about 17 KB (10-mode tasks) to 28 KB (9-mode)
+    with tg.Server(ctx, workers=1, prec="dd", mem_budget_bytes=40 << 10) as srv:
         tickets = [srv.submit(states[0], p) for p in pats]
         res = [srv.wait(t)[0] for t in tickets]
         st = srv.stats()
