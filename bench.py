@@ -128,18 +128,30 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes": n * 8}))
 
 
-def per_n_rates(ctx, cov, prec, ns=(20, 24, 28), reps=3):
-    """subset-dets/s of single Torontonians at several n (whole calls)."""
+def per_n_rates(ctx, cov, prec, ns=(20, 24, 28, 32), full=False):
+    """subset-dets/s of single Torontonians at several n (whole calls).  With
+    full=True every other mode is a no-click mode (the full-pattern variant:
+    the same tree after conditioning on the m - n no-click modes)."""
     import gbs_inputs as gi
     out = {}
     for n in ns:
-        pat = gi.config5_pattern(n)
+        pat = gi.config5_pattern(n).copy()
+        if full:
+            pat[pat == -1] = 0
+        reps = 1 if n >= 32 else 3
         ctx.probability(cov, pat, prec=prec, tol=1e-8)
+        ctx.reset_stats()
         t = time.perf_counter()
         for _ in range(reps):
-            ctx.probability(cov, pat, prec=prec, tol=1e-8)
+            r = ctx.probability(cov, pat, prec=prec, tol=1e-8)
         dt = (time.perf_counter() - t) / reps
-        out[str(n)] = {"subset_dets_per_s": 2.0 ** n / dt, "ms": dt * 1e3}
+        st = ctx.stats()
+        out[str(n)] = {"subset_dets_per_s": 2.0 ** n / dt, "ms": dt * 1e3,
+                       "kernel_ms": (st["wave_ms"] + st["expand_ms"] + st["reduce_ms"]) / reps,
+                       "rel_err_bound": r.rel_err_bound}
+        if full:
+            out[str(n)]["no_click_modes"] = int((pat == 0).sum())
+            out[str(n)]["condition_launches"] = st["condition_launches"] // reps
     return out
 
 
@@ -298,6 +310,7 @@ def main():
     if not args.no_extras:
         out["per_n"] = per_n_rates(ctx, cov, args.prec)
         out["per_n_f64_terms"] = per_n_rates(ctx, cov, "f64")
+        out["per_n_full_pattern"] = per_n_rates(ctx, cov, args.prec, ns=(20, 28), full=True)
         out["sampler"] = sampler_bench(ctx)
         out["serving"] = serving_bench(ctx)
     ctx.close()

@@ -100,6 +100,7 @@ typedef struct {
     int64_t expand_launches;
     int64_t reduce_launches;
     double subsets;       /* number of subset terms evaluated (2^n per sum) */
+    int64_t condition_launches; /* no-click conditioning steps (one launch each) */
 } tor_stats;
 
 /* Options settable on a context (tor_ctx_set_option). */

@@ -56,7 +56,7 @@ class _CStats(ctypes.Structure):
     _fields_ = [("wave_ms", ctypes.c_double), ("expand_ms", ctypes.c_double),
                 ("reduce_ms", ctypes.c_double), ("wave_launches", ctypes.c_int64),
                 ("expand_launches", ctypes.c_int64), ("reduce_launches", ctypes.c_int64),
-                ("subsets", ctypes.c_double)]
+                ("subsets", ctypes.c_double), ("condition_launches", ctypes.c_int64)]
 
 
 class _CGbsStats(ctypes.Structure):

@@ -90,7 +90,7 @@ struct tor_ctx {
     int device = 0;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
-    DevBuf pool, descA, descB, partA, partB, jobs;
+    DevBuf pool, descA, descB, partA, partB, jobs, cond;
     DevBuf kbuf, koff, c_out, c_status, c_tp, c_tu, c_sub;
     Partial *host_res = nullptr;
     size_t host_res_cap = 0;
@@ -205,13 +205,23 @@ bool dd_cholesky(std::vector<dd> &A, int d, std::vector<dd> &rinv, double *log_d
     return true;
 }
 
-// Reduce a pattern to Sigma_C (2n x 2n full, double-double) and P_vac(N).
-// Marginal patterns (N empty): Sigma_C = sigma_Q[C].  Otherwise the vacuum
-// conditioning of Eq. MatrixUpdate over all of N at once:
-// sigma_Q[N] = L L^T, W = L^-1 sigma_Q[N, C], Sigma_C = sigma_Q[C] - W^T W,
-// P_vac(N) = prod 1/L_ii.
-tor_status reduce_pattern(const double *cov, int m, const int8_t *pattern, std::vector<dd> &sig, int &n,
-                          dd &pvac, double &log_pvac) {
+// A pattern reduced to what the subset tree needs.  Marginal patterns (no
+// no-click modes): Sigma_C = sigma_Q[C] and P_vac = 1, formed here.  Otherwise
+// the vacuum conditioning of Eq. MatrixUpdate over N runs on the GPU
+// (condition_on_gpu): `packed` holds sigma_Q over (C, N), clicked modes first,
+// in packed lower storage, and each step conditions on the last remaining
+// mode; P_vac(N) is the product of the steps' pivot factors q.
+struct Reduced {
+    std::vector<dd> sig;  // Sigma_C, 2n x 2n full
+    int n = 0;
+    dd pvac = {1.0, 0.0};
+    double log_pvac = 0.0;
+    bool cond = false;          // conditioning on N still to do
+    int k = 0;                  // |N|
+    std::vector<dd> packed;     // sigma_Q over (C, N), E(n + k) entries
+};
+
+tor_status reduce_pattern(const double *cov, int m, const int8_t *pattern, Reduced &out) {
     if (!pattern) return fail(TOR_EINVAL, "pattern is NULL");
     std::vector<int> C, N;
     for (int i = 0; i < m; i++) {
@@ -220,49 +230,39 @@ tor_status reduce_pattern(const double *cov, int m, const int8_t *pattern, std::
         else if (v == 0) N.push_back(i);
         else if (v != -1) return fail(TOR_EINVAL, "pattern[%d] = %d is not in {-1, 0, 1}", i, v);
     }
-    n = (int)C.size();
+    const int n = (int)C.size(), k = (int)N.size();
     if (n > TOR_MAX_CLICKS) return fail(TOR_ETOOBIG, "%d clicks > %d", n, TOR_MAX_CLICKS);
-    const int dc = 2 * n, dn = 2 * (int)N.size();
-    sig.assign((size_t)dc * dc, dd_from(0.0));
-    for (int a = 0; a < dc; a++)
-        for (int b = 0; b <= a; b++) {
-            dd v = sigq(cov, m, 2 * C[a / 2] + (a & 1), 2 * C[b / 2] + (b & 1));
-            sig[(size_t)a * dc + b] = v;
-            sig[(size_t)b * dc + a] = v;
-        }
-    pvac = dd_from(1.0);
-    log_pvac = 0.0;
-    if (dn == 0) return TOR_OK;
-    std::vector<dd> L((size_t)dn * dn), rinv;
-    for (int a = 0; a < dn; a++)
-        for (int b = 0; b <= a; b++) {
-            dd v = sigq(cov, m, 2 * N[a / 2] + (a & 1), 2 * N[b / 2] + (b & 1));
-            L[(size_t)a * dn + b] = v;
-            L[(size_t)b * dn + a] = v;
-        }
-    double ld = 0.0;
-    if (!dd_cholesky(L, dn, rinv, &ld))
-        return fail(TOR_ENOTPD, "sigma_Q restricted to the no-click modes is not positive definite");
-    log_pvac = -0.5 * ld;
-    for (int i = 0; i < dn; i++) pvac = dd_mul(pvac, rinv[i]);
-    if (dc == 0) return TOR_OK;
-    std::vector<dd> W((size_t)dn * dc);
-    for (int c = 0; c < dc; c++) {
-        int gc = 2 * C[c / 2] + (c & 1);
-        for (int i = 0; i < dn; i++) {
-            dd v = sigq(cov, m, 2 * N[i / 2] + (i & 1), gc);
-            for (int t = 0; t < i; t++) v = dd_sub(v, dd_mul(L[(size_t)i * dn + t], W[(size_t)t * dc + c]));
-            W[(size_t)i * dc + c] = dd_mul(v, rinv[i]);
-        }
+    out = Reduced();
+    out.n = n;
+    out.k = k;
+    if (k == 0) {
+        const int dc = 2 * n;
+        out.sig.assign((size_t)dc * dc, dd_from(0.0));
+        for (int a = 0; a < dc; a++)
+            for (int b = 0; b <= a; b++) {
+                dd v = sigq(cov, m, 2 * C[a / 2] + (a & 1), 2 * C[b / 2] + (b & 1));
+                out.sig[(size_t)a * dc + b] = v;
+                out.sig[(size_t)b * dc + a] = v;
+            }
+        return TOR_OK;
     }
-    for (int a = 0; a < dc; a++)
-        for (int b = 0; b <= a; b++) {
-            dd acc = dd_from(0.0);
-            for (int t = 0; t < dn; t++) acc = dd_add(acc, dd_mul(W[(size_t)t * dc + a], W[(size_t)t * dc + b]));
-            dd v = dd_sub(sig[(size_t)a * dc + b], acc);
-            sig[(size_t)a * dc + b] = v;
-            sig[(size_t)b * dc + a] = v;
-        }
+    if (n + k > TOR_COND_MAX_MODES)
+        return fail(TOR_ETOOBIG, "%d observed modes > %d for a pattern with no-click modes", n + k,
+                    TOR_COND_MAX_MODES);
+    std::vector<int> g;  // quadrature index of each row of the (C, N) matrix
+    for (int c : C) {
+        g.push_back(2 * c);
+        g.push_back(2 * c + 1);
+    }
+    for (int c : N) {
+        g.push_back(2 * c);
+        g.push_back(2 * c + 1);
+    }
+    const int d = (int)g.size();
+    out.packed.resize((size_t)E(n + k));
+    for (int a = 0; a < d; a++)
+        for (int b = 0; b <= a; b++) out.packed[(size_t)pidx(a, b)] = sigq(cov, m, g[a], g[b]);
+    out.cond = true;
     return TOR_OK;
 }
 
@@ -558,6 +558,118 @@ tor_status gpu_sums(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vecto
     return gpu_group(ctx, in, group, use_dd, out);
 }
 
+// Run the no-click conditioning of every reduced pattern with r.cond set, all
+// of them in shared launches: step t conditions every query with more than t
+// no-click modes on its last remaining mode (condition_kernel), so a batch
+// takes max |N| launches.  Afterwards r.sig, r.pvac and r.log_pvac hold the
+// conditioned matrix and the vacuum probability of N; r.cond is cleared.
+tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
+    std::vector<Reduced *> rs;
+    for (Reduced *r : all)
+        if (r->cond) rs.push_back(r);
+    size_t first = 0;
+    while (first < rs.size()) {
+        // a group that fits half the memory budget (at least one query)
+        size_t last = first, bytes = 0;
+        while (last < rs.size()) {
+            size_t b = rs[last]->packed.size() * sizeof(dd) + 64;
+            if (last > first && bytes + b > ctx->mem_budget / 2) break;
+            bytes += b;
+            last++;
+        }
+        const size_t nq = last - first;
+        std::vector<size_t> off(nq);
+        size_t tot = 0;
+        int kmax = 0;
+        for (size_t i = 0; i < nq; i++) {
+            off[i] = tot;
+            tot += rs[first + i]->packed.size();
+            kmax = std::max(kmax, rs[first + i]->k);
+        }
+        // jobs of every step, in step order
+        std::vector<CondJob> jobs;
+        struct Step {
+            size_t first;
+            int count;
+            long long blocks;
+            int rmax;
+        };
+        std::vector<Step> steps;
+        const size_t acc_off = align_up(tot * sizeof(dd), 256);
+        const size_t job_off = align_up(acc_off + nq * 3 * sizeof(double), 256);
+        for (int t = 0; t < kmax; t++) {
+            Step st{jobs.size(), 0, 0, 1};
+            for (size_t i = 0; i < nq; i++) {
+                const Reduced *r = rs[first + i];
+                if (r->k <= t) continue;
+                CondJob j{};
+                j.r = r->n + r->k - t;
+                j.begin = st.blocks;
+                jobs.push_back(j);
+                st.blocks += std::max<long long>(1, (E(j.r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
+                st.count++;
+                st.rmax = std::max(st.rmax, j.r);
+            }
+            steps.push_back(st);
+        }
+        const size_t total_bytes = job_off + jobs.size() * sizeof(CondJob);
+        if (total_bytes > ctx->mem_budget)
+            return fail(TOR_ENOMEM, "conditioning needs %.2f GB of device memory", total_bytes / 1e9);
+        if (ctx->cond.ensure(total_bytes) != hipSuccess)
+            return fail(TOR_ENOMEM, "device allocation of %.2f GB failed", total_bytes / 1e9);
+        unsigned char *dbase = (unsigned char *)ctx->cond.p;
+        dd *dmat = (dd *)dbase;
+        double *dacc = (double *)(dbase + acc_off);
+        // job pointers (device addresses) and the host image of the buffer
+        size_t ji = 0;
+        for (int t = 0; t < kmax; t++)
+            for (size_t i = 0; i < nq; i++) {
+                const Reduced *r = rs[first + i];
+                if (r->k <= t) continue;
+                jobs[ji].mat = dmat + off[i];
+                jobs[ji].acc = dacc + 3 * i;
+                ji++;
+            }
+        std::vector<unsigned char> &stage = ctx->host_stage;
+        if (stage.size() < total_bytes) stage.resize(total_bytes);
+        for (size_t i = 0; i < nq; i++)
+            std::memcpy(stage.data() + off[i] * sizeof(dd), rs[first + i]->packed.data(),
+                        rs[first + i]->packed.size() * sizeof(dd));
+        for (size_t i = 0; i < nq; i++) {
+            double a0[3] = {1.0, 0.0, 0.0};
+            std::memcpy(stage.data() + acc_off + i * 3 * sizeof(double), a0, sizeof a0);
+        }
+        std::memcpy(stage.data() + job_off, jobs.data(), jobs.size() * sizeof(CondJob));
+        hipStream_t st = ctx->stream;
+        HIP_TRY(hipMemcpyAsync(dbase, stage.data(), total_bytes, hipMemcpyHostToDevice, st));
+        const CondJob *djobs = (const CondJob *)(dbase + job_off);
+        for (const Step &sp : steps)
+            HIP_TRY(tor_launch_condition(djobs + sp.first, sp.count, sp.blocks, sp.rmax, st));
+        // results: the leading E(n) block of each matrix and the accumulators
+        HIP_TRY(hipMemcpyAsync(stage.data(), dbase, acc_off + nq * 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        ctx->stats.condition_launches += (int64_t)steps.size();
+        for (size_t i = 0; i < nq; i++) {
+            Reduced *r = rs[first + i];
+            const dd *pk = (const dd *)(stage.data() + off[i] * sizeof(dd));
+            const int dc = 2 * r->n;
+            r->sig.assign((size_t)dc * dc, dd_from(0.0));
+            for (int a = 0; a < dc; a++)
+                for (int b = 0; b <= a; b++) {
+                    r->sig[(size_t)a * dc + b] = pk[pidx(a, b)];
+                    r->sig[(size_t)b * dc + a] = pk[pidx(a, b)];
+                }
+            const double *acc = (const double *)(stage.data() + acc_off + i * 3 * sizeof(double));
+            r->pvac = dd_make(acc[0], acc[1]);
+            r->log_pvac = acc[2];
+            r->cond = false;
+            std::vector<dd>().swap(r->packed);
+        }
+        first = last;
+    }
+    return TOR_OK;
+}
+
 void pack_lower(const std::vector<dd> &full, int n, std::vector<dd> &packed) {
     const int d = 2 * n;
     packed.assign((size_t)E(n), dd_from(0.0));
@@ -740,6 +852,7 @@ void tor_ctx_destroy(tor_ctx *c) {
     c->partA.release();
     c->partB.release();
     c->jobs.release();
+    c->cond.release();
     for (DevBuf *b : {&c->kbuf, &c->koff, &c->c_out, &c->c_status, &c->c_tp, &c->c_tu, &c->c_sub}) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -792,15 +905,14 @@ tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int
     tor_status s = validate_cov_block(cov, m, pattern);
     if (s) return s;
     HIP_TRY(hipSetDevice(ctx->device));
-    std::vector<dd> sig;
-    int n = 0;
-    dd pvac;
-    double log_pvac;
-    s = reduce_pattern(cov, m, pattern, sig, n, pvac, log_pvac);
-    if (s) return s;
     if (!out) return fail(TOR_EINVAL, "out is NULL");
+    Reduced red;
+    s = reduce_pattern(cov, m, pattern, red);
+    if (s) return s;
+    s = condition_on_gpu(ctx, {&red});
+    if (s) return s;
     std::vector<Prepared> qs(1);
-    s = prepare(sig, n, pvac, log_pvac, qs[0]);
+    s = prepare(red.sig, red.n, red.pvac, red.log_pvac, qs[0]);
     if (s) return s;
     return evaluate_many(ctx, qs, prec, tol, out);
 }
@@ -862,13 +974,24 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
     if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
     HIP_TRY(hipSetDevice(ctx->device));
     std::vector<Prepared> qs((size_t)nq);
+    std::vector<Reduced> red((size_t)nq);
+    std::vector<Reduced *> rp;
     for (int q = 0; q < nq; q++) {
-        std::vector<dd> sig;
-        int n = 0;
-        dd pvac;
-        double log_pvac;
-        tor_status s = reduce_pattern(st->cov.data(), st->m, patterns + (size_t)q * st->m, sig, n, pvac, log_pvac);
-        if (s == TOR_OK) s = prepare(sig, n, pvac, log_pvac, qs[q]);
+        tor_status s = reduce_pattern(st->cov.data(), st->m, patterns + (size_t)q * st->m, red[q]);
+        if (s != TOR_OK) qs[q].status = s;
+        else rp.push_back(&red[q]);
+    }
+    tor_status cs = condition_on_gpu(ctx, rp);
+    if (cs < 0) {
+        for (int q = 0; q < nq; q++) {
+            std::memset(&out[q], 0, sizeof out[q]);
+            out[q].status = cs;
+        }
+        return cs;
+    }
+    for (int q = 0; q < nq; q++) {
+        if (qs[q].status != TOR_OK) continue;
+        tor_status s = prepare(red[q].sig, red[q].n, red[q].pvac, red[q].log_pvac, qs[q]);
         if (s != TOR_OK) {
             qs[q].status = s;
             qs[q].n = 0;
@@ -1066,6 +1189,7 @@ tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post,
 namespace {
 
 struct ServerReq {
+    Reduced red;     // patterns with no-click modes: conditioned by the worker
     Prepared prep;
     std::chrono::steady_clock::time_point t_submit, t_done;
     tor_result res;
@@ -1097,6 +1221,7 @@ void server_worker(tor_server *S, int w) {
     for (;;) {
         std::vector<uint64_t> take;
         std::vector<Prepared> batch;
+        std::vector<Reduced> red;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv_work.wait(lk, [&] { return S->stopping || !S->pending.empty(); });
@@ -1105,12 +1230,29 @@ void server_worker(tor_server *S, int w) {
             while (!S->pending.empty() && (int)take.size() < S->opts.max_batch) {
                 uint64_t t = S->pending.front();
                 ServerReq &r = *S->reqs[t];
-                size_t b = sum_bytes(r.prep.n, task_modes_for(ctx, S->opts.prec == TOR_PREC_DD, r.prep.n), es);
+                size_t b = sum_bytes(r.red.n, task_modes_for(ctx, S->opts.prec == TOR_PREC_DD, r.red.n), es) +
+                           r.red.packed.size() * sizeof(dd);
                 if (!take.empty() && bytes + b > S->opts.mem_budget_bytes) break;
                 bytes += b;
                 take.push_back(t);
                 batch.push_back(std::move(r.prep));
+                red.push_back(std::move(r.red));
                 S->pending.pop_front();
+            }
+        }
+        // no-click conditioning of the batch's full patterns, then their checks
+        std::vector<Reduced *> rp;
+        for (Reduced &x : red)
+            if (x.cond) rp.push_back(&x);
+        if (!rp.empty()) {
+            tor_status cs = condition_on_gpu(ctx, rp);
+            for (size_t i = 0; i < batch.size(); i++) {
+                if (!red[i].cond && rp.end() == std::find(rp.begin(), rp.end(), &red[i])) continue;
+                tor_status s = cs < 0 ? cs : prepare(red[i].sig, red[i].n, red[i].pvac, red[i].log_pvac, batch[i]);
+                if (s != TOR_OK) {
+                    batch[i].status = s;
+                    batch[i].n = 0;
+                }
             }
         }
         std::vector<tor_result> out(batch.size());
@@ -1203,13 +1345,14 @@ tor_status tor_submit(tor_server *S, const tor_state *st, const int8_t *pattern,
     std::unique_ptr<ServerReq> r(new (std::nothrow) ServerReq());
     if (!r) return fail(TOR_ENOMEM, "host allocation failed");
     r->t_submit = t0;
-    std::vector<dd> sig;
-    int n = 0;
-    dd pvac;
-    double log_pvac;
-    tor_status s = reduce_pattern(st->cov.data(), st->m, pattern, sig, n, pvac, log_pvac);
-    if (s == TOR_OK) s = prepare(sig, n, pvac, log_pvac, r->prep);
+    tor_status s = reduce_pattern(st->cov.data(), st->m, pattern, r->red);
     if (s) return s;
+    const int n = r->red.n;
+    if (!r->red.cond) {  // marginal pattern: ready now (conditioned ones: in the worker)
+        s = prepare(r->red.sig, n, r->red.pvac, r->red.log_pvac, r->prep);
+        if (s) return s;
+        std::vector<dd>().swap(r->red.sig);
+    }
     const size_t es = S->opts.prec == TOR_PREC_F64 ? sizeof(double) : sizeof(dd);
     if (sum_bytes(n, task_modes_for(S->wctx[0], S->opts.prec == TOR_PREC_DD, n), es) > S->wctx[0]->mem_budget)
         return fail(TOR_ENOMEM, "query with %d clicks exceeds the device memory budget", n);

@@ -55,12 +55,29 @@ struct ReduceJob {
 
 #define TOR_REDUCE_CHUNK 1024
 
+// one vacuum-conditioning step of one query: its packed matrix of r modes (the
+// no-click modes last) loses its last mode in place; acc = {P_vac hi, lo,
+// log P_vac} of the modes conditioned so far
+struct CondJob {
+    dd *mat;
+    double *acc;
+    long long begin;  // first block of the launch that works on this job
+    int r;
+    int pad;
+};
+
+#define TOR_COND_CHUNK 1024
+// largest matrix (modes) a conditioning step takes: its two scaled pivot
+// columns (2 * (2r - 2) double-doubles) must fit 64 KiB of LDS
+#define TOR_COND_MAX_MODES 1024
+
 hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
                            int grid_cap, hipStream_t st);
 hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
                              hipStream_t st);
 hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_blocks, hipStream_t st);
 hipError_t tor_launch_gather(const Partial *const *src, int n, Partial *dst, hipStream_t st);
+hipError_t tor_launch_condition(const CondJob *jobs, int njobs, long long total_blocks, int rmax, hipStream_t st);
 
 // ---- chain-rule sampler
 #define TOR_CHAIN_MAX 16  // largest tree per step (clicks so far + 1)

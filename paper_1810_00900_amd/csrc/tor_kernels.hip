@@ -231,6 +231,49 @@ __global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict
     }
 }
 
+// ---------------------------------------------------------------- no-click conditioning
+
+// One step of the vacuum conditioning (Eq. MatrixUpdate) for every query of
+// the launch: the last mode of the query's matrix (packed lower, r modes, the
+// no-click modes last) is conditioned on vacuum -- the Schur complement of its
+// 2x2 pivot block replaces the leading block in place, the include-child
+// update of the subset tree -- and the query's vacuum probability is
+// multiplied by q = det(pivot)^-1/2.  Each 256-thread block takes
+// TOR_COND_CHUNK entries of one query; it forms the pivot and the scaled pivot
+// columns its entries need in LDS (the last two rows, which the step does not
+// write).  Blocks of one step write disjoint entries.
+__global__ __launch_bounds__(256) void condition_kernel(const CondJob *__restrict__ jobs, int njobs) {
+    extern __shared__ dd cols[];
+    const int j = find_job(jobs, njobs, (long long)blockIdx.x);
+    const CondJob job = jobs[j];
+    const long long blk = (long long)blockIdx.x - job.begin;
+    const int r = job.r, R = 2 * r, RC = R - 2;
+    dd *M = job.mat;
+    const Pivot<dd> pv = make_pivot(M[pidx(R - 2, R - 2)], M[pidx(R - 1, R - 2)], M[pidx(R - 1, R - 1)]);
+    const int EC = E(r - 1);
+    const int e0 = (int)(blk * TOR_COND_CHUNK);
+    const int e1 = e0 + TOR_COND_CHUNK < EC ? e0 + TOR_COND_CHUNK : EC;
+    int amax = -1, bl;  // largest row among this block's entries (none when r = 1)
+    if (e1 > e0) unpack(e1 - 1, amax, bl);
+    for (int c = threadIdx.x; c <= amax; c += blockDim.x) {
+        const dd m0 = M[pidx(R - 2, c)];
+        cols[c] = dd_mul(m0, pv.s1);
+        cols[RC + c] = dd_mul(sub_mul(M[pidx(R - 1, c)], pv.l, m0), pv.s2);
+    }
+    __syncthreads();
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        int a, b;
+        unpack(e, a, b);
+        M[e] = dd_sub_dot2(M[e], cols[a], cols[b], cols[RC + a], cols[RC + b]);
+    }
+    if (blk == 0 && threadIdx.x == 0) {
+        const dd p = dd_mul(dd_make(job.acc[0], job.acc[1]), pv.q);
+        job.acc[0] = p.hi;
+        job.acc[1] = p.lo;
+        job.acc[2] += log(pv.q.hi) + log1p(pv.q.lo / pv.q.hi);
+    }
+}
+
 // ---------------------------------------------------------------- reduction
 
 // One reduction stage: block b of a job sums in[b*chunk, min((b+1)*chunk, count))
@@ -352,6 +395,14 @@ hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_b
     long long g = total_blocks < (1LL << 20) ? total_blocks : (1LL << 20);
     if (g < 1) return hipSuccess;
     hipLaunchKernelGGL(tor::reduce_kernel, dim3((unsigned)g), dim3(256), 0, st, jobs, njobs, total_blocks);
+    return hipGetLastError();
+}
+
+hipError_t tor_launch_condition(const CondJob *jobs, int njobs, long long total_blocks, int rmax, hipStream_t st) {
+    if (total_blocks < 1) return hipSuccess;
+    if (rmax < 1 || rmax > TOR_COND_MAX_MODES || total_blocks > (1LL << 31) - 1) return hipErrorInvalidValue;
+    const size_t lds = sizeof(dd) * 2 * (2 * (size_t)rmax - 2) + 16;
+    hipLaunchKernelGGL(tor::condition_kernel, dim3((unsigned)total_blocks), dim3(256), lds, st, jobs, njobs);
     return hipGetLastError();
 }
 
