@@ -109,7 +109,8 @@ typedef enum {
     TOR_OPT_TASK_MODES = 1, /* modes per wave-tier task, 1..11, both precisions
                              (default 10 for dd terms, 11 for binary64 terms) */
     TOR_OPT_WAVE_GRID = 2,  /* cap on wave-tier workgroups per launch (default 65536) */
-    TOR_OPT_MEM_BUDGET = 3  /* device bytes the context may hold (default 64 GiB) */
+    TOR_OPT_MEM_BUDGET = 3, /* device bytes the context may hold (default 64 GiB) */
+    TOR_OPT_ASYNC_POOL = 4  /* tree pool bytes of tor_batch_async (default 4 GiB) */
 } tor_option;
 
 /* Create a context on HIP device `device` (its own stream, default priority).
@@ -168,6 +169,31 @@ void tor_state_destroy(tor_state *st);
  * TOR_WARN_PRECISION. */
 tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *patterns, tor_prec prec,
                      double tol, tor_result *out);
+
+/* Stream-ordered form of tor_batch for callers whose patterns and results
+ * live in device memory (e.g. torch tensors): d_patterns (nq x m int8, row
+ * per query) and d_out (nq tor_result) are device pointers owned by the
+ * caller.  The call only enqueues work on `stream` (a hipStream_t; NULL: the
+ * context's stream) and returns without waiting; d_patterns is read and
+ * d_out written when the stream reaches the call, so both must stay valid
+ * until then.  The plan is made on the device for the same trees and
+ * reduction order as tor_batch: results (p, p_lo, T, T_lo, abs_sum) are
+ * bitwise those of tor_batch; log_p and tor may differ in the last bit.
+ * Marginal patterns only (entries 1 or -1): a query with a no-click mode (0)
+ * or a bad entry gets status TOR_EINVAL in its result (no-click conditioning
+ * needs host planning: use tor_batch), more than 32 clicks TOR_ETOOBIG.
+ * prec: TOR_PREC_F64 or TOR_PREC_DD; TOR_PREC_AUTO is run as TOR_PREC_DD (a
+ * query cannot be repeated without a host decision).  Device memory: a
+ * workspace whose tree pool holds TOR_OPT_ASYNC_POOL bytes (default 4 GiB);
+ * queries are admitted in order while the trees up to them fit, later ones
+ * get TOR_ENOMEM.  The first call on a state copies its covariance to the
+ * device (synchronously, once).  The workspace belongs to the context: calls
+ * on one context must be ordered (same stream, or the caller waits).
+ * Returns TOR_OK once enqueued; argument errors (NULL pointers, nq < 0, bad
+ * prec, state of another context) and launch or allocation failures are
+ * returned directly. */
+tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *d_patterns, tor_prec prec,
+                           double tol, tor_result *d_out, void *stream);
 
 /* ------------------------------------------------------------------------
  * Exact chain-rule sampling (the paper's mode-by-mode sampler, Sec. II: each

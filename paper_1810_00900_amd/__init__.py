@@ -31,7 +31,7 @@ PREC_AUTO, PREC_F64, PREC_DD = 0, 1, 2
 _PREC = {"auto": PREC_AUTO, "f64": PREC_F64, "dd": PREC_DD,
          PREC_AUTO: PREC_AUTO, PREC_F64: PREC_F64, PREC_DD: PREC_DD}
 
-OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET = 0, 1, 2, 3
+OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET, OPT_ASYNC_POOL = 0, 1, 2, 3, 4
 
 _STATUS_NAMES = {0: "TOR_OK", 1: "TOR_WARN_PRECISION", -1: "TOR_EINVAL", -2: "TOR_ENOTPD",
                  -3: "TOR_ETOOBIG", -4: "TOR_ENOMEM", -5: "TOR_EDEVICE", -6: "TOR_EAGAIN"}
@@ -135,6 +135,7 @@ def lib():
         "tor_state_destroy": ([vp], None),
         "tor_batch": ([vp, vp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
                        ctypes.POINTER(_CResult)], ctypes.c_int32),
+        "tor_batch_async": ([vp, vp, ctypes.c_int32, vp, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int32),
         "tor_server_start": ([vp, ctypes.POINTER(_CServerOpts), ctypes.POINTER(vp)], ctypes.c_int32),
         "tor_submit": ([vp, vp, i8p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
         "tor_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(_CResult), dp], ctypes.c_int32),
@@ -304,6 +305,36 @@ class Context:
         if st < 0 and all(r.status < 0 for r in res):
             raise TorError(st, last_error())
         return res, st
+
+    def batch_async(self, state: "State", d_patterns, prec="dd", tol: float = 1e-10, d_out=None, stream=None):
+        """Stream-ordered batch (tor_batch_async).  d_patterns: contiguous
+        int8 device tensor, nq x m.  Returns d_out, a uint8 device tensor of
+        nq result records, written when `stream` (a torch.cuda.Stream, a raw
+        hipStream_t int, or None for the context's stream) reaches the call;
+        decode it with results_from_device() after synchronising."""
+        import torch
+        if d_patterns.dtype != torch.int8 or not d_patterns.is_cuda or not d_patterns.is_contiguous():
+            raise ValueError("d_patterns must be a contiguous int8 device tensor")
+        if d_patterns.ndim != 2 or d_patterns.shape[1] != state.m:
+            raise ValueError("d_patterns must be nq x m")
+        nq = int(d_patterns.shape[0])
+        rec = ctypes.sizeof(_CResult)
+        if d_out is None:
+            d_out = torch.empty((nq, rec), dtype=torch.uint8, device=d_patterns.device)
+        elif d_out.dtype != torch.uint8 or not d_out.is_cuda or d_out.numel() < nq * rec or not d_out.is_contiguous():
+            raise ValueError("d_out must be a contiguous uint8 device tensor of nq result records")
+        raw = None if stream is None else getattr(stream, "cuda_stream", stream)
+        _check(lib().tor_batch_async(self._h, state.handle, nq, ctypes.c_void_p(d_patterns.data_ptr()),
+                                     _PREC[prec], float(tol), ctypes.c_void_p(d_out.data_ptr()),
+                                     ctypes.c_void_p(raw)))
+        return d_out
+
+
+def results_from_device(d_out) -> list:
+    """Decode the records written by Context.batch_async (copies to the host)."""
+    buf = d_out.detach().cpu().contiguous().numpy().tobytes()
+    rec = ctypes.sizeof(_CResult)
+    return [Result._from(_CResult.from_buffer_copy(buf, i * rec)) for i in range(len(buf) // rec)]
 
 
 class State:

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtorgbs.so")
-SOURCES = ["csrc/tor_api.hip", "csrc/tor_kernels.hip", "csrc/gbs_sampler.hip"]
+SOURCES = ["csrc/tor_api.hip", "csrc/tor_kernels.hip", "csrc/gbs_sampler.hip", "csrc/tor_async.hip"]
 
 # -ffp-contract=off: the double-double error-free transformations must not be
 # fused into FMAs by the compiler (explicit fma() calls are kept).

@@ -254,6 +254,7 @@ __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
 hipError_t tor_launch_chains(const ChainParams &P, int grid_cap, hipStream_t st) {
     int g = P.nchains < grid_cap ? P.nchains : grid_cap;
     if (g < 1) return hipSuccess;
+    (void)hipGetLastError();  // report only this launch's error
     hipLaunchKernelGGL(tor::chain_kernel<double>, dim3((unsigned)g), dim3(64), 0, st, P);
     return hipGetLastError();
 }

@@ -91,6 +91,8 @@ struct tor_ctx {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     DevBuf pool, descA, descB, partA, partB, jobs, cond;
+    DevBuf apool, abuf;  // tor_batch_async: tree pool, plan and job tables
+    size_t async_pool = (size_t)4 << 30;
     DevBuf kbuf, koff, c_out, c_status, c_tp, c_tu, c_sub;
     Partial *host_res = nullptr;
     size_t host_res_cap = 0;
@@ -109,8 +111,10 @@ struct tor_ctx {
 
 struct tor_state {
     tor_ctx *ctx = nullptr;
+    int device = 0;  // the context's device, kept for the release of dcov
     int m = 0;
     std::vector<double> cov;
+    DevBuf dcov;  // device copy for tor_batch_async (made on first use)
 };
 
 // ------------------------------------------------------------------ host math
@@ -846,6 +850,8 @@ void tor_ctx_destroy(tor_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    // stream-ordered batches may still run on the callers' streams
+    if (c->abuf.p || c->apool.p) (void)hipDeviceSynchronize();
     c->pool.release();
     c->descA.release();
     c->descB.release();
@@ -853,11 +859,14 @@ void tor_ctx_destroy(tor_ctx *c) {
     c->partB.release();
     c->jobs.release();
     c->cond.release();
+    c->apool.release();
+    c->abuf.release();
     for (DevBuf *b : {&c->kbuf, &c->koff, &c->c_out, &c->c_status, &c->c_tp, &c->c_tu, &c->c_sub}) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->host_res) (void)hipHostFree(c->host_res);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    (void)hipGetLastError();  // leave no error for the next checked call
     delete c;
 }
 
@@ -882,6 +891,10 @@ tor_status tor_ctx_set_option(tor_ctx *c, tor_option opt, int64_t v) {
     case TOR_OPT_MEM_BUDGET:
         if (v < (1 << 20)) return fail(TOR_EINVAL, "memory budget too small");
         c->mem_budget = (size_t)v;
+        return TOR_OK;
+    case TOR_OPT_ASYNC_POOL:
+        if (v < (1 << 20)) return fail(TOR_EINVAL, "async pool too small");
+        c->async_pool = (size_t)v;
         return TOR_OK;
     }
     return fail(TOR_EINVAL, "unknown option %d", (int)opt);
@@ -954,6 +967,7 @@ tor_status tor_state_create(tor_ctx *ctx, const double *cov, int32_t m, tor_stat
     tor_state *st = new (std::nothrow) tor_state();
     if (!st) return fail(TOR_ENOMEM, "host allocation failed");
     st->ctx = ctx;
+    st->device = ctx->device;
     st->m = m;
     try {
         st->cov.assign(cov, cov + 4 * (size_t)m * m);
@@ -965,7 +979,15 @@ tor_status tor_state_create(tor_ctx *ctx, const double *cov, int32_t m, tor_stat
     return TOR_OK;
 }
 
-void tor_state_destroy(tor_state *st) { delete st; }
+void tor_state_destroy(tor_state *st) {
+    if (!st) return;
+    if (st->dcov.p) {
+        (void)hipSetDevice(st->device);
+        st->dcov.release();
+        (void)hipGetLastError();  // leave no error for the next checked call
+    }
+    delete st;
+}
 
 tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *patterns, tor_prec prec,
                      double tol, tor_result *out) {
@@ -998,6 +1020,111 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
         }
     }
     return evaluate_many(ctx, qs, prec, tol, out);
+}
+
+tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *d_patterns, tor_prec prec,
+                           double tol, tor_result *d_out, void *stream) {
+    if (!ctx || !st) return fail(TOR_EINVAL, "NULL argument");
+    if (st->ctx != ctx) return fail(TOR_EINVAL, "state belongs to another context");
+    if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
+    if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD)
+        return fail(TOR_EINVAL, "bad precision %d", (int)prec);
+    if (nq == 0) return TOR_OK;
+    if (!d_patterns || !d_out) return fail(TOR_EINVAL, "NULL device pointer");
+    if (nq > (1 << 24)) return fail(TOR_ETOOBIG, "nq = %d > 2^24", nq);
+    if (!(tol > 0.0)) tol = 1e-10;
+    const bool use_dd = prec != TOR_PREC_F64;
+    const int used = use_dd ? TOR_PREC_DD : TOR_PREC_F64;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t hs = stream ? (hipStream_t)stream : ctx->stream;
+    tor_state *ms = const_cast<tor_state *>(st);  // the device copy is a cache of the state
+    const int m = st->m;
+    const size_t cov_bytes = 4 * (size_t)m * (size_t)m * sizeof(double);
+    if (!ms->dcov.p) {
+        if (ms->dcov.ensure(cov_bytes) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the state failed");
+        HIP_TRY(hipMemcpy(ms->dcov.p, st->cov.data(), cov_bytes, hipMemcpyHostToDevice));
+    }
+    // task sizes and the launches any pattern of this state can need
+    AsyncPlan P{};
+    P.nq = nq;
+    P.m = m;
+    P.is_dd = use_dd;
+    const int nmax = std::min(TOR_MAX_CLICKS, m);
+    int gcap = 0, jmax = 1;
+    long long max_tasks[TOR_TASK_MAX + 1] = {};  // per J: tasks of the largest tree
+    long long nt_max = 1;
+    bool jused[TOR_TASK_MAX + 1] = {};
+    for (int n = 0; n <= TOR_MAX_CLICKS; n++) {
+        P.J_of_n[n] = n >= 1 ? task_modes_for(ctx, use_dd, n) : 1;
+        if (n < 1 || n > nmax) continue;
+        const int J = std::min(n, P.J_of_n[n]), G = n - J;
+        gcap = std::max(gcap, G);
+        jmax = std::max(jmax, J);
+        jused[J] = true;
+        max_tasks[J] = std::max(max_tasks[J], 1LL << G);
+        nt_max = std::max(nt_max, 1LL << G);
+    }
+    P.gcap = gcap;
+    P.jmax = jmax;
+    const size_t es = use_dd ? sizeof(dd) : sizeof(double);
+    P.pool_cap = (long long)(ctx->async_pool / es);
+    P.desc_cap = P.pool_cap / 16 + nq;
+    P.pb_cap = P.desc_cap / TOR_REDUCE_CHUNK + (long long)TOR_ASYNC_STAGES * nq + 8;
+    // workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t o_q = take((size_t)nq * sizeof(AsyncQuery));
+    const size_t o_roots = take((size_t)nq * sizeof(NodeDesc));
+    const size_t o_dA = take((size_t)P.desc_cap * sizeof(NodeDesc));
+    const size_t o_dB = take((size_t)P.desc_cap * sizeof(NodeDesc));
+    const size_t o_pA = take((size_t)P.desc_cap * sizeof(Partial));
+    const size_t o_pB = take((size_t)P.pb_cap * sizeof(Partial));
+    const size_t o_ej = take((size_t)std::max(gcap, 1) * nq * sizeof(ExpandJob));
+    const size_t o_wj = take((size_t)(TOR_TASK_MAX + 1) * nq * sizeof(WaveJob));
+    const size_t o_rj = take((size_t)TOR_ASYNC_STAGES * nq * sizeof(ReduceJob));
+    const size_t o_dims = take((size_t)(gcap + TOR_TASK_MAX + 1 + TOR_ASYNC_STAGES) * sizeof(LaunchDims));
+    const size_t abytes = off, pbytes = (size_t)P.pool_cap * es;
+    if (abytes + pbytes + cov_bytes > ctx->mem_budget)
+        return fail(TOR_ENOMEM, "async workspace of %.2f GB exceeds the memory budget", (abytes + pbytes) / 1e9);
+    if (ctx->abuf.ensure(abytes) != hipSuccess || ctx->apool.ensure(pbytes) != hipSuccess)
+        return fail(TOR_ENOMEM, "device allocation of the async workspace (%.2f GB) failed", (abytes + pbytes) / 1e9);
+    unsigned char *b = (unsigned char *)ctx->abuf.p;
+    P.q = (AsyncQuery *)(b + o_q);
+    P.pool = ctx->apool.p;
+    P.roots = (NodeDesc *)(b + o_roots);
+    P.descA = (NodeDesc *)(b + o_dA);
+    P.descB = (NodeDesc *)(b + o_dB);
+    P.partA = (Partial *)(b + o_pA);
+    P.partB = (Partial *)(b + o_pB);
+    P.exp_jobs = (ExpandJob *)(b + o_ej);
+    P.wave_jobs = (WaveJob *)(b + o_wj);
+    P.red_jobs = (ReduceJob *)(b + o_rj);
+    P.dims = (LaunchDims *)(b + o_dims);
+    // scan, plan, roots; then the tree launches with device-side dimensions
+    HIP_TRY(tor_launch_async_prologue(d_patterns, (const double *)ms->dcov.p, P, hs));
+    for (int d = 0; d < gcap; d++) {
+        const long long bound = std::min<long long>(1LL << 20, ((long long)nq << d) / 4 + 1);
+        HIP_TRY(tor_launch_expand(use_dd, P.exp_jobs + (size_t)d * nq, 0, d, P.pool, (int)bound, hs, P.dims + d));
+    }
+    for (int J = jmax; J >= 1; J--) {
+        if (!jused[J]) continue;
+        const long long bound = std::min<long long>(ctx->wave_grid, (long long)nq * max_tasks[J]);
+        HIP_TRY(tor_launch_wave(use_dd, J, P.wave_jobs + (size_t)J * nq, 0, 0, P.pool, (int)bound, hs,
+                                P.dims + gcap + J));
+    }
+    long long c = nt_max;
+    for (int s = 0; s < TOR_ASYNC_STAGES && c > 1; s++) {
+        c = (c + TOR_REDUCE_CHUNK - 1) / TOR_REDUCE_CHUNK;
+        const long long bound = std::min<long long>(1LL << 20, (long long)nq * c);
+        HIP_TRY(tor_launch_reduce(P.red_jobs + (size_t)s * nq, 0, bound, hs, P.dims + gcap + TOR_TASK_MAX + 1 + s));
+    }
+    HIP_TRY(tor_launch_async_finalize(P, tol, used, d_out, hs));
+    ctx->stats.expand_launches += gcap;
+    return TOR_OK;
 }
 
 // ------------------------------------------------------------------ sampler

@@ -55,6 +55,14 @@ struct ReduceJob {
 
 #define TOR_REDUCE_CHUNK 1024
 
+// Job count and total work of a launch whose plan was made on the device
+// (stream-ordered batches): the kernels read them at entry when given a
+// non-null pointer, instead of their by-value arguments.
+struct LaunchDims {
+    long long njobs;
+    long long total;
+};
+
 // one vacuum-conditioning step of one query: its packed matrix of r modes (the
 // no-click modes last) loses its last mode in place; acc = {P_vac hi, lo,
 // log P_vac} of the modes conditioned so far
@@ -71,11 +79,55 @@ struct CondJob {
 // columns (2 * (2r - 2) double-doubles) must fit 64 KiB of LDS
 #define TOR_COND_MAX_MODES 1024
 
+// ---------------------------------------------------------------- stream-ordered batches
+// A batch whose click patterns live in device memory is planned on the device
+// (tor_async.hip): the same per-query trees, job tables and reduction order as
+// the host planner, built by one workgroup with deterministic block scans.
+
+#define TOR_ASYNC_STAGES 4   // reduction stages (TOR_REDUCE_CHUNK^4 tasks)
+
+struct AsyncQuery {
+    int status;          // tor_status of this query
+    int n, J, G;         // clicks, task size, HBM levels
+    long long nt;        // tasks (2^G; 0 when n = 0)
+    long long entries;   // pool scalars of the tree
+    long long pb;        // reduction-stage partials
+    long long pool_off, desc_off, pb_off;
+    long long final_off; // partial holding the sum: partA (final_buf 0) or partB (1)
+    int final_buf;
+    int nstage;
+    double log_det;      // log det Sigma_C (binary64 Cholesky)
+    long long slot;      // planner scratch: position of the query's job in a table
+    int C[TOR_MAX_N];    // clicked modes, ascending
+};
+
+struct AsyncPlan {
+    int nq, m, is_dd, gcap, jmax;
+    int J_of_n[TOR_MAX_N + 1];
+    long long pool_cap, desc_cap, pb_cap;  // capacities (scalars, descriptors, partials)
+    AsyncQuery *q;
+    void *pool;
+    NodeDesc *roots, *descA, *descB;
+    Partial *partA, *partB;
+    ExpandJob *exp_jobs;   // [gcap][nq]
+    WaveJob *wave_jobs;    // [TOR_TASK_MAX + 1][nq]
+    ReduceJob *red_jobs;   // [TOR_ASYNC_STAGES][nq]
+    LaunchDims *dims;      // expand [gcap], wave [TOR_TASK_MAX + 1], reduce [TOR_ASYNC_STAGES]
+};
+
+hipError_t tor_launch_async_prologue(const int8_t *d_patterns, const double *d_cov, const AsyncPlan &P,
+                                     hipStream_t st);
+hipError_t tor_launch_async_finalize(const AsyncPlan &P, double tol, int prec_used, void *d_out, hipStream_t st);
+
+// Launchers.  With dyn != nullptr (a plan made on the device) the kernels read
+// the job count and total work from dyn, and the host-side grid argument
+// (grid_cap, total_blocks) is the grid itself, a bound on the work.
 hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
-                           int grid_cap, hipStream_t st);
+                           int grid_cap, hipStream_t st, const LaunchDims *dyn = nullptr);
 hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
-                             hipStream_t st);
-hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_blocks, hipStream_t st);
+                             hipStream_t st, const LaunchDims *dyn = nullptr);
+hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_blocks, hipStream_t st,
+                             const LaunchDims *dyn = nullptr);
 hipError_t tor_launch_gather(const Partial *const *src, int n, Partial *dst, hipStream_t st);
 hipError_t tor_launch_condition(const CondJob *jobs, int njobs, long long total_blocks, int rmax, hipStream_t st);
 

@@ -51,9 +51,14 @@ template <class S, int J> struct WaveOcc {
 
 template <class S, int J>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, J>::value))) void wave_kernel(
-    const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool) {
+    const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool,
+    const LaunchDims *__restrict__ dyn) {
     __shared__ WaveSmem<S, J> sm;
     const int lane = threadIdx.x;
+    if (dyn) {
+        njobs = (int)dyn->njobs;
+        total = dyn->total;
+    }
     wave_tree_init(sm.ab, lane);
     for (long long t = blockIdx.x; t < total; t += gridDim.x) {
         const int j = find_job(jobs, njobs, t);
@@ -136,11 +141,16 @@ __device__ __forceinline__ void top10(TopSmem<S> &sm, dd c, double a, int lane, 
 
 template <class S, int J>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9>::value))) void wave_kernel_top(
-    const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool) {
+    const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool,
+    const LaunchDims *__restrict__ dyn) {
     static_assert(J == 10 || J == 11, "top levels: one or two");
     static_assert(WaveCfg<S, 9>::MAT >= E(J), "the task's matrix must fit the nine-mode working set");
     __shared__ TopSmem<S> sm;
     const int lane = threadIdx.x;
+    if (dyn) {
+        njobs = (int)dyn->njobs;
+        total = dyn->total;
+    }
     wave_tree_init(sm.w.ab, lane);
     for (long long t = blockIdx.x; t < total; t += gridDim.x) {
         const int j = find_job(jobs, njobs, t);
@@ -193,7 +203,9 @@ __device__ __forceinline__ void wave_sync() {
 // keeps the parent's offset.  Waves run independently (no workgroup barrier).
 template <class S>
 __global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict__ jobs, int log2npar,
-                                                     long long total, S *__restrict__ pool) {
+                                                     long long total, S *__restrict__ pool,
+                                                     const LaunchDims *__restrict__ dyn) {
+    if (dyn) total = dyn->njobs << log2npar;
     __shared__ S vs[4][2][2 * TOR_MAX_N];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     S *v0 = vs[w][0], *v1 = vs[w][1];
@@ -279,9 +291,13 @@ __global__ __launch_bounds__(256) void condition_kernel(const CondJob *__restric
 // One reduction stage: block b of a job sums in[b*chunk, min((b+1)*chunk, count))
 // in a fixed order (thread-strided sequential sums, then a fixed LDS tree).
 __global__ __launch_bounds__(256) void reduce_kernel(const ReduceJob *__restrict__ jobs, int njobs,
-                                                     long long total_blocks) {
+                                                     long long total_blocks, const LaunchDims *__restrict__ dyn) {
     __shared__ dd sT[256];
     __shared__ double sA[256];
+    if (dyn) {
+        njobs = (int)dyn->njobs;
+        total_blocks = dyn->total;
+    }
     for (long long gb = blockIdx.x; gb < total_blocks; gb += gridDim.x) {
         int lo_j = 0, hi_j = njobs - 1;
         while (lo_j < hi_j) {
@@ -329,41 +345,45 @@ __global__ void gather_kernel(const Partial *const *__restrict__ src, int n, Par
 
 // ---------------------------------------------------------------- launchers
 
+// With dyn (a plan made on the device) njobs and total are read from dyn by the
+// kernel and grid_cap is the grid itself.
 template <class S, int J>
 static hipError_t launch_wave_J(const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
-                                hipStream_t st) {
-    long long g = total < grid_cap ? total : grid_cap;
+                                hipStream_t st, const LaunchDims *dyn) {
+    long long g = dyn ? grid_cap : (total < grid_cap ? total : grid_cap);
     if (g < 1) return hipSuccess;
+    (void)hipGetLastError();  // report only this launch's error
     hipLaunchKernelGGL((wave_kernel<S, J>), dim3((unsigned)g), dim3(64), 0, st, jobs, njobs, total,
-                       (const S *)pool);
+                       (const S *)pool, dyn);
     return hipGetLastError();
 }
 
 template <class S, int J>
 static hipError_t launch_wave_top(const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
-                                  hipStream_t st) {
-    long long g = total < grid_cap ? total : grid_cap;
+                                  hipStream_t st, const LaunchDims *dyn) {
+    long long g = dyn ? grid_cap : (total < grid_cap ? total : grid_cap);
     if (g < 1) return hipSuccess;
+    (void)hipGetLastError();  // report only this launch's error
     hipLaunchKernelGGL((wave_kernel_top<S, J>), dim3((unsigned)g), dim3(64), 0, st, jobs, njobs, total,
-                       (const S *)pool);
+                       (const S *)pool, dyn);
     return hipGetLastError();
 }
 
 template <class S>
 static hipError_t launch_wave_S(int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
-                                int grid_cap, hipStream_t st) {
+                                int grid_cap, hipStream_t st, const LaunchDims *dyn) {
     switch (J) {
-    case 1: return launch_wave_J<S, 1>(jobs, njobs, total, pool, grid_cap, st);
-    case 2: return launch_wave_J<S, 2>(jobs, njobs, total, pool, grid_cap, st);
-    case 3: return launch_wave_J<S, 3>(jobs, njobs, total, pool, grid_cap, st);
-    case 4: return launch_wave_J<S, 4>(jobs, njobs, total, pool, grid_cap, st);
-    case 5: return launch_wave_J<S, 5>(jobs, njobs, total, pool, grid_cap, st);
-    case 6: return launch_wave_J<S, 6>(jobs, njobs, total, pool, grid_cap, st);
-    case 7: return launch_wave_J<S, 7>(jobs, njobs, total, pool, grid_cap, st);
-    case 8: return launch_wave_J<S, 8>(jobs, njobs, total, pool, grid_cap, st);
-    case 9: return launch_wave_J<S, 9>(jobs, njobs, total, pool, grid_cap, st);
-    case 10: return launch_wave_top<S, 10>(jobs, njobs, total, pool, grid_cap, st);
-    case 11: return launch_wave_top<S, 11>(jobs, njobs, total, pool, grid_cap, st);
+    case 1: return launch_wave_J<S, 1>(jobs, njobs, total, pool, grid_cap, st, dyn);
+    case 2: return launch_wave_J<S, 2>(jobs, njobs, total, pool, grid_cap, st, dyn);
+    case 3: return launch_wave_J<S, 3>(jobs, njobs, total, pool, grid_cap, st, dyn);
+    case 4: return launch_wave_J<S, 4>(jobs, njobs, total, pool, grid_cap, st, dyn);
+    case 5: return launch_wave_J<S, 5>(jobs, njobs, total, pool, grid_cap, st, dyn);
+    case 6: return launch_wave_J<S, 6>(jobs, njobs, total, pool, grid_cap, st, dyn);
+    case 7: return launch_wave_J<S, 7>(jobs, njobs, total, pool, grid_cap, st, dyn);
+    case 8: return launch_wave_J<S, 8>(jobs, njobs, total, pool, grid_cap, st, dyn);
+    case 9: return launch_wave_J<S, 9>(jobs, njobs, total, pool, grid_cap, st, dyn);
+    case 10: return launch_wave_top<S, 10>(jobs, njobs, total, pool, grid_cap, st, dyn);
+    case 11: return launch_wave_top<S, 11>(jobs, njobs, total, pool, grid_cap, st, dyn);
     default: return hipErrorInvalidValue;
     }
 }
@@ -371,30 +391,33 @@ static hipError_t launch_wave_S(int J, const WaveJob *jobs, int njobs, long long
 }  // namespace tor
 
 hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
-                           int grid_cap, hipStream_t st) {
-    return is_dd ? tor::launch_wave_S<dd>(J, jobs, njobs, total, pool, grid_cap, st)
-                 : tor::launch_wave_S<double>(J, jobs, njobs, total, pool, grid_cap, st);
+                           int grid_cap, hipStream_t st, const LaunchDims *dyn) {
+    return is_dd ? tor::launch_wave_S<dd>(J, jobs, njobs, total, pool, grid_cap, st, dyn)
+                 : tor::launch_wave_S<double>(J, jobs, njobs, total, pool, grid_cap, st, dyn);
 }
 
 hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
-                             hipStream_t st) {
+                             hipStream_t st, const LaunchDims *dyn) {
     long long total = (long long)njobs << log2npar;
     long long blocks = (total + 3) / 4;
-    long long g = blocks < grid_cap ? blocks : grid_cap;
+    long long g = dyn ? grid_cap : (blocks < grid_cap ? blocks : grid_cap);
     if (g < 1) return hipSuccess;
+    (void)hipGetLastError();  // report only this launch's error
     if (is_dd)
         hipLaunchKernelGGL(tor::expand_kernel<dd>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
-                           (dd *)pool);
+                           (dd *)pool, dyn);
     else
         hipLaunchKernelGGL(tor::expand_kernel<double>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
-                           (double *)pool);
+                           (double *)pool, dyn);
     return hipGetLastError();
 }
 
-hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_blocks, hipStream_t st) {
+hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_blocks, hipStream_t st,
+                             const LaunchDims *dyn) {
     long long g = total_blocks < (1LL << 20) ? total_blocks : (1LL << 20);
     if (g < 1) return hipSuccess;
-    hipLaunchKernelGGL(tor::reduce_kernel, dim3((unsigned)g), dim3(256), 0, st, jobs, njobs, total_blocks);
+    (void)hipGetLastError();  // report only this launch's error
+    hipLaunchKernelGGL(tor::reduce_kernel, dim3((unsigned)g), dim3(256), 0, st, jobs, njobs, total_blocks, dyn);
     return hipGetLastError();
 }
 
@@ -402,12 +425,14 @@ hipError_t tor_launch_condition(const CondJob *jobs, int njobs, long long total_
     if (total_blocks < 1) return hipSuccess;
     if (rmax < 1 || rmax > TOR_COND_MAX_MODES || total_blocks > (1LL << 31) - 1) return hipErrorInvalidValue;
     const size_t lds = sizeof(dd) * 2 * (2 * (size_t)rmax - 2) + 16;
+    (void)hipGetLastError();  // report only this launch's error
     hipLaunchKernelGGL(tor::condition_kernel, dim3((unsigned)total_blocks), dim3(256), lds, st, jobs, njobs);
     return hipGetLastError();
 }
 
 hipError_t tor_launch_gather(const Partial *const *src, int n, Partial *dst, hipStream_t st) {
     if (n < 1) return hipSuccess;
+    (void)hipGetLastError();  // report only this launch's error
     hipLaunchKernelGGL(tor::gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, n, dst);
     return hipGetLastError();
 }
