@@ -88,13 +88,43 @@ def cpu_baseline(cov, pattern, n, seconds_target=15.0):
     t = time.perf_counter()
     oracle.formS_range(cov, pattern, 0, stride, count)
     dt = time.perf_counter() - t
+    # the same oracle on one thread, a sample sized for about 5 s (masks 1 + j * stride1)
+    count1 = max(1, int(count / dt / max(1, threads) * 5.0))
+    stride1 = max(1, (2 ** n) // count1) | 1
+    t = time.perf_counter()
+    oracle.formS_range(cov, pattern, 1, stride1, count1, threads=1)
+    dt1 = time.perf_counter() - t
     return {"value": count / dt, "unit": "subset-dets/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} of the 2^{n} subsets (masks 0, {stride}, 2*{stride}, ... mod 2^{n}) of the "
-                      f"same n={n} sum, binary128 Cholesky per subset, {dt:.1f} s"}
+                      f"same n={n} sum, binary128 Cholesky per subset, {dt:.1f} s",
+            "single_thread": {"value": count1 / dt1, "unit": "subset-dets/s", "cores": 1,
+                              "sample": f"{count1} subsets (masks 1 + j*{stride1}), {dt1:.1f} s"}}
 
 
 KERNEL_SOURCES = ["paper_1810_00900_amd/csrc/dd.hpp", "paper_1810_00900_amd/csrc/tor_tree.hpp",
                   "paper_1810_00900_amd/csrc/tor_kernels.hip", "paper_1810_00900_amd/csrc/tor_kernels.h"]
+
+
+def measured_fp64(kernel, kernel_ms):
+    """Executed FP64 rate of the wave-tier kernel from the committed rocprofv3
+    PMC pass (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 per launch, 64 lanes per
+    wave instruction, FMA = 2 flops) over this run's kernel time; None when
+    the kernel sources changed since."""
+    import hashlib
+    slug = kernel.replace("<", "_").replace(",", "").replace(">", "").replace("double", "f64")
+    path = os.path.join(ROOT, "profiles", f"pmc_fp64_{slug}_m800_n28.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    if d.get("sources_sha256") != h.hexdigest() or d.get("kernel") != kernel:
+        return None
+    flops = d["executed_fp64_flops_per_launch"]
+    tf = flops / (kernel_ms * 1e-3) / 1e12
+    return {"executed_flops_per_launch": flops, "achieved": tf, "frac": tf / FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "basis": "executed FP64 VALU instructions x 64 lanes (FMA = 2)"}
 
 
 def measured_traffic(kernel):
@@ -301,7 +331,8 @@ def main():
                      "traffic": (measured_traffic(kname) if n == 28 else None),
                      "kernel": kname,
                      "kernel_ms": wave_ms,
-                     "algorithmic_flops_per_launch": wave_flops},
+                     "algorithmic_flops_per_launch": wave_flops,
+                     "executed": (measured_fp64(kname, wave_ms) if n == 28 else None)},
         "phases_ms_per_step": {"expand": st["expand_ms"] / args.steps, "wave": st["wave_ms"] / args.steps,
                                "reduce": st["reduce_ms"] / args.steps},
         "result": {"p": r.p, "cancel_ratio": r.cancel_ratio, "rel_err_bound": r.rel_err_bound,
