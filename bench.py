@@ -185,6 +185,32 @@ def per_n_rates(ctx, cov, prec, ns=(20, 24, 28, 32), full=False):
     return out
 
 
+def paper_worst_case(ctx, sizes=((10, 200), (12, 288), (14, 392), (16, 512), (18, 648), (20, 800))):
+    """The paper's runtime study, worst case (Sec. III): one sample with fixed
+    outcomes, l = 2 m^2 modes, 8 dB squeezing on every mode, Haar
+    interferometer, all m clicks in the first m measured modes (modes are
+    measured from the last down).  Times the whole gbs_chain_fixed call."""
+    import numpy as np
+    import gbs_inputs as gi
+    r8 = 8.0 / (20.0 * np.log10(np.e))
+    out = {}
+    for m, l in sizes:
+        rng = np.random.default_rng([60, m])
+        cov = gi.gbs_covariance(gi.haar_unitary(l, rng), np.full(l, r8))
+        pat = np.zeros(l, np.int8)
+        pat[l - m:] = 1
+        ctx.reset_stats()
+        t = time.perf_counter()
+        tot, steps = ctx.chain_fixed(cov, pat, prec="dd")
+        dt = time.perf_counter() - t
+        st = ctx.stats()
+        out[f"{l},{m}"] = {"seconds": dt, "modes": l, "clicks": m, "p": tot.p, "log_p": tot.log_p,
+                           "steps": int(l), "condition_launches": st["condition_launches"],
+                           "subsets": st["subsets"], "max_rel_err_bound": tot.rel_err_bound,
+                           "max_cancel_ratio": tot.cancel_ratio}
+    return out
+
+
 def sampler_bench(ctx, n_samples=1000):
     """The postselected sampling workload: m = 100, Haar U, r = 0.6, 12 clicks."""
     import gbs_inputs as gi
@@ -343,6 +369,7 @@ def main():
         out["per_n_f64_terms"] = per_n_rates(ctx, cov, "f64")
         out["per_n_full_pattern"] = per_n_rates(ctx, cov, args.prec, ns=(20, 28), full=True)
         out["sampler"] = sampler_bench(ctx)
+        out["paper_worst_case"] = paper_worst_case(ctx)
         out["serving"] = serving_bench(ctx)
     ctx.close()
     if not args.no_cpu:

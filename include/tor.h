@@ -239,6 +239,25 @@ tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post,
                      int64_t chain_begin, int32_t nchains, double *p_click, double *uniform, uint8_t *outcome,
                      int8_t *status);
 
+/* The paper's benchmark mode (Sec. III, "Runtime"): one sample whose
+ * outcomes are fixed in advance, measured mode by mode from the last mode down
+ * (Sec. II).  outcomes[m] (host) holds 1 = click, 0 = no click, -1 = not
+ * measured (traced out).  step_p[j] (host, m doubles, may be NULL) receives
+ * P(outcome of mode j | outcomes of the modes measured before it), 1 for
+ * unmeasured modes; *total the probability of the whole pattern (the product
+ * of the steps), with rel_err_bound the largest bound of the step sums and
+ * cancel_ratio the largest cancellation ratio met.
+ * Each no-click step conditions the matrix of the remaining observed modes on
+ * the measured mode (one GPU step, Eq. MatrixUpdate); the step probabilities
+ * are ratios of the subset sums over the clicks so far before and after each
+ * step, all of them evaluated in one batched launch.  Clicks <= 32, observed
+ * modes <= 1024.  prec as for tor_probability (AUTO repeats in double-double
+ * the sums whose binary64 bound exceeds tol).
+ * Errors: TOR_EINVAL, TOR_ETOOBIG, TOR_ENOTPD, TOR_ENOMEM, TOR_EDEVICE;
+ * TOR_WARN_PRECISION when the bound exceeds tol. */
+tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int8_t *outcomes, tor_prec prec,
+                           double tol, double *step_p, tor_result *total);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of probability queries.
  *

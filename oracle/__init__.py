@@ -179,7 +179,7 @@ def num_threads() -> int:
 # The paper's sequential algorithm (Sec. II), fixed outcomes (Sec. III).
 # ---------------------------------------------------------------------------
 
-def prob_sequential(cov, pattern, dps: int | None = None):
+def prob_sequential(cov, pattern, dps: int | None = None, steps: bool = False):
     """Probability of a click pattern by the paper's mode-by-mode update rule.
 
     The state is the signed linear combination sum_k a_k rho_k(V_k) (hbar = 2,
@@ -192,7 +192,9 @@ def prob_sequential(cov, pattern, dps: int | None = None):
     (-a_k q_k / (1-p), V'_A).  An unobserved mode is traced out (V -> V_A).  The
     pattern probability is the product of the step probabilities.
 
-    With ``dps`` set, everything runs in mpmath at that many digits.
+    With ``dps`` set, everything runs in mpmath at that many digits.  With
+    ``steps`` the step probabilities are returned too: (total, {mode: P(outcome
+    of mode | outcomes of the modes measured before it)}) for observed modes.
     """
     pattern = np.asarray(pattern, dtype=np.int64)
     m = pattern.shape[0]
@@ -246,6 +248,11 @@ def prob_sequential(cov, pattern, dps: int | None = None):
 
     comps = [(one, V0)]
     total = one
+    step_p = {}
+
+    def done(value):
+        return (value, step_p) if steps else value
+
     for mode in range(m - 1, -1, -1):
         d = 2 * mode          # size of the remaining block A
         outcome = int(pattern[mode])
@@ -271,20 +278,22 @@ def prob_sequential(cov, pattern, dps: int | None = None):
             updated.append((a, VA, VAp))
         p = sum(a * q for (a, _, _), q in zip(updated, qs))
         if outcome == 0:
+            step_p[mode] = p
             if p == 0:
-                return 0.0 if dps is None else mp.mpf(0)
+                return done(0.0 if dps is None else mp.mpf(0))
             total = total * p
             comps = [(a * q / p, VAp) for (a, _, VAp), q in zip(updated, qs)]
         else:
             pc = one - p
+            step_p[mode] = pc
             if pc == 0:
-                return 0.0 if dps is None else mp.mpf(0)
+                return done(0.0 if dps is None else mp.mpf(0))
             total = total * pc
             comps = []
             for (a, VA, VAp), q in zip(updated, qs):
                 comps.append((a / pc, VA))
                 comps.append((-a * q / pc, VAp))
-    return total
+    return done(total)
 
 
 # ---------------------------------------------------------------------------

@@ -147,6 +147,8 @@ def lib():
         "tor_get_tuning": ([vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int32),
         "gbs_sample": ([vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                         ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(_CGbsStats)], ctypes.c_int32),
+        "gbs_chain_fixed": ([vp, dp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double, dp,
+                             ctypes.POINTER(_CResult)], ctypes.c_int32),
         "gbs_trace": ([vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
                        dp, dp, ctypes.POINTER(ctypes.c_uint8), i8p], ctypes.c_int32),
     }
@@ -266,6 +268,21 @@ class Context:
         v = ctypes.c_int32()
         _check(lib().tor_get_tuning(self._h, _PREC[prec], int(n), ctypes.byref(v)))
         return v.value
+
+    def chain_fixed(self, cov, outcomes, prec="dd", tol: float = 1e-10):
+        """The paper's fixed-outcome benchmark chain (gbs_chain_fixed): modes
+        measured from the last down; returns (Result for the whole pattern,
+        step probabilities per mode, 1 for unmeasured modes)."""
+        cov = _f64(cov)
+        outcomes = _i8(outcomes)
+        m = cov.shape[0] // 2
+        if outcomes.shape != (m,):
+            raise ValueError("outcomes must have m entries")
+        steps = np.empty(m, np.float64)
+        out = _CResult()
+        _check(lib().gbs_chain_fixed(self._h, _dptr(cov), m, _i8ptr(outcomes), _PREC[prec], float(tol),
+                                     _dptr(steps), ctypes.byref(out)))
+        return Result._from(out), steps
 
     def gbs_sample(self, cov, n_post: int, seed: int, n_samples: int):
         """Exact chain-rule threshold samples (gbs_sample); returns

@@ -632,6 +632,7 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
                 if (r->k <= t) continue;
                 jobs[ji].mat = dmat + off[i];
                 jobs[ji].acc = dacc + 3 * i;
+                jobs[ji].qout = nullptr;
                 ji++;
             }
         std::vector<unsigned char> &stage = ctx->host_stage;
@@ -1276,6 +1277,191 @@ tor_status gbs_sample(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post
         stats->subsets = subsets;
     }
     return TOR_OK;
+}
+
+tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int8_t *outcomes, tor_prec prec,
+                           double tol, double *step_p, tor_result *total) {
+    if (!ctx || !total) return fail(TOR_EINVAL, "NULL argument");
+    if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD)
+        return fail(TOR_EINVAL, "bad precision %d", (int)prec);
+    if (!(tol > 0.0)) tol = 1e-10;
+    tor_status s = validate_cov_block(cov, m, outcomes);
+    if (s) return s;
+    // measurement sequence: modes m-1 .. 0 with an outcome; order of the matrix:
+    // clicked modes in measurement order, then the no-click modes in reverse
+    // measurement order (each no-click step conditions on the last mode)
+    std::vector<int> seq, clicks, noclicks;
+    for (int j = m - 1; j >= 0; j--) {
+        if (outcomes[j] < 0) continue;
+        seq.push_back(j);
+        if (outcomes[j] == 1) clicks.push_back(j);
+        else noclicks.push_back(j);
+    }
+    const int nc = (int)clicks.size(), nn = (int)noclicks.size(), nobs = nc + nn;
+    if (nc > TOR_MAX_CLICKS) return fail(TOR_ETOOBIG, "%d clicks > %d", nc, TOR_MAX_CLICKS);
+    if (nobs > TOR_COND_MAX_MODES) return fail(TOR_ETOOBIG, "%d observed modes > %d", nobs, TOR_COND_MAX_MODES);
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (step_p)
+        for (int j = 0; j < m; j++) step_p[j] = 1.0;
+    std::memset(total, 0, sizeof *total);
+    if (nobs == 0) {
+        total->p = 1.0;
+        total->status = TOR_OK;
+        return TOR_OK;
+    }
+    std::vector<int> g;  // quadrature index per row of the ordered matrix
+    for (int c : clicks) {
+        g.push_back(2 * c);
+        g.push_back(2 * c + 1);
+    }
+    for (auto it = noclicks.rbegin(); it != noclicks.rend(); ++it) {
+        g.push_back(2 * *it);
+        g.push_back(2 * *it + 1);
+    }
+    const size_t EM = (size_t)E(nobs);
+    // device buffer: matrix | acc (3) | q per no-click step (2 each) | snapshots | jobs
+    const int nsteps = nobs;
+    std::vector<long long> snap_off(nsteps + 1), snap_n(nsteps + 1);
+    size_t snap_tot = 0;
+    {
+        int c = 0;
+        for (int k = 0; k < nsteps; k++) {
+            if (outcomes[seq[k]] == 1) c++;
+            snap_n[k] = c;
+            snap_off[k] = (long long)snap_tot;
+            snap_tot += (size_t)E(c);
+        }
+    }
+    const size_t o_acc = align_up(EM * sizeof(dd), 256);
+    const size_t o_q = align_up(o_acc + 3 * sizeof(double), 256);
+    const size_t o_snap = align_up(o_q + 2 * (size_t)std::max(nn, 1) * sizeof(double), 256);
+    const size_t o_jobs = align_up(o_snap + snap_tot * sizeof(dd), 256);
+    const size_t bytes = o_jobs + (size_t)std::max(nn, 1) * sizeof(CondJob);
+    if (bytes > ctx->mem_budget) return fail(TOR_ENOMEM, "chain needs %.2f GB", bytes / 1e9);
+    if (ctx->cond.ensure(bytes) != hipSuccess) return fail(TOR_ENOMEM, "device allocation failed");
+    unsigned char *db = (unsigned char *)ctx->cond.p;
+    dd *dmat = (dd *)db;
+    std::vector<unsigned char> &stage = ctx->host_stage;
+    if (stage.size() < bytes) stage.resize(bytes);
+    dd *hm = (dd *)stage.data();
+    for (int a = 0; a < 2 * nobs; a++)
+        for (int b = 0; b <= a; b++) hm[pidx(a, b)] = sigq(cov, m, g[a], g[b]);
+    const double a0[3] = {1.0, 0.0, 0.0};
+    std::memcpy(stage.data() + o_acc, a0, sizeof a0);
+    CondJob *hj = (CondJob *)(stage.data() + o_jobs);
+    {
+        int r = nobs, t = 0;
+        for (int k = 0; k < nsteps; k++) {
+            if (outcomes[seq[k]] == 1) continue;
+            CondJob j{};
+            j.mat = dmat;
+            j.acc = (double *)(db + o_acc);
+            j.qout = (double *)(db + o_q) + 2 * t;
+            j.begin = 0;
+            j.r = r;
+            hj[t++] = j;
+            r--;
+        }
+    }
+    hipStream_t st = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(db, stage.data(), o_acc + 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(db + o_jobs, stage.data() + o_jobs, (size_t)std::max(nn, 1) * sizeof(CondJob),
+                           hipMemcpyHostToDevice, st));
+    {
+        int t = 0;
+        for (int k = 0; k < nsteps; k++) {
+            if (outcomes[seq[k]] == 0) {
+                const CondJob &j = hj[t];
+                const long long blocks = std::max<long long>(1, (E(j.r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
+                HIP_TRY(tor_launch_condition((const CondJob *)(db + o_jobs) + t, 1, blocks, j.r, st));
+                t++;
+            }
+            if (snap_n[k] > 0)
+                HIP_TRY(hipMemcpyAsync(db + o_snap + snap_off[k] * sizeof(dd), dmat, sizeof(dd) * E(snap_n[k]),
+                                       hipMemcpyDeviceToDevice, st));
+        }
+        ctx->stats.condition_launches += t;
+    }
+    HIP_TRY(hipMemcpyAsync(stage.data() + o_q, db + o_q, o_jobs - o_q, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // the q of each no-click step, out of the staging buffer that the subset
+    // sums below reuse
+    const std::vector<double> qv((const double *)(stage.data() + o_q),
+                                 (const double *)(stage.data() + o_q) + 2 * (size_t)nn);
+    // one subset sum per step over the clicks so far, all in shared launches
+    std::vector<std::vector<dd>> roots(nsteps);
+    std::vector<SumIn> in(nsteps);
+    std::vector<int> which;
+    const dd *snaps = (const dd *)(stage.data() + o_snap);
+    for (int k = 0; k < nsteps; k++) {
+        in[k].n = (int)snap_n[k];
+        roots[k].assign(snaps + snap_off[k], snaps + snap_off[k] + E(snap_n[k]));
+        in[k].packed = &roots[k];
+        which.push_back(k);
+    }
+    std::vector<SumOut> res(nsteps);
+    std::vector<int> used(nsteps, prec == TOR_PREC_DD ? TOR_PREC_DD : TOR_PREC_F64);
+    s = gpu_sums(ctx, in, which, prec == TOR_PREC_DD, res);
+    if (s) return s;
+    if (prec == TOR_PREC_AUTO) {
+        std::vector<int> redo;
+        for (int k = 0; k < nsteps; k++)
+            if (in[k].n > 0 && !(bound_of(TOR_PREC_F64, in[k].n, res[k].T, res[k].A) <= tol)) redo.push_back(k);
+        if (!redo.empty()) {
+            s = gpu_sums(ctx, in, redo, true, res);
+            if (s) return s;
+            for (int k : redo) used[k] = TOR_PREC_DD;
+        }
+    }
+    // step probabilities: click T_k / T_{k-1}; no click q T_k / T_{k-1}
+    const double *hq = qv.data();
+    dd prev = dd_from(1.0), pvac = dd_from(1.0);
+    double worst_bound = 0.0, worst_R = 0.0, log_pvac = 0.0;
+    int worst_used = TOR_PREC_F64;
+    for (int k = 0, t = 0; k < nsteps; k++) {
+        const dd T = res[k].T;
+        if (!std::isfinite(T.hi) || !std::isfinite(res[k].A)) return fail(TOR_ENOTPD, "a Schur pivot was not positive");
+        dd num = T;
+        if (outcomes[seq[k]] == 0) {
+            const dd q = dd_make(hq[2 * t], hq[2 * t + 1]);
+            num = dd_mul(q, T);
+            pvac = dd_mul(pvac, q);
+            log_pvac += std::log(q.hi) + std::log1p(q.lo / q.hi);
+            t++;
+        }
+        if (step_p) step_p[seq[k]] = (num.hi + num.lo) / (prev.hi + prev.lo);
+        if (in[k].n > 0) {
+            worst_bound = std::max(worst_bound, bound_of(used[k], in[k].n, T, res[k].A));
+            worst_R = std::max(worst_R, res[k].A / std::fabs(T.hi));
+            if (used[k] == TOR_PREC_DD) worst_used = TOR_PREC_DD;
+        }
+        prev = T;
+    }
+    // the whole pattern telescopes to P_vac(N) * T(clicks | N), as tor_probability
+    const dd pr = dd_mul(pvac, prev);
+    total->p = pr.hi + pr.lo;
+    total->p_lo = pr.lo - (total->p - pr.hi);
+    total->log_p = total->p > 0 ? log_pvac + std::log(prev.hi) + std::log1p(prev.lo / prev.hi) : -INFINITY;
+    total->T = prev.hi;
+    total->T_lo = prev.lo;
+    total->abs_sum = res[nsteps - 1].A;
+    total->cancel_ratio = worst_R;
+    total->rel_err_bound = 2.0 * worst_bound;  // a step is a ratio of two sums
+    total->log_pvac_n = log_pvac;
+    if (nc > 0) {  // Tor of the final conditioned matrix (log det from its packed snapshot)
+        std::vector<dd> full((size_t)4 * nc * nc);
+        const std::vector<dd> &pk = roots[nsteps - 1];
+        for (int a = 0; a < 2 * nc; a++)
+            for (int b = 0; b <= a; b++) full[(size_t)a * 2 * nc + b] = full[(size_t)b * 2 * nc + a] = pk[pidx(a, b)];
+        double ld = 0.0;
+        if (f64_cholesky_logdet(full, 2 * nc, &ld)) total->tor = std::exp(0.5 * ld) * (prev.hi + prev.lo);
+    } else {
+        total->tor = 1.0;
+    }
+    total->n_clicks = nc;
+    total->prec_used = worst_used;
+    total->status = total->rel_err_bound <= tol ? TOR_OK : TOR_WARN_PRECISION;
+    return total->status;
 }
 
 tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,

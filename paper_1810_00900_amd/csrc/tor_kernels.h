@@ -69,6 +69,7 @@ struct LaunchDims {
 struct CondJob {
     dd *mat;
     double *acc;
+    double *qout;     // if not null: this step's pivot factor q (hi, lo)
     long long begin;  // first block of the launch that works on this job
     int r;
     int pad;

@@ -283,6 +283,10 @@ __global__ __launch_bounds__(256) void condition_kernel(const CondJob *__restric
         job.acc[0] = p.hi;
         job.acc[1] = p.lo;
         job.acc[2] += log(pv.q.hi) + log1p(pv.q.lo / pv.q.hi);
+        if (job.qout) {
+            job.qout[0] = pv.q.hi;
+            job.qout[1] = pv.q.lo;
+        }
     }
 }
 

@@ -1,0 +1,87 @@
+"""The paper's fixed-outcome benchmark chain (gbs_chain_fixed).
+
+* every step probability against the paper's own mode-by-mode rule (the
+  oracle's signed mixture of Gaussians, Sec. II, in 40-digit mpmath);
+* the product of the steps equals the whole-pattern probability of
+  tor_probability;
+* P(click) + P(no click) = 1 at a step with a shared history;
+* the worst case of the paper's runtime study (all clicks measured first,
+  8 dB squeezing, Haar interferometer) at l = 200 modes, 10 clicks.
+"""
+import numpy as np
+import pytest
+
+import gbs_inputs as gi
+import oracle
+import paper_1810_00900_amd as tg
+
+pytestmark = pytest.mark.gpu
+R8DB = 8.0 / (20.0 * np.log10(np.e))     # 8 dB of squeezing
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tg.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return abs(float(a) - float(b)) / abs(float(b))
+
+
+@pytest.mark.parametrize("pat", [
+    [1, 0, 1, 1, 0, -1, 1, 0],
+    [0, 0, 0, 1, 1, 1, 1, 0],
+    [1, 1, 1, 1, 0, 0, 0, 0],
+    [-1, 1, -1, 0, 1, -1, 0, 1],
+])
+def test_steps_match_paper_rule(ctx, pat):
+    cov = gi.state_config1()
+    pat = np.array(pat, np.int8)
+    tot, steps = ctx.chain_fixed(cov, pat, prec="dd")
+    want_tot, want = oracle.prob_sequential(cov, pat, dps=40, steps=True)
+    for j in range(8):
+        if pat[j] < 0:
+            assert steps[j] == 1.0
+            continue
+        assert _rel(steps[j], want[j]) <= 1e-12, (j, steps[j], float(want[j]))
+    assert _rel(tot.p + tot.p_lo, want_tot) <= 1e-12
+    assert tot.n_clicks == int((pat == 1).sum())
+
+
+def test_total_equals_probability_and_complementary_steps(ctx):
+    rng = np.random.default_rng(12)
+    m = 14
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), np.full(m, R8DB))
+    pat = rng.choice(np.array([0, 1], np.int8), m, p=[0.6, 0.4])
+    tot, steps = ctx.chain_fixed(cov, pat, prec="dd")
+    r = ctx.probability(cov, pat, prec="dd")
+    assert _rel(tot.p + tot.p_lo, r.p + r.p_lo) <= 1e-12
+    assert tot.log_pvac_n == pytest.approx(r.log_pvac_n, rel=1e-12)
+    assert np.prod(steps) == pytest.approx(tot.p, rel=1e-12)
+    # flip the outcome of the mode measured at step 5 (modes are measured from the last down)
+    j = m - 1 - 5
+    alt = pat.copy()
+    alt[j] = 1 - alt[j]
+    _, steps2 = ctx.chain_fixed(cov, alt, prec="dd")
+    assert steps[j] + steps2[j] == pytest.approx(1.0, abs=1e-13)
+    for k in range(j + 1, m):          # measured before j: same history, same steps
+        assert steps[k] == steps2[k]
+
+
+def test_worst_case_l200_m10(ctx):
+    """All 10 clicks in the first 10 measured modes, then 190 no-click steps
+    (the paper's worst case at l = 2 m^2)."""
+    rng = np.random.default_rng(200)
+    l, m = 200, 10
+    cov = gi.gbs_covariance(gi.haar_unitary(l, rng), np.full(l, R8DB))
+    pat = np.zeros(l, np.int8)
+    pat[l - m:] = 1
+    ctx.reset_stats()
+    tot, steps = ctx.chain_fixed(cov, pat, prec="dd")
+    assert ctx.stats()["condition_launches"] == l - m
+    assert np.all((steps > 0) & (steps <= 1))
+    r = ctx.probability(cov, pat, prec="dd")
+    assert _rel(tot.p + tot.p_lo, r.p + r.p_lo) <= max(1e-10, 4 * (tot.rel_err_bound + r.rel_err_bound))
+    assert np.prod(steps) == pytest.approx(tot.p, rel=1e-9)
