@@ -39,6 +39,11 @@ __all__ = [
     "config5_pattern",
     "config3_queries",
     "random_product_state",
+    "planted_clique_graph",
+    "takagi_real_symmetric",
+    "graph_covariance",
+    "calibrate_scale",
+    "subgraph_density",
 ]
 
 
@@ -196,3 +201,67 @@ def random_product_state(m: int, rng: np.random.Generator):
     blocks = [single_mode_covariance(rng.uniform(0.1, 1.0), rng.uniform(0, np.pi),
                                      rng.uniform(0.0, 0.5)) for _ in range(m)]
     return direct_sum(blocks), blocks
+
+
+# ---------------------------------------------------------------------------
+# Graph workloads (dense-subgraph search with GBS, Sec. IV): the graph is
+# encoded in the squeezing and interferometer of a pure Gaussian state whose
+# kernel is proportional to the adjacency matrix.  Only input construction
+# lives here; the mean click number used to pick the scale comes from the
+# caller (the library or the oracle).
+
+
+def planted_clique_graph(n: int = 200, p: float = 0.5, k: int = 20, seed: int = 40):
+    """Erdos-Renyi G(n, p) with a clique planted on k uniformly chosen
+    vertices.  Returns (adjacency as float64 0/1, sorted clique vertices)."""
+    rng = np.random.default_rng(seed)
+    up = np.triu(rng.random((n, n)) < p, 1)
+    A = (up | up.T).astype(np.float64)
+    clique = np.sort(rng.choice(n, k, replace=False))
+    A[np.ix_(clique, clique)] = 1.0
+    np.fill_diagonal(A, 0.0)
+    return A, clique
+
+
+def takagi_real_symmetric(A: np.ndarray):
+    """Takagi factorisation A = U diag(lam) U^T (lam >= 0, U unitary) of a real
+    symmetric matrix: from its eigendecomposition, with the columns of
+    negative eigenvalues multiplied by i."""
+    mu, V = np.linalg.eigh(np.asarray(A, dtype=np.float64))
+    U = V.astype(np.complex128) * np.where(mu < 0, 1j, 1.0)[None, :]
+    return U, np.abs(mu)
+
+
+def graph_covariance(A: np.ndarray, c: float, eta: float = 1.0) -> np.ndarray:
+    """Covariance (hbar = 1, interleaved) of the GBS encoding of the graph A at
+    scale c (0 < c max|eig A| < 1): squeezing r_i = artanh(c lam_i) into the
+    Takagi unitary of A, so that the state's kernel is c A up to a global
+    sign; then uniform loss with transmission eta."""
+    U, lam = takagi_real_symmetric(A)
+    if not (0.0 < c * lam.max() < 1.0):
+        raise ValueError("scale c must satisfy 0 < c * max|eig A| < 1")
+    cov = gbs_covariance(U, np.arctanh(c * lam))
+    return apply_loss(cov, eta) if eta != 1.0 else cov
+
+
+def calibrate_scale(A: np.ndarray, target: float, mean_clicks, eta: float = 1.0, iters: int = 60) -> float:
+    """Scale c at which mean_clicks(graph_covariance(A, c, eta)) equals target,
+    by bisection on (0, 1 / max|eig A|) (the mean click number grows with c)."""
+    lam_max = np.abs(np.linalg.eigvalsh(np.asarray(A, dtype=np.float64))).max()
+    lo, hi = 0.0, (1.0 - 1e-9) / lam_max
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        if mean_clicks(graph_covariance(A, mid, eta)) < target:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def subgraph_density(A: np.ndarray, vertices) -> float:
+    """Edge density of the subgraph of A induced by `vertices`."""
+    v = np.asarray(vertices)
+    k = len(v)
+    if k < 2:
+        return 0.0
+    return float(A[np.ix_(v, v)].sum() / (k * (k - 1)))
