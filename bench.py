@@ -212,7 +212,7 @@ def paper_worst_case(ctx, sizes=((10, 200), (12, 288), (14, 392), (16, 512), (18
 
 
 def dense_subgraph(ctx, n=200, p=0.5, clique=20, k=12, target_clicks=16.0, etas=(1.0, 0.5, 0.25),
-                   n_samples=500, seed=40):
+                   n_samples=500, seed=40, k20_samples=100):
     """Dense-subgraph search with GBS (Sec. IV), synthetic graph: G(n, p) with
     a planted clique, encoded at the scale giving target_clicks mean clicks
     without loss, then uniform loss eta.  Samples postselected on k clicks are
@@ -247,8 +247,11 @@ def dense_subgraph(ctx, n=200, p=0.5, clique=20, k=12, target_clicks=16.0, etas=
         samples, st = ctx.gbs_sample(cov, k, seed + int(100 * eta), n_samples)
         dens = np.array([gi.subgraph_density(A, np.nonzero(sm)[0]) for sm in samples])
         inside = float(np.mean([set(np.nonzero(sm)[0].tolist()) <= clset for sm in samples]))
-        raw, st2 = ctx.gbs_sample(cov, -1, seed + 7, 2000)
-        hist = np.bincount(raw.sum(axis=1), minlength=k + 8).tolist()
+        import paper_1810_00900_amd as tg
+        with tg.Context(0) as c20:               # unpostselected, chains of up to 20 clicks
+            c20.set_option(tg.OPT_CHAIN_CLICKS, 20)
+            raw, st2 = c20.gbs_sample(cov, -1, seed + 7, 2000)
+        hist = np.bincount(raw.sum(axis=1), minlength=21).tolist()
         out[f"eta={eta}"] = {"mean_clicks": mc, "samples": n_samples, "seconds": st["seconds"],
                              "samples_per_s": n_samples / st["seconds"],
                              "acceptance": st["chains_accepted"] / st["chains_started"],
@@ -258,6 +261,19 @@ def dense_subgraph(ctx, n=200, p=0.5, clique=20, k=12, target_clicks=16.0, etas=
                              "click_histogram_unpostselected": hist,
                              "unpostselected_chains_capped": st2["chains_capped"],
                              "unpostselected_chains": st2["chains_started"]}
+    # the densest-20 search as specified (20-click samples), lossless only: with
+    # loss, 20 clicks become too rare to sample in bench time
+    if k20_samples:
+        cov = gi.graph_covariance(A, c, 1.0)
+        samples, st = ctx.gbs_sample(cov, clique, seed + 20, k20_samples)
+        dens = np.array([gi.subgraph_density(A, np.nonzero(sm)[0]) for sm in samples])
+        uni20 = np.array([gi.subgraph_density(A, rng.choice(n, clique, replace=False))
+                          for _ in range(k20_samples)])
+        out["k=20,eta=1.0"] = {"samples": k20_samples, "seconds": st["seconds"],
+                               "samples_per_s": k20_samples / st["seconds"],
+                               "acceptance": st["chains_accepted"] / st["chains_started"],
+                               "mean_density": float(dens.mean()), "best": float(dens.max()),
+                               "uniform_mean_density": float(uni20.mean()), "uniform_best": float(uni20.max())}
     return out
 
 

@@ -110,7 +110,10 @@ typedef enum {
                              (default 10 for dd terms, 11 for binary64 terms) */
     TOR_OPT_WAVE_GRID = 2,  /* cap on wave-tier workgroups per launch (default 65536) */
     TOR_OPT_MEM_BUDGET = 3, /* device bytes the context may hold (default 64 GiB) */
-    TOR_OPT_ASYNC_POOL = 4  /* tree pool bytes of tor_batch_async (default 4 GiB) */
+    TOR_OPT_ASYNC_POOL = 4, /* tree pool bytes of tor_batch_async (default 4 GiB) */
+    TOR_OPT_CHAIN_CLICKS = 5 /* most clicks a chain without postselection may carry,
+                              1..TOR_CHAIN_CLICKS (default 15; above 15 the sampler
+                              kernel uses more LDS per chain) */
 } tor_option;
 
 /* Create a context on HIP device `device` (its own stream, default priority).
@@ -205,12 +208,12 @@ typedef struct {
     int64_t chains_started;   /* chains consumed to produce the samples (deterministic) */
     int64_t chains_accepted;  /* = samples produced */
     int64_t chains_evaluated; /* chains the GPU ran (whole launches) */
-    int64_t chains_capped;    /* chains stopped because the clicks exceeded TOR_CHAIN_CLICKS */
+    int64_t chains_capped;    /* chains stopped because the clicks exceeded the cap (TOR_OPT_CHAIN_CLICKS) */
     double seconds;           /* wall time of the call */
     double subsets;           /* subset terms evaluated over the consumed chains */
 } gbs_stats;
 
-#define TOR_CHAIN_CLICKS 15   /* largest click count a chain may carry */
+#define TOR_CHAIN_CLICKS 20   /* largest click count a chain may carry */
 
 /* Draw n_samples threshold-detector samples of the zero-mean Gaussian state
  * `cov` (m modes, conventions above).  Modes are measured in ascending order;
@@ -218,8 +221,11 @@ typedef struct {
  * counter (c, j), so the output depends only on (cov, n_post, seed).  With
  * n_post >= 0 only chains with exactly n_post clicks are accepted (exact
  * rejection with early stopping: the accepted samples follow the
- * distribution conditioned on n_post clicks); with n_post < 0 every chain is
- * accepted.  Samples are the first accepted chains in chain order.
+ * distribution conditioned on n_post clicks); with n_post < 0 every chain
+ * with at most TOR_OPT_CHAIN_CLICKS clicks is accepted and longer chains are
+ * dropped (counted in chains_capped: the samples then follow the distribution
+ * conditioned on at most that many clicks).  Samples are the first accepted
+ * chains in chain order.
  * samples: host, n_samples x m bytes (0/1).  stats may be NULL.
  * Per-mode probabilities use binary64 matrices (K_j = sigma_Q[0..j]^-1 formed
  * in double-double and rounded once) and double-double sums.

@@ -31,7 +31,7 @@ PREC_AUTO, PREC_F64, PREC_DD = 0, 1, 2
 _PREC = {"auto": PREC_AUTO, "f64": PREC_F64, "dd": PREC_DD,
          PREC_AUTO: PREC_AUTO, PREC_F64: PREC_F64, PREC_DD: PREC_DD}
 
-OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET, OPT_ASYNC_POOL = 0, 1, 2, 3, 4
+OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET, OPT_ASYNC_POOL, OPT_CHAIN_CLICKS = 0, 1, 2, 3, 4, 5
 
 _STATUS_NAMES = {0: "TOR_OK", 1: "TOR_WARN_PRECISION", -1: "TOR_EINVAL", -2: "TOR_ENOTPD",
                  -3: "TOR_ETOOBIG", -4: "TOR_ENOMEM", -5: "TOR_EDEVICE", -6: "TOR_EAGAIN"}

@@ -136,12 +136,14 @@ template <class S> struct ChainLds {
     static constexpr size_t wave_bytes = sizeof(WaveSmem<S, 9>);
 };
 
-template <class S>
+// KMAX: largest step tree (clicks so far + 1) the kernel's LDS holds; two
+// instances, so that chains with few clicks keep the smaller footprint.
+template <class S, int KMAX>
 __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
     __shared__ __align__(16) unsigned char raw[ChainLds<S>::wave_bytes];
-    __shared__ S gbuf[3][E(TOR_CHAIN_MAX)];
-    __shared__ S vt[4 * TOR_CHAIN_MAX];
-    __shared__ int Cl[TOR_CHAIN_MAX + 1];
+    __shared__ S gbuf[3][E(KMAX)];
+    __shared__ S vt[4 * KMAX];
+    __shared__ int Cl[KMAX + 1];
     const int lane = threadIdx.x;
     // ab[] then mat[] sit at the same offsets in WaveSmem<S, J> for every J
     S *wmat = reinterpret_cast<WaveSmem<S, 9> *>(raw)->mat;
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
                 st = 0;
                 break;
             }
-            if (nc + 1 > TOR_CHAIN_MAX) {
+            if (nc + 1 > KMAX || nc > P.cap) {
                 st = 2;
                 break;
             }
@@ -255,6 +257,9 @@ hipError_t tor_launch_chains(const ChainParams &P, int grid_cap, hipStream_t st)
     int g = P.nchains < grid_cap ? P.nchains : grid_cap;
     if (g < 1) return hipSuccess;
     (void)hipGetLastError();  // report only this launch's error
-    hipLaunchKernelGGL(tor::chain_kernel<double>, dim3((unsigned)g), dim3(64), 0, st, P);
+    if (P.cap + 1 <= TOR_CHAIN_MAX)
+        hipLaunchKernelGGL((tor::chain_kernel<double, TOR_CHAIN_MAX>), dim3((unsigned)g), dim3(64), 0, st, P);
+    else
+        hipLaunchKernelGGL((tor::chain_kernel<double, TOR_CHAIN_MAX_BIG>), dim3((unsigned)g), dim3(64), 0, st, P);
     return hipGetLastError();
 }

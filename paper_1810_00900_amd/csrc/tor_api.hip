@@ -93,6 +93,7 @@ struct tor_ctx {
     DevBuf pool, descA, descB, partA, partB, jobs, cond;
     DevBuf apool, abuf;  // tor_batch_async: tree pool, plan and job tables
     size_t async_pool = (size_t)4 << 30;
+    int chain_clicks = 15;  // click cap of chains without postselection
     DevBuf kbuf, koff, c_out, c_status, c_tp, c_tu, c_sub;
     Partial *host_res = nullptr;
     size_t host_res_cap = 0;
@@ -897,6 +898,10 @@ tor_status tor_ctx_set_option(tor_ctx *c, tor_option opt, int64_t v) {
         if (v < (1 << 20)) return fail(TOR_EINVAL, "async pool too small");
         c->async_pool = (size_t)v;
         return TOR_OK;
+    case TOR_OPT_CHAIN_CLICKS:
+        if (v < 1 || v > TOR_CHAIN_CLICKS) return fail(TOR_EINVAL, "chain click cap must be in 1..%d", TOR_CHAIN_CLICKS);
+        c->chain_clicks = (int)v;
+        return TOR_OK;
     }
     return fail(TOR_EINVAL, "unknown option %d", (int)opt);
 }
@@ -1214,6 +1219,7 @@ tor_status run_chains(tor_ctx *ctx, int m, int n_post, uint64_t seed, long long 
     P.koff = (const unsigned long long *)ctx->koff.p;
     P.m = m;
     P.n_post = n_post;
+    P.cap = n_post >= 0 ? n_post : ctx->chain_clicks;
     P.seed = seed;
     P.chain_begin = begin;
     P.nchains = nchains;

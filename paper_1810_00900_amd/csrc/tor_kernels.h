@@ -133,13 +133,15 @@ hipError_t tor_launch_gather(const Partial *const *src, int n, Partial *dst, hip
 hipError_t tor_launch_condition(const CondJob *jobs, int njobs, long long total_blocks, int rmax, hipStream_t st);
 
 // ---- chain-rule sampler
-#define TOR_CHAIN_MAX 16  // largest tree per step (clicks so far + 1)
+#define TOR_CHAIN_MAX 16      // step-tree cap of the compact sampler kernel (clicks so far + 1)
+#define TOR_CHAIN_MAX_BIG 21  // step-tree cap of the large sampler kernel (up to 20 clicks)
 
 struct ChainParams {
     const double *K;                 // K_j, full row-major (2j+2)^2, concatenated
     const unsigned long long *koff;  // offset of K_j in K
     int m;
     int n_post;                      // < 0: no postselection
+    int cap;                         // most clicks a chain may carry (<= TOR_CHAIN_MAX_BIG - 1)
     unsigned long long seed;
     long long chain_begin;
     int nchains;

@@ -185,8 +185,49 @@ def test_resume_from_chain_index(ctx):
 def test_sampler_errors(ctx):
     cov = _small_state(6, 6)
     with pytest.raises(tg.TorError):
-        ctx.gbs_sample(cov, 16, 1, 10)
+        ctx.gbs_sample(cov, 21, 1, 10)
+    with pytest.raises(tg.TorError):
+        ctx.set_option(tg.OPT_CHAIN_CLICKS, 21)
     bad = cov.copy()
     bad[0, 1] += 1.0
     with pytest.raises(tg.TorError):
         ctx.gbs_sample(bad, 2, 1, 10)
+
+
+def test_many_clicks_product_state(ctx):
+    """Chains carrying up to 20 clicks (the large sampler kernel): on a
+    product of squeezed modes the click probability of mode j is
+    1 - 1/cosh(r_j) whatever the history, at any click count; the replayed
+    probabilities must match it within the binary64-term bound."""
+    rng = np.random.default_rng(31)
+    m = 30
+    rs = rng.uniform(1.4, 1.8, m)
+    cov = gi.direct_sum([gi.single_mode_covariance(r, rng.uniform(0, np.pi)) for r in rs])
+    pc, un, oc, st = ctx.gbs_trace(cov, 18, 4, 0, 16)
+    want = 1.0 - 1.0 / np.cosh(rs)
+    deep = 0
+    for c in range(16):
+        for j in np.nonzero(~np.isnan(pc[c]))[0]:
+            n = int(oc[c, :j].sum())
+            deep = max(deep, n)
+            R = np.prod([(1 + 1 / np.cosh(rs[i])) / (1 - 1 / np.cosh(rs[i])) for i in np.nonzero(oc[c, :j])[0]])
+            tol = 16 * (n + 1) * U53 * R * 4 + 1e-14
+            assert abs(pc[c, j] - want[j]) <= tol * want[j], (c, j, n, pc[c, j], want[j])
+    assert deep >= 16
+    samples, s2 = ctx.gbs_sample(cov, 18, 4, 20)
+    assert (samples.sum(axis=1) == 18).all()
+
+
+def test_chain_click_cap_option(ctx):
+    rng = np.random.default_rng(32)
+    m = 24
+    rs = rng.uniform(1.2, 1.6, m)
+    cov = gi.direct_sum([gi.single_mode_covariance(r) for r in rs])
+    with tg.Context(0) as c:
+        _, s15 = c.gbs_sample(cov, -1, 9, 200)
+        c.set_option(tg.OPT_CHAIN_CLICKS, 20)
+        smp, s20 = c.gbs_sample(cov, -1, 9, 200)
+    # the expected click count is sum(1 - 1/cosh r) ~ 15: the 15-click cap drops
+    # many chains, the 20-click cap fewer
+    assert s20["chains_capped"] < s15["chains_capped"]
+    assert smp.sum(axis=1).max() <= 20
