@@ -96,13 +96,13 @@ __device__ __forceinline__ S wave_schur_last(const S *in, int r, S *out, S *vt, 
         vt[c] = mul_s(m0, pv.s1);
         vt[RC + c] = mul_s(sub_mul(in[pidx(R - 1, c)], pv.l, m0), pv.s2);
     }
-    __syncthreads();
+    wave_sync();
     for (int e = lane; e < EC; e += 64) {
         int a, b;
         unpack(e, a, b);
         out[e] = sub_dot2(in[e], vt[a], vt[b], vt[RC + a], vt[RC + b]);
     }
-    __syncthreads();
+    wave_sync();
     return pv.q;
 }
 
@@ -120,14 +120,14 @@ template <class S, int J> struct ChainStep {
                 for (int e = 0; e < E(J); ++e) M[e] = sm.mat[e];
                 leaf_split<S, J>(M, X0, X1s);
             }
-            __syncthreads();
+            wave_sync();
         } else {
             dd T;
             double A;
             wave_tree<S, J>(sm, dd_from(1.0), 1.0, lane, T, A);
             X0 = (lane & 1) ? dd_from(0.0) : T;
             X1s = (lane & 1) ? T : dd_from(0.0);
-            __syncthreads();
+            wave_sync();
         }
     }
 };
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
                 const int mb = (b >> 1) < nc ? Cl[b >> 1] : j;
                 G[e] = (S)from_pair<S>(Kj[(2 * ma + (a & 1)) * D + 2 * mb + (b & 1)], 0.0);
             }
-            __syncthreads();
+            wave_sync();
             dd X0 = dd_from(0.0), X1s = dd_from(0.0);
             if (k <= 9) {
                 switch (k) {
@@ -208,13 +208,13 @@ __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
                         }
                     }
                     for (int e = lane; e < E(9); e += 64) sm.mat[e] = cur[e];
-                    __syncthreads();
+                    wave_sync();
                     dd T;
                     double A;
                     wave_tree<S, 9>(sm, c, a, lane, T, A);
                     if (p & 1) X1s = dd_add(X1s, T);
                     else X0 = dd_add(X0, T);
-                    __syncthreads();
+                    wave_sync();
                 }
             }
             double dummy0 = 0.0, dummy1 = 0.0;
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
                 if (P.trace_u) P.trace_u[o] = uni;
                 if (click) Cl[nc] = j;
             }
-            __syncthreads();
+            wave_sync();
             if (click) nc++;
         }
         if (st == 1 && P.n_post >= 0 && nc != P.n_post) st = 0;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
             P.status[ci] = st;
             if (P.subsets) P.subsets[ci] = nsub;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, J
             p.pad = 0.0;
             jobs[j].out[lt] = p;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -125,15 +125,15 @@ template <class S>
 __device__ __forceinline__ void top10(TopSmem<S> &sm, dd c, double a, int lane, dd &T, double &A) {
     S *v = sm.vtop[0];
     const Pivot<S> pv = top_columns<S, 10>(sm.w.mat, v, lane);
-    __syncthreads();
+    wave_sync();
     dd t;
     double x;
     wave_tree<S, 9>(sm.w, c, a, lane, t, x);
     T = dd_add(T, t);
     A += x;
-    __syncthreads();
+    wave_sync();
     top_update<S, 10>(sm.w.mat, sm.w.mat, v, lane);
-    __syncthreads();
+    wave_sync();
     wave_tree<S, 9>(sm.w, dd_neg(coef_mul(c, pv.q)), a * hi_of(pv.q), lane, t, x);
     T = dd_add(T, t);
     A += x;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9
         NodeDesc d = jobs[j].tasks[lt];
         const S *root = pool + d.off;
         for (int e = lane; e < E(J); e += 64) sm.w.mat[e] = root[e];
-        __syncthreads();
+        wave_sync();
         const dd c0 = dd_make(d.coef_hi, d.coef_lo);
         dd T = dd_from(0.0);
         double A = 0.0;
@@ -167,11 +167,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9
         } else {
             S *v = sm.vtop[1];
             const Pivot<S> pv = top_columns<S, 11>(sm.w.mat, v, lane);
-            __syncthreads();
+            wave_sync();
             top10(sm, c0, d.acoef, lane, T, A);
-            __syncthreads();
+            wave_sync();
             top_update<S, 11>(root, sm.w.mat, v, lane);
-            __syncthreads();
+            wave_sync();
             top10(sm, dd_neg(coef_mul(c0, pv.q)), d.acoef * hi_of(pv.q), lane, T, A);
         }
         wave_reduce(T, A);
@@ -183,20 +183,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9
             p.pad = 0.0;
             jobs[j].out[lt] = p;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
 // ---------------------------------------------------------------- HBM tier
 
-// Wave-scope ordering of LDS accesses: writes by some lanes become visible to
-// later reads by other lanes of the same wave (LDS operations of one wave
-// execute in order; this keeps the compiler from reordering them).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // One wave per parent node (four per 256-thread workgroup): the include child
 // (rank-2 Schur update of the last mode) goes to the pool, the exclude child

@@ -30,6 +30,18 @@ __device__ __forceinline__ void unpack(int e, int &a, int &b) {
     b = e - r * (r + 1) / 2;
 }
 
+// Ordering of LDS accesses among the lanes of a one-wave workgroup (every
+// kernel that runs the subset tree launches 64 threads).  LDS operations of a
+// wave execute in issue order, so a wavefront-scope fence, which only keeps
+// the compiler from moving LDS accesses across it, orders a lane's writes
+// before other lanes' later reads; unlike a workgroup barrier it does not
+// wait for outstanding stores or global loads.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <class S> __device__ __forceinline__ S szero();
 template <> __device__ __forceinline__ double szero<double>() { return 0.0; }
 template <> __device__ __forceinline__ dd szero<dd>() { return dd_make(0.0, 0.0); }
@@ -174,7 +186,7 @@ template <class S, int J, int K> struct WaveLevel {
                 acoef[NK + lane] = acoef[lane] * hi_of(pv.q);
                 loc[NK + lane] = C::soff(K) + lane * EC;
             }
-            __syncthreads();
+            wave_sync();
             // phase 1: the two scaled pivot columns of every node
             for (int it = lane; it < NK * RC; it += 64) {
                 int i = it / RC, c = it - i * RC;
@@ -184,7 +196,7 @@ template <class S, int J, int K> struct WaveLevel {
                 vbuf[i * 2 * RC + c] = mul_s(m0, pv.s1);
                 vbuf[i * 2 * RC + RC + c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
             }
-            __syncthreads();
+            wave_sync();
             // phase 2: rank-2 updates into the include children's slots.  Each
             // lane's entries are taken in chunks: all loads of a chunk first,
             // then the independent updates (computed unconditionally so that
@@ -224,7 +236,7 @@ template <class S, int J, int K> struct WaveLevel {
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
             WaveLevel<S, J, K + 1>::run(ab, mat, vbuf, piv, loc, coef, acoef, lane);
         }
     }
@@ -262,7 +274,7 @@ __device__ __forceinline__ void wave_tree_init(unsigned short *ab, int lane) {
         unpack(e, a, b);
         ab[e] = (unsigned short)(a | (b << 8));
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // Subset tree of the J-mode node stored in sm.mat[0 .. E(J)) with path
@@ -281,7 +293,7 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J> &sm, dd c, double a, in
         sm.coef[0] = c;
         sm.acoef[0] = a;
     }
-    __syncthreads();
+    wave_sync();
     WaveLevel<S, J, 0>::run(sm.ab, sm.mat, sm.vbuf, sm.piv, sm.loc, sm.coef, sm.acoef, lane);
     T = dd_from(0.0);
     A = 0.0;
