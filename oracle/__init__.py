@@ -73,6 +73,8 @@ def _lib(path: str | None = None):
             f.argtypes = [dp, ctypes.c_int, i8p, ctypes.c_uint64, ctypes.c_uint64,
                           ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_Result)]
             f.restype = ctypes.c_int
+        lib.oracle_formP_mean.argtypes = [dp, dp, ctypes.c_int, i8p, ctypes.c_int, ctypes.POINTER(_Result)]
+        lib.oracle_formP_mean.restype = ctypes.c_int
         lib.oracle_conditioned.argtypes = [dp, ctypes.c_int, i8p, dp, dp, dp]
         lib.oracle_conditioned.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -134,6 +136,24 @@ def formP(cov, pattern, threads: int = 0, lib_path=None) -> OracleResult:
     return _call("oracle_formP", cov, pattern, threads, lib_path=lib_path)
 
 
+def formP_mean(cov, mean, pattern, threads: int = 0, lib_path=None) -> OracleResult:
+    """Definition route for a displaced state (mean: 2m, hbar = 1, interleaved):
+    each vacuum probability gains exp(-mu^T sigma_Q^-1 mu / 2) (binary128)."""
+    cov, pattern, m = _prep(cov, pattern)
+    mean = np.ascontiguousarray(mean, dtype=np.float64)
+    if mean.shape != (2 * m,):
+        raise ValueError("mean must have 2m entries")
+    lib = _lib(lib_path)
+    res = _Result()
+    rc = lib.oracle_formP_mean(cov.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               mean.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), m,
+                               pattern.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), int(threads),
+                               ctypes.byref(res))
+    if rc != 0:
+        raise OracleError(rc)
+    return OracleResult(res.p_hi, res.p_lo, res.t_hi, res.t_lo, res.abs_sum, res.pvac_n, res.n_terms)
+
+
 def formS(cov, pattern, threads: int = 0, lib_path=None) -> OracleResult:
     """Conditioned route: Schur complement on the no-click modes once, then one
     Cholesky of Sigma_C[Y] per subset (binary128)."""
@@ -179,7 +199,7 @@ def num_threads() -> int:
 # The paper's sequential algorithm (Sec. II), fixed outcomes (Sec. III).
 # ---------------------------------------------------------------------------
 
-def prob_sequential(cov, pattern, dps: int | None = None, steps: bool = False):
+def prob_sequential(cov, pattern, dps: int | None = None, steps: bool = False, mean=None):
     """Probability of a click pattern by the paper's mode-by-mode update rule.
 
     The state is the signed linear combination sum_k a_k rho_k(V_k) (hbar = 2,
@@ -192,6 +212,11 @@ def prob_sequential(cov, pattern, dps: int | None = None, steps: bool = False):
     (-a_k q_k / (1-p), V'_A).  An unobserved mode is traced out (V -> V_A).  The
     pattern probability is the product of the step probabilities.
 
+    With ``mean`` (hbar = 1, interleaved, 2m entries) the state is displaced:
+    r = sqrt(2) mean in the paper's units, the no-click update also moves the
+    mean, r'_A = r_A - V_AB (V_B + 1)^-1 r_B (Sec. II), and q_k gains the
+    factor exp(-r_B^T (V_B + 1)^-1 r_B / 2) (the overlap with the vacuum; the
+    exponent is printed without the 1/2).
     With ``dps`` set, everything runs in mpmath at that many digits.  With
     ``steps`` the step probabilities are returned too: (total, {mode: P(outcome
     of mode | outcomes of the modes measured before it)}) for observed modes.
@@ -246,7 +271,32 @@ def prob_sequential(cov, pattern, dps: int | None = None, steps: bool = False):
     def transpose(M):
         return M.T
 
-    comps = [(one, V0)]
+    if mean is None:
+        r0 = None
+    elif dps is None:
+        r0 = np.sqrt(2.0) * np.asarray(mean, dtype=np.float64)
+    else:
+        r0 = mp.matrix([mp.sqrt(2) * mp.mpf(float(x)) for x in mean])
+
+    def vblock(r, i0, i1):
+        if r is None:
+            return None
+        if dps is None:
+            return r[i0:i1]
+        out = mp.matrix(i1 - i0, 1)
+        for i in range(i0, i1):
+            out[i - i0] = r[i]
+        return out
+
+    def quad(rB, M):          # rB^T M rB
+        if dps is None:
+            return float(rB @ M @ rB)
+        return (rB.T * M * rB)[0, 0]
+
+    def exp_(x):
+        return np.exp(x) if dps is None else mp.exp(x)
+
+    comps = [(one, V0, r0)]
     total = one
     step_p = {}
 
@@ -258,31 +308,38 @@ def prob_sequential(cov, pattern, dps: int | None = None, steps: bool = False):
         outcome = int(pattern[mode])
         new = []
         if outcome == -1:
-            for a, V in comps:
-                new.append((a, block(V, 0, d, 0, d)))
+            for a, V, r in comps:
+                new.append((a, block(V, 0, d, 0, d), vblock(r, 0, d)))
             comps = new
             continue
         qs, updated = [], []
-        for a, V in comps:
+        for a, V, r in comps:
             VA = block(V, 0, d, 0, d)
             VAB = block(V, 0, d, d, d + 2)
             VB = block(V, d, d + 2, d, d + 2)
             VB1 = VB + eye2()
             q = 2 / sqrt(det2(VB1))
+            rA, rAp = vblock(r, 0, d), None
+            if r is not None:
+                rB = vblock(r, d, d + 2)
+                W = inv2(VB1)
+                q = q * exp_(-quad(rB, W) / 2)
+                if d > 0:
+                    rAp = rA - (VAB * W * rB if dps is not None else VAB @ W @ rB)
             if d > 0:
                 VAp = VA - VAB * inv2(VB1) * transpose(VAB) if dps is not None else \
                     VA - VAB @ inv2(VB1) @ VAB.T
             else:
                 VAp = VA
             qs.append(q)
-            updated.append((a, VA, VAp))
-        p = sum(a * q for (a, _, _), q in zip(updated, qs))
+            updated.append((a, VA, VAp, rA, rAp))
+        p = sum(a * q for (a, _, _, _, _), q in zip(updated, qs))
         if outcome == 0:
             step_p[mode] = p
             if p == 0:
                 return done(0.0 if dps is None else mp.mpf(0))
             total = total * p
-            comps = [(a * q / p, VAp) for (a, _, VAp), q in zip(updated, qs)]
+            comps = [(a * q / p, VAp, rAp) for (a, _, VAp, _, rAp), q in zip(updated, qs)]
         else:
             pc = one - p
             step_p[mode] = pc
@@ -290,9 +347,9 @@ def prob_sequential(cov, pattern, dps: int | None = None, steps: bool = False):
                 return done(0.0 if dps is None else mp.mpf(0))
             total = total * pc
             comps = []
-            for (a, VA, VAp), q in zip(updated, qs):
-                comps.append((a / pc, VA))
-                comps.append((-a * q / pc, VAp))
+            for (a, VA, VAp, rA, rAp), q in zip(updated, qs):
+                comps.append((a / pc, VA, rA))
+                comps.append((-a * q / pc, VAp, rAp))
     return done(total)
 
 

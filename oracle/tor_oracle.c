@@ -111,8 +111,25 @@ static int validate(const double *cov, int m, const int8_t *pattern) {
 
 /* ---------------- form P ---------------- */
 
-static int term_formP(const double *cov, int m, const int *cidx, int n,
-                      const int *nidx, int nn, uint64_t mask, qf *work, int *modes,
+/* Displaced states (mean mu, hbar = 1, interleaved): the vacuum probability
+ * of a mode set A becomes det(sigma_Q[A])^-1/2 exp(-mu_A^T sigma_Q[A]^-1 mu_A / 2),
+ * the overlap of a Gaussian state with the vacuum (a coherent state |alpha>
+ * gives exp(-|alpha|^2)).  Sec. II prints the exponent of q_k without the
+ * factor 1/2 (hbar = 2 there); this follows the overlap formula.  With
+ * sigma_Q[A] = L L^T the quadratic form is |L^-1 mu_A|^2. */
+static qf mean_factor(const qf *L, int d, const qf *mu, qf *z) {
+    qf s = 0;
+    for (int i = 0; i < d; i++) {
+        qf v = mu[i];
+        for (int t = 0; t < i; t++) v -= L[i * d + t] * z[t];
+        z[i] = v / L[i * d + i];
+        s += z[i] * z[i];
+    }
+    return expq(-s / 2);
+}
+
+static int term_formP(const double *cov, const double *mean, int m, const int *cidx, int n,
+                      const int *nidx, int nn, uint64_t mask, qf *work, qf *vec, int *modes,
                       qf *term) {
     int k = 0;
     /* Y u N in ascending mode order (the determinant does not depend on the
@@ -140,7 +157,12 @@ static int term_formP(const double *cov, int m, const int *cidx, int n,
             work[b * d + a] = v;
         }
     if (k == 0) { *term = 1; return 0; }
-    return chol_inv_sqrt_det(work, d, term);
+    if (chol_inv_sqrt_det(work, d, term)) return -1;
+    if (mean) {  /* vec holds 2d scalars: mu_A, then the solve */
+        for (int a = 0; a < d; a++) vec[a] = (qf)mean[2 * modes[a / 2] + (a & 1)];
+        *term *= mean_factor(work, d, vec, vec + d);
+    }
+    return 0;
 }
 
 static int split_pattern(int m, const int8_t *pattern, int **cidx, int *n, int **nidx, int *nn) {
@@ -157,9 +179,9 @@ static int split_pattern(int m, const int8_t *pattern, int **cidx, int *n, int *
 
 /* Form P over a strided range of subset masks (the full sum is begin = 0,
  * stride = 1, count = 2^n).  threads <= 0 means the OpenMP default. */
-int oracle_formP_range(const double *cov, int m, const int8_t *pattern,
-                       uint64_t begin, uint64_t stride, uint64_t count, int threads,
-                       oracle_result *out) {
+int oracle_formP_mean_range(const double *cov, const double *mean, int m, const int8_t *pattern,
+                            uint64_t begin, uint64_t stride, uint64_t count, int threads,
+                            oracle_result *out) {
     int rc = validate(cov, m, pattern);
     if (rc) return rc;
     int *cidx, *nidx, n, nn;
@@ -181,9 +203,10 @@ int oracle_formP_range(const double *cov, int m, const int8_t *pattern,
         tid = omp_get_thread_num();
 #endif
         qf *work = (qf *)malloc(sizeof(qf) * (size_t)(dmax > 0 ? dmax * dmax : 1));
+        qf *vec = (qf *)malloc(sizeof(qf) * (size_t)(2 * dmax + 2));
         int *modes = (int *)malloc(sizeof(int) * (size_t)(n + nn + 1));
         qf s = 0, a = 0;
-        int mybad = (!work || !modes);
+        int mybad = (!work || !modes || !vec);
         /* static contiguous chunks: thread t takes j in [lo, hi) */
         uint64_t lo = count * (uint64_t)tid / (uint64_t)nthr;
         uint64_t hi = count * (uint64_t)(tid + 1) / (uint64_t)nthr;
@@ -191,12 +214,12 @@ int oracle_formP_range(const double *cov, int m, const int8_t *pattern,
             uint64_t mask = begin + j * stride;
             if (n < 64) mask &= ((uint64_t)1 << n) - 1;
             qf t;
-            if (term_formP(cov, m, cidx, n, nidx, nn, mask, work, modes, &t)) { mybad = 1; break; }
+            if (term_formP(cov, mean, m, cidx, n, nidx, nn, mask, work, vec, modes, &t)) { mybad = 1; break; }
             if (__builtin_popcountll(mask) & 1) s -= t; else s += t;
             a += t;
         }
         part_s[tid] = s; part_a[tid] = a; bad[tid] = mybad;
-        free(work); free(modes);
+        free(work); free(vec); free(modes);
     }
     qf S = 0, A = 0;
     for (int t = 0; t < nthr; t++) { S += part_s[t]; A += part_a[t]; err |= bad[t]; }
@@ -207,8 +230,10 @@ int oracle_formP_range(const double *cov, int m, const int8_t *pattern,
         /* P_vac(N) alone (the empty subset of C), for reporting */
         int *modes = (int *)malloc(sizeof(int) * (size_t)(nn + 1));
         qf *work = (qf *)malloc(sizeof(qf) * (size_t)(4 * nn * nn));
-        if (!modes || !work || term_formP(cov, m, cidx, n, nidx, nn, 0, work, modes, &pvn)) err = 1;
-        free(modes); free(work);
+        qf *vec = (qf *)malloc(sizeof(qf) * (size_t)(4 * nn + 2));
+        if (!modes || !work || !vec || term_formP(cov, mean, m, cidx, n, nidx, nn, 0, work, vec, modes, &pvn))
+            err = 1;
+        free(modes); free(work); free(vec);
     }
     free(cidx); free(nidx);
     if (err) return OR_ENOTPD;
@@ -219,6 +244,24 @@ int oracle_formP_range(const double *cov, int m, const int8_t *pattern,
     out->pvac_n = (double)pvn;
     out->n_terms = (double)count;
     return OR_OK;
+}
+
+int oracle_formP_range(const double *cov, int m, const int8_t *pattern,
+                       uint64_t begin, uint64_t stride, uint64_t count, int threads,
+                       oracle_result *out) {
+    return oracle_formP_mean_range(cov, NULL, m, pattern, begin, stride, count, threads, out);
+}
+
+/* Form P of a displaced state (mean: 2m doubles, hbar = 1, interleaved). */
+int oracle_formP_mean(const double *cov, const double *mean, int m, const int8_t *pattern, int threads,
+                      oracle_result *out) {
+    int n = 0;
+    if (!pattern || m <= 0 || !mean) return OR_EINVAL;
+    for (int i = 0; i < 2 * m; i++)
+        if (mean[i] != mean[i] || mean[i] - mean[i] != 0) return OR_EINVAL;
+    for (int i = 0; i < m; i++) n += pattern[i] == 1;
+    if (n > 40) return OR_ETOOBIG;
+    return oracle_formP_mean_range(cov, mean, m, pattern, 0, 1, (uint64_t)1 << n, threads, out);
 }
 
 int oracle_formP(const double *cov, int m, const int8_t *pattern, int threads, oracle_result *out) {

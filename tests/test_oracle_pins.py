@@ -279,3 +279,73 @@ def test_mutant_is_caught(name, tmp_path):
         except (AssertionError, oracle.OracleError):
             failed.append(pin.__name__)
     assert failed, f"mutant {name} passed every pin"
+
+
+# ---------------------------------------------------------------------------
+# Displaced states (means): each vacuum probability gains the Gaussian
+# overlap factor exp(-mu^T sigma_Q^-1 mu / 2).  Pinned to closed forms that do
+# not go through that formula.
+
+def _mean_of(alphas):
+    """hbar = 1 quadrature means of coherent amplitudes, interleaved."""
+    out = np.empty(2 * len(alphas))
+    out[0::2] = np.sqrt(2) * np.real(alphas)
+    out[1::2] = np.sqrt(2) * np.imag(alphas)
+    return out
+
+
+def test_displaced_coherent_states_through_interferometer():
+    """Coherent states stay a product of coherent states (beta = U alpha):
+    P = prod_clicks (1 - e^{-|beta|^2}) prod_no_clicks e^{-|beta|^2}."""
+    rng = np.random.default_rng(71)
+    m = 6
+    U = gi.haar_unitary(m, rng)
+    alpha = rng.normal(0, 0.6, m) + 1j * rng.normal(0, 0.6, m)
+    beta = U @ alpha
+    cov = gi.gbs_covariance(U, np.zeros(m))
+    pat = np.array([1, 0, 1, -1, 1, 0], np.int8)
+    want = 1.0
+    for i in range(m):
+        if pat[i] == 1:
+            want *= 1 - np.exp(-abs(beta[i]) ** 2)
+        elif pat[i] == 0:
+            want *= np.exp(-abs(beta[i]) ** 2)
+    o = oracle.formP_mean(cov, _mean_of(beta), pat)
+    assert abs((o.p + o.p_lo) - want) <= 1e-14 * want
+    assert float(oracle.prob_sequential(cov, pat, mean=_mean_of(beta), dps=40)) == pytest.approx(want, rel=1e-13)
+
+
+def test_displaced_tmsv_closed_forms():
+    """Two-mode squeezed vacuum with both modes displaced: from the Fock
+    expansion sech r sum_n tanh^n r |n, n>, the vacuum amplitude is
+    sech r exp(-(|a|^2 + |b|^2)/2 + tanh r a* b*), so
+    P_vac(a, b) = sech^2 r exp(-|a|^2 - |b|^2 + 2 tanh r Re(a b)); each mode
+    alone is displaced thermal with nbar = sinh^2 r:
+    P_vac(a) = exp(-|a|^2 / cosh^2 r) / cosh^2 r.  Click patterns follow by
+    inclusion-exclusion; (1, 0) and (0, 1) need the conditioned mean."""
+    r = 0.7
+    a, b = 0.5 - 0.3j, -0.2 + 0.6j
+    cov = gi.tmsv_covariance(r)
+    mean = _mean_of([a, b])
+    c2 = np.cosh(r) ** 2
+    pa = np.exp(-abs(a) ** 2 / c2) / c2
+    pb = np.exp(-abs(b) ** 2 / c2) / c2
+    pab = np.exp(-abs(a) ** 2 - abs(b) ** 2 + 2 * np.tanh(r) * (a * b).real) / c2
+    want = {(0, 0): pab, (1, 0): pb - pab, (0, 1): pa - pab, (1, 1): 1 - pa - pb + pab,
+            (1, -1): 1 - pa, (-1, 0): pb}
+    for pat, w in want.items():
+        pat = np.array(pat, np.int8)
+        o = oracle.formP_mean(cov, mean, pat)
+        assert abs((o.p + o.p_lo) - w) <= 1e-14, (pat, o.p, w)
+        s = oracle.prob_sequential(cov, pat, mean=mean, dps=40)
+        assert abs(float(s) - w) <= 1e-14, (pat, float(s), w)
+
+
+def test_displaced_zero_mean_limit_and_routes_agree():
+    cov = gi.state_config1()
+    pat = np.array([1, 0, 1, 1, 0, -1, 1, 0], np.int8)
+    assert oracle.formP_mean(cov, np.zeros(16), pat).p == oracle.formP(cov, pat).p
+    mu = np.random.default_rng(3).normal(0, 0.5, 16)
+    o = oracle.formP_mean(cov, mu, pat)
+    s = oracle.prob_sequential(cov, pat, mean=mu, dps=40)
+    assert abs((o.p + o.p_lo) - float(s)) <= 1e-14 * abs(float(s))
