@@ -11,8 +11,9 @@ Conventions (used everywhere in this repository):
 * quadratures are interleaved per mode, (x1, p1, x2, p2, ...), as in the
   paper's definition of the quadrature vector (Sec. II, Eq. 1).
 * the paper uses hbar = 2 (vacuum V = I); the two are related by V = 2 * sigma.
-* states are zero-mean (GBS inputs are squeezed vacua; vacuum conditioning
-  keeps the mean at zero).
+* GBS inputs are squeezed vacua and so zero-mean; displaced states carry a
+  mean vector in the same interleaved order and units (a coherent state
+  |alpha> has mean (sqrt(2) Re alpha, sqrt(2) Im alpha) and covariance I/2).
 
 The benchmark states of the paper (Sec. III, "Memory") are 8 dB squeezed
 inputs sent through Haar-random interferometers; the workloads below use the
@@ -39,6 +40,8 @@ __all__ = [
     "config5_pattern",
     "config3_queries",
     "random_product_state",
+    "random_mean",
+    "coherent_mean",
     "planted_clique_graph",
     "takagi_real_symmetric",
     "graph_covariance",
@@ -201,6 +204,20 @@ def random_product_state(m: int, rng: np.random.Generator):
     blocks = [single_mode_covariance(rng.uniform(0.1, 1.0), rng.uniform(0, np.pi),
                                      rng.uniform(0.0, 0.5)) for _ in range(m)]
     return direct_sum(blocks), blocks
+
+
+def random_mean(m: int, rng: np.random.Generator, scale: float = 0.5) -> np.ndarray:
+    """Random displacement: 2m independent normal quadrature means (hbar = 1)."""
+    return scale * rng.standard_normal(2 * m)
+
+
+def coherent_mean(alpha) -> np.ndarray:
+    """Mean vector (hbar = 1, interleaved) of the coherent states |alpha_k>."""
+    alpha = np.atleast_1d(np.asarray(alpha, dtype=np.complex128))
+    out = np.empty(2 * alpha.shape[0])
+    out[0::2] = np.sqrt(2.0) * alpha.real
+    out[1::2] = np.sqrt(2.0) * alpha.imag
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -152,6 +152,25 @@ const char *tor_last_error(void);
 tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int8_t *pattern, tor_prec prec,
                            double tol, tor_result *out);
 
+/* Probability of one click pattern of a displaced Gaussian state: covariance
+ * cov as for tor_probability and mean vector mean (2m doubles, host, the same
+ * interleaved (x_k, p_k) order and hbar = 1 units, so vacuum has cov = I/2).
+ * Sec. II of the paper for non-zero means: every vacuum probability of
+ * Eq. (prob) carries its mean overlap, det(sigma_Q[A])^{-1/2}
+ * exp(-mu_A^T sigma_Q[A]^-1 mu_A / 2), and the no-click conditioning moves
+ * the mean with the covariance (the update of the mean beside
+ * Eq. MatrixUpdate).  The factor 1/2 in the exponent is the reading of the
+ * printed exponent (given for hbar = 2 without it) that reproduces the
+ * coherent-state closed form p(click) = 1 - exp(-|alpha|^2).  Fields of out as
+ * for tor_probability, except: T is the subset sum with the mean factors of
+ * the conditioned state, tor = det(Sigma_C)^{1/2} * T, and rel_err_bound
+ * carries a further factor (1 + mu_C^T Sigma_C^-1 mu_C) for the rounding of
+ * the exponents.  A zero mean gives the zero-mean result.  Errors as for
+ * tor_probability (TOR_EINVAL also for a NULL or non-finite mean entry of an
+ * observed mode). */
+tor_status tor_probability_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m,
+                                     const int8_t *pattern, tor_prec prec, double tol, tor_result *out);
+
 /* The subset sum alone for a given SPD matrix Sigma (2n x 2n row-major,
  * interleaved, host): T = sum_{Y subset of [n]} (-1)^{|Y|} det(Sigma[Y])^{-1/2}.
  * sigma_lo may be NULL; otherwise Sigma = sigma_hi + sigma_lo entrywise

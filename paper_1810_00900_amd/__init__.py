@@ -129,6 +129,8 @@ def lib():
         "tor_last_error": ([], ctypes.c_char_p),
         "tor_probability": ([vp, dp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
                              ctypes.POINTER(_CResult)], ctypes.c_int32),
+        "tor_probability_displaced": ([vp, dp, dp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
+                                       ctypes.POINTER(_CResult)], ctypes.c_int32),
         "tor_subset_sum": ([vp, dp, dp, ctypes.c_int32, ctypes.c_int, ctypes.c_double,
                             ctypes.POINTER(_CResult)], ctypes.c_int32),
         "tor_state_create": ([vp, dp, ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int32),
@@ -245,6 +247,22 @@ class Context:
         r = _CResult()
         _check(lib().tor_probability(self._h, _dptr(cov), m, _i8ptr(pattern), _PREC[prec], float(tol),
                                      ctypes.byref(r)))
+        return Result._from(r)
+
+    def probability_displaced(self, cov, mean, pattern, prec="auto", tol: float = 1e-10) -> Result:
+        """Click-pattern probability of a displaced Gaussian state (mean: 2m
+        entries, hbar = 1, interleaved like cov) -- tor_probability_displaced."""
+        cov = _f64(cov)
+        mean = _f64(mean)
+        pattern = _i8(pattern)
+        m = pattern.shape[0]
+        if cov.shape != (2 * m, 2 * m):
+            raise ValueError("cov must be 2m x 2m for a pattern of length m")
+        if mean.shape != (2 * m,):
+            raise ValueError("mean must have 2m entries")
+        r = _CResult()
+        _check(lib().tor_probability_displaced(self._h, _dptr(cov), _dptr(mean), m, _i8ptr(pattern), _PREC[prec],
+                                               float(tol), ctypes.byref(r)))
         return Result._from(r)
 
     def subset_sum(self, sigma, sigma_lo=None, prec="dd", tol: float = 1e-10) -> Result:

@@ -1,15 +1,18 @@
 """Build the HIP library libtorgbs.so in-tree for gfx950 with hipcc."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtorgbs.so")
-SOURCES = ["csrc/tor_api.hip", "csrc/tor_kernels.hip", "csrc/gbs_sampler.hip", "csrc/tor_async.hip"]
+SOURCES = ["csrc/tor_api.hip", "csrc/tor_kernels.hip", "csrc/tor_kernels_disp.hip", "csrc/gbs_sampler.hip",
+           "csrc/tor_async.hip"]
 
 # -ffp-contract=off: the double-double error-free transformations must not be
 # fused into FMAs by the compiler (explicit fma() calls are kept).
@@ -26,15 +29,26 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, out: str = LIB) -> str:
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           *[os.path.join(HERE, s) for s in SOURCES], "-o", out + ".tmp"]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed")
+
+
+def build(verbose: bool = False, out: str = LIB) -> str:
+    """Compile every source to an object in parallel (one hipcc per source),
+    then link the shared library."""
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    with tempfile.TemporaryDirectory(prefix="torgbs_build_") as tmp:
+        objs = [os.path.join(tmp, os.path.basename(s) + ".o") for s in SOURCES]
+        cmds = [[hipcc(), *FLAGS, *inc, "-c", os.path.join(HERE, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        _run([hipcc(), *FLAGS, *objs, "-o", out + ".tmp"], verbose)
     os.replace(out + ".tmp", out)
     return out
 

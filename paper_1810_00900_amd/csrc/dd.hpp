@@ -183,6 +183,36 @@ DD_FN dd dd_rsqrt(dd x) {
     return out;
 }
 
+// double-word / double: q1 = a.hi / b, the remainder a - q1 b formed exactly
+// with one TwoProd, then one correction (relative error a few u^2).
+DD_FN dd dd_div_d(dd a, double b) {
+    const double q1 = a.hi / b;
+    double p, e;
+    two_prod(q1, b, p, e);
+    const double r = ((a.hi - p) - e + a.lo) / b;
+    dd o;
+    fast_two_sum(q1, r, o.hi, o.lo);
+    return o;
+}
+
+// exp(x) of a double-word x (finite, x.hi < 709): x = k ln2 + r with
+// |r| <= ln2 / 2; exp(r / 32) from its Taylor series to degree 14 (Horner,
+// truncation below 1e-41), squared five times, scaled by 2^k.  The squarings
+// amplify the rounding of the series 32-fold: relative error below ~1e-30.
+// Returns 0 below exp(-745).
+DD_FN dd dd_exp(dd x) {
+    if (x.hi < -745.0) return dd_from(0.0);
+    const dd ln2 = dd_make(6.93147180559945286227e-01, 2.31904681384629955842e-17);
+    const double k = rint(x.hi / ln2.hi);
+    dd r = dd_add(x, dd_neg(dd_mul_d(ln2, k)));
+    r = dd_make(r.hi * 0.03125, r.lo * 0.03125);
+    dd s = dd_from(1.0);
+    for (int i = 14; i >= 1; --i) s = dd_add(dd_from(1.0), dd_div_d(dd_mul(r, s), (double)i));
+    for (int i = 0; i < 5; ++i) s = dd_mul(s, s);
+    const int ik = (int)k;
+    return dd_make(ldexp(s.hi, ik), ldexp(s.lo, ik));
+}
+
 // binary64 helpers with the same call shape, for the binary64-term tier
 DD_FN double sub_dot2(double x, double a1, double b1, double a2, double b2) {
     return fma(-a2, b2, fma(-a1, b1, x));
@@ -209,3 +239,9 @@ DD_FN dd dd_sub_mul(dd t0, double q, dd t1) { return dd_sub_mul1(t0, t1, dd_from
 DD_FN dd dd_sub_mul(dd t0, dd q, dd t1) { return dd_sub_mul1(t0, t1, q); }
 DD_FN double hi_of(double a) { return a; }
 DD_FN double hi_of(dd a) { return a.hi; }
+DD_FN double exp_s(double x) { return exp(x); }
+DD_FN dd exp_s(dd x) { return dd_exp(x); }
+DD_FN double add_s(double a, double b) { return a + b; }
+DD_FN dd add_s(dd a, dd b) { return dd_add(a, b); }
+DD_FN double scale_s(double a, double f) { return a * f; }
+DD_FN dd scale_s(dd a, double f) { return dd_make(a.hi * f, a.lo * f); }

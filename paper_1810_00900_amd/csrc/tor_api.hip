@@ -48,6 +48,8 @@ tor_status fail(tor_status s, const char *fmt, ...) {
     } while (0)
 
 constexpr long long E(long long r) { return r * (2 * r + 1); }
+// entries of an r-mode packed matrix with D leading mean rows (D = 0 or 1)
+constexpr long long EN(long long r, int D) { return (2 * r + D) * (2 * r + D + 1) / 2; }
 inline long long pidx(long long a, long long b) { return a * (a + 1) / 2 + b; }
 
 struct DevBuf {
@@ -217,14 +219,64 @@ bool dd_cholesky(std::vector<dd> &A, int d, std::vector<dd> &rinv, double *log_d
 // in packed lower storage, and each step conditions on the last remaining
 // mode; P_vac(N) is the product of the steps' pivot factors q.
 struct Reduced {
-    std::vector<dd> sig;  // Sigma_C, 2n x 2n full
+    std::vector<dd> sig;  // Sigma_C, 2n x 2n full (zero-mean states)
     int n = 0;
+    int D = 0;            // 1: displaced state; `packed` has the mean row first and
+                          // holds the conditioned matrix once cond is cleared
     dd pvac = {1.0, 0.0};
     double log_pvac = 0.0;
     bool cond = false;          // conditioning on N still to do
     int k = 0;                  // |N|
-    std::vector<dd> packed;     // sigma_Q over (C, N), E(n + k) entries
+    std::vector<dd> packed;     // sigma_Q over (C, N), EN(n + k, D) entries
 };
+
+// Displaced state (mean mu, hbar = 1, interleaved like cov): the packed matrix
+// over (C, N) gets a leading row [0, mu^T] (rows of mode k: 1 + 2k, 2 + 2k), so
+// that each vacuum-conditioning step moves the mean with the covariance
+// (r_A <- r_A - sigma_AB sigma_Q[B]^-1 r_B, Sec. II) and each pivot factor q
+// gains exp(-w^T w / 2), w = L^-1 r_B, L the Cholesky factor of the pivot
+// block (the vacuum overlap of a displaced Gaussian).  Conditioning runs on the
+// GPU when N is not empty.
+tor_status reduce_pattern_disp(const double *cov, const double *mean, int m, const int8_t *pattern,
+                               Reduced &out) {
+    if (!pattern) return fail(TOR_EINVAL, "pattern is NULL");
+    if (!mean) return fail(TOR_EINVAL, "mean is NULL");
+    std::vector<int> C, N;
+    for (int i = 0; i < m; i++) {
+        int v = pattern[i];
+        if (v == 1) C.push_back(i);
+        else if (v == 0) N.push_back(i);
+        else if (v != -1) return fail(TOR_EINVAL, "pattern[%d] = %d is not in {-1, 0, 1}", i, v);
+    }
+    const int n = (int)C.size(), k = (int)N.size();
+    if (n > TOR_MAX_CLICKS) return fail(TOR_ETOOBIG, "%d clicks > %d", n, TOR_MAX_CLICKS);
+    if (n + k > TOR_COND_MAX_MODES)
+        return fail(TOR_ETOOBIG, "%d observed modes > %d", n + k, TOR_COND_MAX_MODES);
+    std::vector<int> g;  // quadrature index of each covariance row of the (C, N) matrix
+    for (int c : C) {
+        g.push_back(2 * c);
+        g.push_back(2 * c + 1);
+    }
+    for (int c : N) {
+        g.push_back(2 * c);
+        g.push_back(2 * c + 1);
+    }
+    for (int q : g)
+        if (!std::isfinite(mean[q])) return fail(TOR_EINVAL, "mean[%d] is not finite", q);
+    out = Reduced();
+    out.n = n;
+    out.k = k;
+    out.D = 1;
+    const int d = (int)g.size();
+    out.packed.resize((size_t)EN(n + k, 1));
+    out.packed[0] = dd_from(0.0);
+    for (int a = 0; a < d; a++) {
+        out.packed[(size_t)pidx(a + 1, 0)] = dd_from(mean[g[a]]);
+        for (int b = 0; b <= a; b++) out.packed[(size_t)pidx(a + 1, b + 1)] = sigq(cov, m, g[a], g[b]);
+    }
+    out.cond = k > 0;
+    return TOR_OK;
+}
 
 tor_status reduce_pattern(const double *cov, int m, const int8_t *pattern, Reduced &out) {
     if (!pattern) return fail(TOR_EINVAL, "pattern is NULL");
@@ -284,6 +336,7 @@ double elapsed(hipEvent_t a, hipEvent_t b) {
 struct SumIn {
     const std::vector<dd> *packed = nullptr;
     int n = 0;
+    int D = 0;  // 1: displaced, the mean row first (EN(n, 1) entries)
 };
 struct SumOut {
     dd T = {1.0, 0.0};
@@ -300,12 +353,12 @@ int task_modes_for(const tor_ctx *ctx, bool use_dd, int n) {
     return std::min(n, t > 0 ? t : ctx->task_modes[use_dd ? 1 : 0]);
 }
 
-size_t sum_bytes(int n, int J, size_t es) {
+size_t sum_bytes(int n, int J, size_t es, int D = 0) {
     if (n == 0) return 0;
     J = std::min(n, J);
     const int G = n - J;
-    unsigned long long total = (unsigned long long)E(n);
-    for (int d = 0; d < G; d++) total += (1ULL << d) * (unsigned long long)E(n - d - 1);
+    unsigned long long total = (unsigned long long)EN(n, D);
+    for (int d = 0; d < G; d++) total += (1ULL << d) * (unsigned long long)EN(n - d - 1, D);
     const size_t nt = (size_t)1 << G;
     return total * es + 2 * nt * sizeof(NodeDesc) + nt * sizeof(Partial) + (nt / 512 + 8) * sizeof(Partial) +
            1024;
@@ -315,10 +368,12 @@ size_t sum_bytes(int n, int J, size_t es) {
 // every tree are expanded in HBM (one launch per depth, all trees that reach it),
 // then one wave-tier launch per distinct J, then the per-tree reduction stages,
 // then one gather of the results.  The work and the reduction order of each
-// tree do not depend on the other trees in the group.
+// tree do not depend on the other trees in the group.  Every tree of a group
+// has the same mean-row offset D.
 tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vector<int> &idx, bool use_dd,
                      std::vector<SumOut> &out) {
     const size_t es = use_dd ? sizeof(dd) : sizeof(double);
+    const int D = idx.empty() ? 0 : in[idx[0]].D;
     struct Plan {
         int q, n, J, G;
         long long nt;
@@ -338,7 +393,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
         p.G = p.n - p.J;
         p.nt = 1LL << p.G;
         p.root_off = roots;
-        roots += (unsigned long long)E(p.n);
+        roots += (unsigned long long)EN(p.n, D);
         p.desc_off = desc_total;
         desc_total += p.nt;
         Gmax = std::max(Gmax, p.G);
@@ -350,7 +405,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
         p.child_base.resize(p.G);
         for (int d = 0; d < p.G; d++) {
             p.child_base[d] = pool_total;
-            pool_total += (1ULL << d) * (unsigned long long)E(p.n - d - 1);
+            pool_total += (1ULL << d) * (unsigned long long)EN(p.n - d - 1, D);
         }
     }
     // reduction stages: stage outputs laid out one after another in partB
@@ -436,7 +491,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
         for (size_t i = 0; i < P.size(); i++) {
             const Plan &p = P[i];
             if (p.G <= d) continue;
-            ExpandJob job{level_ptr(p, i, d), level_ptr(p, i, d + 1), p.child_base[d], p.n - d, 0};
+            ExpandJob job{level_ptr(p, i, d), level_ptr(p, i, d + 1), p.child_base[d], p.n - d, D};
             std::memcpy(hj + off_exp + ej * sizeof(ExpandJob), &job, sizeof job);
             ej++;
         }
@@ -488,7 +543,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
     if (stage.size() < roots * es) stage.resize(roots * es);
     for (auto &p : P) {
         const std::vector<dd> &pk = *in[p.q].packed;
-        for (long long e = 0; e < E(p.n); e++) {
+        for (long long e = 0; e < EN(p.n, D); e++) {
             if (use_dd) ((dd *)stage.data())[p.root_off + e] = pk[(size_t)e];
             else ((double *)stage.data())[p.root_off + e] = pk[(size_t)e].hi + pk[(size_t)e].lo;
         }
@@ -499,12 +554,12 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
     for (int d = 0; d < Gmax; d++) {
         auto [first, count] = exp_launch[d];
         HIP_TRY(tor_launch_expand(use_dd, (const ExpandJob *)(dj + off_exp) + first, count, d, ctx->pool.p, 1 << 20,
-                                  st));
+                                  st, nullptr, D));
     }
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[1], st));
     for (auto &g : wgroups)
         HIP_TRY(tor_launch_wave(use_dd, g.J, (const WaveJob *)(dj + off_wave) + g.first, g.count, g.total,
-                                ctx->pool.p, ctx->wave_grid, st));
+                                ctx->pool.p, ctx->wave_grid, st, nullptr, D));
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[2], st));
     for (auto &rl : red_launch)
         HIP_TRY(tor_launch_reduce((const ReduceJob *)(dj + off_red) + rl.first, rl.second.first, rl.second.second,
@@ -543,6 +598,14 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
 tor_status gpu_sums(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vector<int> &which, bool use_dd,
                     std::vector<SumOut> &out) {
     const size_t es = use_dd ? sizeof(dd) : sizeof(double);
+    bool mixed = false;
+    for (int q : which) mixed |= in[q].D != in[which[0]].D;
+    if (mixed) {  // zero-mean and displaced trees go to separate groups
+        std::vector<int> w0, w1;
+        for (int q : which) (in[q].D ? w1 : w0).push_back(q);
+        tor_status s = gpu_sums(ctx, in, w0, use_dd, out);
+        return s ? s : gpu_sums(ctx, in, w1, use_dd, out);
+    }
     std::vector<int> group;
     size_t bytes = 0;
     for (int q : which) {
@@ -550,7 +613,7 @@ tor_status gpu_sums(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vecto
             out[q] = SumOut{};
             continue;
         }
-        size_t b = sum_bytes(in[q].n, task_modes_for(ctx, use_dd, in[q].n), es);
+        size_t b = sum_bytes(in[q].n, task_modes_for(ctx, use_dd, in[q].n), es, in[q].D);
         if (!group.empty() && (bytes + b > ctx->mem_budget / 2 || group.size() >= 65536)) {
             tor_status s = gpu_group(ctx, in, group, use_dd, out);
             if (s) return s;
@@ -609,9 +672,10 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
                 if (r->k <= t) continue;
                 CondJob j{};
                 j.r = r->n + r->k - t;
+                j.d = r->D;
                 j.begin = st.blocks;
                 jobs.push_back(j);
-                st.blocks += std::max<long long>(1, (E(j.r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
+                st.blocks += std::max<long long>(1, (EN(j.r - 1, j.d) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
                 st.count++;
                 st.rmax = std::max(st.rmax, j.r);
             }
@@ -658,6 +722,14 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
         for (size_t i = 0; i < nq; i++) {
             Reduced *r = rs[first + i];
             const dd *pk = (const dd *)(stage.data() + off[i] * sizeof(dd));
+            const double *acc = (const double *)(stage.data() + acc_off + i * 3 * sizeof(double));
+            r->pvac = dd_make(acc[0], acc[1]);
+            r->log_pvac = acc[2];
+            r->cond = false;
+            if (r->D) {  // keep the packed form: the leading block with its mean row
+                r->packed.assign(pk, pk + EN(r->n, 1));
+                continue;
+            }
             const int dc = 2 * r->n;
             r->sig.assign((size_t)dc * dc, dd_from(0.0));
             for (int a = 0; a < dc; a++)
@@ -665,10 +737,6 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
                     r->sig[(size_t)a * dc + b] = pk[pidx(a, b)];
                     r->sig[(size_t)b * dc + a] = pk[pidx(a, b)];
                 }
-            const double *acc = (const double *)(stage.data() + acc_off + i * 3 * sizeof(double));
-            r->pvac = dd_make(acc[0], acc[1]);
-            r->log_pvac = acc[2];
-            r->cond = false;
             std::vector<dd>().swap(r->packed);
         }
         first = last;
@@ -687,6 +755,8 @@ void pack_lower(const std::vector<dd> &full, int n, std::vector<dd> &packed) {
 struct Prepared {
     std::vector<dd> packed;
     int n = 0;
+    int D = 0;            // 1: displaced (packed has the mean row first)
+    double quad = 0.0;    // displaced: mu_C^T Sigma_C^-1 mu_C of the conditioned mean
     dd pvac = {1.0, 0.0};
     double log_pvac = 0.0;
     double log_det = 0.0;
@@ -698,7 +768,7 @@ struct Prepared {
 // PD check and log det of Sigma_C by a binary64 Cholesky (log det only feeds
 // the reported Torontonian; the subset tree itself stops with a non-positive
 // pivot on the GPU as well).
-bool f64_cholesky_logdet(const std::vector<dd> &A, int d, double *log_det) {
+bool f64_cholesky_logdet(const std::vector<dd> &A, int d, double *log_det, std::vector<double> *Lout = nullptr) {
     std::vector<double> L((size_t)d * d);
     double ld = 0.0;
     for (int j = 0; j < d; j++) {
@@ -715,6 +785,7 @@ bool f64_cholesky_logdet(const std::vector<dd> &A, int d, double *log_det) {
         }
     }
     *log_det = ld;
+    if (Lout) Lout->swap(L);
     return true;
 }
 
@@ -728,9 +799,46 @@ tor_status prepare(const std::vector<dd> &sig, int n, dd pvac, double log_pvac, 
     return TOR_OK;
 }
 
-double bound_of(int used, int n, dd T, double A) {
+// Displaced states: every term also carries exp(-x/2), x <= quad (the largest
+// exponent of any term: the quadratic form of a principal block's inverse is
+// at most that of the whole matrix); the rounding of x enters the term's
+// relative error in proportion to x, hence the factor (1 + quad).
+double bound_of(int used, int n, dd T, double A, double quad = 0.0) {
     double R = A / std::fabs(T.hi);
-    return kBoundC * std::max(n, 1) * (used == TOR_PREC_DD ? kUDD : kUF64) * R;
+    return kBoundC * std::max(n, 1) * (used == TOR_PREC_DD ? kUDD : kUF64) * R * (1.0 + quad);
+}
+
+// Displaced state: `packed` is the conditioned matrix with its mean row
+// (EN(n, 1) entries).  PD check, log det Sigma_C and mu_C^T Sigma_C^-1 mu_C by
+// a binary64 Cholesky of the covariance block.
+tor_status prepare_disp(std::vector<dd> &&packed, int n, dd pvac, double log_pvac, Prepared &p) {
+    p.n = n;
+    p.D = 1;
+    p.pvac = pvac;
+    p.log_pvac = log_pvac;
+    const int d = 2 * n;
+    if (n > 0) {
+        std::vector<dd> sig((size_t)d * d);
+        for (int a = 0; a < d; a++)
+            for (int b = 0; b <= a; b++) {
+                sig[(size_t)a * d + b] = packed[(size_t)pidx(a + 1, b + 1)];
+                sig[(size_t)b * d + a] = packed[(size_t)pidx(a + 1, b + 1)];
+            }
+        std::vector<double> L;
+        if (!f64_cholesky_logdet(sig, d, &p.log_det, &L)) return fail(TOR_ENOTPD, "Sigma_C is not positive definite");
+        std::vector<double> z(d);
+        double quad = 0.0;
+        for (int a = 0; a < d; a++) {
+            const dd mu = packed[(size_t)pidx(a + 1, 0)];
+            double v = mu.hi + mu.lo;
+            for (int t = 0; t < a; t++) v -= L[(size_t)a * d + t] * z[t];
+            z[a] = v / L[(size_t)a * d + a];
+            quad += z[a] * z[a];
+        }
+        p.quad = quad;
+    }
+    p.packed = std::move(packed);
+    return TOR_OK;
 }
 
 void finalize(const Prepared &p, const SumOut &s, int used, double tol, tor_result *out) {
@@ -746,7 +854,7 @@ void finalize(const Prepared &p, const SumOut &s, int used, double tol, tor_resu
     out->tor = std::exp(0.5 * p.log_det) * (T.hi + T.lo);
     out->abs_sum = A;
     out->cancel_ratio = A / std::fabs(T.hi);
-    out->rel_err_bound = bound_of(used, p.n, T, A);
+    out->rel_err_bound = bound_of(used, p.n, T, A, p.quad);
     out->log_pvac_n = p.log_pvac;
     out->n_clicks = p.n;
     out->prec_used = used;
@@ -764,6 +872,7 @@ tor_status evaluate_many(tor_ctx *ctx, std::vector<Prepared> &qs, tor_prec prec,
     for (size_t i = 0; i < qs.size(); i++) {
         in[i].packed = &qs[i].packed;
         in[i].n = qs[i].n;
+        in[i].D = qs[i].D;
         if (qs[i].status == TOR_OK) ok.push_back((int)i);
     }
     std::vector<SumOut> res(qs.size());
@@ -780,7 +889,8 @@ tor_status evaluate_many(tor_ctx *ctx, std::vector<Prepared> &qs, tor_prec prec,
     if (prec == TOR_PREC_AUTO) {
         std::vector<int> redo;
         for (int i : ok)
-            if (qs[i].n > 0 && !(bound_of(TOR_PREC_F64, qs[i].n, res[i].T, res[i].A) <= tol)) redo.push_back(i);
+            if (qs[i].n > 0 && !(bound_of(TOR_PREC_F64, qs[i].n, res[i].T, res[i].A, qs[i].quad) <= tol))
+                redo.push_back(i);
         if (!redo.empty()) {
             s = gpu_sums(ctx, in, redo, true, res);
             if (s < 0) return fail_all(s);
@@ -932,6 +1042,24 @@ tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int
     if (s) return s;
     std::vector<Prepared> qs(1);
     s = prepare(red.sig, red.n, red.pvac, red.log_pvac, qs[0]);
+    if (s) return s;
+    return evaluate_many(ctx, qs, prec, tol, out);
+}
+
+tor_status tor_probability_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m,
+                                     const int8_t *pattern, tor_prec prec, double tol, tor_result *out) {
+    if (!ctx) return fail(TOR_EINVAL, "ctx is NULL");
+    tor_status s = validate_cov_block(cov, m, pattern);
+    if (s) return s;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!out) return fail(TOR_EINVAL, "out is NULL");
+    Reduced red;
+    s = reduce_pattern_disp(cov, mean, m, pattern, red);
+    if (s) return s;
+    s = condition_on_gpu(ctx, {&red});
+    if (s) return s;
+    std::vector<Prepared> qs(1);
+    s = prepare_disp(std::move(red.packed), red.n, red.pvac, red.log_pvac, qs[0]);
     if (s) return s;
     return evaluate_many(ctx, qs, prec, tol, out);
 }

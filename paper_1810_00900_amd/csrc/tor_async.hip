@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
                 j.chi = level_ptr(P, q, Q, d + 1);
                 j.child_base = (unsigned long long)base;
                 j.r = Q.n - d;
-                j.pad = 0;
+                j.d = 0;
                 P.exp_jobs[(size_t)d * nq + pos] = j;
             },
             lds);

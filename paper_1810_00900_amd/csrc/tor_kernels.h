@@ -34,7 +34,7 @@ struct ExpandJob {
     NodeDesc *chi;
     unsigned long long child_base;
     int r;
-    int pad;
+    int d;  // 1: displaced state, the packed matrix has the mean row first
 };
 
 // wave-tier tasks of one query: tasks[0 .. count) -> out[0 .. count); the
@@ -72,7 +72,7 @@ struct CondJob {
     double *qout;     // if not null: this step's pivot factor q (hi, lo)
     long long begin;  // first block of the launch that works on this job
     int r;
-    int pad;
+    int d;            // 1: displaced state, the packed matrix has the mean row first
 };
 
 #define TOR_COND_CHUNK 1024
@@ -123,10 +123,13 @@ hipError_t tor_launch_async_finalize(const AsyncPlan &P, double tol, int prec_us
 // Launchers.  With dyn != nullptr (a plan made on the device) the kernels read
 // the job count and total work from dyn, and the host-side grid argument
 // (grid_cap, total_blocks) is the grid itself, a bound on the work.
+// disp = 1: displaced state (every packed matrix has the mean row first).
 hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
-                           int grid_cap, hipStream_t st, const LaunchDims *dyn = nullptr);
+                           int grid_cap, hipStream_t st, const LaunchDims *dyn = nullptr, int disp = 0);
+hipError_t tor_launch_wave_disp(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
+                                int grid_cap, hipStream_t st, const LaunchDims *dyn);
 hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
-                             hipStream_t st, const LaunchDims *dyn = nullptr);
+                             hipStream_t st, const LaunchDims *dyn = nullptr, int disp = 0);
 hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_blocks, hipStream_t st,
                              const LaunchDims *dyn = nullptr);
 hipError_t tor_launch_gather(const Partial *const *src, int n, Partial *dst, hipStream_t st);

@@ -37,155 +37,11 @@
 #include "dd.hpp"
 #include "tor_kernels.h"
 #include "tor_tree.hpp"
+#include "tor_wave.hpp"
 
 #pragma clang fp contract(off)
 
 namespace tor {
-
-// Waves per SIMD the wave tier asks the register allocator for: two where two
-// workgroups' LDS fit a quarter of the CU's 160 KiB (one wave per workgroup),
-// so that a second wave can hide the first one's latency; else one.
-template <class S, int J> struct WaveOcc {
-    static constexpr int value = sizeof(WaveSmem<S, J>) + 512 <= 20480 ? 2 : 1;
-};
-
-template <class S, int J>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, J>::value))) void wave_kernel(
-    const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool,
-    const LaunchDims *__restrict__ dyn) {
-    __shared__ WaveSmem<S, J> sm;
-    const int lane = threadIdx.x;
-    if (dyn) {
-        njobs = (int)dyn->njobs;
-        total = dyn->total;
-    }
-    wave_tree_init(sm.ab, lane);
-    for (long long t = blockIdx.x; t < total; t += gridDim.x) {
-        const int j = find_job(jobs, njobs, t);
-        const long long lt = t - jobs[j].begin;
-        NodeDesc d = jobs[j].tasks[lt];
-        const S *root = pool + d.off;
-        for (int e = lane; e < E(J); e += 64) sm.mat[e] = root[e];
-        dd T;
-        double A;
-        wave_tree<S, J>(sm, dd_make(d.coef_hi, d.coef_lo), d.acoef, lane, T, A);
-        wave_reduce(T, A);
-        if (lane == 0) {
-            Partial p;
-            p.t_hi = T.hi;
-            p.t_lo = T.lo;
-            p.a = A;
-            p.pad = 0.0;
-            jobs[j].out[lt] = p;
-        }
-        wave_sync();
-    }
-}
-
-// Tasks of 10 or 11 modes: the top one or two decisions are taken in LDS,
-// depth first, above the nine-mode tree.  At a 10-mode node the pivot columns
-// of its last mode are set aside, the exclude child (the leading nine-mode
-// block, in place) is summed by the nine-mode tree, then the include child is
-// formed in place over that block (the HBM tier's update) and summed the same
-// way.  An 11-mode task sums its exclude child (the leading 10-mode block) so,
-// then rebuilds its include child from the task's matrix, still in HBM, and
-// sums that.  Each top level saves one HBM level for a few hundred bytes of LDS.
-template <class S> struct TopSmem {
-    WaveSmem<S, 9> w;
-    S vtop[2][2 * (2 * TOR_TASK_MAX - 2)];
-};
-
-// pivot of the last mode of the r-mode node m[] and its two scaled columns
-template <class S, int r>
-__device__ __forceinline__ Pivot<S> top_columns(const S *m, S *v, int lane) {
-    constexpr int R = 2 * r, RC = R - 2;
-    // every lane forms the pivot (same value everywhere, no LDS round trip)
-    const Pivot<S> pv = make_pivot(m[pidx(R - 2, R - 2)], m[pidx(R - 1, R - 2)], m[pidx(R - 1, R - 1)]);
-    for (int c = lane; c < RC; c += 64) {
-        S m0 = m[pidx(R - 2, c)];
-        v[c] = mul_s(m0, pv.s1);
-        v[RC + c] = mul_s(sub_mul(m[pidx(R - 1, c)], pv.l, m0), pv.s2);
-    }
-    return pv;
-}
-
-// dst[e] = src[e] - v1(a) v1(b) - v2(a) v2(b) for the (r-1)-mode child, e < E(r-1)
-template <class S, int r>
-__device__ __forceinline__ void top_update(const S *src, S *dst, const S *v, int lane) {
-    constexpr int RC = 2 * r - 2;
-    for (int e = lane; e < E(r - 1); e += 64) {
-        int a, b;
-        unpack(e, a, b);
-        dst[e] = sub_dot2(src[e], v[a], v[b], v[RC + a], v[RC + b]);
-    }
-}
-
-// the 10-mode node in sm.w.mat[0 .. E(10)); adds this lane's share to (T, A)
-template <class S>
-__device__ __forceinline__ void top10(TopSmem<S> &sm, dd c, double a, int lane, dd &T, double &A) {
-    S *v = sm.vtop[0];
-    const Pivot<S> pv = top_columns<S, 10>(sm.w.mat, v, lane);
-    wave_sync();
-    dd t;
-    double x;
-    wave_tree<S, 9>(sm.w, c, a, lane, t, x);
-    T = dd_add(T, t);
-    A += x;
-    wave_sync();
-    top_update<S, 10>(sm.w.mat, sm.w.mat, v, lane);
-    wave_sync();
-    wave_tree<S, 9>(sm.w, dd_neg(coef_mul(c, pv.q)), a * hi_of(pv.q), lane, t, x);
-    T = dd_add(T, t);
-    A += x;
-}
-
-template <class S, int J>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9>::value))) void wave_kernel_top(
-    const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool,
-    const LaunchDims *__restrict__ dyn) {
-    static_assert(J == 10 || J == 11, "top levels: one or two");
-    static_assert(WaveCfg<S, 9>::MAT >= E(J), "the task's matrix must fit the nine-mode working set");
-    __shared__ TopSmem<S> sm;
-    const int lane = threadIdx.x;
-    if (dyn) {
-        njobs = (int)dyn->njobs;
-        total = dyn->total;
-    }
-    wave_tree_init(sm.w.ab, lane);
-    for (long long t = blockIdx.x; t < total; t += gridDim.x) {
-        const int j = find_job(jobs, njobs, t);
-        const long long lt = t - jobs[j].begin;
-        NodeDesc d = jobs[j].tasks[lt];
-        const S *root = pool + d.off;
-        for (int e = lane; e < E(J); e += 64) sm.w.mat[e] = root[e];
-        wave_sync();
-        const dd c0 = dd_make(d.coef_hi, d.coef_lo);
-        dd T = dd_from(0.0);
-        double A = 0.0;
-        if constexpr (J == 10) {
-            top10(sm, c0, d.acoef, lane, T, A);
-        } else {
-            S *v = sm.vtop[1];
-            const Pivot<S> pv = top_columns<S, 11>(sm.w.mat, v, lane);
-            wave_sync();
-            top10(sm, c0, d.acoef, lane, T, A);
-            wave_sync();
-            top_update<S, 11>(root, sm.w.mat, v, lane);
-            wave_sync();
-            top10(sm, dd_neg(coef_mul(c0, pv.q)), d.acoef * hi_of(pv.q), lane, T, A);
-        }
-        wave_reduce(T, A);
-        if (lane == 0) {
-            Partial p;
-            p.t_hi = T.hi;
-            p.t_lo = T.lo;
-            p.a = A;
-            p.pad = 0.0;
-            jobs[j].out[lt] = p;
-        }
-        wave_sync();
-    }
-}
 
 // ---------------------------------------------------------------- HBM tier
 
@@ -193,21 +49,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9
 // One wave per parent node (four per 256-thread workgroup): the include child
 // (rank-2 Schur update of the last mode) goes to the pool, the exclude child
 // keeps the parent's offset.  Waves run independently (no workgroup barrier).
-template <class S>
+// D = 1: displaced state (mean row first in every packed matrix).
+template <class S, int D>
 __global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict__ jobs, int log2npar,
                                                      long long total, S *__restrict__ pool,
                                                      const LaunchDims *__restrict__ dyn) {
     if (dyn) total = dyn->njobs << log2npar;
-    __shared__ S vs[4][2][2 * TOR_MAX_N];
+    __shared__ S vs[4][2][2 * TOR_MAX_N + D];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     S *v0 = vs[w][0], *v1 = vs[w][1];
     for (long long f = (long long)blockIdx.x * 4 + w; f < total; f += (long long)gridDim.x * 4) {
         const ExpandJob job = jobs[f >> log2npar];
         const long long i = f & ((1LL << log2npar) - 1);
-        const int r = job.r, R = 2 * r, RC = R - 2, EC = E(r - 1);
+        const int r = job.r, R = 2 * r + D, RC = R - 2, EC = EN(r - 1, D);
         NodeDesc d = job.par[i];
         const S *base = pool + d.off;
-        Pivot<S> pv = make_pivot(base[pidx(R - 2, R - 2)], base[pidx(R - 1, R - 2)], base[pidx(R - 1, R - 1)]);
+        Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
         unsigned long long coff = job.child_base + (unsigned long long)i * (unsigned long long)EC;
         if (lane == 0) {
             job.chi[2 * i] = d;
@@ -245,16 +102,18 @@ __global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict
 // multiplied by q = det(pivot)^-1/2.  Each 256-thread block takes
 // TOR_COND_CHUNK entries of one query; it forms the pivot and the scaled pivot
 // columns its entries need in LDS (the last two rows, which the step does not
-// write).  Blocks of one step write disjoint entries.
+// write).  Blocks of one step write disjoint entries.  A displaced query
+// (job.d = 1) carries its mean as row 0: the same update conditions the mean,
+// and q gains the overlap factor of the pivot mode's mean.
 __global__ __launch_bounds__(256) void condition_kernel(const CondJob *__restrict__ jobs, int njobs) {
     extern __shared__ dd cols[];
     const int j = find_job(jobs, njobs, (long long)blockIdx.x);
     const CondJob job = jobs[j];
     const long long blk = (long long)blockIdx.x - job.begin;
-    const int r = job.r, R = 2 * r, RC = R - 2;
+    const int r = job.r, R = 2 * r + job.d, RC = R - 2;
     dd *M = job.mat;
-    const Pivot<dd> pv = make_pivot(M[pidx(R - 2, R - 2)], M[pidx(R - 1, R - 2)], M[pidx(R - 1, R - 1)]);
-    const int EC = E(r - 1);
+    const Pivot<dd> pv = job.d ? make_pivot_m<dd, 1>(M, R - 2, R - 1) : make_pivot_m<dd, 0>(M, R - 2, R - 1);
+    const int EC = job.d ? EN(r - 1, 1) : EN(r - 1, 0);
     const int e0 = (int)(blk * TOR_COND_CHUNK);
     const int e1 = e0 + TOR_COND_CHUNK < EC ? e0 + TOR_COND_CHUNK : EC;
     int amax = -1, bl;  // largest row among this block's entries (none when r = 1)
@@ -341,70 +200,34 @@ __global__ void gather_kernel(const Partial *const *__restrict__ src, int n, Par
 
 // ---------------------------------------------------------------- launchers
 
-// With dyn (a plan made on the device) njobs and total are read from dyn by the
-// kernel and grid_cap is the grid itself.
-template <class S, int J>
-static hipError_t launch_wave_J(const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
-                                hipStream_t st, const LaunchDims *dyn) {
-    long long g = dyn ? grid_cap : (total < grid_cap ? total : grid_cap);
-    if (g < 1) return hipSuccess;
-    (void)hipGetLastError();  // report only this launch's error
-    hipLaunchKernelGGL((wave_kernel<S, J>), dim3((unsigned)g), dim3(64), 0, st, jobs, njobs, total,
-                       (const S *)pool, dyn);
-    return hipGetLastError();
-}
-
-template <class S, int J>
-static hipError_t launch_wave_top(const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
-                                  hipStream_t st, const LaunchDims *dyn) {
-    long long g = dyn ? grid_cap : (total < grid_cap ? total : grid_cap);
-    if (g < 1) return hipSuccess;
-    (void)hipGetLastError();  // report only this launch's error
-    hipLaunchKernelGGL((wave_kernel_top<S, J>), dim3((unsigned)g), dim3(64), 0, st, jobs, njobs, total,
-                       (const S *)pool, dyn);
-    return hipGetLastError();
-}
-
-template <class S>
-static hipError_t launch_wave_S(int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
-                                int grid_cap, hipStream_t st, const LaunchDims *dyn) {
-    switch (J) {
-    case 1: return launch_wave_J<S, 1>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    case 2: return launch_wave_J<S, 2>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    case 3: return launch_wave_J<S, 3>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    case 4: return launch_wave_J<S, 4>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    case 5: return launch_wave_J<S, 5>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    case 6: return launch_wave_J<S, 6>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    case 7: return launch_wave_J<S, 7>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    case 8: return launch_wave_J<S, 8>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    case 9: return launch_wave_J<S, 9>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    case 10: return launch_wave_top<S, 10>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    case 11: return launch_wave_top<S, 11>(jobs, njobs, total, pool, grid_cap, st, dyn);
-    default: return hipErrorInvalidValue;
-    }
-}
-
 }  // namespace tor
 
 hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
-                           int grid_cap, hipStream_t st, const LaunchDims *dyn) {
-    return is_dd ? tor::launch_wave_S<dd>(J, jobs, njobs, total, pool, grid_cap, st, dyn)
-                 : tor::launch_wave_S<double>(J, jobs, njobs, total, pool, grid_cap, st, dyn);
+                           int grid_cap, hipStream_t st, const LaunchDims *dyn, int disp) {
+    if (disp) return tor_launch_wave_disp(is_dd, J, jobs, njobs, total, pool, grid_cap, st, dyn);
+    return is_dd ? tor::launch_wave_S<dd, 0>(J, jobs, njobs, total, pool, grid_cap, st, dyn)
+                 : tor::launch_wave_S<double, 0>(J, jobs, njobs, total, pool, grid_cap, st, dyn);
 }
 
 hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
-                             hipStream_t st, const LaunchDims *dyn) {
+                             hipStream_t st, const LaunchDims *dyn, int disp) {
     long long total = (long long)njobs << log2npar;
     long long blocks = (total + 3) / 4;
     long long g = dyn ? grid_cap : (blocks < grid_cap ? blocks : grid_cap);
     if (g < 1) return hipSuccess;
     (void)hipGetLastError();  // report only this launch's error
-    if (is_dd)
-        hipLaunchKernelGGL(tor::expand_kernel<dd>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
+    if (is_dd && disp)
+        hipLaunchKernelGGL((tor::expand_kernel<dd, 1>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
                            (dd *)pool, dyn);
+    else if (is_dd)
+        hipLaunchKernelGGL((tor::expand_kernel<dd, 0>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
+                           (dd *)pool, dyn);
+    else if (disp)
+        hipLaunchKernelGGL((tor::expand_kernel<double, 1>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar,
+                           total, (double *)pool, dyn);
     else
-        hipLaunchKernelGGL(tor::expand_kernel<double>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
-                           (double *)pool, dyn);
+        hipLaunchKernelGGL((tor::expand_kernel<double, 0>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar,
+                           total, (double *)pool, dyn);
     return hipGetLastError();
 }
 
@@ -420,7 +243,7 @@ hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_b
 hipError_t tor_launch_condition(const CondJob *jobs, int njobs, long long total_blocks, int rmax, hipStream_t st) {
     if (total_blocks < 1) return hipSuccess;
     if (rmax < 1 || rmax > TOR_COND_MAX_MODES || total_blocks > (1LL << 31) - 1) return hipErrorInvalidValue;
-    const size_t lds = sizeof(dd) * 2 * (2 * (size_t)rmax - 2) + 16;
+    const size_t lds = sizeof(dd) * 2 * (2 * (size_t)rmax - 1) + 16;  // 2 columns of 2 rmax - 1 rows (mean row)
     (void)hipGetLastError();  // report only this launch's error
     hipLaunchKernelGGL(tor::condition_kernel, dim3((unsigned)total_blocks), dim3(256), lds, st, jobs, njobs);
     return hipGetLastError();

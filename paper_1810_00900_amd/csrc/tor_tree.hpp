@@ -19,6 +19,11 @@
 namespace tor {
 
 __host__ __device__ constexpr int E(int r) { return r * (2 * r + 1); }
+// Entries of an r-mode node: displaced states (D = 1) carry the mean vector as
+// an extra leading row [c, mu^T] of the packed matrix (rows 1 + 2k, 2 + 2k for
+// mode k); the Schur update of the pivot block then moves the mean exactly as
+// the no-click update of Sec. II does.  D = 0: the plain 2r x 2r matrix.
+__host__ __device__ constexpr int EN(int r, int D) { return (2 * r + D) * (2 * r + D + 1) / 2; }
 __host__ __device__ constexpr int pidx(int a, int b) { return a * (a + 1) / 2 + b; }
 
 // packed lower-triangle index -> (row, column)
@@ -73,18 +78,34 @@ __device__ __forceinline__ Pivot<S> make_pivot(S al, S be, S ga) {
     return p;
 }
 
+// Pivot of the mode in rows p0, p1 of the packed matrix M.  With D = 1 the
+// vacuum probability of the mode gains the overlap factor exp(-|w|^2 / 2) of
+// its (conditioned) mean, w = L^-1 mu_B = (v1(0), v2(0)): row 0 holds the
+// means, so w is the mean row's entry of the two scaled pivot columns.
+template <class S, int D>
+__device__ __forceinline__ Pivot<S> make_pivot_m(const S *M, int p0, int p1) {
+    Pivot<S> pv = make_pivot(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)]);
+    if constexpr (D == 1) {
+        const S m0 = M[pidx(p0, 0)];
+        const S w1 = mul_s(m0, pv.s1);
+        const S w2 = mul_s(sub_mul(M[pidx(p1, 0)], pv.l, m0), pv.s2);
+        pv.q = mul_s(pv.q, exp_s(scale_s(add_s(mul_s(w1, w1), mul_s(w2, w2)), -0.5)));
+    }
+    return pv;
+}
+
 __device__ __forceinline__ dd coef_mul(dd c, double q) { return dd_mul_d(c, q); }
 __device__ __forceinline__ dd coef_mul(dd c, dd q) { return dd_mul(c, q); }
 
 // ---------------------------------------------------------------- leaf tier
 
-template <class S, int R> struct Leaf {
+template <class S, int R, int D = 0> struct Leaf {
     static __device__ __forceinline__ void run(const S *M, dd &T, double &A) {
-        constexpr int p0 = 2 * R - 2, p1 = 2 * R - 1, RC = 2 * R - 2;
+        constexpr int p0 = 2 * R - 2 + D, p1 = 2 * R - 1 + D, RC = 2 * R - 2 + D;
         dd T0;
         double A0;
-        Leaf<S, R - 1>::run(M, T0, A0);  // exclude: the prefix of M
-        Pivot<S> pv = make_pivot(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)]);
+        Leaf<S, R - 1, D>::run(M, T0, A0);  // exclude: the prefix of M
+        Pivot<S> pv = make_pivot_m<S, D>(M, p0, p1);
         S v1[RC], v2[RC];
 #pragma unroll
         for (int c = 0; c < RC; ++c) {
@@ -92,7 +113,7 @@ template <class S, int R> struct Leaf {
             v1[c] = mul_s(m0, pv.s1);
             v2[c] = mul_s(sub_mul(M[pidx(p1, c)], pv.l, m0), pv.s2);
         }
-        S C[E(R - 1)];
+        S C[EN(R - 1, D)];
 #pragma unroll
         for (int a = 0; a < RC; ++a)
 #pragma unroll
@@ -100,21 +121,23 @@ template <class S, int R> struct Leaf {
                 C[pidx(a, b)] = sub_dot2(M[pidx(a, b)], v1[a], v1[b], v2[a], v2[b]);
         dd T1;
         double A1;
-        Leaf<S, R - 1>::run(C, T1, A1);
+        Leaf<S, R - 1, D>::run(C, T1, A1);
         T = dd_sub_mul(T0, pv.q, T1);
         A = A0 + hi_of(pv.q) * A1;
     }
 };
 
-template <class S> struct Leaf<S, 1> {
+template <class S, int D> struct Leaf<S, 1, D> {
     static __device__ __forceinline__ void run(const S *M, dd &T, double &A) {
-        S q = rsqrt_s(det2(M[0], M[1], M[2]));
+        S q;
+        if constexpr (D == 0) q = rsqrt_s(det2(M[0], M[1], M[2]));
+        else q = make_pivot_m<S, 1>(M, 1, 2).q;
         T = dd_sub(dd_from(1.0), to_dd(q));
         A = 1.0 + hi_of(q);
     }
 };
 
-template <class S> struct Leaf<S, 0> {
+template <class S, int D> struct Leaf<S, 0, D> {
     static __device__ __forceinline__ void run(const S *, dd &T, double &A) {
         T = dd_from(1.0);
         A = 1.0;
@@ -140,7 +163,7 @@ __device__ __forceinline__ void wave_reduce(dd &T, double &A) {
 
 // ---------------------------------------------------------------- wave tier
 
-template <class S, int J> struct WaveCfg {
+template <class S, int J, int D = 0> struct WaveCfg {
     static constexpr int TL = J < 3 ? J : 3;    // leaf modes (per lane, registers)
     static constexpr int TW = J - TL;           // levels above the leaves
     static constexpr int TWC = TW > 0 ? TW - 1 : 0;  // levels expanded cooperatively in LDS
@@ -148,15 +171,15 @@ template <class S, int J> struct WaveCfg {
     static constexpr int NL = 1 << TW;          // leaves (<= 64), one per lane
     // LDS slot offsets: slot base for include children created at level k
     static constexpr int soff(int k) {
-        int o = E(J);
-        for (int kk = 0; kk < k; ++kk) o += (1 << kk) * E(J - kk - 1);
+        int o = EN(J, D);
+        for (int kk = 0; kk < k; ++kk) o += (1 << kk) * EN(J - kk - 1, D);
         return o;
     }
     static constexpr int MAT = soff(TWC);
     static constexpr int vmax() {
         int m = 1;
         for (int k = 0; k < TWC; ++k) {
-            int v = (1 << k) * 2 * (2 * (J - k) - 2);
+            int v = (1 << k) * 2 * (2 * (J - k) - 2 + D);
             if (v > m) m = v;
         }
         return m;
@@ -165,22 +188,21 @@ template <class S, int J> struct WaveCfg {
     static constexpr int NPIV = NN / 2 > 0 ? NN / 2 : 1;
 };
 
-// (row, column) of packed index e, for every e < E(8) (the largest child of
-// a 9-mode node); identical for every node size since packed storage of a
+// (row, column) of packed index e, for every e < EN(8, D) (the largest child
+// of a 9-mode node); identical for every node size since packed storage of a
 // smaller matrix is a prefix.
-#define TOR_AB_N 136
+__host__ __device__ constexpr int ab_n(int D) { return EN(8, D); }
 
-template <class S, int J, int K> struct WaveLevel {
-    using C = WaveCfg<S, J>;
+template <class S, int J, int K, int D = 0> struct WaveLevel {
+    using C = WaveCfg<S, J, D>;
     static __device__ __forceinline__ void run(const unsigned short *ab, S *mat, S *vbuf, Pivot<S> *piv, int *loc,
                                                dd *coef, double *acoef, int lane) {
         if constexpr (K < C::TWC) {
-            constexpr int r = J - K, R = 2 * r, NK = 1 << K, RC = R - 2, EC = E(r - 1);
+            constexpr int r = J - K, R = 2 * r + D, NK = 1 << K, RC = R - 2, EC = EN(r - 1, D);
             // phase 0: pivot of each node, coefficients and slots of the include children
             if (lane < NK) {
                 const S *base = mat + loc[lane];
-                Pivot<S> pv = make_pivot(base[pidx(R - 2, R - 2)], base[pidx(R - 1, R - 2)],
-                                         base[pidx(R - 1, R - 1)]);
+                Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
                 piv[lane] = pv;
                 coef[NK + lane] = dd_neg(coef_mul(coef[lane], pv.q));
                 acoef[NK + lane] = acoef[lane] * hi_of(pv.q);
@@ -237,7 +259,7 @@ template <class S, int J, int K> struct WaveLevel {
                 }
             }
             wave_sync();
-            WaveLevel<S, J, K + 1>::run(ab, mat, vbuf, piv, loc, coef, acoef, lane);
+            WaveLevel<S, J, K + 1, D>::run(ab, mat, vbuf, piv, loc, coef, acoef, lane);
         }
     }
 };
@@ -256,9 +278,9 @@ __device__ __forceinline__ int find_job(const Job *jobs, int njobs, long long t)
 
 // LDS working set of the wave tier for a J-mode node.  The index table comes
 // first and mat second, at the same offsets for every J.
-template <class S, int J> struct WaveSmem {
-    using C = WaveCfg<S, J>;
-    unsigned short ab[TOR_AB_N];
+template <class S, int J, int D = 0> struct WaveSmem {
+    using C = WaveCfg<S, J, D>;
+    unsigned short ab[ab_n(D)];
     S mat[C::MAT];
     S vbuf[C::VMAX];
     Pivot<S> piv[C::NPIV];
@@ -268,8 +290,9 @@ template <class S, int J> struct WaveSmem {
 };
 
 // Fill the packed-index table (once per workgroup, before the first tree).
+template <int D = 0>
 __device__ __forceinline__ void wave_tree_init(unsigned short *ab, int lane) {
-    for (int e = lane; e < TOR_AB_N; e += 64) {
+    for (int e = lane; e < ab_n(D); e += 64) {
         int a, b;
         unpack(e, a, b);
         ab[e] = (unsigned short)(a | (b << 8));
@@ -277,7 +300,7 @@ __device__ __forceinline__ void wave_tree_init(unsigned short *ab, int lane) {
     wave_sync();
 }
 
-// Subset tree of the J-mode node stored in sm.mat[0 .. E(J)) with path
+// Subset tree of the J-mode node stored in sm.mat[0 .. EN(J, D)) with path
 // coefficient (c, a).  The wave expands all but the last of the J - TL levels
 // above the leaves breadth-first in LDS; lane l < NL then takes node
 // l mod NN, decides its last mode itself (l >= NN: include, a rank-2 Schur
@@ -285,39 +308,39 @@ __device__ __forceinline__ void wave_tree_init(unsigned short *ab, int lane) {
 // and finishes the TL-mode leaf in registers.  Returns this lane's share
 // (T, A) (zero for lanes >= NL).  Lane bit 0 is the decision on the node's last
 // mode (1 = included) when J > TL.  Must be called by all 64 lanes.
-template <class S, int J>
-__device__ __forceinline__ void wave_tree(WaveSmem<S, J> &sm, dd c, double a, int lane, dd &T, double &A) {
-    using C = WaveCfg<S, J>;
+template <class S, int J, int D = 0>
+__device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, dd c, double a, int lane, dd &T, double &A) {
+    using C = WaveCfg<S, J, D>;
     if (lane == 0) {
         sm.loc[0] = 0;
         sm.coef[0] = c;
         sm.acoef[0] = a;
     }
     wave_sync();
-    WaveLevel<S, J, 0>::run(sm.ab, sm.mat, sm.vbuf, sm.piv, sm.loc, sm.coef, sm.acoef, lane);
+    WaveLevel<S, J, 0, D>::run(sm.ab, sm.mat, sm.vbuf, sm.piv, sm.loc, sm.coef, sm.acoef, lane);
     T = dd_from(0.0);
     A = 0.0;
     if constexpr (C::TW == 0) {
         if (lane == 0) {
-            S M[E(C::TL)];
+            S M[EN(C::TL, D)];
 #pragma unroll
-            for (int e = 0; e < E(C::TL); ++e) M[e] = sm.mat[e];
+            for (int e = 0; e < EN(C::TL, D); ++e) M[e] = sm.mat[e];
             dd Tl;
             double Al;
-            Leaf<S, C::TL>::run(M, Tl, Al);
+            Leaf<S, C::TL, D>::run(M, Tl, Al);
             T = dd_mul(c, Tl);
             A = a * Al;
         }
     } else {
         if (lane < C::NL) {
-            constexpr int R1 = C::TL + 1, p0 = 2 * R1 - 2, p1 = 2 * R1 - 1, RC = 2 * R1 - 2;
+            constexpr int R1 = C::TL + 1, p0 = 2 * R1 - 2 + D, p1 = 2 * R1 - 1 + D, RC = 2 * R1 - 2 + D;
             const int i = lane & (C::NN - 1);
             const bool inc = lane >= C::NN;
             const S *base = sm.mat + sm.loc[i];
-            S M[E(R1)];
+            S M[EN(R1, D)];
 #pragma unroll
-            for (int e = 0; e < E(R1); ++e) M[e] = base[e];
-            Pivot<S> pv = make_pivot(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)]);
+            for (int e = 0; e < EN(R1, D); ++e) M[e] = base[e];
+            Pivot<S> pv = make_pivot_m<S, D>(M, p0, p1);
             const S zero = from_pair<S>(0.0, 0.0);
             S v1[RC], v2[RC];
 #pragma unroll
@@ -328,7 +351,7 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J> &sm, dd c, double a, in
                 v1[cc] = inc ? x1 : zero;
                 v2[cc] = inc ? x2 : zero;
             }
-            S Ml[E(C::TL)];
+            S Ml[EN(C::TL, D)];
 #pragma unroll
             for (int x = 0; x < RC; ++x)
 #pragma unroll
@@ -341,7 +364,7 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J> &sm, dd c, double a, in
             }
             dd Tl;
             double Al;
-            Leaf<S, C::TL>::run(Ml, Tl, Al);
+            Leaf<S, C::TL, D>::run(Ml, Tl, Al);
             T = dd_mul(cl, Tl);
             A = al * Al;
         }

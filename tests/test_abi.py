@@ -63,3 +63,14 @@ def test_null_context_rejected():
     pat = np.ones(1, np.int8)
     st = L.tor_probability(None, tg._dptr(cov), 1, tg._i8ptr(pat), 0, 1e-10, ctypes.byref(r))
     assert st == tg.TOR_EINVAL
+
+
+def test_null_context_rejected_displaced():
+    L = tg.lib()
+    r = tg._CResult()
+    cov = np.eye(2) * 0.5
+    mean = np.zeros(2)
+    pat = np.ones(1, np.int8)
+    st = L.tor_probability_displaced(None, tg._dptr(cov), tg._dptr(mean), 1, tg._i8ptr(pat), 0, 1e-10,
+                                     ctypes.byref(r))
+    assert st == tg.TOR_EINVAL
