@@ -62,11 +62,19 @@ def tree_flops(n, top=None):
     return sum((2 ** (r0 - r)) * dd_node_flops(r) for r in range(1, r0 + 1))
 
 
-def wave_kernel_name(prec, J):
+def wave_kernel_name(prec, J, D=0):
     """Name of the wave-tier kernel that runs J-mode tasks (as rocprofv3 lists
-    it, template arguments shortened)."""
+    it, template arguments <scalar, task modes, mean rows> without spaces)."""
     s = "dd" if prec == "dd" else "double"
-    return f"wave_kernel_top<{s},{J}>" if J > 9 else f"wave_kernel<{s},{J}>"
+    return f"wave_kernel_top<{s},{J},{D}>" if J > 9 else f"wave_kernel<{s},{J},{D}>"
+
+
+def kernel_slug(kernel):
+    """File-name form of a wave-kernel name: wave_kernel_top<dd,10,0> ->
+    wave_kernel_top_dd10 (a displaced kernel gets the suffix _disp)."""
+    base, args = kernel[:-1].split("<")
+    s, J, D = args.split(",")
+    return f"{base}_{'f64' if s == 'double' else s}{J}" + ("_disp" if D == "1" else "")
 
 
 def cpu_baseline(cov, pattern, n, seconds_target=15.0):
@@ -102,7 +110,8 @@ def cpu_baseline(cov, pattern, n, seconds_target=15.0):
 
 
 KERNEL_SOURCES = ["paper_1810_00900_amd/csrc/dd.hpp", "paper_1810_00900_amd/csrc/tor_tree.hpp",
-                  "paper_1810_00900_amd/csrc/tor_kernels.hip", "paper_1810_00900_amd/csrc/tor_kernels.h"]
+                  "paper_1810_00900_amd/csrc/tor_wave.hpp", "paper_1810_00900_amd/csrc/tor_kernels.hip",
+                  "paper_1810_00900_amd/csrc/tor_kernels.h"]
 
 
 def measured_fp64(kernel, kernel_ms):
@@ -111,8 +120,7 @@ def measured_fp64(kernel, kernel_ms):
     wave instruction, FMA = 2 flops) over this run's kernel time; None when
     the kernel sources changed since."""
     import hashlib
-    slug = kernel.replace("<", "_").replace(",", "").replace(">", "").replace("double", "f64")
-    path = os.path.join(ROOT, "profiles", f"pmc_fp64_{slug}_m800_n28.json")
+    path = os.path.join(ROOT, "profiles", f"pmc_fp64_{kernel_slug(kernel)}_m800_n28.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -132,8 +140,7 @@ def measured_traffic(kernel):
     rocprofv3 FETCH_SIZE/WRITE_SIZE measurement (profiles/), scaled by the
     copy-kernel calibration; None when the kernel sources changed since."""
     import hashlib
-    slug = kernel.replace("<", "_").replace(",", "").replace(">", "").replace("double", "f64")
-    path = os.path.join(ROOT, "profiles", f"traffic_{slug}_m800_n28.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_slug(kernel)}_m800_n28.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -158,22 +165,29 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes": n * 8}))
 
 
-def per_n_rates(ctx, cov, prec, ns=(20, 24, 28, 32), full=False):
+def per_n_rates(ctx, cov, prec, ns=(20, 24, 28, 32), full=False, mean=None):
     """subset-dets/s of single Torontonians at several n (whole calls).  With
     full=True every other mode is a no-click mode (the full-pattern variant:
-    the same tree after conditioning on the m - n no-click modes)."""
+    the same tree after conditioning on the m - n no-click modes).  With a
+    mean vector the state is displaced (tor_probability_displaced)."""
     import gbs_inputs as gi
     out = {}
+
+    def call(pat):
+        if mean is None:
+            return ctx.probability(cov, pat, prec=prec, tol=1e-8)
+        return ctx.probability_displaced(cov, mean, pat, prec=prec, tol=1e-8)
+
     for n in ns:
         pat = gi.config5_pattern(n).copy()
         if full:
             pat[pat == -1] = 0
         reps = 1 if n >= 32 else 3
-        ctx.probability(cov, pat, prec=prec, tol=1e-8)
+        call(pat)
         ctx.reset_stats()
         t = time.perf_counter()
         for _ in range(reps):
-            r = ctx.probability(cov, pat, prec=prec, tol=1e-8)
+            r = call(pat)
         dt = (time.perf_counter() - t) / reps
         st = ctx.stats()
         out[str(n)] = {"subset_dets_per_s": 2.0 ** n / dt, "ms": dt * 1e3,
@@ -372,7 +386,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np  # noqa: F401
+    import numpy as np
     import gbs_inputs as gi
     import paper_1810_00900_amd as tg
 
@@ -434,6 +448,10 @@ def main():
         out["per_n"] = per_n_rates(ctx, cov, args.prec)
         out["per_n_f64_terms"] = per_n_rates(ctx, cov, "f64")
         out["per_n_full_pattern"] = per_n_rates(ctx, cov, args.prec, ns=(20, 28), full=True)
+        out["per_n_displaced"] = per_n_rates(ctx, cov, args.prec, ns=(20, 24, 28),
+                                             mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
+        out["per_n_displaced_f64_terms"] = per_n_rates(ctx, cov, "f64", ns=(20, 24, 28),
+                                                       mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
         out["sampler"] = sampler_bench(ctx)
         out["paper_worst_case"] = paper_worst_case(ctx)
         out["dense_subgraph"] = dense_subgraph(ctx)

@@ -195,22 +195,50 @@ DD_FN dd dd_div_d(dd a, double b) {
     return o;
 }
 
-// exp(x) of a double-word x (finite, x.hi < 709): x = k ln2 + r with
-// |r| <= ln2 / 2; exp(r / 32) from its Taylor series to degree 14 (Horner,
-// truncation below 1e-41), squared five times, scaled by 2^k.  The squarings
-// amplify the rounding of the series 32-fold: relative error below ~1e-30.
-// Returns 0 below exp(-745).
+// a + b where |b| is far below |a| (no cancellation possible): one TwoSum of
+// the leading words, the trailing words added in binary64 (Dekker's sum).
+DD_FN dd dd_add_small(dd a, dd b) {
+    double s, e;
+    two_sum(a.hi, b.hi, s, e);
+    e += a.lo + b.lo;
+    dd r;
+    fast_two_sum(s, e, r.hi, r.lo);
+    return r;
+}
+
+// exp(x) of a double-word x (finite, x.hi < 709).  Reduction x = k ln2 + r,
+// |r| <= ln2 / 2, t = r / 32.  The expm1 series a = e^t - 1 = sum_{j>=1} t^j/j!
+// is evaluated by Horner: the terms j >= 8 (below 5e-19 relative) in
+// binary64, j <= 7 in double-word with |t s| far below each 1/j! (so the
+// cheaper sum suffices); truncation after j = 12 is below 1e-33 relative.
+// Five doublings e^{2t} - 1 = a (2 + a) keep a's relative precision, then
+// exp(x) = 2^k (1 + a).  Relative error within 2 max(1, |x|) 2^-106 (the
+// conditioning of exp on a double-word argument) for results above 1e-290;
+// below that the trailing word is subnormal.  Returns 0 below exp(-745).
 DD_FN dd dd_exp(dd x) {
     if (x.hi < -745.0) return dd_from(0.0);
     const dd ln2 = dd_make(6.93147180559945286227e-01, 2.31904681384629955842e-17);
     const double k = rint(x.hi / ln2.hi);
-    dd r = dd_add(x, dd_neg(dd_mul_d(ln2, k)));
-    r = dd_make(r.hi * 0.03125, r.lo * 0.03125);
-    dd s = dd_from(1.0);
-    for (int i = 14; i >= 1; --i) s = dd_add(dd_from(1.0), dd_div_d(dd_mul(r, s), (double)i));
-    for (int i = 0; i < 5; ++i) s = dd_mul(s, s);
+    dd t = dd_add(x, dd_neg(dd_mul_d(ln2, k)));
+    t = dd_make(t.hi * 0.03125, t.lo * 0.03125);
+    // 1/j! for j = 2..7 as double-words
+    const double ch[6] = {0.5, 0x1.5555555555555p-3, 0x1.5555555555555p-5, 0x1.1111111111111p-7,
+                          0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13};
+    const double cl[6] = {0.0, 0x1.5555555555555p-57, 0x1.5555555555555p-59, 0x1.1111111111111p-63,
+                          -0x1.f49f49f49f49fp-65, 0x1.a01a01a01a01ap-73};
+    double p = 0x1.1eed8eff8d898p-29;       // 1/12!
+    p = fma(p, t.hi, 0x1.ae64567f544e4p-26);  // 1/11!
+    p = fma(p, t.hi, 0x1.27e4fb7789f5cp-22);  // 1/10!
+    p = fma(p, t.hi, 0x1.71de3a556c734p-19);  // 1/9!
+    p = fma(p, t.hi, 0x1.a01a01a01a01ap-16);  // 1/8!
+    dd s = dd_from(p);
+    for (int j = 5; j >= 0; --j) s = dd_add_small(dd_make(ch[j], cl[j]), dd_mul(t, s));
+    s = dd_add_small(dd_from(1.0), dd_mul(t, s));
+    dd a = dd_mul(t, s);
+    for (int i = 0; i < 5; ++i) a = dd_mul(a, dd_add_small(dd_from(2.0), a));
+    a = dd_add_small(dd_from(1.0), a);
     const int ik = (int)k;
-    return dd_make(ldexp(s.hi, ik), ldexp(s.lo, ik));
+    return dd_make(ldexp(a.hi, ik), ldexp(a.lo, ik));
 }
 
 // binary64 helpers with the same call shape, for the binary64-term tier
