@@ -34,7 +34,13 @@
  * "Memory").  The sum is always accumulated in double-double.  The per-subset
  * factorisation runs in binary64 (TOR_PREC_F64) or in double-double
  * (TOR_PREC_DD); TOR_PREC_AUTO runs binary64 first and repeats in
- * double-double when the a-priori bound exceeds tol.
+ * double-double when the a-priori bound exceeds tol.  TOR_PREC_QD (opt-in,
+ * tor_probability and tor_subset_sum only) runs the no-click conditioning,
+ * the factorisation and the sum in quad-double (about 212 bits): for sums
+ * that cancel beyond double-double, e.g. full patterns conditioned on
+ * hundreds of no-click modes (R ~ 1e36 at n = 28 on 800 modes).  Its trees
+ * use 8-mode wave tasks and need about 5.5 GB of device memory at n = 28
+ * (x 2 per further click).
  *
  * Status codes: 0 = TOR_OK; TOR_WARN_PRECISION (1): result delivered but its
  * error bound exceeds tol; negative values are errors and leave *out
@@ -68,7 +74,7 @@ typedef int32_t tor_status;
 
 #define TOR_MAX_CLICKS 32
 
-typedef enum { TOR_PREC_AUTO = 0, TOR_PREC_F64 = 1, TOR_PREC_DD = 2 } tor_prec;
+typedef enum { TOR_PREC_AUTO = 0, TOR_PREC_F64 = 1, TOR_PREC_DD = 2, TOR_PREC_QD = 3 } tor_prec;
 
 typedef struct tor_ctx tor_ctx;
 typedef struct tor_state tor_state;
@@ -85,7 +91,7 @@ typedef struct {
     double rel_err_bound; /* a-priori relative error bound of p */
     double log_pvac_n;    /* log P_vac(N) */
     int32_t n_clicks;     /* |C| */
-    int32_t prec_used;    /* TOR_PREC_F64 or TOR_PREC_DD */
+    int32_t prec_used;    /* TOR_PREC_F64, TOR_PREC_DD or TOR_PREC_QD */
     int32_t status;       /* per-result status (TOR_OK or TOR_WARN_PRECISION) */
     int32_t reserved;
 } tor_result;

@@ -27,9 +27,9 @@ TOR_ENOMEM = -4
 TOR_EDEVICE = -5
 TOR_EAGAIN = -6
 
-PREC_AUTO, PREC_F64, PREC_DD = 0, 1, 2
-_PREC = {"auto": PREC_AUTO, "f64": PREC_F64, "dd": PREC_DD,
-         PREC_AUTO: PREC_AUTO, PREC_F64: PREC_F64, PREC_DD: PREC_DD}
+PREC_AUTO, PREC_F64, PREC_DD, PREC_QD = 0, 1, 2, 3
+_PREC = {"auto": PREC_AUTO, "f64": PREC_F64, "dd": PREC_DD, "qd": PREC_QD,
+         PREC_AUTO: PREC_AUTO, PREC_F64: PREC_F64, PREC_DD: PREC_DD, PREC_QD: PREC_QD}
 
 OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET, OPT_ASYNC_POOL, OPT_CHAIN_CLICKS = 0, 1, 2, 3, 4, 5
 

@@ -1,0 +1,170 @@
+// Quad-double ("qd") arithmetic on IEEE binary64, host and device.
+//
+// A qd value is an unevaluated sum x0 + x1 + x2 + x3 of binary64 words with
+// |x_{i+1}| <= ulp(x_i) (about 212 significant bits).  Sums and products are
+// formed level by level: level k collects the exact error terms and partial
+// products of order u^k (u = 2^-53) relative to the operands, using the
+// error-free transformations TwoSum and TwoProd (dd.hpp) down to level 2 and
+// plain binary64 sums at levels 3 and 4; a renormalisation then turns the
+// five levels into a non-overlapping expansion.  The design follows the
+// level-accumulation scheme of Hida, Li and Bailey (ARITH 2001) and the
+// expansion renormalisation of Priest (1991), written here from those
+// descriptions.  Error model (checked against mpmath in the CPU tests):
+//   add: |err| <= c u^4 (|a| + |b|),  mul: |err| <= c u^4 |a b|,  c ~ 16.
+// Weak (operand-relative) accuracy is what the subset tree needs: its error
+// bound is relative to the sum of the magnitudes of the terms.
+//
+// Compile with -ffp-contract=off like dd.hpp.
+#pragma once
+
+#include "dd.hpp"
+
+#pragma clang fp contract(off)
+
+struct __align__(16) qd {
+    double x0, x1, x2, x3;
+};
+
+DD_FN qd qd_make(double a, double b, double c, double d) {
+    qd r;
+    r.x0 = a;
+    r.x1 = b;
+    r.x2 = c;
+    r.x3 = d;
+    return r;
+}
+DD_FN qd qd_from(double a) { return qd_make(a, 0.0, 0.0, 0.0); }
+DD_FN qd qd_from_dd(dd a) { return qd_make(a.hi, a.lo, 0.0, 0.0); }
+DD_FN dd qd_to_dd(qd a) {
+    // round the leading two levels together with the rest
+    double s, e;
+    two_sum(a.x0, a.x1 + (a.x2 + a.x3), s, e);
+    return dd_make(s, e);
+}
+DD_FN qd qd_neg(qd a) { return qd_make(-a.x0, -a.x1, -a.x2, -a.x3); }
+
+// Five level sums (|x_k| roughly u^k relative to the leading level, the
+// leading levels possibly cancelled) -> non-overlapping four-word expansion.
+// Two exact bottom-up TwoSum sweeps (each moves the rounded partial sums up
+// and leaves exact errors below) followed by a top-down FastTwoSum sweep that
+// compresses the expansion into four words; only the last word is rounded.
+DD_FN qd qd_renorm5(double x0, double x1, double x2, double x3, double x4) {
+    double s, e1, e2, e3, e4;
+    two_sum(x3, x4, s, e4);
+    two_sum(x2, s, s, e3);
+    two_sum(x1, s, s, e2);
+    two_sum(x0, s, s, e1);
+    // second sweep over (s, e1, e2, e3, e4)
+    double t, f1, f2, f3, f4;
+    two_sum(e3, e4, t, f4);
+    two_sum(e2, t, t, f3);
+    two_sum(e1, t, t, f2);
+    two_sum(s, t, t, f1);
+    // top-down compression of t + f1 + f2 + f3 + f4
+    double r0, r1, r2, r3, c;
+    fast_two_sum(t, f1, r0, c);
+    two_sum(c, f2, r1, c);
+    two_sum(c, f3, r2, c);
+    r3 = c + f4;
+    // make the words non-overlapping after the compression
+    fast_two_sum(r2, r3, r2, r3);
+    fast_two_sum(r1, r2, r1, r2);
+    fast_two_sum(r0, r1, r0, r1);
+    fast_two_sum(r1, r2, r1, r2);
+    fast_two_sum(r2, r3, r2, r3);
+    return qd_make(r0, r1, r2, r3);
+}
+
+// a + b
+DD_FN qd qd_add(qd a, qd b) {
+    double s0, e0, s1, e1, s2, e2, s3, e3;
+    two_sum(a.x0, b.x0, s0, e0);  // level 0 (+ error at level 1)
+    two_sum(a.x1, b.x1, s1, e1);  // level 1 (+ level 2)
+    two_sum(a.x2, b.x2, s2, e2);  // level 2 (+ level 3)
+    two_sum(a.x3, b.x3, s3, e3);  // level 3 (+ level 4)
+    double l1, c1, l2, c2, c3;
+    two_sum(s1, e0, l1, c1);      // level 1, carry to level 2
+    two_sum(s2, e1, l2, c2);      // level 2, carry to level 3
+    two_sum(l2, c1, l2, c3);
+    const double l3 = s3 + e2 + (c2 + c3);
+    return qd_renorm5(s0, l1, l2, l3, e3);
+}
+DD_FN qd qd_sub(qd a, qd b) { return qd_add(a, qd_neg(b)); }
+
+// a * b: partial products a_i b_j of order i + j <= 2 exact (TwoProd), order 3
+// with their rounding, order 4 in binary64; orders >= 5 dropped.
+DD_FN qd qd_mul(qd a, qd b) {
+    double p00, q00;
+    two_prod(a.x0, b.x0, p00, q00);  // order 0, error order 1
+    double p01, q01, p10, q10;
+    two_prod(a.x0, b.x1, p01, q01);  // order 1, errors order 2
+    two_prod(a.x1, b.x0, p10, q10);
+    double p02, q02, p11, q11, p20, q20;
+    two_prod(a.x0, b.x2, p02, q02);  // order 2, errors order 3
+    two_prod(a.x1, b.x1, p11, q11);
+    two_prod(a.x2, b.x0, p20, q20);
+    // level 1: p01 + p10 + q00, carries to level 2
+    double l1, c1, c2;
+    two_sum(p01, p10, l1, c1);
+    two_sum(l1, q00, l1, c2);
+    // level 2: p02 + p11 + p20 + q01 + q10 + c1 + c2, carries to level 3
+    double l2, d1, d2, d3, d4, d5, d6;
+    two_sum(p02, p11, l2, d1);
+    two_sum(l2, p20, l2, d2);
+    two_sum(l2, q01, l2, d3);
+    two_sum(l2, q10, l2, d4);
+    two_sum(l2, c1, l2, d5);
+    two_sum(l2, c2, l2, d6);
+    // level 3: order-3 products and errors, plain sums
+    const double o3 = fma(a.x0, b.x3, fma(a.x1, b.x2, fma(a.x2, b.x1, a.x3 * b.x0)));
+    const double l3 = o3 + ((q02 + q11) + q20) + (((d1 + d2) + (d3 + d4)) + (d5 + d6));
+    // level 4: order-4 products
+    const double l4 = fma(a.x1, b.x3, fma(a.x2, b.x2, a.x3 * b.x1));
+    return qd_renorm5(p00, l1, l2, l3, l4);
+}
+
+// a * b for a binary64 b
+DD_FN qd qd_mul_d(qd a, double b) {
+    double p0, q0, p1, q1, p2, q2;
+    two_prod(a.x0, b, p0, q0);
+    two_prod(a.x1, b, p1, q1);
+    two_prod(a.x2, b, p2, q2);
+    double l1, c1, l2, c2, c3;
+    two_sum(p1, q0, l1, c1);
+    two_sum(p2, q1, l2, c2);
+    two_sum(l2, c1, l2, c3);
+    const double l3 = fma(a.x3, b, q2 + (c2 + c3));
+    return qd_renorm5(p0, l1, l2, l3, 0.0);
+}
+
+// x - a1 b1 - a2 b2 (the rank-2 Schur update of one entry)
+DD_FN qd qd_sub_dot2(qd x, qd a1, qd b1, qd a2, qd b2) {
+    return qd_sub(qd_sub(x, qd_mul(a1, b1)), qd_mul(a2, b2));
+}
+// x - a b
+DD_FN qd qd_sub_mul(qd x, qd a, qd b) { return qd_sub(x, qd_mul(a, b)); }
+// a c - b^2 (2x2 determinant)
+DD_FN qd qd_det2(qd a, qd b, qd c) { return qd_sub(qd_mul(a, c), qd_mul(b, b)); }
+
+// x^-1/2: the double-double estimate, then one Newton step in qd,
+// y <- y + y (1 - x y^2) / 2 (quadratic convergence: 2^-104 -> 2^-207).
+DD_FN qd qd_rsqrt(qd x) {
+    const dd y0 = dd_rsqrt(qd_to_dd(x));
+    const qd y = qd_from_dd(y0);
+    const qd r = qd_sub(qd_from(1.0), qd_mul(x, qd_mul(y, y)));
+    return qd_add(y, qd_mul_d(qd_mul(y, r), 0.5));
+}
+
+// helpers with the call shape of the other scalar tiers
+DD_FN qd sub_dot2(qd x, qd a1, qd b1, qd a2, qd b2) { return qd_sub_dot2(x, a1, b1, a2, b2); }
+DD_FN qd sub_mul(qd x, qd a, qd b) { return qd_sub_mul(x, a, b); }
+DD_FN qd det2(qd a, qd b, qd c) { return qd_det2(a, b, c); }
+DD_FN qd rsqrt_s(qd x) { return qd_rsqrt(x); }
+DD_FN qd mul_s(qd a, qd b) { return qd_mul(a, b); }
+DD_FN double hi_of(qd a) { return a.x0; }
+
+template <> DD_FN qd from_pair<qd>(double h, double l) {
+    double s, e;
+    two_sum(h, l, s, e);
+    return qd_make(s, e, 0.0, 0.0);
+}

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "dd.hpp"
+#include "qd.hpp"
 #include "tor.h"
 #include "tor_kernels.h"
 
@@ -85,6 +86,7 @@ struct DevBuf {
 constexpr double kBoundC = 16.0;
 constexpr double kUF64 = 1.1102230246251565e-16;   // 2^-53
 constexpr double kUDD = 4.930380657631324e-32;     // 2^-104
+constexpr double kUQD = 2.4308653429145085e-63;    // 2^-208 (quad-double terms)
 
 }  // namespace
 
@@ -805,7 +807,8 @@ tor_status prepare(const std::vector<dd> &sig, int n, dd pvac, double log_pvac, 
 // relative error in proportion to x, hence the factor (1 + quad).
 double bound_of(int used, int n, dd T, double A, double quad = 0.0) {
     double R = A / std::fabs(T.hi);
-    return kBoundC * std::max(n, 1) * (used == TOR_PREC_DD ? kUDD : kUF64) * R * (1.0 + quad);
+    const double u = used == TOR_PREC_QD ? kUQD : used == TOR_PREC_DD ? kUDD : kUF64;
+    return kBoundC * std::max(n, 1) * u * R * (1.0 + quad);
 }
 
 // Displaced state: `packed` is the conditioned matrix with its mean row
@@ -861,11 +864,215 @@ void finalize(const Prepared &p, const SumOut &s, int used, double tol, tor_resu
     out->status = out->rel_err_bound <= tol ? TOR_OK : TOR_WARN_PRECISION;
 }
 
+// ------------------------------------------------------------------ quad-double tier
+
+// Subset sum of one packed n-mode matrix in quad-double: the top n - J levels
+// expanded in HBM (slots [coefficient][matrix]), J = min(n, 8)-mode wave
+// tasks, fixed-order reduction stages, one result.
+tor_status gpu_sum_qd(tor_ctx *ctx, const std::vector<qd> &packed, int n, SumOut &out) {
+    if (n == 0) {
+        out = SumOut{};
+        return TOR_OK;
+    }
+    const int J = std::min(n, TOR_QD_TASK_MAX), G = n - J;
+    const long long nt = 1LL << G;
+    const size_t es = sizeof(qd);
+    // pool: root slot, then per level 2^d child slots of E(n - d - 1) + 1 words
+    std::vector<unsigned long long> child_base(G);
+    unsigned long long words = 1 + (unsigned long long)E(n);
+    for (int d = 0; d < G; d++) {
+        child_base[d] = words;
+        words += (1ULL << d) * (unsigned long long)(E(n - d - 1) + 1);
+    }
+    // reduction stages over partials (stage outputs one after another in partB)
+    std::vector<ReduceJobQ> red;
+    std::vector<long long> red_blocks;
+    long long cnt = nt, partB_used = 0;
+    bool in_b = false;
+    long long in_off = 0;
+    struct RS {
+        bool in_b;
+        long long in_off, out_off, count;
+    };
+    std::vector<RS> rs;
+    while (cnt > 1) {
+        const long long nb = (cnt + TOR_REDUCE_CHUNK - 1) / TOR_REDUCE_CHUNK;
+        rs.push_back({in_b, in_off, partB_used, cnt});
+        in_b = true;
+        in_off = partB_used;
+        partB_used += nb;
+        cnt = nb;
+    }
+    const size_t pool_bytes = words * es;
+    const size_t desc_bytes = (size_t)nt * sizeof(NodeDesc);
+    const size_t partA_bytes = (size_t)nt * sizeof(PartialQ);
+    const size_t partB_bytes = (size_t)(partB_used + 1) * sizeof(PartialQ);
+    const size_t off_root = 0;
+    const size_t off_exp = align_up(sizeof(NodeDesc), 64);
+    const size_t off_wave = align_up(off_exp + G * sizeof(ExpandJob), 64);
+    const size_t off_red = align_up(off_wave + sizeof(WaveJob), 64);
+    const size_t job_bytes = off_red + rs.size() * sizeof(ReduceJobQ);
+    if (pool_bytes + 2 * desc_bytes + partA_bytes + partB_bytes + job_bytes > ctx->mem_budget)
+        return fail(TOR_ENOMEM, "a quad-double subset sum of %d modes needs %.2f GB of device memory (budget %.2f GB)",
+                    n, (pool_bytes + 2.0 * desc_bytes + partA_bytes + partB_bytes) / 1e9, ctx->mem_budget / 1e9);
+    if (ctx->pool.ensure(pool_bytes) != hipSuccess || ctx->descA.ensure(desc_bytes) != hipSuccess ||
+        ctx->descB.ensure(desc_bytes) != hipSuccess || ctx->partA.ensure(partA_bytes) != hipSuccess ||
+        ctx->partB.ensure(partB_bytes) != hipSuccess || ctx->jobs.ensure(job_bytes) != hipSuccess)
+        return fail(TOR_ENOMEM, "device allocation of %.2f GB failed", pool_bytes / 1e9);
+    unsigned char *dj = (unsigned char *)ctx->jobs.p;
+    NodeDesc *descA = (NodeDesc *)ctx->descA.p, *descB = (NodeDesc *)ctx->descB.p;
+    PartialQ *partA = (PartialQ *)ctx->partA.p, *partB = (PartialQ *)ctx->partB.p;
+    auto level_ptr = [&](int d) -> NodeDesc * {
+        if (d == 0) return (NodeDesc *)(dj + off_root);
+        return (d & 1) ? descB : descA;
+    };
+    std::vector<unsigned char> hj(job_bytes);
+    const NodeDesc root{1, 1.0, 0.0, 1.0};  // the matrix starts after the coefficient word
+    std::memcpy(hj.data() + off_root, &root, sizeof root);
+    for (int d = 0; d < G; d++) {
+        ExpandJob job{level_ptr(d), level_ptr(d + 1), child_base[d], n - d, 0};
+        std::memcpy(hj.data() + off_exp + d * sizeof(ExpandJob), &job, sizeof job);
+    }
+    const WaveJob wj{level_ptr(G), (Partial *)partA, 0};
+    std::memcpy(hj.data() + off_wave, &wj, sizeof wj);
+    for (size_t k = 0; k < rs.size(); k++) {
+        ReduceJobQ job{(rs[k].in_b ? partB : partA) + rs[k].in_off, partB + rs[k].out_off, rs[k].count, 0};
+        std::memcpy(hj.data() + off_red + k * sizeof(ReduceJobQ), &job, sizeof job);
+    }
+    // root slot: coefficient 1, then the matrix
+    std::vector<qd> root_words(1 + (size_t)E(n));
+    root_words[0] = qd_from(1.0);
+    for (long long e = 0; e < E(n); e++) root_words[1 + (size_t)e] = packed[(size_t)e];
+    hipStream_t st = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(ctx->pool.p, root_words.data(), root_words.size() * es, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dj, hj.data(), job_bytes, hipMemcpyHostToDevice, st));
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[0], st));
+    for (int d = 0; d < G; d++)
+        HIP_TRY(tor_launch_expand_qd((const ExpandJob *)(dj + off_exp) + d, 1, d, ctx->pool.p, 1 << 20, st));
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[1], st));
+    HIP_TRY(tor_launch_wave_qd(J, (const WaveJob *)(dj + off_wave), 1, nt, ctx->pool.p, ctx->wave_grid, st));
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[2], st));
+    for (size_t k = 0; k < rs.size(); k++)
+        HIP_TRY(tor_launch_reduce_qd((const ReduceJobQ *)(dj + off_red) + k, 1,
+                                     (rs[k].count + TOR_REDUCE_CHUNK - 1) / TOR_REDUCE_CHUNK, st));
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[3], st));
+    PartialQ res;
+    const PartialQ *src = rs.empty() ? partA : partB + (partB_used - 1);
+    HIP_TRY(hipMemcpyAsync(&res, src, sizeof res, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ctx->timing) {
+        ctx->stats.expand_ms += elapsed(ctx->ev[0], ctx->ev[1]);
+        ctx->stats.wave_ms += elapsed(ctx->ev[1], ctx->ev[2]);
+        ctx->stats.reduce_ms += elapsed(ctx->ev[2], ctx->ev[3]);
+    }
+    ctx->stats.expand_launches += G;
+    ctx->stats.wave_launches += 1;
+    ctx->stats.reduce_launches += (int64_t)rs.size();
+    ctx->stats.subsets += std::ldexp(1.0, n);
+    out.T = qd_to_dd(qd_make(res.t0, res.t1, res.t2, res.t3));
+    out.A = res.a;
+    return TOR_OK;
+}
+
+// Vacuum conditioning of one reduced pattern (r.cond set) in quad-double, one
+// two-kernel step per no-click mode; returns the conditioned leading block.
+tor_status condition_qd(tor_ctx *ctx, const Reduced &r, std::vector<qd> &sigc, dd &pvac, double &log_pvac) {
+    const int n = r.n, k = r.k;
+    const size_t words = r.packed.size();
+    const size_t cols_off = align_up(words * sizeof(qd), 256);
+    const size_t cols_words = 2 * (2 * (size_t)(n + k) - 2) + 2;
+    const size_t acc_off = align_up(cols_off + cols_words * sizeof(qd), 256);
+    const size_t job_off = align_up(acc_off + 3 * sizeof(double), 256);
+    const size_t total_bytes = job_off + (size_t)k * sizeof(CondJobQ);
+    if (total_bytes > ctx->mem_budget)
+        return fail(TOR_ENOMEM, "conditioning needs %.2f GB of device memory", total_bytes / 1e9);
+    if (ctx->cond.ensure(total_bytes) != hipSuccess)
+        return fail(TOR_ENOMEM, "device allocation of %.2f GB failed", total_bytes / 1e9);
+    unsigned char *db = (unsigned char *)ctx->cond.p;
+    std::vector<unsigned char> stage(total_bytes);
+    qd *hm = (qd *)stage.data();
+    for (size_t e = 0; e < words; e++) hm[e] = qd_from_dd(r.packed[e]);
+    const double a0[3] = {1.0, 0.0, 0.0};
+    std::memcpy(stage.data() + acc_off, a0, sizeof a0);
+    std::vector<long long> blocks(k);
+    for (int t = 0; t < k; t++) {
+        CondJobQ j{};
+        j.mat = db;
+        j.acc = (double *)(db + acc_off);
+        j.cols = db + cols_off;
+        j.r = n + k - t;
+        j.begin = 0;
+        blocks[t] = std::max<long long>(1, (E(j.r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
+        std::memcpy(stage.data() + job_off + t * sizeof(CondJobQ), &j, sizeof j);
+    }
+    hipStream_t st = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(db, stage.data(), total_bytes, hipMemcpyHostToDevice, st));
+    for (int t = 0; t < k; t++)
+        HIP_TRY(tor_launch_condition_qd((const CondJobQ *)(db + job_off) + t, 1, blocks[t], st));
+    sigc.assign((size_t)E(n), qd_from(0.0));
+    double acc[3];
+    HIP_TRY(hipMemcpyAsync(sigc.data(), db, (size_t)E(n) * sizeof(qd), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(acc, db + acc_off, sizeof acc, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    ctx->stats.condition_launches += 2 * (int64_t)k;
+    pvac = dd_make(acc[0], acc[1]);
+    log_pvac = acc[2];
+    return TOR_OK;
+}
+
+// Probability of one pattern with quad-double terms (conditioning included).
+tor_status probability_qd(tor_ctx *ctx, const double *cov, int m, const int8_t *pattern, double tol,
+                          tor_result *out) {
+    Reduced red;
+    tor_status s = reduce_pattern(cov, m, pattern, red);
+    if (s) return s;
+    std::vector<qd> sigc;
+    Prepared p;
+    p.n = red.n;
+    if (red.cond) {
+        s = condition_qd(ctx, red, sigc, p.pvac, p.log_pvac);
+        if (s) return s;
+    } else {
+        const int dc = 2 * red.n;
+        sigc.assign((size_t)E(red.n), qd_from(0.0));
+        for (int a = 0; a < dc; a++)
+            for (int b = 0; b <= a; b++) sigc[(size_t)pidx(a, b)] = qd_from_dd(red.sig[(size_t)a * dc + b]);
+    }
+    if (red.n > 0) {  // PD check and log det from the binary64 rounding
+        const int dc = 2 * red.n;
+        std::vector<dd> full((size_t)dc * dc);
+        for (int a = 0; a < dc; a++)
+            for (int b = 0; b <= a; b++) {
+                const dd v = qd_to_dd(sigc[(size_t)pidx(a, b)]);
+                full[(size_t)a * dc + b] = v;
+                full[(size_t)b * dc + a] = v;
+            }
+        if (!f64_cholesky_logdet(full, dc, &p.log_det)) return fail(TOR_ENOTPD, "Sigma_C is not positive definite");
+    }
+    SumOut so;
+    s = gpu_sum_qd(ctx, sigc, red.n, so);
+    if (s) return s;
+    if (!std::isfinite(so.T.hi) || !std::isfinite(so.A)) {
+        std::memset(out, 0, sizeof *out);
+        out->status = TOR_ENOTPD;
+        return fail(TOR_ENOTPD, "a Schur pivot was not positive (non-physical or near-singular covariance)");
+    }
+    if (!(tol > 0.0)) tol = 1e-10;
+    finalize(p, so, TOR_PREC_QD, tol, out);
+    return out->status;
+}
+
 // Evaluate prepared queries with the precision policy; results in out[i].
 // Queries whose preparation failed keep their error status.
 tor_status evaluate_many(tor_ctx *ctx, std::vector<Prepared> &qs, tor_prec prec, double tol, tor_result *out) {
-    if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD)
-        return fail(TOR_EINVAL, "bad precision %d", (int)prec);
+    if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD) {
+        for (size_t i = 0; i < qs.size(); i++) {  // every result carries the error
+            std::memset(&out[i], 0, sizeof out[i]);
+            out[i].status = TOR_EINVAL;
+        }
+        return fail(TOR_EINVAL, "precision %d is not supported here (TOR_PREC_QD: tor_probability and "
+                                "tor_subset_sum only)", (int)prec);
+    }
     if (!(tol > 0.0)) tol = 1e-10;
     std::vector<SumIn> in(qs.size());
     std::vector<int> ok;
@@ -1035,6 +1242,7 @@ tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int
     if (s) return s;
     HIP_TRY(hipSetDevice(ctx->device));
     if (!out) return fail(TOR_EINVAL, "out is NULL");
+    if (prec == TOR_PREC_QD) return probability_qd(ctx, cov, m, pattern, tol, out);
     Reduced red;
     s = reduce_pattern(cov, m, pattern, red);
     if (s) return s;
@@ -1090,6 +1298,17 @@ tor_status tor_subset_sum(tor_ctx *ctx, const double *sigma_hi, const double *si
     std::vector<Prepared> qs(1);
     tor_status s = prepare(sig, n, dd_from(1.0), 0.0, qs[0]);
     if (s) return s;
+    if (prec == TOR_PREC_QD) {
+        std::vector<qd> pk((size_t)E(n));
+        for (int a = 0; a < 2 * n; a++)
+            for (int b = 0; b <= a; b++) pk[(size_t)pidx(a, b)] = qd_from_dd(sig[(size_t)a * 2 * n + b]);
+        SumOut so;
+        s = gpu_sum_qd(ctx, pk, n, so);
+        if (s) return s;
+        if (!(tol > 0.0)) tol = 1e-10;
+        finalize(qs[0], so, TOR_PREC_QD, tol, out);
+        return out->status;
+    }
     return evaluate_many(ctx, qs, prec, tol, out);
 }
 

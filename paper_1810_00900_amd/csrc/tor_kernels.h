@@ -135,6 +135,43 @@ hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_b
 hipError_t tor_launch_gather(const Partial *const *src, int n, Partial *dst, hipStream_t st);
 hipError_t tor_launch_condition(const CondJob *jobs, int njobs, long long total_blocks, int rmax, hipStream_t st);
 
+// ---- quad-double term tier (one tree per launch sequence)
+// Pool layout: every node slot is [path coefficient (one qd)][packed matrix],
+// a descriptor's off points at the matrix, so the coefficient is pool[off - 1]
+// (the exclude child shares its parent's slot and coefficient).
+#define TOR_QD_TASK_MAX 8  // modes per wave-tier task (two-mode register leaf)
+
+struct PartialQ {
+    double t0, t1, t2, t3, a, pad0, pad1, pad2;
+};
+
+struct ReduceJobQ {
+    const PartialQ *in;
+    PartialQ *out;
+    long long count;
+    long long block_begin;
+};
+
+// one vacuum-conditioning step of one query in quad-double: mat (r modes,
+// packed lower) loses its last mode; cols is scratch for the two scaled pivot
+// columns (2 (2r - 2) words); acc as in CondJob.
+struct CondJobQ {
+    void *mat;
+    double *acc;
+    void *cols;
+    long long begin;
+    int r;
+    int pad;
+};
+
+hipError_t tor_launch_wave_qd(int J, const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
+                              hipStream_t st);
+hipError_t tor_launch_expand_qd(const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
+                                hipStream_t st);
+hipError_t tor_launch_reduce_qd(const ReduceJobQ *jobs, int njobs, long long total_blocks, hipStream_t st);
+// one conditioning step: the pivot columns of every job, then the update
+hipError_t tor_launch_condition_qd(const CondJobQ *jobs, int njobs, long long total_blocks, hipStream_t st);
+
 // ---- chain-rule sampler
 #define TOR_CHAIN_MAX 16      // step-tree cap of the compact sampler kernel (clicks so far + 1)
 #define TOR_CHAIN_MAX_BIG 21  // step-tree cap of the large sampler kernel (up to 20 clicks)

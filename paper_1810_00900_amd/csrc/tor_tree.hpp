@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dd.hpp"
+#include "qd.hpp"
 #include "tor_kernels.h"
 
 #pragma clang fp contract(off)
@@ -94,15 +95,41 @@ __device__ __forceinline__ Pivot<S> make_pivot_m(const S *M, int p0, int p1) {
     return pv;
 }
 
+// Signed sums and path coefficients: double-double for the binary64 and
+// double-double term tiers, quad-double for the quad-double tier.  The
+// acc_* overloads give the tree code one spelling for both.
+template <class S> struct AccOf { using type = dd; };
+template <> struct AccOf<qd> { using type = qd; };
+
 __device__ __forceinline__ dd coef_mul(dd c, double q) { return dd_mul_d(c, q); }
 __device__ __forceinline__ dd coef_mul(dd c, dd q) { return dd_mul(c, q); }
+__device__ __forceinline__ qd coef_mul(qd c, qd q) { return qd_mul(c, q); }
+
+template <class A> __device__ __forceinline__ A acc_const(double x);
+template <> __device__ __forceinline__ dd acc_const<dd>(double x) { return dd_from(x); }
+template <> __device__ __forceinline__ qd acc_const<qd>(double x) { return qd_from(x); }
+__device__ __forceinline__ dd acc_neg(dd a) { return dd_neg(a); }
+__device__ __forceinline__ qd acc_neg(qd a) { return qd_neg(a); }
+__device__ __forceinline__ dd acc_mul(dd a, dd b) { return dd_mul(a, b); }
+__device__ __forceinline__ qd acc_mul(qd a, qd b) { return qd_mul(a, b); }
+__device__ __forceinline__ dd acc_add(dd a, dd b) { return dd_add(a, b); }
+__device__ __forceinline__ qd acc_add(qd a, qd b) { return qd_add(a, b); }
+// T0 - q T1
+__device__ __forceinline__ dd acc_sub_mul(dd t0, double q, dd t1) { return dd_sub_mul(t0, q, t1); }
+__device__ __forceinline__ dd acc_sub_mul(dd t0, dd q, dd t1) { return dd_sub_mul(t0, q, t1); }
+__device__ __forceinline__ qd acc_sub_mul(qd t0, qd q, qd t1) { return qd_sub(t0, qd_mul(q, t1)); }
+// 1 - q
+__device__ __forceinline__ dd acc_one_minus(double q) { return dd_sub(dd_from(1.0), to_dd(q)); }
+__device__ __forceinline__ dd acc_one_minus(dd q) { return dd_sub(dd_from(1.0), to_dd(q)); }
+__device__ __forceinline__ qd acc_one_minus(qd q) { return qd_sub(qd_from(1.0), q); }
 
 // ---------------------------------------------------------------- leaf tier
 
 template <class S, int R, int D = 0> struct Leaf {
-    static __device__ __forceinline__ void run(const S *M, dd &T, double &A) {
+    using Acc = typename AccOf<S>::type;
+    static __device__ __forceinline__ void run(const S *M, Acc &T, double &A) {
         constexpr int p0 = 2 * R - 2 + D, p1 = 2 * R - 1 + D, RC = 2 * R - 2 + D;
-        dd T0;
+        Acc T0;
         double A0;
         Leaf<S, R - 1, D>::run(M, T0, A0);  // exclude: the prefix of M
         Pivot<S> pv = make_pivot_m<S, D>(M, p0, p1);
@@ -119,27 +146,29 @@ template <class S, int R, int D = 0> struct Leaf {
 #pragma unroll
             for (int b = 0; b <= a; ++b)
                 C[pidx(a, b)] = sub_dot2(M[pidx(a, b)], v1[a], v1[b], v2[a], v2[b]);
-        dd T1;
+        Acc T1;
         double A1;
         Leaf<S, R - 1, D>::run(C, T1, A1);
-        T = dd_sub_mul(T0, pv.q, T1);
+        T = acc_sub_mul(T0, pv.q, T1);
         A = A0 + hi_of(pv.q) * A1;
     }
 };
 
 template <class S, int D> struct Leaf<S, 1, D> {
-    static __device__ __forceinline__ void run(const S *M, dd &T, double &A) {
+    using Acc = typename AccOf<S>::type;
+    static __device__ __forceinline__ void run(const S *M, Acc &T, double &A) {
         S q;
         if constexpr (D == 0) q = rsqrt_s(det2(M[0], M[1], M[2]));
         else q = make_pivot_m<S, 1>(M, 1, 2).q;
-        T = dd_sub(dd_from(1.0), to_dd(q));
+        T = acc_one_minus(q);
         A = 1.0 + hi_of(q);
     }
 };
 
 template <class S, int D> struct Leaf<S, 0, D> {
-    static __device__ __forceinline__ void run(const S *, dd &T, double &A) {
-        T = dd_from(1.0);
+    using Acc = typename AccOf<S>::type;
+    static __device__ __forceinline__ void run(const S *, Acc &T, double &A) {
+        T = acc_const<Acc>(1.0);
         A = 1.0;
     }
 };
@@ -161,10 +190,26 @@ __device__ __forceinline__ void wave_reduce(dd &T, double &A) {
     }
 }
 
+__device__ __forceinline__ void wave_reduce(qd &T, double &A) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        qd o = qd_make(shfl_xor_d(T.x0, m), shfl_xor_d(T.x1, m), shfl_xor_d(T.x2, m), shfl_xor_d(T.x3, m));
+        double oa = shfl_xor_d(A, m);
+        bool low = (threadIdx.x & m) == 0;
+        T = low ? qd_add(T, o) : qd_add(o, T);
+        A = low ? A + oa : oa + A;
+    }
+}
+
 // ---------------------------------------------------------------- wave tier
 
+// Modes of the per-lane register leaf: three (binary64, double-double), two
+// for quad-double terms (a three-mode leaf does not fit the register file).
+template <class S> struct LeafModes { static constexpr int value = 3; };
+template <> struct LeafModes<qd> { static constexpr int value = 2; };
+
 template <class S, int J, int D = 0> struct WaveCfg {
-    static constexpr int TL = J < 3 ? J : 3;    // leaf modes (per lane, registers)
+    static constexpr int TL = J < LeafModes<S>::value ? J : LeafModes<S>::value;  // leaf modes (registers)
     static constexpr int TW = J - TL;           // levels above the leaves
     static constexpr int TWC = TW > 0 ? TW - 1 : 0;  // levels expanded cooperatively in LDS
     static constexpr int NN = 1 << TWC;         // nodes after the cooperative levels
@@ -195,8 +240,9 @@ __host__ __device__ constexpr int ab_n(int D) { return EN(8, D); }
 
 template <class S, int J, int K, int D = 0> struct WaveLevel {
     using C = WaveCfg<S, J, D>;
+    using Acc = typename AccOf<S>::type;
     static __device__ __forceinline__ void run(const unsigned short *ab, S *mat, S *vbuf, Pivot<S> *piv, int *loc,
-                                               dd *coef, double *acoef, int lane) {
+                                               Acc *coef, double *acoef, int lane) {
         if constexpr (K < C::TWC) {
             constexpr int r = J - K, R = 2 * r + D, NK = 1 << K, RC = R - 2, EC = EN(r - 1, D);
             // phase 0: pivot of each node, coefficients and slots of the include children
@@ -204,7 +250,7 @@ template <class S, int J, int K, int D = 0> struct WaveLevel {
                 const S *base = mat + loc[lane];
                 Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
                 piv[lane] = pv;
-                coef[NK + lane] = dd_neg(coef_mul(coef[lane], pv.q));
+                coef[NK + lane] = acc_neg(coef_mul(coef[lane], pv.q));
                 acoef[NK + lane] = acoef[lane] * hi_of(pv.q);
                 loc[NK + lane] = C::soff(K) + lane * EC;
             }
@@ -285,7 +331,7 @@ template <class S, int J, int D = 0> struct WaveSmem {
     S vbuf[C::VMAX];
     Pivot<S> piv[C::NPIV];
     int loc[C::NN];
-    dd coef[C::NN];
+    typename AccOf<S>::type coef[C::NN];
     double acoef[C::NN];
 };
 
@@ -309,8 +355,10 @@ __device__ __forceinline__ void wave_tree_init(unsigned short *ab, int lane) {
 // (T, A) (zero for lanes >= NL).  Lane bit 0 is the decision on the node's last
 // mode (1 = included) when J > TL.  Must be called by all 64 lanes.
 template <class S, int J, int D = 0>
-__device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, dd c, double a, int lane, dd &T, double &A) {
+__device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, typename AccOf<S>::type c, double a, int lane,
+                                          typename AccOf<S>::type &T, double &A) {
     using C = WaveCfg<S, J, D>;
+    using Acc = typename AccOf<S>::type;
     if (lane == 0) {
         sm.loc[0] = 0;
         sm.coef[0] = c;
@@ -318,17 +366,17 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, dd c, double a,
     }
     wave_sync();
     WaveLevel<S, J, 0, D>::run(sm.ab, sm.mat, sm.vbuf, sm.piv, sm.loc, sm.coef, sm.acoef, lane);
-    T = dd_from(0.0);
+    T = acc_const<Acc>(0.0);
     A = 0.0;
     if constexpr (C::TW == 0) {
         if (lane == 0) {
             S M[EN(C::TL, D)];
 #pragma unroll
             for (int e = 0; e < EN(C::TL, D); ++e) M[e] = sm.mat[e];
-            dd Tl;
+            Acc Tl;
             double Al;
             Leaf<S, C::TL, D>::run(M, Tl, Al);
-            T = dd_mul(c, Tl);
+            T = acc_mul(c, Tl);
             A = a * Al;
         }
     } else {
@@ -356,16 +404,16 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, dd c, double a,
             for (int x = 0; x < RC; ++x)
 #pragma unroll
                 for (int y = 0; y <= x; ++y) Ml[pidx(x, y)] = sub_dot2(M[pidx(x, y)], v1[x], v1[y], v2[x], v2[y]);
-            dd cl = sm.coef[i];
+            Acc cl = sm.coef[i];
             double al = sm.acoef[i];
             if (inc) {
-                cl = dd_neg(coef_mul(cl, pv.q));
+                cl = acc_neg(coef_mul(cl, pv.q));
                 al *= hi_of(pv.q);
             }
-            dd Tl;
+            Acc Tl;
             double Al;
             Leaf<S, C::TL, D>::run(Ml, Tl, Al);
-            T = dd_mul(cl, Tl);
+            T = acc_mul(cl, Tl);
             A = al * Al;
         }
     }

@@ -1,0 +1,177 @@
+"""Quad-double term tier (TOR_PREC_QD): conditioning, factorisation and sums in
+quad-double, for alternating sums that cancel beyond double-double.
+
+Exact references come from closed forms whose cancellation ratio R is set by
+construction (R = prod (1 + q_k) / (1 - q_k) for a product state):
+* product states, marginal and full patterns, up to n = 28 clicks on 800
+  modes (R ~ 1e15 - 1e37): double-double must flag its bound, quad-double
+  must match the exact product to far below 1e-10;
+* lossy two-mode squeezed pairs with the partner of every clicked mode a
+  no-click mode (correlated conditioning in quad-double);
+* a Haar-random mixing state against the binary128 oracle, and quad-double
+  against double-double wherever the latter's bound is small.
+"""
+import numpy as np
+import pytest
+
+import gbs_inputs as gi
+import oracle
+import paper_1810_00900_amd as tg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tg.Context(0)
+    yield c
+    c.close()
+
+
+def _mp_val(r):
+    import mpmath as mp
+    return mp.mpf(r.p) + mp.mpf(r.p_lo)
+
+
+def _pvac_block(block):
+    """det(block + I/2)^-1/2 in mpmath (60 digits) from the binary64 entries."""
+    import mpmath as mp
+    mp.mp.dps = 60
+    k = block.shape[0]
+    M = mp.matrix([[mp.mpf(float(block[a, b])) + (mp.mpf(1) / 2 if a == b else 0) for b in range(k)]
+                   for a in range(k)])
+    return 1 / mp.sqrt(mp.det(M))
+
+
+def _product_state(m, rng, r_lo=0.4, r_hi=0.6):
+    blocks = [gi.single_mode_covariance(rng.uniform(r_lo, r_hi), rng.uniform(0, np.pi), rng.uniform(0.0, 0.05))
+              for _ in range(m)]
+    return gi.direct_sum(blocks), blocks
+
+
+def _product_exact(blocks, pat):
+    import mpmath as mp
+    mp.mp.dps = 60
+    p = mp.mpf(1)
+    R = mp.mpf(1)
+    for k, v in enumerate(pat):
+        if v < 0:
+            continue
+        q = _pvac_block(blocks[k])
+        if v == 1:
+            p *= 1 - q
+            R *= (1 + q) / (1 - q)
+        else:
+            p *= q
+    return p, R
+
+
+def _rel(r, want):
+    import mpmath as mp
+    return abs(float((_mp_val(r) - want) / want))
+
+
+@pytest.mark.parametrize("m,n,full", [(30, 12, False), (30, 12, True), (40, 20, False), (40, 20, True),
+                                      (800, 28, True)])
+def test_product_state_beyond_double_double(ctx, m, n, full):
+    rng = np.random.default_rng(200 + m + n + full)
+    cov, blocks = _product_state(m, rng)
+    clicks = sorted(rng.choice(m, n, replace=False).tolist())
+    if full and m == 800:
+        pat = np.full(m, -1, np.int8)
+        pat[clicks] = 1
+        others = [i for i in range(m) if pat[i] != 1]
+        pat[others[::2]] = 0  # 386 no-click modes
+    else:
+        pat = gi.full_pattern(m, clicks) if full else gi.marginal_pattern(m, clicks)
+    want, R = _product_exact(blocks, pat)
+    r = ctx.probability(cov, pat, prec="qd", tol=1e-10)
+    assert r.prec_used == tg.PREC_QD
+    assert _rel(r, want) <= 1e-10, (_rel(r, want), r.rel_err_bound, float(R))
+    assert r.rel_err_bound <= 1e-10
+    assert r.cancel_ratio == pytest.approx(float(R), rel=1e-6)
+    assert r.status == tg.TOR_OK
+    if n >= 20:
+        d = ctx.probability(cov, pat, prec="dd", tol=1e-10)
+        assert d.rel_err_bound > 1e-10 and d.status == tg.TOR_WARN_PRECISION
+        # the dd result is as wrong as its bound allows, never more
+        assert _rel(d, want) <= d.rel_err_bound
+
+
+def test_lossy_tmsv_pairs_conditioned_in_qd(ctx):
+    """Pairs (2i, 2i+1) of lossy two-mode squeezed vacua; for 16 pairs one mode
+    clicks and its partner is a no-click mode: P = prod (P_vac(b) - P_vac(a, b))."""
+    import mpmath as mp
+    rng = np.random.default_rng(230)
+    npairs = 24
+    blocks = []
+    for _ in range(npairs):
+        blocks.append(gi.apply_loss(gi.tmsv_covariance(rng.uniform(0.3, 0.6)), rng.uniform(0.9, 0.98)))
+    cov = np.zeros((4 * npairs, 4 * npairs))
+    for i, b in enumerate(blocks):
+        cov[4 * i:4 * i + 4, 4 * i:4 * i + 4] = b
+    m = 2 * npairs
+    pat = np.full(m, -1, np.int8)
+    want = mp.mpf(1)
+    R = mp.mpf(1)
+    for i in range(16):
+        a, b = (2 * i, 2 * i + 1) if i % 2 == 0 else (2 * i + 1, 2 * i)
+        pat[a], pat[b] = 1, 0
+        pb = _pvac_block(blocks[i][2 * (b % 2):2 * (b % 2) + 2, 2 * (b % 2):2 * (b % 2) + 2])
+        pab = _pvac_block(blocks[i])
+        want *= pb - pab
+        R *= (pb + pab) / (pb - pab)
+    r = ctx.probability(cov, pat, prec="qd", tol=1e-10)
+    assert _rel(r, want) <= 1e-10, (_rel(r, want), r.rel_err_bound, float(R))
+    assert r.rel_err_bound <= 1e-10
+    d = ctx.probability(cov, pat, prec="dd", tol=1e-10)
+    assert _rel(d, want) <= max(d.rel_err_bound, 1e-30)
+
+
+@pytest.mark.parametrize("seed", [240, 241])
+def test_mixing_state_against_oracle_and_dd(ctx, seed):
+    m = 14
+    rng = np.random.default_rng(seed)
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), np.full(m, 0.5))
+    pats = [gi.marginal_pattern(m, [0, 2, 3, 5, 7, 8, 11, 13]),
+            gi.full_pattern(m, [1, 4, 6, 9, 10, 12]),
+            gi.full_pattern(m, list(range(10))),
+            np.array([1, 0, -1, 1, 1, 0, -1, 1, 0, 1, 1, -1, 0, 1], np.int8)]
+    for pat in pats:
+        o = oracle.prob(cov, pat)
+        want = o.p + o.p_lo
+        q = ctx.probability(cov, pat, prec="qd")
+        d = ctx.probability(cov, pat, prec="dd")
+        # binary128 oracle: rounding ~1e-34 R
+        tol_o = max(1e-20, 1e-32 * o.cancel_ratio)
+        assert abs((q.p + q.p_lo) - want) <= tol_o * abs(want), (pat.tolist(), q.p, want)
+        assert abs((q.p + q.p_lo) - (d.p + d.p_lo)) <= max(d.rel_err_bound, 1e-30) * abs(want)
+        assert q.n_clicks == d.n_clicks and q.log_pvac_n == pytest.approx(d.log_pvac_n, rel=1e-14)
+
+
+@pytest.mark.parametrize("n", [1, 5, 8, 9, 14])
+def test_subset_sum_qd_matches_dd(ctx, n):
+    """tor_subset_sum: every tier boundary (n <= 8 is one wave task; above, HBM
+    levels); SPD input with moderate cancellation."""
+    rng = np.random.default_rng(250 + n)
+    m = 3 * n
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), np.full(m, 0.4))
+    idx = [q for k in range(n) for q in (2 * k, 2 * k + 1)]
+    sig = cov[np.ix_(idx, idx)] + 0.5 * np.eye(2 * n)
+    q = ctx.subset_sum(sig, prec="qd")
+    d = ctx.subset_sum(sig, prec="dd")
+    assert q.prec_used == tg.PREC_QD
+    assert abs((q.T + q.T_lo) - (d.T + d.T_lo)) <= max(d.rel_err_bound, 1e-31) * abs(d.T)
+    assert q.abs_sum == pytest.approx(d.abs_sum, rel=1e-14)
+
+
+def test_qd_rejected_where_not_supported(ctx):
+    cov = 0.5 * np.eye(4)
+    st = ctx.state(cov)
+    with pytest.raises(tg.TorError) as ei:
+        ctx.batch(st, np.array([[1, 0]], np.int8), prec="qd")
+    assert ei.value.status == tg.TOR_EINVAL
+    st.close()
+    with pytest.raises(tg.TorError) as ei:
+        ctx.probability_displaced(cov, np.zeros(4), np.array([1, 0], np.int8), prec="qd")
+    assert ei.value.status == tg.TOR_EINVAL
