@@ -212,8 +212,8 @@ DD_FN dd dd_add_small(dd a, dd b) {
 // binary64, j <= 7 in double-word with |t s| far below each 1/j! (so the
 // cheaper sum suffices); truncation after j = 12 is below 1e-33 relative.
 // Five doublings e^{2t} - 1 = a (2 + a) keep a's relative precision, then
-// exp(x) = 2^k (1 + a).  Relative error within 2 max(1, |x|) 2^-106 (the
-// conditioning of exp on a double-word argument) for results above 1e-290;
+// exp(x) = 2^k (1 + a).  Relative error within 4 max(1, |x|) 2^-106 (about
+// the conditioning of exp on a double-word argument) for results above 1e-290;
 // below that the trailing word is subnormal.  Returns 0 below exp(-745).
 DD_FN dd dd_exp(dd x) {
     if (x.hi < -745.0) return dd_from(0.0);

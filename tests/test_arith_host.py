@@ -1,0 +1,94 @@
+"""Host build of the kernels' extended-precision arithmetic (csrc/dd.hpp,
+csrc/qd.hpp) against mpmath at 120 digits: quad-double add (including
+cancellation at every level), mul, rsqrt, the fused Schur update and the
+rounding to double-double; the double-double exp of the displaced tier.
+Bounds: |err| <= c u^4 (|a| + |b|) for sums, c u^4 |result| for products
+(u = 2^-53, c = 16), 4 max(1, |x|) 2^-106 relative for exp."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lines(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("arith") / "arith_check")
+    subprocess.run([hipcc, "-O2", "-ffp-contract=off", "--offload-arch=gfx950", "-Wno-unused-command-line-argument",
+                    "-I", os.path.join(ROOT, "paper_1810_00900_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "arith_check.cpp"), "-o", exe],
+                   check=True, capture_output=True)
+    out = subprocess.run([exe, "3500"], check=True, capture_output=True, text=True).stdout
+    return [ln.split() for ln in out.splitlines()]
+
+
+def _q(words):
+    import mpmath as mp
+    return sum(mp.mpf(float.fromhex(w)) for w in words)
+
+
+def _nonoverlapping(words):
+    v = [abs(float.fromhex(w)) for w in words]
+    return all(v[i + 1] <= v[i] * 2.3e-16 or v[i + 1] == 0 for i in range(len(v) - 1))
+
+
+def test_quad_double_against_mpmath(lines):
+    import mpmath as mp
+    mp.mp.dps = 120
+    u4 = mp.mpf(2) ** -212
+    worst = {}
+    for f in lines:
+        kind, w = int(f[0]), f[1:]
+        if kind in (0, 1):
+            a, b, r = _q(w[0:4]), _q(w[4:8]), _q(w[8:12])
+            err = abs(r - (a + b)) / ((abs(a) + abs(b)) * u4)
+            assert _nonoverlapping(w[8:12])
+        elif kind == 2:
+            a, b, r = _q(w[0:4]), _q(w[4:8]), _q(w[8:12])
+            err = abs(r - a * b) / (abs(a * b) * u4)
+            assert _nonoverlapping(w[8:12])
+        elif kind == 3:
+            x, r = _q(w[0:4]), _q(w[4:8])
+            err = abs(r - 1 / mp.sqrt(x)) * mp.sqrt(x) / u4
+        elif kind == 4:
+            c, a, b, r = _q(w[0:4]), _q(w[4:8]), _q(w[8:12]), _q(w[12:16])
+            err = abs(r - (c - 2 * a * b)) / ((abs(c) + 2 * abs(a * b)) * u4)
+        else:
+            continue
+        worst[kind] = max(worst.get(kind, 0), float(err))
+    assert set(worst) == {0, 1, 2, 3, 4}
+    for kind, e in worst.items():
+        # rsqrt: one Newton step from the double-double estimate, 1.5 e^2
+        assert e <= (64 if kind == 3 else 16), (kind, e)
+
+
+def test_quad_double_rounding_to_double_double(lines):
+    import mpmath as mp
+    mp.mp.dps = 120
+    for f in lines:
+        if int(f[0]) != 6:
+            continue
+        a, r = _q(f[1:5]), _q(f[5:7])
+        assert abs(r - a) <= abs(a) * mp.mpf(2) ** -104
+
+
+def test_double_double_exp_against_mpmath(lines):
+    import mpmath as mp
+    mp.mp.dps = 120
+    n = 0
+    for f in lines:
+        if int(f[0]) != 5:
+            continue
+        x = _q(f[1:3])
+        r = _q(f[3:5])
+        want = mp.exp(x)
+        if x == 0:  # the zero-mean limit of the displaced tier relies on exp(0) == 1 exactly
+            assert r == 1
+        assert abs(r - want) <= 4 * max(1, abs(x)) * mp.mpf(2) ** -106 * want, (f, float(abs(r - want) / want))
+        n += 1
+    assert n > 400
