@@ -448,6 +448,8 @@ def main():
         out["per_n"] = per_n_rates(ctx, cov, args.prec)
         out["per_n_f64_terms"] = per_n_rates(ctx, cov, "f64")
         out["per_n_full_pattern"] = per_n_rates(ctx, cov, args.prec, ns=(20, 28), full=True)
+        out["per_n_qd_terms"] = per_n_rates(ctx, cov, "qd", ns=(20, 24, 28))
+        out["per_n_full_pattern_qd"] = per_n_rates(ctx, cov, "qd", ns=(20, 28), full=True)
         out["per_n_displaced"] = per_n_rates(ctx, cov, args.prec, ns=(20, 24, 28),
                                              mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
         out["per_n_displaced_f64_terms"] = per_n_rates(ctx, cov, "f64", ns=(20, 24, 28),
