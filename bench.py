@@ -199,7 +199,7 @@ def per_n_rates(ctx, cov, prec, ns=(20, 24, 28, 32), full=False, mean=None):
     return out
 
 
-def paper_worst_case(ctx, sizes=((10, 200), (12, 288), (14, 392), (16, 512), (18, 648), (20, 800))):
+def paper_worst_case(ctx, sizes=((10, 200), (12, 288), (14, 392), (16, 512), (18, 648), (20, 800)), prec="dd"):
     """The paper's runtime study, worst case (Sec. III): one sample with fixed
     outcomes, l = 2 m^2 modes, 8 dB squeezing on every mode, Haar
     interferometer, all m clicks in the first m measured modes (modes are
@@ -215,7 +215,7 @@ def paper_worst_case(ctx, sizes=((10, 200), (12, 288), (14, 392), (16, 512), (18
         pat[l - m:] = 1
         ctx.reset_stats()
         t = time.perf_counter()
-        tot, steps = ctx.chain_fixed(cov, pat, prec="dd")
+        tot, steps = ctx.chain_fixed(cov, pat, prec=prec)
         dt = time.perf_counter() - t
         st = ctx.stats()
         out[f"{l},{m}"] = {"seconds": dt, "modes": l, "clicks": m, "p": tot.p, "log_p": tot.log_p,
@@ -456,6 +456,7 @@ def main():
                                                        mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
         out["sampler"] = sampler_bench(ctx)
         out["paper_worst_case"] = paper_worst_case(ctx)
+        out["paper_worst_case_qd"] = paper_worst_case(ctx, sizes=((16, 512), (18, 648), (20, 800)), prec="qd")
         out["dense_subgraph"] = dense_subgraph(ctx)
         out["serving"] = serving_bench(ctx)
     ctx.close()

@@ -283,7 +283,9 @@ tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post,
  * are ratios of the subset sums over the clicks so far before and after each
  * step, all of them evaluated in one batched launch.  Clicks <= 32, observed
  * modes <= 1024.  prec as for tor_probability (AUTO repeats in double-double
- * the sums whose binary64 bound exceeds tol).
+ * the sums whose binary64 bound exceeds tol); TOR_PREC_QD conditions and sums
+ * in quad-double (one tree per step: slower, for chains whose double-double
+ * bound exceeds tol, e.g. the worst case with 20 clicks on 800 modes).
  * Errors: TOR_EINVAL, TOR_ETOOBIG, TOR_ENOTPD, TOR_ENOMEM, TOR_EDEVICE;
  * TOR_WARN_PRECISION when the bound exceeds tol. */
 tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int8_t *outcomes, tor_prec prec,

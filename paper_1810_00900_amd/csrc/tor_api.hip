@@ -1000,6 +1000,7 @@ tor_status condition_qd(tor_ctx *ctx, const Reduced &r, std::vector<qd> &sigc, d
         j.mat = db;
         j.acc = (double *)(db + acc_off);
         j.cols = db + cols_off;
+        j.qout = nullptr;
         j.r = n + k - t;
         j.begin = 0;
         blocks[t] = std::max<long long>(1, (E(j.r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
@@ -1581,6 +1582,81 @@ tor_status run_chains(tor_ctx *ctx, int m, int n_post, uint64_t seed, long long 
 
 }  // namespace
 
+namespace {
+
+// The fixed-outcome chain with quad-double terms: the conditioning over the
+// no-click steps in quad-double with a snapshot of the clicked block after
+// every step, then one quad-double subset sum per step.  roots[k] keeps the
+// double-double rounding of snapshot k (for the final log det); qv the q of
+// each no-click step.
+tor_status chain_sums_qd(tor_ctx *ctx, const double *cov, int m, const std::vector<int> &g,
+                         const std::vector<int> &seq, const int8_t *outcomes, int nn,
+                         std::vector<std::vector<dd>> &roots, std::vector<SumIn> &in, std::vector<SumOut> &res,
+                         std::vector<double> &qv) {
+    const int nsteps = (int)seq.size(), nobs = nsteps;
+    const size_t words = (size_t)E(nobs);
+    const size_t cols_off = align_up(words * sizeof(qd), 256);
+    const size_t cols_words = 2 * (2 * (size_t)nobs - 2) + 2;
+    const size_t acc_off = align_up(cols_off + cols_words * sizeof(qd), 256);
+    const size_t q_off = align_up(acc_off + 3 * sizeof(double), 256);
+    const size_t job_off = align_up(q_off + 2 * (size_t)std::max(nn, 1) * sizeof(double), 256);
+    const size_t total_bytes = job_off + (size_t)std::max(nn, 1) * sizeof(CondJobQ);
+    if (total_bytes > ctx->mem_budget) return fail(TOR_ENOMEM, "chain needs %.2f GB", total_bytes / 1e9);
+    if (ctx->cond.ensure(total_bytes) != hipSuccess) return fail(TOR_ENOMEM, "device allocation failed");
+    unsigned char *db = (unsigned char *)ctx->cond.p;
+    std::vector<unsigned char> stage(total_bytes);
+    qd *hm = (qd *)stage.data();
+    for (int a = 0; a < 2 * nobs; a++)
+        for (int b = 0; b <= a; b++) hm[pidx(a, b)] = qd_from_dd(sigq(cov, m, g[a], g[b]));
+    const double a0[3] = {1.0, 0.0, 0.0};
+    std::memcpy(stage.data() + acc_off, a0, sizeof a0);
+    CondJobQ *hj = (CondJobQ *)(stage.data() + job_off);
+    for (int k = 0, t = 0, r = nobs; k < nsteps; k++) {
+        if (outcomes[seq[k]] == 1) continue;
+        CondJobQ j{};
+        j.mat = db;
+        j.acc = (double *)(db + acc_off);
+        j.cols = db + cols_off;
+        j.qout = (double *)(db + q_off) + 2 * t;
+        j.r = r--;
+        hj[t++] = j;
+    }
+    hipStream_t st = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(db, stage.data(), total_bytes, hipMemcpyHostToDevice, st));
+    std::vector<std::vector<qd>> snaps(nsteps);
+    std::vector<int> snap_n(nsteps);
+    int c = 0, t = 0;
+    for (int k = 0; k < nsteps; k++) {
+        if (outcomes[seq[k]] == 1) {
+            c++;
+        } else {
+            const long long blocks = std::max<long long>(1, (E(hj[t].r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
+            HIP_TRY(tor_launch_condition_qd((const CondJobQ *)(db + job_off) + t, 1, blocks, st));
+            t++;
+        }
+        snap_n[k] = c;
+        snaps[k].resize((size_t)E(c));
+        if (c > 0)
+            HIP_TRY(hipMemcpyAsync(snaps[k].data(), db, (size_t)E(c) * sizeof(qd), hipMemcpyDeviceToHost, st));
+    }
+    qv.assign(2 * (size_t)nn, 0.0);
+    if (nn > 0) HIP_TRY(hipMemcpyAsync(qv.data(), db + q_off, 2 * (size_t)nn * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    ctx->stats.condition_launches += 2 * (int64_t)t;
+    for (int k = 0; k < nsteps; k++) {
+        const int n = snap_n[k];
+        in[k].n = n;
+        roots[k].resize(snaps[k].size());
+        for (size_t e = 0; e < snaps[k].size(); e++) roots[k][e] = qd_to_dd(snaps[k][e]);
+        in[k].packed = &roots[k];
+        tor_status s = gpu_sum_qd(ctx, snaps[k], n, res[k]);
+        if (s) return s;
+    }
+    return TOR_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 tor_status gbs_sample(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,
@@ -1635,7 +1711,7 @@ tor_status gbs_sample(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post
 tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int8_t *outcomes, tor_prec prec,
                            double tol, double *step_p, tor_result *total) {
     if (!ctx || !total) return fail(TOR_EINVAL, "NULL argument");
-    if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD)
+    if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD && prec != TOR_PREC_QD)
         return fail(TOR_EINVAL, "bad precision %d", (int)prec);
     if (!(tol > 0.0)) tol = 1e-10;
     tor_status s = validate_cov_block(cov, m, outcomes);
@@ -1672,8 +1748,17 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
         g.push_back(2 * *it + 1);
     }
     const size_t EM = (size_t)E(nobs);
-    // device buffer: matrix | acc (3) | q per no-click step (2 each) | snapshots | jobs
     const int nsteps = nobs;
+    std::vector<std::vector<dd>> roots(nsteps);
+    std::vector<SumIn> in(nsteps);
+    std::vector<SumOut> res(nsteps);
+    std::vector<int> used(nsteps, prec == TOR_PREC_QD ? TOR_PREC_QD : prec == TOR_PREC_DD ? TOR_PREC_DD : TOR_PREC_F64);
+    std::vector<double> qv;
+    if (prec == TOR_PREC_QD) {
+        s = chain_sums_qd(ctx, cov, m, g, seq, outcomes, nn, roots, in, res, qv);
+        if (s) return s;
+    } else {
+    // device buffer: matrix | acc (3) | q per no-click step (2 each) | snapshots | jobs
     std::vector<long long> snap_off(nsteps + 1), snap_n(nsteps + 1);
     size_t snap_tot = 0;
     {
@@ -1739,11 +1824,8 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
     HIP_TRY(hipStreamSynchronize(st));
     // the q of each no-click step, out of the staging buffer that the subset
     // sums below reuse
-    const std::vector<double> qv((const double *)(stage.data() + o_q),
-                                 (const double *)(stage.data() + o_q) + 2 * (size_t)nn);
+    qv.assign((const double *)(stage.data() + o_q), (const double *)(stage.data() + o_q) + 2 * (size_t)nn);
     // one subset sum per step over the clicks so far, all in shared launches
-    std::vector<std::vector<dd>> roots(nsteps);
-    std::vector<SumIn> in(nsteps);
     std::vector<int> which;
     const dd *snaps = (const dd *)(stage.data() + o_snap);
     for (int k = 0; k < nsteps; k++) {
@@ -1752,8 +1834,6 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
         in[k].packed = &roots[k];
         which.push_back(k);
     }
-    std::vector<SumOut> res(nsteps);
-    std::vector<int> used(nsteps, prec == TOR_PREC_DD ? TOR_PREC_DD : TOR_PREC_F64);
     s = gpu_sums(ctx, in, which, prec == TOR_PREC_DD, res);
     if (s) return s;
     if (prec == TOR_PREC_AUTO) {
@@ -1766,6 +1846,7 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
             for (int k : redo) used[k] = TOR_PREC_DD;
         }
     }
+    }  // binary64 / double-double terms
     // step probabilities: click T_k / T_{k-1}; no click q T_k / T_{k-1}
     const double *hq = qv.data();
     dd prev = dd_from(1.0), pvac = dd_from(1.0);
@@ -1786,7 +1867,7 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
         if (in[k].n > 0) {
             worst_bound = std::max(worst_bound, bound_of(used[k], in[k].n, T, res[k].A));
             worst_R = std::max(worst_R, res[k].A / std::fabs(T.hi));
-            if (used[k] == TOR_PREC_DD) worst_used = TOR_PREC_DD;
+            worst_used = std::max(worst_used, used[k]);
         }
         prev = T;
     }

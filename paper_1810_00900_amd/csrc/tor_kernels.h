@@ -159,6 +159,7 @@ struct CondJobQ {
     void *mat;
     double *acc;
     void *cols;
+    double *qout;  // if not null: this step's pivot factor q (double-double rounding, hi, lo)
     long long begin;
     int r;
     int pad;

@@ -159,6 +159,10 @@ __global__ __launch_bounds__(256) void condition_cols_qd(const CondJobQ *__restr
         job.acc[0] = p.hi;
         job.acc[1] = p.lo;
         job.acc[2] += log(q.hi) + log1p(q.lo / q.hi);
+        if (job.qout) {
+            job.qout[0] = q.hi;
+            job.qout[1] = q.lo;
+        }
     }
 }
 

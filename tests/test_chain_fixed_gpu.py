@@ -6,7 +6,10 @@
   tor_probability;
 * P(click) + P(no click) = 1 at a step with a shared history;
 * the worst case of the paper's runtime study (all clicks measured first,
-  8 dB squeezing, Haar interferometer) at l = 200 modes, 10 clicks.
+  8 dB squeezing, Haar interferometer) at l = 200 modes, 10 clicks;
+* quad-double terms (TOR_PREC_QD): the same rule checks, and the worst case
+  at l = 512, 16 clicks, where the double-double bound is ~1e-7, against
+  tor_probability in quad-double (a different conditioning order).
 """
 import numpy as np
 import pytest
@@ -30,16 +33,17 @@ def _rel(a, b):
     return abs(float(a) - float(b)) / abs(float(b))
 
 
+@pytest.mark.parametrize("prec", ["dd", "qd"])
 @pytest.mark.parametrize("pat", [
     [1, 0, 1, 1, 0, -1, 1, 0],
     [0, 0, 0, 1, 1, 1, 1, 0],
     [1, 1, 1, 1, 0, 0, 0, 0],
     [-1, 1, -1, 0, 1, -1, 0, 1],
 ])
-def test_steps_match_paper_rule(ctx, pat):
+def test_steps_match_paper_rule(ctx, pat, prec):
     cov = gi.state_config1()
     pat = np.array(pat, np.int8)
-    tot, steps = ctx.chain_fixed(cov, pat, prec="dd")
+    tot, steps = ctx.chain_fixed(cov, pat, prec=prec)
     want_tot, want = oracle.prob_sequential(cov, pat, dps=40, steps=True)
     for j in range(8):
         if pat[j] < 0:
@@ -85,3 +89,29 @@ def test_worst_case_l200_m10(ctx):
     r = ctx.probability(cov, pat, prec="dd")
     assert _rel(tot.p + tot.p_lo, r.p + r.p_lo) <= max(1e-10, 4 * (tot.rel_err_bound + r.rel_err_bound))
     assert np.prod(steps) == pytest.approx(tot.p, rel=1e-9)
+
+
+def test_worst_case_l512_m16_quad_double(ctx):
+    """All 16 clicks first, then 496 no-click steps: the double-double bound is
+    ~1e-7 here; quad-double steps multiply to tor_probability in quad-double
+    (conditioned in the opposite mode order) to 1e-25, and complementary
+    outcomes at a late step sum to one."""
+    rng = np.random.default_rng(512)
+    l, m = 512, 16
+    cov = gi.gbs_covariance(gi.haar_unitary(l, rng), np.full(l, R8DB))
+    pat = np.zeros(l, np.int8)
+    pat[l - m:] = 1
+    ctx.reset_stats()
+    tot, steps = ctx.chain_fixed(cov, pat, prec="qd")
+    assert ctx.stats()["condition_launches"] == 2 * (l - m)
+    assert tot.prec_used == tg.PREC_QD and tot.status == tg.TOR_OK
+    assert tot.rel_err_bound <= 1e-25
+    r = ctx.probability(cov, pat, prec="qd")
+    assert _rel(tot.p + tot.p_lo, r.p + r.p_lo) <= 1e-25
+    d, _ = ctx.chain_fixed(cov, pat, prec="dd")
+    assert _rel(d.p + d.p_lo, r.p + r.p_lo) <= max(d.rel_err_bound, 1e-30)
+    j = 100  # measured at step l - 1 - j, after all clicks
+    alt = pat.copy()
+    alt[j] = 1
+    _, steps2 = ctx.chain_fixed(cov, alt, prec="qd")
+    assert steps[j] + steps2[j] == pytest.approx(1.0, abs=1e-15)
