@@ -109,9 +109,9 @@ def cpu_baseline(cov, pattern, n, seconds_target=15.0):
                               "sample": f"{count1} subsets (masks 1 + j*{stride1}), {dt1:.1f} s"}}
 
 
-KERNEL_SOURCES = ["paper_1810_00900_amd/csrc/dd.hpp", "paper_1810_00900_amd/csrc/tor_tree.hpp",
-                  "paper_1810_00900_amd/csrc/tor_wave.hpp", "paper_1810_00900_amd/csrc/tor_kernels.hip",
-                  "paper_1810_00900_amd/csrc/tor_kernels.h"]
+KERNEL_SOURCES = ["paper_1810_00900_amd/csrc/dd.hpp", "paper_1810_00900_amd/csrc/qd.hpp",
+                  "paper_1810_00900_amd/csrc/tor_tree.hpp", "paper_1810_00900_amd/csrc/tor_wave.hpp",
+                  "paper_1810_00900_amd/csrc/tor_kernels.hip", "paper_1810_00900_amd/csrc/tor_kernels.h"]
 
 
 def measured_fp64(kernel, kernel_ms):
