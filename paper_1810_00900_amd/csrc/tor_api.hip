@@ -1584,6 +1584,110 @@ tor_status run_chains(tor_ctx *ctx, int m, int n_post, uint64_t seed, long long 
 
 namespace {
 
+// The fixed-outcome chain with binary64 or double-double terms: the
+// conditioning over the no-click steps in double-double with a device-side
+// snapshot of the clicked block after every step, then every step's subset
+// sum in shared launches (AUTO repeats in double-double the sums whose
+// binary64 bound exceeds tol).  roots[k] holds snapshot k, qv the q of each
+// no-click step, used[k] the term precision of step k.
+tor_status chain_sums_dd(tor_ctx *ctx, const double *cov, int m, const std::vector<int> &g,
+                         const std::vector<int> &seq, const int8_t *outcomes, int nn, tor_prec prec, double tol,
+                         std::vector<std::vector<dd>> &roots, std::vector<SumIn> &in, std::vector<SumOut> &res,
+                         std::vector<int> &used, std::vector<double> &qv) {
+    const int nsteps = (int)seq.size(), nobs = nsteps;
+    const size_t EM = (size_t)E(nobs);
+    tor_status s = TOR_OK;
+    // device buffer: matrix | acc (3) | q per no-click step (2 each) | snapshots | jobs
+    std::vector<long long> snap_off(nsteps + 1), snap_n(nsteps + 1);
+    size_t snap_tot = 0;
+    {
+        int c = 0;
+        for (int k = 0; k < nsteps; k++) {
+            if (outcomes[seq[k]] == 1) c++;
+            snap_n[k] = c;
+            snap_off[k] = (long long)snap_tot;
+            snap_tot += (size_t)E(c);
+        }
+    }
+    const size_t o_acc = align_up(EM * sizeof(dd), 256);
+    const size_t o_q = align_up(o_acc + 3 * sizeof(double), 256);
+    const size_t o_snap = align_up(o_q + 2 * (size_t)std::max(nn, 1) * sizeof(double), 256);
+    const size_t o_jobs = align_up(o_snap + snap_tot * sizeof(dd), 256);
+    const size_t bytes = o_jobs + (size_t)std::max(nn, 1) * sizeof(CondJob);
+    if (bytes > ctx->mem_budget) return fail(TOR_ENOMEM, "chain needs %.2f GB", bytes / 1e9);
+    if (ctx->cond.ensure(bytes) != hipSuccess) return fail(TOR_ENOMEM, "device allocation failed");
+    unsigned char *db = (unsigned char *)ctx->cond.p;
+    dd *dmat = (dd *)db;
+    std::vector<unsigned char> &stage = ctx->host_stage;
+    if (stage.size() < bytes) stage.resize(bytes);
+    dd *hm = (dd *)stage.data();
+    for (int a = 0; a < 2 * nobs; a++)
+        for (int b = 0; b <= a; b++) hm[pidx(a, b)] = sigq(cov, m, g[a], g[b]);
+    const double a0[3] = {1.0, 0.0, 0.0};
+    std::memcpy(stage.data() + o_acc, a0, sizeof a0);
+    CondJob *hj = (CondJob *)(stage.data() + o_jobs);
+    {
+        int r = nobs, t = 0;
+        for (int k = 0; k < nsteps; k++) {
+            if (outcomes[seq[k]] == 1) continue;
+            CondJob j{};
+            j.mat = dmat;
+            j.acc = (double *)(db + o_acc);
+            j.qout = (double *)(db + o_q) + 2 * t;
+            j.begin = 0;
+            j.r = r;
+            hj[t++] = j;
+            r--;
+        }
+    }
+    hipStream_t st = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(db, stage.data(), o_acc + 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(db + o_jobs, stage.data() + o_jobs, (size_t)std::max(nn, 1) * sizeof(CondJob),
+                           hipMemcpyHostToDevice, st));
+    {
+        int t = 0;
+        for (int k = 0; k < nsteps; k++) {
+            if (outcomes[seq[k]] == 0) {
+                const CondJob &j = hj[t];
+                const long long blocks = std::max<long long>(1, (E(j.r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
+                HIP_TRY(tor_launch_condition((const CondJob *)(db + o_jobs) + t, 1, blocks, j.r, st));
+                t++;
+            }
+            if (snap_n[k] > 0)
+                HIP_TRY(hipMemcpyAsync(db + o_snap + snap_off[k] * sizeof(dd), dmat, sizeof(dd) * E(snap_n[k]),
+                                       hipMemcpyDeviceToDevice, st));
+        }
+        ctx->stats.condition_launches += t;
+    }
+    HIP_TRY(hipMemcpyAsync(stage.data() + o_q, db + o_q, o_jobs - o_q, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // the q of each no-click step, out of the staging buffer that the subset
+    // sums below reuse
+    qv.assign((const double *)(stage.data() + o_q), (const double *)(stage.data() + o_q) + 2 * (size_t)nn);
+    // one subset sum per step over the clicks so far, all in shared launches
+    std::vector<int> which;
+    const dd *snaps = (const dd *)(stage.data() + o_snap);
+    for (int k = 0; k < nsteps; k++) {
+        in[k].n = (int)snap_n[k];
+        roots[k].assign(snaps + snap_off[k], snaps + snap_off[k] + E(snap_n[k]));
+        in[k].packed = &roots[k];
+        which.push_back(k);
+    }
+    s = gpu_sums(ctx, in, which, prec == TOR_PREC_DD, res);
+    if (s) return s;
+    if (prec == TOR_PREC_AUTO) {
+        std::vector<int> redo;
+        for (int k = 0; k < nsteps; k++)
+            if (in[k].n > 0 && !(bound_of(TOR_PREC_F64, in[k].n, res[k].T, res[k].A) <= tol)) redo.push_back(k);
+        if (!redo.empty()) {
+            s = gpu_sums(ctx, in, redo, true, res);
+            if (s) return s;
+            for (int k : redo) used[k] = TOR_PREC_DD;
+        }
+    }
+    return TOR_OK;
+}
+
 // The fixed-outcome chain with quad-double terms: the conditioning over the
 // no-click steps in quad-double with a snapshot of the clicked block after
 // every step, then one quad-double subset sum per step.  roots[k] keeps the
@@ -1747,7 +1851,6 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
         g.push_back(2 * *it);
         g.push_back(2 * *it + 1);
     }
-    const size_t EM = (size_t)E(nobs);
     const int nsteps = nobs;
     std::vector<std::vector<dd>> roots(nsteps);
     std::vector<SumIn> in(nsteps);
@@ -1756,97 +1859,10 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
     std::vector<double> qv;
     if (prec == TOR_PREC_QD) {
         s = chain_sums_qd(ctx, cov, m, g, seq, outcomes, nn, roots, in, res, qv);
-        if (s) return s;
     } else {
-    // device buffer: matrix | acc (3) | q per no-click step (2 each) | snapshots | jobs
-    std::vector<long long> snap_off(nsteps + 1), snap_n(nsteps + 1);
-    size_t snap_tot = 0;
-    {
-        int c = 0;
-        for (int k = 0; k < nsteps; k++) {
-            if (outcomes[seq[k]] == 1) c++;
-            snap_n[k] = c;
-            snap_off[k] = (long long)snap_tot;
-            snap_tot += (size_t)E(c);
-        }
+        s = chain_sums_dd(ctx, cov, m, g, seq, outcomes, nn, prec, tol, roots, in, res, used, qv);
     }
-    const size_t o_acc = align_up(EM * sizeof(dd), 256);
-    const size_t o_q = align_up(o_acc + 3 * sizeof(double), 256);
-    const size_t o_snap = align_up(o_q + 2 * (size_t)std::max(nn, 1) * sizeof(double), 256);
-    const size_t o_jobs = align_up(o_snap + snap_tot * sizeof(dd), 256);
-    const size_t bytes = o_jobs + (size_t)std::max(nn, 1) * sizeof(CondJob);
-    if (bytes > ctx->mem_budget) return fail(TOR_ENOMEM, "chain needs %.2f GB", bytes / 1e9);
-    if (ctx->cond.ensure(bytes) != hipSuccess) return fail(TOR_ENOMEM, "device allocation failed");
-    unsigned char *db = (unsigned char *)ctx->cond.p;
-    dd *dmat = (dd *)db;
-    std::vector<unsigned char> &stage = ctx->host_stage;
-    if (stage.size() < bytes) stage.resize(bytes);
-    dd *hm = (dd *)stage.data();
-    for (int a = 0; a < 2 * nobs; a++)
-        for (int b = 0; b <= a; b++) hm[pidx(a, b)] = sigq(cov, m, g[a], g[b]);
-    const double a0[3] = {1.0, 0.0, 0.0};
-    std::memcpy(stage.data() + o_acc, a0, sizeof a0);
-    CondJob *hj = (CondJob *)(stage.data() + o_jobs);
-    {
-        int r = nobs, t = 0;
-        for (int k = 0; k < nsteps; k++) {
-            if (outcomes[seq[k]] == 1) continue;
-            CondJob j{};
-            j.mat = dmat;
-            j.acc = (double *)(db + o_acc);
-            j.qout = (double *)(db + o_q) + 2 * t;
-            j.begin = 0;
-            j.r = r;
-            hj[t++] = j;
-            r--;
-        }
-    }
-    hipStream_t st = ctx->stream;
-    HIP_TRY(hipMemcpyAsync(db, stage.data(), o_acc + 3 * sizeof(double), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(db + o_jobs, stage.data() + o_jobs, (size_t)std::max(nn, 1) * sizeof(CondJob),
-                           hipMemcpyHostToDevice, st));
-    {
-        int t = 0;
-        for (int k = 0; k < nsteps; k++) {
-            if (outcomes[seq[k]] == 0) {
-                const CondJob &j = hj[t];
-                const long long blocks = std::max<long long>(1, (E(j.r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
-                HIP_TRY(tor_launch_condition((const CondJob *)(db + o_jobs) + t, 1, blocks, j.r, st));
-                t++;
-            }
-            if (snap_n[k] > 0)
-                HIP_TRY(hipMemcpyAsync(db + o_snap + snap_off[k] * sizeof(dd), dmat, sizeof(dd) * E(snap_n[k]),
-                                       hipMemcpyDeviceToDevice, st));
-        }
-        ctx->stats.condition_launches += t;
-    }
-    HIP_TRY(hipMemcpyAsync(stage.data() + o_q, db + o_q, o_jobs - o_q, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    // the q of each no-click step, out of the staging buffer that the subset
-    // sums below reuse
-    qv.assign((const double *)(stage.data() + o_q), (const double *)(stage.data() + o_q) + 2 * (size_t)nn);
-    // one subset sum per step over the clicks so far, all in shared launches
-    std::vector<int> which;
-    const dd *snaps = (const dd *)(stage.data() + o_snap);
-    for (int k = 0; k < nsteps; k++) {
-        in[k].n = (int)snap_n[k];
-        roots[k].assign(snaps + snap_off[k], snaps + snap_off[k] + E(snap_n[k]));
-        in[k].packed = &roots[k];
-        which.push_back(k);
-    }
-    s = gpu_sums(ctx, in, which, prec == TOR_PREC_DD, res);
     if (s) return s;
-    if (prec == TOR_PREC_AUTO) {
-        std::vector<int> redo;
-        for (int k = 0; k < nsteps; k++)
-            if (in[k].n > 0 && !(bound_of(TOR_PREC_F64, in[k].n, res[k].T, res[k].A) <= tol)) redo.push_back(k);
-        if (!redo.empty()) {
-            s = gpu_sums(ctx, in, redo, true, res);
-            if (s) return s;
-            for (int k : redo) used[k] = TOR_PREC_DD;
-        }
-    }
-    }  // binary64 / double-double terms
     // step probabilities: click T_k / T_{k-1}; no click q T_k / T_{k-1}
     const double *hq = qv.data();
     dd prev = dd_from(1.0), pvac = dd_from(1.0);

@@ -193,3 +193,14 @@ def test_mean_validation(ctx):
     res = tg._CResult()
     st = L.tor_probability_displaced(ctx._h, tg._dptr(cov), None, 3, tg._i8ptr(pat), 0, 1e-10, ctypes.byref(res))
     assert st == tg.TOR_EINVAL
+
+
+def test_displaced_not_positive_definite(ctx):
+    cov = 0.5 * np.eye(4)
+    cov[2, 2] = -3.0
+    with pytest.raises(tg.TorError) as ei:
+        ctx.probability_displaced(cov, np.ones(4), np.array([1, 1], np.int8))
+    assert ei.value.status == tg.TOR_ENOTPD
+    with pytest.raises(tg.TorError) as ei:  # the bad mode conditioned away as a no-click mode
+        ctx.probability_displaced(cov, np.ones(4), np.array([1, 0], np.int8))
+    assert ei.value.status == tg.TOR_ENOTPD

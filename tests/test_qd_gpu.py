@@ -175,3 +175,18 @@ def test_qd_rejected_where_not_supported(ctx):
     with pytest.raises(tg.TorError) as ei:
         ctx.probability_displaced(cov, np.zeros(4), np.array([1, 0], np.int8), prec="qd")
     assert ei.value.status == tg.TOR_EINVAL
+
+
+def test_qd_errors(ctx):
+    # a tree whose quad-double pool exceeds the context's memory budget
+    sig = np.eye(64)
+    with pytest.raises(tg.TorError) as ei:
+        ctx.subset_sum(sig, prec="qd")
+    assert ei.value.status == tg.TOR_ENOMEM
+    assert "quad-double" in tg.last_error()
+    # not positive definite: sigma_Q has a negative eigenvalue
+    cov = 0.5 * np.eye(4)
+    cov[0, 0] = -2.0
+    with pytest.raises(tg.TorError) as ei:
+        ctx.probability(cov, np.array([1, 1], np.int8), prec="qd")
+    assert ei.value.status == tg.TOR_ENOTPD
