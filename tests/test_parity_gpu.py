@@ -181,6 +181,23 @@ def test_m800_golden_n24(ctx, cov800):
         assert _rel(_gpu_p(r), want) <= tol, case["n"]
 
 
+def test_m800_bench_configuration_against_quad_double(ctx, cov800):
+    """The timed configuration itself (n = 28 marginal on the 800-mode state,
+    dd terms, default 10-mode tasks): too large for the oracle (~50 min on 16
+    cores), checked against the quad-double tier, whose bound there is ~1e-40
+    and which is pinned to the oracle and to exact closed forms in
+    test_qd_gpu.py."""
+    import mpmath as mp
+    pat = gi.config5_pattern(28)
+    r = ctx.probability(cov800, pat, prec="dd")
+    q = ctx.probability(cov800, pat, prec="qd")
+    assert q.rel_err_bound <= 1e-30
+    want = mp.mpf(q.p) + mp.mpf(q.p_lo)
+    err = _rel(_gpu_p(r), want)
+    assert err <= r.rel_err_bound and err <= 1e-8, (err, r.rel_err_bound)
+    assert r.cancel_ratio == pytest.approx(q.cancel_ratio, rel=1e-6)
+
+
 def test_auto_escalates(ctx, cov800):
     """AUTO starts with binary64 terms and repeats in double-double when the
     bound exceeds tol."""
