@@ -10,7 +10,9 @@
 // level-accumulation scheme of Hida, Li and Bailey (ARITH 2001) and the
 // expansion renormalisation of Priest (1991), written here from those
 // descriptions.  Error model (checked against mpmath in the CPU tests):
-//   add: |err| <= c u^4 (|a| + |b|),  mul: |err| <= c u^4 |a b|,  c ~ 16.
+//   add: |err| <= c u^4 (|a| + |b|),  mul: |err| <= c u^4 |a b|,  c ~ 16;
+//   rsqrt: relative error about 1.5 e^2 <= ~100 u^4 for a double-double seed
+//   with relative error e ~ 2^-103 (one Newton step).
 // Weak (operand-relative) accuracy is what the subset tree needs: its error
 // bound is relative to the sum of the magnitudes of the terms.
 //
@@ -91,36 +93,42 @@ DD_FN qd qd_add(qd a, qd b) {
 }
 DD_FN qd qd_sub(qd a, qd b) { return qd_add(a, qd_neg(b)); }
 
+// Level sums of a * b before renormalisation: a*b = L0 + L1 + L2 + L3 + L4
+// up to order-5 terms, with L0..L2 single words (the exact errors of their
+// TwoSums pushed to the next level) and L3, L4 plain binary64 sums.
+struct QdLevels {
+    double l0, l1, l2, l3, l4;
+};
+DD_FN QdLevels qd_mul_levels(qd a, qd b) {
+    QdLevels o;
+    double q00, p01, q01, p10, q10, p02, q02, p11, q11, p20, q20;
+    two_prod(a.x0, b.x0, o.l0, q00);
+    two_prod(a.x0, b.x1, p01, q01);
+    two_prod(a.x1, b.x0, p10, q10);
+    two_prod(a.x0, b.x2, p02, q02);
+    two_prod(a.x1, b.x1, p11, q11);
+    two_prod(a.x2, b.x0, p20, q20);
+    double c1, c2;
+    two_sum(p01, p10, o.l1, c1);
+    two_sum(o.l1, q00, o.l1, c2);
+    double d1, d2, d3, d4, d5, d6;
+    two_sum(p02, p11, o.l2, d1);
+    two_sum(o.l2, p20, o.l2, d2);
+    two_sum(o.l2, q01, o.l2, d3);
+    two_sum(o.l2, q10, o.l2, d4);
+    two_sum(o.l2, c1, o.l2, d5);
+    two_sum(o.l2, c2, o.l2, d6);
+    const double o3 = fma(a.x0, b.x3, fma(a.x1, b.x2, fma(a.x2, b.x1, a.x3 * b.x0)));
+    o.l3 = o3 + ((q02 + q11) + q20) + (((d1 + d2) + (d3 + d4)) + (d5 + d6));
+    o.l4 = fma(a.x1, b.x3, fma(a.x2, b.x2, a.x3 * b.x1));
+    return o;
+}
+
 // a * b: partial products a_i b_j of order i + j <= 2 exact (TwoProd), order 3
 // with their rounding, order 4 in binary64; orders >= 5 dropped.
 DD_FN qd qd_mul(qd a, qd b) {
-    double p00, q00;
-    two_prod(a.x0, b.x0, p00, q00);  // order 0, error order 1
-    double p01, q01, p10, q10;
-    two_prod(a.x0, b.x1, p01, q01);  // order 1, errors order 2
-    two_prod(a.x1, b.x0, p10, q10);
-    double p02, q02, p11, q11, p20, q20;
-    two_prod(a.x0, b.x2, p02, q02);  // order 2, errors order 3
-    two_prod(a.x1, b.x1, p11, q11);
-    two_prod(a.x2, b.x0, p20, q20);
-    // level 1: p01 + p10 + q00, carries to level 2
-    double l1, c1, c2;
-    two_sum(p01, p10, l1, c1);
-    two_sum(l1, q00, l1, c2);
-    // level 2: p02 + p11 + p20 + q01 + q10 + c1 + c2, carries to level 3
-    double l2, d1, d2, d3, d4, d5, d6;
-    two_sum(p02, p11, l2, d1);
-    two_sum(l2, p20, l2, d2);
-    two_sum(l2, q01, l2, d3);
-    two_sum(l2, q10, l2, d4);
-    two_sum(l2, c1, l2, d5);
-    two_sum(l2, c2, l2, d6);
-    // level 3: order-3 products and errors, plain sums
-    const double o3 = fma(a.x0, b.x3, fma(a.x1, b.x2, fma(a.x2, b.x1, a.x3 * b.x0)));
-    const double l3 = o3 + ((q02 + q11) + q20) + (((d1 + d2) + (d3 + d4)) + (d5 + d6));
-    // level 4: order-4 products
-    const double l4 = fma(a.x1, b.x3, fma(a.x2, b.x2, a.x3 * b.x1));
-    return qd_renorm5(p00, l1, l2, l3, l4);
+    const QdLevels p = qd_mul_levels(a, b);
+    return qd_renorm5(p.l0, p.l1, p.l2, p.l3, p.l4);
 }
 
 // a * b for a binary64 b
@@ -137,14 +145,56 @@ DD_FN qd qd_mul_d(qd a, double b) {
     return qd_renorm5(p0, l1, l2, l3, 0.0);
 }
 
-// x - a1 b1 - a2 b2 (the rank-2 Schur update of one entry)
+// x - a1 b1 - a2 b2 (the rank-2 Schur update of one entry), fused: the two
+// products stay level sums, the three operands are combined level by level
+// (exact TwoSums at levels 0-2, their errors carried down; plain sums at
+// levels 3-4) and the result is renormalised once.  Error within c u^4
+// (|x| + |a1 b1| + |a2 b2|), as for the unfused form.
 DD_FN qd qd_sub_dot2(qd x, qd a1, qd b1, qd a2, qd b2) {
-    return qd_sub(qd_sub(x, qd_mul(a1, b1)), qd_mul(a2, b2));
+    const QdLevels p = qd_mul_levels(a1, b1), r = qd_mul_levels(a2, b2);
+    double s0, s1, s2, e0, e1, f0, f1, f2, f3, g0, g1, g2, g3, g4, g5;
+    two_sum(x.x0, -p.l0, s0, e0);  // level 0
+    two_sum(s0, -r.l0, s0, e1);
+    two_sum(x.x1, -p.l1, s1, f0);  // level 1
+    two_sum(s1, -r.l1, s1, f1);
+    two_sum(s1, e0, s1, f2);
+    two_sum(s1, e1, s1, f3);
+    two_sum(x.x2, -p.l2, s2, g0);  // level 2
+    two_sum(s2, -r.l2, s2, g1);
+    two_sum(s2, f0, s2, g2);
+    two_sum(s2, f1, s2, g3);
+    two_sum(s2, f2, s2, g4);
+    two_sum(s2, f3, s2, g5);
+    const double s3 = ((x.x3 - p.l3) - r.l3) + (((g0 + g1) + (g2 + g3)) + (g4 + g5));
+    const double s4 = -(p.l4 + r.l4);
+    return qd_renorm5(s0, s1, s2, s3, s4);
 }
 // x - a b
-DD_FN qd qd_sub_mul(qd x, qd a, qd b) { return qd_sub(x, qd_mul(a, b)); }
-// a c - b^2 (2x2 determinant)
-DD_FN qd qd_det2(qd a, qd b, qd c) { return qd_sub(qd_mul(a, c), qd_mul(b, b)); }
+DD_FN qd qd_sub_mul(qd x, qd a, qd b) {
+    const QdLevels p = qd_mul_levels(a, b);
+    double s0, s1, s2, e0, f0, f1, g0, g1, g2;
+    two_sum(x.x0, -p.l0, s0, e0);
+    two_sum(x.x1, -p.l1, s1, f0);
+    two_sum(s1, e0, s1, f1);
+    two_sum(x.x2, -p.l2, s2, g0);
+    two_sum(s2, f0, s2, g1);
+    two_sum(s2, f1, s2, g2);
+    const double s3 = (x.x3 - p.l3) + ((g0 + g1) + g2);
+    return qd_renorm5(s0, s1, s2, s3, -p.l4);
+}
+// a c - b^2 (2x2 determinant), fused like qd_sub_dot2
+DD_FN qd qd_det2(qd a, qd b, qd c) {
+    const QdLevels p = qd_mul_levels(a, c), r = qd_mul_levels(b, b);
+    double s0, s1, s2, e0, f0, f1, g0, g1, g2;
+    two_sum(p.l0, -r.l0, s0, e0);
+    two_sum(p.l1, -r.l1, s1, f0);
+    two_sum(s1, e0, s1, f1);
+    two_sum(p.l2, -r.l2, s2, g0);
+    two_sum(s2, f0, s2, g1);
+    two_sum(s2, f1, s2, g2);
+    const double s3 = (p.l3 - r.l3) + ((g0 + g1) + g2);
+    return qd_renorm5(s0, s1, s2, s3, p.l4 - r.l4);
+}
 
 // x^-1/2: the double-double estimate, then one Newton step in qd,
 // y <- y + y (1 - x y^2) / 2 (quadratic convergence: 2^-104 -> 2^-207).

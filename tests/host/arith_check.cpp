@@ -28,7 +28,7 @@ static void put(qd a) { printf(" %a %a %a %a", a.x0, a.x1, a.x2, a.x3); }
 int main(int argc, char **argv) {
     const int n = argc > 1 ? atoi(argv[1]) : 3000;
     for (int i = 0; i < n; i++) {
-        const int kind = i % 7;
+        const int kind = i % 9;
         qd a = rand_qd(ldexp(1.0, (int)(urand() * 40) - 20)), b = rand_qd(ldexp(1.0, (int)(urand() * 40) - 20));
         if (kind == 1) {  // b = -a perturbed at one level: heavy cancellation
             b = qd_neg(a);
@@ -55,6 +55,8 @@ int main(int argc, char **argv) {
             break;
         }
         case 6: { const dd r = qd_to_dd(a); put(a); printf(" %a %a", r.hi, r.lo); break; }
+        case 7: { const qd c = rand_qd(1.0); put(a); put(b); put(c); put(qd_det2(a, b, c)); break; }
+        case 8: { const qd c = rand_qd(1.0); put(c); put(a); put(b); put(qd_sub_mul(c, a, b)); break; }
         }
         printf("\n");
     }

@@ -58,13 +58,21 @@ def test_quad_double_against_mpmath(lines):
         elif kind == 4:
             c, a, b, r = _q(w[0:4]), _q(w[4:8]), _q(w[8:12]), _q(w[12:16])
             err = abs(r - (c - 2 * a * b)) / ((abs(c) + 2 * abs(a * b)) * u4)
+            assert _nonoverlapping(w[12:16])
+        elif kind == 7:
+            a, b, c, r = _q(w[0:4]), _q(w[4:8]), _q(w[8:12]), _q(w[12:16])
+            err = abs(r - (a * c - b * b)) / ((abs(a * c) + b * b) * u4)
+        elif kind == 8:
+            c, a, b, r = _q(w[0:4]), _q(w[4:8]), _q(w[8:12]), _q(w[12:16])
+            err = abs(r - (c - a * b)) / ((abs(c) + abs(a * b)) * u4)
         else:
             continue
         worst[kind] = max(worst.get(kind, 0), float(err))
-    assert set(worst) == {0, 1, 2, 3, 4}
+    assert set(worst) == {0, 1, 2, 3, 4, 7, 8}
     for kind, e in worst.items():
-        # rsqrt: one Newton step from the double-double estimate, 1.5 e^2
-        assert e <= (64 if kind == 3 else 16), (kind, e)
+        # rsqrt: one Newton step from the double-double estimate (relative
+        # error e ~ 2^-103) leaves 1.5 e^2 ~ 96 u^4
+        assert e <= (128 if kind == 3 else 16), (kind, e)
 
 
 def test_quad_double_rounding_to_double_double(lines):
@@ -91,4 +99,4 @@ def test_double_double_exp_against_mpmath(lines):
             assert r == 1
         assert abs(r - want) <= 4 * max(1, abs(x)) * mp.mpf(2) ** -106 * want, (f, float(abs(r - want) / want))
         n += 1
-    assert n > 400
+    assert n > 300
