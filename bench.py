@@ -71,8 +71,11 @@ def wave_kernel_name(prec, J, D=0):
 
 def kernel_slug(kernel):
     """File-name form of a wave-kernel name: wave_kernel_top<dd,10,0> ->
-    wave_kernel_top_dd10 (a displaced kernel gets the suffix _disp)."""
+    wave_kernel_top_dd10 (a displaced kernel gets the suffix _disp),
+    wave_kernel_qd<8> -> wave_kernel_qd8."""
     base, args = kernel[:-1].split("<")
+    if "," not in args:
+        return f"{base}{args}"
     s, J, D = args.split(",")
     return f"{base}_{'f64' if s == 'double' else s}{J}" + ("_disp" if D == "1" else "")
 
@@ -111,7 +114,8 @@ def cpu_baseline(cov, pattern, n, seconds_target=15.0):
 
 KERNEL_SOURCES = ["paper_1810_00900_amd/csrc/dd.hpp", "paper_1810_00900_amd/csrc/qd.hpp",
                   "paper_1810_00900_amd/csrc/tor_tree.hpp", "paper_1810_00900_amd/csrc/tor_wave.hpp",
-                  "paper_1810_00900_amd/csrc/tor_kernels.hip", "paper_1810_00900_amd/csrc/tor_kernels.h"]
+                  "paper_1810_00900_amd/csrc/tor_kernels.hip", "paper_1810_00900_amd/csrc/tor_kernels_disp.hip",
+                  "paper_1810_00900_amd/csrc/tor_kernels_qd.hip", "paper_1810_00900_amd/csrc/tor_kernels.h"]
 
 
 def measured_fp64(kernel, kernel_ms):
@@ -373,6 +377,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--prec", default="dd", choices=["dd", "f64"])
+    ap.add_argument("--variant", default="zero-mean", choices=["zero-mean", "displaced", "qd"],
+                    help="the same n-click Torontonian on a displaced state (random mean) or with quad-double "
+                         "terms; for profiling those kernels (the headline is the zero-mean default)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-n, sampler and serving measurements")
     ap.add_argument("--copy-calibration", action="store_true", help="only run the 1 GiB copy used to scale counters")
@@ -395,14 +402,22 @@ def main():
     pattern = gi.config5_pattern(n)
     ctx = tg.Context(0)
     ctx.set_option(tg.OPT_TIMING, 1)
+    mean = gi.random_mean(800, np.random.default_rng(51), 0.3) if args.variant == "displaced" else None
+    prec = "qd" if args.variant == "qd" else args.prec
+
+    def call():
+        if mean is not None:
+            return ctx.probability_displaced(cov, mean, pattern, prec=prec, tol=1e-8)
+        return ctx.probability(cov, pattern, prec=prec, tol=1e-8)
+
     for _ in range(args.warmup):
-        r = ctx.probability(cov, pattern, prec=args.prec, tol=1e-8)
+        r = call()
     ctx.reset_stats()
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        r = ctx.probability(cov, pattern, prec=args.prec, tol=1e-8)
+        r = call()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = ctx.stats()
@@ -410,12 +425,20 @@ def main():
     subsets = 2.0 ** n * args.steps
     value = subsets / wall
 
-    J = ctx.tuning(args.prec, n)
+    J = ctx.tuning(args.prec, n) if prec != "qd" else min(n, 8)
     ntasks = 2 ** (n - J)
     wave_ms = st["wave_ms"] / max(st["wave_launches"], 1)
-    wave_flops = tree_flops(n, top=J) * ntasks
-    kname = wave_kernel_name(args.prec, J)
-    achieved = wave_flops / (wave_ms * 1e-3) / 1e12
+    if args.variant == "zero-mean":
+        wave_flops = tree_flops(n, top=J) * ntasks
+        kname = wave_kernel_name(args.prec, J)
+        achieved = wave_flops / (wave_ms * 1e-3) / 1e12
+    else:
+        # no algorithmic model for these trees: the roofline uses the executed
+        # FP64 flops of the committed PMC pass when its sources still match
+        kname = wave_kernel_name(args.prec, J, 1) if args.variant == "displaced" else f"wave_kernel_qd<{J}>"
+        wave_flops = None
+        ex = measured_fp64(kname, wave_ms) if n == 28 else None
+        achieved = ex["achieved"] if ex else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -427,13 +450,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64-dd" if args.prec == "dd" else "f64",
+        "dtype": {"dd": "f64-dd", "f64": "f64", "qd": "f64-qd"}[prec],
         "data": "synthetic (seeded Haar-random 800-mode GBS state)",
         "config": {"workload": f"large single Torontonian: m=800 modes (Haar U, r~U[0.3,0.9], seed 50), "
-                               f"marginal click pattern with n={n} (2^{n} subsets)",
-                   "m": 800, "n": n, "precision": args.prec, "task_modes": J},
+                               f"marginal click pattern with n={n} (2^{n} subsets)"
+                               + (", displaced state (mean 0.3 N(0,1) per quadrature, seed 51)"
+                                  if args.variant == "displaced" else ""),
+                   "m": 800, "n": n, "precision": prec, "task_modes": J},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "frac": achieved / FP64_PEAK_TFLOPS if achieved else None,
+                     "basis": "algorithmic" if args.variant == "zero-mean" else "executed (PMC)",
                      "traffic": (measured_traffic(kname) if n == 28 else None),
                      "kernel": kname,
                      "kernel_ms": wave_ms,
@@ -444,7 +470,9 @@ def main():
         "result": {"p": r.p, "cancel_ratio": r.cancel_ratio, "rel_err_bound": r.rel_err_bound,
                    "prec_used": r.prec_used},
     }
-    if not args.no_extras:
+    if args.variant != "zero-mean":
+        out["metric"] = METRIC + f" ({args.variant} variant)"
+    if not args.no_extras and args.variant == "zero-mean":
         out["per_n"] = per_n_rates(ctx, cov, args.prec)
         out["per_n_f64_terms"] = per_n_rates(ctx, cov, "f64")
         out["per_n_full_pattern"] = per_n_rates(ctx, cov, args.prec, ns=(20, 28), full=True)
