@@ -291,6 +291,18 @@ tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post,
 tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int8_t *outcomes, tor_prec prec,
                            double tol, double *step_p, tor_result *total);
 
+/* gbs_chain_fixed for a displaced state (the paper's mode-by-mode rule with
+ * non-zero means, Sec. II): mean (host, 2m doubles, interleaved, hbar = 1) as
+ * for tor_probability_displaced.  Each no-click step also moves the mean of
+ * the remaining modes, and every vacuum probability carries its mean-overlap
+ * factor; rel_err_bound includes the exponent factor (1 + mu^T Sigma^-1 mu)
+ * of each step's sum.  prec: AUTO, F64 or DD (TOR_PREC_QD: TOR_EINVAL).
+ * Errors as for gbs_chain_fixed, TOR_EINVAL also for a NULL mean or a
+ * non-finite mean entry of a measured mode. */
+tor_status gbs_chain_fixed_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m,
+                                     const int8_t *outcomes, tor_prec prec, double tol, double *step_p,
+                                     tor_result *total);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of probability queries.
  *

@@ -151,6 +151,8 @@ def lib():
                         ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(_CGbsStats)], ctypes.c_int32),
         "gbs_chain_fixed": ([vp, dp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double, dp,
                              ctypes.POINTER(_CResult)], ctypes.c_int32),
+        "gbs_chain_fixed_displaced": ([vp, dp, dp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double, dp,
+                                       ctypes.POINTER(_CResult)], ctypes.c_int32),
         "gbs_trace": ([vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
                        dp, dp, ctypes.POINTER(ctypes.c_uint8), i8p], ctypes.c_int32),
     }
@@ -287,8 +289,9 @@ class Context:
         _check(lib().tor_get_tuning(self._h, _PREC[prec], int(n), ctypes.byref(v)))
         return v.value
 
-    def chain_fixed(self, cov, outcomes, prec="dd", tol: float = 1e-10):
-        """The paper's fixed-outcome benchmark chain (gbs_chain_fixed): modes
+    def chain_fixed(self, cov, outcomes, prec="dd", tol: float = 1e-10, mean=None):
+        """The paper's fixed-outcome benchmark chain (gbs_chain_fixed, or
+        gbs_chain_fixed_displaced with a mean vector of 2m entries): modes
         measured from the last down; returns (Result for the whole pattern,
         step probabilities per mode, 1 for unmeasured modes)."""
         cov = _f64(cov)
@@ -298,8 +301,15 @@ class Context:
             raise ValueError("outcomes must have m entries")
         steps = np.empty(m, np.float64)
         out = _CResult()
-        _check(lib().gbs_chain_fixed(self._h, _dptr(cov), m, _i8ptr(outcomes), _PREC[prec], float(tol),
-                                     _dptr(steps), ctypes.byref(out)))
+        if mean is None:
+            _check(lib().gbs_chain_fixed(self._h, _dptr(cov), m, _i8ptr(outcomes), _PREC[prec], float(tol),
+                                         _dptr(steps), ctypes.byref(out)))
+        else:
+            mean = _f64(mean)
+            if mean.shape != (2 * m,):
+                raise ValueError("mean must have 2m entries")
+            _check(lib().gbs_chain_fixed_displaced(self._h, _dptr(cov), _dptr(mean), m, _i8ptr(outcomes),
+                                                   _PREC[prec], float(tol), _dptr(steps), ctypes.byref(out)))
         return Result._from(out), steps
 
     def gbs_sample(self, cov, n_post: int, seed: int, n_samples: int):

@@ -811,6 +811,36 @@ double bound_of(int used, int n, dd T, double A, double quad = 0.0) {
     return kBoundC * std::max(n, 1) * u * R * (1.0 + quad);
 }
 
+// mu^T Sigma^-1 mu of an n-mode packed matrix with its mean row first
+// (binary64 Cholesky of the covariance block; 0 for D = 0 or n = 0, +inf if
+// the block is not positive definite).
+double quad_of(const std::vector<dd> &packed, int n, int D) {
+    if (!D || n == 0) return 0.0;
+    const int d = 2 * n;
+    std::vector<double> L((size_t)d * d, 0.0), z(d);
+    double quad = 0.0;
+    for (int j = 0; j < d; j++) {
+        const dd djj = packed[(size_t)pidx(j + 1, j + 1)];
+        double sjj = djj.hi + djj.lo;
+        for (int t = 0; t < j; t++) sjj -= L[(size_t)j * d + t] * L[(size_t)j * d + t];
+        if (!(sjj > 0.0)) return INFINITY;
+        const double l = std::sqrt(sjj);
+        L[(size_t)j * d + j] = l;
+        for (int i = j + 1; i < d; i++) {
+            const dd dij = packed[(size_t)pidx(i + 1, j + 1)];
+            double v = dij.hi + dij.lo;
+            for (int t = 0; t < j; t++) v -= L[(size_t)i * d + t] * L[(size_t)j * d + t];
+            L[(size_t)i * d + j] = v / l;
+        }
+        const dd mu = packed[(size_t)pidx(j + 1, 0)];
+        double v = mu.hi + mu.lo;
+        for (int t = 0; t < j; t++) v -= L[(size_t)j * d + t] * z[t];
+        z[j] = v / l;
+        quad += z[j] * z[j];
+    }
+    return quad;
+}
+
 // Displaced state: `packed` is the conditioned matrix with its mean row
 // (EN(n, 1) entries).  PD check, log det Sigma_C and mu_C^T Sigma_C^-1 mu_C by
 // a binary64 Cholesky of the covariance block.
@@ -1589,13 +1619,15 @@ namespace {
 // snapshot of the clicked block after every step, then every step's subset
 // sum in shared launches (AUTO repeats in double-double the sums whose
 // binary64 bound exceeds tol).  roots[k] holds snapshot k, qv the q of each
-// no-click step, used[k] the term precision of step k.
-tor_status chain_sums_dd(tor_ctx *ctx, const double *cov, int m, const std::vector<int> &g,
+// no-click step, used[k] the term precision of step k.  With a mean vector
+// every packed matrix carries the mean row first (displaced states): the
+// conditioning moves the mean and q gains the mean-overlap factor.
+tor_status chain_sums_dd(tor_ctx *ctx, const double *cov, const double *mean, int m, const std::vector<int> &g,
                          const std::vector<int> &seq, const int8_t *outcomes, int nn, tor_prec prec, double tol,
                          std::vector<std::vector<dd>> &roots, std::vector<SumIn> &in, std::vector<SumOut> &res,
                          std::vector<int> &used, std::vector<double> &qv) {
-    const int nsteps = (int)seq.size(), nobs = nsteps;
-    const size_t EM = (size_t)E(nobs);
+    const int nsteps = (int)seq.size(), nobs = nsteps, D = mean ? 1 : 0;
+    const size_t EM = (size_t)EN(nobs, D);
     tor_status s = TOR_OK;
     // device buffer: matrix | acc (3) | q per no-click step (2 each) | snapshots | jobs
     std::vector<long long> snap_off(nsteps + 1), snap_n(nsteps + 1);
@@ -1606,7 +1638,7 @@ tor_status chain_sums_dd(tor_ctx *ctx, const double *cov, int m, const std::vect
             if (outcomes[seq[k]] == 1) c++;
             snap_n[k] = c;
             snap_off[k] = (long long)snap_tot;
-            snap_tot += (size_t)E(c);
+            snap_tot += (size_t)EN(c, D);
         }
     }
     const size_t o_acc = align_up(EM * sizeof(dd), 256);
@@ -1621,8 +1653,11 @@ tor_status chain_sums_dd(tor_ctx *ctx, const double *cov, int m, const std::vect
     std::vector<unsigned char> &stage = ctx->host_stage;
     if (stage.size() < bytes) stage.resize(bytes);
     dd *hm = (dd *)stage.data();
-    for (int a = 0; a < 2 * nobs; a++)
-        for (int b = 0; b <= a; b++) hm[pidx(a, b)] = sigq(cov, m, g[a], g[b]);
+    if (D) hm[0] = dd_from(0.0);
+    for (int a = 0; a < 2 * nobs; a++) {
+        if (D) hm[pidx(a + 1, 0)] = dd_from(mean[g[a]]);
+        for (int b = 0; b <= a; b++) hm[pidx(a + D, b + D)] = sigq(cov, m, g[a], g[b]);
+    }
     const double a0[3] = {1.0, 0.0, 0.0};
     std::memcpy(stage.data() + o_acc, a0, sizeof a0);
     CondJob *hj = (CondJob *)(stage.data() + o_jobs);
@@ -1636,6 +1671,7 @@ tor_status chain_sums_dd(tor_ctx *ctx, const double *cov, int m, const std::vect
             j.qout = (double *)(db + o_q) + 2 * t;
             j.begin = 0;
             j.r = r;
+            j.d = D;
             hj[t++] = j;
             r--;
         }
@@ -1649,12 +1685,13 @@ tor_status chain_sums_dd(tor_ctx *ctx, const double *cov, int m, const std::vect
         for (int k = 0; k < nsteps; k++) {
             if (outcomes[seq[k]] == 0) {
                 const CondJob &j = hj[t];
-                const long long blocks = std::max<long long>(1, (E(j.r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
+                const long long blocks =
+                    std::max<long long>(1, (EN(j.r - 1, D) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
                 HIP_TRY(tor_launch_condition((const CondJob *)(db + o_jobs) + t, 1, blocks, j.r, st));
                 t++;
             }
             if (snap_n[k] > 0)
-                HIP_TRY(hipMemcpyAsync(db + o_snap + snap_off[k] * sizeof(dd), dmat, sizeof(dd) * E(snap_n[k]),
+                HIP_TRY(hipMemcpyAsync(db + o_snap + snap_off[k] * sizeof(dd), dmat, sizeof(dd) * EN(snap_n[k], D),
                                        hipMemcpyDeviceToDevice, st));
         }
         ctx->stats.condition_launches += t;
@@ -1669,7 +1706,9 @@ tor_status chain_sums_dd(tor_ctx *ctx, const double *cov, int m, const std::vect
     const dd *snaps = (const dd *)(stage.data() + o_snap);
     for (int k = 0; k < nsteps; k++) {
         in[k].n = (int)snap_n[k];
-        roots[k].assign(snaps + snap_off[k], snaps + snap_off[k] + E(snap_n[k]));
+        in[k].D = D;
+        if (snap_n[k] > 0) roots[k].assign(snaps + snap_off[k], snaps + snap_off[k] + EN(snap_n[k], D));
+        else roots[k].assign((size_t)EN(0, D), dd_from(0.0));
         in[k].packed = &roots[k];
         which.push_back(k);
     }
@@ -1678,7 +1717,8 @@ tor_status chain_sums_dd(tor_ctx *ctx, const double *cov, int m, const std::vect
     if (prec == TOR_PREC_AUTO) {
         std::vector<int> redo;
         for (int k = 0; k < nsteps; k++)
-            if (in[k].n > 0 && !(bound_of(TOR_PREC_F64, in[k].n, res[k].T, res[k].A) <= tol)) redo.push_back(k);
+            if (in[k].n > 0 && !(bound_of(TOR_PREC_F64, in[k].n, res[k].T, res[k].A, quad_of(roots[k], in[k].n, D)) <= tol))
+                redo.push_back(k);
         if (!redo.empty()) {
             s = gpu_sums(ctx, in, redo, true, res);
             if (s) return s;
@@ -1812,14 +1852,23 @@ tor_status gbs_sample(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post
     return TOR_OK;
 }
 
-tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int8_t *outcomes, tor_prec prec,
-                           double tol, double *step_p, tor_result *total) {
+// gbs_chain_fixed and its displaced form (mean != NULL)
+static tor_status chain_fixed_impl(tor_ctx *ctx, const double *cov, const double *mean, int32_t m,
+                                   const int8_t *outcomes, tor_prec prec, double tol, double *step_p,
+                                   tor_result *total) {
     if (!ctx || !total) return fail(TOR_EINVAL, "NULL argument");
     if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD && prec != TOR_PREC_QD)
         return fail(TOR_EINVAL, "bad precision %d", (int)prec);
+    if (mean && prec == TOR_PREC_QD)
+        return fail(TOR_EINVAL, "quad-double terms take zero-mean states only");
     if (!(tol > 0.0)) tol = 1e-10;
     tor_status s = validate_cov_block(cov, m, outcomes);
     if (s) return s;
+    const int D = mean ? 1 : 0;
+    if (mean)
+        for (int j = 0; j < m; j++)
+            if (outcomes[j] >= 0 && !(std::isfinite(mean[2 * j]) && std::isfinite(mean[2 * j + 1])))
+                return fail(TOR_EINVAL, "mean of mode %d is not finite", j);
     // measurement sequence: modes m-1 .. 0 with an outcome; order of the matrix:
     // clicked modes in measurement order, then the no-click modes in reverse
     // measurement order (each no-click step conditions on the last mode)
@@ -1860,7 +1909,7 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
     if (prec == TOR_PREC_QD) {
         s = chain_sums_qd(ctx, cov, m, g, seq, outcomes, nn, roots, in, res, qv);
     } else {
-        s = chain_sums_dd(ctx, cov, m, g, seq, outcomes, nn, prec, tol, roots, in, res, used, qv);
+        s = chain_sums_dd(ctx, cov, mean, m, g, seq, outcomes, nn, prec, tol, roots, in, res, used, qv);
     }
     if (s) return s;
     // step probabilities: click T_k / T_{k-1}; no click q T_k / T_{k-1}
@@ -1881,7 +1930,7 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
         }
         if (step_p) step_p[seq[k]] = (num.hi + num.lo) / (prev.hi + prev.lo);
         if (in[k].n > 0) {
-            worst_bound = std::max(worst_bound, bound_of(used[k], in[k].n, T, res[k].A));
+            worst_bound = std::max(worst_bound, bound_of(used[k], in[k].n, T, res[k].A, quad_of(roots[k], in[k].n, D)));
             worst_R = std::max(worst_R, res[k].A / std::fabs(T.hi));
             worst_used = std::max(worst_used, used[k]);
         }
@@ -1902,7 +1951,8 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
         std::vector<dd> full((size_t)4 * nc * nc);
         const std::vector<dd> &pk = roots[nsteps - 1];
         for (int a = 0; a < 2 * nc; a++)
-            for (int b = 0; b <= a; b++) full[(size_t)a * 2 * nc + b] = full[(size_t)b * 2 * nc + a] = pk[pidx(a, b)];
+            for (int b = 0; b <= a; b++)
+                full[(size_t)a * 2 * nc + b] = full[(size_t)b * 2 * nc + a] = pk[pidx(a + D, b + D)];
         double ld = 0.0;
         if (f64_cholesky_logdet(full, 2 * nc, &ld)) total->tor = std::exp(0.5 * ld) * (prev.hi + prev.lo);
     } else {
@@ -1912,6 +1962,18 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
     total->prec_used = worst_used;
     total->status = total->rel_err_bound <= tol ? TOR_OK : TOR_WARN_PRECISION;
     return total->status;
+}
+
+tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int8_t *outcomes, tor_prec prec,
+                           double tol, double *step_p, tor_result *total) {
+    return chain_fixed_impl(ctx, cov, nullptr, m, outcomes, prec, tol, step_p, total);
+}
+
+tor_status gbs_chain_fixed_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m,
+                                     const int8_t *outcomes, tor_prec prec, double tol, double *step_p,
+                                     tor_result *total) {
+    if (!mean) return fail(TOR_EINVAL, "mean is NULL");
+    return chain_fixed_impl(ctx, cov, mean, m, outcomes, prec, tol, step_p, total);
 }
 
 tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,

@@ -115,3 +115,59 @@ def test_worst_case_l512_m16_quad_double(ctx):
     alt[j] = 1
     _, steps2 = ctx.chain_fixed(cov, alt, prec="qd")
     assert steps[j] + steps2[j] == pytest.approx(1.0, abs=1e-15)
+
+
+# ---------------------------------------------------------------- displaced states
+
+@pytest.mark.parametrize("pat", [
+    [1, 0, 1, 1, 0, -1, 1, 0],
+    [0, 0, 0, 1, 1, 1, 1, 0],
+    [-1, 1, -1, 0, 1, -1, 0, 1],
+])
+def test_displaced_steps_match_paper_rule(ctx, pat):
+    """gbs_chain_fixed_displaced against the oracle's mode-by-mode rule with
+    means (the no-click update moves the mean; 40-digit mpmath)."""
+    cov = gi.state_config1()
+    pat = np.array(pat, np.int8)
+    mu = gi.random_mean(8, np.random.default_rng(300), 0.5)
+    tot, steps = ctx.chain_fixed(cov, pat, prec="dd", mean=mu)
+    want_tot, want = oracle.prob_sequential(cov, pat, dps=40, steps=True, mean=mu)
+    for j in range(8):
+        if pat[j] < 0:
+            assert steps[j] == 1.0
+            continue
+        assert _rel(steps[j], want[j]) <= 1e-12, (j, steps[j], float(want[j]))
+    assert _rel(tot.p + tot.p_lo, want_tot) <= 1e-12
+    r = ctx.probability_displaced(cov, mu, pat, prec="dd")
+    assert _rel(tot.p + tot.p_lo, r.p + r.p_lo) <= 1e-12
+
+
+def test_displaced_coherent_chain_closed_form(ctx):
+    """Coherent states through an interferometer stay a product of coherent
+    states beta = U alpha: every step is independent of the history,
+    P(click) = 1 - exp(-|beta_j|^2)."""
+    rng = np.random.default_rng(301)
+    m = 24
+    U = gi.haar_unitary(m, rng)
+    beta = U @ (0.8 * (rng.standard_normal(m) + 1j * rng.standard_normal(m)))
+    cov = gi.gbs_covariance(U, np.zeros(m))
+    pat = rng.choice(np.array([0, 1], np.int8), m)
+    tot, steps = ctx.chain_fixed(cov, pat, prec="dd", mean=gi.coherent_mean(beta))
+    pv = np.exp(-np.abs(beta) ** 2)
+    want = np.where(pat == 1, 1 - pv, pv)
+    assert np.allclose(steps, want, rtol=1e-12, atol=0)
+    assert tot.p == pytest.approx(float(np.prod(want)), rel=1e-12)
+
+
+def test_displaced_chain_zero_mean_is_the_zero_mean_chain(ctx):
+    rng = np.random.default_rng(302)
+    m = 14
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), np.full(m, R8DB))
+    pat = rng.choice(np.array([-1, 0, 1], np.int8), m, p=[0.2, 0.5, 0.3])
+    a, sa = ctx.chain_fixed(cov, pat, prec="dd")
+    b, sb = ctx.chain_fixed(cov, pat, prec="dd", mean=np.zeros(2 * m))
+    assert np.array_equal(sa, sb)
+    assert (a.p, a.p_lo, a.T, a.T_lo) == (b.p, b.p_lo, b.T, b.T_lo)
+    with pytest.raises(tg.TorError) as ei:
+        ctx.chain_fixed(cov, pat, prec="qd", mean=np.zeros(2 * m))
+    assert ei.value.status == tg.TOR_EINVAL
