@@ -198,6 +198,15 @@ void tor_state_destroy(tor_state *st);
 tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *patterns, tor_prec prec,
                      double tol, tor_result *out);
 
+/* tor_batch for a displaced state: the state's covariance with the mean
+ * vector mean (host, 2m doubles, as for tor_probability_displaced) shared by
+ * all nq queries.  Zero-mean and displaced trees never share a launch; every
+ * result is bitwise that of tor_probability_displaced on the same query.
+ * Errors as for tor_batch (TOR_EINVAL also for a NULL mean; a non-finite
+ * mean entry of an observed mode fails that query with TOR_EINVAL). */
+tor_status tor_batch_displaced(tor_ctx *ctx, const tor_state *st, const double *mean, int32_t nq,
+                               const int8_t *patterns, tor_prec prec, double tol, tor_result *out);
+
 /* Stream-ordered form of tor_batch for callers whose patterns and results
  * live in device memory (e.g. torch tensors): d_patterns (nq x m int8, row
  * per query) and d_out (nq tor_result) are device pointers owned by the

@@ -137,6 +137,8 @@ def lib():
         "tor_state_destroy": ([vp], None),
         "tor_batch": ([vp, vp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
                        ctypes.POINTER(_CResult)], ctypes.c_int32),
+        "tor_batch_displaced": ([vp, vp, dp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
+                                 ctypes.POINTER(_CResult)], ctypes.c_int32),
         "tor_batch_async": ([vp, vp, ctypes.c_int32, vp, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int32),
         "tor_server_start": ([vp, ctypes.POINTER(_CServerOpts), ctypes.POINTER(vp)], ctypes.c_int32),
         "tor_submit": ([vp, vp, i8p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
@@ -346,6 +348,24 @@ class Context:
         nq = patterns.shape[0]
         out = (_CResult * max(nq, 1))()
         st = lib().tor_batch(self._h, state.handle, nq, _i8ptr(patterns), _PREC[prec], float(tol), out)
+        res = [Result._from(out[i]) for i in range(nq)]
+        if st < 0 and all(r.status < 0 for r in res):
+            raise TorError(st, last_error())
+        return res, st
+
+    def batch_displaced(self, state: "State", mean, patterns, prec="auto", tol: float = 1e-10):
+        """tor_batch_displaced: nq patterns on the state's covariance with the
+        given mean (2m entries); returns (results, status)."""
+        patterns = _i8(patterns)
+        mean = _f64(mean)
+        if patterns.ndim != 2 or patterns.shape[1] != state.m:
+            raise ValueError("patterns must be nq x m")
+        if mean.shape != (2 * state.m,):
+            raise ValueError("mean must have 2m entries")
+        nq = patterns.shape[0]
+        out = (_CResult * max(nq, 1))()
+        st = lib().tor_batch_displaced(self._h, state.handle, _dptr(mean), nq, _i8ptr(patterns), _PREC[prec],
+                                       float(tol), out)
         res = [Result._from(out[i]) for i in range(nq)]
         if st < 0 and all(r.status < 0 for r in res):
             raise TorError(st, last_error())

@@ -1406,6 +1406,39 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
     return evaluate_many(ctx, qs, prec, tol, out);
 }
 
+tor_status tor_batch_displaced(tor_ctx *ctx, const tor_state *st, const double *mean, int32_t nq,
+                               const int8_t *patterns, tor_prec prec, double tol, tor_result *out) {
+    if (!ctx || !st || !out || !mean || (nq > 0 && !patterns)) return fail(TOR_EINVAL, "NULL argument");
+    if (st->ctx != ctx) return fail(TOR_EINVAL, "state belongs to another context");
+    if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::vector<Prepared> qs((size_t)nq);
+    std::vector<Reduced> red((size_t)nq);
+    std::vector<Reduced *> rp;
+    for (int q = 0; q < nq; q++) {
+        tor_status s = reduce_pattern_disp(st->cov.data(), mean, st->m, patterns + (size_t)q * st->m, red[q]);
+        if (s != TOR_OK) qs[q].status = s;
+        else rp.push_back(&red[q]);
+    }
+    tor_status cs = condition_on_gpu(ctx, rp);
+    if (cs < 0) {
+        for (int q = 0; q < nq; q++) {
+            std::memset(&out[q], 0, sizeof out[q]);
+            out[q].status = cs;
+        }
+        return cs;
+    }
+    for (int q = 0; q < nq; q++) {
+        if (qs[q].status != TOR_OK) continue;
+        tor_status s = prepare_disp(std::move(red[q].packed), red[q].n, red[q].pvac, red[q].log_pvac, qs[q]);
+        if (s != TOR_OK) {
+            qs[q].status = s;
+            qs[q].n = 0;
+        }
+    }
+    return evaluate_many(ctx, qs, prec, tol, out);
+}
+
 tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *d_patterns, tor_prec prec,
                            double tol, tor_result *d_out, void *stream) {
     if (!ctx || !st) return fail(TOR_EINVAL, "NULL argument");

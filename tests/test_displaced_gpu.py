@@ -204,3 +204,34 @@ def test_displaced_not_positive_definite(ctx):
     with pytest.raises(tg.TorError) as ei:  # the bad mode conditioned away as a no-click mode
         ctx.probability_displaced(cov, np.ones(4), np.array([1, 0], np.int8))
     assert ei.value.status == tg.TOR_ENOTPD
+
+
+def test_batch_displaced_matches_single(ctx):
+    """tor_batch_displaced: marginal and full patterns of uneven size share
+    launches; every result is bitwise the single-query result, failures stay
+    per query."""
+    rng = np.random.default_rng(130)
+    m = 40
+    cov, _ = _haar_state(m, 131, r=0.5)
+    mean = gi.random_mean(m, rng, 0.5)
+    pats = []
+    for n in (0, 3, 9, 12, 15):
+        clicks = sorted(rng.choice(m, n, replace=False).tolist())
+        pats.append(gi.marginal_pattern(m, clicks))
+        pats.append(gi.full_pattern(m, clicks))
+    bad = np.full(m, -1, np.int8)
+    bad[0] = 2  # not a pattern value
+    pats.append(bad)
+    st = ctx.state(cov)
+    res, status = ctx.batch_displaced(st, mean, np.stack(pats), prec="dd")
+    assert status == tg.TOR_EINVAL
+    for p, r in zip(pats[:-1], res[:-1]):
+        s = ctx.probability_displaced(cov, mean, p, prec="dd")
+        assert (r.p, r.p_lo, r.T, r.T_lo, r.abs_sum, r.rel_err_bound) == (s.p, s.p_lo, s.T, s.T_lo, s.abs_sum,
+                                                                          s.rel_err_bound)
+        assert r.status == s.status
+    assert res[-1].status == tg.TOR_EINVAL
+    # a zero-mean batch and a displaced batch on the same state differ
+    z, _ = ctx.batch(st, np.stack(pats[:-1]), prec="dd")
+    assert any(a.p != b.p for a, b in zip(z, res[:-1]))
+    st.close()
