@@ -295,13 +295,17 @@ def dense_subgraph(ctx, n=200, p=0.5, clique=20, k=12, target_clicks=16.0, etas=
     return out
 
 
-def sampler_bench(ctx, n_samples=1000):
-    """The postselected sampling workload: m = 100, Haar U, r = 0.6, 12 clicks."""
+def sampler_bench(ctx, n_samples=1000, displaced=False):
+    """The postselected sampling workload: m = 100, Haar U, r = 0.6, 12 clicks
+    (displaced: the same state with mean 0.3 N(0, 1) per quadrature, seed 52)."""
+    import numpy as np
     import gbs_inputs as gi
     cov = gi.state_config2()
-    samples, st = ctx.gbs_sample(cov, 12, 2, n_samples)
+    mean = gi.random_mean(100, np.random.default_rng(52), 0.3) if displaced else None
+    samples, st = ctx.gbs_sample(cov, 12, 2, n_samples, mean=mean)
     assert (samples.sum(axis=1) == 12).all()
-    return {"workload": "m=100, Haar U, r=0.6, postselected on 12 clicks, seed 2",
+    return {"workload": "m=100, Haar U, r=0.6, postselected on 12 clicks, seed 2"
+                        + (", displaced (mean 0.3 N(0,1), seed 52)" if displaced else ""),
             "samples": n_samples, "seconds": st["seconds"], "samples_per_s": n_samples / st["seconds"],
             "chains": st["chains_started"], "acceptance": st["chains_accepted"] / st["chains_started"],
             "subset_dets_per_s": st["subsets"] / st["seconds"], "precision": "f64 terms, dd sums"}
@@ -483,6 +487,7 @@ def main():
         out["per_n_displaced_f64_terms"] = per_n_rates(ctx, cov, "f64", ns=(20, 24, 28),
                                                        mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
         out["sampler"] = sampler_bench(ctx)
+        out["sampler_displaced"] = sampler_bench(ctx, n_samples=200, displaced=True)
         out["paper_worst_case"] = paper_worst_case(ctx)
         out["paper_worst_case_qd"] = paper_worst_case(ctx, sizes=((16, 512), (18, 648), (20, 800)), prec="qd")
         out["dense_subgraph"] = dense_subgraph(ctx)

@@ -279,6 +279,23 @@ tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post,
                      int64_t chain_begin, int32_t nchains, double *p_click, double *uniform, uint8_t *outcome,
                      int8_t *status);
 
+/* gbs_sample and gbs_trace for a displaced Gaussian state: mean (host, 2m
+ * doubles, interleaved, hbar = 1, all finite) as for
+ * tor_probability_displaced.  The paper's sampling rule with non-zero means
+ * (Sec. II): each step's click probability is the ratio of two displaced
+ * vacuum sums, evaluated in the information form of the measured modes
+ * (K_j = sigma_Q[0..j]^-1 and h_j = K_j mu[0..j], double-double, rounded
+ * once), where every vacuum probability becomes a common factor times
+ * det(K[Z])^-1/2 exp(+h_Z^T K[Z]^-1 h_Z / 2) over the complementary set Z.
+ * Chains, coins, postselection and outputs as for the zero-mean calls; a
+ * zero mean gives the zero-mean results.  Errors as for gbs_sample /
+ * gbs_trace, TOR_EINVAL also for a NULL or non-finite mean. */
+tor_status gbs_sample_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m, int32_t n_post,
+                                uint64_t seed, int32_t n_samples, uint8_t *samples, gbs_stats *stats);
+tor_status gbs_trace_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m, int32_t n_post,
+                               uint64_t seed, int64_t chain_begin, int32_t nchains, double *p_click,
+                               double *uniform, uint8_t *outcome, int8_t *status);
+
 /* The paper's benchmark mode (Sec. III, "Runtime"): one sample whose
  * outcomes are fixed in advance, measured mode by mode from the last mode down
  * (Sec. II).  outcomes[m] (host) holds 1 = click, 0 = no click, -1 = not

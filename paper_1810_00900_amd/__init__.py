@@ -157,6 +157,10 @@ def lib():
                                        ctypes.POINTER(_CResult)], ctypes.c_int32),
         "gbs_trace": ([vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
                        dp, dp, ctypes.POINTER(ctypes.c_uint8), i8p], ctypes.c_int32),
+        "gbs_sample_displaced": ([vp, dp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                  ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(_CGbsStats)], ctypes.c_int32),
+        "gbs_trace_displaced": ([vp, dp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
+                                 ctypes.c_int32, dp, dp, ctypes.POINTER(ctypes.c_uint8), i8p], ctypes.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -314,28 +318,46 @@ class Context:
                                                    _PREC[prec], float(tol), _dptr(steps), ctypes.byref(out)))
         return Result._from(out), steps
 
-    def gbs_sample(self, cov, n_post: int, seed: int, n_samples: int):
-        """Exact chain-rule threshold samples (gbs_sample); returns
+    def gbs_sample(self, cov, n_post: int, seed: int, n_samples: int, mean=None):
+        """Exact chain-rule threshold samples (gbs_sample, or
+        gbs_sample_displaced with a mean vector of 2m entries); returns
         (samples uint8[n_samples, m], stats dict)."""
         cov = _f64(cov)
         m = cov.shape[0] // 2
         out = np.zeros((n_samples, m), dtype=np.uint8)
         st = _CGbsStats()
-        _check(lib().gbs_sample(self._h, _dptr(cov), m, int(n_post), int(seed) & (2**64 - 1), int(n_samples),
-                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(st)))
+        op = out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        if mean is None:
+            _check(lib().gbs_sample(self._h, _dptr(cov), m, int(n_post), int(seed) & (2**64 - 1), int(n_samples),
+                                    op, ctypes.byref(st)))
+        else:
+            mean = _f64(mean)
+            if mean.shape != (2 * m,):
+                raise ValueError("mean must have 2m entries")
+            _check(lib().gbs_sample_displaced(self._h, _dptr(cov), _dptr(mean), m, int(n_post),
+                                              int(seed) & (2**64 - 1), int(n_samples), op, ctypes.byref(st)))
         return out, {f: getattr(st, f) for f, _ in _CGbsStats._fields_}
 
-    def gbs_trace(self, cov, n_post: int, seed: int, chain_begin: int, nchains: int):
-        """Replay chains of gbs_sample: (p_click, uniform, outcome, status)."""
+    def gbs_trace(self, cov, n_post: int, seed: int, chain_begin: int, nchains: int, mean=None):
+        """Replay chains of gbs_sample (gbs_trace_displaced with a mean):
+        (p_click, uniform, outcome, status)."""
         cov = _f64(cov)
         m = cov.shape[0] // 2
         pc = np.zeros((nchains, m))
         un = np.zeros((nchains, m))
         oc = np.zeros((nchains, m), dtype=np.uint8)
         stt = np.zeros(nchains, dtype=np.int8)
-        _check(lib().gbs_trace(self._h, _dptr(cov), m, int(n_post), int(seed) & (2**64 - 1), int(chain_begin),
-                               int(nchains), _dptr(pc), _dptr(un), oc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
-                               _i8ptr(stt)))
+        op = oc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        if mean is None:
+            _check(lib().gbs_trace(self._h, _dptr(cov), m, int(n_post), int(seed) & (2**64 - 1), int(chain_begin),
+                                   int(nchains), _dptr(pc), _dptr(un), op, _i8ptr(stt)))
+        else:
+            mean = _f64(mean)
+            if mean.shape != (2 * m,):
+                raise ValueError("mean must have 2m entries")
+            _check(lib().gbs_trace_displaced(self._h, _dptr(cov), _dptr(mean), m, int(n_post),
+                                             int(seed) & (2**64 - 1), int(chain_begin), int(nchains), _dptr(pc),
+                                             _dptr(un), op, _i8ptr(stt)))
         return pc, un, oc, stt
 
     def state(self, cov) -> "State":

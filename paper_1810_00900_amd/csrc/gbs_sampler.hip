@@ -16,6 +16,15 @@
 // over the top decisions with rank-2 Schur updates in LDS), draws the coin from
 // Philox4x32-10 keyed by (seed, chain, mode), and stops early when the
 // postselection on n clicks can no longer be met.
+//
+// Displaced states (mean mu): in the same information form every vacuum
+// probability P_vac(S) = det(sigma_Q[S])^-1/2 exp(-mu_S^T sigma_Q[S]^-1 mu_S / 2)
+// becomes, with K = K_j and h = K mu[0..j], a common factor times
+// det(K[Sbar])^-1/2 exp(+h_Sbar^T K[Sbar]^-1 h_Sbar / 2), Sbar the complement
+// of S in modes 0..j (the quadratic form of a marginal in information form is
+// the full one minus the complement's).  The common factors cancel in the
+// ratio, so the same split tree runs over G with h[C + j] as a leading mean
+// row and pivot factors exp(+|w|^2 / 2) (tree mode D = -1).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -55,17 +64,19 @@ __device__ __forceinline__ double philox_uniform(unsigned long long seed, long l
 
 // Root split of a TL-mode tree for J <= 3 (one leaf): X0 = T(exclude last),
 // X1s = -q T(include last).
-template <class S, int R>
+template <class S, int R, int D>
 __device__ __forceinline__ void leaf_split(const S *M, dd &X0, dd &X1s) {
     if constexpr (R == 1) {
-        S q = rsqrt_s(det2(M[0], M[1], M[2]));
+        S q;
+        if constexpr (D == 0) q = rsqrt_s(det2(M[0], M[1], M[2]));
+        else q = make_pivot_m<S, D>(M, 1, 2).q;
         X0 = dd_from(1.0);
         X1s = dd_neg(to_dd(q));
     } else {
-        constexpr int p0 = 2 * R - 2, p1 = 2 * R - 1, RC = 2 * R - 2;
+        constexpr int p0 = 2 * R - 2 + MR(D), p1 = 2 * R - 1 + MR(D), RC = 2 * R - 2 + MR(D);
         double A0;
-        Leaf<S, R - 1>::run(M, X0, A0);
-        Pivot<S> pv = make_pivot(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)]);
+        Leaf<S, R - 1, D>::run(M, X0, A0);
+        Pivot<S> pv = make_pivot_m<S, D>(M, p0, p1);
         S v1[RC], v2[RC];
 #pragma unroll
         for (int c = 0; c < RC; ++c) {
@@ -73,24 +84,24 @@ __device__ __forceinline__ void leaf_split(const S *M, dd &X0, dd &X1s) {
             v1[c] = mul_s(m0, pv.s1);
             v2[c] = mul_s(sub_mul(M[pidx(p1, c)], pv.l, m0), pv.s2);
         }
-        S Cm[E(R - 1)];
+        S Cm[EN(R - 1, MR(D))];
 #pragma unroll
         for (int a = 0; a < RC; ++a)
 #pragma unroll
             for (int b = 0; b <= a; ++b) Cm[pidx(a, b)] = sub_dot2(M[pidx(a, b)], v1[a], v1[b], v2[a], v2[b]);
         dd T1;
         double A1;
-        Leaf<S, R - 1>::run(Cm, T1, A1);
+        Leaf<S, R - 1, D>::run(Cm, T1, A1);
         X1s = dd_neg(coef_mul(T1, pv.q));
     }
 }
 
 // Include-child of an r-mode node in LDS (cooperative rank-2 Schur update of
 // the last mode); returns q.  in and out must not overlap.
-template <class S>
+template <class S, int D>
 __device__ __forceinline__ S wave_schur_last(const S *in, int r, S *out, S *vt, int lane) {
-    const int R = 2 * r, RC = R - 2, EC = E(r - 1);
-    Pivot<S> pv = make_pivot(in[pidx(R - 2, R - 2)], in[pidx(R - 1, R - 2)], in[pidx(R - 1, R - 1)]);
+    const int R = 2 * r + MR(D), RC = R - 2, EC = EN(r - 1, MR(D));
+    Pivot<S> pv = make_pivot_m<S, D>(in, R - 2, R - 1);
     for (int c = lane; c < RC; c += 64) {
         S m0 = in[pidx(R - 2, c)];
         vt[c] = mul_s(m0, pv.s1);
@@ -106,25 +117,25 @@ __device__ __forceinline__ S wave_schur_last(const S *in, int r, S *out, S *vt, 
     return pv.q;
 }
 
-template <class S, int J> struct ChainStep {
+template <class S, int J, int D> struct ChainStep {
     // tree of the k = J modes already gathered into the wave LDS (k <= 9)
     static __device__ __forceinline__ void run(unsigned char *raw, int lane, dd &X0, dd &X1s) {
-        using C = WaveCfg<S, J>;
-        WaveSmem<S, J> &sm = *reinterpret_cast<WaveSmem<S, J> *>(raw);
+        using C = WaveCfg<S, J, D>;
+        WaveSmem<S, J, D> &sm = *reinterpret_cast<WaveSmem<S, J, D> *>(raw);
         if constexpr (C::TW == 0) {
             X0 = dd_from(0.0);
             X1s = dd_from(0.0);
             if (lane == 0) {
-                S M[E(J)];
+                S M[EN(J, MR(D))];
 #pragma unroll
-                for (int e = 0; e < E(J); ++e) M[e] = sm.mat[e];
-                leaf_split<S, J>(M, X0, X1s);
+                for (int e = 0; e < EN(J, MR(D)); ++e) M[e] = sm.mat[e];
+                leaf_split<S, J, D>(M, X0, X1s);
             }
             wave_sync();
         } else {
             dd T;
             double A;
-            wave_tree<S, J>(sm, dd_from(1.0), 1.0, lane, T, A);
+            wave_tree<S, J, D>(sm, dd_from(1.0), 1.0, lane, T, A);
             X0 = (lane & 1) ? dd_from(0.0) : T;
             X1s = (lane & 1) ? T : dd_from(0.0);
             wave_sync();
@@ -132,22 +143,24 @@ template <class S, int J> struct ChainStep {
     }
 };
 
-template <class S> struct ChainLds {
-    static constexpr size_t wave_bytes = sizeof(WaveSmem<S, 9>);
+template <class S, int D> struct ChainLds {
+    static constexpr size_t wave_bytes = sizeof(WaveSmem<S, 9, D>);
 };
 
 // KMAX: largest step tree (clicks so far + 1) the kernel's LDS holds; two
 // instances, so that chains with few clicks keep the smaller footprint.
-template <class S, int KMAX>
+// D = 0: zero-mean state; D = -1: displaced state (mean row h = K_j mu).
+template <class S, int KMAX, int D>
 __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
-    __shared__ __align__(16) unsigned char raw[ChainLds<S>::wave_bytes];
-    __shared__ S gbuf[3][E(KMAX)];
+    constexpr int O = MR(D);  // mean rows
+    __shared__ __align__(16) unsigned char raw[ChainLds<S, D>::wave_bytes];
+    __shared__ S gbuf[3][EN(KMAX, O)];
     __shared__ S vt[4 * KMAX];
     __shared__ int Cl[KMAX + 1];
     const int lane = threadIdx.x;
-    // ab[] then mat[] sit at the same offsets in WaveSmem<S, J> for every J
-    S *wmat = reinterpret_cast<WaveSmem<S, 9> *>(raw)->mat;
-    wave_tree_init(reinterpret_cast<WaveSmem<S, 9> *>(raw)->ab, lane);
+    // ab[] then mat[] sit at the same offsets in WaveSmem<S, J, D> for every J
+    S *wmat = reinterpret_cast<WaveSmem<S, 9, D> *>(raw)->mat;
+    wave_tree_init<D>(reinterpret_cast<WaveSmem<S, 9, D> *>(raw)->ab, lane);
     for (int ci = blockIdx.x; ci < P.nchains; ci += gridDim.x) {
         const long long chain = P.chain_begin + ci;
         int nc = 0;
@@ -164,34 +177,42 @@ __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
                 break;
             }
             const int k = nc + 1;
-            const int D = 2 * j + 2;
+            const int ld = 2 * j + 2;
             const double *Kj = P.K + P.koff[j];
             S *G = k <= 9 ? wmat : gbuf[0];
-            for (int e = lane; e < E(k); e += 64) {
+            for (int e = lane; e < EN(k, O); e += 64) {
                 int a, b;
                 unpack(e, a, b);
+                if (O && b == 0) {  // the mean column: h_j of the row's quadrature (0 at the corner)
+                    const int aa = a - 1;
+                    const int ma = (aa >> 1) < nc ? Cl[aa >> 1] : j;
+                    G[e] = a == 0 ? from_pair<S>(0.0, 0.0) : from_pair<S>(P.H[P.hoff[j] + 2 * ma + (aa & 1)], 0.0);
+                    continue;
+                }
+                a -= O;
+                b -= O;
                 const int ma = (a >> 1) < nc ? Cl[a >> 1] : j;
                 const int mb = (b >> 1) < nc ? Cl[b >> 1] : j;
-                G[e] = (S)from_pair<S>(Kj[(2 * ma + (a & 1)) * D + 2 * mb + (b & 1)], 0.0);
+                G[e] = (S)from_pair<S>(Kj[(2 * ma + (a & 1)) * ld + 2 * mb + (b & 1)], 0.0);
             }
             wave_sync();
             dd X0 = dd_from(0.0), X1s = dd_from(0.0);
             if (k <= 9) {
                 switch (k) {
-                case 1: ChainStep<S, 1>::run(raw, lane, X0, X1s); break;
-                case 2: ChainStep<S, 2>::run(raw, lane, X0, X1s); break;
-                case 3: ChainStep<S, 3>::run(raw, lane, X0, X1s); break;
-                case 4: ChainStep<S, 4>::run(raw, lane, X0, X1s); break;
-                case 5: ChainStep<S, 5>::run(raw, lane, X0, X1s); break;
-                case 6: ChainStep<S, 6>::run(raw, lane, X0, X1s); break;
-                case 7: ChainStep<S, 7>::run(raw, lane, X0, X1s); break;
-                case 8: ChainStep<S, 8>::run(raw, lane, X0, X1s); break;
-                default: ChainStep<S, 9>::run(raw, lane, X0, X1s); break;
+                case 1: ChainStep<S, 1, D>::run(raw, lane, X0, X1s); break;
+                case 2: ChainStep<S, 2, D>::run(raw, lane, X0, X1s); break;
+                case 3: ChainStep<S, 3, D>::run(raw, lane, X0, X1s); break;
+                case 4: ChainStep<S, 4, D>::run(raw, lane, X0, X1s); break;
+                case 5: ChainStep<S, 5, D>::run(raw, lane, X0, X1s); break;
+                case 6: ChainStep<S, 6, D>::run(raw, lane, X0, X1s); break;
+                case 7: ChainStep<S, 7, D>::run(raw, lane, X0, X1s); break;
+                case 8: ChainStep<S, 8, D>::run(raw, lane, X0, X1s); break;
+                default: ChainStep<S, 9, D>::run(raw, lane, X0, X1s); break;
                 }
             } else {
                 // decisions on the top u = k - 9 modes (bit b: mode k-1-b; bit 0 is mode j)
                 const int u = k - 9;
-                WaveSmem<S, 9> &sm = *reinterpret_cast<WaveSmem<S, 9> *>(raw);
+                WaveSmem<S, 9, D> &sm = *reinterpret_cast<WaveSmem<S, 9, D> *>(raw);
                 for (int p = 0; p < (1 << u); ++p) {
                     const S *cur = gbuf[0];
                     int r = k, nb = 1;
@@ -200,18 +221,18 @@ __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
                     for (int b = 0; b < u; ++b, --r) {
                         if ((p >> b) & 1) {
                             S *o = gbuf[nb];
-                            S q = wave_schur_last<S>(cur, r, o, vt, lane);
+                            S q = wave_schur_last<S, D>(cur, r, o, vt, lane);
                             c = dd_neg(coef_mul(c, q));
                             a *= hi_of(q);
                             cur = o;
                             nb = 3 - nb;
                         }
                     }
-                    for (int e = lane; e < E(9); e += 64) sm.mat[e] = cur[e];
+                    for (int e = lane; e < EN(9, O); e += 64) sm.mat[e] = cur[e];
                     wave_sync();
                     dd T;
                     double A;
-                    wave_tree<S, 9>(sm, c, a, lane, T, A);
+                    wave_tree<S, 9, D>(sm, c, a, lane, T, A);
                     if (p & 1) X1s = dd_add(X1s, T);
                     else X0 = dd_add(X0, T);
                     wave_sync();
@@ -257,9 +278,14 @@ hipError_t tor_launch_chains(const ChainParams &P, int grid_cap, hipStream_t st)
     int g = P.nchains < grid_cap ? P.nchains : grid_cap;
     if (g < 1) return hipSuccess;
     (void)hipGetLastError();  // report only this launch's error
-    if (P.cap + 1 <= TOR_CHAIN_MAX)
-        hipLaunchKernelGGL((tor::chain_kernel<double, TOR_CHAIN_MAX>), dim3((unsigned)g), dim3(64), 0, st, P);
+    const bool small = P.cap + 1 <= TOR_CHAIN_MAX;
+    if (P.H && small)
+        hipLaunchKernelGGL((tor::chain_kernel<double, TOR_CHAIN_MAX, -1>), dim3((unsigned)g), dim3(64), 0, st, P);
+    else if (P.H)
+        hipLaunchKernelGGL((tor::chain_kernel<double, TOR_CHAIN_MAX_BIG, -1>), dim3((unsigned)g), dim3(64), 0, st, P);
+    else if (small)
+        hipLaunchKernelGGL((tor::chain_kernel<double, TOR_CHAIN_MAX, 0>), dim3((unsigned)g), dim3(64), 0, st, P);
     else
-        hipLaunchKernelGGL((tor::chain_kernel<double, TOR_CHAIN_MAX_BIG>), dim3((unsigned)g), dim3(64), 0, st, P);
+        hipLaunchKernelGGL((tor::chain_kernel<double, TOR_CHAIN_MAX_BIG, 0>), dim3((unsigned)g), dim3(64), 0, st, P);
     return hipGetLastError();
 }

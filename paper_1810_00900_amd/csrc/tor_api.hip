@@ -98,7 +98,7 @@ struct tor_ctx {
     DevBuf apool, abuf;  // tor_batch_async: tree pool, plan and job tables
     size_t async_pool = (size_t)4 << 30;
     int chain_clicks = 15;  // click cap of chains without postselection
-    DevBuf kbuf, koff, c_out, c_status, c_tp, c_tu, c_sub;
+    DevBuf kbuf, koff, hbuf, hoff, c_out, c_status, c_tp, c_tu, c_sub;
     Partial *host_res = nullptr;
     size_t host_res_cap = 0;
     std::vector<unsigned char> host_jobs, host_stage;
@@ -1554,7 +1554,9 @@ namespace {
 // sigma_Q = L L^T: with M = L^-1 (lower triangular) the leading block of M is
 // the inverse factor of the leading block, so K_j[a][b] = sum_{t <= 2j+1}
 // M[t][a] M[t][b], accumulated row pair by row pair.  Rounded to binary64.
-tor_status build_k_tables(const double *cov, int m, std::vector<double> &K, std::vector<unsigned long long> &koff) {
+tor_status build_k_tables(const double *cov, int m, std::vector<double> &K, std::vector<unsigned long long> &koff,
+                          const double *mean = nullptr, std::vector<double> *H = nullptr,
+                          std::vector<unsigned long long> *hoff = nullptr) {
     const int d = 2 * m;
     std::vector<dd> L((size_t)d * d), rinv;
     for (int a = 0; a < d; a++)
@@ -1576,14 +1578,31 @@ tor_status build_k_tables(const double *cov, int m, std::vector<double> &K, std:
     koff.assign(m + 1, 0);
     for (int j = 0; j < m; j++) koff[j + 1] = koff[j] + (unsigned long long)(2 * j + 2) * (2 * j + 2);
     K.assign(koff[m], 0.0);
+    // displaced states: h_j = K_j mu[0..2j+1] = sum_{t < 2j+2} M[t]^T (M[t] . mu),
+    // accumulated row pair by row pair like K_j (z_t = M[t] . mu)
+    std::vector<dd> z, hacc;
+    if (mean) {
+        z.assign(d, dd_from(0.0));
+        for (int t = 0; t < d; t++)
+            for (int b = 0; b <= t; b++) z[t] = dd_add(z[t], dd_mul(Mi[(size_t)t * d + b], dd_from(mean[b])));
+        hacc.assign(d, dd_from(0.0));
+        hoff->assign(m + 1, 0);
+        for (int j = 0; j < m; j++) (*hoff)[j + 1] = (*hoff)[j] + (unsigned long long)(2 * j + 2);
+        H->assign((*hoff)[m], 0.0);
+    }
     std::vector<dd> acc((size_t)d * d, dd_from(0.0));
     for (int j = 0; j < m; j++) {
         const int D = 2 * j + 2;
-        for (int t = 2 * j; t < D; t++)
+        for (int t = 2 * j; t < D; t++) {
             for (int a = 0; a <= t; a++)
                 for (int b = 0; b <= a; b++)
                     acc[(size_t)a * d + b] =
                         dd_add(acc[(size_t)a * d + b], dd_mul(Mi[(size_t)t * d + a], Mi[(size_t)t * d + b]));
+            if (mean)
+                for (int a = 0; a <= t; a++) hacc[a] = dd_add(hacc[a], dd_mul(Mi[(size_t)t * d + a], z[t]));
+        }
+        if (mean)
+            for (int a = 0; a < D; a++) (*H)[(*hoff)[j] + a] = hacc[a].hi + hacc[a].lo;
         double *Kj = K.data() + koff[j];
         for (int a = 0; a < D; a++)
             for (int b = 0; b <= a; b++) {
@@ -1594,11 +1613,19 @@ tor_status build_k_tables(const double *cov, int m, std::vector<double> &K, std:
     return TOR_OK;
 }
 
-tor_status upload_chain_tables(tor_ctx *ctx, const double *cov, int m) {
-    std::vector<double> K;
-    std::vector<unsigned long long> koff;
-    tor_status s = build_k_tables(cov, m, K, koff);
+tor_status upload_chain_tables(tor_ctx *ctx, const double *cov, int m, const double *mean = nullptr) {
+    std::vector<double> K, H;
+    std::vector<unsigned long long> koff, hoff;
+    tor_status s = build_k_tables(cov, m, K, koff, mean, &H, &hoff);
     if (s) return s;
+    if (mean) {
+        if (ctx->hbuf.ensure(H.size() * sizeof(double)) != hipSuccess ||
+            ctx->hoff.ensure(hoff.size() * sizeof(unsigned long long)) != hipSuccess)
+            return fail(TOR_ENOMEM, "device allocation of the mean tables failed");
+        HIP_TRY(hipMemcpyAsync(ctx->hbuf.p, H.data(), H.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(ctx->hoff.p, hoff.data(), hoff.size() * sizeof(unsigned long long),
+                               hipMemcpyHostToDevice, ctx->stream));
+    }
     if (ctx->kbuf.ensure(K.size() * sizeof(double)) != hipSuccess ||
         ctx->koff.ensure(koff.size() * sizeof(unsigned long long)) != hipSuccess)
         return fail(TOR_ENOMEM, "device allocation of the K tables failed");
@@ -1609,16 +1636,22 @@ tor_status upload_chain_tables(tor_ctx *ctx, const double *cov, int m) {
     return TOR_OK;
 }
 
-tor_status check_sampler_args(const double *cov, int m, int n_post) {
+tor_status check_sampler_args(const double *cov, int m, int n_post, const double *mean = nullptr,
+                              bool displaced = false) {
     tor_status s = validate_cov(cov, m);
     if (s) return s;
+    if (displaced && !mean) return fail(TOR_EINVAL, "mean is NULL");
+    if (mean)
+        for (int i = 0; i < 2 * m; i++)
+            if (!std::isfinite(mean[i])) return fail(TOR_EINVAL, "mean[%d] is not finite", i);
     if (m > 1024) return fail(TOR_ETOOBIG, "m = %d > 1024 for the sampler", m);
     if (n_post > TOR_CHAIN_CLICKS) return fail(TOR_ETOOBIG, "n_post = %d > %d", n_post, TOR_CHAIN_CLICKS);
     if (n_post > m) return fail(TOR_EINVAL, "n_post > m");
     return TOR_OK;
 }
 
-tor_status run_chains(tor_ctx *ctx, int m, int n_post, uint64_t seed, long long begin, int nchains, bool trace) {
+tor_status run_chains(tor_ctx *ctx, int m, int n_post, uint64_t seed, long long begin, int nchains, bool trace,
+                      bool displaced = false) {
     const size_t nm = (size_t)nchains * (size_t)m;
     if (ctx->c_out.ensure(nm) != hipSuccess || ctx->c_status.ensure((size_t)nchains) != hipSuccess ||
         ctx->c_sub.ensure((size_t)nchains * sizeof(double)) != hipSuccess ||
@@ -1628,6 +1661,8 @@ tor_status run_chains(tor_ctx *ctx, int m, int n_post, uint64_t seed, long long 
     ChainParams P;
     P.K = (const double *)ctx->kbuf.p;
     P.koff = (const unsigned long long *)ctx->koff.p;
+    P.H = displaced ? (const double *)ctx->hbuf.p : nullptr;  // null selects the zero-mean kernels
+    P.hoff = displaced ? (const unsigned long long *)ctx->hoff.p : nullptr;
     P.m = m;
     P.n_post = n_post;
     P.cap = n_post >= 0 ? n_post : ctx->chain_clicks;
@@ -1836,15 +1871,16 @@ tor_status chain_sums_qd(tor_ctx *ctx, const double *cov, int m, const std::vect
 
 extern "C" {
 
-tor_status gbs_sample(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,
-                      int32_t n_samples, uint8_t *samples, gbs_stats *stats) {
+// gbs_sample and its displaced form (mean != NULL)
+static tor_status sample_impl(tor_ctx *ctx, const double *cov, const double *mean, int32_t m, int32_t n_post,
+                              uint64_t seed, int32_t n_samples, uint8_t *samples, gbs_stats *stats) {
     if (!ctx) return fail(TOR_EINVAL, "ctx is NULL");
     if (n_samples < 0 || (n_samples > 0 && !samples)) return fail(TOR_EINVAL, "bad samples buffer");
-    tor_status s = check_sampler_args(cov, m, n_post);
+    tor_status s = check_sampler_args(cov, m, n_post, mean, mean != nullptr);
     if (s) return s;
     HIP_TRY(hipSetDevice(ctx->device));
     auto t0 = std::chrono::steady_clock::now();
-    s = upload_chain_tables(ctx, cov, m);
+    s = upload_chain_tables(ctx, cov, m, mean);
     if (s) return s;
     const int NB = 16384;
     std::vector<unsigned char> out((size_t)NB * m);
@@ -1855,7 +1891,7 @@ tor_status gbs_sample(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post
     int got = 0;
     while (got < n_samples) {
         if (begin >= (1LL << 31)) return fail(TOR_EAGAIN, "no %d accepted samples within 2^31 chains", n_samples);
-        s = run_chains(ctx, m, n_post, seed, begin, NB, false);
+        s = run_chains(ctx, m, n_post, seed, begin, NB, false, mean != nullptr);
         if (s) return s;
         HIP_TRY(hipMemcpyAsync(out.data(), ctx->c_out.p, out.size(), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipMemcpyAsync(st.data(), ctx->c_status.p, st.size(), hipMemcpyDeviceToHost, ctx->stream));
@@ -1883,6 +1919,17 @@ tor_status gbs_sample(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post
         stats->subsets = subsets;
     }
     return TOR_OK;
+}
+
+tor_status gbs_sample(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,
+                      int32_t n_samples, uint8_t *samples, gbs_stats *stats) {
+    return sample_impl(ctx, cov, nullptr, m, n_post, seed, n_samples, samples, stats);
+}
+
+tor_status gbs_sample_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m, int32_t n_post,
+                                uint64_t seed, int32_t n_samples, uint8_t *samples, gbs_stats *stats) {
+    if (!mean) return fail(TOR_EINVAL, "mean is NULL");
+    return sample_impl(ctx, cov, mean, m, n_post, seed, n_samples, samples, stats);
 }
 
 // gbs_chain_fixed and its displaced form (mean != NULL)
@@ -2009,18 +2056,19 @@ tor_status gbs_chain_fixed_displaced(tor_ctx *ctx, const double *cov, const doub
     return chain_fixed_impl(ctx, cov, mean, m, outcomes, prec, tol, step_p, total);
 }
 
-tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,
-                     int64_t chain_begin, int32_t nchains, double *p_click, double *uniform, uint8_t *outcome,
-                     int8_t *status) {
+// gbs_trace and its displaced form (mean != NULL)
+static tor_status trace_impl(tor_ctx *ctx, const double *cov, const double *mean, int32_t m, int32_t n_post,
+                             uint64_t seed, int64_t chain_begin, int32_t nchains, double *p_click, double *uniform,
+                             uint8_t *outcome, int8_t *status) {
     if (!ctx) return fail(TOR_EINVAL, "ctx is NULL");
     if (nchains < 0 || chain_begin < 0) return fail(TOR_EINVAL, "bad chain range");
-    tor_status s = check_sampler_args(cov, m, n_post);
+    tor_status s = check_sampler_args(cov, m, n_post, mean, mean != nullptr);
     if (s) return s;
     if (nchains == 0) return TOR_OK;
     HIP_TRY(hipSetDevice(ctx->device));
-    s = upload_chain_tables(ctx, cov, m);
+    s = upload_chain_tables(ctx, cov, m, mean);
     if (s) return s;
-    s = run_chains(ctx, m, n_post, seed, chain_begin, nchains, true);
+    s = run_chains(ctx, m, n_post, seed, chain_begin, nchains, true, mean != nullptr);
     if (s) return s;
     const size_t nm = (size_t)nchains * m;
     if (p_click)
@@ -2031,6 +2079,19 @@ tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post,
     if (status) HIP_TRY(hipMemcpyAsync(status, ctx->c_status.p, (size_t)nchains, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return TOR_OK;
+}
+
+tor_status gbs_trace(tor_ctx *ctx, const double *cov, int32_t m, int32_t n_post, uint64_t seed,
+                     int64_t chain_begin, int32_t nchains, double *p_click, double *uniform, uint8_t *outcome,
+                     int8_t *status) {
+    return trace_impl(ctx, cov, nullptr, m, n_post, seed, chain_begin, nchains, p_click, uniform, outcome, status);
+}
+
+tor_status gbs_trace_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m, int32_t n_post,
+                               uint64_t seed, int64_t chain_begin, int32_t nchains, double *p_click,
+                               double *uniform, uint8_t *outcome, int8_t *status) {
+    if (!mean) return fail(TOR_EINVAL, "mean is NULL");
+    return trace_impl(ctx, cov, mean, m, n_post, seed, chain_begin, nchains, p_click, uniform, outcome, status);
 }
 
 }  // extern "C"

@@ -180,6 +180,8 @@ hipError_t tor_launch_condition_qd(const CondJobQ *jobs, int njobs, long long to
 struct ChainParams {
     const double *K;                 // K_j, full row-major (2j+2)^2, concatenated
     const unsigned long long *koff;  // offset of K_j in K
+    const double *H;                 // displaced states: h_j = K_j mu[0..2j+1], concatenated (else null)
+    const unsigned long long *hoff;  // offset of h_j in H
     int m;
     int n_post;                      // < 0: no postselection
     int cap;                         // most clicks a chain may carry (<= TOR_CHAIN_MAX_BIG - 1)

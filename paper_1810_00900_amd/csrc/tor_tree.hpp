@@ -25,6 +25,12 @@ __host__ __device__ constexpr int E(int r) { return r * (2 * r + 1); }
 // mode k); the Schur update of the pivot block then moves the mean exactly as
 // the no-click update of Sec. II does.  D = 0: the plain 2r x 2r matrix.
 __host__ __device__ constexpr int EN(int r, int D) { return (2 * r + D) * (2 * r + D + 1) / 2; }
+// Mean-row mode of the tree templates: D = 0 no mean row; D = 1 a mean row
+// whose pivots carry exp(-|w|^2 / 2) (vacuum overlap of a displaced mode);
+// D = -1 a mean row whose pivots carry exp(+|w|^2 / 2) (the information-form
+// trees of the sampler, where the row holds K mu instead of mu).  MR(D) is
+// the number of mean rows.
+__host__ __device__ constexpr int MR(int D) { return D != 0 ? 1 : 0; }
 __host__ __device__ constexpr int pidx(int a, int b) { return a * (a + 1) / 2 + b; }
 
 // packed lower-triangle index -> (row, column)
@@ -86,11 +92,11 @@ __device__ __forceinline__ Pivot<S> make_pivot(S al, S be, S ga) {
 template <class S, int D>
 __device__ __forceinline__ Pivot<S> make_pivot_m(const S *M, int p0, int p1) {
     Pivot<S> pv = make_pivot(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)]);
-    if constexpr (D == 1) {
+    if constexpr (D != 0) {
         const S m0 = M[pidx(p0, 0)];
         const S w1 = mul_s(m0, pv.s1);
         const S w2 = mul_s(sub_mul(M[pidx(p1, 0)], pv.l, m0), pv.s2);
-        pv.q = mul_s(pv.q, exp_s(scale_s(add_s(mul_s(w1, w1), mul_s(w2, w2)), -0.5)));
+        pv.q = mul_s(pv.q, exp_s(scale_s(add_s(mul_s(w1, w1), mul_s(w2, w2)), D > 0 ? -0.5 : 0.5)));
     }
     return pv;
 }
@@ -128,7 +134,7 @@ __device__ __forceinline__ qd acc_one_minus(qd q) { return qd_sub(qd_from(1.0), 
 template <class S, int R, int D = 0> struct Leaf {
     using Acc = typename AccOf<S>::type;
     static __device__ __forceinline__ void run(const S *M, Acc &T, double &A) {
-        constexpr int p0 = 2 * R - 2 + D, p1 = 2 * R - 1 + D, RC = 2 * R - 2 + D;
+        constexpr int p0 = 2 * R - 2 + MR(D), p1 = 2 * R - 1 + MR(D), RC = 2 * R - 2 + MR(D);
         Acc T0;
         double A0;
         Leaf<S, R - 1, D>::run(M, T0, A0);  // exclude: the prefix of M
@@ -140,7 +146,7 @@ template <class S, int R, int D = 0> struct Leaf {
             v1[c] = mul_s(m0, pv.s1);
             v2[c] = mul_s(sub_mul(M[pidx(p1, c)], pv.l, m0), pv.s2);
         }
-        S C[EN(R - 1, D)];
+        S C[EN(R - 1, MR(D))];
 #pragma unroll
         for (int a = 0; a < RC; ++a)
 #pragma unroll
@@ -159,7 +165,7 @@ template <class S, int D> struct Leaf<S, 1, D> {
     static __device__ __forceinline__ void run(const S *M, Acc &T, double &A) {
         S q;
         if constexpr (D == 0) q = rsqrt_s(det2(M[0], M[1], M[2]));
-        else q = make_pivot_m<S, 1>(M, 1, 2).q;
+        else q = make_pivot_m<S, D>(M, 1, 2).q;
         T = acc_one_minus(q);
         A = 1.0 + hi_of(q);
     }
@@ -216,15 +222,15 @@ template <class S, int J, int D = 0> struct WaveCfg {
     static constexpr int NL = 1 << TW;          // leaves (<= 64), one per lane
     // LDS slot offsets: slot base for include children created at level k
     static constexpr int soff(int k) {
-        int o = EN(J, D);
-        for (int kk = 0; kk < k; ++kk) o += (1 << kk) * EN(J - kk - 1, D);
+        int o = EN(J, MR(D));
+        for (int kk = 0; kk < k; ++kk) o += (1 << kk) * EN(J - kk - 1, MR(D));
         return o;
     }
     static constexpr int MAT = soff(TWC);
     static constexpr int vmax() {
         int m = 1;
         for (int k = 0; k < TWC; ++k) {
-            int v = (1 << k) * 2 * (2 * (J - k) - 2 + D);
+            int v = (1 << k) * 2 * (2 * (J - k) - 2 + MR(D));
             if (v > m) m = v;
         }
         return m;
@@ -244,7 +250,7 @@ template <class S, int J, int K, int D = 0> struct WaveLevel {
     static __device__ __forceinline__ void run(const unsigned short *ab, S *mat, S *vbuf, Pivot<S> *piv, int *loc,
                                                Acc *coef, double *acoef, int lane) {
         if constexpr (K < C::TWC) {
-            constexpr int r = J - K, R = 2 * r + D, NK = 1 << K, RC = R - 2, EC = EN(r - 1, D);
+            constexpr int r = J - K, R = 2 * r + MR(D), NK = 1 << K, RC = R - 2, EC = EN(r - 1, MR(D));
             // phase 0: pivot of each node, coefficients and slots of the include children
             if (lane < NK) {
                 const S *base = mat + loc[lane];
@@ -326,7 +332,7 @@ __device__ __forceinline__ int find_job(const Job *jobs, int njobs, long long t)
 // first and mat second, at the same offsets for every J.
 template <class S, int J, int D = 0> struct WaveSmem {
     using C = WaveCfg<S, J, D>;
-    unsigned short ab[ab_n(D)];
+    unsigned short ab[ab_n(MR(D))];
     S mat[C::MAT];
     S vbuf[C::VMAX];
     Pivot<S> piv[C::NPIV];
@@ -338,7 +344,7 @@ template <class S, int J, int D = 0> struct WaveSmem {
 // Fill the packed-index table (once per workgroup, before the first tree).
 template <int D = 0>
 __device__ __forceinline__ void wave_tree_init(unsigned short *ab, int lane) {
-    for (int e = lane; e < ab_n(D); e += 64) {
+    for (int e = lane; e < ab_n(MR(D)); e += 64) {
         int a, b;
         unpack(e, a, b);
         ab[e] = (unsigned short)(a | (b << 8));
@@ -370,9 +376,9 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, typename AccOf<
     A = 0.0;
     if constexpr (C::TW == 0) {
         if (lane == 0) {
-            S M[EN(C::TL, D)];
+            S M[EN(C::TL, MR(D))];
 #pragma unroll
-            for (int e = 0; e < EN(C::TL, D); ++e) M[e] = sm.mat[e];
+            for (int e = 0; e < EN(C::TL, MR(D)); ++e) M[e] = sm.mat[e];
             Acc Tl;
             double Al;
             Leaf<S, C::TL, D>::run(M, Tl, Al);
@@ -381,13 +387,13 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, typename AccOf<
         }
     } else {
         if (lane < C::NL) {
-            constexpr int R1 = C::TL + 1, p0 = 2 * R1 - 2 + D, p1 = 2 * R1 - 1 + D, RC = 2 * R1 - 2 + D;
+            constexpr int R1 = C::TL + 1, p0 = 2 * R1 - 2 + MR(D), p1 = 2 * R1 - 1 + MR(D), RC = 2 * R1 - 2 + MR(D);
             const int i = lane & (C::NN - 1);
             const bool inc = lane >= C::NN;
             const S *base = sm.mat + sm.loc[i];
-            S M[EN(R1, D)];
+            S M[EN(R1, MR(D))];
 #pragma unroll
-            for (int e = 0; e < EN(R1, D); ++e) M[e] = base[e];
+            for (int e = 0; e < EN(R1, MR(D)); ++e) M[e] = base[e];
             Pivot<S> pv = make_pivot_m<S, D>(M, p0, p1);
             const S zero = from_pair<S>(0.0, 0.0);
             S v1[RC], v2[RC];
@@ -399,7 +405,7 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, typename AccOf<
                 v1[cc] = inc ? x1 : zero;
                 v2[cc] = inc ? x2 : zero;
             }
-            S Ml[EN(C::TL, D)];
+            S Ml[EN(C::TL, MR(D))];
 #pragma unroll
             for (int x = 0; x < RC; ++x)
 #pragma unroll

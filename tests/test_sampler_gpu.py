@@ -231,3 +231,85 @@ def test_chain_click_cap_option(ctx):
     # many chains, the 20-click cap fewer
     assert s20["chains_capped"] < s15["chains_capped"]
     assert smp.sum(axis=1).max() <= 20
+
+
+# ---------------------------------------------------------------- displaced states
+
+def _oracle_click_prob_displaced(cov, mean, m, hist, j):
+    """P(click at j | outcomes hist[0..j-1]) of a displaced state from two
+    oracle probabilities with mean factors (form P)."""
+    base = np.full(m, -1, np.int8)
+    base[:j] = hist[:j]
+    num = base.copy()
+    num[j] = 1
+    a = oracle.formP_mean(cov, mean, num)
+    b = oracle.formP_mean(cov, mean, base)
+    R = max(a.cancel_ratio, b.cancel_ratio)
+    return (a.p + a.p_lo) / (b.p + b.p_lo), R
+
+
+def test_displaced_replay_small_all_steps(ctx):
+    """gbs_trace_displaced: every step's click probability against the oracle's
+    ratio of displaced probabilities (the information-form tree with mean row
+    h = K_j mu and pivot factors exp(+|w|^2 / 2))."""
+    m = 7
+    cov = _small_state(m, 40)
+    mean = gi.random_mean(m, np.random.default_rng(41), 0.6)
+    pc, un, oc, st = ctx.gbs_trace(cov, -1, 123, 0, 8, mean=mean)
+    for c in range(8):
+        for j in range(m):
+            want, R = _oracle_click_prob_displaced(cov, mean, m, oc[c], j)
+            n = int(oc[c, :j].sum()) + 1
+            tol = 16 * n * U53 * max(R, 1.0) * 32 + 1e-14
+            assert abs(pc[c, j] - want) <= tol * max(abs(want), 1e-300), (c, j, pc[c, j], want)
+            assert oc[c, j] == (1 if un[c, j] < pc[c, j] else 0)
+
+
+def test_displaced_coherent_many_clicks(ctx):
+    """Coherent states through an interferometer (a product of coherent states
+    beta = U alpha): P(click at j) = 1 - exp(-|beta_j|^2) whatever the
+    history, up to 20 clicks (the large kernel and the LDS Schur loop above
+    nine modes, with the mean row)."""
+    rng = np.random.default_rng(42)
+    m = 32
+    U = gi.haar_unitary(m, rng)
+    beta = np.sqrt(rng.uniform(0.4, 1.4, m)) * np.exp(2j * np.pi * rng.random(m))
+    alpha = U.conj().T @ beta
+    cov = gi.gbs_covariance(U, np.zeros(m))
+    want = 1 - np.exp(-np.abs(U @ alpha) ** 2)
+    with tg.Context(0) as c:
+        c.set_option(tg.OPT_CHAIN_CLICKS, 20)
+        pc, un, oc, st = c.gbs_trace(cov, -1, 17, 0, 12, mean=gi.coherent_mean(U @ alpha))
+    deep = 0
+    for ch in range(12):
+        for j in np.nonzero(~np.isnan(pc[ch]))[0]:
+            n = int(oc[ch, :j].sum())
+            deep = max(deep, n)
+            assert abs(pc[ch, j] - want[j]) <= 1e-8 * want[j], (ch, j, n, pc[ch, j], want[j])
+    assert deep >= 12
+
+
+def test_displaced_zero_mean_is_the_zero_mean_sampler(ctx):
+    cov = _small_state(9, 43)
+    a = ctx.gbs_trace(cov, 3, 21, 0, 32)
+    b = ctx.gbs_trace(cov, 3, 21, 0, 32, mean=np.zeros(18))
+    assert np.array_equal(a[0], b[0], equal_nan=True)
+    for x, y in zip(a[1:], b[1:]):
+        assert np.array_equal(x, y, equal_nan=True)
+
+
+def test_displaced_distribution_m5(ctx):
+    m = 5
+    cov = _small_state(m, 44, 0.5, 1.0)
+    mean = gi.random_mean(m, np.random.default_rng(45), 0.7)
+    probs = np.array([oracle.formP_mean(cov, mean, np.array([(k >> i) & 1 for i in range(m)], np.int8)).p
+                      for k in range(1 << m)])
+    assert abs(probs.sum() - 1) < 1e-13
+    samples, st = ctx.gbs_sample(cov, -1, 8, 200000, mean=mean)
+    assert st["chains_accepted"] == 200000
+    assert _chi2_pvalue(samples, probs) > 1e-4
+    with pytest.raises(tg.TorError) as ei:
+        bad = mean.copy()
+        bad[3] = np.nan
+        ctx.gbs_sample(cov, -1, 8, 10, mean=bad)
+    assert ei.value.status == tg.TOR_EINVAL
