@@ -23,14 +23,17 @@
 // the same prefix).
 //
 // Three tiers:
-//   expand  (HBM)   top levels, one workgroup per node, children written to a
-//                   pool in HBM (breadth-first, one launch per level);
+//   expand  (HBM)   top levels, one 64-lane wave per node, children written to
+//                   a pool in HBM (breadth-first, one launch per level);
 //   wave    (LDS)   a 64-lane workgroup takes one node with J modes and expands
 //                   J - TL more levels breadth-first in LDS (64 leaves);
 //   leaf    (VGPR)  each lane finishes a TL-mode node depth-first in registers.
 // Scalars S are binary64 ("f64 tier") or double-double ("dd tier"); T, A and the
 // path coefficients are always accumulated in double-double.  Reductions are in
-// a fixed order, so results are bitwise reproducible.
+// a fixed order, so results are bitwise reproducible.  This file holds the
+// zero-mean wave kernels, the expansion, conditioning and reduction kernels;
+// the displaced-state wave kernels are in tor_kernels_disp.hip and the
+// quad-double tier in tor_kernels_qd.hip.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -227,10 +227,14 @@ template <class S, int J, int D = 0> struct WaveCfg {
         return o;
     }
     static constexpr int MAT = soff(TWC);
+    // Levels whose pivot columns are formed for half of the nodes at a time:
+    // the levels with 8 or more nodes of displaced double-double trees, so
+    // that their working set fits four workgroups per CU.
+    static constexpr int halves(int k) { return (D != 0 && sizeof(S) > sizeof(double) && (1 << k) >= 8) ? 2 : 1; }
     static constexpr int vmax() {
         int m = 1;
         for (int k = 0; k < TWC; ++k) {
-            int v = (1 << k) * 2 * (2 * (J - k) - 2 + MR(D));
+            int v = (1 << k) / halves(k) * 2 * (2 * (J - k) - 2 + MR(D));
             if (v > m) m = v;
         }
         return m;
@@ -261,56 +265,116 @@ template <class S, int J, int K, int D = 0> struct WaveLevel {
                 loc[NK + lane] = C::soff(K) + lane * EC;
             }
             wave_sync();
-            // phase 1: the two scaled pivot columns of every node
-            for (int it = lane; it < NK * RC; it += 64) {
-                int i = it / RC, c = it - i * RC;
-                const S *base = mat + loc[i];
-                Pivot<S> pv = piv[i];
-                S m0 = base[pidx(R - 2, c)];
-                vbuf[i * 2 * RC + c] = mul_s(m0, pv.s1);
-                vbuf[i * 2 * RC + RC + c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
-            }
-            wave_sync();
-            // phase 2: rank-2 updates into the include children's slots.  Each
-            // lane's entries are taken in chunks: all loads of a chunk first,
-            // then the independent updates (computed unconditionally so that
-            // their dependency chains interleave), then the stores.  A lane
-            // past the end stores into piv[] (dead until the next level's
-            // phase 0), so the whole phase is one branch-free block.
-            {
-                constexpr int TOT = NK * EC, JJ = (TOT + 63) / 64;
-                constexpr int NCH = (JJ + 3) / 4, CH = (JJ + NCH - 1) / NCH;
-#pragma unroll
-                for (int j0 = 0; j0 < JJ; j0 += CH) {
-                    S x[CH], p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
-                    int dst[CH];
-#pragma unroll
-                    for (int u = 0; u < CH; ++u) {
-                        const int it0 = lane + 64 * (j0 + u);
-                        const bool ok = (j0 + u < JJ) && it0 < TOT;
-                        const int it = ok ? it0 : 0;
-                        const int i = it / EC, e = it - i * EC;
-                        const unsigned short w = ab[e];
-                        const int a = w & 0xff, b = w >> 8;
-                        const S *base = mat + loc[i];
-                        const S *v = vbuf + i * 2 * RC;
-                        x[u] = base[e];
-                        p1[u] = v[a];
-                        q1[u] = v[b];
-                        p2[u] = v[RC + a];
-                        q2[u] = v[RC + b];
-                        dst[u] = ok ? C::soff(K) + i * EC + e : -1;
-                    }
-#pragma unroll
-                    for (int u = 0; u < CH; ++u) r[u] = sub_dot2(x[u], p1[u], q1[u], p2[u], q2[u]);
-#pragma unroll
-                    for (int u = 0; u < CH; ++u) {
-                        S *dp = dst[u] >= 0 ? mat + dst[u] : reinterpret_cast<S *>(piv);
-                        *dp = r[u];
+            // phases 1 and 2: for all nodes at once, or (halves(K) = 2) for each
+            // half of the nodes in turn
+            constexpr int NH = C::halves(K), NKH = NK / NH;
+            if constexpr (NH == 1) {
+                // phase 1: the two scaled pivot columns of every node
+                for (int it = lane; it < NK * RC; it += 64) {
+                    int i = it / RC, c = it - i * RC;
+                    const S *base = mat + loc[i];
+                    Pivot<S> pv = piv[i];
+                    S m0 = base[pidx(R - 2, c)];
+                    vbuf[i * 2 * RC + c] = mul_s(m0, pv.s1);
+                    vbuf[i * 2 * RC + RC + c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
+                }
+                wave_sync();
+                // phase 2: rank-2 updates into the include children's slots.  Each
+                // lane's entries are taken in chunks: all loads of a chunk first,
+                // then the independent updates (computed unconditionally so that
+                // their dependency chains interleave), then the stores.  A lane
+                // past the end stores into piv[] (dead until the next level's
+                // phase 0), so the whole phase is one branch-free block.
+                {
+                    constexpr int TOT = NK * EC, JJ = (TOT + 63) / 64;
+                    constexpr int NCH = (JJ + 3) / 4, CH = (JJ + NCH - 1) / NCH;
+    #pragma unroll
+                    for (int j0 = 0; j0 < JJ; j0 += CH) {
+                        S x[CH], p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
+                        int dst[CH];
+    #pragma unroll
+                        for (int u = 0; u < CH; ++u) {
+                            const int it0 = lane + 64 * (j0 + u);
+                            const bool ok = (j0 + u < JJ) && it0 < TOT;
+                            const int it = ok ? it0 : 0;
+                            const int i = it / EC, e = it - i * EC;
+                            const unsigned short w = ab[e];
+                            const int a = w & 0xff, b = w >> 8;
+                            const S *base = mat + loc[i];
+                            const S *v = vbuf + i * 2 * RC;
+                            x[u] = base[e];
+                            p1[u] = v[a];
+                            q1[u] = v[b];
+                            p2[u] = v[RC + a];
+                            q2[u] = v[RC + b];
+                            dst[u] = ok ? C::soff(K) + i * EC + e : -1;
+                        }
+    #pragma unroll
+                        for (int u = 0; u < CH; ++u) r[u] = sub_dot2(x[u], p1[u], q1[u], p2[u], q2[u]);
+    #pragma unroll
+                        for (int u = 0; u < CH; ++u) {
+                            S *dp = dst[u] >= 0 ? mat + dst[u] : reinterpret_cast<S *>(piv);
+                            *dp = r[u];
+                        }
                     }
                 }
+                wave_sync();
+            } else {
+    #pragma unroll
+                for (int h = 0; h < NH; ++h) {
+                    // phase 1: the two scaled pivot columns of every node of the part
+                    for (int it = lane; it < NKH * RC; it += 64) {
+                        int il = it / RC, c = it - il * RC;
+                        const int i = h * NKH + il;
+                        const S *base = mat + loc[i];
+                        Pivot<S> pv = piv[i];
+                        S m0 = base[pidx(R - 2, c)];
+                        vbuf[il * 2 * RC + c] = mul_s(m0, pv.s1);
+                        vbuf[il * 2 * RC + RC + c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
+                    }
+                    wave_sync();
+                    // phase 2: rank-2 updates into the include children's slots.  Each
+                    // lane's entries are taken in chunks: all loads of a chunk first,
+                    // then the independent updates (computed unconditionally so that
+                    // their dependency chains interleave), then the stores.  A lane
+                    // past the end stores into piv[0] (its node's pivot is not read
+                    // again before the next level's phase 0; node 0 is in the first
+                    // part), so the whole phase is one branch-free block.
+                    constexpr int TOT = NKH * EC, JJ = (TOT + 63) / 64;
+                    constexpr int NCH = (JJ + 3) / 4, CH = (JJ + NCH - 1) / NCH;
+    #pragma unroll
+                    for (int j0 = 0; j0 < JJ; j0 += CH) {
+                        S x[CH], p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
+                        int dst[CH];
+    #pragma unroll
+                        for (int u = 0; u < CH; ++u) {
+                            const int it0 = lane + 64 * (j0 + u);
+                            const bool ok = (j0 + u < JJ) && it0 < TOT;
+                            const int it = ok ? it0 : 0;
+                            const int il = it / EC, e = it - il * EC;
+                            const int i = h * NKH + il;
+                            const unsigned short w = ab[e];
+                            const int a = w & 0xff, b = w >> 8;
+                            const S *base = mat + loc[i];
+                            const S *v = vbuf + il * 2 * RC;
+                            x[u] = base[e];
+                            p1[u] = v[a];
+                            q1[u] = v[b];
+                            p2[u] = v[RC + a];
+                            q2[u] = v[RC + b];
+                            dst[u] = ok ? C::soff(K) + i * EC + e : -1;
+                        }
+    #pragma unroll
+                        for (int u = 0; u < CH; ++u) r[u] = sub_dot2(x[u], p1[u], q1[u], p2[u], q2[u]);
+    #pragma unroll
+                        for (int u = 0; u < CH; ++u) {
+                            S *dp = dst[u] >= 0 ? mat + dst[u] : reinterpret_cast<S *>(piv);
+                            *dp = r[u];
+                        }
+                    }
+                    wave_sync();
+                }
             }
-            wave_sync();
             WaveLevel<S, J, K + 1, D>::run(ab, mat, vbuf, piv, loc, coef, acoef, lane);
         }
     }
@@ -352,7 +416,7 @@ __device__ __forceinline__ void wave_tree_init(unsigned short *ab, int lane) {
     wave_sync();
 }
 
-// Subset tree of the J-mode node stored in sm.mat[0 .. EN(J, D)) with path
+// Subset tree of the J-mode node stored in sm.mat[0 .. EN(J, MR(D))) with path
 // coefficient (c, a).  The wave expands all but the last of the J - TL levels
 // above the leaves breadth-first in LDS; lane l < NL then takes node
 // l mod NN, decides its last mode itself (l >= NN: include, a rank-2 Schur

@@ -67,9 +67,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, J
 // way.  An 11-mode task sums its exclude child (the leading 10-mode block) so,
 // then rebuilds its include child from the task's matrix, still in HBM, and
 // sums that.  Each top level saves one HBM level for a few hundred bytes of LDS.
-template <class S, int D> struct TopSmem {
+template <class S, int D, int NT> struct TopSmem {  // NT = J - 9 set-aside column pairs
     WaveSmem<S, 9, D> w;
-    S vtop[2][2 * (2 * TOR_TASK_MAX - 2 + D)];
+    S vtop[NT][2 * (2 * TOR_TASK_MAX - 2 + MR(D))];
 };
 
 // pivot of the last mode of the r-mode node m[] and its two scaled columns
@@ -98,8 +98,8 @@ __device__ __forceinline__ void top_update(const S *src, S *dst, const S *v, int
 }
 
 // the 10-mode node in sm.w.mat[0 .. EN(10, D)); adds this lane's share to (T, A)
-template <class S, int D>
-__device__ __forceinline__ void top10(TopSmem<S, D> &sm, dd c, double a, int lane, dd &T, double &A) {
+template <class S, int D, int NT>
+__device__ __forceinline__ void top10(TopSmem<S, D, NT> &sm, dd c, double a, int lane, dd &T, double &A) {
     S *v = sm.vtop[0];
     const Pivot<S> pv = top_columns<S, 10, D>(sm.w.mat, v, lane);
     wave_sync();
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9
     const LaunchDims *__restrict__ dyn) {
     static_assert(J == 10 || J == 11, "top levels: one or two");
     static_assert(WaveCfg<S, 9, D>::MAT >= EN(J, D), "the task's matrix must fit the nine-mode working set");
-    __shared__ TopSmem<S, D> sm;
+    __shared__ TopSmem<S, D, J - 9> sm;
     const int lane = threadIdx.x;
     if (dyn) {
         njobs = (int)dyn->njobs;
@@ -140,16 +140,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9
         dd T = dd_from(0.0);
         double A = 0.0;
         if constexpr (J == 10) {
-            top10<S, D>(sm, c0, d.acoef, lane, T, A);
+            top10<S, D, J - 9>(sm, c0, d.acoef, lane, T, A);
         } else {
             S *v = sm.vtop[1];
             const Pivot<S> pv = top_columns<S, 11, D>(sm.w.mat, v, lane);
             wave_sync();
-            top10<S, D>(sm, c0, d.acoef, lane, T, A);
+            top10<S, D, J - 9>(sm, c0, d.acoef, lane, T, A);
             wave_sync();
             top_update<S, 11, D>(root, sm.w.mat, v, lane);
             wave_sync();
-            top10<S, D>(sm, dd_neg(coef_mul(c0, pv.q)), d.acoef * hi_of(pv.q), lane, T, A);
+            top10<S, D, J - 9>(sm, dd_neg(coef_mul(c0, pv.q)), d.acoef * hi_of(pv.q), lane, T, A);
         }
         wave_reduce(T, A);
         if (lane == 0) {
