@@ -34,8 +34,9 @@
  * "Memory").  The sum is always accumulated in double-double.  The per-subset
  * factorisation runs in binary64 (TOR_PREC_F64) or in double-double
  * (TOR_PREC_DD); TOR_PREC_AUTO runs binary64 first and repeats in
- * double-double when the a-priori bound exceeds tol.  TOR_PREC_QD (opt-in,
- * tor_probability and tor_subset_sum only) runs the no-click conditioning,
+ * double-double when the a-priori bound exceeds tol.  TOR_PREC_QD (opt-in;
+ * tor_probability, tor_subset_sum, tor_batch (one query at a time) and
+ * gbs_chain_fixed; zero-mean states) runs the no-click conditioning,
  * the factorisation and the sum in quad-double (about 212 bits): for sums
  * that cancel beyond double-double, e.g. full patterns conditioned on
  * hundreds of no-click modes (R ~ 1e36 at n = 28 on 800 modes).  Its trees

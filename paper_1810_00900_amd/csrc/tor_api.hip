@@ -1379,6 +1379,21 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
     if (st->ctx != ctx) return fail(TOR_EINVAL, "state belongs to another context");
     if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
     HIP_TRY(hipSetDevice(ctx->device));
+    if (prec == TOR_PREC_QD) {  // quad-double conditioning and trees, one query at a time
+        tor_status first = TOR_OK;
+        for (int q = 0; q < nq; q++) {
+            std::memset(&out[q], 0, sizeof out[q]);
+            tor_status s = probability_qd(ctx, st->cov.data(), st->m, patterns + (size_t)q * st->m, tol, &out[q]);
+            if (s < 0) {
+                std::memset(&out[q], 0, sizeof out[q]);
+                out[q].status = s;
+                if (s == TOR_EDEVICE) return s;
+            }
+            if (s < 0 && first >= 0) first = s;
+            else if (s == TOR_WARN_PRECISION && first == TOR_OK) first = s;
+        }
+        return first;
+    }
     std::vector<Prepared> qs((size_t)nq);
     std::vector<Reduced> red((size_t)nq);
     std::vector<Reduced *> rp;

@@ -165,13 +165,25 @@ def test_subset_sum_qd_matches_dd(ctx, n):
     assert q.abs_sum == pytest.approx(d.abs_sum, rel=1e-14)
 
 
-def test_qd_rejected_where_not_supported(ctx):
-    cov = 0.5 * np.eye(4)
+def test_qd_batch_equals_single_and_rejections(ctx):
+    """tor_batch with quad-double terms (one query at a time): every result is
+    the single query's, failures stay per query; displaced queries reject
+    quad-double terms."""
+    rng = np.random.default_rng(260)
+    m = 16
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), np.full(m, 0.5))
+    pats = [gi.marginal_pattern(m, [1, 4, 9]), gi.full_pattern(m, [0, 2, 3, 7, 11]), np.full(m, -1, np.int8)]
+    bad = np.full(m, -1, np.int8)
+    bad[3] = 5
     st = ctx.state(cov)
-    with pytest.raises(tg.TorError) as ei:
-        ctx.batch(st, np.array([[1, 0]], np.int8), prec="qd")
-    assert ei.value.status == tg.TOR_EINVAL
+    res, status = ctx.batch(st, np.stack(pats + [bad]), prec="qd")
+    assert status == tg.TOR_EINVAL
+    for p, r in zip(pats, res):
+        q = ctx.probability(cov, p, prec="qd")
+        assert (r.p, r.p_lo, r.T, r.abs_sum, r.prec_used) == (q.p, q.p_lo, q.T, q.abs_sum, tg.PREC_QD)
+    assert res[-1].status == tg.TOR_EINVAL
     st.close()
+    cov = 0.5 * np.eye(4)
     with pytest.raises(tg.TorError) as ei:
         ctx.probability_displaced(cov, np.zeros(4), np.array([1, 0], np.int8), prec="qd")
     assert ei.value.status == tg.TOR_EINVAL
