@@ -188,6 +188,12 @@ tor_status tor_subset_sum(tor_ctx *ctx, const double *sigma_hi, const double *si
 /* A state: validated covariance kept on the host (and sigma_Q formed once)
  * for many queries.  cov as above. */
 tor_status tor_state_create(tor_ctx *ctx, const double *cov, int32_t m, tor_state **out);
+/* A displaced state: cov as above and mean (host, 2m doubles, all finite,
+ * as for tor_probability_displaced).  tor_batch and the server evaluate its
+ * queries as tor_probability_displaced does (bitwise the same results);
+ * tor_batch_async and quad-double terms reject it with TOR_EINVAL. */
+tor_status tor_state_create_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m,
+                                      tor_state **out);
 void tor_state_destroy(tor_state *st);
 
 /* nq queries on one state, patterns = nq x m int8 (row per query), results in

@@ -134,6 +134,7 @@ def lib():
         "tor_subset_sum": ([vp, dp, dp, ctypes.c_int32, ctypes.c_int, ctypes.c_double,
                             ctypes.POINTER(_CResult)], ctypes.c_int32),
         "tor_state_create": ([vp, dp, ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int32),
+        "tor_state_create_displaced": ([vp, dp, dp, ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int32),
         "tor_state_destroy": ([vp], None),
         "tor_batch": ([vp, vp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
                        ctypes.POINTER(_CResult)], ctypes.c_int32),
@@ -360,8 +361,9 @@ class Context:
                                              _dptr(un), op, _i8ptr(stt)))
         return pc, un, oc, stt
 
-    def state(self, cov) -> "State":
-        return State(self, cov)
+    def state(self, cov, mean=None) -> "State":
+        """A state kept by the library; with a mean vector a displaced state."""
+        return State(self, cov, mean)
 
     def batch(self, state: "State", patterns, prec="auto", tol: float = 1e-10):
         patterns = _i8(patterns)
@@ -427,11 +429,17 @@ def results_from_device(d_out) -> list:
 class State:
     """A validated covariance kept by the library (tor_state)."""
 
-    def __init__(self, ctx: Context, cov):
+    def __init__(self, ctx: Context, cov, mean=None):
         cov = _f64(cov)
         self.m = cov.shape[0] // 2
         h = ctypes.c_void_p()
-        _check(lib().tor_state_create(ctx.handle, _dptr(cov), self.m, ctypes.byref(h)))
+        if mean is None:
+            _check(lib().tor_state_create(ctx.handle, _dptr(cov), self.m, ctypes.byref(h)))
+        else:
+            mean = _f64(mean)
+            if mean.shape != (2 * self.m,):
+                raise ValueError("mean must have 2m entries")
+            _check(lib().tor_state_create_displaced(ctx.handle, _dptr(cov), _dptr(mean), self.m, ctypes.byref(h)))
         self._h = h
         self.ctx = ctx
 

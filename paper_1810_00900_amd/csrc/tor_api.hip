@@ -119,6 +119,7 @@ struct tor_state {
     int device = 0;  // the context's device, kept for the release of dcov
     int m = 0;
     std::vector<double> cov;
+    std::vector<double> mean;  // displaced states only (2m entries), else empty
     DevBuf dcov;  // device copy for tor_batch_async (made on first use)
 };
 
@@ -874,6 +875,18 @@ tor_status prepare_disp(std::vector<dd> &&packed, int n, dd pvac, double log_pva
     return TOR_OK;
 }
 
+// A pattern of a state (zero-mean or displaced) reduced for the subset tree.
+tor_status reduce_for_state(const tor_state *st, const int8_t *pattern, Reduced &out) {
+    return st->mean.empty() ? reduce_pattern(st->cov.data(), st->m, pattern, out)
+                            : reduce_pattern_disp(st->cov.data(), st->mean.data(), st->m, pattern, out);
+}
+
+// A reduced pattern, conditioned if it had no-click modes, made ready for the GPU.
+tor_status prepare_reduced(Reduced &r, Prepared &p) {
+    if (r.D) return prepare_disp(std::move(r.packed), r.n, r.pvac, r.log_pvac, p);
+    return prepare(r.sig, r.n, r.pvac, r.log_pvac, p);
+}
+
 void finalize(const Prepared &p, const SumOut &s, int used, double tol, tor_result *out) {
     const dd T = s.T;
     const double A = s.A;
@@ -1363,6 +1376,25 @@ tor_status tor_state_create(tor_ctx *ctx, const double *cov, int32_t m, tor_stat
     return TOR_OK;
 }
 
+tor_status tor_state_create_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m,
+                                      tor_state **out) {
+    if (!ctx || !out || !mean) return fail(TOR_EINVAL, "NULL argument");
+    *out = nullptr;
+    for (int i = 0; i < 2 * m; i++)
+        if (!std::isfinite(mean[i])) return fail(TOR_EINVAL, "mean[%d] is not finite", i);
+    tor_state *st = nullptr;
+    tor_status s = tor_state_create(ctx, cov, m, &st);
+    if (s) return s;
+    try {
+        st->mean.assign(mean, mean + 2 * (size_t)m);
+    } catch (...) {
+        tor_state_destroy(st);
+        return fail(TOR_ENOMEM, "host allocation failed");
+    }
+    *out = st;
+    return TOR_OK;
+}
+
 void tor_state_destroy(tor_state *st) {
     if (!st) return;
     if (st->dcov.p) {
@@ -1379,6 +1411,13 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
     if (st->ctx != ctx) return fail(TOR_EINVAL, "state belongs to another context");
     if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
     HIP_TRY(hipSetDevice(ctx->device));
+    if (prec == TOR_PREC_QD && !st->mean.empty()) {
+        for (int q = 0; q < nq; q++) {
+            std::memset(&out[q], 0, sizeof out[q]);
+            out[q].status = TOR_EINVAL;
+        }
+        return fail(TOR_EINVAL, "quad-double terms take zero-mean states only");
+    }
     if (prec == TOR_PREC_QD) {  // quad-double conditioning and trees, one query at a time
         tor_status first = TOR_OK;
         for (int q = 0; q < nq; q++) {
@@ -1398,7 +1437,7 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
     std::vector<Reduced> red((size_t)nq);
     std::vector<Reduced *> rp;
     for (int q = 0; q < nq; q++) {
-        tor_status s = reduce_pattern(st->cov.data(), st->m, patterns + (size_t)q * st->m, red[q]);
+        tor_status s = reduce_for_state(st, patterns + (size_t)q * st->m, red[q]);
         if (s != TOR_OK) qs[q].status = s;
         else rp.push_back(&red[q]);
     }
@@ -1412,7 +1451,7 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
     }
     for (int q = 0; q < nq; q++) {
         if (qs[q].status != TOR_OK) continue;
-        tor_status s = prepare(red[q].sig, red[q].n, red[q].pvac, red[q].log_pvac, qs[q]);
+        tor_status s = prepare_reduced(red[q], qs[q]);
         if (s != TOR_OK) {
             qs[q].status = s;
             qs[q].n = 0;
@@ -1461,6 +1500,7 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
     if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD)
         return fail(TOR_EINVAL, "bad precision %d", (int)prec);
+    if (!st->mean.empty()) return fail(TOR_EINVAL, "tor_batch_async takes zero-mean states only");
     if (nq == 0) return TOR_OK;
     if (!d_patterns || !d_out) return fail(TOR_EINVAL, "NULL device pointer");
     if (nq > (1 << 24)) return fail(TOR_ETOOBIG, "nq = %d > 2^24", nq);
@@ -2164,7 +2204,8 @@ void server_worker(tor_server *S, int w) {
             while (!S->pending.empty() && (int)take.size() < S->opts.max_batch) {
                 uint64_t t = S->pending.front();
                 ServerReq &r = *S->reqs[t];
-                size_t b = sum_bytes(r.red.n, task_modes_for(ctx, S->opts.prec == TOR_PREC_DD, r.red.n), es) +
+                size_t b = sum_bytes(r.red.n, task_modes_for(ctx, S->opts.prec == TOR_PREC_DD, r.red.n), es,
+                                     r.red.D) +
                            r.red.packed.size() * sizeof(dd);
                 if (!take.empty() && bytes + b > S->opts.mem_budget_bytes) break;
                 bytes += b;
@@ -2182,7 +2223,7 @@ void server_worker(tor_server *S, int w) {
             tor_status cs = condition_on_gpu(ctx, rp);
             for (size_t i = 0; i < batch.size(); i++) {
                 if (!red[i].cond && rp.end() == std::find(rp.begin(), rp.end(), &red[i])) continue;
-                tor_status s = cs < 0 ? cs : prepare(red[i].sig, red[i].n, red[i].pvac, red[i].log_pvac, batch[i]);
+                tor_status s = cs < 0 ? cs : prepare_reduced(red[i], batch[i]);
                 if (s != TOR_OK) {
                     batch[i].status = s;
                     batch[i].n = 0;
@@ -2279,16 +2320,16 @@ tor_status tor_submit(tor_server *S, const tor_state *st, const int8_t *pattern,
     std::unique_ptr<ServerReq> r(new (std::nothrow) ServerReq());
     if (!r) return fail(TOR_ENOMEM, "host allocation failed");
     r->t_submit = t0;
-    tor_status s = reduce_pattern(st->cov.data(), st->m, pattern, r->red);
+    tor_status s = reduce_for_state(st, pattern, r->red);
     if (s) return s;
-    const int n = r->red.n;
+    const int n = r->red.n, D = r->red.D;
     if (!r->red.cond) {  // marginal pattern: ready now (conditioned ones: in the worker)
-        s = prepare(r->red.sig, n, r->red.pvac, r->red.log_pvac, r->prep);
+        s = prepare_reduced(r->red, r->prep);
         if (s) return s;
         std::vector<dd>().swap(r->red.sig);
     }
     const size_t es = S->opts.prec == TOR_PREC_F64 ? sizeof(double) : sizeof(dd);
-    if (sum_bytes(n, task_modes_for(S->wctx[0], S->opts.prec == TOR_PREC_DD, n), es) > S->wctx[0]->mem_budget)
+    if (sum_bytes(n, task_modes_for(S->wctx[0], S->opts.prec == TOR_PREC_DD, n), es, D) > S->wctx[0]->mem_budget)
         return fail(TOR_ENOMEM, "query with %d clicks exceeds the device memory budget", n);
     {
         std::lock_guard<std::mutex> lk(S->mu);

@@ -235,3 +235,38 @@ def test_batch_displaced_matches_single(ctx):
     z, _ = ctx.batch(st, np.stack(pats[:-1]), prec="dd")
     assert any(a.p != b.p for a, b in zip(z, res[:-1]))
     st.close()
+
+
+def test_displaced_state_batch_and_server(ctx):
+    """A state created with a mean: tor_batch and the continuous-batching
+    server give bitwise the tor_probability_displaced results; the async batch
+    rejects it."""
+    rng = np.random.default_rng(140)
+    m = 30
+    cov, _ = _haar_state(m, 141, r=0.5)
+    mean = gi.random_mean(m, rng, 0.5)
+    pats = []
+    for n in (2, 6, 10, 13):
+        clicks = sorted(rng.choice(m, n, replace=False).tolist())
+        pats.append(gi.marginal_pattern(m, clicks))
+        pats.append(gi.full_pattern(m, clicks))
+    st = ctx.state(cov, mean=mean)
+    res, status = ctx.batch(st, np.stack(pats), prec="dd")
+    assert status >= 0
+    singles = [ctx.probability_displaced(cov, mean, p, prec="dd") for p in pats]
+    for r, s in zip(res, singles):
+        assert (r.p, r.p_lo, r.T, r.abs_sum) == (s.p, s.p_lo, s.T, s.abs_sum)
+    srv = tg.Server(ctx, workers=2, prec="dd")
+    tickets = [srv.submit(st, p) for p in pats]
+    for t, s in zip(tickets, singles):
+        r, _lat = srv.wait(t)
+        assert (r.p, r.p_lo, r.T) == (s.p, s.p_lo, s.T)
+    srv.stop()
+    import torch
+    d_pat = torch.tensor(np.stack(pats[:1]), dtype=torch.int8, device="cuda")
+    with pytest.raises(tg.TorError) as ei:
+        ctx.batch_async(st, d_pat)
+    assert ei.value.status == tg.TOR_EINVAL
+    with pytest.raises(tg.TorError):
+        ctx.batch(st, np.stack(pats[:1]), prec="qd")
+    st.close()
