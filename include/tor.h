@@ -190,8 +190,9 @@ tor_status tor_subset_sum(tor_ctx *ctx, const double *sigma_hi, const double *si
 tor_status tor_state_create(tor_ctx *ctx, const double *cov, int32_t m, tor_state **out);
 /* A displaced state: cov as above and mean (host, 2m doubles, all finite,
  * as for tor_probability_displaced).  tor_batch and the server evaluate its
- * queries as tor_probability_displaced does (bitwise the same results);
- * tor_batch_async and quad-double terms reject it with TOR_EINVAL. */
+ * queries as tor_probability_displaced does (bitwise the same results), and
+ * tor_batch_async as tor_batch does; quad-double terms reject it with
+ * TOR_EINVAL. */
 tor_status tor_state_create_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m,
                                       tor_state **out);
 void tor_state_destroy(tor_state *st);
@@ -230,8 +231,8 @@ tor_status tor_batch_displaced(tor_ctx *ctx, const tor_state *st, const double *
  * query cannot be repeated without a host decision).  Device memory: a
  * workspace whose tree pool holds TOR_OPT_ASYNC_POOL bytes (default 4 GiB);
  * queries are admitted in order while the trees up to them fit, later ones
- * get TOR_ENOMEM.  The first call on a state copies its covariance to the
- * device (synchronously, once).  The workspace belongs to the context: calls
+ * get TOR_ENOMEM.  The first call on a state copies its covariance (and the
+ * mean of a displaced state) to the device (synchronously, once).  The workspace belongs to the context: calls
  * on one context must be ordered (same stream, or the caller waits).
  * Returns TOR_OK once enqueued; argument errors (NULL pointers, nq < 0, bad
  * prec, state of another context) and launch or allocation failures are

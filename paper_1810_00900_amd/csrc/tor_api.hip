@@ -120,6 +120,7 @@ struct tor_state {
     int m = 0;
     std::vector<double> cov;
     std::vector<double> mean;  // displaced states only (2m entries), else empty
+    DevBuf dmean;               // device copy of the mean for tor_batch_async (made on first use)
     DevBuf dcov;  // device copy for tor_batch_async (made on first use)
 };
 
@@ -1500,7 +1501,6 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
     if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD)
         return fail(TOR_EINVAL, "bad precision %d", (int)prec);
-    if (!st->mean.empty()) return fail(TOR_EINVAL, "tor_batch_async takes zero-mean states only");
     if (nq == 0) return TOR_OK;
     if (!d_patterns || !d_out) return fail(TOR_EINVAL, "NULL device pointer");
     if (nq > (1 << 24)) return fail(TOR_ETOOBIG, "nq = %d > 2^24", nq);
@@ -1516,11 +1516,19 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
         if (ms->dcov.ensure(cov_bytes) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the state failed");
         HIP_TRY(hipMemcpy(ms->dcov.p, st->cov.data(), cov_bytes, hipMemcpyHostToDevice));
     }
+    const int D = st->mean.empty() ? 0 : 1;
+    if (D && !ms->dmean.p) {
+        if (ms->dmean.ensure(st->mean.size() * sizeof(double)) != hipSuccess)
+            return fail(TOR_ENOMEM, "device copy of the mean failed");
+        HIP_TRY(hipMemcpy(ms->dmean.p, st->mean.data(), st->mean.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     // task sizes and the launches any pattern of this state can need
     AsyncPlan P{};
     P.nq = nq;
     P.m = m;
     P.is_dd = use_dd;
+    P.D = D;
+    P.mean = D ? (const double *)ms->dmean.p : nullptr;
     const int nmax = std::min(TOR_MAX_CLICKS, m);
     int gcap = 0, jmax = 1;
     long long max_tasks[TOR_TASK_MAX + 1] = {};  // per J: tasks of the largest tree
@@ -1580,13 +1588,13 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     HIP_TRY(tor_launch_async_prologue(d_patterns, (const double *)ms->dcov.p, P, hs));
     for (int d = 0; d < gcap; d++) {
         const long long bound = std::min<long long>(1LL << 20, ((long long)nq << d) / 4 + 1);
-        HIP_TRY(tor_launch_expand(use_dd, P.exp_jobs + (size_t)d * nq, 0, d, P.pool, (int)bound, hs, P.dims + d));
+        HIP_TRY(tor_launch_expand(use_dd, P.exp_jobs + (size_t)d * nq, 0, d, P.pool, (int)bound, hs, P.dims + d, D));
     }
     for (int J = jmax; J >= 1; J--) {
         if (!jused[J]) continue;
         const long long bound = std::min<long long>(ctx->wave_grid, (long long)nq * max_tasks[J]);
         HIP_TRY(tor_launch_wave(use_dd, J, P.wave_jobs + (size_t)J * nq, 0, 0, P.pool, (int)bound, hs,
-                                P.dims + gcap + J));
+                                P.dims + gcap + J, D));
     }
     long long c = nt_max;
     for (int s = 0; s < TOR_ASYNC_STAGES && c > 1; s++) {

@@ -125,12 +125,13 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
         Q.pool_off = Q.desc_off = Q.pb_off = Q.final_off = 0;
         Q.final_buf = 0;
         Q.log_det = 0.0;
+        Q.quad = 0.0;
         if (Q.status != TOR_OK || Q.n == 0) continue;
         const int n = Q.n;
         const int J = min(n, P.J_of_n[n]);
         const int G = n - J;
-        long long entries = E(n);
-        for (int d = 0; d < G; d++) entries += (1LL << d) * (long long)E(n - d - 1);
+        long long entries = EN(n, P.D);
+        for (int d = 0; d < G; d++) entries += (1LL << d) * (long long)EN(n - d - 1, P.D);
         Q.J = J;
         Q.G = G;
         Q.nt = 1LL << G;
@@ -185,14 +186,14 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
             [&](int q, long long pos) {
                 const AsyncQuery &Q = Qs[q];
                 if (!(live(q) && Q.G > d)) return;
-                long long base = Q.pool_off + E(Q.n);
-                for (int k = 0; k < d; k++) base += (1LL << k) * (long long)E(Q.n - k - 1);
+                long long base = Q.pool_off + EN(Q.n, P.D);
+                for (int k = 0; k < d; k++) base += (1LL << k) * (long long)EN(Q.n - k - 1, P.D);
                 ExpandJob j;
                 j.par = level_ptr(P, q, Q, d);
                 j.chi = level_ptr(P, q, Q, d + 1);
                 j.child_base = (unsigned long long)base;
                 j.r = Q.n - d;
-                j.d = 0;
+                j.d = P.D;
                 P.exp_jobs[(size_t)d * nq + pos] = j;
             },
             lds);
@@ -260,9 +261,13 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
 // the diagonal exact in double-double) in packed lower storage, and
 // log det Sigma_C from a binary64 Cholesky (the same operations in the same
 // order as the host's, one row per lane); a non-positive pivot gives ENOTPD.
+// Displaced states: the root has the mean row [0, mu_C] first, and the
+// forward solve with the Cholesky factor gives mu_C^T Sigma_C^-1 mu_C for the
+// error bound (as the host computes it).
 template <class S>
 __global__ __launch_bounds__(64) void async_gather_kernel(const double *__restrict__ cov, AsyncPlan P) {
     __shared__ double L[2 * TOR_MAX_N][2 * TOR_MAX_N];
+    __shared__ double z[2 * TOR_MAX_N];
     __shared__ double piv;
     __shared__ int ok;
     const int lane = threadIdx.x;
@@ -271,18 +276,24 @@ __global__ __launch_bounds__(64) void async_gather_kernel(const double *__restri
         AsyncQuery &Q = P.q[q];
         const bool run = Q.status == TOR_OK && Q.n > 0;  // uniform over the block
         if (!run) continue;
-        const int n = Q.n, d = 2 * n;
+        const int n = Q.n, d = 2 * n, o = P.D;
         S *root = (S *)P.pool + Q.pool_off;
-        for (int e = lane; e < E(n); e += 64) {
+        for (int e = lane; e < EN(n, o); e += 64) {
             int a, b;
             unpack(e, a, b);
+            if (o && b == 0) {  // mean column (0 at the corner)
+                root[e] = from_pair<S>(a == 0 ? 0.0 : P.mean[2 * Q.C[(a - 1) >> 1] + ((a - 1) & 1)], 0.0);
+                continue;
+            }
+            a -= o;
+            b -= o;
             const int ga = 2 * Q.C[a >> 1] + (a & 1), gb = 2 * Q.C[b >> 1] + (b & 1);
             const int r = ga > gb ? ga : gb, c = ga > gb ? gb : ga;
             const double v = cov[(size_t)r * ld + (size_t)c];
             dd x;
             if (ga == gb) two_sum(v, 0.5, x.hi, x.lo);
             else x = dd_from(v);
-            root[e] = from_pair<S>(x.hi, x.lo);
+            root[pidx(a + o, b + o)] = from_pair<S>(x.hi, x.lo);
             L[a][b] = x.hi + x.lo;
         }
         if (lane == 0) ok = 1;
@@ -308,6 +319,16 @@ __global__ __launch_bounds__(64) void async_gather_kernel(const double *__restri
         if (lane == 0) {
             Q.log_det = logdet;
             if (!ok) Q.status = TOR_ENOTPD;
+            if (o && ok) {  // z = L^-1 mu_C, quad = |z|^2 (forward solve, row order of the host)
+                double quad = 0.0;
+                for (int a = 0; a < d; a++) {
+                    double v = P.mean[2 * Q.C[a >> 1] + (a & 1)];
+                    for (int t = 0; t < a; t++) v -= L[a][t] * z[t];
+                    z[a] = v / L[a][a];
+                    quad += z[a] * z[a];
+                }
+                Q.quad = quad;
+            }
         }
         __syncthreads();
     }
@@ -352,7 +373,7 @@ __global__ void async_finalize_kernel(AsyncPlan P, double tol, int prec_used, to
     r.abs_sum = A;
     r.cancel_ratio = A / fabs(T.hi);
     const double u = prec_used == TOR_PREC_DD ? 4.930380657631324e-32 : 1.1102230246251565e-16;
-    r.rel_err_bound = 16.0 * (Q.n > 1 ? Q.n : 1) * u * (A / fabs(T.hi));
+    r.rel_err_bound = 16.0 * (Q.n > 1 ? Q.n : 1) * u * (A / fabs(T.hi)) * (1.0 + Q.quad);
     r.n_clicks = Q.n;
     r.prec_used = prec_used;
     r.status = r.rel_err_bound <= tol ? TOR_OK : TOR_WARN_PRECISION;

@@ -98,12 +98,15 @@ struct AsyncQuery {
     int final_buf;
     int nstage;
     double log_det;      // log det Sigma_C (binary64 Cholesky)
+    double quad;         // displaced states: mu_C^T Sigma_C^-1 mu_C (binary64), else 0
     long long slot;      // planner scratch: position of the query's job in a table
     int C[TOR_MAX_N];    // clicked modes, ascending
 };
 
 struct AsyncPlan {
     int nq, m, is_dd, gcap, jmax;
+    int D;               // 1: displaced state (mean row first in every packed matrix)
+    const double *mean;  // displaced states: device copy of the mean (2m), else null
     int J_of_n[TOR_MAX_N + 1];
     long long pool_cap, desc_cap, pb_cap;  // capacities (scalars, descriptors, partials)
     AsyncQuery *q;

@@ -67,6 +67,34 @@ def test_async_equals_batch(ctx, st800, prec):
         _same(g, w)
 
 
+@pytest.mark.parametrize("prec", ["dd", "f64"])
+def test_async_displaced_equals_batch(ctx, prec):
+    """A displaced state (800 modes, mean 0.3 x N(0, 1) per quadrature): the
+    device planner lays out matrices with the mean row, and the results equal
+    tor_batch's on the same state bitwise, error bound included."""
+    import torch
+    cov = gi.state_m800(30)
+    mean = gi.random_mean(800, np.random.default_rng(53), 0.3)
+    st = ctx.state(cov, mean=mean)
+    ns = [0, 1, 2, 9, 10, 11, 12, 16, 20] + list(np.random.default_rng(4).integers(0, 21, 15))
+    pats = _patterns(800, ns, 12)
+    want, _ = ctx.batch(st, pats, prec=prec)
+    d_out = ctx.batch_async(st, _dev(pats), prec=prec)
+    torch.cuda.synchronize()
+    got = tg.results_from_device(d_out)
+    assert len(got) == len(ns)
+    for g, w in zip(got, want):
+        _same(g, w)
+    # the mean matters: the zero-mean state gives other probabilities
+    st0 = ctx.state(cov)
+    d0 = ctx.batch_async(st0, _dev(pats), prec=prec)
+    torch.cuda.synchronize()
+    z = tg.results_from_device(d0)
+    assert all(a.p != b.p for a, b, n in zip(z, got, ns) if n > 0)
+    st0.close()
+    st.close()
+
+
 def test_async_statuses_in_a_mixed_batch(ctx, st800):
     import torch
     cov, st = st800
