@@ -203,6 +203,35 @@ def per_n_rates(ctx, cov, prec, ns=(20, 24, 28, 32), full=False, mean=None):
     return out
 
 
+def full_pattern_inverse(ctx, cov, ns=(20, 28)):
+    """Full patterns (the per_n_full_pattern queries) on a state inverted once
+    (tor_state_invert): the time of the inversion per precision, then each
+    query as a one-query tor_batch on that state (a gather of sigma_Q^-1 over
+    the clicked modes and one subset tree, no per-query conditioning)."""
+    import gbs_inputs as gi
+    out = {}
+    for prec in ("dd", "qd"):
+        st = ctx.state(cov)
+        t = time.perf_counter()
+        st.invert(prec)
+        inv_ms = (time.perf_counter() - t) * 1e3
+        rec = {"invert_ms": inv_ms}
+        for n in ns:
+            pat = gi.config5_pattern(n).copy()
+            pat[pat == -1] = 0
+            ctx.batch(st, pat[None, :], prec=prec, tol=1e-8)
+            reps = 3
+            t = time.perf_counter()
+            for _ in range(reps):
+                r, _ = ctx.batch(st, pat[None, :], prec=prec, tol=1e-8)
+            dt = (time.perf_counter() - t) / reps
+            rec[str(n)] = {"ms": dt * 1e3, "subset_dets_per_s": 2.0 ** n / dt, "rel_err_bound": r[0].rel_err_bound,
+                           "no_click_modes": int((pat == 0).sum())}
+        out[prec] = rec
+        st.close()
+    return out
+
+
 def paper_worst_case(ctx, sizes=((10, 200), (12, 288), (14, 392), (16, 512), (18, 648), (20, 800)), prec="dd"):
     """The paper's runtime study, worst case (Sec. III): one sample with fixed
     outcomes, l = 2 m^2 modes, 8 dB squeezing on every mode, Haar
@@ -482,6 +511,7 @@ def main():
         out["per_n_full_pattern"] = per_n_rates(ctx, cov, args.prec, ns=(20, 28), full=True)
         out["per_n_qd_terms"] = per_n_rates(ctx, cov, "qd", ns=(20, 24, 28))
         out["per_n_full_pattern_qd"] = per_n_rates(ctx, cov, "qd", ns=(20, 28), full=True)
+        out["full_pattern_inverse"] = full_pattern_inverse(ctx, cov)
         out["per_n_displaced"] = per_n_rates(ctx, cov, args.prec, ns=(20, 24, 28),
                                              mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
         out["per_n_displaced_f64_terms"] = per_n_rates(ctx, cov, "f64", ns=(20, 24, 28),

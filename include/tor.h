@@ -197,6 +197,29 @@ tor_status tor_state_create_displaced(tor_ctx *ctx, const double *cov, const dou
                                       tor_state **out);
 void tor_state_destroy(tor_state *st);
 
+/* Per-state preprocessing for full patterns (every mode 1 or 0; Sec. II's
+ * vacuum conditioning done once per state instead of once per query).
+ * Forms K = sigma_Q^-1 of a zero-mean state on the GPU by one symmetric 2x2
+ * sweep per mode, with det(sigma_Q)^-1/2, in double-double words (prec
+ * TOR_PREC_F64, TOR_PREC_DD or TOR_PREC_AUTO) or quad-double words
+ * (TOR_PREC_QD), and keeps them with the state (E(m) = m(2m+1) words on the
+ * host; the device buffer is freed before returning).  Afterwards tor_batch
+ * and the server evaluate a full pattern with at least one no-click mode of
+ * this state from G = K[C] (the clicked modes' block) by Jacobi's
+ * complementary-minor identity:
+ *   p(C, N) = (-1)^n det(sigma_Q)^-1/2 T(G),   T(Sigma_C) = (-1)^n det(G)^1/2 T(G),
+ * a gather and one subset tree per query.  The terms of T(G) are those of
+ * T(Sigma_C) times one constant, so the cancellation ratio and error bound
+ * are the same.  A double-double inverse serves binary64 and double-double
+ * terms (quad-double queries of the state keep the per-query conditioning);
+ * a quad-double inverse serves every precision.  Patterns with unobserved
+ * modes (-1) keep the per-query conditioning.  Errors: TOR_EINVAL (NULL,
+ * displaced state, bad prec), TOR_ETOOBIG (m > 2048), TOR_ENOMEM,
+ * TOR_ENOTPD (a non-positive pivot; a previous inverse is kept).  Not
+ * thread-safe against other calls on the state (call it before submitting
+ * queries of the state). */
+tor_status tor_state_invert(tor_state *st, tor_prec prec);
+
 /* nq queries on one state, patterns = nq x m int8 (row per query), results in
  * out[nq].  All queries' subset trees are evaluated in shared launches, each
  * with its own fixed reduction order, so every result is bitwise identical to

@@ -136,6 +136,7 @@ def lib():
         "tor_state_create": ([vp, dp, ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int32),
         "tor_state_create_displaced": ([vp, dp, dp, ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int32),
         "tor_state_destroy": ([vp], None),
+        "tor_state_invert": ([vp, ctypes.c_int], ctypes.c_int32),
         "tor_batch": ([vp, vp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
                        ctypes.POINTER(_CResult)], ctypes.c_int32),
         "tor_batch_displaced": ([vp, vp, dp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
@@ -446,6 +447,13 @@ class State:
     @property
     def handle(self):
         return self._h
+
+    def invert(self, prec="dd"):
+        """tor_state_invert: sigma_Q^-1 of this (zero-mean) state, after which
+        full patterns are evaluated from its clicked block (no per-query
+        conditioning).  prec "qd" keeps quad-double words."""
+        _check(lib().tor_state_invert(self._h, _PREC[prec]))
+        return self
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -24,6 +24,7 @@
 #include "dd.hpp"
 #include "qd.hpp"
 #include "tor.h"
+#include "tor_invert.h"
 #include "tor_kernels.h"
 
 #pragma clang fp contract(off)
@@ -122,6 +123,13 @@ struct tor_state {
     std::vector<double> mean;  // displaced states only (2m entries), else empty
     DevBuf dmean;               // device copy of the mean for tor_batch_async (made on first use)
     DevBuf dcov;  // device copy for tor_batch_async (made on first use)
+    // tor_state_invert: sigma_Q^-1 in packed lower storage (double-double or
+    // quad-double words), det(sigma_Q)^-1/2 and log det sigma_Q
+    int inv_prec = 0;  // 0: not inverted; TOR_PREC_DD or TOR_PREC_QD
+    std::vector<dd> inv;
+    std::vector<qd> inv_q;
+    dd det_rsqrt = {1.0, 0.0};
+    double log_det_sigq = 0.0;
 };
 
 // ------------------------------------------------------------------ host math
@@ -232,6 +240,11 @@ struct Reduced {
     bool cond = false;          // conditioning on N still to do
     int k = 0;                  // |N|
     std::vector<dd> packed;     // sigma_Q over (C, N), EN(n + k, D) entries
+    // full pattern on an inverted state: sig holds G = sigma_Q^-1 over C (not
+    // Sigma_C = G^-1), and the tree's sum of G times tscale = (-1)^n det(G)^1/2
+    // is the sum of Sigma_C
+    bool jacobi = false;
+    dd tscale = {1.0, 0.0};
 };
 
 // Displaced state (mean mu, hbar = 1, interleaved like cov): the packed matrix
@@ -764,6 +777,8 @@ struct Prepared {
     dd pvac = {1.0, 0.0};
     double log_pvac = 0.0;
     double log_det = 0.0;
+    bool scaled = false;  // the tree sums G = Sigma_C^-1: multiply its (T, A) by tscale
+    dd tscale = {1.0, 0.0};
     tor_status status = TOR_OK;
     std::string err;
 };
@@ -876,21 +891,84 @@ tor_status prepare_disp(std::vector<dd> &&packed, int n, dd pvac, double log_pva
     return TOR_OK;
 }
 
+// Every mode observed (1 or 0) and at least one no-click mode.
+bool is_full_pattern(const int8_t *pattern, int m) {
+    bool zero = false;
+    for (int i = 0; i < m; i++) {
+        if (pattern[i] == 0) zero = true;
+        else if (pattern[i] != 1) return false;
+    }
+    return zero;
+}
+
+// A full pattern on an inverted state (Jacobi's complementary-minor identity,
+// det sigma_Q[S] = det sigma_Q det K[S^c] with K = sigma_Q^-1): Sigma_C =
+// G^-1 with G = K[C], so every term of the subset sum of Sigma_C is
+// det(G)^1/2 times a term of the subset sum of G with the complementary set,
+// T(Sigma_C) = (-1)^n det(G)^1/2 T(G), and P_vac(N) = (det sigma_Q det G)^-1/2.
+// G is gathered in double-double (the quad-double inverse rounded when the
+// state holds that one); det(G)^(+-1/2) from its double-double Cholesky.
+tor_status reduce_pattern_jacobi(const tor_state *st, const int8_t *pattern, Reduced &out) {
+    std::vector<int> C;
+    for (int i = 0; i < st->m; i++)
+        if (pattern[i] == 1) C.push_back(i);
+    const int n = (int)C.size();
+    if (n > TOR_MAX_CLICKS) return fail(TOR_ETOOBIG, "%d clicks > %d", n, TOR_MAX_CLICKS);
+    out = Reduced();
+    out.n = n;
+    out.k = st->m - n;
+    out.jacobi = true;
+    const int dc = 2 * n;
+    out.sig.assign((size_t)dc * dc, dd_from(0.0));
+    for (int a = 0; a < dc; a++)
+        for (int b = 0; b <= a; b++) {  // C ascending: global row >= global column
+            const size_t e = (size_t)pidx(2 * C[a / 2] + (a & 1), 2 * C[b / 2] + (b & 1));
+            const dd v = st->inv_prec == TOR_PREC_QD ? qd_to_dd(st->inv_q[e]) : st->inv[e];
+            out.sig[(size_t)a * dc + b] = v;
+            out.sig[(size_t)b * dc + a] = v;
+        }
+    dd root = dd_from(1.0), rroot = dd_from(1.0);  // det(G)^1/2, det(G)^-1/2
+    double log_det_g = 0.0;
+    if (n > 0) {
+        std::vector<dd> L = out.sig, rinv;
+        if (!dd_cholesky(L, dc, rinv, &log_det_g)) return fail(TOR_ENOTPD, "sigma_Q^-1 over C is not positive definite");
+        for (int j = 0; j < dc; j++) {
+            root = dd_mul(root, L[(size_t)j * dc + j]);
+            rroot = dd_mul(rroot, rinv[j]);
+        }
+    }
+    out.pvac = dd_mul(st->det_rsqrt, rroot);
+    out.log_pvac = -0.5 * (st->log_det_sigq + log_det_g);
+    out.tscale = (n & 1) ? dd_neg(root) : root;
+    return TOR_OK;
+}
+
 // A pattern of a state (zero-mean or displaced) reduced for the subset tree.
+// Full patterns on an inverted zero-mean state take the complementary-minor
+// route (no conditioning); the quad-double inverse also serves binary64 and
+// double-double terms.
 tor_status reduce_for_state(const tor_state *st, const int8_t *pattern, Reduced &out) {
-    return st->mean.empty() ? reduce_pattern(st->cov.data(), st->m, pattern, out)
-                            : reduce_pattern_disp(st->cov.data(), st->mean.data(), st->m, pattern, out);
+    if (!pattern) return fail(TOR_EINVAL, "pattern is NULL");
+    if (!st->mean.empty()) return reduce_pattern_disp(st->cov.data(), st->mean.data(), st->m, pattern, out);
+    if (st->inv_prec && is_full_pattern(pattern, st->m)) return reduce_pattern_jacobi(st, pattern, out);
+    return reduce_pattern(st->cov.data(), st->m, pattern, out);
 }
 
 // A reduced pattern, conditioned if it had no-click modes, made ready for the GPU.
 tor_status prepare_reduced(Reduced &r, Prepared &p) {
     if (r.D) return prepare_disp(std::move(r.packed), r.n, r.pvac, r.log_pvac, p);
-    return prepare(r.sig, r.n, r.pvac, r.log_pvac, p);
+    tor_status s = prepare(r.sig, r.n, r.pvac, r.log_pvac, p);
+    if (s == TOR_OK && r.jacobi) {  // prepare saw G: log det Sigma_C = -log det G
+        p.log_det = -p.log_det;
+        p.scaled = true;
+        p.tscale = r.tscale;
+    }
+    return s;
 }
 
 void finalize(const Prepared &p, const SumOut &s, int used, double tol, tor_result *out) {
-    const dd T = s.T;
-    const double A = s.A;
+    const dd T = p.scaled ? dd_mul(p.tscale, s.T) : s.T;
+    const double A = p.scaled ? std::fabs(p.tscale.hi) * s.A : s.A;
     dd pr = dd_mul(p.pvac, T);
     std::memset(out, 0, sizeof *out);
     out->p = pr.hi + pr.lo;
@@ -1066,15 +1144,31 @@ tor_status condition_qd(tor_ctx *ctx, const Reduced &r, std::vector<qd> &sigc, d
 }
 
 // Probability of one pattern with quad-double terms (conditioning included).
+// With st (a state inverted in quad-double) a full pattern takes the
+// complementary-minor route with G gathered from the quad-double inverse.
 tor_status probability_qd(tor_ctx *ctx, const double *cov, int m, const int8_t *pattern, double tol,
-                          tor_result *out) {
+                          tor_result *out, const tor_state *st = nullptr) {
     Reduced red;
-    tor_status s = reduce_pattern(cov, m, pattern, red);
+    const bool jacobi = st && st->inv_prec == TOR_PREC_QD && pattern && is_full_pattern(pattern, m);
+    tor_status s = jacobi ? reduce_pattern_jacobi(st, pattern, red) : reduce_pattern(cov, m, pattern, red);
     if (s) return s;
     std::vector<qd> sigc;
     Prepared p;
     p.n = red.n;
-    if (red.cond) {
+    if (jacobi) {
+        std::vector<int> C;
+        for (int i = 0; i < m; i++)
+            if (pattern[i] == 1) C.push_back(i);
+        const int dc = 2 * red.n;
+        sigc.assign((size_t)E(red.n), qd_from(0.0));
+        for (int a = 0; a < dc; a++)
+            for (int b = 0; b <= a; b++)
+                sigc[(size_t)pidx(a, b)] = st->inv_q[(size_t)pidx(2 * C[a / 2] + (a & 1), 2 * C[b / 2] + (b & 1))];
+        p.pvac = red.pvac;
+        p.log_pvac = red.log_pvac;
+        p.scaled = true;
+        p.tscale = red.tscale;
+    } else if (red.cond) {
         s = condition_qd(ctx, red, sigc, p.pvac, p.log_pvac);
         if (s) return s;
     } else {
@@ -1093,6 +1187,7 @@ tor_status probability_qd(tor_ctx *ctx, const double *cov, int m, const int8_t *
                 full[(size_t)b * dc + a] = v;
             }
         if (!f64_cholesky_logdet(full, dc, &p.log_det)) return fail(TOR_ENOTPD, "Sigma_C is not positive definite");
+        if (jacobi) p.log_det = -p.log_det;  // the matrix was G = Sigma_C^-1
     }
     SumOut so;
     s = gpu_sum_qd(ctx, sigc, red.n, so);
@@ -1398,12 +1493,78 @@ tor_status tor_state_create_displaced(tor_ctx *ctx, const double *cov, const dou
 
 void tor_state_destroy(tor_state *st) {
     if (!st) return;
-    if (st->dcov.p) {
+    if (st->dcov.p || st->dmean.p) {
         (void)hipSetDevice(st->device);
         st->dcov.release();
+        st->dmean.release();
         (void)hipGetLastError();  // leave no error for the next checked call
     }
     delete st;
+}
+
+tor_status tor_state_invert(tor_state *st, tor_prec prec) {
+    if (!st) return fail(TOR_EINVAL, "state is NULL");
+    if (!st->mean.empty())
+        return fail(TOR_EINVAL, "tor_state_invert takes zero-mean states (a displaced state conditions per query)");
+    if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD && prec != TOR_PREC_QD)
+        return fail(TOR_EINVAL, "precision %d is not a tor_prec", (int)prec);
+    const int m = st->m;
+    if (m > TOR_INVERT_MAX_MODES) return fail(TOR_ETOOBIG, "m = %d > %d modes for the inverse", m, TOR_INVERT_MAX_MODES);
+    const bool q = prec == TOR_PREC_QD;
+    tor_ctx *ctx = st->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int d = 2 * m;
+    const size_t ent = (size_t)E(m), es = q ? sizeof(qd) : sizeof(dd);
+    const size_t cols_off = align_up(ent * es, 256);
+    const size_t piv_off = align_up(cols_off + 2 * (size_t)d * es, 256);
+    const size_t acc_off = align_up(piv_off + 3 * es, 256);
+    const size_t total = acc_off + 3 * sizeof(double);
+    if (total > ctx->mem_budget) return fail(TOR_ENOMEM, "the inverse needs %.2f GB of device memory", total / 1e9);
+    struct Scoped {  // the device buffer lives for this call only
+        DevBuf b;
+        ~Scoped() { b.release(); }
+    } buf;
+    if (buf.b.ensure(total) != hipSuccess)
+        return fail(TOR_ENOMEM, "device allocation of %.2f GB failed", total / 1e9);
+    unsigned char *db = (unsigned char *)buf.b.p;
+    std::vector<unsigned char> stage(total);
+    const double *cov = st->cov.data();
+    for (int a = 0; a < d; a++)
+        for (int b = 0; b <= a; b++) {
+            const dd v = sigq(cov, m, a, b);
+            const size_t e = (size_t)pidx(a, b);
+            if (q) ((qd *)stage.data())[e] = qd_from_dd(v);
+            else ((dd *)stage.data())[e] = v;
+        }
+    const double a0[3] = {1.0, 0.0, 0.0};
+    std::memcpy(stage.data() + acc_off, a0, sizeof a0);
+    hipStream_t hs = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(db, stage.data(), total, hipMemcpyHostToDevice, hs));
+    for (int k = 0; k < m; k++)
+        HIP_TRY(tor_launch_sweep(q, db, m, k, db + cols_off, db + piv_off, (double *)(db + acc_off), hs));
+    HIP_TRY(hipMemcpyAsync(stage.data(), db, cols_off, hipMemcpyDeviceToHost, hs));
+    double acc[3];
+    HIP_TRY(hipMemcpyAsync(acc, db + acc_off, sizeof acc, hipMemcpyDeviceToHost, hs));
+    HIP_TRY(hipStreamSynchronize(hs));
+    if (!(acc[0] > 0.0) || !std::isfinite(acc[0]) || !std::isfinite(acc[2]))
+        return fail(TOR_ENOTPD, "a pivot of sigma_Q was not positive");
+    // the sweeps leave -sigma_Q^-1
+    st->inv_prec = 0;
+    std::vector<dd>().swap(st->inv);
+    std::vector<qd>().swap(st->inv_q);
+    if (q) {
+        st->inv_q.resize(ent);
+        const qd *A = (const qd *)stage.data();
+        for (size_t e = 0; e < ent; e++) st->inv_q[e] = qd_neg(A[e]);
+    } else {
+        st->inv.resize(ent);
+        const dd *A = (const dd *)stage.data();
+        for (size_t e = 0; e < ent; e++) st->inv[e] = dd_neg(A[e]);
+    }
+    st->det_rsqrt = dd_make(acc[0], acc[1]);
+    st->log_det_sigq = -2.0 * acc[2];
+    st->inv_prec = q ? TOR_PREC_QD : TOR_PREC_DD;
+    return TOR_OK;
 }
 
 tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *patterns, tor_prec prec,
@@ -1423,7 +1584,8 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
         tor_status first = TOR_OK;
         for (int q = 0; q < nq; q++) {
             std::memset(&out[q], 0, sizeof out[q]);
-            tor_status s = probability_qd(ctx, st->cov.data(), st->m, patterns + (size_t)q * st->m, tol, &out[q]);
+            tor_status s =
+                probability_qd(ctx, st->cov.data(), st->m, patterns + (size_t)q * st->m, tol, &out[q], st);
             if (s < 0) {
                 std::memset(&out[q], 0, sizeof out[q]);
                 out[q].status = s;

@@ -74,3 +74,7 @@ def test_null_context_rejected_displaced():
     st = L.tor_probability_displaced(None, tg._dptr(cov), tg._dptr(mean), 1, tg._i8ptr(pat), 0, 1e-10,
                                      ctypes.byref(r))
     assert st == tg.TOR_EINVAL
+
+
+def test_null_state_rejected_by_invert():
+    assert tg.lib().tor_state_invert(None, tg.PREC_DD) == tg.TOR_EINVAL

@@ -1,0 +1,203 @@
+"""Per-state inverse (tor_state_invert) and the complementary-minor route for
+full patterns: with K = sigma_Q^-1 and G = K[C], p(C, N) = (-1)^n
+det(sigma_Q)^-1/2 T(G) (Jacobi's identity det sigma_Q[S] = det sigma_Q
+det K[S^c] applied to every vacuum probability of Eq. (prob)).
+
+* the all-no-click pattern is det(sigma_Q)^-1/2: against the binary128 oracle
+  and the closed form prod_k sech(r_k) of squeezed vacua (the interferometer
+  keeps the vacuum overlap);
+* full patterns against the oracle's definition route (form P) and its
+  conditioned route (form S), and against the per-query conditioning of the
+  library itself, in double-double and quad-double;
+* the 800-mode full pattern of the bench workload: quad-double inverse against
+  quad-double per-query conditioning;
+* batches mixing full, partial and marginal patterns, the server, and errors.
+"""
+import numpy as np
+import pytest
+
+import gbs_inputs as gi
+import oracle
+import paper_1810_00900_amd as tg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tg.Context(0)
+    yield c
+    c.close()
+
+
+def _mp(r):
+    import mpmath as mp
+    mp.mp.dps = 80
+    return mp.mpf(r.p) + mp.mpf(r.p_lo)
+
+
+def _rel(a, b):
+    import mpmath as mp
+    mp.mp.dps = 80
+    a, b = mp.mpf(a), mp.mpf(b)
+    return float(abs((a - b) / b)) if b != 0 else float(abs(a))
+
+
+def _orc(o):
+    import mpmath as mp
+    mp.mp.dps = 80
+    return mp.mpf(o.p) + mp.mpf(o.p_lo)
+
+
+def _state(m, seed, lo=0.3, hi=0.9):
+    rng = np.random.default_rng(seed)
+    U = gi.haar_unitary(m, rng)
+    r = rng.uniform(lo, hi, size=m)
+    return gi.gbs_covariance(U, r), r, rng
+
+
+@pytest.mark.parametrize("prec", ["dd", "qd"])
+def test_all_no_click_is_det_rsqrt(ctx, prec):
+    cov, r, _ = _state(40, 150)
+    st = ctx.state(cov).invert(prec)
+    pat = np.zeros(40, np.int8)
+    res, status = ctx.batch(st, pat[None, :], prec="dd")
+    got = _mp(res[0])
+    want = _orc(oracle.formS(cov, pat))
+    assert _rel(got, want) <= 1e-28
+    import mpmath as mp
+    mp.mp.dps = 50
+    closed = mp.mpf(1)
+    for x in r:
+        closed /= mp.cosh(mp.mpf(float(x)))
+    assert _rel(got, closed) <= 1e-12  # the binary64 covariance is exact only to ~1e-16
+    assert res[0].n_clicks == 0 and res[0].status == tg.TOR_OK
+    st.close()
+
+
+@pytest.mark.parametrize("prec", ["dd", "f64"])
+def test_full_patterns_dd_inverse(ctx, prec):
+    m = 20
+    cov, _, rng = _state(m, 151)
+    plain = ctx.state(cov)
+    inv = ctx.state(cov).invert("dd")
+    pats = [gi.full_pattern(m, gi.random_click_set(m, n, rng)) for n in (1, 3, 6, 9, 12)]
+    pats = np.stack(pats)
+    got, _ = ctx.batch(inv, pats, prec=prec)
+    cond, _ = ctx.batch(plain, pats, prec=prec)
+    for pat, g, c in zip(pats, got, cond):
+        n = int(pat.sum())
+        o = oracle.formP(cov, pat) if n <= 6 else oracle.formS(cov, pat)
+        err = _rel(_mp(g), _orc(o))
+        assert err <= g.rel_err_bound + 1e-28
+        if prec == "dd":
+            assert err <= 1e-10
+        # the other route of the library: same quantity, same cancellation
+        assert g.n_clicks == c.n_clicks == n
+        both = g.rel_err_bound + c.rel_err_bound
+        assert _rel(g.cancel_ratio, c.cancel_ratio) <= both + 1e-10
+        assert _rel(_mp(g), _mp(c)) <= both + 1e-28
+        assert _rel(g.T, c.T) <= both + 1e-14  # T of Sigma_C from the sum of G
+        assert _rel(g.tor, c.tor) <= both + 1e-9
+        assert abs(g.log_p - c.log_p) <= both + 1e-12 * abs(c.log_p)
+    plain.close()
+    inv.close()
+
+
+def test_full_patterns_qd_inverse(ctx):
+    m = 24
+    cov, _, rng = _state(m, 152)
+    inv = ctx.state(cov).invert("qd")
+    plain = ctx.state(cov)
+    pats = np.stack([gi.full_pattern(m, gi.random_click_set(m, n, rng)) for n in (2, 5, 10, 14)])
+    got, _ = ctx.batch(inv, pats, prec="qd")
+    cond, _ = ctx.batch(plain, pats, prec="qd")
+    dd_on_qd, _ = ctx.batch(inv, pats, prec="dd")  # double-double terms from the rounded qd inverse
+    for pat, g, c, d in zip(pats, got, cond, dd_on_qd):
+        assert g.prec_used == tg.PREC_QD
+        o = oracle.formS(cov, pat)
+        assert _rel(_mp(g), _orc(o)) <= 1e-25
+        # results are reported as double-double (p + p_lo), the factors
+        # det(sigma_Q)^-1/2 and det(G)^1/2 formed in double-double
+        assert _rel(_mp(g), _mp(c)) <= g.rel_err_bound + c.rel_err_bound + 1e-29
+        assert _rel(_mp(d), _mp(g)) <= d.rel_err_bound + 1e-28
+    inv.close()
+    plain.close()
+
+
+def test_m800_full_pattern_qd_routes_agree(ctx):
+    """An 800-mode full pattern with 20 clicks (all modes observed, 780
+    without a click): quad-double inverse against quad-double per-query
+    conditioning."""
+    cov = gi.state_m800(50)
+    m = 800
+    rng = np.random.default_rng(153)
+    clicks = gi.random_click_set(m, 20, rng)
+    pat = gi.full_pattern(m, clicks)
+    inv = ctx.state(cov).invert("qd")
+    got, _ = ctx.batch(inv, pat[None, :], prec="qd")
+    want = ctx.probability(cov, pat, prec="qd")
+    g = got[0]
+    print("m800 n20 full: p", g.p, "bound", g.rel_err_bound, want.rel_err_bound,
+          "routes differ by", _rel(_mp(g), _mp(want)))
+    assert g.status in (tg.TOR_OK, tg.TOR_WARN_PRECISION)
+    assert g.cancel_ratio == pytest.approx(want.cancel_ratio, rel=1e-6)
+    assert _rel(_mp(g), _mp(want)) <= g.rel_err_bound + want.rel_err_bound + 1e-29  # observed 8.7e-31
+    inv.close()
+
+
+def test_mixed_batch_and_server(ctx):
+    m = 30
+    cov, _, rng = _state(m, 154)
+    inv = ctx.state(cov).invert("dd")
+    pats = []
+    for n in (2, 5, 8, 11):
+        c = gi.random_click_set(m, n, rng)
+        pats.append(gi.full_pattern(m, c))          # inverse route
+        pats.append(gi.marginal_pattern(m, c))      # gather of sigma_Q[C]
+        part = gi.full_pattern(m, c)
+        part[np.setdiff1d(np.arange(m), c)[:4]] = -1
+        pats.append(part)                          # per-query conditioning
+    pats = np.stack(pats)
+    a, _ = ctx.batch(inv, pats, prec="dd")
+    b, _ = ctx.batch(inv, pats, prec="dd")
+    for x, y in zip(a, b):
+        assert (x.p, x.p_lo, x.T, x.T_lo, x.abs_sum) == (y.p, y.p_lo, y.T, y.T_lo, y.abs_sum)
+    for pat, x in zip(pats, a):
+        if (pat == -1).any():  # not a full pattern: the single-query path, bitwise
+            s = ctx.probability(cov, pat, prec="dd")
+            assert (x.p, x.p_lo, x.T, x.T_lo) == (s.p, s.p_lo, s.T, s.T_lo)
+        assert _rel(_mp(x), _orc(oracle.formS(cov, pat))) <= 1e-10
+    srv = tg.Server(ctx, workers=2, prec="dd")
+    tickets = [srv.submit(inv, p) for p in pats]
+    for t, x in zip(tickets, a):
+        r, _lat = srv.wait(t)
+        assert (r.p, r.p_lo, r.T, r.T_lo) == (x.p, x.p_lo, x.T, x.T_lo)
+    srv.stop()
+    inv.close()
+
+
+def test_invert_errors(ctx):
+    m = 6
+    cov, _, rng = _state(m, 155)
+    disp = ctx.state(cov, mean=gi.random_mean(m, rng, 0.3))
+    with pytest.raises(tg.TorError) as e:
+        disp.invert("dd")
+    assert e.value.status == tg.TOR_EINVAL
+    disp.close()
+    bad = ctx.state(-np.eye(2 * m))  # sigma_Q = -I/2: not positive definite
+    with pytest.raises(tg.TorError) as e:
+        bad.invert("dd")
+    assert e.value.status == tg.TOR_ENOTPD
+    # a failed inversion leaves the state usable by the per-query route
+    with pytest.raises(tg.TorError) as e:
+        ctx.batch(bad, gi.marginal_pattern(m, [1])[None, :], prec="dd")
+    assert e.value.status == tg.TOR_ENOTPD
+    bad.close()
+    st = ctx.state(cov)
+    import ctypes
+    assert tg.lib().tor_state_invert(st.handle, ctypes.c_int(9)) == tg.TOR_EINVAL
+    st.invert("dd").invert("qd")  # re-inversion replaces the inverse
+    res, _ = ctx.batch(st, gi.full_pattern(m, [0, 3])[None, :], prec="qd")
+    assert _rel(_mp(res[0]), _orc(oracle.formP(cov, gi.full_pattern(m, [0, 3])))) <= 1e-28
+    st.close()
