@@ -416,12 +416,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-n, sampler and serving measurements")
     ap.add_argument("--copy-calibration", action="store_true", help="only run the 1 GiB copy used to scale counters")
+    ap.add_argument("--invert-only", action="store_true",
+                    help="only invert the 800-mode state (dd, qd) and time full patterns on it (for profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.invert_only:
+        import gbs_inputs as gi
+        import paper_1810_00900_amd as tg
+        ctx = tg.Context(0)
+        print(json.dumps(full_pattern_inverse(ctx, gi.state_m800(50))), flush=True)
+        ctx.close()
+        return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the subset sum would shard by prefix bits with one 24-byte exchange per GPU)",
               file=sys.stderr)
         sys.exit(2)

@@ -202,6 +202,39 @@ def test_routes_agree_mpmath(oracle_lib):
         assert abs((b.p + b.p_lo) - ref) <= 1e-28 * abs(ref) * b.cancel_ratio
 
 
+def test_complementary_minor_route(oracle_lib):
+    """The identity behind full patterns on an inverted state: with
+    K = sigma_Q^-1 and G = K[C], p(C, N) = (-1)^n det(sigma_Q)^-1/2 T(G) when
+    every mode is observed (Jacobi: det sigma_Q[S] = det sigma_Q det K[S^c]).
+    Evaluated by brute force in mpmath (inverse, determinants and the subset
+    sum of G) against the oracle's definition route."""
+    import mpmath as mp
+    mp.mp.dps = 60
+    rng = np.random.default_rng(160)
+    m = 7
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.3, 0.9, m))
+    d = 2 * m
+    sq = mp.matrix(d, d)
+    for a in range(d):
+        for b in range(d):
+            sq[a, b] = mp.mpf(float(cov[a, b])) + (mp.mpf(1) / 2 if a == b else 0)
+    K = sq ** -1
+    rdet = mp.det(sq) ** (-mp.mpf(1) / 2)
+    for clicks in ([2], [0, 5], [1, 3, 6], [0, 2, 4, 6], list(range(m))):
+        pat = gi.full_pattern(m, clicks)
+        n = len(clicks)
+        rows = [2 * c + t for c in clicks for t in (0, 1)]
+        T = mp.mpf(0)
+        for mask in range(1 << n):
+            sub = [rows[2 * i + t] for i in range(n) if mask >> i & 1 for t in (0, 1)]
+            det = mp.det(mp.matrix([[K[a, b] for b in sub] for a in sub])) if sub else mp.mpf(1)
+            T += (-1) ** bin(mask).count("1") / mp.sqrt(det)
+        want = (-1) ** n * rdet * T
+        o = oracle.formP(cov, pat)
+        got = mp.mpf(o.p) + mp.mpf(o.p_lo)
+        assert abs(got - want) <= 1e-28 * abs(want) * max(o.cancel_ratio, 1.0)
+
+
 def test_product_state_many_clicks(oracle_lib):
     """A product state with 14 clicks: heavy cancellation (R ~ 1e7+), closed
     form known, so binary128 accuracy is pinned at a size where FP64 fails."""
