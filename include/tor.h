@@ -208,7 +208,8 @@ void tor_state_destroy(tor_state *st);
  * this state from G = K[C] (the clicked modes' block) by Jacobi's
  * complementary-minor identity:
  *   p(C, N) = (-1)^n det(sigma_Q)^-1/2 T(G),   T(Sigma_C) = (-1)^n det(G)^1/2 T(G),
- * a gather and one subset tree per query.  The terms of T(G) are those of
+ * a gather and one subset tree per query (tor_batch_async takes such full
+ * patterns too).  The terms of T(G) are those of
  * T(Sigma_C) times one constant, so the cancellation ratio and error bound
  * are the same.  A double-double inverse serves binary64 and double-double
  * terms (quad-double queries of the state keep the per-query conditioning);
@@ -247,15 +248,22 @@ tor_status tor_batch_displaced(tor_ctx *ctx, const tor_state *st, const double *
  * until then.  The plan is made on the device for the same trees and
  * reduction order as tor_batch: results (p, p_lo, T, T_lo, abs_sum) are
  * bitwise those of tor_batch; log_p and tor may differ in the last bit.
- * Marginal patterns only (entries 1 or -1): a query with a no-click mode (0)
- * or a bad entry gets status TOR_EINVAL in its result (no-click conditioning
- * needs host planning: use tor_batch), more than 32 clicks TOR_ETOOBIG.
+ * Marginal patterns (entries 1 or -1), and full patterns (entries 1 or 0)
+ * of a state inverted by tor_state_invert: G = sigma_Q^-1 over C is
+ * gathered on the device and p = (-1)^n det(sigma_Q)^-1/2 T(G) is bitwise
+ * tor_batch's; the reported T, abs_sum, cancel_ratio, rel_err_bound and tor
+ * of such a query are rescaled to Sigma_C with a binary64 det(G)^1/2 (relative
+ * difference from tor_batch's ~1e-15).  Any other query with a no-click mode
+ * (0), or with a bad entry, gets status TOR_EINVAL in its result (per-query
+ * conditioning needs host planning: use tor_batch), more than 32 clicks
+ * TOR_ETOOBIG.
  * prec: TOR_PREC_F64 or TOR_PREC_DD; TOR_PREC_AUTO is run as TOR_PREC_DD (a
  * query cannot be repeated without a host decision).  Device memory: a
  * workspace whose tree pool holds TOR_OPT_ASYNC_POOL bytes (default 4 GiB);
  * queries are admitted in order while the trees up to them fit, later ones
  * get TOR_ENOMEM.  The first call on a state copies its covariance (and the
- * mean of a displaced state) to the device (synchronously, once).  The workspace belongs to the context: calls
+ * mean of a displaced state, or the inverse of an inverted state) to the
+ * device (synchronously, once).  The workspace belongs to the context: calls
  * on one context must be ordered (same stream, or the caller waits).
  * Returns TOR_OK once enqueued; argument errors (NULL pointers, nq < 0, bad
  * prec, state of another context) and launch or allocation failures are

@@ -130,6 +130,7 @@ struct tor_state {
     std::vector<qd> inv_q;
     dd det_rsqrt = {1.0, 0.0};
     double log_det_sigq = 0.0;
+    DevBuf dinv;  // device copy of the inverse in double-double words for tor_batch_async (first use)
 };
 
 // ------------------------------------------------------------------ host math
@@ -245,6 +246,7 @@ struct Reduced {
     // is the sum of Sigma_C
     bool jacobi = false;
     dd tscale = {1.0, 0.0};
+    dd pdirect = {1.0, 0.0};  // (-1)^n det(sigma_Q)^-1/2: p = pdirect T(G)
 };
 
 // Displaced state (mean mu, hbar = 1, interleaved like cov): the packed matrix
@@ -779,6 +781,7 @@ struct Prepared {
     double log_det = 0.0;
     bool scaled = false;  // the tree sums G = Sigma_C^-1: multiply its (T, A) by tscale
     dd tscale = {1.0, 0.0};
+    dd pdirect = {1.0, 0.0};  // scaled: p = pdirect T(G)
     tor_status status = TOR_OK;
     std::string err;
 };
@@ -940,6 +943,7 @@ tor_status reduce_pattern_jacobi(const tor_state *st, const int8_t *pattern, Red
     out.pvac = dd_mul(st->det_rsqrt, rroot);
     out.log_pvac = -0.5 * (st->log_det_sigq + log_det_g);
     out.tscale = (n & 1) ? dd_neg(root) : root;
+    out.pdirect = (n & 1) ? dd_neg(st->det_rsqrt) : st->det_rsqrt;
     return TOR_OK;
 }
 
@@ -962,6 +966,7 @@ tor_status prepare_reduced(Reduced &r, Prepared &p) {
         p.log_det = -p.log_det;
         p.scaled = true;
         p.tscale = r.tscale;
+        p.pdirect = r.pdirect;
     }
     return s;
 }
@@ -969,7 +974,9 @@ tor_status prepare_reduced(Reduced &r, Prepared &p) {
 void finalize(const Prepared &p, const SumOut &s, int used, double tol, tor_result *out) {
     const dd T = p.scaled ? dd_mul(p.tscale, s.T) : s.T;
     const double A = p.scaled ? std::fabs(p.tscale.hi) * s.A : s.A;
-    dd pr = dd_mul(p.pvac, T);
+    // p = P_vac(N) T(Sigma_C); for the sum of G it is formed directly as
+    // (-1)^n det(sigma_Q)^-1/2 T(G)
+    dd pr = p.scaled ? dd_mul(p.pdirect, s.T) : dd_mul(p.pvac, T);
     std::memset(out, 0, sizeof *out);
     out->p = pr.hi + pr.lo;
     out->p_lo = pr.lo - (out->p - pr.hi);
@@ -1168,6 +1175,7 @@ tor_status probability_qd(tor_ctx *ctx, const double *cov, int m, const int8_t *
         p.log_pvac = red.log_pvac;
         p.scaled = true;
         p.tscale = red.tscale;
+        p.pdirect = red.pdirect;
     } else if (red.cond) {
         s = condition_qd(ctx, red, sigc, p.pvac, p.log_pvac);
         if (s) return s;
@@ -1493,10 +1501,11 @@ tor_status tor_state_create_displaced(tor_ctx *ctx, const double *cov, const dou
 
 void tor_state_destroy(tor_state *st) {
     if (!st) return;
-    if (st->dcov.p || st->dmean.p) {
+    if (st->dcov.p || st->dmean.p || st->dinv.p) {
         (void)hipSetDevice(st->device);
         st->dcov.release();
         st->dmean.release();
+        st->dinv.release();
         (void)hipGetLastError();  // leave no error for the next checked call
     }
     delete st;
@@ -1550,6 +1559,7 @@ tor_status tor_state_invert(tor_state *st, tor_prec prec) {
         return fail(TOR_ENOTPD, "a pivot of sigma_Q was not positive");
     // the sweeps leave -sigma_Q^-1
     st->inv_prec = 0;
+    st->dinv.release();  // a device copy of an earlier inverse is stale
     std::vector<dd>().swap(st->inv);
     std::vector<qd>().swap(st->inv_q);
     if (q) {
@@ -1691,6 +1701,21 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     P.is_dd = use_dd;
     P.D = D;
     P.mean = D ? (const double *)ms->dmean.p : nullptr;
+    // full patterns of an inverted (zero-mean) state: the inverse on the device
+    if (st->inv_prec && !D) {
+        const size_t ent = (size_t)E(m);
+        if (!ms->dinv.p) {
+            std::vector<dd> h(ent);
+            for (size_t e = 0; e < ent; e++) h[e] = st->inv_prec == TOR_PREC_QD ? qd_to_dd(st->inv_q[e]) : st->inv[e];
+            if (ms->dinv.ensure(ent * sizeof(dd)) != hipSuccess)
+                return fail(TOR_ENOMEM, "device copy of the inverse failed");
+            HIP_TRY(hipMemcpy(ms->dinv.p, h.data(), ent * sizeof(dd), hipMemcpyHostToDevice));
+        }
+        P.inv = ms->dinv.p;
+        P.det_rsqrt_hi = st->det_rsqrt.hi;
+        P.det_rsqrt_lo = st->det_rsqrt.lo;
+        P.log_det_sigq = st->log_det_sigq;
+    }
     const int nmax = std::min(TOR_MAX_CLICKS, m);
     int gcap = 0, jmax = 1;
     long long max_tasks[TOR_TASK_MAX + 1] = {};  // per J: tasks of the largest tree

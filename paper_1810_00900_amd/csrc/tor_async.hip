@@ -33,13 +33,14 @@ __global__ __launch_bounds__(64) void async_scan_kernel(const int8_t *__restrict
     for (int q = blockIdx.x; q < P.nq; q += gridDim.x) {
         const int8_t *row = pats + (size_t)q * (size_t)P.m;
         int count = 0;
-        bool bad = false, noclick = false;
+        bool bad = false, noclick = false, unobs = false;
         for (int base = 0; base < P.m; base += 64) {
             const int k = base + lane;
-            const int v = k < P.m ? (int)row[k] : -1;
-            const bool one = v == 1;
+            const int v = k < P.m ? (int)row[k] : 1;  // lanes past the end count as observed
+            const bool one = v == 1 && k < P.m;
             if (v == 0) noclick = true;
-            else if (v != 1 && v != -1) bad = true;
+            else if (v == -1) unobs = true;
+            else if (v != 1) bad = true;
             const unsigned long long mask = __ballot(one);
             const int pos = count + __popcll(mask & ((1ULL << lane) - 1ULL));
             if (one && pos < TOR_MAX_N) P.q[q].C[pos] = k;
@@ -47,10 +48,15 @@ __global__ __launch_bounds__(64) void async_scan_kernel(const int8_t *__restrict
         }
         bad = __any(bad);
         noclick = __any(noclick);
+        unobs = __any(unobs);
         if (lane == 0) {
             AsyncQuery &Q = P.q[q];
+            // a full pattern (no unobserved mode) of an inverted state takes the
+            // complementary-minor route; other no-click patterns are not taken
+            const bool jac = noclick && !unobs && P.inv != nullptr;
             Q.n = count;
-            Q.status = (bad || noclick) ? TOR_EINVAL : (count > TOR_MAX_N ? TOR_ETOOBIG : TOR_OK);
+            Q.jac = jac ? 1 : 0;
+            Q.status = (bad || (noclick && !jac)) ? TOR_EINVAL : (count > TOR_MAX_N ? TOR_ETOOBIG : TOR_OK);
         }
     }
 }
@@ -126,6 +132,8 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
         Q.final_buf = 0;
         Q.log_det = 0.0;
         Q.quad = 0.0;
+        Q.jscale = 1.0;
+        Q.log_pvac = Q.jac ? -0.5 * P.log_det_sigq : 0.0;
         if (Q.status != TOR_OK || Q.n == 0) continue;
         const int n = Q.n;
         const int J = min(n, P.J_of_n[n]);
@@ -263,7 +271,10 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
 // order as the host's, one row per lane); a non-positive pivot gives ENOTPD.
 // Displaced states: the root has the mean row [0, mu_C] first, and the
 // forward solve with the Cholesky factor gives mu_C^T Sigma_C^-1 mu_C for the
-// error bound (as the host computes it).
+// error bound (as the host computes it).  A full pattern of an inverted state
+// (jac) gathers G = sigma_Q^-1 over C instead; its binary64 log det G gives
+// log det Sigma_C = -log det G, log P_vac(N) and the factor (-1)^n det(G)^1/2
+// that turns the tree's sum of G into the sum of Sigma_C.
 template <class S>
 __global__ __launch_bounds__(64) void async_gather_kernel(const double *__restrict__ cov, AsyncPlan P) {
     __shared__ double L[2 * TOR_MAX_N][2 * TOR_MAX_N];
@@ -289,10 +300,14 @@ __global__ __launch_bounds__(64) void async_gather_kernel(const double *__restri
             b -= o;
             const int ga = 2 * Q.C[a >> 1] + (a & 1), gb = 2 * Q.C[b >> 1] + (b & 1);
             const int r = ga > gb ? ga : gb, c = ga > gb ? gb : ga;
-            const double v = cov[(size_t)r * ld + (size_t)c];
             dd x;
-            if (ga == gb) two_sum(v, 0.5, x.hi, x.lo);
-            else x = dd_from(v);
+            if (Q.jac) {
+                x = ((const dd *)P.inv)[pidx(r, c)];
+            } else {
+                const double v = cov[(size_t)r * ld + (size_t)c];
+                if (ga == gb) two_sum(v, 0.5, x.hi, x.lo);
+                else x = dd_from(v);
+            }
             root[pidx(a + o, b + o)] = from_pair<S>(x.hi, x.lo);
             L[a][b] = x.hi + x.lo;
         }
@@ -317,8 +332,12 @@ __global__ __launch_bounds__(64) void async_gather_kernel(const double *__restri
             __syncthreads();
         }
         if (lane == 0) {
-            Q.log_det = logdet;
+            Q.log_det = Q.jac ? -logdet : logdet;
             if (!ok) Q.status = TOR_ENOTPD;
+            if (Q.jac && ok) {
+                Q.jscale = ((n & 1) ? -1.0 : 1.0) * exp(0.5 * logdet);
+                Q.log_pvac = -0.5 * (P.log_det_sigq + logdet);
+            }
             if (o && ok) {  // z = L^-1 mu_C, quad = |z|^2 (forward solve, row order of the host)
                 double quad = 0.0;
                 for (int a = 0; a < d; a++) {
@@ -362,11 +381,22 @@ __global__ void async_finalize_kernel(AsyncPlan P, double tol, int prec_used, to
         out[q] = r;
         return;
     }
-    // marginal pattern: P_vac(N) = 1, p = T
-    const dd pr = dd_mul(dd_from(1.0), T);
+    // marginal pattern: P_vac(N) = 1, p = T.  Full pattern of an inverted
+    // state: p = (-1)^n det(sigma_Q)^-1/2 T(G) (as the host forms it), and the
+    // reported sums are those of Sigma_C, T(Sigma_C) = jscale T(G).
+    dd pr;
+    if (Q.jac) {
+        const double sg = (Q.n & 1) ? -1.0 : 1.0;
+        pr = dd_mul(dd_make(sg * P.det_rsqrt_hi, sg * P.det_rsqrt_lo), T);
+        T = dd_mul_d(T, Q.jscale);
+        A *= fabs(Q.jscale);
+    } else {
+        pr = dd_mul(dd_from(1.0), T);
+    }
     r.p = pr.hi + pr.lo;
     r.p_lo = pr.lo - (r.p - pr.hi);
-    r.log_p = r.p > 0 ? 0.0 + log(T.hi) + log1p(T.lo / T.hi) : -INFINITY;
+    r.log_p = r.p > 0 ? Q.log_pvac + log(T.hi) + log1p(T.lo / T.hi) : -INFINITY;
+    r.log_pvac_n = Q.log_pvac;
     r.T = T.hi;
     r.T_lo = T.lo;
     r.tor = exp(0.5 * Q.log_det) * (T.hi + T.lo);

@@ -99,6 +99,9 @@ struct AsyncQuery {
     int nstage;
     double log_det;      // log det Sigma_C (binary64 Cholesky)
     double quad;         // displaced states: mu_C^T Sigma_C^-1 mu_C (binary64), else 0
+    int jac;             // full pattern on an inverted state: the tree sums G = sigma_Q^-1 over C
+    double jscale;       // jac: (-1)^n det(G)^1/2 (binary64), T(Sigma_C) = jscale T(G)
+    double log_pvac;     // jac: log P_vac(N) = -(log det sigma_Q + log det G) / 2; else 0
     long long slot;      // planner scratch: position of the query's job in a table
     int C[TOR_MAX_N];    // clicked modes, ascending
 };
@@ -107,6 +110,8 @@ struct AsyncPlan {
     int nq, m, is_dd, gcap, jmax;
     int D;               // 1: displaced state (mean row first in every packed matrix)
     const double *mean;  // displaced states: device copy of the mean (2m), else null
+    const void *inv;     // inverted state: sigma_Q^-1 packed lower, double-double words; else null
+    double det_rsqrt_hi, det_rsqrt_lo, log_det_sigq;  // inverted state: det(sigma_Q)^-1/2, log det sigma_Q
     int J_of_n[TOR_MAX_N + 1];
     long long pool_cap, desc_cap, pb_cap;  // capacities (scalars, descriptors, partials)
     AsyncQuery *q;

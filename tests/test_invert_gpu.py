@@ -61,7 +61,7 @@ def test_all_no_click_is_det_rsqrt(ctx, prec):
     cov, r, _ = _state(40, 150)
     st = ctx.state(cov).invert(prec)
     pat = np.zeros(40, np.int8)
-    res, status = ctx.batch(st, pat[None, :], prec="dd")
+    res, status = ctx.batch(st, pat[None, :], prec=prec)  # qd: the one-query quad-double path
     got = _mp(res[0])
     want = _orc(oracle.formS(cov, pat))
     assert _rel(got, want) <= 1e-28
@@ -175,6 +175,38 @@ def test_mixed_batch_and_server(ctx):
         assert (r.p, r.p_lo, r.T, r.T_lo) == (x.p, x.p_lo, x.T, x.T_lo)
     srv.stop()
     inv.close()
+
+
+@pytest.mark.parametrize("inv_prec,prec", [("dd", "dd"), ("dd", "f64"), ("qd", "dd")])
+def test_async_full_patterns(ctx, inv_prec, prec):
+    """tor_batch_async on an inverted state: full patterns gathered from the
+    device copy of the inverse; p bitwise tor_batch's, the sums rescaled to
+    Sigma_C within 1e-13; partial patterns still rejected per query."""
+    import torch
+    m = 40
+    cov, _, rng = _state(m, 156)
+    st = ctx.state(cov).invert(inv_prec)
+    pats = [np.zeros(m, np.int8)]
+    for n in (1, 4, 9, 12, 16):
+        c = gi.random_click_set(m, n, rng)
+        pats.append(gi.full_pattern(m, c))
+        pats.append(gi.marginal_pattern(m, c))
+    part = gi.full_pattern(m, [3, 7])
+    part[10] = -1
+    pats.append(part)
+    pats = np.stack(pats)
+    want, _ = ctx.batch(st, pats, prec=prec)
+    d_out = ctx.batch_async(st, torch.from_numpy(pats).to("cuda"), prec=prec)
+    torch.cuda.synchronize()
+    got = tg.results_from_device(d_out)
+    for pat, g, w in zip(pats, got, want):
+        if (pat == 0).any() and (pat == -1).any():
+            assert g.status == tg.TOR_EINVAL
+            continue
+        assert (g.p, g.p_lo, g.n_clicks, g.prec_used, g.status) == (w.p, w.p_lo, w.n_clicks, w.prec_used, w.status)
+        for f in ("T", "abs_sum", "cancel_ratio", "rel_err_bound", "tor", "log_p", "log_pvac_n"):
+            assert getattr(g, f) == pytest.approx(getattr(w, f), rel=1e-13, abs=1e-300), f
+    st.close()
 
 
 def test_invert_errors(ctx):
