@@ -24,6 +24,7 @@
 #include "dd.hpp"
 #include "qd.hpp"
 #include "tor.h"
+#include "tor_gather.h"
 #include "tor_invert.h"
 #include "tor_kernels.h"
 
@@ -131,6 +132,7 @@ struct tor_state {
     dd det_rsqrt = {1.0, 0.0};
     double log_det_sigq = 0.0;
     DevBuf dinv;  // device copy of the inverse in double-double words for tor_batch_async (first use)
+    std::mutex dev_mu;  // guards the creation of the device copies (dcov, dmean)
 };
 
 // ------------------------------------------------------------------ host math
@@ -241,6 +243,10 @@ struct Reduced {
     bool cond = false;          // conditioning on N still to do
     int k = 0;                  // |N|
     std::vector<dd> packed;     // sigma_Q over (C, N), EN(n + k, D) entries
+    // gathered on the device instead (queries of a state): the rows of (C, N)
+    // as global quadrature indices; packed stays empty until conditioned
+    const tor_state *st = nullptr;
+    std::vector<int> g;
     // full pattern on an inverted state: sig holds G = sigma_Q^-1 over C (not
     // Sigma_C = G^-1), and the tree's sum of G times tscale = (-1)^n det(G)^1/2
     // is the sum of Sigma_C
@@ -257,7 +263,7 @@ struct Reduced {
 // block (the vacuum overlap of a displaced Gaussian).  Conditioning runs on the
 // GPU when N is not empty.
 tor_status reduce_pattern_disp(const double *cov, const double *mean, int m, const int8_t *pattern,
-                               Reduced &out) {
+                               Reduced &out, bool defer = false) {
     if (!pattern) return fail(TOR_EINVAL, "pattern is NULL");
     if (!mean) return fail(TOR_EINVAL, "mean is NULL");
     std::vector<int> C, N;
@@ -286,6 +292,11 @@ tor_status reduce_pattern_disp(const double *cov, const double *mean, int m, con
     out.n = n;
     out.k = k;
     out.D = 1;
+    if (defer && k > 0) {  // gathered on the device by condition_on_gpu
+        out.g = std::move(g);
+        out.cond = true;
+        return TOR_OK;
+    }
     const int d = (int)g.size();
     out.packed.resize((size_t)EN(n + k, 1));
     out.packed[0] = dd_from(0.0);
@@ -297,7 +308,7 @@ tor_status reduce_pattern_disp(const double *cov, const double *mean, int m, con
     return TOR_OK;
 }
 
-tor_status reduce_pattern(const double *cov, int m, const int8_t *pattern, Reduced &out) {
+tor_status reduce_pattern(const double *cov, int m, const int8_t *pattern, Reduced &out, bool defer = false) {
     if (!pattern) return fail(TOR_EINVAL, "pattern is NULL");
     std::vector<int> C, N;
     for (int i = 0; i < m; i++) {
@@ -334,11 +345,50 @@ tor_status reduce_pattern(const double *cov, int m, const int8_t *pattern, Reduc
         g.push_back(2 * c);
         g.push_back(2 * c + 1);
     }
+    out.cond = true;
+    if (defer) {  // gathered on the device by condition_on_gpu
+        out.g = std::move(g);
+        return TOR_OK;
+    }
     const int d = (int)g.size();
     out.packed.resize((size_t)E(n + k));
     for (int a = 0; a < d; a++)
         for (int b = 0; b <= a; b++) out.packed[(size_t)pidx(a, b)] = sigq(cov, m, g[a], g[b]);
-    out.cond = true;
+    return TOR_OK;
+}
+
+// Words of the matrix a query's conditioning starts from.
+size_t cond_words(const Reduced *r) { return r->st ? (size_t)EN(r->n + r->k, r->D) : r->packed.size(); }
+
+// The host packing of a deferred query (its state lives on another device).
+void host_pack(Reduced *r) {
+    const tor_state *st = r->st;
+    const int o = r->D, d = (int)r->g.size();
+    r->packed.assign((size_t)EN(r->n + r->k, o), dd_from(0.0));
+    for (int a = 0; a < d; a++) {
+        if (o) r->packed[(size_t)pidx(a + 1, 0)] = dd_from(st->mean[r->g[a]]);
+        for (int b = 0; b <= a; b++)
+            r->packed[(size_t)pidx(a + o, b + o)] = sigq(st->cov.data(), st->m, r->g[a], r->g[b]);
+    }
+    r->st = nullptr;
+    std::vector<int>().swap(r->g);
+}
+
+// Device copies of a state's covariance (and mean) for the device-side
+// gathers, made once; the caller has the state's device current.
+tor_status state_on_device(const tor_state *st) {
+    tor_state *ms = const_cast<tor_state *>(st);  // the device copies are a cache of the state
+    std::lock_guard<std::mutex> lk(ms->dev_mu);
+    const size_t cov_bytes = 4 * (size_t)st->m * (size_t)st->m * sizeof(double);
+    if (!ms->dcov.p) {
+        if (ms->dcov.ensure(cov_bytes) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the state failed");
+        HIP_TRY(hipMemcpy(ms->dcov.p, st->cov.data(), cov_bytes, hipMemcpyHostToDevice));
+    }
+    if (!st->mean.empty() && !ms->dmean.p) {
+        const size_t mb = st->mean.size() * sizeof(double);
+        if (ms->dmean.ensure(mb) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the mean failed");
+        HIP_TRY(hipMemcpy(ms->dmean.p, st->mean.data(), mb, hipMemcpyHostToDevice));
+    }
     return TOR_OK;
 }
 
@@ -654,24 +704,46 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
     std::vector<Reduced *> rs;
     for (Reduced *r : all)
         if (r->cond) rs.push_back(r);
+    // queries of a state are gathered on the device from its device copy
+    for (Reduced *r : rs) {
+        if (!r->st) continue;
+        if (r->st->device != ctx->device) {
+            host_pack(r);
+            continue;
+        }
+        tor_status s = state_on_device(r->st);
+        if (s) return s;
+    }
     size_t first = 0;
     while (first < rs.size()) {
         // a group that fits half the memory budget (at least one query)
         size_t last = first, bytes = 0;
         while (last < rs.size()) {
-            size_t b = rs[last]->packed.size() * sizeof(dd) + 64;
+            size_t b = cond_words(rs[last]) * sizeof(dd) + 64;
             if (last > first && bytes + b > ctx->mem_budget / 2) break;
             bytes += b;
             last++;
         }
         const size_t nq = last - first;
         std::vector<size_t> off(nq);
-        size_t tot = 0;
+        size_t tot = 0, gtot = 0;
         int kmax = 0;
+        std::vector<GatherJob> gjobs;
+        long long gentries = 0;
         for (size_t i = 0; i < nq; i++) {
+            const Reduced *r = rs[first + i];
             off[i] = tot;
-            tot += rs[first + i]->packed.size();
-            kmax = std::max(kmax, rs[first + i]->k);
+            tot += cond_words(r);
+            kmax = std::max(kmax, r->k);
+            if (r->st) {
+                GatherJob gj{};
+                gj.begin = gentries;
+                gj.m = r->st->m;
+                gj.R = (int)r->g.size();
+                gentries += (long long)cond_words(r);
+                gjobs.push_back(gj);
+                gtot += r->g.size();
+            }
         }
         // jobs of every step, in step order
         std::vector<CondJob> jobs;
@@ -682,6 +754,8 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
             int rmax;
         };
         std::vector<Step> steps;
+        // device layout: the matrices, then [accumulators | step jobs | gather
+        // jobs | gather rows], the latter staged from the host in one copy
         const size_t acc_off = align_up(tot * sizeof(dd), 256);
         const size_t job_off = align_up(acc_off + nq * 3 * sizeof(double), 256);
         for (int t = 0; t < kmax; t++) {
@@ -700,7 +774,9 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
             }
             steps.push_back(st);
         }
-        const size_t total_bytes = job_off + jobs.size() * sizeof(CondJob);
+        const size_t gjob_off = align_up(job_off + jobs.size() * sizeof(CondJob), 256);
+        const size_t gidx_off = align_up(gjob_off + gjobs.size() * sizeof(GatherJob), 256);
+        const size_t total_bytes = gidx_off + gtot * sizeof(int);
         if (total_bytes > ctx->mem_budget)
             return fail(TOR_ENOMEM, "conditioning needs %.2f GB of device memory", total_bytes / 1e9);
         if (ctx->cond.ensure(total_bytes) != hipSuccess)
@@ -708,7 +784,7 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
         unsigned char *dbase = (unsigned char *)ctx->cond.p;
         dd *dmat = (dd *)dbase;
         double *dacc = (double *)(dbase + acc_off);
-        // job pointers (device addresses) and the host image of the buffer
+        // job pointers (device addresses)
         size_t ji = 0;
         for (int t = 0; t < kmax; t++)
             for (size_t i = 0; i < nq; i++) {
@@ -719,34 +795,66 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
                 jobs[ji].qout = nullptr;
                 ji++;
             }
+        // the staged tail: accumulators, step jobs, gather jobs and rows
         std::vector<unsigned char> &stage = ctx->host_stage;
-        if (stage.size() < total_bytes) stage.resize(total_bytes);
-        for (size_t i = 0; i < nq; i++)
-            std::memcpy(stage.data() + off[i] * sizeof(dd), rs[first + i]->packed.data(),
-                        rs[first + i]->packed.size() * sizeof(dd));
+        const size_t tail = total_bytes - acc_off;
+        if (stage.size() < tail) stage.resize(tail);
+        auto at = [&](size_t dev_off) { return stage.data() + (dev_off - acc_off); };  // staged byte
         for (size_t i = 0; i < nq; i++) {
-            double a0[3] = {1.0, 0.0, 0.0};
-            std::memcpy(stage.data() + acc_off + i * 3 * sizeof(double), a0, sizeof a0);
+            const double a0[3] = {1.0, 0.0, 0.0};
+            std::memcpy(at(acc_off) + i * 3 * sizeof(double), a0, sizeof a0);
         }
-        std::memcpy(stage.data() + job_off, jobs.data(), jobs.size() * sizeof(CondJob));
+        std::memcpy(at(job_off), jobs.data(), jobs.size() * sizeof(CondJob));
+        {
+            size_t gi = 0, gw = 0;
+            int *gidx = (int *)at(gidx_off);
+            for (size_t i = 0; i < nq; i++) {
+                const Reduced *r = rs[first + i];
+                if (!r->st) continue;
+                GatherJob &gj = gjobs[gi++];
+                gj.cov = (const double *)r->st->dcov.p;
+                gj.mean = r->D ? (const double *)r->st->dmean.p : nullptr;
+                gj.g = (const int *)(dbase + gidx_off) + gw;
+                gj.out = dmat + off[i];
+                std::memcpy(gidx + gw, r->g.data(), r->g.size() * sizeof(int));
+                gw += r->g.size();
+            }
+            std::memcpy(at(gjob_off), gjobs.data(), gjobs.size() * sizeof(GatherJob));
+        }
         hipStream_t st = ctx->stream;
-        HIP_TRY(hipMemcpyAsync(dbase, stage.data(), total_bytes, hipMemcpyHostToDevice, st));
+        for (size_t i = 0; i < nq; i++)  // host-packed matrices
+            if (!rs[first + i]->st)
+                HIP_TRY(hipMemcpyAsync(dmat + off[i], rs[first + i]->packed.data(),
+                                       rs[first + i]->packed.size() * sizeof(dd), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(dbase + acc_off, stage.data(), tail, hipMemcpyHostToDevice, st));
+        HIP_TRY(tor_launch_cond_gather((const GatherJob *)(dbase + gjob_off), (int)gjobs.size(), gentries, st));
         const CondJob *djobs = (const CondJob *)(dbase + job_off);
         for (const Step &sp : steps)
             HIP_TRY(tor_launch_condition(djobs + sp.first, sp.count, sp.blocks, sp.rmax, st));
-        // results: the leading E(n) block of each matrix and the accumulators
-        HIP_TRY(hipMemcpyAsync(stage.data(), dbase, acc_off + nq * 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+        // results: the leading block of each matrix and the accumulators
+        std::vector<std::vector<dd>> lead(nq);
+        for (size_t i = 0; i < nq; i++) {
+            const Reduced *r = rs[first + i];
+            lead[i].resize((size_t)EN(r->n, r->D));
+            if (!lead[i].empty())
+                HIP_TRY(hipMemcpyAsync(lead[i].data(), dmat + off[i], lead[i].size() * sizeof(dd),
+                                       hipMemcpyDeviceToHost, st));
+        }
+        std::vector<double> accs(3 * nq);
+        HIP_TRY(hipMemcpyAsync(accs.data(), dacc, accs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         ctx->stats.condition_launches += (int64_t)steps.size();
         for (size_t i = 0; i < nq; i++) {
             Reduced *r = rs[first + i];
-            const dd *pk = (const dd *)(stage.data() + off[i] * sizeof(dd));
-            const double *acc = (const double *)(stage.data() + acc_off + i * 3 * sizeof(double));
+            const dd *pk = lead[i].data();
+            const double *acc = accs.data() + 3 * i;
             r->pvac = dd_make(acc[0], acc[1]);
             r->log_pvac = acc[2];
             r->cond = false;
+            r->st = nullptr;
+            std::vector<int>().swap(r->g);
             if (r->D) {  // keep the packed form: the leading block with its mean row
-                r->packed.assign(pk, pk + EN(r->n, 1));
+                r->packed.swap(lead[i]);
                 continue;
             }
             const int dc = 2 * r->n;
@@ -953,9 +1061,12 @@ tor_status reduce_pattern_jacobi(const tor_state *st, const int8_t *pattern, Red
 // double-double terms.
 tor_status reduce_for_state(const tor_state *st, const int8_t *pattern, Reduced &out) {
     if (!pattern) return fail(TOR_EINVAL, "pattern is NULL");
-    if (!st->mean.empty()) return reduce_pattern_disp(st->cov.data(), st->mean.data(), st->m, pattern, out);
-    if (st->inv_prec && is_full_pattern(pattern, st->m)) return reduce_pattern_jacobi(st, pattern, out);
-    return reduce_pattern(st->cov.data(), st->m, pattern, out);
+    tor_status s;
+    if (!st->mean.empty()) s = reduce_pattern_disp(st->cov.data(), st->mean.data(), st->m, pattern, out, true);
+    else if (st->inv_prec && is_full_pattern(pattern, st->m)) return reduce_pattern_jacobi(st, pattern, out);
+    else s = reduce_pattern(st->cov.data(), st->m, pattern, out, true);
+    if (s == TOR_OK && out.cond) out.st = st;  // gathered on the device from the state's copy
+    return s;
 }
 
 // A reduced pattern, conditioned if it had no-click modes, made ready for the GPU.
@@ -1681,19 +1792,12 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     const int used = use_dd ? TOR_PREC_DD : TOR_PREC_F64;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t hs = stream ? (hipStream_t)stream : ctx->stream;
-    tor_state *ms = const_cast<tor_state *>(st);  // the device copy is a cache of the state
+    tor_state *ms = const_cast<tor_state *>(st);  // the device copies are a cache of the state
     const int m = st->m;
     const size_t cov_bytes = 4 * (size_t)m * (size_t)m * sizeof(double);
-    if (!ms->dcov.p) {
-        if (ms->dcov.ensure(cov_bytes) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the state failed");
-        HIP_TRY(hipMemcpy(ms->dcov.p, st->cov.data(), cov_bytes, hipMemcpyHostToDevice));
-    }
+    tor_status ds = state_on_device(st);
+    if (ds) return ds;
     const int D = st->mean.empty() ? 0 : 1;
-    if (D && !ms->dmean.p) {
-        if (ms->dmean.ensure(st->mean.size() * sizeof(double)) != hipSuccess)
-            return fail(TOR_ENOMEM, "device copy of the mean failed");
-        HIP_TRY(hipMemcpy(ms->dmean.p, st->mean.data(), st->mean.size() * sizeof(double), hipMemcpyHostToDevice));
-    }
     // task sizes and the launches any pattern of this state can need
     AsyncPlan P{};
     P.nq = nq;
@@ -1704,6 +1808,7 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     // full patterns of an inverted (zero-mean) state: the inverse on the device
     if (st->inv_prec && !D) {
         const size_t ent = (size_t)E(m);
+        std::lock_guard<std::mutex> lk(ms->dev_mu);
         if (!ms->dinv.p) {
             std::vector<dd> h(ent);
             for (size_t e = 0; e < ent; e++) h[e] = st->inv_prec == TOR_PREC_QD ? qd_to_dd(st->inv_q[e]) : st->inv[e];
@@ -2401,7 +2506,7 @@ void server_worker(tor_server *S, int w) {
                 ServerReq &r = *S->reqs[t];
                 size_t b = sum_bytes(r.red.n, task_modes_for(ctx, S->opts.prec == TOR_PREC_DD, r.red.n), es,
                                      r.red.D) +
-                           r.red.packed.size() * sizeof(dd);
+                           cond_words(&r.red) * sizeof(dd);
                 if (!take.empty() && bytes + b > S->opts.mem_budget_bytes) break;
                 bytes += b;
                 take.push_back(t);
