@@ -115,7 +115,8 @@ def cpu_baseline(cov, pattern, n, seconds_target=15.0):
 KERNEL_SOURCES = ["paper_1810_00900_amd/csrc/dd.hpp", "paper_1810_00900_amd/csrc/qd.hpp",
                   "paper_1810_00900_amd/csrc/tor_tree.hpp", "paper_1810_00900_amd/csrc/tor_wave.hpp",
                   "paper_1810_00900_amd/csrc/tor_kernels.hip", "paper_1810_00900_amd/csrc/tor_kernels_disp.hip",
-                  "paper_1810_00900_amd/csrc/tor_kernels_qd.hip", "paper_1810_00900_amd/csrc/tor_kernels.h"]
+                  "paper_1810_00900_amd/csrc/tor_kernels_info.hip", "paper_1810_00900_amd/csrc/tor_kernels_qd.hip",
+                  "paper_1810_00900_amd/csrc/tor_kernels.h"]
 
 
 def measured_fp64(kernel, kernel_ms):
@@ -203,15 +204,15 @@ def per_n_rates(ctx, cov, prec, ns=(20, 24, 28, 32), full=False, mean=None):
     return out
 
 
-def full_pattern_inverse(ctx, cov, ns=(20, 28)):
+def full_pattern_inverse(ctx, cov, ns=(20, 28), mean=None):
     """Full patterns (the per_n_full_pattern queries) on a state inverted once
     (tor_state_invert): the time of the inversion per precision, then each
     query as a one-query tor_batch on that state (a gather of sigma_Q^-1 over
     the clicked modes and one subset tree, no per-query conditioning)."""
     import gbs_inputs as gi
     out = {}
-    for prec in ("dd", "qd"):
-        st = ctx.state(cov)
+    for prec in (("dd", "qd") if mean is None else ("dd",)):
+        st = ctx.state(cov, mean=mean)
         t = time.perf_counter()
         st.invert(prec)
         inv_ms = (time.perf_counter() - t) * 1e3
@@ -521,6 +522,8 @@ def main():
         out["per_n_qd_terms"] = per_n_rates(ctx, cov, "qd", ns=(20, 24, 28))
         out["per_n_full_pattern_qd"] = per_n_rates(ctx, cov, "qd", ns=(20, 28), full=True)
         out["full_pattern_inverse"] = full_pattern_inverse(ctx, cov)
+        out["full_pattern_inverse_displaced"] = full_pattern_inverse(
+            ctx, cov, mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
         out["per_n_displaced"] = per_n_rates(ctx, cov, args.prec, ns=(20, 24, 28),
                                              mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
         out["per_n_displaced_f64_terms"] = per_n_rates(ctx, cov, "f64", ns=(20, 24, 28),

@@ -199,7 +199,7 @@ void tor_state_destroy(tor_state *st);
 
 /* Per-state preprocessing for full patterns (every mode 1 or 0; Sec. II's
  * vacuum conditioning done once per state instead of once per query).
- * Forms K = sigma_Q^-1 of a zero-mean state on the GPU by one symmetric 2x2
+ * Forms K = sigma_Q^-1 of a state on the GPU by one symmetric 2x2
  * sweep per mode, with det(sigma_Q)^-1/2, in double-double words (prec
  * TOR_PREC_F64, TOR_PREC_DD or TOR_PREC_AUTO) or quad-double words
  * (TOR_PREC_QD), and keeps them with the state (E(m) = m(2m+1) words on the
@@ -214,8 +214,13 @@ void tor_state_destroy(tor_state *st);
  * are the same.  A double-double inverse serves binary64 and double-double
  * terms (quad-double queries of the state keep the per-query conditioning);
  * a quad-double inverse serves every precision.  Patterns with unobserved
- * modes (-1) keep the per-query conditioning.  Errors: TOR_EINVAL (NULL,
- * displaced state, bad prec), TOR_ETOOBIG (m > 2048), TOR_ENOMEM,
+ * modes (-1) keep the per-query conditioning.  A displaced state also keeps
+ * h = K mu and mu^T K mu (double-double); its full patterns are the
+ * information-form sums of [0, h_C; h_C, G] (each pivot's factor carries
+ * exp(+|w|^2/2)): p = (-1)^n det(sigma_Q)^-1/2 exp(-mu^T K mu / 2) T_h(G),
+ * binary64 or double-double terms, in tor_batch and the server (not in
+ * tor_batch_async; quad-double terms take zero-mean states only).  Errors:
+ * TOR_EINVAL (NULL, bad prec), TOR_ETOOBIG (m > 2048), TOR_ENOMEM,
  * TOR_ENOTPD (a non-positive pivot; a previous inverse is kept).  Not
  * thread-safe against other calls on the state (call it before submitting
  * queries of the state). */

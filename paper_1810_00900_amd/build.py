@@ -11,7 +11,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtorgbs.so")
-SOURCES = ["csrc/tor_api.hip", "csrc/tor_kernels.hip", "csrc/tor_kernels_disp.hip", "csrc/tor_kernels_qd.hip",
+SOURCES = ["csrc/tor_api.hip", "csrc/tor_kernels.hip", "csrc/tor_kernels_disp.hip", "csrc/tor_kernels_info.hip",
+           "csrc/tor_kernels_qd.hip",
            "csrc/gbs_sampler.hip", "csrc/tor_async.hip", "csrc/tor_invert.hip", "csrc/tor_gather.hip"]
 
 # -ffp-contract=off: the double-double error-free transformations must not be

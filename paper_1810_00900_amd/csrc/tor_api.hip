@@ -53,6 +53,7 @@ tor_status fail(tor_status s, const char *fmt, ...) {
 constexpr long long E(long long r) { return r * (2 * r + 1); }
 // entries of an r-mode packed matrix with D leading mean rows (D = 0 or 1)
 constexpr long long EN(long long r, int D) { return (2 * r + D) * (2 * r + D + 1) / 2; }
+constexpr int MR(int D) { return D != 0 ? 1 : 0; }  // mean rows of a tree kind (0, 1 or -1)
 inline long long pidx(long long a, long long b) { return a * (a + 1) / 2 + b; }
 
 struct DevBuf {
@@ -131,6 +132,11 @@ struct tor_state {
     std::vector<qd> inv_q;
     dd det_rsqrt = {1.0, 0.0};
     double log_det_sigq = 0.0;
+    // displaced states: h = sigma_Q^-1 mu (2m words), mu^T sigma_Q^-1 mu and
+    // det(sigma_Q)^-1/2 exp(-mu^T sigma_Q^-1 mu / 2)
+    std::vector<dd> inv_h;
+    dd mu_k_mu = {0.0, 0.0};
+    dd det_rsqrt_mean = {1.0, 0.0};
     DevBuf dinv;  // device copy of the inverse in double-double words for tor_batch_async (first use)
     std::mutex dev_mu;  // guards the creation of the device copies (dcov, dmean)
 };
@@ -405,7 +411,8 @@ double elapsed(hipEvent_t a, hipEvent_t b) {
 struct SumIn {
     const std::vector<dd> *packed = nullptr;
     int n = 0;
-    int D = 0;  // 1: displaced, the mean row first (EN(n, 1) entries)
+    int D = 0;  // 1: displaced, the mean row first (EN(n, 1) entries); -1: the same
+                // layout in the information form (sigma_Q^-1 mu first, exp(+|w|^2 / 2))
 };
 struct SumOut {
     dd T = {1.0, 0.0};
@@ -424,6 +431,7 @@ int task_modes_for(const tor_ctx *ctx, bool use_dd, int n) {
 
 size_t sum_bytes(int n, int J, size_t es, int D = 0) {
     if (n == 0) return 0;
+    D = MR(D);  // mean rows
     J = std::min(n, J);
     const int G = n - J;
     unsigned long long total = (unsigned long long)EN(n, D);
@@ -442,7 +450,7 @@ size_t sum_bytes(int n, int J, size_t es, int D = 0) {
 tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vector<int> &idx, bool use_dd,
                      std::vector<SumOut> &out) {
     const size_t es = use_dd ? sizeof(dd) : sizeof(double);
-    const int D = idx.empty() ? 0 : in[idx[0]].D;
+    const int D = idx.empty() ? 0 : in[idx[0]].D, o = MR(D);  // tree kind, mean rows
     struct Plan {
         int q, n, J, G;
         long long nt;
@@ -462,7 +470,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
         p.G = p.n - p.J;
         p.nt = 1LL << p.G;
         p.root_off = roots;
-        roots += (unsigned long long)EN(p.n, D);
+        roots += (unsigned long long)EN(p.n, o);
         p.desc_off = desc_total;
         desc_total += p.nt;
         Gmax = std::max(Gmax, p.G);
@@ -474,7 +482,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
         p.child_base.resize(p.G);
         for (int d = 0; d < p.G; d++) {
             p.child_base[d] = pool_total;
-            pool_total += (1ULL << d) * (unsigned long long)EN(p.n - d - 1, D);
+            pool_total += (1ULL << d) * (unsigned long long)EN(p.n - d - 1, o);
         }
     }
     // reduction stages: stage outputs laid out one after another in partB
@@ -560,7 +568,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
         for (size_t i = 0; i < P.size(); i++) {
             const Plan &p = P[i];
             if (p.G <= d) continue;
-            ExpandJob job{level_ptr(p, i, d), level_ptr(p, i, d + 1), p.child_base[d], p.n - d, D};
+            ExpandJob job{level_ptr(p, i, d), level_ptr(p, i, d + 1), p.child_base[d], p.n - d, o};
             std::memcpy(hj + off_exp + ej * sizeof(ExpandJob), &job, sizeof job);
             ej++;
         }
@@ -612,7 +620,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
     if (stage.size() < roots * es) stage.resize(roots * es);
     for (auto &p : P) {
         const std::vector<dd> &pk = *in[p.q].packed;
-        for (long long e = 0; e < EN(p.n, D); e++) {
+        for (long long e = 0; e < EN(p.n, o); e++) {
             if (use_dd) ((dd *)stage.data())[p.root_off + e] = pk[(size_t)e];
             else ((double *)stage.data())[p.root_off + e] = pk[(size_t)e].hi + pk[(size_t)e].lo;
         }
@@ -669,11 +677,14 @@ tor_status gpu_sums(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vecto
     const size_t es = use_dd ? sizeof(dd) : sizeof(double);
     bool mixed = false;
     for (int q : which) mixed |= in[q].D != in[which[0]].D;
-    if (mixed) {  // zero-mean and displaced trees go to separate groups
-        std::vector<int> w0, w1;
-        for (int q : which) (in[q].D ? w1 : w0).push_back(q);
-        tor_status s = gpu_sums(ctx, in, w0, use_dd, out);
-        return s ? s : gpu_sums(ctx, in, w1, use_dd, out);
+    if (mixed) {  // zero-mean, displaced and information-form trees go to separate groups
+        std::vector<int> w[3];
+        for (int q : which) w[in[q].D + 1].push_back(q);
+        for (int k = 0; k < 3; k++) {
+            tor_status s = gpu_sums(ctx, in, w[k], use_dd, out);
+            if (s) return s;
+        }
+        return TOR_OK;
     }
     std::vector<int> group;
     size_t bytes = 0;
@@ -1019,7 +1030,10 @@ bool is_full_pattern(const int8_t *pattern, int m) {
 // T(Sigma_C) = (-1)^n det(G)^1/2 T(G), and P_vac(N) = (det sigma_Q det G)^-1/2.
 // G is gathered in double-double (the quad-double inverse rounded when the
 // state holds that one); det(G)^(+-1/2) from its double-double Cholesky.
+tor_status reduce_pattern_jacobi_disp(const tor_state *st, const int8_t *pattern, Reduced &out);
+
 tor_status reduce_pattern_jacobi(const tor_state *st, const int8_t *pattern, Reduced &out) {
+    if (!st->mean.empty()) return reduce_pattern_jacobi_disp(st, pattern, out);
     std::vector<int> C;
     for (int i = 0; i < st->m; i++)
         if (pattern[i] == 1) C.push_back(i);
@@ -1055,15 +1069,77 @@ tor_status reduce_pattern_jacobi(const tor_state *st, const int8_t *pattern, Red
     return TOR_OK;
 }
 
+// A full pattern of an inverted displaced state.  With h = K mu, the vacuum
+// probability of S = Y + N (complement Z = C \ Y) is
+//   det(sigma_Q)^-1/2 exp(-mu^T K mu / 2) det(G[Z])^-1/2 exp(+h_Z^T G[Z]^-1 h_Z / 2)
+// (mu_S^T sigma_Q[S]^-1 mu_S = mu^T K mu - h_Z^T K[Z]^-1 h_Z), so p is
+// (-1)^n det(sigma_Q)^-1/2 exp(-mu^T K mu / 2) times the information-form
+// subset sum of [0, h_C; h_C, G] (tree kind -1).  The reported sum of Sigma_C
+// with its conditioned mean is that sum times (-1)^n det(G)^1/2
+// exp(-h_C^T G^-1 h_C / 2), and P_vac(N) = det(sigma_Q)^-1/2 det(G)^-1/2
+// exp(-mu^T K mu / 2) exp(+h_C^T G^-1 h_C / 2); h_C^T G^-1 h_C from the
+// double-double Cholesky of G.
+tor_status reduce_pattern_jacobi_disp(const tor_state *st, const int8_t *pattern, Reduced &out) {
+    std::vector<int> C;
+    for (int i = 0; i < st->m; i++)
+        if (pattern[i] == 1) C.push_back(i);
+    const int n = (int)C.size();
+    if (n > TOR_MAX_CLICKS) return fail(TOR_ETOOBIG, "%d clicks > %d", n, TOR_MAX_CLICKS);
+    out = Reduced();
+    out.n = n;
+    out.k = st->m - n;
+    out.D = 1;
+    out.jacobi = true;
+    const int dc = 2 * n;
+    std::vector<int> g(dc);
+    for (int a = 0; a < dc; a++) g[a] = 2 * C[a / 2] + (a & 1);
+    out.packed.assign((size_t)EN(n, 1), dd_from(0.0));
+    std::vector<dd> G((size_t)dc * dc);
+    for (int a = 0; a < dc; a++) {
+        out.packed[(size_t)pidx(a + 1, 0)] = st->inv_h[g[a]];
+        for (int b = 0; b <= a; b++) {
+            const size_t e = (size_t)pidx(g[a], g[b]);
+            const dd v = st->inv_prec == TOR_PREC_QD ? qd_to_dd(st->inv_q[e]) : st->inv[e];
+            out.packed[(size_t)pidx(a + 1, b + 1)] = v;
+            G[(size_t)a * dc + b] = v;
+            G[(size_t)b * dc + a] = v;
+        }
+    }
+    dd root = dd_from(1.0), rroot = dd_from(1.0), q = dd_from(0.0);  // det(G)^(+-1/2), h_C^T G^-1 h_C
+    double log_det_g = 0.0;
+    if (n > 0) {
+        std::vector<dd> rinv;
+        if (!dd_cholesky(G, dc, rinv, &log_det_g))
+            return fail(TOR_ENOTPD, "sigma_Q^-1 over C is not positive definite");
+        std::vector<dd> z(dc);
+        for (int a = 0; a < dc; a++) {
+            root = dd_mul(root, G[(size_t)a * dc + a]);
+            rroot = dd_mul(rroot, rinv[a]);
+            dd v = st->inv_h[g[a]];
+            for (int t = 0; t < a; t++) v = dd_sub(v, dd_mul(G[(size_t)a * dc + t], z[t]));
+            z[a] = dd_mul(v, rinv[a]);
+            q = dd_add(q, dd_mul(z[a], z[a]));
+        }
+    }
+    const dd half_q = dd_make(0.5 * q.hi, 0.5 * q.lo);
+    out.pvac = dd_mul(dd_mul(st->det_rsqrt_mean, rroot), dd_exp(half_q));
+    out.log_pvac = -0.5 * (st->log_det_sigq + log_det_g) - 0.5 * (st->mu_k_mu.hi + st->mu_k_mu.lo) +
+                   (half_q.hi + half_q.lo);
+    const dd ts = dd_mul(root, dd_exp(dd_neg(half_q)));
+    out.tscale = (n & 1) ? dd_neg(ts) : ts;
+    out.pdirect = (n & 1) ? dd_neg(st->det_rsqrt_mean) : st->det_rsqrt_mean;
+    return TOR_OK;
+}
+
 // A pattern of a state (zero-mean or displaced) reduced for the subset tree.
 // Full patterns on an inverted zero-mean state take the complementary-minor
 // route (no conditioning); the quad-double inverse also serves binary64 and
 // double-double terms.
 tor_status reduce_for_state(const tor_state *st, const int8_t *pattern, Reduced &out) {
     if (!pattern) return fail(TOR_EINVAL, "pattern is NULL");
+    if (st->inv_prec && is_full_pattern(pattern, st->m)) return reduce_pattern_jacobi(st, pattern, out);
     tor_status s;
     if (!st->mean.empty()) s = reduce_pattern_disp(st->cov.data(), st->mean.data(), st->m, pattern, out, true);
-    else if (st->inv_prec && is_full_pattern(pattern, st->m)) return reduce_pattern_jacobi(st, pattern, out);
     else s = reduce_pattern(st->cov.data(), st->m, pattern, out, true);
     if (s == TOR_OK && out.cond) out.st = st;  // gathered on the device from the state's copy
     return s;
@@ -1071,7 +1147,17 @@ tor_status reduce_for_state(const tor_state *st, const int8_t *pattern, Reduced 
 
 // A reduced pattern, conditioned if it had no-click modes, made ready for the GPU.
 tor_status prepare_reduced(Reduced &r, Prepared &p) {
-    if (r.D) return prepare_disp(std::move(r.packed), r.n, r.pvac, r.log_pvac, p);
+    if (r.D) {
+        tor_status s = prepare_disp(std::move(r.packed), r.n, r.pvac, r.log_pvac, p);
+        if (s == TOR_OK && r.jacobi) {  // [0, h_C; h_C, G]: the information-form tree
+            p.D = -1;                   // quad = h_C^T G^-1 h_C bounds its exponents
+            p.log_det = -p.log_det;
+            p.scaled = true;
+            p.tscale = r.tscale;
+            p.pdirect = r.pdirect;
+        }
+        return s;
+    }
     tor_status s = prepare(r.sig, r.n, r.pvac, r.log_pvac, p);
     if (s == TOR_OK && r.jacobi) {  // prepare saw G: log det Sigma_C = -log det G
         p.log_det = -p.log_det;
@@ -1624,8 +1710,6 @@ void tor_state_destroy(tor_state *st) {
 
 tor_status tor_state_invert(tor_state *st, tor_prec prec) {
     if (!st) return fail(TOR_EINVAL, "state is NULL");
-    if (!st->mean.empty())
-        return fail(TOR_EINVAL, "tor_state_invert takes zero-mean states (a displaced state conditions per query)");
     if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD && prec != TOR_PREC_QD)
         return fail(TOR_EINVAL, "precision %d is not a tor_prec", (int)prec);
     const int m = st->m;
@@ -1684,6 +1768,24 @@ tor_status tor_state_invert(tor_state *st, tor_prec prec) {
     }
     st->det_rsqrt = dd_make(acc[0], acc[1]);
     st->log_det_sigq = -2.0 * acc[2];
+    std::vector<dd>().swap(st->inv_h);
+    st->mu_k_mu = dd_from(0.0);
+    st->det_rsqrt_mean = st->det_rsqrt;
+    if (!st->mean.empty()) {  // h = K mu and mu^T K mu in double-double
+        st->inv_h.assign(d, dd_from(0.0));
+        for (int a = 0; a < d; a++) {
+            dd s = dd_from(0.0);
+            for (int b = 0; b < d; b++) {
+                const size_t e = (size_t)(a >= b ? pidx(a, b) : pidx(b, a));
+                const dd kab = q ? qd_to_dd(st->inv_q[e]) : st->inv[e];
+                s = dd_add(s, dd_mul_d(kab, st->mean[b]));
+            }
+            st->inv_h[a] = s;
+            st->mu_k_mu = dd_add(st->mu_k_mu, dd_mul_d(s, st->mean[a]));
+        }
+        const dd hm = dd_make(-0.5 * st->mu_k_mu.hi, -0.5 * st->mu_k_mu.lo);
+        st->det_rsqrt_mean = dd_mul(st->det_rsqrt, dd_exp(hm));
+    }
     st->inv_prec = q ? TOR_PREC_QD : TOR_PREC_DD;
     return TOR_OK;
 }

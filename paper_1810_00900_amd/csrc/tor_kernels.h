@@ -131,10 +131,14 @@ hipError_t tor_launch_async_finalize(const AsyncPlan &P, double tol, int prec_us
 // Launchers.  With dyn != nullptr (a plan made on the device) the kernels read
 // the job count and total work from dyn, and the host-side grid argument
 // (grid_cap, total_blocks) is the grid itself, a bound on the work.
-// disp = 1: displaced state (every packed matrix has the mean row first).
+// disp = 1: displaced state (every packed matrix has the mean row first);
+// disp = -1: the information form of a displaced state's full patterns.
 hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
                            int grid_cap, hipStream_t st, const LaunchDims *dyn = nullptr, int disp = 0);
 hipError_t tor_launch_wave_disp(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
+                                int grid_cap, hipStream_t st, const LaunchDims *dyn);
+// disp = -1: the information form (first row sigma_Q^-1 mu, pivots carry exp(+|w|^2 / 2))
+hipError_t tor_launch_wave_info(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
                                 int grid_cap, hipStream_t st, const LaunchDims *dyn);
 hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
                              hipStream_t st, const LaunchDims *dyn = nullptr, int disp = 0);

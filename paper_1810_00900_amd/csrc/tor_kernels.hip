@@ -52,19 +52,20 @@ namespace tor {
 // One wave per parent node (four per 256-thread workgroup): the include child
 // (rank-2 Schur update of the last mode) goes to the pool, the exclude child
 // keeps the parent's offset.  Waves run independently (no workgroup barrier).
-// D = 1: displaced state (mean row first in every packed matrix).
+// D = 1: displaced state (mean row first in every packed matrix); D = -1: the
+// information form (the first row holds sigma_Q^-1 mu; see make_pivot_m).
 template <class S, int D>
 __global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict__ jobs, int log2npar,
                                                      long long total, S *__restrict__ pool,
                                                      const LaunchDims *__restrict__ dyn) {
     if (dyn) total = dyn->njobs << log2npar;
-    __shared__ S vs[4][2][2 * TOR_MAX_N + D];
+    __shared__ S vs[4][2][2 * TOR_MAX_N + MR(D)];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     S *v0 = vs[w][0], *v1 = vs[w][1];
     for (long long f = (long long)blockIdx.x * 4 + w; f < total; f += (long long)gridDim.x * 4) {
         const ExpandJob job = jobs[f >> log2npar];
         const long long i = f & ((1LL << log2npar) - 1);
-        const int r = job.r, R = 2 * r + D, RC = R - 2, EC = EN(r - 1, D);
+        const int r = job.r, R = 2 * r + MR(D), RC = R - 2, EC = EN(r - 1, MR(D));
         NodeDesc d = job.par[i];
         const S *base = pool + d.off;
         Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
@@ -207,6 +208,7 @@ __global__ void gather_kernel(const Partial *const *__restrict__ src, int n, Par
 
 hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, long long total, const void *pool,
                            int grid_cap, hipStream_t st, const LaunchDims *dyn, int disp) {
+    if (disp < 0) return tor_launch_wave_info(is_dd, J, jobs, njobs, total, pool, grid_cap, st, dyn);
     if (disp) return tor_launch_wave_disp(is_dd, J, jobs, njobs, total, pool, grid_cap, st, dyn);
     return is_dd ? tor::launch_wave_S<dd, 0>(J, jobs, njobs, total, pool, grid_cap, st, dyn)
                  : tor::launch_wave_S<double, 0>(J, jobs, njobs, total, pool, grid_cap, st, dyn);
@@ -219,7 +221,13 @@ hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int lo
     long long g = dyn ? grid_cap : (blocks < grid_cap ? blocks : grid_cap);
     if (g < 1) return hipSuccess;
     (void)hipGetLastError();  // report only this launch's error
-    if (is_dd && disp)
+    if (is_dd && disp < 0)
+        hipLaunchKernelGGL((tor::expand_kernel<dd, -1>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
+                           (dd *)pool, dyn);
+    else if (!is_dd && disp < 0)
+        hipLaunchKernelGGL((tor::expand_kernel<double, -1>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar,
+                           total, (double *)pool, dyn);
+    else if (is_dd && disp)
         hipLaunchKernelGGL((tor::expand_kernel<dd, 1>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
                            (dd *)pool, dyn);
     else if (is_dd)

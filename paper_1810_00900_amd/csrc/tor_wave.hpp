@@ -1,7 +1,9 @@
 // Wave-tier kernels of the subset tree (the LDS and register tiers), templated
 // on the scalar S (binary64 or double-double), the task size J (modes per
-// workgroup task) and the mean-row offset D (0: zero-mean state; 1: displaced
-// state, the packed matrix carries the mean vector as its first row).  Each
+// workgroup task) and the mean-row mode D (0: zero-mean state; 1: displaced
+// state, the packed matrix carries the mean vector as its first row; -1: the
+// information form, the first row holds sigma_Q^-1 mu and the pivots carry
+// exp(+|w|^2 / 2)).  Each
 // translation unit that includes this header instantiates the launchers it
 // needs, so the zero-mean and displaced kernels compile in parallel.
 #pragma once
@@ -19,10 +21,10 @@ namespace tor {
 // Waves per SIMD the wave tier asks the register allocator for: two where two
 // workgroups' LDS fit a quarter of the CU's 160 KiB (one wave per workgroup),
 // so that a second wave can hide the first one's latency; else one.  The
-// displaced double-double leaf (one more packed row per node) does not fit
-// the 256 registers of two waves without spilling, so it asks for one.
+// double-double leaf with a mean row (one more packed row per node) does not
+// fit the 256 registers of two waves without spilling, so it asks for one.
 template <class S, int J, int D> struct WaveOcc {
-    static constexpr int value = (D == 1 && sizeof(S) > sizeof(double)) ? 1
+    static constexpr int value = (D != 0 && sizeof(S) > sizeof(double)) ? 1
                                  : sizeof(WaveSmem<S, J, D>) + 512 <= 20480 ? 2 : 1;
 };
 
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, J
         const long long lt = t - jobs[j].begin;
         NodeDesc d = jobs[j].tasks[lt];
         const S *root = pool + d.off;
-        for (int e = lane; e < EN(J, D); e += 64) sm.mat[e] = root[e];
+        for (int e = lane; e < EN(J, MR(D)); e += 64) sm.mat[e] = root[e];
         dd T;
         double A;
         wave_tree<S, J, D>(sm, dd_make(d.coef_hi, d.coef_lo), d.acoef, lane, T, A);
@@ -75,7 +77,7 @@ template <class S, int D, int NT> struct TopSmem {  // NT = J - 9 set-aside colu
 // pivot of the last mode of the r-mode node m[] and its two scaled columns
 template <class S, int r, int D>
 __device__ __forceinline__ Pivot<S> top_columns(const S *m, S *v, int lane) {
-    constexpr int R = 2 * r + D, RC = R - 2;
+    constexpr int R = 2 * r + MR(D), RC = R - 2;
     // every lane forms the pivot (same value everywhere, no LDS round trip)
     const Pivot<S> pv = make_pivot_m<S, D>(m, R - 2, R - 1);
     for (int c = lane; c < RC; c += 64) {
@@ -86,18 +88,18 @@ __device__ __forceinline__ Pivot<S> top_columns(const S *m, S *v, int lane) {
     return pv;
 }
 
-// dst[e] = src[e] - v1(a) v1(b) - v2(a) v2(b) for the (r-1)-mode child, e < EN(r-1, D)
+// dst[e] = src[e] - v1(a) v1(b) - v2(a) v2(b) for the (r-1)-mode child, e < EN(r-1, MR(D))
 template <class S, int r, int D>
 __device__ __forceinline__ void top_update(const S *src, S *dst, const S *v, int lane) {
-    constexpr int RC = 2 * r - 2 + D;
-    for (int e = lane; e < EN(r - 1, D); e += 64) {
+    constexpr int RC = 2 * r - 2 + MR(D);
+    for (int e = lane; e < EN(r - 1, MR(D)); e += 64) {
         int a, b;
         unpack(e, a, b);
         dst[e] = sub_dot2(src[e], v[a], v[b], v[RC + a], v[RC + b]);
     }
 }
 
-// the 10-mode node in sm.w.mat[0 .. EN(10, D)); adds this lane's share to (T, A)
+// the 10-mode node in sm.w.mat[0 .. EN(10, MR(D))); adds this lane's share to (T, A)
 template <class S, int D, int NT>
 __device__ __forceinline__ void top10(TopSmem<S, D, NT> &sm, dd c, double a, int lane, dd &T, double &A) {
     S *v = sm.vtop[0];
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9
     const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool,
     const LaunchDims *__restrict__ dyn) {
     static_assert(J == 10 || J == 11, "top levels: one or two");
-    static_assert(WaveCfg<S, 9, D>::MAT >= EN(J, D), "the task's matrix must fit the nine-mode working set");
+    static_assert(WaveCfg<S, 9, D>::MAT >= EN(J, MR(D)), "the task's matrix must fit the nine-mode working set");
     __shared__ TopSmem<S, D, J - 9> sm;
     const int lane = threadIdx.x;
     if (dyn) {
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9
         const long long lt = t - jobs[j].begin;
         NodeDesc d = jobs[j].tasks[lt];
         const S *root = pool + d.off;
-        for (int e = lane; e < EN(J, D); e += 64) sm.w.mat[e] = root[e];
+        for (int e = lane; e < EN(J, MR(D)); e += 64) sm.w.mat[e] = root[e];
         wave_sync();
         const dd c0 = dd_make(d.coef_hi, d.coef_lo);
         dd T = dd_from(0.0);

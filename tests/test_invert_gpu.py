@@ -209,12 +209,78 @@ def test_async_full_patterns(ctx, inv_prec, prec):
     st.close()
 
 
+def _coherent(beta, pat):
+    import mpmath as mp
+    mp.mp.dps = 60
+    want = mp.mpf(1)
+    for i, v in enumerate(pat):
+        a2 = mp.mpf(float(beta[i].real)) ** 2 + mp.mpf(float(beta[i].imag)) ** 2
+        want *= (1 - mp.exp(-a2)) if v == 1 else mp.exp(-a2) if v == 0 else 1
+    return want
+
+
+@pytest.mark.parametrize("prec", ["dd", "f64"])
+def test_displaced_full_patterns_inverse(ctx, prec):
+    """Full patterns of an inverted displaced state: the information-form tree
+    over [0, h_C; h_C, G] with h = sigma_Q^-1 mu, against the oracle's
+    definition route with mean factors and against the per-query conditioning
+    of the displaced state."""
+    m = 16
+    cov, _, rng = _state(m, 157, 0.3, 0.7)
+    mean = gi.random_mean(m, rng, 0.4)
+    plain = ctx.state(cov, mean=mean)
+    inv = ctx.state(cov, mean=mean).invert("dd")
+    pats = np.stack([np.zeros(m, np.int8)] + [gi.full_pattern(m, gi.random_click_set(m, n, rng))
+                                              for n in (1, 3, 6, 9)])
+    got, _ = ctx.batch(inv, pats, prec=prec)
+    cond, _ = ctx.batch(plain, pats, prec=prec)
+    for pat, g, c in zip(pats, got, cond):
+        o = oracle.formP_mean(cov, mean, pat)
+        err = _rel(_mp(g), _orc(o))
+        assert err <= g.rel_err_bound + 1e-27, (int(pat.sum()), err, g.rel_err_bound)
+        if prec == "dd":
+            assert err <= 1e-10
+        both = g.rel_err_bound + c.rel_err_bound
+        assert _rel(_mp(g), _mp(c)) <= both + 1e-27
+        assert _rel(g.T, c.T) <= both + 1e-13  # T of Sigma_C with its conditioned mean
+        assert abs(g.log_p - c.log_p) <= both + 1e-12 * abs(c.log_p)
+        assert abs(g.log_pvac_n - c.log_pvac_n) <= 1e-11 * max(1.0, abs(c.log_pvac_n))
+    # the server and a second batch give the same words
+    srv = tg.Server(ctx, workers=2, prec=prec)
+    tickets = [srv.submit(inv, p) for p in pats]
+    for t, g in zip(tickets, got):
+        r, _lat = srv.wait(t)
+        assert (r.p, r.p_lo, r.T, r.T_lo) == (g.p, g.p_lo, g.T, g.T_lo)
+    srv.stop()
+    plain.close()
+    inv.close()
+
+
+def test_displaced_inverse_coherent_closed_form(ctx):
+    """Coherent states through an interferometer (beta = U alpha) on an
+    inverted state, all 40 modes observed: prod_clicks (1 - e^{-|beta|^2})
+    prod_no_clicks e^{-|beta|^2}."""
+    m, n = 40, 12
+    rng = np.random.default_rng(158)
+    clicks = sorted(rng.choice(m, n, replace=False).tolist())
+    beta = 0.3 * (rng.standard_normal(m) + 1j * rng.standard_normal(m))
+    beta[clicks] = np.sqrt(rng.uniform(0.7, 3.0, n)) * np.exp(2j * np.pi * rng.random(n))
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), np.zeros(m))
+    st = ctx.state(cov, mean=gi.coherent_mean(beta)).invert("dd")
+    pats = np.stack([gi.full_pattern(m, clicks), gi.full_pattern(m, clicks[:5]), np.zeros(m, np.int8)])
+    res, _ = ctx.batch(st, pats, prec="dd")
+    for pat, r in zip(pats, res):
+        assert _rel(_mp(r), _coherent(beta, pat)) <= 1e-12, (int(pat.sum()), r.rel_err_bound)
+        assert r.status == tg.TOR_OK
+    st.close()
+
+
 def test_invert_errors(ctx):
     m = 6
     cov, _, rng = _state(m, 155)
-    disp = ctx.state(cov, mean=gi.random_mean(m, rng, 0.3))
-    with pytest.raises(tg.TorError) as e:
-        disp.invert("dd")
+    disp = ctx.state(cov, mean=gi.random_mean(m, rng, 0.3)).invert("qd")  # displaced: allowed
+    with pytest.raises(tg.TorError) as e:  # quad-double terms still take zero-mean states only
+        ctx.batch(disp, gi.full_pattern(m, [1])[None, :], prec="qd")
     assert e.value.status == tg.TOR_EINVAL
     disp.close()
     bad = ctx.state(-np.eye(2 * m))  # sigma_Q = -I/2: not positive definite
