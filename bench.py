@@ -233,6 +233,38 @@ def full_pattern_inverse(ctx, cov, ns=(20, 28), mean=None):
     return out
 
 
+def serving_full_patterns(ctx, nq=2000, workers=2):
+    """Full patterns (every mode observed, n ~ U{8..20} clicks) of one 800-mode
+    state served closed-loop, once on the inverted state (a gather of
+    sigma_Q^-1 per query) and once with per-query conditioning (780-792
+    in-place steps per query, batched by the server)."""
+    import numpy as np
+
+    import gbs_inputs as gi
+    import paper_1810_00900_amd as tg
+    cov = gi.state_m800(30)
+    rng = np.random.default_rng(36)
+    pats = [gi.full_pattern(800, gi.random_click_set(800, int(n), rng)) for n in rng.integers(8, 21, nq)]
+    out = {"workload": f"{nq} full patterns, n ~ U{{8..20}}, state m=800 (seed 30), queries seed 36, dd terms"}
+    for label, inverted in (("inverted_state", True), ("per_query_conditioning", False)):
+        st = ctx.state(cov)
+        t = time.perf_counter()
+        if inverted:
+            st.invert("dd")
+        prep = time.perf_counter() - t
+        srv = tg.Server(ctx, workers=workers, prec="dd", tol=1e-10, max_batch=4096)
+        t0 = time.perf_counter()
+        tickets = [srv.submit(st, p) for p in pats]
+        res = [srv.wait(tk) for tk in tickets]
+        T = time.perf_counter() - t0
+        srv.stop()
+        st.close()
+        lat = np.array([x[1] for x in res])
+        out[label] = {"queries_per_s": nq / T, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                      "p99_ms": float(np.percentile(lat, 99) * 1e3), "state_prep_ms": prep * 1e3}
+    return out
+
+
 def paper_worst_case(ctx, sizes=((10, 200), (12, 288), (14, 392), (16, 512), (18, 648), (20, 800)), prec="dd"):
     """The paper's runtime study, worst case (Sec. III): one sample with fixed
     outcomes, l = 2 m^2 modes, 8 dB squeezing on every mode, Haar
@@ -534,6 +566,7 @@ def main():
         out["paper_worst_case_qd"] = paper_worst_case(ctx, sizes=((16, 512), (18, 648), (20, 800)), prec="qd")
         out["dense_subgraph"] = dense_subgraph(ctx)
         out["serving"] = serving_bench(ctx)
+        out["serving_full_patterns"] = serving_full_patterns(ctx)
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cov, pattern, n)

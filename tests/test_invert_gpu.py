@@ -275,6 +275,57 @@ def test_displaced_inverse_coherent_closed_form(ctx):
     st.close()
 
 
+def _product_state(r):
+    d = np.empty(2 * len(r))
+    d[0::2] = np.exp(-2 * r) / 2
+    d[1::2] = np.exp(2 * r) / 2
+    return np.diag(d), d
+
+
+def _product_closed_form(d, pat):
+    import mpmath as mp
+    mp.mp.dps = 60
+    want = mp.mpf(1)
+    half = mp.mpf(1) / 2
+    for k, v in enumerate(pat):
+        p0 = 1 / mp.sqrt((mp.mpf(d[2 * k]) + half) * (mp.mpf(d[2 * k + 1]) + half))
+        want *= (1 - p0) if v == 1 else p0 if v == 0 else 1
+    return want
+
+
+def test_single_mode_and_largest_state(ctx):
+    """m = 1, and m = 2048 (the largest inverse; twice the observed modes the
+    per-query conditioning takes): squeezed product states, whose full
+    patterns factorise into sech r_k and 1 - sech r_k per mode."""
+    cov1, d1 = _product_state(np.array([0.5]))
+    st = ctx.state(cov1).invert("dd")
+    res, _ = ctx.batch(st, np.array([[0], [1]], np.int8), prec="dd")
+    for pat, r in zip(([0], [1]), res):
+        assert _rel(_mp(r), _product_closed_form(d1, pat)) <= 1e-30
+    st.close()
+    m = 2048
+    rng = np.random.default_rng(159)
+    cov, d = _product_state(rng.uniform(0.2, 0.8, m))
+    st = ctx.state(cov).invert("dd")
+    pats = np.stack([gi.full_pattern(m, gi.random_click_set(m, n, rng)) for n in (0, 5, 12)])
+    res, _ = ctx.batch(st, pats, prec="dd")
+    for pat, r in zip(pats, res):
+        # a product state cancels by prod (1 + sech r)/(1 - sech r): R ~ 1e15 at 12 clicks
+        err = _rel(_mp(r), _product_closed_form(d, pat))
+        assert err <= r.rel_err_bound + 1e-28 and err <= 1e-20, (int(pat.sum()), err, r.rel_err_bound)
+    plain = ctx.state(cov)  # per-query conditioning: more than 1024 observed modes
+    with pytest.raises(tg.TorError) as e:
+        ctx.batch(plain, pats[1:2], prec="dd")
+    assert e.value.status == tg.TOR_ETOOBIG
+    plain.close()
+    st.close()
+    big = ctx.state(0.5 * np.eye(2 * (m + 1)))
+    with pytest.raises(tg.TorError) as e:
+        big.invert("dd")
+    assert e.value.status == tg.TOR_ETOOBIG
+    big.close()
+
+
 def test_invert_errors(ctx):
     m = 6
     cov, _, rng = _state(m, 155)
