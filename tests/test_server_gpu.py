@@ -106,3 +106,38 @@ def test_poll_and_errors(ctx, setup):
         with pytest.raises(tg.TorError) as e:
             srv.submit(states[0], bad)
         assert e.value.status == tg.TOR_EINVAL
+
+
+def test_concurrent_clients_conditioned_queries(ctx):
+    """Patterns with no-click modes from four client threads on fresh states
+    (plain and displaced): the workers gather each state's matrices on the
+    device from one device copy, created once under the state's lock, and
+    every result equals the query alone bitwise."""
+    rng = np.random.default_rng(180)
+    m = 60
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.3, 0.8, m))
+    mean = gi.random_mean(m, rng, 0.3)
+    states = [ctx.state(cov), ctx.state(cov, mean=mean)]
+    qs = []
+    for i in range(160):
+        s = i % 2
+        c = gi.random_click_set(m, int(rng.integers(0, 11)), rng)
+        p = gi.full_pattern(m, c)
+        p[np.setdiff1d(np.arange(m), c)[: int(rng.integers(0, 20))]] = -1
+        qs.append((s, p))
+    tickets = [None] * len(qs)
+    with tg.Server(ctx, workers=3, prec="dd", tol=1e-10, max_batch=16) as srv:
+        def client(k):
+            for i in range(k, len(qs), 4):
+                tickets[i] = srv.submit(states[qs[i][0]], qs[i][1])
+        th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        got = [srv.wait(t)[0] for t in tickets]
+    for (s, p), g in zip(qs, got):
+        w = ctx.probability(cov, p, prec="dd") if s == 0 else ctx.probability_displaced(cov, mean, p, prec="dd")
+        assert (g.p, g.p_lo, g.T, g.T_lo, g.status) == (w.p, w.p_lo, w.T, w.T_lo, w.status)
+    for st in states:
+        st.close()
