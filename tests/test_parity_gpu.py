@@ -198,6 +198,25 @@ def test_m800_bench_configuration_against_quad_double(ctx, cov800):
     assert r.cancel_ratio == pytest.approx(q.cancel_ratio, rel=1e-6)
 
 
+def test_m800_largest_tree_against_quad_double(ctx, cov800):
+    """The largest tree the library takes (n = 32 clicks, 2^32 subsets; a
+    32-click marginal of the 800-mode state): double-double terms against the
+    quad-double tier, within the dd bound."""
+    import mpmath as mp
+    pat = gi.config5_pattern(32)
+    assert int((pat == 1).sum()) == 32
+    r = ctx.probability(cov800, pat, prec="dd")
+    big = tg.Context(0)  # the quad-double tree of 32 modes holds ~96 GB of HBM
+    big.set_option(tg.OPT_MEM_BUDGET, 160 << 30)
+    q = big.probability(cov800, pat, prec="qd")
+    big.close()
+    assert q.rel_err_bound <= 1e-30
+    err = _rel(_gpu_p(r), mp.mpf(q.p) + mp.mpf(q.p_lo))
+    print("n = 32: dd vs qd", err, "dd bound", r.rel_err_bound, "R", q.cancel_ratio)
+    assert err <= r.rel_err_bound, (err, r.rel_err_bound)
+    assert r.cancel_ratio == pytest.approx(q.cancel_ratio, rel=1e-4)
+
+
 def test_auto_escalates(ctx, cov800):
     """AUTO starts with binary64 terms and repeats in double-double when the
     bound exceeds tol."""
