@@ -205,6 +205,53 @@ DD_FN qd qd_rsqrt(qd x) {
     return qd_add(y, qd_mul_d(qd_mul(y, r), 0.5));
 }
 
+// exp(x) of a quad-double x (finite, x.x0 < 709).  Reduction x = k ln2 + r
+// with a four-word ln2 (|r| <= ln2 / 2), t = r / 1024.  expm1(t) = t P(t),
+// P(t) = sum_{j=0}^{16} t^j / (j+1)!, by Horner: the coefficients 1/13!..1/17!
+// in binary64 and 1/9!..1/12! in double-word (their terms sit below 2^-51 and
+// 2^-110 of the result, so those precisions suffice), 1/1!..1/8! in
+// quad-double; the next term, t^17/18!, is below 2^-220.  Ten doublings
+// e^{2t} - 1 = a (2 + a) keep a's relative precision; exp(x) = 2^k (1 + a).
+// The constants are the round-to-nearest four-word splits of ln2 and 1/j!.
+// Relative error within a few max(1, |x|) 2^-208 (the conditioning of exp on
+// a four-word argument) for results above 1e-290; 0 below exp(-745).
+DD_FN qd qd_exp(qd x) {
+    if (x.x0 < -745.0) return qd_from(0.0);
+    const qd ln2 = qd_make(0x1.62e42fefa39efp-1, 0x1.abc9e3b39803fp-56, 0x1.7b57a079a1934p-111,
+                           -0x1.ace93a4ebe5d1p-165);
+    const double k = rint(x.x0 / ln2.x0);
+    qd t = qd_sub(x, qd_mul_d(ln2, k));
+    t = qd_make(ldexp(t.x0, -10), ldexp(t.x1, -10), ldexp(t.x2, -10), ldexp(t.x3, -10));
+    double p = 0x1.952c77030ad4ap-49;         // 1/17!
+    p = fma(p, t.x0, 0x1.ae7f3e733b81fp-45);  // 1/16!
+    p = fma(p, t.x0, 0x1.ae7f3e733b81fp-41);  // 1/15!
+    p = fma(p, t.x0, 0x1.93974a8c07c9dp-37);  // 1/14!
+    p = fma(p, t.x0, 0x1.6124613a86d09p-33);  // 1/13!
+    const dd td = dd_make(t.x0, t.x1);
+    const double dh[4] = {0x1.1eed8eff8d898p-29, 0x1.ae64567f544e4p-26, 0x1.27e4fb7789f5cp-22,
+                          0x1.71de3a556c734p-19};  // 1/12!, 1/11!, 1/10!, 1/9!
+    const double dl[4] = {-0x1.2aec959e14c06p-83, -0x1.c062e06d1f209p-80, 0x1.cbbc05b4fa99ap-76,
+                          -0x1.c154f8ddc6c00p-73};
+    dd sd = dd_from(p);
+    for (int j = 0; j < 4; ++j) sd = dd_add_small(dd_make(dh[j], dl[j]), dd_mul(td, sd));
+    const double c[8][4] = {  // 1/8!, 1/7!, ..., 1/1!
+        {0x1.a01a01a01a01ap-16, 0x1.a01a01a01a01ap-76, 0x1.a01a01a01a01ap-136, 0x1.a01a01a01a01ap-196},
+        {0x1.a01a01a01a01ap-13, 0x1.a01a01a01a01ap-73, 0x1.a01a01a01a01ap-133, 0x1.a01a01a01a01ap-193},
+        {0x1.6c16c16c16c17p-10, -0x1.f49f49f49f49fp-65, -0x1.27d27d27d27d2p-119, -0x1.f49f49f49f49fp-173},
+        {0x1.1111111111111p-7, 0x1.1111111111111p-63, 0x1.1111111111111p-119, 0x1.1111111111111p-175},
+        {0x1.5555555555555p-5, 0x1.5555555555555p-59, 0x1.5555555555555p-113, 0x1.5555555555555p-167},
+        {0x1.5555555555555p-3, 0x1.5555555555555p-57, 0x1.5555555555555p-111, 0x1.5555555555555p-165},
+        {0x1.0000000000000p-1, 0.0, 0.0, 0.0},
+        {1.0, 0.0, 0.0, 0.0}};
+    qd s = qd_from_dd(sd);
+    for (int j = 0; j < 8; ++j) s = qd_add(qd_make(c[j][0], c[j][1], c[j][2], c[j][3]), qd_mul(t, s));
+    qd a = qd_mul(t, s);
+    for (int i = 0; i < 10; ++i) a = qd_mul(a, qd_add(qd_from(2.0), a));
+    a = qd_add(qd_from(1.0), a);
+    const int ik = (int)k;
+    return qd_make(ldexp(a.x0, ik), ldexp(a.x1, ik), ldexp(a.x2, ik), ldexp(a.x3, ik));
+}
+
 // helpers with the call shape of the other scalar tiers
 DD_FN qd sub_dot2(qd x, qd a1, qd b1, qd a2, qd b2) { return qd_sub_dot2(x, a1, b1, a2, b2); }
 DD_FN qd sub_mul(qd x, qd a, qd b) { return qd_sub_mul(x, a, b); }
@@ -212,6 +259,9 @@ DD_FN qd det2(qd a, qd b, qd c) { return qd_det2(a, b, c); }
 DD_FN qd rsqrt_s(qd x) { return qd_rsqrt(x); }
 DD_FN qd mul_s(qd a, qd b) { return qd_mul(a, b); }
 DD_FN double hi_of(qd a) { return a.x0; }
+DD_FN qd exp_s(qd x) { return qd_exp(x); }
+DD_FN qd add_s(qd a, qd b) { return qd_add(a, b); }
+DD_FN qd scale_s(qd a, double f) { return qd_mul_d(a, f); }
 
 template <> DD_FN qd from_pair<qd>(double h, double l) {
     double s, e;

@@ -1,4 +1,4 @@
-// Host build of the double-double exp and the quad-double arithmetic used by
+// Host build of the double-double and quad-double exp and the quad-double arithmetic used by
 // the GPU kernels (the same headers), driven by tests/test_arith_host.py:
 // prints operands and results as hex floats for an mpmath comparison.
 #include <cmath>
@@ -28,7 +28,7 @@ static void put(qd a) { printf(" %a %a %a %a", a.x0, a.x1, a.x2, a.x3); }
 int main(int argc, char **argv) {
     const int n = argc > 1 ? atoi(argv[1]) : 3000;
     for (int i = 0; i < n; i++) {
-        const int kind = i % 9;
+        const int kind = i % 10;
         qd a = rand_qd(ldexp(1.0, (int)(urand() * 40) - 20)), b = rand_qd(ldexp(1.0, (int)(urand() * 40) - 20));
         if (kind == 1) {  // b = -a perturbed at one level: heavy cancellation
             b = qd_neg(a);
@@ -57,6 +57,15 @@ int main(int argc, char **argv) {
         case 6: { const dd r = qd_to_dd(a); put(a); printf(" %a %a", r.hi, r.lo); break; }
         case 7: { const qd c = rand_qd(1.0); put(a); put(b); put(c); put(qd_det2(a, b, c)); break; }
         case 8: { const qd c = rand_qd(1.0); put(c); put(a); put(b); put(qd_sub_mul(c, a, b)); break; }
+        case 9: {  // quad-double exp on [-60, 5] (both signs of the tree's exponents), and exp(0)
+            const double x0 = i == 9 ? 0.0 : (i % 4 == 0 ? urand() * 5.0 : -urand() * (i % 3 == 0 ? 0.5 : 60.0));
+            const qd x = x0 == 0.0 ? qd_from(0.0) : rand_qd(1.0).x0 > 0 ? qd_renorm5(x0, x0 * 1e-17 * urand(),
+                                                                                    x0 * 1e-34 * urand(), 0.0, 0.0)
+                                                                        : qd_from(x0);
+            put(x);
+            put(qd_exp(x));
+            break;
+        }
         }
         printf("\n");
     }

@@ -1,9 +1,10 @@
 """Host build of the kernels' extended-precision arithmetic (csrc/dd.hpp,
 csrc/qd.hpp) against mpmath at 120 digits: quad-double add (including
 cancellation at every level), mul, rsqrt, the fused Schur update and the
-rounding to double-double; the double-double exp of the displaced tier.
-Bounds: |err| <= c u^4 (|a| + |b|) for sums, c u^4 |result| for products
-(u = 2^-53, c = 16), 4 max(1, |x|) 2^-106 relative for exp."""
+rounding to double-double; the double-double and quad-double exp of the
+displaced tiers.  Bounds: |err| <= c u^4 (|a| + |b|) for sums, c u^4 |result|
+for products (u = 2^-53, c = 16), 4 max(1, |x|) 2^-106 relative for the
+double-double exp and 8 max(1, |x|) 2^-208 for the quad-double exp."""
 import os
 import shutil
 import subprocess
@@ -100,3 +101,22 @@ def test_double_double_exp_against_mpmath(lines):
         assert abs(r - want) <= 4 * max(1, abs(x)) * mp.mpf(2) ** -106 * want, (f, float(abs(r - want) / want))
         n += 1
     assert n > 300
+
+
+def test_quad_double_exp_against_mpmath(lines):
+    import mpmath as mp
+    mp.mp.dps = 120
+    n, worst = 0, 0.0
+    for f in lines:
+        if int(f[0]) != 9:
+            continue
+        x, r = _q(f[1:5]), _q(f[5:9])
+        want = mp.exp(x)
+        if x == 0:  # a zero mean must leave every overlap factor exactly 1
+            assert r == 1
+        err = abs(r - want) / (want * max(1, abs(x)) * mp.mpf(2) ** -208)
+        worst = max(worst, float(err))
+        assert _nonoverlapping(f[5:9])
+        n += 1
+    assert n > 300
+    assert worst <= 8, worst
