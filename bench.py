@@ -560,6 +560,10 @@ def main():
                                              mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
         out["per_n_displaced_f64_terms"] = per_n_rates(ctx, cov, "f64", ns=(20, 24, 28),
                                                        mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
+        out["per_n_displaced_qd_terms"] = per_n_rates(ctx, cov, "qd", ns=(20, 24),
+                                                      mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
+        out["per_n_full_pattern_displaced_qd"] = per_n_rates(
+            ctx, cov, "qd", ns=(20,), full=True, mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
         out["sampler"] = sampler_bench(ctx)
         out["sampler_displaced"] = sampler_bench(ctx, n_samples=200, displaced=True)
         out["paper_worst_case"] = paper_worst_case(ctx)

@@ -35,13 +35,16 @@
  * factorisation runs in binary64 (TOR_PREC_F64) or in double-double
  * (TOR_PREC_DD); TOR_PREC_AUTO runs binary64 first and repeats in
  * double-double when the a-priori bound exceeds tol.  TOR_PREC_QD (opt-in;
- * tor_probability, tor_subset_sum, tor_batch (one query at a time) and
- * gbs_chain_fixed; zero-mean states) runs the no-click conditioning,
+ * tor_probability, tor_probability_displaced, tor_subset_sum, tor_batch and
+ * tor_batch_displaced (one query at a time) and gbs_chain_fixed) runs the
+ * no-click conditioning,
  * the factorisation and the sum in quad-double (about 212 bits): for sums
  * that cancel beyond double-double, e.g. full patterns conditioned on
  * hundreds of no-click modes (R ~ 1e36 at n = 28 on 800 modes).  Its trees
- * use 8-mode wave tasks and need about 5.5 GB of device memory at n = 28
- * (x 2 per further click).
+ * use 8-mode wave tasks (7-mode with a mean row) and need about 5.5 GB of
+ * device memory at n = 28 (x 2 per further click).  Displaced states take
+ * the per-query conditioning route in quad-double (an inverted state's
+ * inverse serves binary64 and double-double terms).
  *
  * Status codes: 0 = TOR_OK; TOR_WARN_PRECISION (1): result delivered but its
  * error bound exceeds tol; negative values are errors and leave *out
@@ -219,7 +222,8 @@ void tor_state_destroy(tor_state *st);
  * information-form sums of [0, h_C; h_C, G] (each pivot's factor carries
  * exp(+|w|^2/2)): p = (-1)^n det(sigma_Q)^-1/2 exp(-mu^T K mu / 2) T_h(G),
  * binary64 or double-double terms, in tor_batch and the server (not in
- * tor_batch_async; quad-double terms take zero-mean states only).  Errors:
+ * tor_batch_async; their quad-double queries take the per-query
+ * conditioning route).  Errors:
  * TOR_EINVAL (NULL, bad prec), TOR_ETOOBIG (m > 2048), TOR_ENOMEM,
  * TOR_ENOTPD (a non-positive pivot; a previous inverse is kept).  Not
  * thread-safe against other calls on the state (call it before submitting

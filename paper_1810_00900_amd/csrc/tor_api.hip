@@ -1195,20 +1195,22 @@ void finalize(const Prepared &p, const SumOut &s, int used, double tol, tor_resu
 // Subset sum of one packed n-mode matrix in quad-double: the top n - J levels
 // expanded in HBM (slots [coefficient][matrix]), J = min(n, 8)-mode wave
 // tasks, fixed-order reduction stages, one result.
-tor_status gpu_sum_qd(tor_ctx *ctx, const std::vector<qd> &packed, int n, SumOut &out) {
+tor_status gpu_sum_qd(tor_ctx *ctx, const std::vector<qd> &packed, int n, SumOut &out, int D = 0) {
     if (n == 0) {
         out = SumOut{};
         return TOR_OK;
     }
-    const int J = std::min(n, TOR_QD_TASK_MAX), G = n - J;
+    // displaced trees: seven-mode tasks (the eight-mode working set with the
+    // mean row needs 56 KB of LDS, two workgroups per CU)
+    const int J = std::min(n, D ? TOR_QD_TASK_MAX - 1 : TOR_QD_TASK_MAX), G = n - J;
     const long long nt = 1LL << G;
     const size_t es = sizeof(qd);
-    // pool: root slot, then per level 2^d child slots of E(n - d - 1) + 1 words
+    // pool: root slot, then per level 2^d child slots of EN(n - d - 1, D) + 1 words
     std::vector<unsigned long long> child_base(G);
-    unsigned long long words = 1 + (unsigned long long)E(n);
+    unsigned long long words = 1 + (unsigned long long)EN(n, D);
     for (int d = 0; d < G; d++) {
         child_base[d] = words;
-        words += (1ULL << d) * (unsigned long long)(E(n - d - 1) + 1);
+        words += (1ULL << d) * (unsigned long long)(EN(n - d - 1, D) + 1);
     }
     // reduction stages over partials (stage outputs one after another in partB)
     std::vector<ReduceJobQ> red;
@@ -1256,7 +1258,7 @@ tor_status gpu_sum_qd(tor_ctx *ctx, const std::vector<qd> &packed, int n, SumOut
     const NodeDesc root{1, 1.0, 0.0, 1.0};  // the matrix starts after the coefficient word
     std::memcpy(hj.data() + off_root, &root, sizeof root);
     for (int d = 0; d < G; d++) {
-        ExpandJob job{level_ptr(d), level_ptr(d + 1), child_base[d], n - d, 0};
+        ExpandJob job{level_ptr(d), level_ptr(d + 1), child_base[d], n - d, D};
         std::memcpy(hj.data() + off_exp + d * sizeof(ExpandJob), &job, sizeof job);
     }
     const WaveJob wj{level_ptr(G), (Partial *)partA, 0};
@@ -1266,17 +1268,17 @@ tor_status gpu_sum_qd(tor_ctx *ctx, const std::vector<qd> &packed, int n, SumOut
         std::memcpy(hj.data() + off_red + k * sizeof(ReduceJobQ), &job, sizeof job);
     }
     // root slot: coefficient 1, then the matrix
-    std::vector<qd> root_words(1 + (size_t)E(n));
+    std::vector<qd> root_words(1 + (size_t)EN(n, D));
     root_words[0] = qd_from(1.0);
-    for (long long e = 0; e < E(n); e++) root_words[1 + (size_t)e] = packed[(size_t)e];
+    for (long long e = 0; e < EN(n, D); e++) root_words[1 + (size_t)e] = packed[(size_t)e];
     hipStream_t st = ctx->stream;
     HIP_TRY(hipMemcpyAsync(ctx->pool.p, root_words.data(), root_words.size() * es, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dj, hj.data(), job_bytes, hipMemcpyHostToDevice, st));
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[0], st));
     for (int d = 0; d < G; d++)
-        HIP_TRY(tor_launch_expand_qd((const ExpandJob *)(dj + off_exp) + d, 1, d, ctx->pool.p, 1 << 20, st));
+        HIP_TRY(tor_launch_expand_qd((const ExpandJob *)(dj + off_exp) + d, 1, d, ctx->pool.p, 1 << 20, st, D));
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[1], st));
-    HIP_TRY(tor_launch_wave_qd(J, (const WaveJob *)(dj + off_wave), 1, nt, ctx->pool.p, ctx->wave_grid, st));
+    HIP_TRY(tor_launch_wave_qd(J, (const WaveJob *)(dj + off_wave), 1, nt, ctx->pool.p, ctx->wave_grid, st, D));
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev[2], st));
     for (size_t k = 0; k < rs.size(); k++)
         HIP_TRY(tor_launch_reduce_qd((const ReduceJobQ *)(dj + off_red) + k, 1,
@@ -1303,10 +1305,10 @@ tor_status gpu_sum_qd(tor_ctx *ctx, const std::vector<qd> &packed, int n, SumOut
 // Vacuum conditioning of one reduced pattern (r.cond set) in quad-double, one
 // two-kernel step per no-click mode; returns the conditioned leading block.
 tor_status condition_qd(tor_ctx *ctx, const Reduced &r, std::vector<qd> &sigc, dd &pvac, double &log_pvac) {
-    const int n = r.n, k = r.k;
+    const int n = r.n, k = r.k, D = r.D;
     const size_t words = r.packed.size();
     const size_t cols_off = align_up(words * sizeof(qd), 256);
-    const size_t cols_words = 2 * (2 * (size_t)(n + k) - 2) + 2;
+    const size_t cols_words = 2 * (2 * (size_t)(n + k) - 2 + D) + 2;
     const size_t acc_off = align_up(cols_off + cols_words * sizeof(qd), 256);
     const size_t job_off = align_up(acc_off + 3 * sizeof(double), 256);
     const size_t total_bytes = job_off + (size_t)k * sizeof(CondJobQ);
@@ -1328,17 +1330,18 @@ tor_status condition_qd(tor_ctx *ctx, const Reduced &r, std::vector<qd> &sigc, d
         j.cols = db + cols_off;
         j.qout = nullptr;
         j.r = n + k - t;
+        j.d = D;
         j.begin = 0;
-        blocks[t] = std::max<long long>(1, (E(j.r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
+        blocks[t] = std::max<long long>(1, (EN(j.r - 1, D) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
         std::memcpy(stage.data() + job_off + t * sizeof(CondJobQ), &j, sizeof j);
     }
     hipStream_t st = ctx->stream;
     HIP_TRY(hipMemcpyAsync(db, stage.data(), total_bytes, hipMemcpyHostToDevice, st));
     for (int t = 0; t < k; t++)
         HIP_TRY(tor_launch_condition_qd((const CondJobQ *)(db + job_off) + t, 1, blocks[t], st));
-    sigc.assign((size_t)E(n), qd_from(0.0));
+    sigc.assign((size_t)EN(n, D), qd_from(0.0));
     double acc[3];
-    HIP_TRY(hipMemcpyAsync(sigc.data(), db, (size_t)E(n) * sizeof(qd), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(sigc.data(), db, sigc.size() * sizeof(qd), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(acc, db + acc_off, sizeof acc, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     ctx->stats.condition_launches += 2 * (int64_t)k;
@@ -1396,6 +1399,44 @@ tor_status probability_qd(tor_ctx *ctx, const double *cov, int m, const int8_t *
     }
     SumOut so;
     s = gpu_sum_qd(ctx, sigc, red.n, so);
+    if (s) return s;
+    if (!std::isfinite(so.T.hi) || !std::isfinite(so.A)) {
+        std::memset(out, 0, sizeof *out);
+        out->status = TOR_ENOTPD;
+        return fail(TOR_ENOTPD, "a Schur pivot was not positive (non-physical or near-singular covariance)");
+    }
+    if (!(tol > 0.0)) tol = 1e-10;
+    finalize(p, so, TOR_PREC_QD, tol, out);
+    return out->status;
+}
+
+// Probability of one pattern of a displaced state with quad-double terms:
+// the packed matrix with its mean row, conditioned in qd when the pattern has
+// no-click modes, then the qd tree with the pivots' overlap factors.
+tor_status probability_qd_disp(tor_ctx *ctx, const double *cov, const double *mean, int m, const int8_t *pattern,
+                               double tol, tor_result *out) {
+    Reduced red;
+    tor_status s = reduce_pattern_disp(cov, mean, m, pattern, red);
+    if (s) return s;
+    std::vector<qd> sigc;
+    dd pvac = dd_from(1.0);
+    double log_pvac = 0.0;
+    if (red.cond) {
+        s = condition_qd(ctx, red, sigc, pvac, log_pvac);
+        if (s) return s;
+    } else {
+        sigc.resize(red.packed.size());
+        for (size_t e = 0; e < sigc.size(); e++) sigc[e] = qd_from_dd(red.packed[e]);
+    }
+    // PD check, log det Sigma_C and the bound's mu_C^T Sigma_C^-1 mu_C from the
+    // double-double rounding
+    std::vector<dd> rounded(sigc.size());
+    for (size_t e = 0; e < sigc.size(); e++) rounded[e] = qd_to_dd(sigc[e]);
+    Prepared p;
+    s = prepare_disp(std::move(rounded), red.n, pvac, log_pvac, p);
+    if (s) return s;
+    SumOut so;
+    s = gpu_sum_qd(ctx, sigc, red.n, so, 1);
     if (s) return s;
     if (!std::isfinite(so.T.hi) || !std::isfinite(so.A)) {
         std::memset(out, 0, sizeof *out);
@@ -1606,6 +1647,7 @@ tor_status tor_probability_displaced(tor_ctx *ctx, const double *cov, const doub
     if (s) return s;
     HIP_TRY(hipSetDevice(ctx->device));
     if (!out) return fail(TOR_EINVAL, "out is NULL");
+    if (prec == TOR_PREC_QD) return probability_qd_disp(ctx, cov, mean, m, pattern, tol, out);
     Reduced red;
     s = reduce_pattern_disp(cov, mean, m, pattern, red);
     if (s) return s;
@@ -1796,19 +1838,14 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
     if (st->ctx != ctx) return fail(TOR_EINVAL, "state belongs to another context");
     if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
     HIP_TRY(hipSetDevice(ctx->device));
-    if (prec == TOR_PREC_QD && !st->mean.empty()) {
-        for (int q = 0; q < nq; q++) {
-            std::memset(&out[q], 0, sizeof out[q]);
-            out[q].status = TOR_EINVAL;
-        }
-        return fail(TOR_EINVAL, "quad-double terms take zero-mean states only");
-    }
     if (prec == TOR_PREC_QD) {  // quad-double conditioning and trees, one query at a time
         tor_status first = TOR_OK;
         for (int q = 0; q < nq; q++) {
             std::memset(&out[q], 0, sizeof out[q]);
-            tor_status s =
-                probability_qd(ctx, st->cov.data(), st->m, patterns + (size_t)q * st->m, tol, &out[q], st);
+            const int8_t *pat = patterns + (size_t)q * st->m;
+            tor_status s = st->mean.empty()
+                               ? probability_qd(ctx, st->cov.data(), st->m, pat, tol, &out[q], st)
+                               : probability_qd_disp(ctx, st->cov.data(), st->mean.data(), st->m, pat, tol, &out[q]);
             if (s < 0) {
                 std::memset(&out[q], 0, sizeof out[q]);
                 out[q].status = s;
@@ -1852,6 +1889,22 @@ tor_status tor_batch_displaced(tor_ctx *ctx, const tor_state *st, const double *
     if (st->ctx != ctx) return fail(TOR_EINVAL, "state belongs to another context");
     if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
     HIP_TRY(hipSetDevice(ctx->device));
+    if (prec == TOR_PREC_QD) {  // quad-double conditioning and trees, one query at a time
+        tor_status first = TOR_OK;
+        for (int q = 0; q < nq; q++) {
+            std::memset(&out[q], 0, sizeof out[q]);
+            tor_status s =
+                probability_qd_disp(ctx, st->cov.data(), mean, st->m, patterns + (size_t)q * st->m, tol, &out[q]);
+            if (s < 0) {
+                std::memset(&out[q], 0, sizeof out[q]);
+                out[q].status = s;
+                if (s == TOR_EDEVICE) return s;
+            }
+            if (s < 0 && first >= 0) first = s;
+            else if (s == TOR_WARN_PRECISION && first == TOR_OK) first = s;
+        }
+        return first;
+    }
     std::vector<Prepared> qs((size_t)nq);
     std::vector<Reduced> red((size_t)nq);
     std::vector<Reduced *> rp;

@@ -174,13 +174,13 @@ struct CondJobQ {
     double *qout;  // if not null: this step's pivot factor q (double-double rounding, hi, lo)
     long long begin;
     int r;
-    int pad;
+    int d;  // 1: displaced state, the packed matrix has the mean row first
 };
 
 hipError_t tor_launch_wave_qd(int J, const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
-                              hipStream_t st);
+                              hipStream_t st, int disp = 0);
 hipError_t tor_launch_expand_qd(const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
-                                hipStream_t st);
+                                hipStream_t st, int disp = 0);
 hipError_t tor_launch_reduce_qd(const ReduceJobQ *jobs, int njobs, long long total_blocks, hipStream_t st);
 // one conditioning step: the pivot columns of every job, then the update
 hipError_t tor_launch_condition_qd(const CondJobQ *jobs, int njobs, long long total_blocks, hipStream_t st);

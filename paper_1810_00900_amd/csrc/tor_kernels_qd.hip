@@ -6,7 +6,9 @@
 // no-click modes): the relative error bound 16 n u R becomes 16 n 2^-208 R.
 //
 // The path coefficient of a node lives in its pool slot, one word before the
-// packed matrix, so descriptors keep the layout of the other tiers.
+// packed matrix, so descriptors keep the layout of the other tiers.  D = 1: a
+// displaced state, the packed matrices carry the mean row first (the pivots'
+// overlap factors exp(-|w|^2 / 2) by the quad-double exp).
 #include <hip/hip_runtime.h>
 
 #include "dd.hpp"
@@ -20,22 +22,22 @@ namespace tor {
 
 // One 64-lane workgroup per task of J <= 8 modes (LDS 50 KB at J = 8: three
 // workgroups per CU, one wave per SIMD for the register leaf).
-template <int J>
+template <int J, int D>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void wave_kernel_qd(
     const WaveJob *__restrict__ jobs, int njobs, long long total, const qd *__restrict__ pool) {
-    __shared__ WaveSmem<qd, J, 0> sm;
+    __shared__ WaveSmem<qd, J, D> sm;
     const int lane = threadIdx.x;
-    wave_tree_init<0>(sm.ab, lane);
+    wave_tree_init<D>(sm.ab, lane);
     for (long long t = blockIdx.x; t < total; t += gridDim.x) {
         const int j = find_job(jobs, njobs, t);
         const long long lt = t - jobs[j].begin;
         const NodeDesc d = jobs[j].tasks[lt];
         const qd *root = pool + d.off;
-        for (int e = lane; e < E(J); e += 64) sm.mat[e] = root[e];
+        for (int e = lane; e < EN(J, MR(D)); e += 64) sm.mat[e] = root[e];
         const qd c = root[-1];
         qd T;
         double A;
-        wave_tree<qd, J, 0>(sm, c, d.acoef, lane, T, A);
+        wave_tree<qd, J, D>(sm, c, d.acoef, lane, T, A);
         wave_reduce(T, A);
         if (lane == 0) {
             PartialQ p;
@@ -53,18 +55,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void wa
 
 // One wave per parent node (four per 256-thread workgroup): the include child
 // goes to the pool with its coefficient -c q in the word before it.
+template <int D>
 __global__ __launch_bounds__(256) void expand_kernel_qd(const ExpandJob *__restrict__ jobs, int log2npar,
                                                         long long total, qd *__restrict__ pool) {
-    __shared__ qd vs[4][2][2 * TOR_MAX_N];
+    __shared__ qd vs[4][2][2 * TOR_MAX_N + MR(D)];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     qd *v0 = vs[w][0], *v1 = vs[w][1];
     for (long long f = (long long)blockIdx.x * 4 + w; f < total; f += (long long)gridDim.x * 4) {
         const ExpandJob job = jobs[f >> log2npar];
         const long long i = f & ((1LL << log2npar) - 1);
-        const int r = job.r, R = 2 * r, RC = R - 2, EC = E(r - 1);
+        const int r = job.r, R = 2 * r + MR(D), RC = R - 2, EC = EN(r - 1, MR(D));
         const NodeDesc d = job.par[i];
         const qd *base = pool + d.off;
-        const Pivot<qd> pv = make_pivot(base[pidx(R - 2, R - 2)], base[pidx(R - 1, R - 2)], base[pidx(R - 1, R - 1)]);
+        const Pivot<qd> pv = make_pivot_m<qd, D>(base, R - 2, R - 1);
         const unsigned long long coff = job.child_base + (unsigned long long)i * (unsigned long long)(EC + 1) + 1;
         if (lane == 0) {
             job.chi[2 * i] = d;
@@ -144,10 +147,10 @@ __global__ __launch_bounds__(256) void reduce_kernel_qd(const ReduceJobQ *__rest
 // columns to the job's scratch (and multiplies the job's P_vac by q).
 __global__ __launch_bounds__(256) void condition_cols_qd(const CondJobQ *__restrict__ jobs) {
     const CondJobQ job = jobs[blockIdx.x];
-    const int r = job.r, R = 2 * r, RC = R - 2;
+    const int r = job.r, R = 2 * r + (job.d ? 1 : 0), RC = R - 2;
     const qd *M = static_cast<const qd *>(job.mat);
     qd *cols = static_cast<qd *>(job.cols);
-    const Pivot<qd> pv = make_pivot(M[pidx(R - 2, R - 2)], M[pidx(R - 1, R - 2)], M[pidx(R - 1, R - 1)]);
+    const Pivot<qd> pv = job.d ? make_pivot_m<qd, 1>(M, R - 2, R - 1) : make_pivot_m<qd, 0>(M, R - 2, R - 1);
     for (int c = threadIdx.x; c < RC; c += blockDim.x) {
         const qd m0 = M[pidx(R - 2, c)];
         cols[c] = qd_mul(m0, pv.s1);
@@ -173,10 +176,10 @@ __global__ __launch_bounds__(256) void condition_update_qd(const CondJobQ *__res
     const int j = find_job(jobs, njobs, (long long)blockIdx.x);
     const CondJobQ job = jobs[j];
     const long long blk = (long long)blockIdx.x - job.begin;
-    const int r = job.r, RC = 2 * r - 2;
+    const int r = job.r, RC = 2 * r - 2 + (job.d ? 1 : 0);
     qd *M = static_cast<qd *>(job.mat);
     const qd *cols = static_cast<const qd *>(job.cols);
-    const int EC = E(r - 1);
+    const int EC = job.d ? EN(r - 1, 1) : EN(r - 1, 0);
     const int e0 = (int)(blk * TOR_COND_CHUNK);
     const int e1 = e0 + TOR_COND_CHUNK < EC ? e0 + TOR_COND_CHUNK : EC;
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
@@ -186,42 +189,54 @@ __global__ __launch_bounds__(256) void condition_update_qd(const CondJobQ *__res
     }
 }
 
-template <int J>
+template <int J, int D>
 static hipError_t launch_qd_J(const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
                               hipStream_t st) {
     const long long g = total < grid_cap ? total : grid_cap;
     if (g < 1) return hipSuccess;
     (void)hipGetLastError();  // report only this launch's error
-    hipLaunchKernelGGL((wave_kernel_qd<J>), dim3((unsigned)g), dim3(64), 0, st, jobs, njobs, total,
+    hipLaunchKernelGGL((wave_kernel_qd<J, D>), dim3((unsigned)g), dim3(64), 0, st, jobs, njobs, total,
                        (const qd *)pool);
     return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_qd_D(int J, const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
+                              hipStream_t st) {
+    switch (J) {
+    case 1: return launch_qd_J<1, D>(jobs, njobs, total, pool, grid_cap, st);
+    case 2: return launch_qd_J<2, D>(jobs, njobs, total, pool, grid_cap, st);
+    case 3: return launch_qd_J<3, D>(jobs, njobs, total, pool, grid_cap, st);
+    case 4: return launch_qd_J<4, D>(jobs, njobs, total, pool, grid_cap, st);
+    case 5: return launch_qd_J<5, D>(jobs, njobs, total, pool, grid_cap, st);
+    case 6: return launch_qd_J<6, D>(jobs, njobs, total, pool, grid_cap, st);
+    case 7: return launch_qd_J<7, D>(jobs, njobs, total, pool, grid_cap, st);
+    case 8: return launch_qd_J<8, D>(jobs, njobs, total, pool, grid_cap, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace tor
 
 hipError_t tor_launch_wave_qd(int J, const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
-                              hipStream_t st) {
-    switch (J) {
-    case 1: return tor::launch_qd_J<1>(jobs, njobs, total, pool, grid_cap, st);
-    case 2: return tor::launch_qd_J<2>(jobs, njobs, total, pool, grid_cap, st);
-    case 3: return tor::launch_qd_J<3>(jobs, njobs, total, pool, grid_cap, st);
-    case 4: return tor::launch_qd_J<4>(jobs, njobs, total, pool, grid_cap, st);
-    case 5: return tor::launch_qd_J<5>(jobs, njobs, total, pool, grid_cap, st);
-    case 6: return tor::launch_qd_J<6>(jobs, njobs, total, pool, grid_cap, st);
-    case 7: return tor::launch_qd_J<7>(jobs, njobs, total, pool, grid_cap, st);
-    case 8: return tor::launch_qd_J<8>(jobs, njobs, total, pool, grid_cap, st);
-    default: return hipErrorInvalidValue;
-    }
+                              hipStream_t st, int disp) {
+    return disp ? tor::launch_qd_D<1>(J, jobs, njobs, total, pool, grid_cap, st)
+                : tor::launch_qd_D<0>(J, jobs, njobs, total, pool, grid_cap, st);
 }
 
 hipError_t tor_launch_expand_qd(const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
-                                hipStream_t st) {
+                                hipStream_t st, int disp) {
     const long long total = (long long)njobs << log2npar;
     const long long blocks = (total + 3) / 4;
     const long long g = blocks < grid_cap ? blocks : grid_cap;
     if (g < 1) return hipSuccess;
     (void)hipGetLastError();  // report only this launch's error
-    hipLaunchKernelGGL(tor::expand_kernel_qd, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total, (qd *)pool);
+    if (disp)
+        hipLaunchKernelGGL(tor::expand_kernel_qd<1>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
+                           (qd *)pool);
+    else
+        hipLaunchKernelGGL(tor::expand_kernel_qd<0>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
+                           (qd *)pool);
     return hipGetLastError();
 }
 

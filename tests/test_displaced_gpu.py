@@ -274,6 +274,11 @@ def test_displaced_state_batch_and_server(ctx):
         else:
             assert (g.p, g.p_lo, g.T, g.T_lo, g.abs_sum, g.rel_err_bound, g.status) == (
                 r.p, r.p_lo, r.T, r.T_lo, r.abs_sum, r.rel_err_bound, r.status)
-    with pytest.raises(tg.TorError):
-        ctx.batch(st, np.stack(pats[:1]), prec="qd")
+    # quad-double terms: the per-query conditioning route with the mean row
+    import mpmath as mp
+    mp.mp.dps = 50
+    q, _ = ctx.batch(st, np.stack(pats[:2]), prec="qd")
+    for g, s in zip(q, singles[:2]):
+        assert g.prec_used == tg.PREC_QD
+        assert _rel_mp(g, mp.mpf(s.p) + mp.mpf(s.p_lo)) <= s.rel_err_bound + 1e-28
     st.close()

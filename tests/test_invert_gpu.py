@@ -329,10 +329,13 @@ def test_single_mode_and_largest_state(ctx):
 def test_invert_errors(ctx):
     m = 6
     cov, _, rng = _state(m, 155)
-    disp = ctx.state(cov, mean=gi.random_mean(m, rng, 0.3)).invert("qd")  # displaced: allowed
-    with pytest.raises(tg.TorError) as e:  # quad-double terms still take zero-mean states only
-        ctx.batch(disp, gi.full_pattern(m, [1])[None, :], prec="qd")
-    assert e.value.status == tg.TOR_EINVAL
+    mean = gi.random_mean(m, rng, 0.3)
+    disp = ctx.state(cov, mean=mean).invert("qd")  # displaced: allowed
+    # quad-double queries of a displaced state take the per-query conditioning
+    fp = gi.full_pattern(m, [1])
+    r, _ = ctx.batch(disp, fp[None, :], prec="qd")
+    w = ctx.probability_displaced(cov, mean, fp, prec="qd")
+    assert (r[0].p, r[0].p_lo, r[0].prec_used) == (w.p, w.p_lo, tg.PREC_QD)
     disp.close()
     bad = ctx.state(-np.eye(2 * m))  # sigma_Q = -I/2: not positive definite
     with pytest.raises(tg.TorError) as e:

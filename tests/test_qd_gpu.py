@@ -9,7 +9,10 @@ construction (R = prod (1 + q_k) / (1 - q_k) for a product state):
 * lossy two-mode squeezed pairs with the partner of every clicked mode a
   no-click mode (correlated conditioning in quad-double);
 * a Haar-random mixing state against the binary128 oracle, and quad-double
-  against double-double wherever the latter's bound is small.
+  against double-double wherever the latter's bound is small;
+* displaced states (mean row, quad-double exp): the oracle's definition route
+  with mean factors, double-double within its bound, and weak coherent states
+  whose exact product cancels by R ~ 1e40.
 """
 import numpy as np
 import pytest
@@ -167,8 +170,7 @@ def test_subset_sum_qd_matches_dd(ctx, n):
 
 def test_qd_batch_equals_single_and_rejections(ctx):
     """tor_batch with quad-double terms (one query at a time): every result is
-    the single query's, failures stay per query; displaced queries reject
-    quad-double terms."""
+    the single query's, failures stay per query."""
     rng = np.random.default_rng(260)
     m = 16
     cov = gi.gbs_covariance(gi.haar_unitary(m, rng), np.full(m, 0.5))
@@ -183,10 +185,69 @@ def test_qd_batch_equals_single_and_rejections(ctx):
         assert (r.p, r.p_lo, r.T, r.abs_sum, r.prec_used) == (q.p, q.p_lo, q.T, q.abs_sum, tg.PREC_QD)
     assert res[-1].status == tg.TOR_EINVAL
     st.close()
-    cov = 0.5 * np.eye(4)
-    with pytest.raises(tg.TorError) as ei:
-        ctx.probability_displaced(cov, np.zeros(4), np.array([1, 0], np.int8), prec="qd")
-    assert ei.value.status == tg.TOR_EINVAL
+
+
+@pytest.mark.parametrize("seed", [270, 271])
+def test_displaced_qd_against_oracle_and_dd(ctx, seed):
+    """Displaced states with quad-double terms (mean row in every matrix, the
+    overlap factors by the quad-double exp, conditioning in qd, 7-mode tasks):
+    against the binary128 definition route with mean factors, and against
+    double-double terms within the latter's bound; batches on a displaced
+    state equal the single queries."""
+    import mpmath as mp
+    mp.mp.dps = 60
+    rng = np.random.default_rng(seed)
+    m = 18
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.3, 0.8, m))
+    mean = gi.random_mean(m, rng, 0.4)
+    pats = []
+    for n in (0, 3, 7, 10):
+        c = gi.random_click_set(m, n, rng)
+        pats.append(gi.full_pattern(m, c))
+        pats.append(gi.marginal_pattern(m, c))
+    for pat in pats:
+        q = ctx.probability_displaced(cov, mean, pat, prec="qd")
+        d = ctx.probability_displaced(cov, mean, pat, prec="dd")
+        o = oracle.formP_mean(cov, mean, pat)
+        want = mp.mpf(o.p) + mp.mpf(o.p_lo)
+        assert q.prec_used == tg.PREC_QD and q.status == tg.TOR_OK
+        assert abs(_mp_val(q) - want) <= abs(want) * max(1e-28, 1e-33 * o.cancel_ratio)
+        assert abs(_mp_val(d) - _mp_val(q)) <= abs(_mp_val(q)) * (d.rel_err_bound + 1e-28)
+        assert q.rel_err_bound <= 1e-40 * max(1.0, q.cancel_ratio)
+    st = ctx.state(cov, mean=mean)
+    res, _ = ctx.batch(st, np.stack(pats), prec="qd")
+    for pat, r in zip(pats, res):
+        s = ctx.probability_displaced(cov, mean, pat, prec="qd")
+        assert (r.p, r.p_lo, r.T, r.abs_sum) == (s.p, s.p_lo, s.T, s.abs_sum)
+    st.close()
+
+
+def test_displaced_qd_coherent_beyond_double_double(ctx):
+    """Weak coherent states (|beta|^2 = 1e-3 on 12 clicked modes of 30, the rest
+    observed without a click): the click factors 1 - e^{-|beta|^2} make the
+    alternating sum cancel by R ~ (2 / |beta|^2)^12 ~ 1e40.  Double-double
+    flags its bound; quad-double matches the exact product."""
+    import mpmath as mp
+    mp.mp.dps = 80
+    rng = np.random.default_rng(272)
+    m, n = 30, 12
+    clicks = sorted(rng.choice(m, n, replace=False).tolist())
+    beta = 0.2 * (rng.standard_normal(m) + 1j * rng.standard_normal(m))
+    beta[clicks] = np.sqrt(1e-3) * np.exp(2j * np.pi * rng.random(n))
+    cov = 0.5 * np.eye(2 * m)
+    mean = gi.coherent_mean(beta)
+    pat = gi.full_pattern(m, clicks)
+    want = mp.mpf(1)
+    for i in range(m):
+        # |beta|^2 = |mu|^2 / 2 (hbar = 1), from the binary64 mean actually passed
+        a2 = (mp.mpf(float(mean[2 * i])) ** 2 + mp.mpf(float(mean[2 * i + 1])) ** 2) / 2
+        want *= (1 - mp.exp(-a2)) if pat[i] == 1 else mp.exp(-a2)
+    q = ctx.probability_displaced(cov, mean, pat, prec="qd")
+    d = ctx.probability_displaced(cov, mean, pat, prec="dd")
+    assert q.cancel_ratio > 1e35
+    assert d.status == tg.TOR_WARN_PRECISION and d.rel_err_bound > 1e-6
+    err = abs(_mp_val(q) - want) / want
+    assert err <= q.rel_err_bound and err <= 1e-15, (float(err), q.rel_err_bound)
 
 
 def test_qd_errors(ctx):
