@@ -72,11 +72,12 @@ def wave_kernel_name(prec, J, D=0):
 def kernel_slug(kernel):
     """File-name form of a wave-kernel name: wave_kernel_top<dd,10,0> ->
     wave_kernel_top_dd10 (a displaced kernel gets the suffix _disp),
-    wave_kernel_qd<8> -> wave_kernel_qd8."""
+    wave_kernel_qd<8,0> -> wave_kernel_qd8."""
     base, args = kernel[:-1].split("<")
-    if "," not in args:
-        return f"{base}{args}"
-    s, J, D = args.split(",")
+    parts = args.split(",")
+    if len(parts) == 2:  # quad-double: <J,D>
+        return f"{base}{parts[0]}" + ("_disp" if parts[1] == "1" else "")
+    s, J, D = parts
     return f"{base}_{'f64' if s == 'double' else s}{J}" + ("_disp" if D == "1" else "")
 
 
@@ -510,7 +511,7 @@ def main():
     else:
         # no algorithmic model for these trees: the roofline uses the executed
         # FP64 flops of the committed PMC pass when its sources still match
-        kname = wave_kernel_name(args.prec, J, 1) if args.variant == "displaced" else f"wave_kernel_qd<{J}>"
+        kname = wave_kernel_name(args.prec, J, 1) if args.variant == "displaced" else f"wave_kernel_qd<{J},0>"
         wave_flops = None
         ex = measured_fp64(kname, wave_ms) if n == 28 else None
         achieved = ex["achieved"] if ex else None
