@@ -175,9 +175,10 @@ tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int
  * for tor_probability, except: T is the subset sum with the mean factors of
  * the conditioned state, tor = det(Sigma_C)^{1/2} * T, and rel_err_bound
  * carries a further factor (1 + mu_C^T Sigma_C^-1 mu_C) for the rounding of
- * the exponents.  A zero mean gives the zero-mean result.  Errors as for
- * tor_probability (TOR_EINVAL also for a NULL or non-finite mean entry of an
- * observed mode). */
+ * the exponents.  A zero mean gives the zero-mean result.  prec as for
+ * tor_probability, TOR_PREC_QD included (the overlap factors then come from
+ * a quad-double exp).  Errors as for tor_probability (TOR_EINVAL also for a
+ * NULL or non-finite mean entry of an observed mode). */
 tor_status tor_probability_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m,
                                      const int8_t *pattern, tor_prec prec, double tol, tor_result *out);
 
