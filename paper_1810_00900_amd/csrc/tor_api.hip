@@ -450,7 +450,7 @@ size_t sum_bytes(int n, int J, size_t es, int D = 0) {
 tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vector<int> &idx, bool use_dd,
                      std::vector<SumOut> &out) {
     const size_t es = use_dd ? sizeof(dd) : sizeof(double);
-    const int D = idx.empty() ? 0 : in[idx[0]].D, o = MR(D);  // tree kind, mean rows
+    const int D = idx.empty() ? 0 : in[idx[0]].D, mrows = MR(D);  // tree kind, mean rows
     struct Plan {
         int q, n, J, G;
         long long nt;
@@ -470,7 +470,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
         p.G = p.n - p.J;
         p.nt = 1LL << p.G;
         p.root_off = roots;
-        roots += (unsigned long long)EN(p.n, o);
+        roots += (unsigned long long)EN(p.n, mrows);
         p.desc_off = desc_total;
         desc_total += p.nt;
         Gmax = std::max(Gmax, p.G);
@@ -482,7 +482,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
         p.child_base.resize(p.G);
         for (int d = 0; d < p.G; d++) {
             p.child_base[d] = pool_total;
-            pool_total += (1ULL << d) * (unsigned long long)EN(p.n - d - 1, o);
+            pool_total += (1ULL << d) * (unsigned long long)EN(p.n - d - 1, mrows);
         }
     }
     // reduction stages: stage outputs laid out one after another in partB
@@ -568,7 +568,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
         for (size_t i = 0; i < P.size(); i++) {
             const Plan &p = P[i];
             if (p.G <= d) continue;
-            ExpandJob job{level_ptr(p, i, d), level_ptr(p, i, d + 1), p.child_base[d], p.n - d, o};
+            ExpandJob job{level_ptr(p, i, d), level_ptr(p, i, d + 1), p.child_base[d], p.n - d, mrows};
             std::memcpy(hj + off_exp + ej * sizeof(ExpandJob), &job, sizeof job);
             ej++;
         }
@@ -620,7 +620,7 @@ tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vect
     if (stage.size() < roots * es) stage.resize(roots * es);
     for (auto &p : P) {
         const std::vector<dd> &pk = *in[p.q].packed;
-        for (long long e = 0; e < EN(p.n, o); e++) {
+        for (long long e = 0; e < EN(p.n, mrows); e++) {
             if (use_dd) ((dd *)stage.data())[p.root_off + e] = pk[(size_t)e];
             else ((double *)stage.data())[p.root_off + e] = pk[(size_t)e].hi + pk[(size_t)e].lo;
         }
