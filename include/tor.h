@@ -371,7 +371,7 @@ tor_status gbs_chain_fixed(tor_ctx *ctx, const double *cov, int32_t m, const int
  * for tor_probability_displaced.  Each no-click step also moves the mean of
  * the remaining modes, and every vacuum probability carries its mean-overlap
  * factor; rel_err_bound includes the exponent factor (1 + mu^T Sigma^-1 mu)
- * of each step's sum.  prec: AUTO, F64 or DD (TOR_PREC_QD: TOR_EINVAL).
+ * of each step's sum.  prec as for gbs_chain_fixed (TOR_PREC_QD included).
  * Errors as for gbs_chain_fixed, TOR_EINVAL also for a NULL mean or a
  * non-finite mean entry of a measured mode. */
 tor_status gbs_chain_fixed_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m,

@@ -2311,14 +2311,14 @@ tor_status chain_sums_dd(tor_ctx *ctx, const double *cov, const double *mean, in
 // every step, then one quad-double subset sum per step.  roots[k] keeps the
 // double-double rounding of snapshot k (for the final log det); qv the q of
 // each no-click step.
-tor_status chain_sums_qd(tor_ctx *ctx, const double *cov, int m, const std::vector<int> &g,
+tor_status chain_sums_qd(tor_ctx *ctx, const double *cov, const double *mean, int m, const std::vector<int> &g,
                          const std::vector<int> &seq, const int8_t *outcomes, int nn,
                          std::vector<std::vector<dd>> &roots, std::vector<SumIn> &in, std::vector<SumOut> &res,
                          std::vector<double> &qv) {
-    const int nsteps = (int)seq.size(), nobs = nsteps;
-    const size_t words = (size_t)E(nobs);
+    const int nsteps = (int)seq.size(), nobs = nsteps, D = mean ? 1 : 0;  // D: the mean row first
+    const size_t words = (size_t)EN(nobs, D);
     const size_t cols_off = align_up(words * sizeof(qd), 256);
-    const size_t cols_words = 2 * (2 * (size_t)nobs - 2) + 2;
+    const size_t cols_words = 2 * (2 * (size_t)nobs - 2 + D) + 2;
     const size_t acc_off = align_up(cols_off + cols_words * sizeof(qd), 256);
     const size_t q_off = align_up(acc_off + 3 * sizeof(double), 256);
     const size_t job_off = align_up(q_off + 2 * (size_t)std::max(nn, 1) * sizeof(double), 256);
@@ -2328,8 +2328,11 @@ tor_status chain_sums_qd(tor_ctx *ctx, const double *cov, int m, const std::vect
     unsigned char *db = (unsigned char *)ctx->cond.p;
     std::vector<unsigned char> stage(total_bytes);
     qd *hm = (qd *)stage.data();
-    for (int a = 0; a < 2 * nobs; a++)
-        for (int b = 0; b <= a; b++) hm[pidx(a, b)] = qd_from_dd(sigq(cov, m, g[a], g[b]));
+    if (D) hm[0] = qd_from(0.0);
+    for (int a = 0; a < 2 * nobs; a++) {
+        if (D) hm[pidx(a + 1, 0)] = qd_from(mean[g[a]]);
+        for (int b = 0; b <= a; b++) hm[pidx(a + D, b + D)] = qd_from_dd(sigq(cov, m, g[a], g[b]));
+    }
     const double a0[3] = {1.0, 0.0, 0.0};
     std::memcpy(stage.data() + acc_off, a0, sizeof a0);
     CondJobQ *hj = (CondJobQ *)(stage.data() + job_off);
@@ -2341,6 +2344,7 @@ tor_status chain_sums_qd(tor_ctx *ctx, const double *cov, int m, const std::vect
         j.cols = db + cols_off;
         j.qout = (double *)(db + q_off) + 2 * t;
         j.r = r--;
+        j.d = D;
         hj[t++] = j;
     }
     hipStream_t st = ctx->stream;
@@ -2352,14 +2356,15 @@ tor_status chain_sums_qd(tor_ctx *ctx, const double *cov, int m, const std::vect
         if (outcomes[seq[k]] == 1) {
             c++;
         } else {
-            const long long blocks = std::max<long long>(1, (E(hj[t].r - 1) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
+            const long long blocks =
+                std::max<long long>(1, (EN(hj[t].r - 1, D) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
             HIP_TRY(tor_launch_condition_qd((const CondJobQ *)(db + job_off) + t, 1, blocks, st));
             t++;
         }
         snap_n[k] = c;
-        snaps[k].resize((size_t)E(c));
+        snaps[k].assign((size_t)EN(c, D), qd_from(0.0));
         if (c > 0)
-            HIP_TRY(hipMemcpyAsync(snaps[k].data(), db, (size_t)E(c) * sizeof(qd), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(snaps[k].data(), db, snaps[k].size() * sizeof(qd), hipMemcpyDeviceToHost, st));
     }
     qv.assign(2 * (size_t)nn, 0.0);
     if (nn > 0) HIP_TRY(hipMemcpyAsync(qv.data(), db + q_off, 2 * (size_t)nn * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2371,7 +2376,8 @@ tor_status chain_sums_qd(tor_ctx *ctx, const double *cov, int m, const std::vect
         roots[k].resize(snaps[k].size());
         for (size_t e = 0; e < snaps[k].size(); e++) roots[k][e] = qd_to_dd(snaps[k][e]);
         in[k].packed = &roots[k];
-        tor_status s = gpu_sum_qd(ctx, snaps[k], n, res[k]);
+        in[k].D = D;
+        tor_status s = gpu_sum_qd(ctx, snaps[k], n, res[k], D);
         if (s) return s;
     }
     return TOR_OK;
@@ -2449,8 +2455,6 @@ static tor_status chain_fixed_impl(tor_ctx *ctx, const double *cov, const double
     if (!ctx || !total) return fail(TOR_EINVAL, "NULL argument");
     if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD && prec != TOR_PREC_QD)
         return fail(TOR_EINVAL, "bad precision %d", (int)prec);
-    if (mean && prec == TOR_PREC_QD)
-        return fail(TOR_EINVAL, "quad-double terms take zero-mean states only");
     if (!(tol > 0.0)) tol = 1e-10;
     tor_status s = validate_cov_block(cov, m, outcomes);
     if (s) return s;
@@ -2497,7 +2501,7 @@ static tor_status chain_fixed_impl(tor_ctx *ctx, const double *cov, const double
     std::vector<int> used(nsteps, prec == TOR_PREC_QD ? TOR_PREC_QD : prec == TOR_PREC_DD ? TOR_PREC_DD : TOR_PREC_F64);
     std::vector<double> qv;
     if (prec == TOR_PREC_QD) {
-        s = chain_sums_qd(ctx, cov, m, g, seq, outcomes, nn, roots, in, res, qv);
+        s = chain_sums_qd(ctx, cov, mean, m, g, seq, outcomes, nn, roots, in, res, qv);
     } else {
         s = chain_sums_dd(ctx, cov, mean, m, g, seq, outcomes, nn, prec, tol, roots, in, res, used, qv);
     }

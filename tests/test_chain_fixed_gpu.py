@@ -168,6 +168,26 @@ def test_displaced_chain_zero_mean_is_the_zero_mean_chain(ctx):
     b, sb = ctx.chain_fixed(cov, pat, prec="dd", mean=np.zeros(2 * m))
     assert np.array_equal(sa, sb)
     assert (a.p, a.p_lo, a.T, a.T_lo) == (b.p, b.p_lo, b.T, b.T_lo)
-    with pytest.raises(tg.TorError) as ei:
-        ctx.chain_fixed(cov, pat, prec="qd", mean=np.zeros(2 * m))
-    assert ei.value.status == tg.TOR_EINVAL
+
+
+@pytest.mark.parametrize("pat", [
+    [1, 0, 1, 1, 0, -1, 1, 0],
+    [-1, 1, -1, 0, 1, -1, 0, 1],
+])
+def test_displaced_chain_quad_double(ctx, pat):
+    """gbs_chain_fixed_displaced with quad-double terms (mean row in the qd
+    conditioning snapshots and trees): every step against the oracle's rule
+    with means, the whole pattern against tor_probability_displaced in qd."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    cov = gi.state_config1()
+    pat = np.array(pat, np.int8)
+    mu = gi.random_mean(8, np.random.default_rng(303), 0.5)
+    tot, steps = ctx.chain_fixed(cov, pat, prec="qd", mean=mu)
+    assert tot.prec_used == tg.PREC_QD
+    want_tot, want = oracle.prob_sequential(cov, pat, dps=40, steps=True, mean=mu)
+    for j in range(8):
+        if pat[j] >= 0:
+            assert _rel(steps[j], want[j]) <= 1e-14, (j, steps[j], float(want[j]))
+    r = ctx.probability_displaced(cov, mu, pat, prec="qd")
+    assert abs(mp.mpf(tot.p) + mp.mpf(tot.p_lo) - (mp.mpf(r.p) + mp.mpf(r.p_lo))) <= 1e-28 * abs(mp.mpf(r.p))
