@@ -396,7 +396,9 @@ typedef struct {
     int32_t workers;         /* concurrent batches (each its own stream); default 2, at most 16 */
     int32_t max_pending;     /* admission: queries waiting; further submits get TOR_EAGAIN (default 65536) */
     size_t mem_budget_bytes; /* device bytes per batch (admission by memory; default 16 GiB) */
-    tor_prec prec;           /* precision policy of every query (TOR_PREC_DD recommended) */
+    tor_prec prec;           /* precision policy of every query (TOR_PREC_DD recommended; with
+                                TOR_PREC_QD each worker evaluates one query at a time through
+                                the quad-double single-query path, bitwise its result) */
     double tol;              /* relative error target; <= 0 means 1e-10 */
     int32_t max_batch;       /* queries per fused batch (default 4096) */
 } tor_server_opts;

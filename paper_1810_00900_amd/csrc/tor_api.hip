@@ -2624,6 +2624,8 @@ namespace {
 struct ServerReq {
     Reduced red;     // patterns with no-click modes: conditioned by the worker
     Prepared prep;
+    std::vector<int8_t> pattern;   // quad-double servers: the query itself, evaluated alone
+    const tor_state *st = nullptr;
     std::chrono::steady_clock::time_point t_submit, t_done;
     tor_result res;
     bool done = false;
@@ -2660,7 +2662,9 @@ void server_worker(tor_server *S, int w) {
             S->cv_work.wait(lk, [&] { return S->stopping || !S->pending.empty(); });
             if (S->pending.empty()) return;  // stopping and drained
             size_t bytes = 0;
-            while (!S->pending.empty() && (int)take.size() < S->opts.max_batch) {
+            // quad-double queries are taken one at a time so that the workers share them
+            const int most = S->opts.prec == TOR_PREC_QD ? 1 : S->opts.max_batch;
+            while (!S->pending.empty() && (int)take.size() < most) {
                 uint64_t t = S->pending.front();
                 ServerReq &r = *S->reqs[t];
                 size_t b = sum_bytes(r.red.n, task_modes_for(ctx, S->opts.prec == TOR_PREC_DD, r.red.n), es,
@@ -2673,6 +2677,42 @@ void server_worker(tor_server *S, int w) {
                 red.push_back(std::move(r.red));
                 S->pending.pop_front();
             }
+        }
+        if (S->opts.prec == TOR_PREC_QD) {  // quad-double: the single-query paths, one at a time
+            std::vector<std::pair<const tor_state *, std::vector<int8_t>>> qq;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                for (uint64_t t : take) qq.emplace_back(S->reqs[t]->st, std::move(S->reqs[t]->pattern));
+            }
+            std::vector<tor_result> out(take.size());
+            for (size_t i = 0; i < qq.size(); i++) {
+                const tor_state *st = qq[i].first;
+                const int8_t *pat = qq[i].second.data();
+                std::memset(&out[i], 0, sizeof out[i]);
+                tor_status s = st->mean.empty()
+                                   ? probability_qd(ctx, st->cov.data(), st->m, pat, S->opts.tol, &out[i], st)
+                                   : probability_qd_disp(ctx, st->cov.data(), st->mean.data(), st->m, pat,
+                                                         S->opts.tol, &out[i]);
+                if (s < 0) {
+                    std::memset(&out[i], 0, sizeof out[i]);
+                    out[i].status = s;
+                }
+            }
+            auto now = std::chrono::steady_clock::now();
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                for (size_t i = 0; i < take.size(); i++) {
+                    ServerReq &r = *S->reqs[take[i]];
+                    r.res = out[i];
+                    r.t_done = now;
+                    r.done = true;
+                }
+                S->stats.batches += 1;
+                S->stats.completed += (int64_t)take.size();
+                S->stats.max_batch_seen = std::max<int64_t>(S->stats.max_batch_seen, (int64_t)take.size());
+            }
+            S->cv_done.notify_all();
+            continue;
         }
         // no-click conditioning of the batch's full patterns, then their checks
         std::vector<Reduced *> rp;
@@ -2742,7 +2782,7 @@ tor_status tor_server_start(tor_ctx *ctx, const tor_server_opts *opts, tor_serve
         if (opts->max_batch > 0) o.max_batch = opts->max_batch;
     }
     if (o.workers > 16) return fail(TOR_EINVAL, "at most 16 workers");
-    if (o.prec != TOR_PREC_AUTO && o.prec != TOR_PREC_F64 && o.prec != TOR_PREC_DD)
+    if (o.prec != TOR_PREC_AUTO && o.prec != TOR_PREC_F64 && o.prec != TOR_PREC_DD && o.prec != TOR_PREC_QD)
         return fail(TOR_EINVAL, "bad precision");
     tor_server *S = new (std::nothrow) tor_server();
     if (!S) return fail(TOR_ENOMEM, "host allocation failed");
@@ -2779,8 +2819,22 @@ tor_status tor_submit(tor_server *S, const tor_state *st, const int8_t *pattern,
     std::unique_ptr<ServerReq> r(new (std::nothrow) ServerReq());
     if (!r) return fail(TOR_ENOMEM, "host allocation failed");
     r->t_submit = t0;
-    tor_status s = reduce_for_state(st, pattern, r->red);
+    tor_status s = reduce_for_state(st, pattern, r->red);  // validates the pattern
     if (s) return s;
+    if (S->opts.prec == TOR_PREC_QD) {  // evaluated alone by a worker from the pattern itself
+        r->pattern.assign(pattern, pattern + st->m);
+        r->st = st;
+        r->red = Reduced();
+        std::lock_guard<std::mutex> lk(S->mu);
+        if ((int)S->pending.size() >= S->opts.max_pending) return fail(TOR_EAGAIN, "queue full");
+        uint64_t t = S->next_ticket++;
+        S->reqs.emplace(t, std::move(r));
+        S->pending.push_back(t);
+        S->stats.submitted += 1;
+        *ticket = t;
+        S->cv_work.notify_one();
+        return TOR_OK;
+    }
     const int n = r->red.n, D = r->red.D;
     if (!r->red.cond) {  // marginal pattern: ready now (conditioned ones: in the worker)
         s = prepare_reduced(r->red, r->prep);

@@ -141,3 +141,26 @@ def test_concurrent_clients_conditioned_queries(ctx):
         assert (g.p, g.p_lo, g.T, g.T_lo, g.status) == (w.p, w.p_lo, w.T, w.T_lo, w.status)
     for st in states:
         st.close()
+
+
+def test_quad_double_server(ctx):
+    """A server with quad-double terms: each query (plain and displaced
+    states, marginal and full patterns) is evaluated alone by a worker, and
+    its result is bitwise the single quad-double query's."""
+    rng = np.random.default_rng(181)
+    m = 20
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.3, 0.8, m))
+    mean = gi.random_mean(m, rng, 0.3)
+    states = [ctx.state(cov), ctx.state(cov, mean=mean)]
+    qs = []
+    for i in range(12):
+        c = gi.random_click_set(m, int(rng.integers(0, 9)), rng)
+        qs.append((i % 2, gi.full_pattern(m, c) if i % 3 else gi.marginal_pattern(m, c)))
+    with tg.Server(ctx, workers=3, prec="qd") as srv:
+        tickets = [srv.submit(states[s], p) for s, p in qs]
+        got = [srv.wait(t)[0] for t in tickets]
+    for (s, p), g in zip(qs, got):
+        w = ctx.probability(cov, p, prec="qd") if s == 0 else ctx.probability_displaced(cov, mean, p, prec="qd")
+        assert (g.p, g.p_lo, g.T, g.T_lo, g.prec_used) == (w.p, w.p_lo, w.T, w.T_lo, tg.PREC_QD)
+    for st in states:
+        st.close()
