@@ -222,9 +222,9 @@ void tor_state_destroy(tor_state *st);
  * h = K mu and mu^T K mu (double-double); its full patterns are the
  * information-form sums of [0, h_C; h_C, G] (each pivot's factor carries
  * exp(+|w|^2/2)): p = (-1)^n det(sigma_Q)^-1/2 exp(-mu^T K mu / 2) T_h(G),
- * binary64 or double-double terms, in tor_batch and the server (not in
- * tor_batch_async; their quad-double queries take the per-query
- * conditioning route).  Errors:
+ * in tor_batch and the server (not in tor_batch_async); quad-double terms
+ * take this route from a quad-double inverse (h then in quad-double too),
+ * else the per-query conditioning.  Errors:
  * TOR_EINVAL (NULL, bad prec), TOR_ETOOBIG (m > 2048), TOR_ENOMEM,
  * TOR_ENOTPD (a non-positive pivot; a previous inverse is kept).  Not
  * thread-safe against other calls on the state (call it before submitting

@@ -135,6 +135,7 @@ struct tor_state {
     // displaced states: h = sigma_Q^-1 mu (2m words), mu^T sigma_Q^-1 mu and
     // det(sigma_Q)^-1/2 exp(-mu^T sigma_Q^-1 mu / 2)
     std::vector<dd> inv_h;
+    std::vector<qd> inv_h_q;  // h in quad-double words (quad-double inverse)
     dd mu_k_mu = {0.0, 0.0};
     dd det_rsqrt_mean = {1.0, 0.0};
     DevBuf dinv;  // device copy of the inverse in double-double words for tor_batch_async (first use)
@@ -1203,14 +1204,15 @@ tor_status gpu_sum_qd(tor_ctx *ctx, const std::vector<qd> &packed, int n, SumOut
     // displaced trees: seven-mode tasks (the eight-mode working set with the
     // mean row needs 56 KB of LDS, two workgroups per CU)
     const int J = std::min(n, D ? TOR_QD_TASK_MAX - 1 : TOR_QD_TASK_MAX), G = n - J;
+    const int mrows = MR(D);  // D = -1 (information form) has the displaced layout
     const long long nt = 1LL << G;
     const size_t es = sizeof(qd);
-    // pool: root slot, then per level 2^d child slots of EN(n - d - 1, D) + 1 words
+    // pool: root slot, then per level 2^d child slots of EN(n - d - 1, MR(D)) + 1 words
     std::vector<unsigned long long> child_base(G);
-    unsigned long long words = 1 + (unsigned long long)EN(n, D);
+    unsigned long long words = 1 + (unsigned long long)EN(n, mrows);
     for (int d = 0; d < G; d++) {
         child_base[d] = words;
-        words += (1ULL << d) * (unsigned long long)(EN(n - d - 1, D) + 1);
+        words += (1ULL << d) * (unsigned long long)(EN(n - d - 1, mrows) + 1);
     }
     // reduction stages over partials (stage outputs one after another in partB)
     std::vector<ReduceJobQ> red;
@@ -1258,7 +1260,7 @@ tor_status gpu_sum_qd(tor_ctx *ctx, const std::vector<qd> &packed, int n, SumOut
     const NodeDesc root{1, 1.0, 0.0, 1.0};  // the matrix starts after the coefficient word
     std::memcpy(hj.data() + off_root, &root, sizeof root);
     for (int d = 0; d < G; d++) {
-        ExpandJob job{level_ptr(d), level_ptr(d + 1), child_base[d], n - d, D};
+        ExpandJob job{level_ptr(d), level_ptr(d + 1), child_base[d], n - d, mrows};
         std::memcpy(hj.data() + off_exp + d * sizeof(ExpandJob), &job, sizeof job);
     }
     const WaveJob wj{level_ptr(G), (Partial *)partA, 0};
@@ -1268,9 +1270,9 @@ tor_status gpu_sum_qd(tor_ctx *ctx, const std::vector<qd> &packed, int n, SumOut
         std::memcpy(hj.data() + off_red + k * sizeof(ReduceJobQ), &job, sizeof job);
     }
     // root slot: coefficient 1, then the matrix
-    std::vector<qd> root_words(1 + (size_t)EN(n, D));
+    std::vector<qd> root_words(1 + (size_t)EN(n, mrows));
     root_words[0] = qd_from(1.0);
-    for (long long e = 0; e < EN(n, D); e++) root_words[1 + (size_t)e] = packed[(size_t)e];
+    for (long long e = 0; e < EN(n, mrows); e++) root_words[1 + (size_t)e] = packed[(size_t)e];
     hipStream_t st = ctx->stream;
     HIP_TRY(hipMemcpyAsync(ctx->pool.p, root_words.data(), root_words.size() * es, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dj, hj.data(), job_bytes, hipMemcpyHostToDevice, st));
@@ -1414,7 +1416,38 @@ tor_status probability_qd(tor_ctx *ctx, const double *cov, int m, const int8_t *
 // the packed matrix with its mean row, conditioned in qd when the pattern has
 // no-click modes, then the qd tree with the pivots' overlap factors.
 tor_status probability_qd_disp(tor_ctx *ctx, const double *cov, const double *mean, int m, const int8_t *pattern,
-                               double tol, tor_result *out) {
+                               double tol, tor_result *out, const tor_state *st = nullptr) {
+    if (st && st->inv_prec == TOR_PREC_QD && pattern && is_full_pattern(pattern, m)) {
+        // inverted state: the information-form tree over [0, h_C; h_C, G] in qd
+        Reduced red;
+        tor_status s = reduce_pattern_jacobi_disp(st, pattern, red);  // the dd factors
+        if (s) return s;
+        std::vector<int> C;
+        for (int i = 0; i < m; i++)
+            if (pattern[i] == 1) C.push_back(i);
+        const int dc = 2 * red.n;
+        std::vector<qd> sigc((size_t)EN(red.n, 1), qd_from(0.0));
+        for (int a = 0; a < dc; a++) {
+            const int ga = 2 * C[a / 2] + (a & 1);
+            sigc[(size_t)pidx(a + 1, 0)] = st->inv_h_q[ga];
+            for (int b = 0; b <= a; b++)
+                sigc[(size_t)pidx(a + 1, b + 1)] = st->inv_q[(size_t)pidx(ga, 2 * C[b / 2] + (b & 1))];
+        }
+        Prepared p;
+        s = prepare_reduced(red, p);  // log det Sigma_C, quad = h_C^T G^-1 h_C, tree kind -1
+        if (s) return s;
+        SumOut so;
+        s = gpu_sum_qd(ctx, sigc, red.n, so, -1);
+        if (s) return s;
+        if (!std::isfinite(so.T.hi) || !std::isfinite(so.A)) {
+            std::memset(out, 0, sizeof *out);
+            out->status = TOR_ENOTPD;
+            return fail(TOR_ENOTPD, "a Schur pivot was not positive (non-physical or near-singular covariance)");
+        }
+        if (!(tol > 0.0)) tol = 1e-10;
+        finalize(p, so, TOR_PREC_QD, tol, out);
+        return out->status;
+    }
     Reduced red;
     tor_status s = reduce_pattern_disp(cov, mean, m, pattern, red);
     if (s) return s;
@@ -1811,20 +1844,35 @@ tor_status tor_state_invert(tor_state *st, tor_prec prec) {
     st->det_rsqrt = dd_make(acc[0], acc[1]);
     st->log_det_sigq = -2.0 * acc[2];
     std::vector<dd>().swap(st->inv_h);
+    std::vector<qd>().swap(st->inv_h_q);
     st->mu_k_mu = dd_from(0.0);
     st->det_rsqrt_mean = st->det_rsqrt;
-    if (!st->mean.empty()) {  // h = K mu and mu^T K mu in double-double
+    if (!st->mean.empty() && q) {  // h = K mu and mu^T K mu in quad-double
+        st->inv_h_q.assign(d, qd_from(0.0));
+        st->inv_h.assign(d, dd_from(0.0));
+        qd mkm = qd_from(0.0);
+        for (int a = 0; a < d; a++) {
+            qd s = qd_from(0.0);
+            for (int b = 0; b < d; b++)
+                s = qd_add(s, qd_mul_d(st->inv_q[(size_t)(a >= b ? pidx(a, b) : pidx(b, a))], st->mean[b]));
+            st->inv_h_q[a] = s;
+            st->inv_h[a] = qd_to_dd(s);
+            mkm = qd_add(mkm, qd_mul_d(s, st->mean[a]));
+        }
+        st->mu_k_mu = qd_to_dd(mkm);
+    } else if (!st->mean.empty()) {  // h = K mu and mu^T K mu in double-double
         st->inv_h.assign(d, dd_from(0.0));
         for (int a = 0; a < d; a++) {
             dd s = dd_from(0.0);
             for (int b = 0; b < d; b++) {
                 const size_t e = (size_t)(a >= b ? pidx(a, b) : pidx(b, a));
-                const dd kab = q ? qd_to_dd(st->inv_q[e]) : st->inv[e];
-                s = dd_add(s, dd_mul_d(kab, st->mean[b]));
+                s = dd_add(s, dd_mul_d(st->inv[e], st->mean[b]));
             }
             st->inv_h[a] = s;
             st->mu_k_mu = dd_add(st->mu_k_mu, dd_mul_d(s, st->mean[a]));
         }
+    }
+    if (!st->mean.empty()) {
         const dd hm = dd_make(-0.5 * st->mu_k_mu.hi, -0.5 * st->mu_k_mu.lo);
         st->det_rsqrt_mean = dd_mul(st->det_rsqrt, dd_exp(hm));
     }
@@ -1845,7 +1893,8 @@ tor_status tor_batch(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t
             const int8_t *pat = patterns + (size_t)q * st->m;
             tor_status s = st->mean.empty()
                                ? probability_qd(ctx, st->cov.data(), st->m, pat, tol, &out[q], st)
-                               : probability_qd_disp(ctx, st->cov.data(), st->mean.data(), st->m, pat, tol, &out[q]);
+                               : probability_qd_disp(ctx, st->cov.data(), st->mean.data(), st->m, pat, tol, &out[q],
+                                                     st);
             if (s < 0) {
                 std::memset(&out[q], 0, sizeof out[q]);
                 out[q].status = s;
@@ -2692,7 +2741,7 @@ void server_worker(tor_server *S, int w) {
                 tor_status s = st->mean.empty()
                                    ? probability_qd(ctx, st->cov.data(), st->m, pat, S->opts.tol, &out[i], st)
                                    : probability_qd_disp(ctx, st->cov.data(), st->mean.data(), st->m, pat,
-                                                         S->opts.tol, &out[i]);
+                                                         S->opts.tol, &out[i], st);
                 if (s < 0) {
                     std::memset(&out[i], 0, sizeof out[i]);
                     out[i].status = s;

@@ -8,7 +8,9 @@
 // The path coefficient of a node lives in its pool slot, one word before the
 // packed matrix, so descriptors keep the layout of the other tiers.  D = 1: a
 // displaced state, the packed matrices carry the mean row first (the pivots'
-// overlap factors exp(-|w|^2 / 2) by the quad-double exp).
+// overlap factors exp(-|w|^2 / 2) by the quad-double exp); D = -1: the
+// information form of an inverted displaced state's full patterns (the first
+// row holds sigma_Q^-1 mu, the factors are exp(+|w|^2 / 2)).
 #include <hip/hip_runtime.h>
 
 #include "dd.hpp"
@@ -220,6 +222,7 @@ static hipError_t launch_qd_D(int J, const WaveJob *jobs, int njobs, long long t
 
 hipError_t tor_launch_wave_qd(int J, const WaveJob *jobs, int njobs, long long total, const void *pool, int grid_cap,
                               hipStream_t st, int disp) {
+    if (disp < 0) return tor::launch_qd_D<-1>(J, jobs, njobs, total, pool, grid_cap, st);
     return disp ? tor::launch_qd_D<1>(J, jobs, njobs, total, pool, grid_cap, st)
                 : tor::launch_qd_D<0>(J, jobs, njobs, total, pool, grid_cap, st);
 }
@@ -231,7 +234,10 @@ hipError_t tor_launch_expand_qd(const ExpandJob *jobs, int njobs, int log2npar, 
     const long long g = blocks < grid_cap ? blocks : grid_cap;
     if (g < 1) return hipSuccess;
     (void)hipGetLastError();  // report only this launch's error
-    if (disp)
+    if (disp < 0)
+        hipLaunchKernelGGL(tor::expand_kernel_qd<-1>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
+                           (qd *)pool);
+    else if (disp)
         hipLaunchKernelGGL(tor::expand_kernel_qd<1>, dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
                            (qd *)pool);
     else

@@ -256,6 +256,44 @@ def test_displaced_full_patterns_inverse(ctx, prec):
     inv.close()
 
 
+def test_displaced_inverse_quad_double(ctx):
+    """Quad-double full patterns of a displaced state inverted in quad-double:
+    the information-form tree over [0, h_C; h_C, G] with h = K mu in qd,
+    against the per-query qd route and the oracle, and weak coherent states
+    (R ~ 1e40) against their exact product."""
+    import mpmath as mp
+    mp.mp.dps = 80
+    m = 16
+    cov, _, rng = _state(m, 160, 0.3, 0.7)
+    mean = gi.random_mean(m, rng, 0.4)
+    inv = ctx.state(cov, mean=mean).invert("qd")
+    pats = np.stack([np.zeros(m, np.int8)] + [gi.full_pattern(m, gi.random_click_set(m, n, rng)) for n in (2, 6, 9)])
+    got, _ = ctx.batch(inv, pats, prec="qd")
+    for pat, g in zip(pats, got):
+        w = ctx.probability_displaced(cov, mean, pat, prec="qd")
+        o = oracle.formP_mean(cov, mean, pat)
+        assert g.prec_used == tg.PREC_QD
+        assert _rel(_mp(g), _mp(w)) <= 1e-28
+        assert _rel(_mp(g), _orc(o)) <= max(1e-28, 1e-33 * o.cancel_ratio)
+    inv.close()
+    m, n = 30, 12
+    rng = np.random.default_rng(161)
+    clicks = sorted(rng.choice(m, n, replace=False).tolist())
+    beta = 0.2 * (rng.standard_normal(m) + 1j * rng.standard_normal(m))
+    beta[clicks] = np.sqrt(1e-3) * np.exp(2j * np.pi * rng.random(n))
+    cov, mean = 0.5 * np.eye(2 * m), gi.coherent_mean(beta)
+    st = ctx.state(cov, mean=mean).invert("qd")
+    pat = gi.full_pattern(m, clicks)
+    r, _ = ctx.batch(st, pat[None, :], prec="qd")
+    want = mp.mpf(1)
+    for i in range(m):
+        a2 = (mp.mpf(float(mean[2 * i])) ** 2 + mp.mpf(float(mean[2 * i + 1])) ** 2) / 2
+        want *= (1 - mp.exp(-a2)) if pat[i] == 1 else mp.exp(-a2)
+    assert r[0].cancel_ratio > 1e35
+    assert _rel(_mp(r[0]), want) <= 1e-15 and _rel(_mp(r[0]), want) <= r[0].rel_err_bound
+    st.close()
+
+
 def test_displaced_inverse_coherent_closed_form(ctx):
     """Coherent states through an interferometer (beta = U alpha) on an
     inverted state, all 40 modes observed: prod_clicks (1 - e^{-|beta|^2})
@@ -331,11 +369,12 @@ def test_invert_errors(ctx):
     cov, _, rng = _state(m, 155)
     mean = gi.random_mean(m, rng, 0.3)
     disp = ctx.state(cov, mean=mean).invert("qd")  # displaced: allowed
-    # quad-double queries of a displaced state take the per-query conditioning
+    # quad-double full patterns of a state inverted in qd take the
+    # information-form route: the per-query route's value to the output words
     fp = gi.full_pattern(m, [1])
     r, _ = ctx.batch(disp, fp[None, :], prec="qd")
     w = ctx.probability_displaced(cov, mean, fp, prec="qd")
-    assert (r[0].p, r[0].p_lo, r[0].prec_used) == (w.p, w.p_lo, tg.PREC_QD)
+    assert r[0].prec_used == tg.PREC_QD and _rel(_mp(r[0]), _mp(w)) <= 1e-29
     disp.close()
     bad = ctx.state(-np.eye(2 * m))  # sigma_Q = -I/2: not positive definite
     with pytest.raises(tg.TorError) as e:
