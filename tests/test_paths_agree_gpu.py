@@ -89,3 +89,44 @@ def test_paths_agree(ctx, m, seed):
         assert err <= 1e-10 and err <= b.rel_err_bound + 1e-28, (pat, err, b.rel_err_bound)
     st.close()
     inv.close()
+
+
+@pytest.mark.parametrize("m,seed", [(10, 173), (40, 174)])
+def test_displaced_paths_agree(ctx, m, seed):
+    """The same for a displaced state: tor_probability_displaced, tor_batch on
+    the state, the server and the async batch (marginal patterns) agree
+    bitwise; the inverted state (information-form trees, dd and qd) within the
+    bounds; every result against the oracle's definition route with means."""
+    import torch
+    rng = np.random.default_rng(seed)
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.2, 0.8, m))
+    mean = gi.random_mean(m, rng, 0.4)
+    pats = _patterns(m, rng, 16)
+    st = ctx.state(cov, mean=mean)
+    inv = ctx.state(cov, mean=mean).invert("qd")
+    batch, _ = ctx.batch(st, pats, prec="dd")
+    on_inv, _ = ctx.batch(inv, pats, prec="dd")
+    on_inv_qd, _ = ctx.batch(inv, pats, prec="qd")
+    srv = tg.Server(ctx, workers=2, prec="dd")
+    served = [srv.wait(t)[0] for t in [srv.submit(st, p) for p in pats]]
+    srv.stop()
+    d_out = ctx.batch_async(st, torch.from_numpy(pats).to("cuda"), prec="dd")
+    torch.cuda.synchronize()
+    asyn = tg.results_from_device(d_out)
+    for pat, b, j, jq, s, a in zip(pats, batch, on_inv, on_inv_qd, served, asyn):
+        single = ctx.probability_displaced(cov, mean, pat, prec="dd")
+        key = lambda r: (r.p, r.p_lo, r.T, r.T_lo, r.abs_sum, r.status)
+        assert key(single) == key(b) == key(s)
+        if not (pat == 0).any():
+            assert (a.p, a.p_lo, a.T, a.T_lo) == (b.p, b.p_lo, b.T, b.T_lo)
+        else:
+            assert a.status == tg.TOR_EINVAL
+        pb = _mp(b.p, b.p_lo)
+        assert _rel(_mp(j.p, j.p_lo), pb) <= j.rel_err_bound + b.rel_err_bound + 1e-27
+        assert _rel(_mp(jq.p, jq.p_lo), pb) <= b.rel_err_bound + 1e-27
+        if int((pat >= 0).sum()) <= 14:  # the definition route: 2^n Cholesky factorisations
+            o = oracle.formP_mean(cov, mean, pat)
+            err = _rel(pb, _mp(o.p, o.p_lo))
+            assert err <= 1e-10 and err <= b.rel_err_bound + 1e-27, (pat, err, b.rel_err_bound)
+    st.close()
+    inv.close()
