@@ -222,7 +222,7 @@ void tor_state_destroy(tor_state *st);
  * h = K mu and mu^T K mu (double-double); its full patterns are the
  * information-form sums of [0, h_C; h_C, G] (each pivot's factor carries
  * exp(+|w|^2/2)): p = (-1)^n det(sigma_Q)^-1/2 exp(-mu^T K mu / 2) T_h(G),
- * in tor_batch and the server (not in tor_batch_async); quad-double terms
+ * in tor_batch, the server and tor_batch_async; quad-double terms
  * take this route from a quad-double inverse (h then in quad-double too),
  * else the per-query conditioning.  Errors:
  * TOR_EINVAL (NULL, bad prec), TOR_ETOOBIG (m > 2048), TOR_ENOMEM,
@@ -263,7 +263,10 @@ tor_status tor_batch_displaced(tor_ctx *ctx, const tor_state *st, const double *
  * gathered on the device and p = (-1)^n det(sigma_Q)^-1/2 T(G) is bitwise
  * tor_batch's; the reported T, abs_sum, cancel_ratio, rel_err_bound and tor
  * of such a query are rescaled to Sigma_C with a binary64 det(G)^1/2 (relative
- * difference from tor_batch's ~1e-15).  Any other query with a no-click mode
+ * difference from tor_batch's ~1e-15).  On an inverted displaced state the
+ * full patterns are the information-form trees of [0, h_C; h_C, G] (p as in
+ * tor_state_invert, bitwise tor_batch's) and its marginal patterns the
+ * displaced trees, both kinds in one call.  Any other query with a no-click mode
  * (0), or with a bad entry, gets status TOR_EINVAL in its result (per-query
  * conditioning needs host planning: use tor_batch), more than 32 clicks
  * TOR_ETOOBIG.
@@ -272,7 +275,7 @@ tor_status tor_batch_displaced(tor_ctx *ctx, const tor_state *st, const double *
  * workspace whose tree pool holds TOR_OPT_ASYNC_POOL bytes (default 4 GiB);
  * queries are admitted in order while the trees up to them fit, later ones
  * get TOR_ENOMEM.  The first call on a state copies its covariance (and the
- * mean of a displaced state, or the inverse of an inverted state) to the
+ * mean of a displaced state, or the inverse (and h) of an inverted state) to the
  * device (synchronously, once).  The workspace belongs to the context: calls
  * on one context must be ordered (same stream, or the caller waits).
  * Returns TOR_OK once enqueued; argument errors (NULL pointers, nq < 0, bad

@@ -138,7 +138,8 @@ struct tor_state {
     std::vector<qd> inv_h_q;  // h in quad-double words (quad-double inverse)
     dd mu_k_mu = {0.0, 0.0};
     dd det_rsqrt_mean = {1.0, 0.0};
-    DevBuf dinv;  // device copy of the inverse in double-double words for tor_batch_async (first use)
+    DevBuf dinv;   // device copy of the inverse in double-double words for tor_batch_async (first use)
+    DevBuf dinvh;  // device copy of h (displaced states), likewise
     std::mutex dev_mu;  // guards the creation of the device copies (dcov, dmean)
 };
 
@@ -1773,11 +1774,12 @@ tor_status tor_state_create_displaced(tor_ctx *ctx, const double *cov, const dou
 
 void tor_state_destroy(tor_state *st) {
     if (!st) return;
-    if (st->dcov.p || st->dmean.p || st->dinv.p) {
+    if (st->dcov.p || st->dmean.p || st->dinv.p || st->dinvh.p) {
         (void)hipSetDevice(st->device);
         st->dcov.release();
         st->dmean.release();
         st->dinv.release();
+        st->dinvh.release();
         (void)hipGetLastError();  // leave no error for the next checked call
     }
     delete st;
@@ -1829,7 +1831,8 @@ tor_status tor_state_invert(tor_state *st, tor_prec prec) {
         return fail(TOR_ENOTPD, "a pivot of sigma_Q was not positive");
     // the sweeps leave -sigma_Q^-1
     st->inv_prec = 0;
-    st->dinv.release();  // a device copy of an earlier inverse is stale
+    st->dinv.release();  // device copies of an earlier inverse are stale
+    st->dinvh.release();
     std::vector<dd>().swap(st->inv);
     std::vector<qd>().swap(st->inv_q);
     if (q) {
@@ -2009,8 +2012,11 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     P.is_dd = use_dd;
     P.D = D;
     P.mean = D ? (const double *)ms->dmean.p : nullptr;
-    // full patterns of an inverted (zero-mean) state: the inverse on the device
-    if (st->inv_prec && !D) {
+    // full patterns of an inverted state: the inverse (and h = K mu) on the
+    // device; a displaced state's full patterns are a second tree kind (the
+    // information form) beside its displaced trees
+    P.nkinds = 1;
+    if (st->inv_prec) {
         const size_t ent = (size_t)E(m);
         std::lock_guard<std::mutex> lk(ms->dev_mu);
         if (!ms->dinv.p) {
@@ -2020,10 +2026,18 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
                 return fail(TOR_ENOMEM, "device copy of the inverse failed");
             HIP_TRY(hipMemcpy(ms->dinv.p, h.data(), ent * sizeof(dd), hipMemcpyHostToDevice));
         }
+        if (D && !ms->dinvh.p) {
+            if (ms->dinvh.ensure(st->inv_h.size() * sizeof(dd)) != hipSuccess)
+                return fail(TOR_ENOMEM, "device copy of h failed");
+            HIP_TRY(hipMemcpy(ms->dinvh.p, st->inv_h.data(), st->inv_h.size() * sizeof(dd), hipMemcpyHostToDevice));
+        }
         P.inv = ms->dinv.p;
-        P.det_rsqrt_hi = st->det_rsqrt.hi;
-        P.det_rsqrt_lo = st->det_rsqrt.lo;
+        P.inv_h = D ? ms->dinvh.p : nullptr;
+        P.det_rsqrt_hi = st->det_rsqrt_mean.hi;  // = det_rsqrt for a zero-mean state
+        P.det_rsqrt_lo = st->det_rsqrt_mean.lo;
         P.log_det_sigq = st->log_det_sigq;
+        P.mu_k_mu = st->mu_k_mu.hi + st->mu_k_mu.lo;
+        P.nkinds = D ? 2 : 1;
     }
     const int nmax = std::min(TOR_MAX_CLICKS, m);
     int gcap = 0, jmax = 1;
@@ -2059,10 +2073,11 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     const size_t o_dB = take((size_t)P.desc_cap * sizeof(NodeDesc));
     const size_t o_pA = take((size_t)P.desc_cap * sizeof(Partial));
     const size_t o_pB = take((size_t)P.pb_cap * sizeof(Partial));
-    const size_t o_ej = take((size_t)std::max(gcap, 1) * nq * sizeof(ExpandJob));
-    const size_t o_wj = take((size_t)(TOR_TASK_MAX + 1) * nq * sizeof(WaveJob));
+    const size_t o_ej = take((size_t)P.nkinds * std::max(gcap, 1) * nq * sizeof(ExpandJob));
+    const size_t o_wj = take((size_t)P.nkinds * (TOR_TASK_MAX + 1) * nq * sizeof(WaveJob));
     const size_t o_rj = take((size_t)TOR_ASYNC_STAGES * nq * sizeof(ReduceJob));
-    const size_t o_dims = take((size_t)(gcap + TOR_TASK_MAX + 1 + TOR_ASYNC_STAGES) * sizeof(LaunchDims));
+    const int stride = gcap + TOR_TASK_MAX + 1;  // launch dimensions per tree kind
+    const size_t o_dims = take(((size_t)P.nkinds * stride + TOR_ASYNC_STAGES) * sizeof(LaunchDims));
     const size_t abytes = off, pbytes = (size_t)P.pool_cap * es;
     if (abytes + pbytes + cov_bytes > ctx->mem_budget)
         return fail(TOR_ENOMEM, "async workspace of %.2f GB exceeds the memory budget", (abytes + pbytes) / 1e9);
@@ -2082,24 +2097,28 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     P.dims = (LaunchDims *)(b + o_dims);
     // scan, plan, roots; then the tree launches with device-side dimensions
     HIP_TRY(tor_launch_async_prologue(d_patterns, (const double *)ms->dcov.p, P, hs));
-    for (int d = 0; d < gcap; d++) {
-        const long long bound = std::min<long long>(1LL << 20, ((long long)nq << d) / 4 + 1);
-        HIP_TRY(tor_launch_expand(use_dd, P.exp_jobs + (size_t)d * nq, 0, d, P.pool, (int)bound, hs, P.dims + d, D));
-    }
-    for (int J = jmax; J >= 1; J--) {
-        if (!jused[J]) continue;
-        const long long bound = std::min<long long>(ctx->wave_grid, (long long)nq * max_tasks[J]);
-        HIP_TRY(tor_launch_wave(use_dd, J, P.wave_jobs + (size_t)J * nq, 0, 0, P.pool, (int)bound, hs,
-                                P.dims + gcap + J, D));
+    for (int k = 0; k < P.nkinds; k++) {  // kind 1: the information-form trees (tree kind -1)
+        const int Dk = k ? -1 : D;
+        for (int d = 0; d < gcap; d++) {
+            const long long bound = std::min<long long>(1LL << 20, ((long long)nq << d) / 4 + 1);
+            HIP_TRY(tor_launch_expand(use_dd, P.exp_jobs + ((size_t)k * gcap + d) * nq, 0, d, P.pool, (int)bound,
+                                      hs, P.dims + k * stride + d, Dk));
+        }
+        for (int J = jmax; J >= 1; J--) {
+            if (!jused[J]) continue;
+            const long long bound = std::min<long long>(ctx->wave_grid, (long long)nq * max_tasks[J]);
+            HIP_TRY(tor_launch_wave(use_dd, J, P.wave_jobs + ((size_t)k * (TOR_TASK_MAX + 1) + J) * nq, 0, 0, P.pool,
+                                    (int)bound, hs, P.dims + k * stride + gcap + J, Dk));
+        }
     }
     long long c = nt_max;
     for (int s = 0; s < TOR_ASYNC_STAGES && c > 1; s++) {
         c = (c + TOR_REDUCE_CHUNK - 1) / TOR_REDUCE_CHUNK;
         const long long bound = std::min<long long>(1LL << 20, (long long)nq * c);
-        HIP_TRY(tor_launch_reduce(P.red_jobs + (size_t)s * nq, 0, bound, hs, P.dims + gcap + TOR_TASK_MAX + 1 + s));
+        HIP_TRY(tor_launch_reduce(P.red_jobs + (size_t)s * nq, 0, bound, hs, P.dims + P.nkinds * stride + s));
     }
     HIP_TRY(tor_launch_async_finalize(P, tol, used, d_out, hs));
-    ctx->stats.expand_launches += gcap;
+    ctx->stats.expand_launches += (int64_t)gcap * P.nkinds;
     return TOR_OK;
 }
 

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
         Q.log_det = 0.0;
         Q.quad = 0.0;
         Q.jscale = 1.0;
-        Q.log_pvac = Q.jac ? -0.5 * P.log_det_sigq : 0.0;
+        Q.log_pvac = Q.jac ? -0.5 * (P.log_det_sigq + P.mu_k_mu) : 0.0;
         if (Q.status != TOR_OK || Q.n == 0) continue;
         const int n = Q.n;
         const int J = min(n, P.J_of_n[n]);
@@ -187,13 +187,18 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
     }
     __syncthreads();
     auto live = [&](int q) { return Qs[q].status == TOR_OK && Qs[q].n > 0; };
+    // tree kind of a query: 1 for the information-form trees of an inverted
+    // displaced state's full patterns, else 0; the tables are kind-major
+    auto kind = [&](int q) { return P.nkinds > 1 && Qs[q].jac ? 1 : 0; };
+    const int stride = P.gcap + TOR_TASK_MAX + 1;  // launch dimensions per kind
+    for (int k = 0; k < P.nkinds; k++) {
     // HBM levels: depth d expands every tree with more than d levels
     for (int d = 0; d < P.gcap; d++) {
         const long long cnt = scan_queries(
-            nq, [&](int q) { return (long long)(live(q) && Qs[q].G > d); },
+            nq, [&](int q) { return (long long)(live(q) && kind(q) == k && Qs[q].G > d); },
             [&](int q, long long pos) {
                 const AsyncQuery &Q = Qs[q];
-                if (!(live(q) && Q.G > d)) return;
+                if (!(live(q) && kind(q) == k && Q.G > d)) return;
                 long long base = Q.pool_off + EN(Q.n, P.D);
                 for (int k = 0; k < d; k++) base += (1LL << k) * (long long)EN(Q.n - k - 1, P.D);
                 ExpandJob j;
@@ -202,17 +207,17 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
                 j.child_base = (unsigned long long)base;
                 j.r = Q.n - d;
                 j.d = P.D;
-                P.exp_jobs[(size_t)d * nq + pos] = j;
+                P.exp_jobs[((size_t)k * P.gcap + d) * nq + pos] = j;
             },
             lds);
         if (threadIdx.x == 0) {
-            P.dims[d].njobs = cnt;
-            P.dims[d].total = cnt << d;
+            P.dims[k * stride + d].njobs = cnt;
+            P.dims[k * stride + d].total = cnt << d;
         }
     }
     // wave tier: one launch per task size (descending J, query order within)
     for (int J = P.jmax; J >= 1; J--) {
-        auto in = [&](int q) { return live(q) && Qs[q].J == J; };
+        auto in = [&](int q) { return live(q) && kind(q) == k && Qs[q].J == J; };
         const long long cnt = scan_queries(
             nq, [&](int q) { return (long long)in(q); }, [&](int q, long long pos) { Qs[q].slot = pos; }, lds);
         const long long tot = scan_queries(
@@ -224,14 +229,15 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
                 w.tasks = level_ptr(P, q, Q, Q.G);
                 w.out = P.partA + Q.desc_off;
                 w.begin = begin;
-                P.wave_jobs[(size_t)J * nq + Q.slot] = w;
+                P.wave_jobs[((size_t)k * (TOR_TASK_MAX + 1) + J) * nq + Q.slot] = w;
             },
             lds);
         if (threadIdx.x == 0) {
-            P.dims[P.gcap + J].njobs = cnt;
-            P.dims[P.gcap + J].total = tot;
+            P.dims[k * stride + P.gcap + J].njobs = cnt;
+            P.dims[k * stride + P.gcap + J].total = tot;
         }
     }
+    }  // kinds
     // reduction stages: stage s sums chunks of stage s - 1 (stage 0: the tasks)
     for (int s = 0; s < TOR_ASYNC_STAGES; s++) {
         auto in = [&](int q) { return live(q) && Qs[q].nstage > s; };
@@ -257,8 +263,8 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
             },
             lds);
         if (threadIdx.x == 0) {
-            P.dims[P.gcap + TOR_TASK_MAX + 1 + s].njobs = cnt;
-            P.dims[P.gcap + TOR_TASK_MAX + 1 + s].total = blocks;
+            P.dims[P.nkinds * stride + s].njobs = cnt;
+            P.dims[P.nkinds * stride + s].total = blocks;
         }
     }
 }
@@ -292,8 +298,11 @@ __global__ __launch_bounds__(64) void async_gather_kernel(const double *__restri
         for (int e = lane; e < EN(n, o); e += 64) {
             int a, b;
             unpack(e, a, b);
-            if (o && b == 0) {  // mean column (0 at the corner)
-                root[e] = from_pair<S>(a == 0 ? 0.0 : P.mean[2 * Q.C[(a - 1) >> 1] + ((a - 1) & 1)], 0.0);
+            if (o && b == 0) {  // mean column (0 at the corner); h = K mu for the information form
+                const int ga = a == 0 ? 0 : 2 * Q.C[(a - 1) >> 1] + ((a - 1) & 1);
+                if (a == 0) root[e] = from_pair<S>(0.0, 0.0);
+                else if (Q.jac) root[e] = from_pair<S>(((const dd *)P.inv_h)[ga].hi, ((const dd *)P.inv_h)[ga].lo);
+                else root[e] = from_pair<S>(P.mean[ga], 0.0);
                 continue;
             }
             a -= o;
@@ -334,19 +343,24 @@ __global__ __launch_bounds__(64) void async_gather_kernel(const double *__restri
         if (lane == 0) {
             Q.log_det = Q.jac ? -logdet : logdet;
             if (!ok) Q.status = TOR_ENOTPD;
-            if (Q.jac && ok) {
+            if (Q.jac && ok && !o) {
                 Q.jscale = ((n & 1) ? -1.0 : 1.0) * exp(0.5 * logdet);
                 Q.log_pvac = -0.5 * (P.log_det_sigq + logdet);
             }
-            if (o && ok) {  // z = L^-1 mu_C, quad = |z|^2 (forward solve, row order of the host)
+            if (o && ok) {  // z = L^-1 mu_C (h_C for the information form), quad = |z|^2
                 double quad = 0.0;
                 for (int a = 0; a < d; a++) {
-                    double v = P.mean[2 * Q.C[a >> 1] + (a & 1)];
+                    const int ga = 2 * Q.C[a >> 1] + (a & 1);
+                    double v = Q.jac ? ((const dd *)P.inv_h)[ga].hi + ((const dd *)P.inv_h)[ga].lo : P.mean[ga];
                     for (int t = 0; t < a; t++) v -= L[a][t] * z[t];
                     z[a] = v / L[a][a];
                     quad += z[a] * z[a];
                 }
                 Q.quad = quad;
+                if (Q.jac) {  // T(Sigma_C) = (-1)^n det(G)^1/2 exp(-quad / 2) T_h(G)
+                    Q.jscale = ((n & 1) ? -1.0 : 1.0) * exp(0.5 * logdet - 0.5 * quad);
+                    Q.log_pvac = -0.5 * (P.log_det_sigq + logdet) - 0.5 * P.mu_k_mu + 0.5 * quad;
+                }
             }
         }
         __syncthreads();

@@ -111,7 +111,12 @@ struct AsyncPlan {
     int D;               // 1: displaced state (mean row first in every packed matrix)
     const double *mean;  // displaced states: device copy of the mean (2m), else null
     const void *inv;     // inverted state: sigma_Q^-1 packed lower, double-double words; else null
-    double det_rsqrt_hi, det_rsqrt_lo, log_det_sigq;  // inverted state: det(sigma_Q)^-1/2, log det sigma_Q
+    const void *inv_h;   // inverted displaced state: h = sigma_Q^-1 mu (2m double-double words); else null
+    // inverted state: det(sigma_Q)^-1/2 (times exp(-mu^T sigma_Q^-1 mu / 2) when displaced),
+    // log det sigma_Q and mu^T sigma_Q^-1 mu
+    double det_rsqrt_hi, det_rsqrt_lo, log_det_sigq, mu_k_mu;
+    int nkinds;          // tree kinds in the batch: 2 when full patterns of an inverted displaced
+                         // state (information form, kind 1) join the displaced trees (kind 0)
     int J_of_n[TOR_MAX_N + 1];
     long long pool_cap, desc_cap, pb_cap;  // capacities (scalars, descriptors, partials)
     AsyncQuery *q;

@@ -209,6 +209,40 @@ def test_async_full_patterns(ctx, inv_prec, prec):
     st.close()
 
 
+@pytest.mark.parametrize("inv_prec,prec", [("dd", "dd"), ("dd", "f64"), ("qd", "dd")])
+def test_async_displaced_full_patterns(ctx, inv_prec, prec):
+    """tor_batch_async on an inverted displaced state: marginal patterns run
+    the displaced trees and full patterns the information-form trees, in one
+    call (two tree kinds); p bitwise tor_batch's, the other fields within
+    1e-13; partial patterns still rejected per query."""
+    import torch
+    m = 36
+    cov, _, rng = _state(m, 158, 0.3, 0.8)
+    mean = gi.random_mean(m, rng, 0.4)
+    st = ctx.state(cov, mean=mean).invert(inv_prec)
+    pats = [np.zeros(m, np.int8)]
+    for n in (1, 5, 10, 14):
+        c = gi.random_click_set(m, n, rng)
+        pats.append(gi.full_pattern(m, c))
+        pats.append(gi.marginal_pattern(m, c))
+    part = gi.full_pattern(m, [2, 9])
+    part[11] = -1
+    pats.append(part)
+    pats = np.stack(pats)
+    want, _ = ctx.batch(st, pats, prec=prec)
+    d_out = ctx.batch_async(st, torch.from_numpy(pats).to("cuda"), prec=prec)
+    torch.cuda.synchronize()
+    got = tg.results_from_device(d_out)
+    for pat, g, w in zip(pats, got, want):
+        if (pat == 0).any() and (pat == -1).any():
+            assert g.status == tg.TOR_EINVAL
+            continue
+        assert (g.p, g.p_lo, g.n_clicks, g.prec_used, g.status) == (w.p, w.p_lo, w.n_clicks, w.prec_used, w.status)
+        for f in ("T", "abs_sum", "cancel_ratio", "rel_err_bound", "tor", "log_p", "log_pvac_n"):
+            assert getattr(g, f) == pytest.approx(getattr(w, f), rel=1e-13, abs=1e-300), (f, int((pat == 1).sum()))
+    st.close()
+
+
 def _coherent(beta, pat):
     import mpmath as mp
     mp.mp.dps = 60

@@ -95,8 +95,8 @@ def test_paths_agree(ctx, m, seed):
 def test_displaced_paths_agree(ctx, m, seed):
     """The same for a displaced state: tor_probability_displaced, tor_batch on
     the state, the server and the async batch (marginal patterns) agree
-    bitwise; the inverted state (information-form trees, dd and qd) within the
-    bounds; every result against the oracle's definition route with means."""
+    bitwise; the inverted state (information-form trees, dd and qd, also
+    through the async batch) within the bounds; every result against the oracle's definition route with means."""
     import torch
     rng = np.random.default_rng(seed)
     cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.2, 0.8, m))
@@ -111,9 +111,11 @@ def test_displaced_paths_agree(ctx, m, seed):
     served = [srv.wait(t)[0] for t in [srv.submit(st, p) for p in pats]]
     srv.stop()
     d_out = ctx.batch_async(st, torch.from_numpy(pats).to("cuda"), prec="dd")
+    d_inv = ctx.batch_async(inv, torch.from_numpy(pats).to("cuda"), prec="dd")
     torch.cuda.synchronize()
     asyn = tg.results_from_device(d_out)
-    for pat, b, j, jq, s, a in zip(pats, batch, on_inv, on_inv_qd, served, asyn):
+    asyn_inv = tg.results_from_device(d_inv)
+    for pat, b, j, jq, s, a, ai in zip(pats, batch, on_inv, on_inv_qd, served, asyn, asyn_inv):
         single = ctx.probability_displaced(cov, mean, pat, prec="dd")
         key = lambda r: (r.p, r.p_lo, r.T, r.T_lo, r.abs_sum, r.status)
         assert key(single) == key(b) == key(s)
@@ -121,6 +123,10 @@ def test_displaced_paths_agree(ctx, m, seed):
             assert (a.p, a.p_lo, a.T, a.T_lo) == (b.p, b.p_lo, b.T, b.T_lo)
         else:
             assert a.status == tg.TOR_EINVAL
+        if (pat >= 0).all() or not (pat == 0).any():  # async on the inverted state
+            assert (ai.p, ai.p_lo) == (j.p, j.p_lo)
+        else:
+            assert ai.status == tg.TOR_EINVAL
         pb = _mp(b.p, b.p_lo)
         assert _rel(_mp(j.p, j.p_lo), pb) <= j.rel_err_bound + b.rel_err_bound + 1e-27
         assert _rel(_mp(jq.p, jq.p_lo), pb) <= b.rel_err_bound + 1e-27
