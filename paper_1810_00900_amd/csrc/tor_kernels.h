@@ -98,10 +98,13 @@ struct AsyncQuery {
     int final_buf;
     int nstage;
     double log_det;      // log det Sigma_C (binary64 Cholesky)
-    double quad;         // displaced states: mu_C^T Sigma_C^-1 mu_C (binary64), else 0
+    double quad;         // displaced states: mu_C^T Sigma_C^-1 mu_C, or h_C^T G^-1 h_C for the
+                         // information form (binary64); else 0
     int jac;             // full pattern on an inverted state: the tree sums G = sigma_Q^-1 over C
-    double jscale;       // jac: (-1)^n det(G)^1/2 (binary64), T(Sigma_C) = jscale T(G)
-    double log_pvac;     // jac: log P_vac(N) = -(log det sigma_Q + log det G) / 2; else 0
+    double jscale;       // jac: (-1)^n det(G)^1/2 (times exp(-quad / 2) when displaced, binary64),
+                         // T(Sigma_C) = jscale T(G)
+    double log_pvac;     // jac: log P_vac(N) = -(log det sigma_Q + log det G) / 2 (displaced:
+                         // - mu^T sigma_Q^-1 mu / 2 + quad / 2); else 0
     long long slot;      // planner scratch: position of the query's job in a table
     int C[TOR_MAX_N];    // clicked modes, ascending
 };
@@ -123,10 +126,10 @@ struct AsyncPlan {
     void *pool;
     NodeDesc *roots, *descA, *descB;
     Partial *partA, *partB;
-    ExpandJob *exp_jobs;   // [gcap][nq]
-    WaveJob *wave_jobs;    // [TOR_TASK_MAX + 1][nq]
+    ExpandJob *exp_jobs;   // [nkinds][gcap][nq]
+    WaveJob *wave_jobs;    // [nkinds][TOR_TASK_MAX + 1][nq]
     ReduceJob *red_jobs;   // [TOR_ASYNC_STAGES][nq]
-    LaunchDims *dims;      // expand [gcap], wave [TOR_TASK_MAX + 1], reduce [TOR_ASYNC_STAGES]
+    LaunchDims *dims;      // per kind: expand [gcap], wave [TOR_TASK_MAX + 1]; then reduce [TOR_ASYNC_STAGES]
 };
 
 hipError_t tor_launch_async_prologue(const int8_t *d_patterns, const double *d_cov, const AsyncPlan &P,

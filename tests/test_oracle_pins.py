@@ -235,6 +235,48 @@ def test_complementary_minor_route(oracle_lib):
         assert abs(got - want) <= 1e-28 * abs(want) * max(o.cancel_ratio, 1.0)
 
 
+def test_information_form_route(oracle_lib):
+    """The identity behind full patterns of an inverted displaced state: with
+    K = sigma_Q^-1, h = K mu, G = K[C], and Z the clicked modes left out of a
+    term, det sigma_Q[S] = det sigma_Q det K[Z] and
+    mu_S^T sigma_Q[S]^-1 mu_S = mu^T K mu - h_Z^T K[Z]^-1 h_Z, so
+    p(C, N) = (-1)^n det(sigma_Q)^-1/2 exp(-mu^T K mu / 2)
+              sum_Z (-1)^|Z| det(G[Z])^-1/2 exp(+h_Z^T G[Z]^-1 h_Z / 2).
+    Brute force in mpmath against the oracle's definition route with means."""
+    import mpmath as mp
+    mp.mp.dps = 60
+    rng = np.random.default_rng(161)
+    m = 6
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.3, 0.8, m))
+    mean = gi.random_mean(m, rng, 0.5)
+    d = 2 * m
+    sq = mp.matrix(d, d)
+    for a in range(d):
+        for b in range(d):
+            sq[a, b] = mp.mpf(float(cov[a, b])) + (mp.mpf(1) / 2 if a == b else 0)
+    mu = mp.matrix([mp.mpf(float(x)) for x in mean])
+    K = sq ** -1
+    h = K * mu
+    pre = mp.det(sq) ** (-mp.mpf(1) / 2) * mp.exp(-(mu.T * K * mu)[0] / 2)
+    for clicks in ([4], [1, 3], [0, 2, 5], list(range(m))):
+        pat = gi.full_pattern(m, clicks)
+        n = len(clicks)
+        rows = [2 * c + t for c in clicks for t in (0, 1)]
+        T = mp.mpf(0)
+        for mask in range(1 << n):
+            sub = [rows[2 * i + t] for i in range(n) if mask >> i & 1 for t in (0, 1)]
+            term = mp.mpf(1)
+            if sub:
+                Gz = mp.matrix([[K[a, b] for b in sub] for a in sub])
+                hz = mp.matrix([h[a] for a in sub])
+                term = mp.exp((hz.T * Gz ** -1 * hz)[0] / 2) / mp.sqrt(mp.det(Gz))
+            T += (-1) ** bin(mask).count("1") * term
+        want = (-1) ** n * pre * T
+        o = oracle.formP_mean(cov, mean, pat)
+        got = mp.mpf(o.p) + mp.mpf(o.p_lo)
+        assert abs(got - want) <= 1e-28 * abs(want) * max(o.cancel_ratio, 1.0), clicks
+
+
 def test_product_state_many_clicks(oracle_lib):
     """A product state with 14 clicks: heavy cancellation (R ~ 1e7+), closed
     form known, so binary128 accuracy is pinned at a size where FP64 fails."""
