@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
     // displaced state's full patterns, else 0; the tables are kind-major
     auto kind = [&](int q) { return P.nkinds > 1 && Qs[q].jac ? 1 : 0; };
     const int stride = P.gcap + TOR_TASK_MAX + 1;  // launch dimensions per kind
-    for (int k = 0; k < P.nkinds; k++) {
+    for (int k = 0; k < P.nkinds; k++) {  // a tree kind's expand and wave tables
     // HBM levels: depth d expands every tree with more than d levels
     for (int d = 0; d < P.gcap; d++) {
         const long long cnt = scan_queries(
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kPlanThreads) void async_plan_kernel(AsyncPlan P) {
                 const AsyncQuery &Q = Qs[q];
                 if (!(live(q) && kind(q) == k && Q.G > d)) return;
                 long long base = Q.pool_off + EN(Q.n, P.D);
-                for (int k = 0; k < d; k++) base += (1LL << k) * (long long)EN(Q.n - k - 1, P.D);
+                for (int t = 0; t < d; t++) base += (1LL << t) * (long long)EN(Q.n - t - 1, P.D);
                 ExpandJob j;
                 j.par = level_ptr(P, q, Q, d);
                 j.chi = level_ptr(P, q, Q, d + 1);
