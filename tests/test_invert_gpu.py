@@ -221,7 +221,7 @@ def test_async_displaced_full_patterns(ctx, inv_prec, prec):
     mean = gi.random_mean(m, rng, 0.4)
     st = ctx.state(cov, mean=mean).invert(inv_prec)
     pats = [np.zeros(m, np.int8)]
-    for n in (1, 5, 10, 14):
+    for n in (1, 5, 10, 14, 20, 24):
         c = gi.random_click_set(m, n, rng)
         pats.append(gi.full_pattern(m, c))
         pats.append(gi.marginal_pattern(m, c))
