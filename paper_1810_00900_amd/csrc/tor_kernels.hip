@@ -54,23 +54,41 @@ namespace tor {
 // keeps the parent's offset.  Waves run independently (no workgroup barrier).
 // D = 1: displaced state (mean row first in every packed matrix); D = -1: the
 // information form (the first row holds sigma_Q^-1 mu; see make_pivot_m).
+// The pivot columns and the first kExpandPre entries of each lane are loaded
+// before the pivot is formed, so that one HBM round trip serves all three
+// (the child region never overlaps a parent's).  On the top levels, where
+// there are few nodes, 2^log2split waves share a node: each forms the pivot
+// and the columns and writes every 2^log2split-th 64-entry chunk of the child.
+constexpr int kExpandPre = 4;
 template <class S, int D>
 __global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict__ jobs, int log2npar,
                                                      long long total, S *__restrict__ pool,
-                                                     const LaunchDims *__restrict__ dyn) {
+                                                     const LaunchDims *__restrict__ dyn, int log2split) {
     if (dyn) total = dyn->njobs << log2npar;
     __shared__ S vs[4][2][2 * TOR_MAX_N + MR(D)];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     S *v0 = vs[w][0], *v1 = vs[w][1];
-    for (long long f = (long long)blockIdx.x * 4 + w; f < total; f += (long long)gridDim.x * 4) {
+    const int nsplit = 1 << log2split;
+    const long long work = total << log2split;
+    for (long long g = (long long)blockIdx.x * 4 + w; g < work; g += (long long)gridDim.x * 4) {
+        const long long f = g >> log2split;
+        const int first = lane + 64 * (int)(g & (nsplit - 1));  // this wave's first entry
         const ExpandJob job = jobs[f >> log2npar];
         const long long i = f & ((1LL << log2npar) - 1);
         const int r = job.r, R = 2 * r + MR(D), RC = R - 2, EC = EN(r - 1, MR(D));
         NodeDesc d = job.par[i];
         const S *base = pool + d.off;
+        S pre[kExpandPre], c0 = S(), c1 = S();
+#pragma unroll
+        for (int k = 0; k < kExpandPre; k++)
+            if (first + 64 * nsplit * k < EC) pre[k] = base[first + 64 * nsplit * k];
+        if (lane < RC) {  // RC <= 2 * TOR_MAX_N - 1 < 64
+            c0 = base[pidx(R - 2, lane)];
+            c1 = base[pidx(R - 1, lane)];
+        }
         Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
         unsigned long long coff = job.child_base + (unsigned long long)i * (unsigned long long)EC;
-        if (lane == 0) {
+        if (first == 0) {
             job.chi[2 * i] = d;
             NodeDesc c;
             c.off = coff;
@@ -80,14 +98,22 @@ __global__ __launch_bounds__(256) void expand_kernel(const ExpandJob *__restrict
             c.acoef = d.acoef * hi_of(pv.q);
             job.chi[2 * i + 1] = c;
         }
-        for (int c = lane; c < RC; c += 64) {
-            S m0 = base[pidx(R - 2, c)];
-            v0[c] = mul_s(m0, pv.s1);
-            v1[c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
+        if (lane < RC) {
+            v0[lane] = mul_s(c0, pv.s1);
+            v1[lane] = mul_s(sub_mul(c1, pv.l, c0), pv.s2);
         }
         wave_sync();
         S *outp = pool + coff;
-        for (int e = lane; e < EC; e += 64) {
+#pragma unroll
+        for (int k = 0; k < kExpandPre; k++) {
+            const int e = first + 64 * nsplit * k;
+            if (e < EC) {
+                int a, b;
+                unpack(e, a, b);
+                outp[e] = sub_dot2(pre[k], v0[a], v0[b], v1[a], v1[b]);
+            }
+        }
+        for (int e = first + 64 * nsplit * kExpandPre; e < EC; e += 64 * nsplit) {
             int a, b;
             unpack(e, a, b);
             outp[e] = sub_dot2(base[e], v0[a], v0[b], v1[a], v1[b]);
@@ -217,28 +243,31 @@ hipError_t tor_launch_wave(int is_dd, int J, const WaveJob *jobs, int njobs, lon
 hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int log2npar, void *pool, int grid_cap,
                              hipStream_t st, const LaunchDims *dyn, int disp) {
     long long total = (long long)njobs << log2npar;
-    long long blocks = (total + 3) / 4;
+    // few nodes (host-planned levels only): up to 16 waves per node
+    int log2split = 0;
+    while (!dyn && log2split < 4 && (total << log2split) < 8192) log2split++;
+    long long blocks = ((total << log2split) + 3) / 4;
     long long g = dyn ? grid_cap : (blocks < grid_cap ? blocks : grid_cap);
     if (g < 1) return hipSuccess;
     (void)hipGetLastError();  // report only this launch's error
     if (is_dd && disp < 0)
         hipLaunchKernelGGL((tor::expand_kernel<dd, -1>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
-                           (dd *)pool, dyn);
+                           (dd *)pool, dyn, log2split);
     else if (!is_dd && disp < 0)
         hipLaunchKernelGGL((tor::expand_kernel<double, -1>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar,
-                           total, (double *)pool, dyn);
+                           total, (double *)pool, dyn, log2split);
     else if (is_dd && disp)
         hipLaunchKernelGGL((tor::expand_kernel<dd, 1>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
-                           (dd *)pool, dyn);
+                           (dd *)pool, dyn, log2split);
     else if (is_dd)
         hipLaunchKernelGGL((tor::expand_kernel<dd, 0>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar, total,
-                           (dd *)pool, dyn);
+                           (dd *)pool, dyn, log2split);
     else if (disp)
         hipLaunchKernelGGL((tor::expand_kernel<double, 1>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar,
-                           total, (double *)pool, dyn);
+                           total, (double *)pool, dyn, log2split);
     else
         hipLaunchKernelGGL((tor::expand_kernel<double, 0>), dim3((unsigned)g), dim3(256), 0, st, jobs, log2npar,
-                           total, (double *)pool, dyn);
+                           total, (double *)pool, dyn, log2split);
     return hipGetLastError();
 }
 
