@@ -23,8 +23,9 @@
 // the same prefix).
 //
 // Three tiers:
-//   expand  (HBM)   top levels, one 64-lane wave per node, children written to
-//                   a pool in HBM (breadth-first, one launch per level);
+//   expand  (HBM)   top levels, one 64-lane wave per node (up to 16 while a
+//                   level has few nodes), children written to a pool in HBM
+//                   (breadth-first, one launch per level);
 //   wave    (LDS)   a 64-lane workgroup takes one node with J modes and expands
 //                   J - TL more levels breadth-first in LDS (64 leaves);
 //   leaf    (VGPR)  each lane finishes a TL-mode node depth-first in registers.
