@@ -1800,7 +1800,9 @@ tor_status tor_state_invert(tor_state *st, tor_prec prec) {
     const size_t piv_off = align_up(cols_off + 2 * (size_t)d * es, 256);
     const size_t acc_off = align_up(piv_off + 3 * es, 256);
     const size_t total = acc_off + 3 * sizeof(double);
-    if (total > ctx->mem_budget) return fail(TOR_ENOMEM, "the inverse needs %.2f GB of device memory", total / 1e9);
+    const size_t cov_bytes = 4 * (size_t)m * (size_t)m * sizeof(double);  // the state's device copy of sigma
+    if (total + cov_bytes > ctx->mem_budget)
+        return fail(TOR_ENOMEM, "the inverse needs %.2f GB of device memory", (total + cov_bytes) / 1e9);
     struct Scoped {  // the device buffer lives for this call only
         DevBuf b;
         ~Scoped() { b.release(); }
@@ -1808,42 +1810,31 @@ tor_status tor_state_invert(tor_state *st, tor_prec prec) {
     if (buf.b.ensure(total) != hipSuccess)
         return fail(TOR_ENOMEM, "device allocation of %.2f GB failed", total / 1e9);
     unsigned char *db = (unsigned char *)buf.b.p;
-    std::vector<unsigned char> stage(total);
-    const double *cov = st->cov.data();
-    for (int a = 0; a < d; a++)
-        for (int b = 0; b <= a; b++) {
-            const dd v = sigq(cov, m, a, b);
-            const size_t e = (size_t)pidx(a, b);
-            if (q) ((qd *)stage.data())[e] = qd_from_dd(v);
-            else ((dd *)stage.data())[e] = v;
-        }
-    const double a0[3] = {1.0, 0.0, 0.0};
-    std::memcpy(stage.data() + acc_off, a0, sizeof a0);
+    // sigma_Q packed on the device from the state's device copy of sigma
+    // (made once per state and kept for the gathers), then the sweeps, the
+    // negation of -sigma_Q^-1 and one copy into the state's host words
+    tor_status ds = state_on_device(st);
+    if (ds) return ds;
     hipStream_t hs = ctx->stream;
-    HIP_TRY(hipMemcpyAsync(db, stage.data(), total, hipMemcpyHostToDevice, hs));
-    for (int k = 0; k < m; k++)
-        HIP_TRY(tor_launch_sweep(q, db, m, k, db + cols_off, db + piv_off, (double *)(db + acc_off), hs));
-    HIP_TRY(hipMemcpyAsync(stage.data(), db, cols_off, hipMemcpyDeviceToHost, hs));
+    double *dacc = (double *)(db + acc_off);
+    HIP_TRY(tor_launch_pack_sigq(q, (const double *)st->dcov.p, m, db, dacc, hs));
+    for (int k = 0; k < m; k++) HIP_TRY(tor_launch_sweep(q, db, m, k, db + cols_off, db + piv_off, dacc, hs));
+    HIP_TRY(tor_launch_negate(q, db, m, hs));
+    std::vector<dd> inv;
+    std::vector<qd> inv_q;
+    if (q) inv_q.resize(ent);
+    else inv.resize(ent);
+    HIP_TRY(hipMemcpyAsync(q ? (void *)inv_q.data() : (void *)inv.data(), db, ent * es, hipMemcpyDeviceToHost, hs));
     double acc[3];
-    HIP_TRY(hipMemcpyAsync(acc, db + acc_off, sizeof acc, hipMemcpyDeviceToHost, hs));
+    HIP_TRY(hipMemcpyAsync(acc, dacc, sizeof acc, hipMemcpyDeviceToHost, hs));
     HIP_TRY(hipStreamSynchronize(hs));
     if (!(acc[0] > 0.0) || !std::isfinite(acc[0]) || !std::isfinite(acc[2]))
         return fail(TOR_ENOTPD, "a pivot of sigma_Q was not positive");
-    // the sweeps leave -sigma_Q^-1
     st->inv_prec = 0;
     st->dinv.release();  // device copies of an earlier inverse are stale
     st->dinvh.release();
-    std::vector<dd>().swap(st->inv);
-    std::vector<qd>().swap(st->inv_q);
-    if (q) {
-        st->inv_q.resize(ent);
-        const qd *A = (const qd *)stage.data();
-        for (size_t e = 0; e < ent; e++) st->inv_q[e] = qd_neg(A[e]);
-    } else {
-        st->inv.resize(ent);
-        const dd *A = (const dd *)stage.data();
-        for (size_t e = 0; e < ent; e++) st->inv[e] = dd_neg(A[e]);
-    }
+    st->inv.swap(inv);
+    st->inv_q.swap(inv_q);
     st->det_rsqrt = dd_make(acc[0], acc[1]);
     st->log_det_sigq = -2.0 * acc[2];
     std::vector<dd>().swap(st->inv_h);

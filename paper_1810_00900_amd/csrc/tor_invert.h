@@ -15,3 +15,8 @@
 // modes in any order A holds -A0^-1.  is_qd: the words are quad-double,
 // else double-double.
 hipError_t tor_launch_sweep(int is_qd, void *A, int m, int k, void *cols, void *piv, double *acc, hipStream_t st);
+// A <- packed sigma_Q (double-double or quad-double words) from the row-major
+// 2m x 2m covariance cov (device); acc <- (1, 0, 0)
+hipError_t tor_launch_pack_sigq(int is_qd, const double *cov, int m, void *A, double *acc, hipStream_t st);
+// A <- -A over the E(m) packed words
+hipError_t tor_launch_negate(int is_qd, void *A, int m, hipStream_t st);

@@ -18,9 +18,10 @@
 // v2 = (A[i, p1] - l A[i, p0]) s2): the first line is the tree's rank-2
 // update A - v1 v1^T - v2 v2^T; A[i, P] P^-1 = (v1 s1 - v2 l s2, v2 s2); and
 // -P^-1 = [[-(s1^2 + l^2 s2^2), l s2^2], [l s2^2, -s2^2]].  After all sweeps A
-// holds -sigma_Q^-1, and the product of the blocks' det^-1/2 is
-// det(sigma_Q)^-1/2.  Two launches per mode: the pivot columns go to a
-// scratch buffer first because the update rewrites them.
+// holds -sigma_Q^-1 (negated in place at the end), and the product of the
+// blocks' det^-1/2 is det(sigma_Q)^-1/2.  Two launches per mode: the pivot
+// columns go to a scratch buffer first because the update rewrites them.
+// sigma_Q is packed on the device from the state's device copy of sigma.
 #include <hip/hip_runtime.h>
 
 #include "dd.hpp"
@@ -91,6 +92,39 @@ __global__ __launch_bounds__(256) void sweep_update_kernel(S *__restrict__ A, in
     }
 }
 
+__device__ __forceinline__ void put_word(dd *A, int e, dd x) { A[e] = x; }
+__device__ __forceinline__ void put_word(qd *A, int e, dd x) { A[e] = qd_from_dd(x); }
+__device__ __forceinline__ dd negate(dd x) { return dd_neg(x); }
+__device__ __forceinline__ qd negate(qd x) { return qd_neg(x); }
+
+// sigma_Q = sigma + I/2 in packed lower storage from the row-major 2m x 2m
+// covariance on the device (the diagonal exact in double-double); entry 0's
+// thread also starts the determinant accumulator (product 1, log 0).
+template <class S>
+__global__ __launch_bounds__(256) void pack_sigq_kernel(const double *__restrict__ cov, int d, int entries,
+                                                        S *__restrict__ A, double *__restrict__ acc) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= entries) return;
+    int a, b;
+    unpack(e, a, b);
+    const double v = cov[(size_t)a * (size_t)d + (size_t)b];
+    dd x;
+    if (a == b) two_sum(v, 0.5, x.hi, x.lo);
+    else x = dd_from(v);
+    put_word(A, e, x);
+    if (e == 0) {
+        acc[0] = 1.0;
+        acc[1] = 0.0;
+        acc[2] = 0.0;
+    }
+}
+
+// the sweeps leave -sigma_Q^-1: negate in place
+template <class S> __global__ __launch_bounds__(256) void negate_kernel(S *__restrict__ A, int entries) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < entries) A[e] = negate(A[e]);
+}
+
 template <class S>
 static hipError_t launch_sweep(void *A, int m, int k, void *cols, void *piv, double *acc, hipStream_t st) {
     const int d = 2 * m;
@@ -111,4 +145,30 @@ hipError_t tor_launch_sweep(int is_qd, void *A, int m, int k, void *cols, void *
     if (m < 1 || m > TOR_INVERT_MAX_MODES || k < 0 || k >= m) return hipErrorInvalidValue;
     return is_qd ? tor::launch_sweep<qd>(A, m, k, cols, piv, acc, st)
                  : tor::launch_sweep<dd>(A, m, k, cols, piv, acc, st);
+}
+
+hipError_t tor_launch_pack_sigq(int is_qd, const double *cov, int m, void *A, double *acc, hipStream_t st) {
+    if (m < 1 || m > TOR_INVERT_MAX_MODES) return hipErrorInvalidValue;
+    const int d = 2 * m, entries = d * (d + 1) / 2;
+    (void)hipGetLastError();
+    if (is_qd)
+        hipLaunchKernelGGL((tor::pack_sigq_kernel<qd>), dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st, cov,
+                           d, entries, (qd *)A, acc);
+    else
+        hipLaunchKernelGGL((tor::pack_sigq_kernel<dd>), dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st, cov,
+                           d, entries, (dd *)A, acc);
+    return hipGetLastError();
+}
+
+hipError_t tor_launch_negate(int is_qd, void *A, int m, hipStream_t st) {
+    if (m < 1 || m > TOR_INVERT_MAX_MODES) return hipErrorInvalidValue;
+    const int d = 2 * m, entries = d * (d + 1) / 2;
+    (void)hipGetLastError();
+    if (is_qd)
+        hipLaunchKernelGGL((tor::negate_kernel<qd>), dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st,
+                           (qd *)A, entries);
+    else
+        hipLaunchKernelGGL((tor::negate_kernel<dd>), dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st,
+                           (dd *)A, entries);
+    return hipGetLastError();
 }
