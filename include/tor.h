@@ -92,7 +92,13 @@ typedef struct {
     double T_lo;          /* low word of T */
     double abs_sum;       /* sum of |terms| over Sigma_C */
     double cancel_ratio;  /* abs_sum / |T| */
-    double rel_err_bound; /* a-priori relative error bound of p */
+    double rel_err_bound; /* a-priori relative error bound of p, first order in the unit
+                             roundoffs: 16 (n u + k u_c) R (1 + quad), u of the term
+                             precision, k the elimination steps that formed Sigma_C
+                             (no-click conditioning steps, or the m sweeps of a state's
+                             inverse for its full patterns; 0 for a marginal pattern)
+                             with unit roundoff u_c, R = cancel_ratio, quad the
+                             largest mean exponent (displaced states; else 0) */
     double log_pvac_n;    /* log P_vac(N) */
     int32_t n_clicks;     /* |C| */
     int32_t prec_used;    /* TOR_PREC_F64, TOR_PREC_DD or TOR_PREC_QD */

@@ -261,6 +261,11 @@ struct Reduced {
     bool jacobi = false;
     dd tscale = {1.0, 0.0};
     dd pdirect = {1.0, 0.0};  // (-1)^n det(sigma_Q)^-1/2: p = pdirect T(G)
+    // sum over the elimination steps that formed the tree's matrix of their
+    // unit roundoff: k u for k no-click conditioning steps, m u for the m
+    // sweeps of a state's inverse (0 for a marginal pattern, whose sigma_Q[C]
+    // is exact); enters the error bound beside the tree's own n u
+    double cond_u = 0.0;
 };
 
 // Displaced state (mean mu, hbar = 1, interleaved like cov): the packed matrix
@@ -863,6 +868,7 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
             const double *acc = accs.data() + 3 * i;
             r->pvac = dd_make(acc[0], acc[1]);
             r->log_pvac = acc[2];
+            r->cond_u = r->k * kUDD;  // k double-double conditioning steps
             r->cond = false;
             r->st = nullptr;
             std::vector<int>().swap(r->g);
@@ -903,6 +909,7 @@ struct Prepared {
     bool scaled = false;  // the tree sums G = Sigma_C^-1: multiply its (T, A) by tscale
     dd tscale = {1.0, 0.0};
     dd pdirect = {1.0, 0.0};  // scaled: p = pdirect T(G)
+    double cond_u = 0.0;      // as Reduced::cond_u
     tor_status status = TOR_OK;
     std::string err;
 };
@@ -942,14 +949,25 @@ tor_status prepare(const std::vector<dd> &sig, int n, dd pvac, double log_pvac, 
     return TOR_OK;
 }
 
+// A-priori relative error bound of a subset sum, first order in the unit
+// roundoffs: every term det(Sigma_C[Y])^-1/2 is a product of at most n pivot
+// factors, each the result of a few rounded operations on Schur complements,
+// so its relative error is a small multiple of n u (u of the term precision);
+// the elimination steps that formed Sigma_C from sigma_Q (k no-click
+// conditioning steps of Eq. MatrixUpdate, or the m sweeps of a state's
+// inverse) are each backward stable, the exact step of a matrix perturbed by a
+// few u_c relative to sigma_Q >= I/2, and those perturbations add up over the
+// steps, moving every term by a small multiple of k u_c more (cond_u = k u_c).
+// Errors of the terms add up to R = sum|t| / |T| times the relative error of
+// the largest terms; the constant 16 covers the per-step constants.
 // Displaced states: every term also carries exp(-x/2), x <= quad (the largest
 // exponent of any term: the quadratic form of a principal block's inverse is
 // at most that of the whole matrix); the rounding of x enters the term's
 // relative error in proportion to x, hence the factor (1 + quad).
-double bound_of(int used, int n, dd T, double A, double quad = 0.0) {
+double bound_of(int used, int n, dd T, double A, double quad = 0.0, double cond_u = 0.0) {
     double R = A / std::fabs(T.hi);
     const double u = used == TOR_PREC_QD ? kUQD : used == TOR_PREC_DD ? kUDD : kUF64;
-    return kBoundC * std::max(n, 1) * u * R * (1.0 + quad);
+    return kBoundC * (std::max(n, 1) * u + cond_u) * R * (1.0 + quad);
 }
 
 // mu^T Sigma^-1 mu of an n-mode packed matrix with its mean row first
@@ -1034,6 +1052,13 @@ bool is_full_pattern(const int8_t *pattern, int m) {
 // state holds that one); det(G)^(+-1/2) from its double-double Cholesky.
 tor_status reduce_pattern_jacobi_disp(const tor_state *st, const int8_t *pattern, Reduced &out);
 
+// Elimination error carried by G = K[C] gathered from a state's inverse: the
+// m sweeps that formed K (unit roundoff of the inverse's words), plus one
+// rounding of a quad-double inverse to the double-double words of the tree.
+double inverse_cond_u(const tor_state *st) {
+    return st->inv_prec == TOR_PREC_QD ? st->m * kUQD + kUDD : st->m * kUDD;
+}
+
 tor_status reduce_pattern_jacobi(const tor_state *st, const int8_t *pattern, Reduced &out) {
     if (!st->mean.empty()) return reduce_pattern_jacobi_disp(st, pattern, out);
     std::vector<int> C;
@@ -1066,6 +1091,7 @@ tor_status reduce_pattern_jacobi(const tor_state *st, const int8_t *pattern, Red
     }
     out.pvac = dd_mul(st->det_rsqrt, rroot);
     out.log_pvac = -0.5 * (st->log_det_sigq + log_det_g);
+    out.cond_u = inverse_cond_u(st);
     out.tscale = (n & 1) ? dd_neg(root) : root;
     out.pdirect = (n & 1) ? dd_neg(st->det_rsqrt) : st->det_rsqrt;
     return TOR_OK;
@@ -1124,6 +1150,7 @@ tor_status reduce_pattern_jacobi_disp(const tor_state *st, const int8_t *pattern
         }
     }
     const dd half_q = dd_make(0.5 * q.hi, 0.5 * q.lo);
+    out.cond_u = inverse_cond_u(st);
     out.pvac = dd_mul(dd_mul(st->det_rsqrt_mean, rroot), dd_exp(half_q));
     out.log_pvac = -0.5 * (st->log_det_sigq + log_det_g) - 0.5 * (st->mu_k_mu.hi + st->mu_k_mu.lo) +
                    (half_q.hi + half_q.lo);
@@ -1149,6 +1176,7 @@ tor_status reduce_for_state(const tor_state *st, const int8_t *pattern, Reduced 
 
 // A reduced pattern, conditioned if it had no-click modes, made ready for the GPU.
 tor_status prepare_reduced(Reduced &r, Prepared &p) {
+    p.cond_u = r.cond_u;
     if (r.D) {
         tor_status s = prepare_disp(std::move(r.packed), r.n, r.pvac, r.log_pvac, p);
         if (s == TOR_OK && r.jacobi) {  // [0, h_C; h_C, G]: the information-form tree
@@ -1185,7 +1213,7 @@ void finalize(const Prepared &p, const SumOut &s, int used, double tol, tor_resu
     out->tor = std::exp(0.5 * p.log_det) * (T.hi + T.lo);
     out->abs_sum = A;
     out->cancel_ratio = A / std::fabs(T.hi);
-    out->rel_err_bound = bound_of(used, p.n, T, A, p.quad);
+    out->rel_err_bound = bound_of(used, p.n, T, A, p.quad, p.cond_u);
     out->log_pvac_n = p.log_pvac;
     out->n_clicks = p.n;
     out->prec_used = used;
@@ -1379,9 +1407,11 @@ tor_status probability_qd(tor_ctx *ctx, const double *cov, int m, const int8_t *
         p.scaled = true;
         p.tscale = red.tscale;
         p.pdirect = red.pdirect;
+        p.cond_u = m * kUQD;  // the quad-double inverse's sweeps, no rounding
     } else if (red.cond) {
         s = condition_qd(ctx, red, sigc, p.pvac, p.log_pvac);
         if (s) return s;
+        p.cond_u = red.k * kUQD;
     } else {
         const int dc = 2 * red.n;
         sigc.assign((size_t)E(red.n), qd_from(0.0));
@@ -1437,6 +1467,7 @@ tor_status probability_qd_disp(tor_ctx *ctx, const double *cov, const double *me
         Prepared p;
         s = prepare_reduced(red, p);  // log det Sigma_C, quad = h_C^T G^-1 h_C, tree kind -1
         if (s) return s;
+        p.cond_u = m * kUQD;  // the quad-double inverse's sweeps, no rounding
         SumOut so;
         s = gpu_sum_qd(ctx, sigc, red.n, so, -1);
         if (s) return s;
@@ -1469,6 +1500,7 @@ tor_status probability_qd_disp(tor_ctx *ctx, const double *cov, const double *me
     Prepared p;
     s = prepare_disp(std::move(rounded), red.n, pvac, log_pvac, p);
     if (s) return s;
+    p.cond_u = red.cond ? red.k * kUQD : 0.0;
     SumOut so;
     s = gpu_sum_qd(ctx, sigc, red.n, so, 1);
     if (s) return s;
@@ -1516,7 +1548,8 @@ tor_status evaluate_many(tor_ctx *ctx, std::vector<Prepared> &qs, tor_prec prec,
     if (prec == TOR_PREC_AUTO) {
         std::vector<int> redo;
         for (int i : ok)
-            if (qs[i].n > 0 && !(bound_of(TOR_PREC_F64, qs[i].n, res[i].T, res[i].A, qs[i].quad) <= tol))
+            if (qs[i].n > 0 &&
+                !(bound_of(TOR_PREC_F64, qs[i].n, res[i].T, res[i].A, qs[i].quad, qs[i].cond_u) <= tol))
                 redo.push_back(i);
         if (!redo.empty()) {
             s = gpu_sums(ctx, in, redo, true, res);
@@ -1671,6 +1704,7 @@ tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int
     std::vector<Prepared> qs(1);
     s = prepare(red.sig, red.n, red.pvac, red.log_pvac, qs[0]);
     if (s) return s;
+    qs[0].cond_u = red.cond_u;
     return evaluate_many(ctx, qs, prec, tol, out);
 }
 
@@ -1690,6 +1724,7 @@ tor_status tor_probability_displaced(tor_ctx *ctx, const double *cov, const doub
     std::vector<Prepared> qs(1);
     s = prepare_disp(std::move(red.packed), red.n, red.pvac, red.log_pvac, qs[0]);
     if (s) return s;
+    qs[0].cond_u = red.cond_u;
     return evaluate_many(ctx, qs, prec, tol, out);
 }
 
@@ -1966,6 +2001,7 @@ tor_status tor_batch_displaced(tor_ctx *ctx, const tor_state *st, const double *
     }
     for (int q = 0; q < nq; q++) {
         if (qs[q].status != TOR_OK) continue;
+        qs[q].cond_u = red[q].cond_u;
         tor_status s = prepare_disp(std::move(red[q].packed), red[q].n, red[q].pvac, red[q].log_pvac, qs[q]);
         if (s != TOR_OK) {
             qs[q].status = s;
@@ -2028,6 +2064,7 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
         P.det_rsqrt_lo = st->det_rsqrt_mean.lo;
         P.log_det_sigq = st->log_det_sigq;
         P.mu_k_mu = st->mu_k_mu.hi + st->mu_k_mu.lo;
+        P.inv_cond_u = inverse_cond_u(st);
         P.nkinds = D ? 2 : 1;
     }
     const int nmax = std::min(TOR_MAX_CLICKS, m);
@@ -2583,7 +2620,10 @@ static tor_status chain_fixed_impl(tor_ctx *ctx, const double *cov, const double
         }
         if (step_p) step_p[seq[k]] = (num.hi + num.lo) / (prev.hi + prev.lo);
         if (in[k].n > 0) {
-            worst_bound = std::max(worst_bound, bound_of(used[k], in[k].n, T, res[k].A, quad_of(roots[k], in[k].n, D)));
+            // the step's sum is over the matrix after t conditioning steps
+            const double cu = t * (prec == TOR_PREC_QD ? kUQD : kUDD);
+            worst_bound =
+                std::max(worst_bound, bound_of(used[k], in[k].n, T, res[k].A, quad_of(roots[k], in[k].n, D), cu));
             worst_R = std::max(worst_R, res[k].A / std::fabs(T.hi));
             worst_used = std::max(worst_used, used[k]);
         }

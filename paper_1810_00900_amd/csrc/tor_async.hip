@@ -417,7 +417,10 @@ __global__ void async_finalize_kernel(AsyncPlan P, double tol, int prec_used, to
     r.abs_sum = A;
     r.cancel_ratio = A / fabs(T.hi);
     const double u = prec_used == TOR_PREC_DD ? 4.930380657631324e-32 : 1.1102230246251565e-16;
-    r.rel_err_bound = 16.0 * (Q.n > 1 ? Q.n : 1) * u * (A / fabs(T.hi)) * (1.0 + Q.quad);
+    // the host's bound: the tree's n u plus, for a full pattern of an inverted
+    // state, the roundoff of the sweeps that formed the inverse
+    const double cu = Q.jac ? P.inv_cond_u : 0.0;
+    r.rel_err_bound = 16.0 * ((Q.n > 1 ? Q.n : 1) * u + cu) * (A / fabs(T.hi)) * (1.0 + Q.quad);
     r.n_clicks = Q.n;
     r.prec_used = prec_used;
     r.status = r.rel_err_bound <= tol ? TOR_OK : TOR_WARN_PRECISION;

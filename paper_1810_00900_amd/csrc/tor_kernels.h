@@ -118,6 +118,7 @@ struct AsyncPlan {
     // inverted state: det(sigma_Q)^-1/2 (times exp(-mu^T sigma_Q^-1 mu / 2) when displaced),
     // log det sigma_Q and mu^T sigma_Q^-1 mu
     double det_rsqrt_hi, det_rsqrt_lo, log_det_sigq, mu_k_mu;
+    double inv_cond_u;   // inverted state: elimination roundoff carried by G (m u of the inverse)
     int nkinds;          // tree kinds in the batch: 2 when full patterns of an inverted displaced
                          // state (information form, kind 1) join the displaced trees (kind 0)
     int J_of_n[TOR_MAX_N + 1];
