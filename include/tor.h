@@ -290,6 +290,41 @@ tor_status tor_batch_displaced(tor_ctx *ctx, const tor_state *st, const double *
 tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *d_patterns, tor_prec prec,
                            double tol, tor_result *d_out, void *stream);
 
+/* Allocation-free form of tor_batch_async, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It calls no hipMalloc, hipFree or other allocating
+ * routine: its whole workspace (plan tables and tree pool) is one static
+ * device array of TOR_NOALLOC_SCRATCH_BYTES per GPU, resolved when a context
+ * is created on that GPU and held until the process ends.
+ *   d_cov       device pointer, 2m x 2m row-major binary64, the zero-mean
+ *               covariance (conventions as for cov above), owned by the
+ *               caller; it is not validated on the host (finite and
+ *               symmetric is the caller's guarantee; a Sigma_C that is not
+ *               positive definite gives TOR_ENOTPD in its result)
+ *   d_patterns  device, nq x m int8, marginal patterns (1 = click, -1 =
+ *               unobserved); a query with a no-click mode (0) or a bad entry
+ *               gets TOR_EINVAL in its result, more than 32 clicks TOR_ETOOBIG
+ *   d_out       device, nq tor_result records
+ *   nq          at most TOR_NOALLOC_MAX_QUERIES
+ * prec, tol and stream as for tor_batch_async; the call only enqueues work.
+ * The trees share the workspace's tree pool (about 90 MiB of double-double
+ * scalars: one double-double tree of n = 24, or many smaller ones); queries
+ * are admitted in order while their trees fit, later ones get TOR_ENOMEM in
+ * their result.  Results of admitted queries are bitwise those of
+ * tor_batch_async on a zero-mean state with the same covariance (same
+ * kernels, trees and reduction order).  Every call on a GPU shares that GPU's
+ * workspace and leaves its contents behind (each call's plan rewrites what it
+ * reads): calls whose work overlaps on one GPU (different streams, or other
+ * threads) race, so order them on one stream or wait in between.
+ * Errors: TOR_EINVAL (NULL pointer, m <= 0, nq < 0, bad prec), TOR_ETOOBIG
+ * (nq above the limit, m too large), TOR_EDEVICE (no workspace address for
+ * the device, launch failure). */
+#define TOR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+#define TOR_NOALLOC_MAX_QUERIES 4096
+tor_status tor_batch_async_noalloc(tor_ctx *ctx, const double *d_cov, int32_t m, int32_t nq,
+                                   const int8_t *d_patterns, tor_prec prec, double tol, tor_result *d_out,
+                                   void *stream);
+
 /* ------------------------------------------------------------------------
  * Exact chain-rule sampling (the paper's mode-by-mode sampler, Sec. II: each
  * mode's coin is flipped with the conditional no-click probability given the

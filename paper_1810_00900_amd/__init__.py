@@ -142,6 +142,8 @@ def lib():
         "tor_batch_displaced": ([vp, vp, dp, ctypes.c_int32, i8p, ctypes.c_int, ctypes.c_double,
                                  ctypes.POINTER(_CResult)], ctypes.c_int32),
         "tor_batch_async": ([vp, vp, ctypes.c_int32, vp, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int32),
+        "tor_batch_async_noalloc": ([vp, vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int, ctypes.c_double, vp,
+                                     vp], ctypes.c_int32),
         "tor_server_start": ([vp, ctypes.POINTER(_CServerOpts), ctypes.POINTER(vp)], ctypes.c_int32),
         "tor_submit": ([vp, vp, i8p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
         "tor_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(_CResult), dp], ctypes.c_int32),
@@ -418,6 +420,33 @@ class Context:
                                      _PREC[prec], float(tol), ctypes.c_void_p(d_out.data_ptr()),
                                      ctypes.c_void_p(raw)))
         return d_out
+
+
+NOALLOC_MAX_QUERIES = 4096
+
+
+def batch_async_noalloc(ctx: "Context", d_cov, d_patterns, d_out, prec="dd", tol: float = 1e-10, stream=None):
+    """tor_batch_async_noalloc: marginal patterns of the zero-mean covariance
+    d_cov (contiguous float64 device tensor, 2m x 2m), results into d_out (a
+    contiguous uint8 device tensor of nq result records, caller-allocated: the
+    call itself allocates nothing).  Stream-ordered like Context.batch_async."""
+    import torch
+    if d_cov.dtype != torch.float64 or not d_cov.is_cuda or not d_cov.is_contiguous():
+        raise ValueError("d_cov must be a contiguous float64 device tensor")
+    if d_patterns.dtype != torch.int8 or not d_patterns.is_cuda or not d_patterns.is_contiguous():
+        raise ValueError("d_patterns must be a contiguous int8 device tensor")
+    m = int(d_patterns.shape[1])
+    if tuple(d_cov.shape) != (2 * m, 2 * m):
+        raise ValueError("d_cov must be 2m x 2m for patterns of length m")
+    nq = int(d_patterns.shape[0])
+    rec = ctypes.sizeof(_CResult)
+    if d_out.dtype != torch.uint8 or not d_out.is_cuda or d_out.numel() < nq * rec or not d_out.is_contiguous():
+        raise ValueError("d_out must be a contiguous uint8 device tensor of nq result records")
+    raw = None if stream is None else getattr(stream, "cuda_stream", stream)
+    _check(lib().tor_batch_async_noalloc(ctx.handle, ctypes.c_void_p(d_cov.data_ptr()), m, nq,
+                                         ctypes.c_void_p(d_patterns.data_ptr()), _PREC[prec], float(tol),
+                                         ctypes.c_void_p(d_out.data_ptr()), ctypes.c_void_p(raw)))
+    return d_out
 
 
 def results_from_device(d_out) -> list:

@@ -93,6 +93,49 @@ constexpr double kUQD = 2.4308653429145085e-63;    // 2^-208 (quad-double terms)
 
 }  // namespace
 
+// Workspace of tor_batch_async_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  In host code its name is only a
+// stand-in: the device address of each GPU's copy comes from
+// hipGetSymbolAddress (scratch_setup, at context creation) and is the only
+// address host code passes on.
+static __device__ __align__(256) unsigned char scratch[TOR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+std::string g_scratch_err[kMaxScratchDevices];
+
+// Resolve this device's copy of scratch (the caller has made `device`
+// current); once per device.  A failure is kept and reported by the
+// allocation-free entry point, not by context creation.
+void scratch_setup(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        g_scratch_err[device] = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return;
+    }
+    g_scratch_ptr[device] = ptr;
+}
+
+void *scratch_of(int device, std::string *err) {
+    if (device < 0 || device >= kMaxScratchDevices) {
+        *err = "device index beyond the scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) *err = g_scratch_err[device];
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 struct tor_ctx {
     int device = 0;
     hipStream_t own_stream = nullptr;
@@ -1611,6 +1654,7 @@ tor_status tor_ctx_create(int device, tor_ctx **out) {
     }
     c->host_res_cap = 64;
     for (auto &e : c->ev) (void)hipEventCreate(&e);
+    scratch_setup(device);
     if (const char *tc = std::getenv("TOR_TUNE_CACHE")) {
         if (*tc && tor_load_tuning(c, tc) != TOR_OK) g_err.clear();  // a missing cache is not an error
     }
@@ -2011,27 +2055,32 @@ tor_status tor_batch_displaced(tor_ctx *ctx, const tor_state *st, const double *
     return evaluate_many(ctx, qs, prec, tol, out);
 }
 
-tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *d_patterns, tor_prec prec,
-                           double tol, tor_result *d_out, void *stream) {
-    if (!ctx || !st) return fail(TOR_EINVAL, "NULL argument");
-    if (st->ctx != ctx) return fail(TOR_EINVAL, "state belongs to another context");
-    if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
-    if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD)
-        return fail(TOR_EINVAL, "bad precision %d", (int)prec);
-    if (nq == 0) return TOR_OK;
-    if (!d_patterns || !d_out) return fail(TOR_EINVAL, "NULL device pointer");
-    if (nq > (1 << 24)) return fail(TOR_ETOOBIG, "nq = %d > 2^24", nq);
+}  // extern "C"
+
+namespace {
+
+// Enqueue a stream-ordered batch.  With st the queries are patterns of that
+// state (its device copies are made on first use); with st == nullptr they
+// are marginal patterns of the zero-mean covariance d_cov (caller-owned
+// device memory, 2m x 2m row-major).  With ws == nullptr the workspace is the
+// context's own (grown on demand); otherwise it is ws[0 .. ws_bytes), and
+// nothing is allocated: the tree pool takes what the plan tables leave.
+tor_status batch_async_impl(tor_ctx *ctx, const tor_state *st, const double *d_cov, int32_t m, int32_t nq,
+                            const int8_t *d_patterns, tor_prec prec, double tol, tor_result *d_out, void *stream,
+                            unsigned char *ws, size_t ws_bytes) {
     if (!(tol > 0.0)) tol = 1e-10;
     const bool use_dd = prec != TOR_PREC_F64;
     const int used = use_dd ? TOR_PREC_DD : TOR_PREC_F64;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t hs = stream ? (hipStream_t)stream : ctx->stream;
     tor_state *ms = const_cast<tor_state *>(st);  // the device copies are a cache of the state
-    const int m = st->m;
     const size_t cov_bytes = 4 * (size_t)m * (size_t)m * sizeof(double);
-    tor_status ds = state_on_device(st);
-    if (ds) return ds;
-    const int D = st->mean.empty() ? 0 : 1;
+    if (st) {
+        tor_status ds = state_on_device(st);
+        if (ds) return ds;
+        d_cov = (const double *)ms->dcov.p;
+    }
+    const int D = (st && !st->mean.empty()) ? 1 : 0;
     // task sizes and the launches any pattern of this state can need
     AsyncPlan P{};
     P.nq = nq;
@@ -2043,7 +2092,7 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     // device; a displaced state's full patterns are a second tree kind (the
     // information form) beside its displaced trees
     P.nkinds = 1;
-    if (st->inv_prec) {
+    if (st && st->inv_prec) {
         const size_t ent = (size_t)E(m);
         std::lock_guard<std::mutex> lk(ms->dev_mu);
         if (!ms->dinv.p) {
@@ -2085,35 +2134,55 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     P.gcap = gcap;
     P.jmax = jmax;
     const size_t es = use_dd ? sizeof(dd) : sizeof(double);
-    P.pool_cap = (long long)(ctx->async_pool / es);
-    P.desc_cap = P.pool_cap / 16 + nq;
-    P.pb_cap = P.desc_cap / TOR_REDUCE_CHUNK + (long long)TOR_ASYNC_STAGES * nq + 8;
-    // workspace layout
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o = off;
-        off = align_up(off + bytes, 256);
-        return o;
-    };
-    const size_t o_q = take((size_t)nq * sizeof(AsyncQuery));
-    const size_t o_roots = take((size_t)nq * sizeof(NodeDesc));
-    const size_t o_dA = take((size_t)P.desc_cap * sizeof(NodeDesc));
-    const size_t o_dB = take((size_t)P.desc_cap * sizeof(NodeDesc));
-    const size_t o_pA = take((size_t)P.desc_cap * sizeof(Partial));
-    const size_t o_pB = take((size_t)P.pb_cap * sizeof(Partial));
-    const size_t o_ej = take((size_t)P.nkinds * std::max(gcap, 1) * nq * sizeof(ExpandJob));
-    const size_t o_wj = take((size_t)P.nkinds * (TOR_TASK_MAX + 1) * nq * sizeof(WaveJob));
-    const size_t o_rj = take((size_t)TOR_ASYNC_STAGES * nq * sizeof(ReduceJob));
     const int stride = gcap + TOR_TASK_MAX + 1;  // launch dimensions per tree kind
-    const size_t o_dims = take(((size_t)P.nkinds * stride + TOR_ASYNC_STAGES) * sizeof(LaunchDims));
-    const size_t abytes = off, pbytes = (size_t)P.pool_cap * es;
-    if (abytes + pbytes + cov_bytes > ctx->mem_budget)
-        return fail(TOR_ENOMEM, "async workspace of %.2f GB exceeds the memory budget", (abytes + pbytes) / 1e9);
-    if (ctx->abuf.ensure(abytes) != hipSuccess || ctx->apool.ensure(pbytes) != hipSuccess)
-        return fail(TOR_ENOMEM, "device allocation of the async workspace (%.2f GB) failed", (abytes + pbytes) / 1e9);
-    unsigned char *b = (unsigned char *)ctx->abuf.p;
+    // workspace layout for a tree pool of pool_cap scalars: the plan tables,
+    // then (given workspace) the pool
+    size_t o_q = 0, o_roots = 0, o_dA = 0, o_dB = 0, o_pA = 0, o_pB = 0, o_ej = 0, o_wj = 0, o_rj = 0, o_dims = 0;
+    auto layout = [&](long long pool_cap) {
+        P.pool_cap = pool_cap;
+        P.desc_cap = P.pool_cap / 16 + nq;
+        P.pb_cap = P.desc_cap / TOR_REDUCE_CHUNK + (long long)TOR_ASYNC_STAGES * nq + 8;
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t o = off;
+            off = align_up(off + bytes, 256);
+            return o;
+        };
+        o_q = take((size_t)nq * sizeof(AsyncQuery));
+        o_roots = take((size_t)nq * sizeof(NodeDesc));
+        o_dA = take((size_t)P.desc_cap * sizeof(NodeDesc));
+        o_dB = take((size_t)P.desc_cap * sizeof(NodeDesc));
+        o_pA = take((size_t)P.desc_cap * sizeof(Partial));
+        o_pB = take((size_t)P.pb_cap * sizeof(Partial));
+        o_ej = take((size_t)P.nkinds * std::max(gcap, 1) * nq * sizeof(ExpandJob));
+        o_wj = take((size_t)P.nkinds * (TOR_TASK_MAX + 1) * nq * sizeof(WaveJob));
+        o_rj = take((size_t)TOR_ASYNC_STAGES * nq * sizeof(ReduceJob));
+        o_dims = take(((size_t)P.nkinds * stride + TOR_ASYNC_STAGES) * sizeof(LaunchDims));
+        return off;  // bytes of the tables
+    };
+    unsigned char *b = nullptr;
+    if (ws) {
+        // the tables grow by about (6 + nq-dependent) bytes per pool scalar
+        // (descriptors at pool_cap / 16): size the pool to fill the rest
+        const size_t fixed = layout(0);
+        if (fixed + 4096 > ws_bytes)
+            return fail(TOR_ETOOBIG, "nq = %d: the plan tables alone exceed the %zu-byte workspace", nq, ws_bytes);
+        long long cap = (long long)((ws_bytes - fixed - 4096) / (es + 7));
+        while (cap > 0 && align_up(layout(cap), 256) + (size_t)cap * es > ws_bytes) cap -= cap / 64 + 1;
+        if (cap <= 0) return fail(TOR_ETOOBIG, "nq = %d leaves no tree pool in the workspace", nq);
+        const size_t tab = align_up(layout(cap), 256);
+        b = ws;
+        P.pool = ws + tab;
+    } else {
+        const size_t abytes = layout((long long)(ctx->async_pool / es)), pbytes = (size_t)P.pool_cap * es;
+        if (abytes + pbytes + cov_bytes > ctx->mem_budget)
+            return fail(TOR_ENOMEM, "async workspace of %.2f GB exceeds the memory budget", (abytes + pbytes) / 1e9);
+        if (ctx->abuf.ensure(abytes) != hipSuccess || ctx->apool.ensure(pbytes) != hipSuccess)
+            return fail(TOR_ENOMEM, "device allocation of the async workspace (%.2f GB) failed", (abytes + pbytes) / 1e9);
+        b = (unsigned char *)ctx->abuf.p;
+        P.pool = ctx->apool.p;
+    }
     P.q = (AsyncQuery *)(b + o_q);
-    P.pool = ctx->apool.p;
     P.roots = (NodeDesc *)(b + o_roots);
     P.descA = (NodeDesc *)(b + o_dA);
     P.descB = (NodeDesc *)(b + o_dB);
@@ -2124,7 +2193,7 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     P.red_jobs = (ReduceJob *)(b + o_rj);
     P.dims = (LaunchDims *)(b + o_dims);
     // scan, plan, roots; then the tree launches with device-side dimensions
-    HIP_TRY(tor_launch_async_prologue(d_patterns, (const double *)ms->dcov.p, P, hs));
+    HIP_TRY(tor_launch_async_prologue(d_patterns, d_cov, P, hs));
     for (int k = 0; k < P.nkinds; k++) {  // kind 1: the information-form trees (tree kind -1)
         const int Dk = k ? -1 : D;
         for (int d = 0; d < gcap; d++) {
@@ -2148,6 +2217,43 @@ tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const 
     HIP_TRY(tor_launch_async_finalize(P, tol, used, d_out, hs));
     ctx->stats.expand_launches += (int64_t)gcap * P.nkinds;
     return TOR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tor_status tor_batch_async(tor_ctx *ctx, const tor_state *st, int32_t nq, const int8_t *d_patterns, tor_prec prec,
+                           double tol, tor_result *d_out, void *stream) {
+    if (!ctx || !st) return fail(TOR_EINVAL, "NULL argument");
+    if (st->ctx != ctx) return fail(TOR_EINVAL, "state belongs to another context");
+    if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
+    if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD)
+        return fail(TOR_EINVAL, "bad precision %d", (int)prec);
+    if (nq == 0) return TOR_OK;
+    if (!d_patterns || !d_out) return fail(TOR_EINVAL, "NULL device pointer");
+    if (nq > (1 << 24)) return fail(TOR_ETOOBIG, "nq = %d > 2^24", nq);
+    return batch_async_impl(ctx, st, nullptr, st->m, nq, d_patterns, prec, tol, d_out, stream, nullptr, 0);
+}
+
+tor_status tor_batch_async_noalloc(tor_ctx *ctx, const double *d_cov, int32_t m, int32_t nq,
+                                   const int8_t *d_patterns, tor_prec prec, double tol, tor_result *d_out,
+                                   void *stream) {
+    if (!ctx) return fail(TOR_EINVAL, "ctx is NULL");
+    if (m <= 0) return fail(TOR_EINVAL, "m must be positive (got %d)", m);
+    if (m > TOR_COND_MAX_MODES * 100) return fail(TOR_ETOOBIG, "m = %d too large", m);
+    if (nq < 0) return fail(TOR_EINVAL, "nq < 0");
+    if (prec != TOR_PREC_AUTO && prec != TOR_PREC_F64 && prec != TOR_PREC_DD)
+        return fail(TOR_EINVAL, "bad precision %d", (int)prec);
+    if (nq == 0) return TOR_OK;
+    if (!d_cov || !d_patterns || !d_out) return fail(TOR_EINVAL, "NULL device pointer");
+    if (nq > TOR_NOALLOC_MAX_QUERIES)
+        return fail(TOR_ETOOBIG, "nq = %d > %d queries per call", nq, TOR_NOALLOC_MAX_QUERIES);
+    std::string err;
+    void *ws = scratch_of(ctx->device, &err);
+    if (!ws) return fail(TOR_EDEVICE, "no scratch address for device %d: %s", ctx->device, err.c_str());
+    return batch_async_impl(ctx, nullptr, d_cov, m, nq, d_patterns, prec, tol, d_out, stream,
+                            (unsigned char *)ws, TOR_NOALLOC_SCRATCH_BYTES);
 }
 
 // ------------------------------------------------------------------ sampler
