@@ -473,6 +473,96 @@ tor_status tor_server_get_stats(tor_server *srv, tor_server_stats *out);
 /* Finish every pending query, then stop the workers and free the server. */
 tor_status tor_server_stop(tor_server *srv);
 
+/* ------------------------------------------------------------------------
+ * Persistent request loop: one long-running kernel on the device takes the
+ * work of probability queries and of sampling batches as they are submitted.
+ *
+ * Requests go, in submission order, into a ring of TOR_PS_SLOTS request slots
+ * in host-coherent memory.  The kernel's workgroups claim the work units of
+ * the published requests with atomic counters on the device (a probability
+ * query of n clicks: 2^g subtrees of its subset tree, the schedule (task
+ * modes, depth-first levels per unit) per n from the context's tuning table;
+ * a sampling batch: one chain per unit), so the units of a request that
+ * arrives while others are on the GPU start as soon as workgroups free up,
+ * and the work of different requests overlaps on the device.  The last unit
+ * of a request sums its partial results and sets the request's completion
+ * word (a system-scope release the host reads).  No unit waits for another;
+ * a workgroup waits only for new work, and the kernel exits on the stop flag
+ * or after idle_ms without work, and is launched again on demand (by submit
+ * and poll).
+ *
+ * Probability queries (Sec. II of the paper, as tor_probability): zero-mean
+ * states, marginal patterns (1 and -1 entries) and full patterns (1 and 0
+ * entries) of a state inverted by tor_state_invert; double-double terms.
+ * Every result is bitwise that of tor_batch on the same state and pattern
+ * with TOR_PREC_DD (same trees, tasks and reduction order), whatever else is
+ * in flight.  Sampling batches: chains chain_begin .. chain_begin + nchains - 1
+ * of gbs_sample / gbs_trace with the same (state, n_post, seed): the outcomes
+ * and statuses are bitwise gbs_trace's (binary64 terms); at most
+ * TOR_PS_CHAIN_CLICKS clicks per chain (n_post, and the cap of chains
+ * without postselection).
+ * Admission: a request is refused with TOR_EAGAIN when its ring slot is still
+ * held (poll results promptly: a slot is freed when its result is read), when
+ * its partial sums do not fit mem_budget_bytes of device memory (2^(n - J)
+ * task partials of 32 bytes), or when a batch's outputs do not fit the pinned
+ * chain buffer.  Thread-safe.  While the kernel runs it holds every CU it
+ * fits, so other work on the device waits for its idle exit.
+ * ------------------------------------------------------------------------ */
+
+#define TOR_PS_SLOTS 4096
+#define TOR_PS_CHAIN_CLICKS 15
+
+typedef struct tor_pserver tor_pserver;
+
+typedef struct {
+    double tol;                /* relative error target of the results' status; <= 0: 1e-10 */
+    size_t mem_budget_bytes;   /* device bytes for the partial sums of requests in flight (default 1 GiB) */
+    size_t chain_buffer_bytes; /* pinned host bytes for the outputs of sampling batches (default 64 MiB) */
+    int32_t grid;              /* workgroups of the kernel; 0: as many as fit the device at once */
+    int32_t idle_ms;           /* the kernel exits after this long without work (default 50) */
+} tor_pserver_opts;
+
+typedef struct {
+    int64_t submitted;
+    int64_t completed;
+    int64_t pending;   /* submitted and not yet read */
+    int64_t units;     /* work units published */
+    int64_t launches;  /* launches of the persistent kernel */
+    int32_t running;   /* 1 while the kernel runs */
+    int32_t reserved;
+} tor_pserver_stats;
+
+/* Start the loop on ctx's device (opts may be NULL) and launch its kernel.
+ * The server must be stopped before ctx or any state it serves is destroyed.
+ * Errors: TOR_EINVAL, TOR_ENOMEM, TOR_EDEVICE. */
+tor_status tor_pserver_start(tor_ctx *ctx, const tor_pserver_opts *opts, tor_pserver **out);
+/* Submit a probability query of state st (pattern as for tor_probability);
+ * *ticket names its result.  Errors: TOR_EINVAL (a displaced state, a pattern
+ * with no-click modes that is not a full pattern of an inverted state, a bad
+ * entry), TOR_ETOOBIG (more than 32 clicks), TOR_ENOTPD, TOR_EAGAIN (not
+ * admitted: try again after reading results). */
+tor_status tor_pserver_submit(tor_pserver *srv, const tor_state *st, const int8_t *pattern, uint64_t *ticket);
+/* Submit a sampling batch: chains chain_begin .. chain_begin + nchains - 1 of
+ * gbs_sample with postselection n_post (< 0: none) and seed on state st.
+ * Errors: TOR_EINVAL, TOR_ETOOBIG (n_post > TOR_PS_CHAIN_CLICKS, m > 1024),
+ * TOR_ENOTPD, TOR_ENOMEM, TOR_EAGAIN. */
+tor_status tor_pserver_submit_chains(tor_pserver *srv, const tor_state *st, int32_t n_post, uint64_t seed,
+                                     int64_t chain_begin, int32_t nchains, uint64_t *ticket);
+/* Result of a probability query: TOR_EAGAIN while pending (with wait != 0,
+ * block until ready); else fills *out (and the submit-to-result latency in
+ * seconds), frees the ticket and returns the result's status. */
+tor_status tor_pserver_poll(tor_pserver *srv, uint64_t ticket, int32_t wait, tor_result *out, double *latency_s);
+/* Result of a sampling batch: outcomes (host, nchains x m bytes 0/1) and
+ * status (host, nchains: 1 accepted, 0 rejected, 2 capped) as gbs_trace
+ * reports them; either may be NULL.  TOR_EAGAIN while pending (wait as for
+ * tor_pserver_poll). */
+tor_status tor_pserver_poll_chains(tor_pserver *srv, uint64_t ticket, int32_t wait, uint8_t *outcomes,
+                                   int8_t *status, double *latency_s);
+tor_status tor_pserver_get_stats(tor_pserver *srv, tor_pserver_stats *out);
+/* Finish every submitted request (unread results are dropped), set the stop
+ * flag, wait for the kernel to exit and free the server. */
+tor_status tor_pserver_stop(tor_pserver *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,17 @@ class _CServerStats(ctypes.Structure):
                 ("max_batch_seen", ctypes.c_int64), ("pending", ctypes.c_int64)]
 
 
+class _CPServerOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("mem_budget_bytes", ctypes.c_size_t),
+                ("chain_buffer_bytes", ctypes.c_size_t), ("grid", ctypes.c_int32), ("idle_ms", ctypes.c_int32)]
+
+
+class _CPServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("pending", ctypes.c_int64),
+                ("units", ctypes.c_int64), ("launches", ctypes.c_int64), ("running", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 @dataclass
 class Result:
     p: float
@@ -145,6 +156,15 @@ def lib():
         "tor_batch_async_noalloc": ([vp, vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int, ctypes.c_double, vp,
                                      vp], ctypes.c_int32),
         "tor_server_start": ([vp, ctypes.POINTER(_CServerOpts), ctypes.POINTER(vp)], ctypes.c_int32),
+        "tor_pserver_start": ([vp, ctypes.POINTER(_CPServerOpts), ctypes.POINTER(vp)], ctypes.c_int32),
+        "tor_pserver_submit": ([vp, vp, i8p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+        "tor_pserver_submit_chains": ([vp, vp, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+        "tor_pserver_poll": ([vp, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(_CResult), dp], ctypes.c_int32),
+        "tor_pserver_poll_chains": ([vp, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8), i8p, dp],
+                                    ctypes.c_int32),
+        "tor_pserver_get_stats": ([vp, ctypes.POINTER(_CPServerStats)], ctypes.c_int32),
+        "tor_pserver_stop": ([vp], ctypes.c_int32),
         "tor_submit": ([vp, vp, i8p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
         "tor_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(_CResult), dp], ctypes.c_int32),
         "tor_wait": ([vp, ctypes.c_uint64, ctypes.POINTER(_CResult), dp], ctypes.c_int32),
@@ -547,3 +567,84 @@ class Server:
 
     def __exit__(self, *exc):
         self.stop()
+
+
+class PServer:
+    """Persistent request loop (tor_pserver_*): one long-running kernel takes
+    probability queries and sampling batches as they are submitted.  Submit
+    from any thread; poll or wait for results (each with its submit-to-result
+    latency)."""
+
+    def __init__(self, ctx: Context, tol=1e-10, mem_budget_bytes=1 << 30, chain_buffer_bytes=64 << 20, grid=0,
+                 idle_ms=50):
+        o = _CPServerOpts(float(tol), int(mem_budget_bytes), int(chain_buffer_bytes), int(grid), int(idle_ms))
+        h = ctypes.c_void_p()
+        _check(lib().tor_pserver_start(ctx.handle, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+
+    def submit(self, state: State, pattern) -> int:
+        """Ticket of a probability query; raises TorError (TOR_EAGAIN: not admitted)."""
+        pattern = _i8(pattern)
+        if pattern.shape != (state.m,):
+            raise ValueError("pattern must have m entries")
+        t = ctypes.c_uint64()
+        _check(lib().tor_pserver_submit(self._h, state.handle, _i8ptr(pattern), ctypes.byref(t)))
+        return t.value
+
+    def submit_chains(self, state: State, n_post: int, seed: int, chain_begin: int, nchains: int) -> int:
+        """Ticket of a sampling batch (chains chain_begin .. + nchains - 1 of gbs_sample)."""
+        t = ctypes.c_uint64()
+        _check(lib().tor_pserver_submit_chains(self._h, state.handle, int(n_post), int(seed), int(chain_begin),
+                                               int(nchains), ctypes.byref(t)))
+        self._chains = getattr(self, "_chains", {})
+        self._chains[t.value] = (state.m, int(nchains))
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = False):
+        """(Result, latency_s) once done, else None (wait=False)."""
+        r = _CResult()
+        lat = ctypes.c_double()
+        st = lib().tor_pserver_poll(self._h, ticket, 1 if wait else 0, ctypes.byref(r), ctypes.byref(lat))
+        if st == TOR_EAGAIN:
+            return None
+        _check(st)
+        return Result._from(r), lat.value
+
+    def wait(self, ticket: int):
+        return self.poll(ticket, wait=True)
+
+    def poll_chains(self, ticket: int, wait: bool = False):
+        """(outcomes nchains x m uint8, status nchains int8, latency_s) once done, else None."""
+        m, nchains = self._chains[ticket]
+        outcomes = np.zeros((nchains, m), np.uint8)
+        status = np.zeros(nchains, np.int8)
+        lat = ctypes.c_double()
+        st = lib().tor_pserver_poll_chains(self._h, ticket, 1 if wait else 0,
+                                           outcomes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _i8ptr(status),
+                                           ctypes.byref(lat))
+        if st == TOR_EAGAIN:
+            return None
+        _check(st)
+        del self._chains[ticket]
+        return outcomes, status, lat.value
+
+    def wait_chains(self, ticket: int):
+        return self.poll_chains(ticket, wait=True)
+
+    def stats(self) -> dict:
+        s = _CPServerStats()
+        _check(lib().tor_pserver_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in _CPServerStats._fields_}
+
+    def stop(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            h, self._h = self._h, None
+            _check(lib().tor_pserver_stop(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()
+

@@ -8,6 +8,8 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <atomic>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -154,6 +156,10 @@ struct tor_ctx {
     int task_modes[2] = {11, 10};
     // autotuned task size per (precision, n); 0 = use task_modes
     int tuned[2][TOR_MAX_CLICKS + 1] = {};
+    // persistent-server schedule per n (double-double terms): task modes and
+    // depth-first levels per unit plus one; 0 = the default rule
+    int ps_J[TOR_MAX_CLICKS + 1] = {};
+    int ps_t1[TOR_MAX_CLICKS + 1] = {};
     int wave_grid = 65536;
     size_t mem_budget = (size_t)64 << 30;
     tor_stats stats{};
@@ -183,6 +189,7 @@ struct tor_state {
     dd det_rsqrt_mean = {1.0, 0.0};
     DevBuf dinv;   // device copy of the inverse in double-double words for tor_batch_async (first use)
     DevBuf dinvh;  // device copy of h (displaced states), likewise
+    DevBuf dK, dKoff;  // the sampler's K_j tables for the persistent server (first use)
     std::mutex dev_mu;  // guards the creation of the device copies (dcov, dmean)
 };
 
@@ -1853,12 +1860,14 @@ tor_status tor_state_create_displaced(tor_ctx *ctx, const double *cov, const dou
 
 void tor_state_destroy(tor_state *st) {
     if (!st) return;
-    if (st->dcov.p || st->dmean.p || st->dinv.p || st->dinvh.p) {
+    if (st->dcov.p || st->dmean.p || st->dinv.p || st->dinvh.p || st->dK.p || st->dKoff.p) {
         (void)hipSetDevice(st->device);
         st->dcov.release();
         st->dmean.release();
         st->dinv.release();
         st->dinvh.release();
+        st->dK.release();
+        st->dKoff.release();
         (void)hipGetLastError();  // leave no error for the next checked call
     }
     delete st;
@@ -3229,6 +3238,519 @@ tor_status tor_get_tuning(const tor_ctx *ctx, tor_prec prec, int32_t n, int32_t 
     if (n < 0 || n > TOR_MAX_CLICKS) return fail(TOR_EINVAL, "bad n");
     *task_modes = task_modes_for(ctx, prec == TOR_PREC_DD, n);
     return TOR_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ persistent server
+
+namespace {
+
+// First-fit allocator of index ranges (the partial arena, the chain output buffer).
+struct RangeAlloc {
+    std::map<size_t, size_t> free_;  // offset -> length
+    void reset(size_t total) {
+        free_.clear();
+        if (total) free_[0] = total;
+    }
+    size_t alloc(size_t len) {
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= len) {
+                const size_t off = it->first, rest = it->second - len;
+                free_.erase(it);
+                if (rest) free_[off + len] = rest;
+                return off;
+            }
+        return SIZE_MAX;
+    }
+    void release(size_t off, size_t len) {
+        if (!len) return;
+        auto it = free_.emplace(off, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+// Schedule of an n-mode tree in the persistent kernel: task modes J and the
+// depth-first levels t of a unit (units = 2^(n - J - t)).  Tuned per n, else
+// J as the batched path (at most TOR_PS_TASK_MAX) and t leaving 4096 units.
+void ps_schedule(const tor_ctx *ctx, int n, int &J, int &t) {
+    J = ctx->ps_J[n] > 0 ? ctx->ps_J[n] : std::min(task_modes_for(ctx, true, n), TOR_PS_TASK_MAX);
+    J = std::min(J, n);
+    const int G = n - J;
+    t = ctx->ps_t1[n] > 0 ? ctx->ps_t1[n] - 1 : std::max(0, G - 12);
+    t = std::max(0, std::min({t, G, TOR_PS_LMAX}));
+}
+
+// Partials a request needs: one per task, then every reduction stage's.
+size_t ps_parts(long long tasks) {
+    size_t total = (size_t)tasks;
+    for (long long c = tasks; c > 1;) {
+        c = (c + TOR_REDUCE_CHUNK - 1) / TOR_REDUCE_CHUNK;
+        total += (size_t)c;
+    }
+    return total;
+}
+
+// The device copy of an inverted state's inverse in double-double words.
+tor_status state_inverse_on_device(const tor_state *st) {
+    tor_state *ms = const_cast<tor_state *>(st);
+    std::lock_guard<std::mutex> lk(ms->dev_mu);
+    if (ms->dinv.p) return TOR_OK;
+    const size_t ent = (size_t)E(st->m);
+    std::vector<dd> h(ent);
+    for (size_t e = 0; e < ent; e++) h[e] = st->inv_prec == TOR_PREC_QD ? qd_to_dd(st->inv_q[e]) : st->inv[e];
+    if (ms->dinv.ensure(ent * sizeof(dd)) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the inverse failed");
+    HIP_TRY(hipMemcpy(ms->dinv.p, h.data(), ent * sizeof(dd), hipMemcpyHostToDevice));
+    return TOR_OK;
+}
+
+// The sampler's K_j tables of a zero-mean state on the device (made once).
+tor_status state_chain_tables(const tor_state *st) {
+    tor_state *ms = const_cast<tor_state *>(st);
+    std::lock_guard<std::mutex> lk(ms->dev_mu);
+    if (ms->dK.p) return TOR_OK;
+    std::vector<double> K;
+    std::vector<unsigned long long> koff;
+    tor_status s = build_k_tables(st->cov.data(), st->m, K, koff);
+    if (s) return s;
+    if (ms->dK.ensure(K.size() * sizeof(double)) != hipSuccess ||
+        ms->dKoff.ensure(koff.size() * sizeof(unsigned long long)) != hipSuccess) {
+        ms->dK.release();
+        ms->dKoff.release();
+        return fail(TOR_ENOMEM, "device allocation of the K tables failed");
+    }
+    HIP_TRY(hipMemcpy(ms->dK.p, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ms->dKoff.p, koff.data(), koff.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
+    return TOR_OK;
+}
+
+struct PsEntry {  // host bookkeeping of a ticket
+    int type = TOR_PS_PROB;
+    bool host_only = false;       // finished on the host (no clicks): res holds the result
+    unsigned long long seq = 0;   // the request's index in the ring
+    Prepared prep;                // probability: what the result's assembly needs
+    size_t part_off = 0, part_len = 0;  // probability: partials in the arena
+    size_t out_off = 0, out_len = 0;    // chains: outputs in the pinned buffer
+    int m = 0, nchains = 0;
+    tor_result res{};
+    std::chrono::steady_clock::time_point t0;
+};
+
+}  // namespace
+
+struct tor_pserver {
+    tor_ctx *ctx = nullptr;
+    int device = 0;
+    hipStream_t kst = nullptr;
+    PsHost *host = nullptr;
+    PsReq *ring = nullptr;
+    PsResult *res = nullptr;
+    unsigned char *outbuf = nullptr;
+    size_t outbuf_bytes = 0;
+    DevBuf dev, scratch, arena;
+    RangeAlloc parts, outs;
+    PsParams params{};
+    int grid = 0;
+    double tol = 1e-10;
+    std::mutex mu;
+    unsigned long long next_seq = 0;        // next request index to publish
+    uint64_t next_ticket = 1;
+    std::unordered_map<uint64_t, PsEntry> live;
+    uint64_t slot_ticket[TOR_PS_SLOTS] = {};  // ticket whose request holds the slot (0: free)
+    tor_pserver_stats stats{};
+};
+
+namespace {
+
+// Launch the persistent kernel unless it is running (S->mu held).
+tor_status ps_ensure_running(tor_pserver *S) {
+    const hipError_t q = hipStreamQuery(S->kst);
+    if (q == hipErrorNotReady) return TOR_OK;
+    if (q != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TOR_EDEVICE, "persistent kernel failed: %s", hipGetErrorString(q));
+    }
+    HIP_TRY(hipSetDevice(S->device));
+    HIP_TRY(tor_launch_pserver(S->params, S->grid, S->kst));
+    S->stats.launches++;
+    return TOR_OK;
+}
+
+// Claim the next ring slot and publish a filled request (S->mu held).
+tor_status ps_publish(tor_pserver *S, PsReq &rq, PsEntry &&e, uint64_t *ticket) {
+    const unsigned long long seq = S->next_seq;
+    const int slot = (int)(seq % TOR_PS_SLOTS);
+    rq.seq = (long long)seq;
+    PsReq *dst = &S->ring[slot];
+    std::memcpy((char *)dst + sizeof(long long), (const char *)&rq + sizeof(long long), sizeof(PsReq) - sizeof(long long));
+    std::atomic_thread_fence(std::memory_order_release);
+    __atomic_store_n(&dst->seq, (long long)seq, __ATOMIC_RELEASE);
+    __atomic_store_n(&S->host->published, seq + 1, __ATOMIC_RELEASE);
+    S->next_seq = seq + 1;
+    e.seq = seq;
+    e.t0 = std::chrono::steady_clock::now();
+    const uint64_t t = S->next_ticket++;
+    S->slot_ticket[slot] = t;
+    S->live.emplace(t, std::move(e));
+    *ticket = t;
+    S->stats.submitted++;
+    return ps_ensure_running(S);
+}
+
+// A ticket's request finished on the device (S->mu held)?
+bool ps_done(const tor_pserver *S, const PsEntry &e) {
+    if (e.host_only) return true;
+    const int slot = (int)(e.seq % TOR_PS_SLOTS);
+    return __atomic_load_n(&S->res[slot].done, __ATOMIC_ACQUIRE) == e.seq + 1;
+}
+
+void ps_release(tor_pserver *S, uint64_t ticket, PsEntry &e) {
+    if (!e.host_only) {
+        S->slot_ticket[e.seq % TOR_PS_SLOTS] = 0;
+        S->parts.release(e.part_off, e.part_len);
+        S->outs.release(e.out_off, e.out_len);
+    }
+    S->stats.completed++;
+    S->live.erase(ticket);
+}
+
+}  // namespace
+
+extern "C" {
+
+tor_status tor_pserver_start(tor_ctx *ctx, const tor_pserver_opts *opts, tor_pserver **out) {
+    if (!ctx || !out) return fail(TOR_EINVAL, "NULL argument");
+    *out = nullptr;
+    tor_pserver_opts o{};
+    o.tol = 1e-10;
+    o.mem_budget_bytes = (size_t)1 << 30;
+    o.chain_buffer_bytes = (size_t)64 << 20;
+    o.grid = 0;
+    o.idle_ms = 50;
+    if (opts) {
+        if (opts->tol > 0) o.tol = opts->tol;
+        if (opts->mem_budget_bytes > 0) o.mem_budget_bytes = opts->mem_budget_bytes;
+        if (opts->chain_buffer_bytes > 0) o.chain_buffer_bytes = opts->chain_buffer_bytes;
+        if (opts->grid < 0 || opts->idle_ms < 0) return fail(TOR_EINVAL, "negative grid or idle time");
+        o.grid = opts->grid;
+        if (opts->idle_ms > 0) o.idle_ms = opts->idle_ms;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::unique_ptr<tor_pserver> S(new (std::nothrow) tor_pserver());
+    if (!S) return fail(TOR_ENOMEM, "host allocation failed");
+    S->ctx = ctx;
+    S->device = ctx->device;
+    S->tol = o.tol;
+    const int occ = tor_pserver_occupancy(ctx->device);
+    if (occ < 1) return fail(TOR_EDEVICE, "the persistent kernel does not fit the device");
+    S->grid = o.grid > 0 ? std::min(o.grid, occ) : occ;
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
+    if (khz <= 0) return fail(TOR_EDEVICE, "no wall clock rate");
+    auto cleanup = [&]() {
+        if (S->kst) (void)hipStreamDestroy(S->kst);
+        if (S->host) (void)hipHostFree(S->host);
+        if (S->ring) (void)hipHostFree(S->ring);
+        if (S->res) (void)hipHostFree(S->res);
+        if (S->outbuf) (void)hipHostFree(S->outbuf);
+        S->dev.release();
+        S->scratch.release();
+        S->arena.release();
+        (void)hipGetLastError();
+    };
+    // host-coherent ring, results, control block and chain outputs
+    if (hipHostMalloc((void **)&S->host, sizeof(PsHost), hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void **)&S->ring, sizeof(PsReq) * TOR_PS_SLOTS, hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void **)&S->res, sizeof(PsResult) * TOR_PS_SLOTS, hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void **)&S->outbuf, o.chain_buffer_bytes, hipHostMallocCoherent) != hipSuccess) {
+        cleanup();
+        return fail(TOR_ENOMEM, "pinned allocation of the request ring failed");
+    }
+    S->outbuf_bytes = o.chain_buffer_bytes;
+    std::memset(S->host, 0, sizeof(PsHost));
+    std::memset(S->ring, 0, sizeof(PsReq) * TOR_PS_SLOTS);
+    for (int i = 0; i < TOR_PS_SLOTS; i++) S->ring[i].seq = -1;
+    std::memset(S->res, 0, sizeof(PsResult) * TOR_PS_SLOTS);
+    // device state, per-workgroup scratch and the partial arena
+    const size_t scratch_bytes = (size_t)S->grid * TOR_PS_SCRATCH_WORDS * sizeof(dd);
+    if (S->dev.ensure(sizeof(PsDev)) != hipSuccess || S->scratch.ensure(scratch_bytes) != hipSuccess ||
+        S->arena.ensure(o.mem_budget_bytes) != hipSuccess) {
+        cleanup();
+        return fail(TOR_ENOMEM, "device allocation of the persistent server failed");
+    }
+    S->parts.reset(o.mem_budget_bytes / sizeof(Partial));
+    S->outs.reset(o.chain_buffer_bytes);
+    if (hipStreamCreateWithFlags(&S->kst, hipStreamNonBlocking) != hipSuccess) {
+        cleanup();
+        return fail(TOR_EDEVICE, "hipStreamCreate failed");
+    }
+    {
+        std::vector<unsigned char> init(sizeof(PsDev), 0);
+        PsDev *d = reinterpret_cast<PsDev *>(init.data());
+        for (int i = 0; i < TOR_PS_SLOTS; i++) d->next[i] = (unsigned long long)i << 32;
+        if (hipMemcpy(S->dev.p, init.data(), init.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            cleanup();
+            return fail(TOR_EDEVICE, "initialising the persistent server failed");
+        }
+    }
+    PsParams &P = S->params;
+    P.host = S->host;
+    P.ring = S->ring;
+    P.res = S->res;
+    P.dev = (PsDev *)S->dev.p;
+    P.scratch = (dd *)S->scratch.p;
+    P.scratch_stride = TOR_PS_SCRATCH_WORDS;
+    P.idle_ticks = (long long)o.idle_ms * khz;
+    P.refresh_ticks = std::max(1LL, (long long)khz * 2 / 1000);  // 2 us
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (ps_ensure_running(S.get()) != TOR_OK) {
+            std::string msg = g_err;
+            cleanup();
+            return fail(TOR_EDEVICE, "%s", msg.c_str());
+        }
+    }
+    *out = S.release();
+    return TOR_OK;
+}
+
+tor_status tor_pserver_submit(tor_pserver *S, const tor_state *st, const int8_t *pattern, uint64_t *ticket) {
+    if (!S || !st || !pattern || !ticket) return fail(TOR_EINVAL, "NULL argument");
+    if (st->ctx != S->ctx) return fail(TOR_EINVAL, "state belongs to another context");
+    if (!st->mean.empty()) return fail(TOR_EINVAL, "displaced states are served by tor_submit");
+    const int m = st->m;
+    bool zero = false;
+    for (int i = 0; i < m; i++) {
+        if (pattern[i] < -1 || pattern[i] > 1) return fail(TOR_EINVAL, "pattern[%d] = %d", i, (int)pattern[i]);
+        zero |= pattern[i] == 0;
+    }
+    const bool jac = zero && is_full_pattern(pattern, m);
+    if (zero && !(jac && st->inv_prec))
+        return fail(TOR_EINVAL, "a pattern with no-click modes needs a full pattern of an inverted state "
+                                "(tor_state_invert), or tor_submit");
+    HIP_TRY(hipSetDevice(S->device));
+    Reduced red;
+    tor_status s = jac ? reduce_pattern_jacobi(st, pattern, red) : reduce_pattern(st->cov.data(), m, pattern, red);
+    if (s) return s;
+    PsEntry e;
+    e.type = TOR_PS_PROB;
+    s = prepare_reduced(red, e.prep);
+    if (s) return s;
+    const int n = red.n;
+    if (n == 0) {  // nothing to sum: the result is known on the host
+        SumOut so;
+        finalize(e.prep, so, TOR_PREC_DD, S->tol, &e.res);
+        e.host_only = true;
+        e.t0 = std::chrono::steady_clock::now();
+        std::lock_guard<std::mutex> lk(S->mu);
+        *ticket = S->next_ticket++;
+        S->live.emplace(*ticket, std::move(e));
+        S->stats.submitted++;
+        return TOR_OK;
+    }
+    s = jac ? state_inverse_on_device(st) : state_on_device(st);
+    if (s) return s;
+    int J, t;
+    PsReq rq{};
+    rq.type = TOR_PS_PROB;
+    rq.n = n;
+    rq.m = m;
+    rq.jac = jac ? 1 : 0;
+    rq.cov = (const double *)st->dcov.p;
+    rq.inv = jac ? (const dd *)st->dinv.p : nullptr;
+    std::lock_guard<std::mutex> lk(S->mu);
+    ps_schedule(S->ctx, n, J, t);
+    const int G = n - J, g = G - t;
+    rq.J = J;
+    rq.g = g;
+    rq.t = t;
+    rq.units = 1LL << g;
+    rq.tasks = 1LL << G;
+    int k = 0;
+    for (int i = 0; i < m; i++)
+        if (pattern[i] == 1) rq.C[k++] = i;
+    if (S->slot_ticket[S->next_seq % TOR_PS_SLOTS]) return fail(TOR_EAGAIN, "request ring full");
+    e.part_len = ps_parts(rq.tasks);
+    e.part_off = S->parts.alloc(e.part_len);
+    if (e.part_off == SIZE_MAX) {
+        e.part_len = 0;
+        return fail(TOR_EAGAIN, "not admitted: partial sums of %zu bytes do not fit", ps_parts(rq.tasks) * sizeof(Partial));
+    }
+    rq.part = (Partial *)S->arena.p + e.part_off;
+    S->stats.units += rq.units;
+    return ps_publish(S, rq, std::move(e), ticket);
+}
+
+tor_status tor_pserver_submit_chains(tor_pserver *S, const tor_state *st, int32_t n_post, uint64_t seed,
+                                     int64_t chain_begin, int32_t nchains, uint64_t *ticket) {
+    if (!S || !st || !ticket) return fail(TOR_EINVAL, "NULL argument");
+    if (st->ctx != S->ctx) return fail(TOR_EINVAL, "state belongs to another context");
+    if (!st->mean.empty()) return fail(TOR_EINVAL, "displaced states are sampled by gbs_sample_displaced");
+    if (nchains < 1 || chain_begin < 0) return fail(TOR_EINVAL, "bad chain range");
+    const int m = st->m;
+    if (m > 1024) return fail(TOR_ETOOBIG, "m = %d > 1024 for the sampler", m);
+    if (n_post > TOR_CHAIN_MAX - 1) return fail(TOR_ETOOBIG, "n_post = %d > %d", n_post, TOR_CHAIN_MAX - 1);
+    if (n_post > m) return fail(TOR_EINVAL, "n_post > m");
+    HIP_TRY(hipSetDevice(S->device));
+    tor_status s = state_chain_tables(st);
+    if (s) return s;
+    PsEntry e;
+    e.type = TOR_PS_CHAINS;
+    e.m = m;
+    e.nchains = nchains;
+    e.out_len = (size_t)nchains * (size_t)(m + 1);
+    PsReq rq{};
+    rq.type = TOR_PS_CHAINS;
+    rq.m = m;
+    rq.units = nchains;
+    ChainParams &P = rq.cp;
+    P.K = (const double *)st->dK.p;
+    P.koff = (const unsigned long long *)st->dKoff.p;
+    P.H = nullptr;
+    P.hoff = nullptr;
+    P.m = m;
+    P.n_post = n_post;
+    P.cap = n_post >= 0 ? n_post : std::min(S->ctx->chain_clicks, TOR_CHAIN_MAX - 1);
+    P.seed = seed;
+    P.chain_begin = chain_begin;
+    P.nchains = nchains;
+    P.trace_p = nullptr;
+    P.trace_u = nullptr;
+    P.subsets = nullptr;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->slot_ticket[S->next_seq % TOR_PS_SLOTS]) return fail(TOR_EAGAIN, "request ring full");
+    e.out_off = S->outs.alloc(e.out_len);
+    if (e.out_off == SIZE_MAX) {
+        e.out_len = 0;
+        return fail(TOR_EAGAIN, "not admitted: chain outputs do not fit the pinned buffer");
+    }
+    P.outcome = S->outbuf + e.out_off;
+    P.status = (signed char *)(S->outbuf + e.out_off + (size_t)nchains * m);
+    S->stats.units += nchains;
+    return ps_publish(S, rq, std::move(e), ticket);
+}
+
+tor_status tor_pserver_poll(tor_pserver *S, uint64_t ticket, int32_t wait, tor_result *out, double *latency_s) {
+    if (!S || !out) return fail(TOR_EINVAL, "NULL argument");
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            auto it = S->live.find(ticket);
+            if (it == S->live.end()) return fail(TOR_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+            PsEntry &e = it->second;
+            if (e.type != TOR_PS_PROB) return fail(TOR_EINVAL, "ticket %llu is a sampling request", (unsigned long long)ticket);
+            if (ps_done(S, e)) {
+                if (!e.host_only) {
+                    const PsResult &r = S->res[e.seq % TOR_PS_SLOTS];
+                    SumOut so;
+                    so.T = dd_make(r.t_hi, r.t_lo);
+                    so.A = r.a;
+                    if (!std::isfinite(so.T.hi) || !std::isfinite(so.A)) {
+                        std::memset(&e.res, 0, sizeof e.res);
+                        e.res.status = TOR_ENOTPD;
+                    } else {
+                        finalize(e.prep, so, TOR_PREC_DD, S->tol, &e.res);
+                    }
+                }
+                *out = e.res;
+                if (latency_s)
+                    *latency_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - e.t0).count();
+                const tor_status st = e.res.status;
+                ps_release(S, ticket, e);
+                return st;
+            }
+            tor_status s = ps_ensure_running(S);
+            if (s) return s;
+        }
+        if (!wait) return TOR_EAGAIN;
+        std::this_thread::yield();
+    }
+}
+
+tor_status tor_pserver_poll_chains(tor_pserver *S, uint64_t ticket, int32_t wait, uint8_t *outcomes,
+                                   int8_t *status, double *latency_s) {
+    if (!S) return fail(TOR_EINVAL, "NULL argument");
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            auto it = S->live.find(ticket);
+            if (it == S->live.end()) return fail(TOR_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+            PsEntry &e = it->second;
+            if (e.type != TOR_PS_CHAINS) return fail(TOR_EINVAL, "ticket %llu is a probability query", (unsigned long long)ticket);
+            if (ps_done(S, e)) {
+                const unsigned char *o = S->outbuf + e.out_off;
+                if (outcomes) std::memcpy(outcomes, o, (size_t)e.nchains * e.m);
+                if (status) std::memcpy(status, o + (size_t)e.nchains * e.m, (size_t)e.nchains);
+                if (latency_s)
+                    *latency_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - e.t0).count();
+                ps_release(S, ticket, e);
+                return TOR_OK;
+            }
+            tor_status s = ps_ensure_running(S);
+            if (s) return s;
+        }
+        if (!wait) return TOR_EAGAIN;
+        std::this_thread::yield();
+    }
+}
+
+tor_status tor_pserver_get_stats(tor_pserver *S, tor_pserver_stats *out) {
+    if (!S || !out) return fail(TOR_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->stats;
+    out->pending = (int64_t)S->live.size();
+    out->running = hipStreamQuery(S->kst) == hipErrorNotReady ? 1 : 0;
+    (void)hipGetLastError();
+    return TOR_OK;
+}
+
+tor_status tor_pserver_stop(tor_pserver *S) {
+    if (!S) return fail(TOR_EINVAL, "NULL argument");
+    (void)hipSetDevice(S->device);
+    tor_status first = TOR_OK;
+    // finish every published request (their results are dropped if not polled)
+    for (;;) {
+        bool pending = false;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (auto &kv : S->live)
+                if (!ps_done(S, kv.second)) pending = true;
+            if (pending) {
+                tor_status s = ps_ensure_running(S);
+                if (s) {
+                    first = s;
+                    break;
+                }
+            }
+        }
+        if (!pending) break;
+        std::this_thread::yield();
+    }
+    __atomic_store_n(&S->host->stop, 1u, __ATOMIC_RELEASE);
+    const hipError_t e = hipStreamSynchronize(S->kst);
+    if (e != hipSuccess && first == TOR_OK) first = fail(TOR_EDEVICE, "persistent kernel: %s", hipGetErrorString(e));
+    (void)hipStreamDestroy(S->kst);
+    (void)hipHostFree(S->host);
+    (void)hipHostFree(S->ring);
+    (void)hipHostFree(S->res);
+    (void)hipHostFree(S->outbuf);
+    S->dev.release();
+    S->scratch.release();
+    S->arena.release();
+    (void)hipGetLastError();
+    delete S;
+    return first;
 }
 
 }  // extern "C"

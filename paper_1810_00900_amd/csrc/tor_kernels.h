@@ -217,3 +217,72 @@ struct ChainParams {
 };
 
 hipError_t tor_launch_chains(const ChainParams &P, int grid_cap, hipStream_t st);
+
+// ---- persistent request loop (tor_pserver.hip)
+// Requests are published in order into a ring of TOR_PS_SLOTS slots in
+// host-coherent memory; request k uses slot k % TOR_PS_SLOTS.  Workgroups of
+// the persistent kernel claim the units of the request being distributed with
+// a compare-and-swap on the slot's counter, which carries the request's
+// sequence number, so a unit is never claimed twice and never for a request
+// that is not yet published.  No unit waits for another: the last unit of a
+// request (counted per slot) reduces and publishes its result.
+#define TOR_PS_SLOTS 4096
+#define TOR_PS_LMAX 8  // most depth-first levels a probability unit walks
+#define TOR_PS_TASK_MAX 10  // largest wave-tier task of the persistent kernel (modes)
+
+enum { TOR_PS_PROB = 1, TOR_PS_CHAINS = 2 };
+
+struct PsReq {             // host-coherent; the host writes every field, then seq, then publishes
+    long long seq;         // request index
+    int type;              // TOR_PS_PROB or TOR_PS_CHAINS
+    int n, J, g;           // probability: clicks, task modes (<= n), unit depth (units = 2^g)
+    int t;                 // probability: depth-first levels of a unit (tasks per unit = 2^t)
+    int m, jac;            // modes of the state; 1: gather G from the inverse (a full pattern)
+    long long units;       // work units of the request
+    long long tasks;       // probability: wave tasks, 2^(g + t)
+    const double *cov;     // device: the state's covariance, 2m x 2m row-major (jac = 0)
+    const dd *inv;         // device: the state's inverse, packed lower, double-double words (jac = 1)
+    Partial *part;         // device: task partials, then the reduction stages
+    ChainParams cp;        // chains: parameters of chains cp.chain_begin .. + units (outputs host-coherent)
+    int C[TOR_MAX_N];      // probability: clicked modes, ascending
+};
+
+struct PsResult {          // host-coherent, one per slot
+    unsigned long long done;  // seq + 1 once the request is complete
+    double t_hi, t_lo, a;     // probability: the subset sum T and the sum of |terms|
+};
+
+struct PsHost {            // host-coherent control block
+    unsigned long long published;  // requests 0 .. published - 1 are in the ring
+    unsigned int stop;             // 1: the kernel exits once it has no work
+    unsigned int pad;
+};
+
+struct PsDev {             // device memory (zeroed, next[s] = s << 32, before the first launch)
+    unsigned long long cur;        // request whose units are being claimed
+    unsigned long long pub;        // the kernel's copy of PsHost::published
+    unsigned long long refresh;    // wall-clock time of the last copy
+    unsigned int stop;             // the kernel's copy of PsHost::stop
+    unsigned int pad;
+    unsigned long long next[TOR_PS_SLOTS];  // (seq << 32) | next unit of the slot's request
+    unsigned int done[TOR_PS_SLOTS];        // finished units of the slot's request
+};
+
+struct PsParams {
+    PsHost *host;
+    PsReq *ring;                // [TOR_PS_SLOTS]
+    PsResult *res;              // [TOR_PS_SLOTS]
+    PsDev *dev;
+    dd *scratch;                // per-workgroup buffers of the depth-first walk
+    long long scratch_stride;   // double-double words per workgroup
+    long long idle_ticks;       // a workgroup exits after this long (wall clock) without work
+    long long refresh_ticks;    // the control block is read at most this often
+};
+
+// words of per-workgroup scratch: the root, two prefix buffers and one per level
+#define TOR_PS_SCRATCH_WORDS ((3 + TOR_PS_LMAX) * (TOR_MAX_N * (2 * TOR_MAX_N + 1)))
+
+hipError_t tor_launch_pserver(const PsParams &P, int grid, hipStream_t st);
+// workgroups of the persistent kernel that fit the device at once
+int tor_pserver_occupancy(int device);
+

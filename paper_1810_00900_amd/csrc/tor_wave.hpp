@@ -28,6 +28,16 @@ template <class S, int J, int D> struct WaveOcc {
                                  : sizeof(WaveSmem<S, J, D>) + 512 <= 20480 ? 2 : 1;
 };
 
+// One wave-tier task of J <= 9 modes: the node's matrix at root (global
+// memory) with path coefficient (c, a); every lane returns the task's (T, A).
+template <class S, int J, int D>
+__device__ __forceinline__ void wave_task(WaveSmem<S, J, D> &sm, const S *root, dd c, double a, int lane, dd &T,
+                                          double &A) {
+    for (int e = lane; e < EN(J, MR(D)); e += 64) sm.mat[e] = root[e];
+    wave_tree<S, J, D>(sm, c, a, lane, T, A);
+    wave_reduce(T, A);
+}
+
 template <class S, int J, int D>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, J, D>::value))) void wave_kernel(
     const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool,
@@ -43,12 +53,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, J
         const int j = find_job(jobs, njobs, t);
         const long long lt = t - jobs[j].begin;
         NodeDesc d = jobs[j].tasks[lt];
-        const S *root = pool + d.off;
-        for (int e = lane; e < EN(J, MR(D)); e += 64) sm.mat[e] = root[e];
         dd T;
         double A;
-        wave_tree<S, J, D>(sm, dd_make(d.coef_hi, d.coef_lo), d.acoef, lane, T, A);
-        wave_reduce(T, A);
+        wave_task<S, J, D>(sm, pool + d.off, dd_make(d.coef_hi, d.coef_lo), d.acoef, lane, T, A);
         if (lane == 0) {
             Partial p;
             p.t_hi = T.hi;
@@ -118,12 +125,37 @@ __device__ __forceinline__ void top10(TopSmem<S, D, NT> &sm, dd c, double a, int
     A += x;
 }
 
+// One wave-tier task of J = 10 or 11 modes (the node's matrix at root, which
+// stays readable: the 11-mode task rebuilds its include child from it); every
+// lane returns the task's (T, A).
+template <class S, int J, int D>
+__device__ __forceinline__ void wave_task_top(TopSmem<S, D, J - 9> &sm, const S *root, dd c0, double a0, int lane,
+                                              dd &T, double &A) {
+    static_assert(J == 10 || J == 11, "top levels: one or two");
+    static_assert(WaveCfg<S, 9, D>::MAT >= EN(J, MR(D)), "the task's matrix must fit the nine-mode working set");
+    for (int e = lane; e < EN(J, MR(D)); e += 64) sm.w.mat[e] = root[e];
+    wave_sync();
+    T = dd_from(0.0);
+    A = 0.0;
+    if constexpr (J == 10) {
+        top10<S, D, J - 9>(sm, c0, a0, lane, T, A);
+    } else {
+        S *v = sm.vtop[1];
+        const Pivot<S> pv = top_columns<S, 11, D>(sm.w.mat, v, lane);
+        wave_sync();
+        top10<S, D, J - 9>(sm, c0, a0, lane, T, A);
+        wave_sync();
+        top_update<S, 11, D>(root, sm.w.mat, v, lane);
+        wave_sync();
+        top10<S, D, J - 9>(sm, dd_neg(coef_mul(c0, pv.q)), a0 * hi_of(pv.q), lane, T, A);
+    }
+    wave_reduce(T, A);
+}
+
 template <class S, int J, int D>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9, D>::value))) void wave_kernel_top(
     const WaveJob *__restrict__ jobs, int njobs, long long total, const S *__restrict__ pool,
     const LaunchDims *__restrict__ dyn) {
-    static_assert(J == 10 || J == 11, "top levels: one or two");
-    static_assert(WaveCfg<S, 9, D>::MAT >= EN(J, MR(D)), "the task's matrix must fit the nine-mode working set");
     __shared__ TopSmem<S, D, J - 9> sm;
     const int lane = threadIdx.x;
     if (dyn) {
@@ -135,25 +167,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WaveOcc<S, 9
         const int j = find_job(jobs, njobs, t);
         const long long lt = t - jobs[j].begin;
         NodeDesc d = jobs[j].tasks[lt];
-        const S *root = pool + d.off;
-        for (int e = lane; e < EN(J, MR(D)); e += 64) sm.w.mat[e] = root[e];
-        wave_sync();
-        const dd c0 = dd_make(d.coef_hi, d.coef_lo);
-        dd T = dd_from(0.0);
-        double A = 0.0;
-        if constexpr (J == 10) {
-            top10<S, D, J - 9>(sm, c0, d.acoef, lane, T, A);
-        } else {
-            S *v = sm.vtop[1];
-            const Pivot<S> pv = top_columns<S, 11, D>(sm.w.mat, v, lane);
-            wave_sync();
-            top10<S, D, J - 9>(sm, c0, d.acoef, lane, T, A);
-            wave_sync();
-            top_update<S, 11, D>(root, sm.w.mat, v, lane);
-            wave_sync();
-            top10<S, D, J - 9>(sm, dd_neg(coef_mul(c0, pv.q)), d.acoef * hi_of(pv.q), lane, T, A);
-        }
-        wave_reduce(T, A);
+        dd T;
+        double A;
+        wave_task_top<S, J, D>(sm, pool + d.off, dd_make(d.coef_hi, d.coef_lo), d.acoef, lane, T, A);
         if (lane == 0) {
             Partial p;
             p.t_hi = T.hi;
