@@ -14,6 +14,7 @@ CPU oracle timed on a bounded sample of the same sum.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 28]
 """
 import argparse
+import collections
 import json
 import os
 import sys
@@ -431,24 +432,36 @@ def serving_bench(ctx, nq=10000, workers=2):
         srv = make()
         arr = arrivals(rate)
         t0 = time.perf_counter()
-        tickets, ctk = [], []
+        pending = collections.deque()  # (kind, ticket) in submission order
+        res, cres = [], []
+
+        def read_oldest():
+            kind, t = pending.popleft()
+            if kind == "p":
+                res.append(srv.wait(t))
+            else:
+                cres.append(srv.wait_chains(t))
+
+        def submit(fn, *a):
+            while True:
+                try:
+                    return fn(*a)
+                except tg.TorError as e:  # not admitted (ring or memory full): read a result, retry
+                    if e.status != tg.TOR_EAGAIN or not pending:
+                        raise
+                    read_oldest()
+
         for k, (s, n, p) in enumerate(qs):
             if arr is not None:
                 while time.perf_counter() - t0 < arr[k]:
                     pass
-            while True:
-                try:
-                    tickets.append(srv.submit(sts[s], p))
-                    break
-                except tg.TorError as e:  # not admitted yet: read a result, then retry
-                    if e.status != tg.TOR_EAGAIN:
-                        raise
-                    time.sleep(1e-4)
+            pending.append(("p", submit(srv.submit, sts[s], p)))
             if chains and k % chains["every"] == 0:
-                ctk.append(srv.submit_chains(chains["state"], chains["n_post"], 2, chains["next"], chains["batch"]))
+                pending.append(("c", submit(srv.submit_chains, chains["state"], chains["n_post"], 2, chains["next"],
+                                            chains["batch"])))
                 chains["next"] += chains["batch"]
-        res = [srv.wait(t) for t in tickets]
-        cres = [srv.wait_chains(t) for t in ctk]
+        while pending:
+            read_oldest()
         T = time.perf_counter() - t0
         st = srv.stats()
         srv.stop()
@@ -492,18 +505,24 @@ def serving_bench(ctx, nq=10000, workers=2):
     res = {"workload": "10^4 queries, n ~ U{8..24}, marginal click sets, 4 states m=800 (seeds 30-33), "
                        "queries seed 34, dd terms, tol 1e-10; Poisson arrivals seed 35 at fractions of the "
                        "persistent loop's closed-loop rate"}
-    res["persistent_closed_loop"] = run_server(persistent, None)
+    def phase(name, fn, *a):
+        t = time.perf_counter()
+        print(f"[bench] serving: {name} ...", file=sys.stderr, flush=True)
+        res[name] = fn(*a)
+        print(f"[bench] serving: {name} done in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+
+    phase("persistent_closed_loop", run_server, persistent, None)
     X = res["persistent_closed_loop"]["queries_per_s"]
-    res["served_closed_loop"] = run_server(hostworkers, None)
-    res["one_per_launch_closed_loop"] = single(None)
+    phase("served_closed_loop", run_server, hostworkers, None)
+    phase("one_per_launch_closed_loop", single, None)
     for f in (0.5, 0.8):
-        res[f"persistent_poisson_{f}x"] = run_server(persistent, f * X)
-        res[f"served_poisson_{f}x"] = run_server(hostworkers, f * X)
-        res[f"one_per_launch_poisson_{f}x"] = single(f * X)
+        phase(f"persistent_poisson_{f}x", run_server, persistent, f * X)
+        phase(f"served_poisson_{f}x", run_server, hostworkers, f * X)
+        phase(f"one_per_launch_poisson_{f}x", single, f * X)
     res["poisson_rates_qps"] = {"0.5x": 0.5 * X, "0.8x": 0.8 * X}
     st2 = ctx.state(gi.state_config2())
     chains = {"state": st2, "n_post": 12, "batch": 256, "every": 100, "next": 0}
-    res["persistent_mixed_sampling_0.5x"] = run_server(persistent, 0.5 * X, chains)
+    phase("persistent_mixed_sampling_0.5x", run_server, persistent, 0.5 * X, chains)
     res["persistent_mixed_sampling_0.5x"]["sampling"] = ("a batch of 256 config-2 chains (m=100, r=0.6, "
                                                          "postselection on 12 clicks) every 100 queries")
     st2.close()
@@ -526,6 +545,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-n, sampler and serving measurements")
     ap.add_argument("--copy-calibration", action="store_true", help="only run the 1 GiB copy used to scale counters")
+    ap.add_argument("--only", default=None,
+                    help="run one extra measurement by name (e.g. serving, sampler) and print its JSON")
     ap.add_argument("--invert-only", action="store_true",
                     help="only invert the 800-mode state (dd, qd) and time full patterns on it (for profiling)")
     args = ap.parse_args()
@@ -537,6 +558,15 @@ def main():
         import paper_1810_00900_amd as tg
         ctx = tg.Context(0)
         print(json.dumps(full_pattern_inverse(ctx, gi.state_m800(50))), flush=True)
+        ctx.close()
+        return
+    if args.only:
+        import gbs_inputs as gi
+        import paper_1810_00900_amd as tg
+        fns = {"serving": serving_bench, "serving_full_patterns": serving_full_patterns, "sampler": sampler_bench,
+               "dense_subgraph": dense_subgraph, "paper_worst_case": paper_worst_case}
+        ctx = tg.Context(0)
+        print(json.dumps({args.only: fns[args.only](ctx)}), flush=True)
         ctx.close()
         return
     if args.gpus != 1:
@@ -624,30 +654,31 @@ def main():
     }
     if args.variant != "zero-mean":
         out["metric"] = METRIC + f" ({args.variant} variant)"
+    def step(name, fn, *a, **kw):  # one extra measurement, with a progress line on stderr
+        t = time.perf_counter()
+        out[name] = fn(*a, **kw)
+        print(f"bench: {name} done in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+
     if not args.no_extras and args.variant == "zero-mean":
-        out["per_n"] = per_n_rates(ctx, cov, args.prec)
-        out["per_n_f64_terms"] = per_n_rates(ctx, cov, "f64")
-        out["per_n_full_pattern"] = per_n_rates(ctx, cov, args.prec, ns=(20, 28), full=True)
-        out["per_n_qd_terms"] = per_n_rates(ctx, cov, "qd", ns=(20, 24, 28))
-        out["per_n_full_pattern_qd"] = per_n_rates(ctx, cov, "qd", ns=(20, 28), full=True)
-        out["full_pattern_inverse"] = full_pattern_inverse(ctx, cov)
-        out["full_pattern_inverse_displaced"] = full_pattern_inverse(
-            ctx, cov, mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
-        out["per_n_displaced"] = per_n_rates(ctx, cov, args.prec, ns=(20, 24, 28),
-                                             mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
-        out["per_n_displaced_f64_terms"] = per_n_rates(ctx, cov, "f64", ns=(20, 24, 28),
-                                                       mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
-        out["per_n_displaced_qd_terms"] = per_n_rates(ctx, cov, "qd", ns=(20, 24),
-                                                      mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
-        out["per_n_full_pattern_displaced_qd"] = per_n_rates(
-            ctx, cov, "qd", ns=(20,), full=True, mean=gi.random_mean(800, np.random.default_rng(51), 0.3))
-        out["sampler"] = sampler_bench(ctx)
-        out["sampler_displaced"] = sampler_bench(ctx, n_samples=200, displaced=True)
-        out["paper_worst_case"] = paper_worst_case(ctx)
-        out["paper_worst_case_qd"] = paper_worst_case(ctx, sizes=((16, 512), (18, 648), (20, 800)), prec="qd")
-        out["dense_subgraph"] = dense_subgraph(ctx)
-        out["serving"] = serving_bench(ctx)
-        out["serving_full_patterns"] = serving_full_patterns(ctx)
+        mu = gi.random_mean(800, np.random.default_rng(51), 0.3)
+        step("per_n", per_n_rates, ctx, cov, args.prec)
+        step("per_n_f64_terms", per_n_rates, ctx, cov, "f64")
+        step("per_n_full_pattern", per_n_rates, ctx, cov, args.prec, ns=(20, 28), full=True)
+        step("per_n_qd_terms", per_n_rates, ctx, cov, "qd", ns=(20, 24, 28))
+        step("per_n_full_pattern_qd", per_n_rates, ctx, cov, "qd", ns=(20, 28), full=True)
+        step("full_pattern_inverse", full_pattern_inverse, ctx, cov)
+        step("full_pattern_inverse_displaced", full_pattern_inverse, ctx, cov, mean=mu)
+        step("per_n_displaced", per_n_rates, ctx, cov, args.prec, ns=(20, 24, 28), mean=mu)
+        step("per_n_displaced_f64_terms", per_n_rates, ctx, cov, "f64", ns=(20, 24, 28), mean=mu)
+        step("per_n_displaced_qd_terms", per_n_rates, ctx, cov, "qd", ns=(20, 24), mean=mu)
+        step("per_n_full_pattern_displaced_qd", per_n_rates, ctx, cov, "qd", ns=(20,), full=True, mean=mu)
+        step("sampler", sampler_bench, ctx)
+        step("sampler_displaced", sampler_bench, ctx, n_samples=200, displaced=True)
+        step("paper_worst_case", paper_worst_case, ctx)
+        step("paper_worst_case_qd", paper_worst_case, ctx, sizes=((16, 512), (18, 648), (20, 800)), prec="qd")
+        step("dense_subgraph", dense_subgraph, ctx)
+        step("serving", serving_bench, ctx)
+        step("serving_full_patterns", serving_full_patterns, ctx)
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cov, pattern, n)

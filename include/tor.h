@@ -123,7 +123,9 @@ typedef struct {
 typedef enum {
     TOR_OPT_TIMING = 0,     /* 1: record HIP events around every launch (default 0) */
     TOR_OPT_TASK_MODES = 1, /* modes per wave-tier task, 1..11, both precisions
-                             (default 10 for dd terms, 11 for binary64 terms) */
+                             (default 10 for dd terms, 11 for binary64 terms, or the
+                             tuning table's choice per n); setting it clears the
+                             table's task sizes */
     TOR_OPT_WAVE_GRID = 2,  /* cap on wave-tier workgroups per launch (default 65536) */
     TOR_OPT_MEM_BUDGET = 3, /* device bytes the context may hold (default 64 GiB) */
     TOR_OPT_ASYNC_POOL = 4, /* tree pool bytes of tor_batch_async (default 4 GiB) */
@@ -147,11 +149,13 @@ tor_status tor_ctx_reset_stats(tor_ctx *ctx);
 /* Autotuner: for each tree size n in [n_lo, n_hi] time the candidate
  * wave-tier task sizes (6..11 modes per task) on a synthetic SPD matrix and
  * keep the fastest for (prec, n) in ctx; with cache_path != NULL also write
- * the table as JSON ({"arch": ..., "task_modes": {"dd:24": 9, ...}}).  The
- * choice depends only on (prec, n): results of a query never depend on the
- * other queries it is batched with.  prec must be TOR_PREC_F64 or
- * TOR_PREC_DD.  A context created while the environment variable
- * TOR_TUNE_CACHE names such a file loads it. */
+ * the context's table as JSON ({"arch": ..., "task_modes": {"dd:24": 9, ...},
+ * "persistent_unit_levels": {"pst:24": 2, ...}}).  The choice depends only on
+ * (prec, n): results of a query never depend on the other queries it is
+ * batched with.  prec must be TOR_PREC_F64 or TOR_PREC_DD.  A context loads
+ * the table named by the environment variable TOR_TUNE_CACHE when it is set
+ * (an empty value: no table), else the table tor_tuning.json beside the
+ * library when it exists. */
 tor_status tor_autotune(tor_ctx *ctx, tor_prec prec, int32_t n_lo, int32_t n_hi, const char *cache_path);
 tor_status tor_load_tuning(tor_ctx *ctx, const char *cache_path);
 /* The task size a tree of n modes will use with precision prec. */
@@ -487,9 +491,10 @@ tor_status tor_server_stop(tor_server *srv);
  * and the work of different requests overlaps on the device.  The last unit
  * of a request sums its partial results and sets the request's completion
  * word (a system-scope release the host reads).  No unit waits for another;
- * a workgroup waits only for new work, and the kernel exits on the stop flag
- * or after idle_ms without work, and is launched again on demand (by submit
- * and poll).
+ * a workgroup waits only for new work.  The kernel exits on the stop flag, or
+ * as a whole once every workgroup has been idle_ms without work (workgroups
+ * never leave one by one, so a long request with few units does not shrink
+ * the kernel), and is launched again on demand (by submit and poll).
  *
  * Probability queries (Sec. II of the paper, as tor_probability): zero-mean
  * states, marginal patterns (1 and -1 entries) and full patterns (1 and 0
@@ -519,7 +524,7 @@ typedef struct {
     size_t mem_budget_bytes;   /* device bytes for the partial sums of requests in flight (default 1 GiB) */
     size_t chain_buffer_bytes; /* pinned host bytes for the outputs of sampling batches (default 64 MiB) */
     int32_t grid;              /* workgroups of the kernel; 0: as many as fit the device at once */
-    int32_t idle_ms;           /* the kernel exits after this long without work (default 50) */
+    int32_t idle_ms;           /* the kernel exits once all its workgroups are this long without work (default 50) */
 } tor_pserver_opts;
 
 typedef struct {
@@ -528,8 +533,12 @@ typedef struct {
     int64_t pending;   /* submitted and not yet read */
     int64_t units;     /* work units published */
     int64_t launches;  /* launches of the persistent kernel */
+    int64_t device_cursor;    /* index of the request whose units the kernel is claiming */
+    int64_t device_published; /* requests the kernel has seen published */
     int32_t running;   /* 1 while the kernel runs */
-    int32_t reserved;
+    int32_t workgroups;          /* workgroups per launch */
+    int32_t workgroups_started;  /* workgroups started over all launches */
+    int32_t workgroups_peak;     /* most workgroups resident at once */
 } tor_pserver_stats;
 
 /* Start the loop on ctx's device (opts may be NULL) and launch its kernel.
@@ -559,6 +568,17 @@ tor_status tor_pserver_poll(tor_pserver *srv, uint64_t ticket, int32_t wait, tor
 tor_status tor_pserver_poll_chains(tor_pserver *srv, uint64_t ticket, int32_t wait, uint8_t *outcomes,
                                    int8_t *status, double *latency_s);
 tor_status tor_pserver_get_stats(tor_pserver *srv, tor_pserver_stats *out);
+/* Autotuner of the persistent schedule: for each tree size n in [n_lo, n_hi]
+ * and every depth-first unit depth t (units of 2^t wave tasks; the task size
+ * is the batched path's, so results stay bitwise tor_batch's) time one query
+ * alone and a burst of eight (a synthetic 32-mode state), and keep the t of
+ * the least latency plus time per query of the burst in the server's context;
+ * with cache_path also write the context's whole table (task sizes and unit
+ * depths) as JSON for tor_load_tuning.  With the environment variable
+ * TOR_TUNE_VERBOSE set (not "0") every measurement goes to stderr.  A context
+ * loads TOR_TUNE_CACHE when that variable is set, else the table
+ * tor_tuning.json beside the library when it exists. */
+tor_status tor_pserver_autotune(tor_pserver *srv, int32_t n_lo, int32_t n_hi, const char *cache_path);
 /* Finish every submitted request (unread results are dropped), set the stop
  * flag, wait for the kernel to exit and free the server. */
 tor_status tor_pserver_stop(tor_pserver *srv);

@@ -26,6 +26,7 @@ TOR_ETOOBIG = -3
 TOR_ENOMEM = -4
 TOR_EDEVICE = -5
 TOR_EAGAIN = -6
+PS_SLOTS = 4096  # TOR_PS_SLOTS: request slots of the persistent loop's ring
 
 PREC_AUTO, PREC_F64, PREC_DD, PREC_QD = 0, 1, 2, 3
 _PREC = {"auto": PREC_AUTO, "f64": PREC_F64, "dd": PREC_DD, "qd": PREC_QD,
@@ -83,8 +84,9 @@ class _CPServerOpts(ctypes.Structure):
 
 class _CPServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("pending", ctypes.c_int64),
-                ("units", ctypes.c_int64), ("launches", ctypes.c_int64), ("running", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("units", ctypes.c_int64), ("launches", ctypes.c_int64), ("device_cursor", ctypes.c_int64),
+                ("device_published", ctypes.c_int64), ("running", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("workgroups_started", ctypes.c_int32), ("workgroups_peak", ctypes.c_int32)]
 
 
 @dataclass
@@ -164,6 +166,7 @@ def lib():
         "tor_pserver_poll_chains": ([vp, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8), i8p, dp],
                                     ctypes.c_int32),
         "tor_pserver_get_stats": ([vp, ctypes.POINTER(_CPServerStats)], ctypes.c_int32),
+        "tor_pserver_autotune": ([vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p], ctypes.c_int32),
         "tor_pserver_stop": ([vp], ctypes.c_int32),
         "tor_submit": ([vp, vp, i8p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
         "tor_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(_CResult), dp], ctypes.c_int32),
@@ -631,6 +634,11 @@ class PServer:
 
     def wait_chains(self, ticket: int):
         return self.poll_chains(ticket, wait=True)
+
+    def autotune(self, n_lo=14, n_hi=24, cache_path=None):
+        """Tune the unit depth per n (tor_pserver_autotune); optionally write the table."""
+        _check(lib().tor_pserver_autotune(self._h, int(n_lo), int(n_hi),
+                                          None if cache_path is None else str(cache_path).encode()))
 
     def stats(self) -> dict:
         s = _CPServerStats()

@@ -2,6 +2,7 @@
 // reduction of a click pattern to a conditioned matrix Sigma_C, the launch
 // plan of the subset-tree kernels, and the final assembly of p, Tor and the
 // error bound.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -156,9 +157,8 @@ struct tor_ctx {
     int task_modes[2] = {11, 10};
     // autotuned task size per (precision, n); 0 = use task_modes
     int tuned[2][TOR_MAX_CLICKS + 1] = {};
-    // persistent-server schedule per n (double-double terms): task modes and
-    // depth-first levels per unit plus one; 0 = the default rule
-    int ps_J[TOR_MAX_CLICKS + 1] = {};
+    // persistent-server schedule per n (double-double terms): depth-first
+    // levels per unit plus one; 0 = the default rule
     int ps_t1[TOR_MAX_CLICKS + 1] = {};
     int wave_grid = 65536;
     size_t mem_budget = (size_t)64 << 30;
@@ -189,7 +189,8 @@ struct tor_state {
     dd det_rsqrt_mean = {1.0, 0.0};
     DevBuf dinv;   // device copy of the inverse in double-double words for tor_batch_async (first use)
     DevBuf dinvh;  // device copy of h (displaced states), likewise
-    DevBuf dK, dKoff;  // the sampler's K_j tables for the persistent server (first use)
+    DevBuf dK;  // the sampler's tables for the persistent server (first use): K_j offsets, then K_j
+    size_t k_off_bytes = 0;
     std::mutex dev_mu;  // guards the creation of the device copies (dcov, dmean)
 };
 
@@ -437,6 +438,11 @@ void host_pack(Reduced *r) {
     std::vector<int>().swap(r->g);
 }
 
+// Generation of device data made for states (incremented by every new device
+// copy): a persistent kernel's workgroups acquire device memory again when a
+// request carries a newer generation than they last acquired.
+std::atomic<unsigned int> g_data_gen{1};
+
 // Device copies of a state's covariance (and mean) for the device-side
 // gathers, made once; the caller has the state's device current.
 tor_status state_on_device(const tor_state *st) {
@@ -446,11 +452,13 @@ tor_status state_on_device(const tor_state *st) {
     if (!ms->dcov.p) {
         if (ms->dcov.ensure(cov_bytes) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the state failed");
         HIP_TRY(hipMemcpy(ms->dcov.p, st->cov.data(), cov_bytes, hipMemcpyHostToDevice));
+        g_data_gen++;
     }
     if (!st->mean.empty() && !ms->dmean.p) {
         const size_t mb = st->mean.size() * sizeof(double);
         if (ms->dmean.ensure(mb) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the mean failed");
         HIP_TRY(hipMemcpy(ms->dmean.p, st->mean.data(), mb, hipMemcpyHostToDevice));
+        g_data_gen++;
     }
     return TOR_OK;
 }
@@ -1662,8 +1670,22 @@ tor_status tor_ctx_create(int device, tor_ctx **out) {
     c->host_res_cap = 64;
     for (auto &e : c->ev) (void)hipEventCreate(&e);
     scratch_setup(device);
-    if (const char *tc = std::getenv("TOR_TUNE_CACHE")) {
-        if (*tc && tor_load_tuning(c, tc) != TOR_OK) g_err.clear();  // a missing cache is not an error
+    // tuning table: TOR_TUNE_CACHE if set, else the table shipped beside the
+    // library (tor_tuning.json); a missing or unreadable table is not an error
+    const char *tc = std::getenv("TOR_TUNE_CACHE");
+    if (tc && *tc) {
+        if (tor_load_tuning(c, tc) != TOR_OK) g_err.clear();
+    } else if (!tc) {
+        Dl_info info;
+        if (dladdr((void *)&tor_ctx_create, &info) && info.dli_fname) {
+            std::string path(info.dli_fname);
+            const size_t slash = path.rfind('/');
+            path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/tor_tuning.json";
+            if (FILE *f = std::fopen(path.c_str(), "r")) {
+                std::fclose(f);
+                if (tor_load_tuning(c, path.c_str()) != TOR_OK) g_err.clear();
+            }
+        }
     }
     *out = c;
     return TOR_OK;
@@ -1706,6 +1728,7 @@ tor_status tor_ctx_set_option(tor_ctx *c, tor_option opt, int64_t v) {
     case TOR_OPT_TASK_MODES:
         if (v < 1 || v > TOR_TASK_MAX) return fail(TOR_EINVAL, "task modes must be in 1..%d", TOR_TASK_MAX);
         c->task_modes[0] = c->task_modes[1] = (int)v;
+        std::memset(c->tuned, 0, sizeof c->tuned);  // an explicit size overrides the tuning table
         return TOR_OK;
     case TOR_OPT_WAVE_GRID:
         if (v < 1 || v > (1LL << 30)) return fail(TOR_EINVAL, "bad wave grid cap");
@@ -1860,14 +1883,13 @@ tor_status tor_state_create_displaced(tor_ctx *ctx, const double *cov, const dou
 
 void tor_state_destroy(tor_state *st) {
     if (!st) return;
-    if (st->dcov.p || st->dmean.p || st->dinv.p || st->dinvh.p || st->dK.p || st->dKoff.p) {
+    if (st->dcov.p || st->dmean.p || st->dinv.p || st->dinvh.p || st->dK.p) {
         (void)hipSetDevice(st->device);
         st->dcov.release();
         st->dmean.release();
         st->dinv.release();
         st->dinvh.release();
         st->dK.release();
-        st->dKoff.release();
         (void)hipGetLastError();  // leave no error for the next checked call
     }
     delete st;
@@ -2110,11 +2132,13 @@ tor_status batch_async_impl(tor_ctx *ctx, const tor_state *st, const double *d_c
             if (ms->dinv.ensure(ent * sizeof(dd)) != hipSuccess)
                 return fail(TOR_ENOMEM, "device copy of the inverse failed");
             HIP_TRY(hipMemcpy(ms->dinv.p, h.data(), ent * sizeof(dd), hipMemcpyHostToDevice));
+            g_data_gen++;
         }
         if (D && !ms->dinvh.p) {
             if (ms->dinvh.ensure(st->inv_h.size() * sizeof(dd)) != hipSuccess)
                 return fail(TOR_ENOMEM, "device copy of h failed");
             HIP_TRY(hipMemcpy(ms->dinvh.p, st->inv_h.data(), st->inv_h.size() * sizeof(dd), hipMemcpyHostToDevice));
+            g_data_gen++;
         }
         P.inv = ms->dinv.p;
         P.inv_h = D ? ms->dinvh.p : nullptr;
@@ -3142,6 +3166,33 @@ std::vector<dd> synthetic_sigma(int n) {
     return sig;
 }
 
+// The context's tuning table as JSON: task sizes of the batched path
+// ("dd:24": 10) and unit depths of the persistent kernel ("pst:24": 2).
+tor_status write_tuning(const tor_ctx *ctx, const char *path) {
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(TOR_EINVAL, "cannot write %s", path);
+    hipDeviceProp_t prop;
+    (void)hipGetDeviceProperties(&prop, ctx->device);
+    std::fprintf(f, "{\"arch\": \"%s\", \"task_modes\": {", prop.gcnArchName);
+    bool first = true;
+    for (int sl = 0; sl < 2; sl++)
+        for (int n = 0; n <= TOR_MAX_CLICKS; n++)
+            if (ctx->tuned[sl][n] > 0) {
+                std::fprintf(f, "%s\"%s:%d\": %d", first ? "" : ", ", sl ? "dd" : "f64", n, ctx->tuned[sl][n]);
+                first = false;
+            }
+    std::fprintf(f, "}, \"persistent_unit_levels\": {");
+    first = true;
+    for (int n = 0; n <= TOR_MAX_CLICKS; n++)
+        if (ctx->ps_t1[n] > 0) {
+            std::fprintf(f, "%s\"pst:%d\": %d", first ? "" : ", ", n, ctx->ps_t1[n] - 1);
+            first = false;
+        }
+    std::fprintf(f, "}}\n");
+    std::fclose(f);
+    return TOR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -3183,22 +3234,7 @@ tor_status tor_autotune(tor_ctx *ctx, tor_prec prec, int32_t n_lo, int32_t n_hi,
         }
         ctx->tuned[slot][n] = best;
     }
-    if (cache_path && *cache_path) {
-        FILE *f = std::fopen(cache_path, "w");
-        if (!f) return fail(TOR_EINVAL, "cannot write %s", cache_path);
-        hipDeviceProp_t prop;
-        (void)hipGetDeviceProperties(&prop, ctx->device);
-        std::fprintf(f, "{\"arch\": \"%s\", \"task_modes\": {", prop.gcnArchName);
-        bool first = true;
-        for (int sl = 0; sl < 2; sl++)
-            for (int n = 0; n <= TOR_MAX_CLICKS; n++)
-                if (ctx->tuned[sl][n] > 0) {
-                    std::fprintf(f, "%s\"%s:%d\": %d", first ? "" : ", ", sl ? "dd" : "f64", n, ctx->tuned[sl][n]);
-                    first = false;
-                }
-        std::fprintf(f, "}}\n");
-        std::fclose(f);
-    }
+    if (cache_path && *cache_path) return write_tuning(ctx, cache_path);
     return TOR_OK;
 }
 
@@ -3218,6 +3254,17 @@ tor_status tor_load_tuning(tor_ctx *ctx, const char *cache_path) {
         if (end == std::string::npos) break;
         std::string key = txt.substr(pos + 1, end - pos - 1);
         pos = end + 1;
+        if (key.rfind("pst:", 0) == 0) {  // persistent kernel: depth-first levels per unit
+            const int n = std::atoi(key.c_str() + 4);
+            const size_t colon = txt.find(':', pos);
+            if (colon == std::string::npos) break;
+            const int t = std::atoi(txt.c_str() + colon + 1);
+            if (n >= 0 && n <= TOR_MAX_CLICKS && t >= 0 && t <= TOR_PS_LMAX) {
+                ctx->ps_t1[n] = t + 1;
+                loaded++;
+            }
+            continue;
+        }
         int sl = key.rfind("dd:", 0) == 0 ? 1 : (key.rfind("f64:", 0) == 0 ? 0 : -1);
         if (sl < 0) continue;
         int n = std::atoi(key.c_str() + (sl ? 3 : 4));
@@ -3229,7 +3276,7 @@ tor_status tor_load_tuning(tor_ctx *ctx, const char *cache_path) {
             loaded++;
         }
     }
-    if (!loaded) return fail(TOR_EINVAL, "no task sizes in %s", cache_path);
+    if (!loaded) return fail(TOR_EINVAL, "no tuning entries in %s", cache_path);
     return TOR_OK;
 }
 
@@ -3281,12 +3328,12 @@ struct RangeAlloc {
     }
 };
 
-// Schedule of an n-mode tree in the persistent kernel: task modes J and the
-// depth-first levels t of a unit (units = 2^(n - J - t)).  Tuned per n, else
-// J as the batched path (at most TOR_PS_TASK_MAX) and t leaving 4096 units.
+// Schedule of an n-mode tree in the persistent kernel: the task modes J of the
+// batched path (so that the trees, tasks and reduction order are the same)
+// and the depth-first levels t of a unit (units = 2^(n - J - t)): tuned per n
+// (tor_pserver_autotune), else leaving 4096 units.
 void ps_schedule(const tor_ctx *ctx, int n, int &J, int &t) {
-    J = ctx->ps_J[n] > 0 ? ctx->ps_J[n] : std::min(task_modes_for(ctx, true, n), TOR_PS_TASK_MAX);
-    J = std::min(J, n);
+    J = task_modes_for(ctx, true, n);
     const int G = n - J;
     t = ctx->ps_t1[n] > 0 ? ctx->ps_t1[n] - 1 : std::max(0, G - 12);
     t = std::max(0, std::min({t, G, TOR_PS_LMAX}));
@@ -3312,6 +3359,7 @@ tor_status state_inverse_on_device(const tor_state *st) {
     for (size_t e = 0; e < ent; e++) h[e] = st->inv_prec == TOR_PREC_QD ? qd_to_dd(st->inv_q[e]) : st->inv[e];
     if (ms->dinv.ensure(ent * sizeof(dd)) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the inverse failed");
     HIP_TRY(hipMemcpy(ms->dinv.p, h.data(), ent * sizeof(dd), hipMemcpyHostToDevice));
+    g_data_gen++;
     return TOR_OK;
 }
 
@@ -3324,14 +3372,16 @@ tor_status state_chain_tables(const tor_state *st) {
     std::vector<unsigned long long> koff;
     tor_status s = build_k_tables(st->cov.data(), st->m, K, koff);
     if (s) return s;
-    if (ms->dK.ensure(K.size() * sizeof(double)) != hipSuccess ||
-        ms->dKoff.ensure(koff.size() * sizeof(unsigned long long)) != hipSuccess) {
-        ms->dK.release();
-        ms->dKoff.release();
-        return fail(TOR_ENOMEM, "device allocation of the K tables failed");
-    }
-    HIP_TRY(hipMemcpy(ms->dK.p, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(ms->dKoff.p, koff.data(), koff.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
+    // one buffer [koff | K] and one large copy (a small separate copy could
+    // wait for the persistent kernel to leave a CU free)
+    const size_t ob = align_up(koff.size() * sizeof(unsigned long long), 256);
+    std::vector<unsigned char> blob(ob + K.size() * sizeof(double), 0);
+    std::memcpy(blob.data(), koff.data(), koff.size() * sizeof(unsigned long long));
+    std::memcpy(blob.data() + ob, K.data(), K.size() * sizeof(double));
+    if (ms->dK.ensure(blob.size()) != hipSuccess) return fail(TOR_ENOMEM, "device allocation of the K tables failed");
+    HIP_TRY(hipMemcpy(ms->dK.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    ms->k_off_bytes = ob;
+    g_data_gen++;
     return TOR_OK;
 }
 
@@ -3361,6 +3411,7 @@ struct tor_pserver {
     DevBuf dev, scratch, arena;
     RangeAlloc parts, outs;
     PsParams params{};
+    unsigned long long epoch = 0;  // launches so far: the newest launch's number
     int grid = 0;
     double tol = 1e-10;
     std::mutex mu;
@@ -3368,20 +3419,34 @@ struct tor_pserver {
     uint64_t next_ticket = 1;
     std::unordered_map<uint64_t, PsEntry> live;
     uint64_t slot_ticket[TOR_PS_SLOTS] = {};  // ticket whose request holds the slot (0: free)
+    unsigned long long slot_seq[TOR_PS_SLOTS] = {};  // the request last published into the slot
+    // completion watcher: stamps the time each published request finishes
+    std::thread watcher;
+    std::condition_variable cv_work, cv_done;
+    bool stopping = false;
+    unsigned long long watch_seq = 0;          // requests before it are stamped or read
+    bool slot_done[TOR_PS_SLOTS] = {};         // the slot's request is finished (stamped)
+    std::chrono::steady_clock::time_point slot_t_done[TOR_PS_SLOTS];
+    tor_status kernel_error = TOR_OK;          // a failed relaunch seen by the watcher
+    std::string kernel_error_msg;              // and its message
     tor_pserver_stats stats{};
 };
 
 namespace {
 
-// Launch the persistent kernel unless it is running (S->mu held).
+// Launch the persistent kernel unless it is running (S->mu held).  A launch
+// that is closing (its workgroups are leaving) counts as not running: the next
+// one is queued behind it on the kernel's stream.
 tor_status ps_ensure_running(tor_pserver *S) {
     const hipError_t q = hipStreamQuery(S->kst);
-    if (q == hipErrorNotReady) return TOR_OK;
-    if (q != hipSuccess) {
+    if (q == hipErrorNotReady) {
+        if (__atomic_load_n(&S->host->seen_closing, __ATOMIC_ACQUIRE) != S->epoch) return TOR_OK;
+    } else if (q != hipSuccess) {
         (void)hipGetLastError();
         return fail(TOR_EDEVICE, "persistent kernel failed: %s", hipGetErrorString(q));
     }
     HIP_TRY(hipSetDevice(S->device));
+    S->params.epoch = ++S->epoch;
     HIP_TRY(tor_launch_pserver(S->params, S->grid, S->kst));
     S->stats.launches++;
     return TOR_OK;
@@ -3392,6 +3457,7 @@ tor_status ps_publish(tor_pserver *S, PsReq &rq, PsEntry &&e, uint64_t *ticket) 
     const unsigned long long seq = S->next_seq;
     const int slot = (int)(seq % TOR_PS_SLOTS);
     rq.seq = (long long)seq;
+    rq.gen = g_data_gen.load();
     PsReq *dst = &S->ring[slot];
     std::memcpy((char *)dst + sizeof(long long), (const char *)&rq + sizeof(long long), sizeof(PsReq) - sizeof(long long));
     std::atomic_thread_fence(std::memory_order_release);
@@ -3402,17 +3468,74 @@ tor_status ps_publish(tor_pserver *S, PsReq &rq, PsEntry &&e, uint64_t *ticket) 
     e.t0 = std::chrono::steady_clock::now();
     const uint64_t t = S->next_ticket++;
     S->slot_ticket[slot] = t;
+    S->slot_seq[slot] = seq;
+    S->slot_done[slot] = false;
     S->live.emplace(t, std::move(e));
     *ticket = t;
     S->stats.submitted++;
+    S->cv_work.notify_one();
     return ps_ensure_running(S);
 }
 
+// Stamp request seq finished if its completion word says so (S->mu held).  A
+// request whose slot already holds a later one was read and released: it is
+// finished, and the slot's flags belong to the later request.
+bool ps_check(tor_pserver *S, unsigned long long seq) {
+    const int slot = (int)(seq % TOR_PS_SLOTS);
+    if (S->slot_seq[slot] != seq) return true;
+    if (S->slot_done[slot]) return true;
+    if (__atomic_load_n(&S->res[slot].done, __ATOMIC_ACQUIRE) != seq + 1) return false;
+    S->slot_done[slot] = true;
+    S->slot_t_done[slot] = std::chrono::steady_clock::now();
+    return true;
+}
+
 // A ticket's request finished on the device (S->mu held)?
-bool ps_done(const tor_pserver *S, const PsEntry &e) {
-    if (e.host_only) return true;
-    const int slot = (int)(e.seq % TOR_PS_SLOTS);
-    return __atomic_load_n(&S->res[slot].done, __ATOMIC_ACQUIRE) == e.seq + 1;
+bool ps_done(tor_pserver *S, const PsEntry &e) { return e.host_only || ps_check(S, e.seq); }
+
+// Completion time of a finished ticket (S->mu held).
+std::chrono::steady_clock::time_point ps_t_done(const tor_pserver *S, const PsEntry &e) {
+    return e.host_only ? e.t0 : S->slot_t_done[e.seq % TOR_PS_SLOTS];
+}
+
+// The completion watcher: stamps finished requests as their completion words
+// arrive (so that latencies are the device's, not the reader's), wakes
+// waiting readers, and launches the kernel again if it exited with requests
+// outstanding.
+void ps_watch(tor_pserver *S) {
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto last_check = std::chrono::steady_clock::now();
+    while (!S->stopping) {
+        if (S->watch_seq == S->next_seq) {
+            S->cv_work.wait(lk);
+            continue;
+        }
+        bool any = false;
+        // a slot holding a later request than q means q was read already
+        auto unstamped = [&](unsigned long long q) {
+            const int slot = (int)(q % TOR_PS_SLOTS);
+            return S->slot_seq[slot] == q && S->slot_ticket[slot] && !S->slot_done[slot];
+        };
+        for (unsigned long long q = S->watch_seq; q < S->next_seq; ++q)
+            if (unstamped(q) && ps_check(S, q)) any = true;
+        while (S->watch_seq < S->next_seq && !unstamped(S->watch_seq))  // past every stamped or read request
+            S->watch_seq++;
+        if (any) S->cv_done.notify_all();
+        const auto now = std::chrono::steady_clock::now();
+        if (now - last_check > std::chrono::milliseconds(1)) {
+            last_check = now;
+            if (S->watch_seq < S->next_seq && S->kernel_error == TOR_OK) {
+                S->kernel_error = ps_ensure_running(S);
+                if (S->kernel_error) {
+                    S->kernel_error_msg = g_err;
+                    S->cv_done.notify_all();
+                }
+            }
+        }
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(2));
+        lk.lock();
+    }
 }
 
 void ps_release(tor_pserver *S, uint64_t ticket, PsEntry &e) {
@@ -3521,6 +3644,7 @@ tor_status tor_pserver_start(tor_ctx *ctx, const tor_pserver_opts *opts, tor_pse
             return fail(TOR_EDEVICE, "%s", msg.c_str());
         }
     }
+    S->watcher = std::thread(ps_watch, S.get());
     *out = S.release();
     return TOR_OK;
 }
@@ -3615,8 +3739,8 @@ tor_status tor_pserver_submit_chains(tor_pserver *S, const tor_state *st, int32_
     rq.m = m;
     rq.units = nchains;
     ChainParams &P = rq.cp;
-    P.K = (const double *)st->dK.p;
-    P.koff = (const unsigned long long *)st->dKoff.p;
+    P.koff = (const unsigned long long *)st->dK.p;
+    P.K = (const double *)((const unsigned char *)st->dK.p + st->k_off_bytes);
     P.H = nullptr;
     P.hoff = nullptr;
     P.m = m;
@@ -3643,9 +3767,9 @@ tor_status tor_pserver_submit_chains(tor_pserver *S, const tor_state *st, int32_
 
 tor_status tor_pserver_poll(tor_pserver *S, uint64_t ticket, int32_t wait, tor_result *out, double *latency_s) {
     if (!S || !out) return fail(TOR_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         {
-            std::lock_guard<std::mutex> lk(S->mu);
             auto it = S->live.find(ticket);
             if (it == S->live.end()) return fail(TOR_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
             PsEntry &e = it->second;
@@ -3664,26 +3788,24 @@ tor_status tor_pserver_poll(tor_pserver *S, uint64_t ticket, int32_t wait, tor_r
                     }
                 }
                 *out = e.res;
-                if (latency_s)
-                    *latency_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - e.t0).count();
+                if (latency_s) *latency_s = std::chrono::duration<double>(ps_t_done(S, e) - e.t0).count();
                 const tor_status st = e.res.status;
                 ps_release(S, ticket, e);
                 return st;
             }
-            tor_status s = ps_ensure_running(S);
-            if (s) return s;
+            if (S->kernel_error) return fail(S->kernel_error, "persistent kernel: %s", S->kernel_error_msg.c_str());
+            if (!wait) return TOR_EAGAIN;
+            S->cv_done.wait_for(lk, std::chrono::milliseconds(1));
         }
-        if (!wait) return TOR_EAGAIN;
-        std::this_thread::yield();
     }
 }
 
 tor_status tor_pserver_poll_chains(tor_pserver *S, uint64_t ticket, int32_t wait, uint8_t *outcomes,
                                    int8_t *status, double *latency_s) {
     if (!S) return fail(TOR_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         {
-            std::lock_guard<std::mutex> lk(S->mu);
             auto it = S->live.find(ticket);
             if (it == S->live.end()) return fail(TOR_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
             PsEntry &e = it->second;
@@ -3692,16 +3814,14 @@ tor_status tor_pserver_poll_chains(tor_pserver *S, uint64_t ticket, int32_t wait
                 const unsigned char *o = S->outbuf + e.out_off;
                 if (outcomes) std::memcpy(outcomes, o, (size_t)e.nchains * e.m);
                 if (status) std::memcpy(status, o + (size_t)e.nchains * e.m, (size_t)e.nchains);
-                if (latency_s)
-                    *latency_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - e.t0).count();
+                if (latency_s) *latency_s = std::chrono::duration<double>(ps_t_done(S, e) - e.t0).count();
                 ps_release(S, ticket, e);
                 return TOR_OK;
             }
-            tor_status s = ps_ensure_running(S);
-            if (s) return s;
+            if (S->kernel_error) return fail(S->kernel_error, "persistent kernel: %s", S->kernel_error_msg.c_str());
+            if (!wait) return TOR_EAGAIN;
+            S->cv_done.wait_for(lk, std::chrono::milliseconds(1));
         }
-        if (!wait) return TOR_EAGAIN;
-        std::this_thread::yield();
     }
 }
 
@@ -3712,6 +3832,13 @@ tor_status tor_pserver_get_stats(tor_pserver *S, tor_pserver_stats *out) {
     out->pending = (int64_t)S->live.size();
     out->running = hipStreamQuery(S->kst) == hipErrorNotReady ? 1 : 0;
     (void)hipGetLastError();
+    // the kernel's counters as it last mirrored them into host memory (a
+    // device copy could wait for the kernel to leave a CU free)
+    out->device_cursor = (int64_t)__atomic_load_n(&S->host->seen_cur, __ATOMIC_ACQUIRE);
+    out->device_published = (int64_t)__atomic_load_n(&S->host->seen_pub, __ATOMIC_ACQUIRE);
+    out->workgroups = S->grid;
+    out->workgroups_started = (int32_t)__atomic_load_n(&S->host->seen_started, __ATOMIC_ACQUIRE);
+    out->workgroups_peak = (int32_t)__atomic_load_n(&S->host->seen_peak, __ATOMIC_ACQUIRE);
     return TOR_OK;
 }
 
@@ -3720,23 +3847,23 @@ tor_status tor_pserver_stop(tor_pserver *S) {
     (void)hipSetDevice(S->device);
     tor_status first = TOR_OK;
     // finish every published request (their results are dropped if not polled)
-    for (;;) {
-        bool pending = false;
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        for (;;) {
+            bool pending = false;
             for (auto &kv : S->live)
                 if (!ps_done(S, kv.second)) pending = true;
-            if (pending) {
-                tor_status s = ps_ensure_running(S);
-                if (s) {
-                    first = s;
-                    break;
-                }
+            if (!pending) break;
+            if (S->kernel_error) {
+                first = S->kernel_error;
+                break;
             }
+            S->cv_done.wait_for(lk, std::chrono::milliseconds(1));
         }
-        if (!pending) break;
-        std::this_thread::yield();
+        S->stopping = true;
+        S->cv_work.notify_all();
     }
+    S->watcher.join();
     __atomic_store_n(&S->host->stop, 1u, __ATOMIC_RELEASE);
     const hipError_t e = hipStreamSynchronize(S->kst);
     if (e != hipSuccess && first == TOR_OK) first = fail(TOR_EDEVICE, "persistent kernel: %s", hipGetErrorString(e));
@@ -3754,3 +3881,86 @@ tor_status tor_pserver_stop(tor_pserver *S) {
 }
 
 }  // extern "C"
+
+extern "C" {
+
+tor_status tor_pserver_autotune(tor_pserver *S, int32_t n_lo, int32_t n_hi, const char *cache_path) {
+    if (!S) return fail(TOR_EINVAL, "NULL argument");
+    if (n_lo < 1 || n_hi > TOR_MAX_CLICKS || n_lo > n_hi) return fail(TOR_EINVAL, "bad n range");
+    tor_ctx *ctx = S->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    // a synthetic 32-mode state (sigma = I + B B^T / 64, SPD), marginal queries
+    // of n clicks drawn by a fixed generator.  Cost of a unit depth: the time
+    // of one query alone (latency) plus the time per query of a burst of
+    // eight submitted together (throughput), the median of three.
+    constexpr int M = TOR_MAX_CLICKS, BURST = 8;
+    const char *vb = std::getenv("TOR_TUNE_VERBOSE");  // print each measurement to stderr
+    const bool verbose = vb && *vb && *vb != '0';
+    const std::vector<dd> sig = synthetic_sigma(M);
+    std::vector<double> cov(sig.size());
+    for (size_t i = 0; i < sig.size(); i++) cov[i] = sig[i].hi;
+    tor_state *st = nullptr;
+    tor_status s = tor_state_create(ctx, cov.data(), M, &st);
+    if (s) return s;
+    unsigned lcg = 7u;
+    auto run = [&](const std::vector<std::vector<int8_t>> &pats, int count, double &secs) -> tor_status {
+        auto t0 = std::chrono::steady_clock::now();
+        uint64_t tk[BURST];
+        for (int q = 0; q < count; q++) {
+            tor_status e = tor_pserver_submit(S, st, pats[q].data(), &tk[q]);
+            if (e < 0) return e;
+        }
+        for (int q = 0; q < count; q++) {
+            tor_result r;
+            tor_status e = tor_pserver_poll(S, tk[q], 1, &r, nullptr);
+            if (e < 0) return e;
+        }
+        secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return TOR_OK;
+    };
+    for (int n = n_lo; n <= n_hi; n++) {
+        std::vector<std::vector<int8_t>> pats(BURST, std::vector<int8_t>(M, -1));
+        for (auto &p : pats)
+            for (int k = 0; k < n;) {
+                lcg = lcg * 1664525u + 1013904223u;
+                const int i = (int)((lcg >> 8) % M);
+                if (p[i] != 1) {
+                    p[i] = 1;
+                    k++;
+                }
+            }
+        const int J = task_modes_for(ctx, true, n), G = n - J;
+        int best = -1;
+        double best_c = 1e300;
+        for (int t = 0; t <= std::min(G, TOR_PS_LMAX); t++) {
+            ctx->ps_t1[n] = t + 1;
+            double c[3], x;
+            for (int rep = 0; rep < 4; rep++) {  // one warm-up pass, three timed
+                double one, burst;
+                s = run(pats, 1, one);
+                if (s == TOR_OK) s = run(pats, BURST, burst);
+                if (s < 0) {
+                    tor_state_destroy(st);
+                    return s;
+                }
+                x = one + burst / BURST;
+                if (rep) c[rep - 1] = x;
+            }
+            std::sort(c, c + 3);
+            if (verbose)
+                std::fprintf(stderr, "pserver autotune n=%d J=%d t=%d units=%lld cost %.3f %.3f %.3f ms\n", n, J, t,
+                             1LL << (G - t), c[0] * 1e3, c[1] * 1e3, c[2] * 1e3);
+            if (c[1] < best_c) {
+                best_c = c[1];
+                best = t;
+            }
+        }
+        ctx->ps_t1[n] = best + 1;
+    }
+    tor_state_destroy(st);
+    if (cache_path && *cache_path) return write_tuning(ctx, cache_path);
+    return TOR_OK;
+}
+
+}  // extern "C"
+

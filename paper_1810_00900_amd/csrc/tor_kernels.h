@@ -222,19 +222,27 @@ hipError_t tor_launch_chains(const ChainParams &P, int grid_cap, hipStream_t st)
 // Requests are published in order into a ring of TOR_PS_SLOTS slots in
 // host-coherent memory; request k uses slot k % TOR_PS_SLOTS.  Workgroups of
 // the persistent kernel claim the units of the request being distributed with
-// a compare-and-swap on the slot's counter, which carries the request's
-// sequence number, so a unit is never claimed twice and never for a request
-// that is not yet published.  No unit waits for another: the last unit of a
-// request (counted per slot) reduces and publishes its result.
+// a fetch-and-add on the slot's counter, which carries the request's sequence
+// number in its high word.  A check before the add keeps workgroups off a
+// finished request's counter, and a slot's counter is reset for its next
+// request only once that request is published, by the first workgroup that
+// reaches it; so a workgroup held up between the check and the add either
+// overshoots the old request or takes a unit of the published one.  No unit
+// waits for another: the last unit of a request (counted per slot) reduces and
+// publishes its result.  The kernel leaves the device as a whole: when every
+// running workgroup has been without work for the idle time, one of them
+// closes the launch and all exit (each after the unit it holds); the host
+// launches it again when work arrives.
 #define TOR_PS_SLOTS 4096
 #define TOR_PS_LMAX 8  // most depth-first levels a probability unit walks
-#define TOR_PS_TASK_MAX 10  // largest wave-tier task of the persistent kernel (modes)
+#define TOR_PS_TASK_MAX TOR_TASK_MAX  // the persistent kernel takes every task size
 
 enum { TOR_PS_PROB = 1, TOR_PS_CHAINS = 2 };
 
 struct PsReq {             // host-coherent; the host writes every field, then seq, then publishes
     long long seq;         // request index
     int type;              // TOR_PS_PROB or TOR_PS_CHAINS
+    unsigned int gen;      // generation of the device data the request reads (acquired when new)
     int n, J, g;           // probability: clicks, task modes (<= n), unit depth (units = 2^g)
     int t;                 // probability: depth-first levels of a unit (tasks per unit = 2^t)
     int m, jac;            // modes of the state; 1: gather G from the inverse (a full pattern)
@@ -256,15 +264,26 @@ struct PsHost {            // host-coherent control block
     unsigned long long published;  // requests 0 .. published - 1 are in the ring
     unsigned int stop;             // 1: the kernel exits once it has no work
     unsigned int pad;
+    // written by the kernel (on refresh and when its last workgroup exits), for
+    // the host's statistics without a device copy
+    unsigned long long seen_cur, seen_pub;
+    unsigned int seen_started, seen_peak;
+    unsigned long long seen_closing;  // the newest launch that decided to close
 };
 
 struct PsDev {             // device memory (zeroed, next[s] = s << 32, before the first launch)
     unsigned long long cur;        // request whose units are being claimed
     unsigned long long pub;        // the kernel's copy of PsHost::published
-    unsigned long long refresh;    // wall-clock time of the last copy
-    unsigned int stop;             // the kernel's copy of PsHost::stop
-    unsigned int pad;
-    unsigned long long next[TOR_PS_SLOTS];  // (seq << 32) | next unit of the slot's request
+    unsigned long long refresh;    // wall-clock time of the last copy of the control block
+    unsigned int idle;             // running workgroups past the idle time without work
+    unsigned int active;           // workgroups of the kernel running now
+    unsigned int started;          // workgroups that have started (all launches)
+    unsigned int active_peak;      // most workgroups running at once
+    // copies of the control words, one per XCD (workgroup i polls copy i % 8,
+    // each in a line of its own): [0] pub with the host's stop flag in bit 63,
+    // [1] the launch (PsParams::epoch) that is closing
+    unsigned long long pubx[8][16];
+    unsigned long long next[TOR_PS_SLOTS];  // (seq << 32) | next unit of the slot's request (seq's low word)
     unsigned int done[TOR_PS_SLOTS];        // finished units of the slot's request
 };
 
@@ -275,12 +294,13 @@ struct PsParams {
     PsDev *dev;
     dd *scratch;                // per-workgroup buffers of the depth-first walk
     long long scratch_stride;   // double-double words per workgroup
-    long long idle_ticks;       // a workgroup exits after this long (wall clock) without work
+    long long idle_ticks;       // the launch closes after every workgroup has been this long without work
     long long refresh_ticks;    // the control block is read at most this often
+    unsigned long long epoch;   // launch number (from 1)
 };
 
-// words of per-workgroup scratch: the root, two prefix buffers and one per level
-#define TOR_PS_SCRATCH_WORDS ((3 + TOR_PS_LMAX) * (TOR_MAX_N * (2 * TOR_MAX_N + 1)))
+// words of per-workgroup scratch: the unit's node and one buffer per level
+#define TOR_PS_SCRATCH_WORDS ((1 + TOR_PS_LMAX) * (TOR_MAX_N * (2 * TOR_MAX_N + 1)))
 
 hipError_t tor_launch_pserver(const PsParams &P, int grid, hipStream_t st);
 // workgroups of the persistent kernel that fit the device at once

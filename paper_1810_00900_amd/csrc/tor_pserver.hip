@@ -55,7 +55,7 @@ struct PsReduceLds {
 };
 
 union PsLds {
-    TopSmem<dd, 0, 1> top;  // largest probability task (10 modes); smaller tasks use its prefix
+    TopSmem<dd, 0, 2> top;  // largest probability task (11 modes); smaller tasks use its prefix
     PsChainLds chain;
     PsReduceLds red;
 };
@@ -96,7 +96,7 @@ __device__ __forceinline__ Pivot<dd> ps_schur(const dd *in, int r, dd *out, dd *
 // Sigma_C of the request (packed lower, exact double-double) into out: sigma_Q
 // over the clicked modes from the covariance (sigma + I/2, the diagonal by an
 // exact two-sum), or G = sigma_Q^-1 over them from the inverse.
-__device__ __forceinline__ void ps_gather(const PsReq &R, dd *out, int lane) {
+__device__ __forceinline__ void ps_gather(const PsReq &R, dd *out, int lane) {  // out: LDS
     const int E = EN(R.n, 0);
     const long long ld = 2LL * R.m;
     for (int e = lane; e < E; e += 64) {
@@ -113,7 +113,30 @@ __device__ __forceinline__ void ps_gather(const PsReq &R, dd *out, int lane) {
             out[e] = o;
         }
     }
-    ps_sync();
+    wave_sync();
+}
+
+// Byte offset of the prefix buffer in the shared LDS region: after the
+// packed-index table, room for 32 modes (E(32) double-doubles).
+constexpr int kPsPrefixOffset = 512;
+
+// Include child of the r-mode node m (LDS) in place (the expansion's update).
+__device__ __forceinline__ Pivot<dd> ps_schur_lds(dd *m, int r, dd *vt, int lane) {
+    const int R = 2 * r, RC = R - 2, EC = EN(r - 1, 0);
+    const Pivot<dd> pv = make_pivot_m<dd, 0>(m, R - 2, R - 1);
+    for (int c = lane; c < RC; c += 64) {
+        const dd c0 = m[pidx(R - 2, c)];
+        vt[c] = mul_s(c0, pv.s1);
+        vt[RC + c] = mul_s(sub_mul(m[pidx(R - 1, c)], pv.l, c0), pv.s2);
+    }
+    wave_sync();
+    for (int e = lane; e < EC; e += 64) {
+        int a, b;
+        unpack(e, a, b);
+        m[e] = sub_dot2(m[e], vt[a], vt[b], vt[RC + a], vt[RC + b]);
+    }
+    wave_sync();
+    return pv;
 }
 
 // One wave-tier task of J <= TOR_PS_TASK_MAX modes at node (global memory).
@@ -129,9 +152,10 @@ __device__ __forceinline__ void ps_task(PsLds &L, int J, const dd *node, dd c, d
     case 7: wave_task<dd, 7, 0>(*reinterpret_cast<WaveSmem<dd, 7, 0> *>(&L), node, c, a, lane, T, A); break;
     case 8: wave_task<dd, 8, 0>(*reinterpret_cast<WaveSmem<dd, 8, 0> *>(&L), node, c, a, lane, T, A); break;
     case 9: wave_task<dd, 9, 0>(L.top.w, node, c, a, lane, T, A); break;
-    default:
+    case 10:
         wave_task_top<dd, 10, 0>(*reinterpret_cast<TopSmem<dd, 0, 1> *>(&L), node, c, a, lane, T, A);
         break;
+    default: wave_task_top<dd, 11, 0>(L.top, node, c, a, lane, T, A); break;
     }
 }
 
@@ -142,6 +166,8 @@ struct PsPath {  // node of each level of the depth-first walk (wave-uniform)
 };
 
 // LDS of the kernel: four workgroups per CU (160 KiB).
+static_assert(kPsPrefixOffset + EN(TOR_MAX_N, 0) * (int)sizeof(dd) <= (int)sizeof(PsLds),
+              "the prefix buffer fits the shared LDS region");
 static_assert(sizeof(PsLds) + sizeof(PsReq) + sizeof(PsPath) + 2 * (2 * TOR_MAX_N - 2) * sizeof(dd) + 64 <=
                   40 * 1024,
               "four workgroups per CU");
@@ -149,27 +175,33 @@ static_assert(sizeof(PsLds) + sizeof(PsReq) + sizeof(PsPath) + 2 * (2 * TOR_MAX_
 // Unit u of a probability request: the subtree below the depth-g node whose
 // decisions are u's bits (most significant first; 1 = include), its tasks
 // (u << t) .. (u << t) + 2^t - 1 in the batched path's order.
-__device__ __attribute__((noinline)) void ps_prob_unit(const PsReq &R, long long u, dd *ws, PsLds &L, dd *vt, PsPath &path, int lane) {
+__device__ __attribute__((noinline)) void ps_prob_unit(const PsReq &R, long long u, dd *ws, PsLds &L, dd *vt,
+                                                      PsPath &path, int lane) {
     constexpr long long EW = TOR_MAX_N * (2 * TOR_MAX_N + 1);
-    dd *root = ws;
-    dd *pre[2] = {ws + EW, ws + 2 * EW};
-    ps_gather(R, root, lane);
-    const dd *cur = root;
+    // the unit's g decisions in LDS (the task working set is free until the
+    // first task; the packed-index table before it is kept): Sigma_C gathered
+    // there, each include decision an in-place Schur update (an entry of the
+    // child needs only itself and the pivot columns, set aside in vt), the
+    // arithmetic of the expansion's update
+    dd *lm = reinterpret_cast<dd *>(reinterpret_cast<unsigned char *>(&L) + kPsPrefixOffset);
+    ps_gather(R, lm, lane);
     dd c = dd_from(1.0);
     double a = 1.0;
-    int r = R.n, pb = 0;
+    int r = R.n;
     for (int k = 0; k < R.g; ++k, --r) {
         if ((u >> (R.g - 1 - k)) & 1) {
-            const Pivot<dd> pv = ps_schur(cur, r, pre[pb], vt, lane);
+            const Pivot<dd> pv = ps_schur_lds(lm, r, vt, lane);
             c = dd_neg(coef_mul(c, pv.q));
             a = a * hi_of(pv.q);
-            cur = pre[pb];
-            pb ^= 1;
         }
     }
+    // the unit's node to global memory: the root of its depth-first walk
+    dd *root = ws;
+    for (int e = lane; e < EN(r, 0); e += 64) root[e] = lm[e];
+    ps_sync();
     const int t = R.t;
     if (lane == 0) {
-        path.node[0] = cur;
+        path.node[0] = root;
         path.c[0] = c;
         path.a[0] = a;
     }
@@ -183,7 +215,7 @@ __device__ __attribute__((noinline)) void ps_prob_unit(const PsReq &R, long long
             const double pa = path.a[k];
             wave_sync();
             if ((q >> (t - 1 - k)) & 1) {
-                dd *out = ws + (3 + k) * EW;
+                dd *out = ws + (1 + k) * EW;
                 const Pivot<dd> pv = ps_schur(par, r - k, out, vt, lane);
                 if (lane == 0) {
                     path.node[k + 1] = out;
@@ -269,9 +301,20 @@ __device__ __forceinline__ Partial ps_reduce(const PsReq &R, PsLds &L, int lane)
     return in[0];
 }
 
-// Publish a finished request: the result words, the slot's counters made
-// ready for request seq + TOR_PS_SLOTS, then the completion word (system-scope
-// release, read by the host).  Lane 0 only.
+constexpr int kPsMaxBackoff = 3;  // log2 of the most sleeps between idle polls
+
+// Move the claim cursor past request k (lane 0; a failed exchange means
+// another workgroup moved it).
+__device__ __forceinline__ void ps_advance(const PsParams &P, unsigned long long k) {
+    unsigned long long kk = k;
+    __hip_atomic_compare_exchange_strong(&P.dev->cur, &kk, k + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish a finished request: the result words, the claim cursor moved past
+// it, the slot's completion count made ready for request seq + TOR_PS_SLOTS
+// (its claim counter is reset once that request is published), then the
+// completion word (system-scope release, read by the host).  Lane 0 only.
 __device__ __forceinline__ void ps_publish(const PsParams &P, const PsReq &R, const Partial *res) {
     const int slot = (int)(R.seq % TOR_PS_SLOTS);
     if (res) {
@@ -279,11 +322,50 @@ __device__ __forceinline__ void ps_publish(const PsParams &P, const PsReq &R, co
         P.res[slot].t_lo = res->t_lo;
         P.res[slot].a = res->a;
     }
+    ps_advance(P, (unsigned long long)R.seq);
     __hip_atomic_store(&P.dev->done[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&P.dev->next[slot], (unsigned long long)(R.seq + TOR_PS_SLOTS) << 32, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&P.res[slot].done, (unsigned long long)R.seq + 1ULL, __ATOMIC_RELEASE,
                        __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ void ps_mirror(const PsParams &P);
+
+// Copy the host's control block into the per-XCD copies if this workgroup
+// refreshes (one of the eight designated ones, or at its longest backoff) and
+// the refresh period has passed (lane 0).  Returns whether requests beyond k
+// were found; sets stop when the host has asked the kernel to stop.
+__device__ __forceinline__ bool ps_refresh(const PsParams &P, unsigned long long k, int backoff, bool &stop) {
+    if (!(blockIdx.x < 8 || backoff == kPsMaxBackoff)) return false;
+    const unsigned long long now = wall_clock64();
+    unsigned long long last = __hip_atomic_load(&P.dev->refresh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (now - last <= (unsigned long long)P.refresh_ticks ||
+        !__hip_atomic_compare_exchange_strong(&P.dev->refresh, &last, now, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT))
+        return false;
+    const unsigned long long hp = __hip_atomic_load(&P.host->published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+    const unsigned int hs = __hip_atomic_load(&P.host->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+    const unsigned long long v = hp | (hs ? 1ULL << 63 : 0ULL);
+    for (int x = 0; x < 8; ++x)
+        __hip_atomic_fetch_max(&P.dev->pubx[x][0], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(&P.dev->pub, hp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (hs) stop = true;
+    ps_mirror(P);
+    return hp > k;
+}
+
+// Copy the kernel's counters into the host's control block (lane 0).
+__device__ __forceinline__ void ps_mirror(const PsParams &P) {
+    PsHost *h = P.host;
+    __hip_atomic_store(&h->seen_cur, __hip_atomic_load(&P.dev->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&h->seen_pub, __hip_atomic_load(&P.dev->pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&h->seen_started,
+                       __hip_atomic_load(&P.dev->started, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&h->seen_peak,
+                       __hip_atomic_load(&P.dev->active_peak, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void pserver_kernel(PsParams P) {
@@ -297,68 +379,137 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void ps
     wave_tree_init<0>(L.top.w.ab, lane);
     dd *ws = P.scratch + (long long)blockIdx.x * P.scratch_stride;
     long long cached = -1;
+    int backoff = 0;  // lane 0: log2 of the sleeps between idle polls
+    unsigned int acq_gen = 0;  // newest device-data generation this workgroup has acquired
     unsigned long long idle_since = wall_clock64();
+    if (lane == 0) {
+        __hip_atomic_fetch_add(&P.dev->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int a = __hip_atomic_fetch_add(&P.dev->active, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_max(&P.dev->active_peak, a + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // lane 0: a unit taken by a fetch-and-add that found the slot already
+    // reset for a later (published) request; and whether this workgroup is
+    // counted in P.dev->idle
+    long long pend_k = -1, pend_u = 0;
+    bool counted = false;
     for (;;) {
         // --- claim a unit (lane 0 decides; act: 0 retry, 1 unit, 2 load the
         // request, 3 exit).  Polling loads are relaxed: they only pick what to
         // do; the request's data is acquired once, when it is loaded.
         if (lane == 0) {
             int act = 0;
-            bool stalled = false;  // work published but not claimable yet
+            bool stalled = false;  // no work to take now
             const unsigned long long k = __hip_atomic_load(&P.dev->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned long long pub = __hip_atomic_load(&P.dev->pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (k < pub) {
+            unsigned long long *ctl = P.dev->pubx[blockIdx.x & 7];
+            const unsigned long long px = __hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const bool closing =
+                __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == P.epoch;
+            const unsigned long long pub = px & ~(1ULL << 63);
+            bool stop = (px >> 63) != 0;
+            if (pend_k >= 0) {
+                // the held unit: its request is published, so this waits at
+                // most until this workgroup's copy of the control block shows it
+                if ((unsigned long long)pend_k < pub) {
+                    s_k = pend_k;
+                    if (pend_k != cached) {
+                        act = 2;
+                    } else {
+                        if (pend_u < R.units) {  // else an overshoot: nothing to do
+                            act = 1;
+                            s_u = pend_u;
+                        }
+                        pend_k = -1;
+                    }
+                } else if (stop) {
+                    act = 3;
+                } else if (!ps_refresh(P, k, backoff, stop)) {
+                    for (int b = 0; b < (1 << backoff); ++b) __builtin_amdgcn_s_sleep(127);
+                    if (backoff < kPsMaxBackoff) ++backoff;
+                }
+            } else if (closing || stop) {
+                act = 3;  // the launch is closing (or the host stops): claim nothing more
+            } else if (k < pub) {
                 s_k = (long long)k;
                 if ((long long)k != cached) {
                     act = 2;
                 } else {
+                    // one fetch-and-add claims a unit; the check before it keeps
+                    // late workgroups off a finished request's counter
                     const int slot = (int)(k % TOR_PS_SLOTS);
-                    unsigned long long v =
+                    const unsigned long long klo = k & 0xffffffffULL;
+                    unsigned long long v0 =
                         __hip_atomic_load(&P.dev->next[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const int ahead = (int)(unsigned int)((v >> 32) - (k & 0xffffffffULL));
-                    if (ahead > 0) {  // the slot serves a later request: k is finished
-                        unsigned long long kk = k;
-                        __hip_atomic_compare_exchange_strong(&P.dev->cur, &kk, k + 1, __ATOMIC_RELAXED,
+                    const int ahead = (int)(unsigned int)((v0 >> 32) - klo);
+                    if (ahead == -TOR_PS_SLOTS) {
+                        // the slot still counts request k - TOR_PS_SLOTS, which
+                        // is finished (k is published): reset it for k
+                        __hip_atomic_compare_exchange_strong(&P.dev->next[slot], &v0, klo << 32, __ATOMIC_RELAXED,
                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else if (ahead > 0 || (ahead == 0 && (long long)(v0 & 0xffffffffULL) >= R.units)) {
+                        ps_advance(P, k);  // every unit of k is taken
                     } else if (ahead < 0) {
-                        stalled = true;  // not yet reset for k
-                    } else if ((long long)(v & 0xffffffffULL) < R.units) {
-                        if (__hip_atomic_compare_exchange_strong(&P.dev->next[slot], &v, v + 1, __ATOMIC_RELAXED,
-                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                            act = 1;
-                            s_u = (long long)(v & 0xffffffffULL);
+                        stalled = true;  // not expected: wait as for no work
+                    } else {
+                        const unsigned long long v = __hip_atomic_fetch_add(&P.dev->next[slot], 1ULL,
+                                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const long long u = (long long)(v & 0xffffffffULL);
+                        const int d = (int)(unsigned int)((v >> 32) - klo);
+                        if (d == 0) {
+                            if (u < R.units) {
+                                act = 1;
+                                s_u = u;
+                            } else {
+                                ps_advance(P, k);  // the last unit went in between: overshoot
+                            }
+                        } else {
+                            // k finished and the slot was reset for request
+                            // k + d between the check and the add (this wave was
+                            // held up): this workgroup took that request's unit u
+                            pend_k = (long long)k + d;
+                            pend_u = u;
                         }
-                    } else {  // every unit taken: move on to the next request
-                        unsigned long long kk = k;
-                        __hip_atomic_compare_exchange_strong(&P.dev->cur, &kk, k + 1, __ATOMIC_RELAXED,
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
             } else {
-                // no work: refresh the copy of the control block (one workgroup
-                // per refresh period), then stop or wait; every pass through
-                // here checks the stop flag and the idle limit
-                const unsigned long long now = wall_clock64();
-                unsigned long long last =
-                    __hip_atomic_load(&P.dev->refresh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                bool fresh = false;  // the refresh found new work
-                if (now - last > (unsigned long long)P.refresh_ticks &&
-                    __hip_atomic_compare_exchange_strong(&P.dev->refresh, &last, now, __ATOMIC_RELAXED,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    const unsigned long long hp =
-                        __hip_atomic_load(&P.host->published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-                    const unsigned int hs =
-                        __hip_atomic_load(&P.host->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-                    __hip_atomic_fetch_max(&P.dev->pub, hp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (hs) __hip_atomic_store(&P.dev->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    fresh = hp > k;
-                }
-                if (__hip_atomic_load(&P.dev->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) act = 3;
+                // no work.  Eight workgroups (and any at its longest backoff)
+                // refresh the copies of the control block, one per refresh
+                // period; the others poll their XCD's copy.
+                const bool fresh = ps_refresh(P, k, backoff, stop);
+                if (stop) act = 3;
                 else stalled = !fresh;
             }
-            if (stalled) {  // bounded: no work for idle_ticks ends the workgroup
-                if (wall_clock64() - idle_since > (unsigned long long)P.idle_ticks) act = 3;
-                else __builtin_amdgcn_s_sleep(64);
+            if (stalled) {
+                if (wall_clock64() - idle_since > (unsigned long long)P.idle_ticks) {
+                    // past the idle time: counted as idle; once every running
+                    // workgroup is, this one closes the launch (bounded: the
+                    // kernel leaves the device as a whole)
+                    if (!counted) {
+                        counted = true;
+                        __hip_atomic_fetch_add(&P.dev->idle, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    if (__hip_atomic_load(&P.dev->idle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                        __hip_atomic_load(&P.dev->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        for (int x = 0; x < 8; ++x)
+                            __hip_atomic_store(&P.dev->pubx[x][1], P.epoch, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&P.host->seen_closing, P.epoch, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                        act = 3;
+                    }
+                }
+                if (act != 3) {
+                    // exponential backoff, up to 8 sleeps of ~3.4 us between polls:
+                    // a thousand idle workgroups must not crowd the memory path
+                    // the busy ones use
+                    for (int b = 0; b < (1 << backoff); ++b) __builtin_amdgcn_s_sleep(127);
+                    if (backoff < kPsMaxBackoff) ++backoff;
+                }
+            } else if (pend_k < 0) {
+                backoff = 0;
+            }
+            if (counted && (act == 1 || act == 2 || act == 3)) {  // found work, or leaves
+                counted = false;
+                __hip_atomic_fetch_sub(&P.dev->idle, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             s_act = act;
         }
@@ -369,6 +520,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void ps
         if (act == 2) {
             // copy request s_k from its ring slot (host memory) into LDS, then
             // acquire what the host wrote to device memory before publishing it
+            // (once per generation of device data)
             const long long k = s_k;
             const unsigned long long *src =
                 reinterpret_cast<const unsigned long long *>(&P.ring[k % TOR_PS_SLOTS]);
@@ -377,7 +529,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void ps
             static_assert(sizeof(PsReq) % 8 == 0, "request copied in 8-byte words");
             for (int w = lane; w < W; w += 64)
                 dst[w] = __hip_atomic_load(&src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            wave_sync();
+            if (R.gen != acq_gen) {  // device data made since this workgroup last acquired
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                acq_gen = R.gen;
+            }
             wave_sync();
             const bool ok = R.seq == k;
             cached = ok ? k : -1;
@@ -386,14 +542,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void ps
                     unsigned long long kk = (unsigned long long)k;
                     __hip_atomic_compare_exchange_strong(&P.dev->cur, &kk, kk + 1, __ATOMIC_RELAXED,
                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                } else if (wall_clock64() - idle_since > (unsigned long long)P.idle_ticks) {
-                    s_act = 3;  // not visible yet: wait as for no work (bounded)
                 } else {
-                    __builtin_amdgcn_s_sleep(64);
+                    __builtin_amdgcn_s_sleep(64);  // not visible yet (the claim loop still sees the stop flag)
                 }
             }
             wave_sync();
-            if (s_act == 3) break;
             continue;
         }
         // --- a unit of request cached
@@ -425,6 +578,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void ps
         }
         wave_sync();
     }
+    if (lane == 0 && __hip_atomic_fetch_sub(&P.dev->active, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1)
+        ps_mirror(P);  // the last workgroup to exit
 }
 
 }  // namespace tor

@@ -78,3 +78,12 @@ def test_null_context_rejected_displaced():
 
 def test_null_state_rejected_by_invert():
     assert tg.lib().tor_state_invert(None, tg.PREC_DD) == tg.TOR_EINVAL
+
+
+def test_binding_constants_match_header():
+    src = open(os.path.join(ROOT, "include", "tor.h")).read()
+    consts = dict(re.findall(r"^#define (TOR_[A-Z_]+) \(?(-?\d+)\)?", src, flags=re.M))
+    for name in ("TOR_OK", "TOR_WARN_PRECISION", "TOR_EINVAL", "TOR_ENOTPD", "TOR_ETOOBIG", "TOR_ENOMEM",
+                 "TOR_EDEVICE", "TOR_EAGAIN"):
+        assert getattr(tg, name) == int(consts[name]), name
+    assert tg.PS_SLOTS == int(consts["TOR_PS_SLOTS"])

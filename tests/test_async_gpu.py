@@ -118,6 +118,7 @@ def test_async_admission_by_pool(st800):
     cov, _ = st800
     with tg.Context(0) as c:
         st = c.state(cov)
+        c.set_option(tg.OPT_TASK_MODES, 10)  # the tree sizes below (not the tuning table's choice)
         c.set_option(tg.OPT_ASYNC_POOL, 1 << 20)
         pats = _patterns(800, [16] * 7, 9)
         out = c.batch_async(st, _dev(pats), prec="dd")
