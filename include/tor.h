@@ -571,8 +571,9 @@ tor_status tor_pserver_get_stats(tor_pserver *srv, tor_pserver_stats *out);
 /* Autotuner of the persistent schedule: for each tree size n in [n_lo, n_hi]
  * and every depth-first unit depth t (units of 2^t wave tasks; the task size
  * is the batched path's, so results stay bitwise tor_batch's) time one query
- * alone and a burst of eight (a synthetic 32-mode state), and keep the t of
- * the least latency plus time per query of the burst in the server's context;
+ * alone and a burst of 32 (a synthetic 32-mode state), and keep in the
+ * server's context the t of the least time per query in the burst among those
+ * whose time alone is within 1.5x (+ 20 us) of the least;
  * with cache_path also write the context's whole table (task sizes and unit
  * depths) as JSON for tor_load_tuning.  With the environment variable
  * TOR_TUNE_VERBOSE set (not "0") every measurement goes to stderr.  A context

@@ -3890,10 +3890,12 @@ tor_status tor_pserver_autotune(tor_pserver *S, int32_t n_lo, int32_t n_hi, cons
     tor_ctx *ctx = S->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
     // a synthetic 32-mode state (sigma = I + B B^T / 64, SPD), marginal queries
-    // of n clicks drawn by a fixed generator.  Cost of a unit depth: the time
-    // of one query alone (latency) plus the time per query of a burst of
-    // eight submitted together (throughput), the median of three.
-    constexpr int M = TOR_MAX_CLICKS, BURST = 8;
+    // of n clicks drawn by a fixed generator.  For each unit depth: the time of
+    // one query alone (latency) and the time per query of a burst of 32
+    // submitted together (throughput under load), medians of three.  The
+    // choice: the best throughput among the depths whose latency is within
+    // 1.5x (+ 20 us) of the best latency.
+    constexpr int M = TOR_MAX_CLICKS, BURST = 32;
     const char *vb = std::getenv("TOR_TUNE_VERBOSE");  // print each measurement to stderr
     const bool verbose = vb && *vb && *vb != '0';
     const std::vector<dd> sig = synthetic_sigma(M);
@@ -3929,12 +3931,11 @@ tor_status tor_pserver_autotune(tor_pserver *S, int32_t n_lo, int32_t n_hi, cons
                     k++;
                 }
             }
-        const int J = task_modes_for(ctx, true, n), G = n - J;
-        int best = -1;
-        double best_c = 1e300;
-        for (int t = 0; t <= std::min(G, TOR_PS_LMAX); t++) {
+        const int J = task_modes_for(ctx, true, n), G = n - J, TMAX = std::min(G, TOR_PS_LMAX);
+        std::vector<double> lat(TMAX + 1), per(TMAX + 1);
+        for (int t = 0; t <= TMAX; t++) {
             ctx->ps_t1[n] = t + 1;
-            double c[3], x;
+            double a[3], b[3];
             for (int rep = 0; rep < 4; rep++) {  // one warm-up pass, three timed
                 double one, burst;
                 s = run(pats, 1, one);
@@ -3943,18 +3944,23 @@ tor_status tor_pserver_autotune(tor_pserver *S, int32_t n_lo, int32_t n_hi, cons
                     tor_state_destroy(st);
                     return s;
                 }
-                x = one + burst / BURST;
-                if (rep) c[rep - 1] = x;
+                if (rep) {
+                    a[rep - 1] = one;
+                    b[rep - 1] = burst / BURST;
+                }
             }
-            std::sort(c, c + 3);
+            std::sort(a, a + 3);
+            std::sort(b, b + 3);
+            lat[t] = a[1];
+            per[t] = b[1];
             if (verbose)
-                std::fprintf(stderr, "pserver autotune n=%d J=%d t=%d units=%lld cost %.3f %.3f %.3f ms\n", n, J, t,
-                             1LL << (G - t), c[0] * 1e3, c[1] * 1e3, c[2] * 1e3);
-            if (c[1] < best_c) {
-                best_c = c[1];
-                best = t;
-            }
+                std::fprintf(stderr, "pserver autotune n=%d J=%d t=%d units=%lld alone %.3f ms, per query in a burst %.3f ms\n",
+                             n, J, t, 1LL << (G - t), lat[t] * 1e3, per[t] * 1e3);
         }
+        const double lmin = *std::min_element(lat.begin(), lat.end());
+        int best = 0;
+        for (int t = 0; t <= TMAX; t++)
+            if (lat[t] <= 1.5 * lmin + 20e-6 && (lat[best] > 1.5 * lmin + 20e-6 || per[t] < per[best])) best = t;
         ctx->ps_t1[n] = best + 1;
     }
     tor_state_destroy(st);

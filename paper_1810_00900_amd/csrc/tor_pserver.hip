@@ -18,10 +18,12 @@
 // requests in flight.  A sampling unit is one chain (tor_chain.hpp).
 //
 // Waiting: a workgroup waits only for new work, polling a device copy of the
-// host's control block (one workgroup at a time refreshes the copy), and exits
-// on the host's stop flag or after idle_ticks without work; the host launches
-// the kernel again when work arrives and it has exited.  Units never wait for
-// each other.
+// host's control block (one workgroup at a time refreshes the copy).  The
+// kernel exits on the host's stop flag, or as a whole once every running
+// workgroup has been idle_ticks without work (one of them closes the launch;
+// the others leave when they see it, each after the unit it holds); the host
+// launches the kernel again when work arrives, queued behind a launch that is
+// closing.  Units never wait for each other.
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
