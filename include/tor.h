@@ -116,7 +116,8 @@ typedef struct {
     int64_t expand_launches;
     int64_t reduce_launches;
     double subsets;       /* number of subset terms evaluated (2^n per sum) */
-    int64_t condition_launches; /* no-click conditioning steps (one launch each) */
+    int64_t condition_launches; /* launches of no-click conditioning (one per mode, or two per
+                                   block of TOR_OPT_COND_BLOCK modes) */
 } tor_stats;
 
 /* Options settable on a context (tor_ctx_set_option). */
@@ -129,9 +130,14 @@ typedef enum {
     TOR_OPT_WAVE_GRID = 2,  /* cap on wave-tier workgroups per launch (default 65536) */
     TOR_OPT_MEM_BUDGET = 3, /* device bytes the context may hold (default 64 GiB) */
     TOR_OPT_ASYNC_POOL = 4, /* tree pool bytes of tor_batch_async (default 4 GiB) */
-    TOR_OPT_CHAIN_CLICKS = 5 /* most clicks a chain without postselection may carry,
+    TOR_OPT_CHAIN_CLICKS = 5, /* most clicks a chain without postselection may carry,
                               1..TOR_CHAIN_CLICKS (default 15; above 15 the sampler
                               kernel uses more LDS per chain) */
+    TOR_OPT_COND_BLOCK = 6   /* no-click modes conditioned per pair of launches, 1..16
+                              (default 16; 1: one launch per mode).  Every value gives
+                              bitwise the same result: each entry takes the same
+                              rank-2 updates in the same order (Eq. MatrixUpdate
+                              iterated over the no-click modes, Sec. II) */
 } tor_option;
 
 /* Create a context on HIP device `device` (its own stream, default priority).

@@ -32,7 +32,8 @@ PREC_AUTO, PREC_F64, PREC_DD, PREC_QD = 0, 1, 2, 3
 _PREC = {"auto": PREC_AUTO, "f64": PREC_F64, "dd": PREC_DD, "qd": PREC_QD,
          PREC_AUTO: PREC_AUTO, PREC_F64: PREC_F64, PREC_DD: PREC_DD, PREC_QD: PREC_QD}
 
-OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET, OPT_ASYNC_POOL, OPT_CHAIN_CLICKS = 0, 1, 2, 3, 4, 5
+OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET, OPT_ASYNC_POOL, OPT_CHAIN_CLICKS, OPT_COND_BLOCK = (
+    0, 1, 2, 3, 4, 5, 6)
 
 _STATUS_NAMES = {0: "TOR_OK", 1: "TOR_WARN_PRECISION", -1: "TOR_EINVAL", -2: "TOR_ENOTPD",
                  -3: "TOR_ETOOBIG", -4: "TOR_ENOMEM", -5: "TOR_EDEVICE", -6: "TOR_EAGAIN"}

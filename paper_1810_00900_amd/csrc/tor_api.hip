@@ -147,6 +147,7 @@ struct tor_ctx {
     DevBuf apool, abuf;  // tor_batch_async: tree pool, plan and job tables
     size_t async_pool = (size_t)4 << 30;
     int chain_clicks = 15;  // click cap of chains without postselection
+    int cond_block = TOR_COND_BLOCK;  // no-click modes per conditioning launch pair (1: one launch per mode)
     DevBuf kbuf, koff, hbuf, hoff, c_out, c_status, c_tp, c_tu, c_sub;
     Partial *host_res = nullptr;
     size_t host_res_cap = 0;
@@ -242,11 +243,15 @@ tor_status validate_cov_block(const double *cov, int m, const int8_t *pattern) {
             if (!std::isfinite(v)) return fail(TOR_EINVAL, "cov has a non-finite entry at (%d, %d)", a, b);
             amax = std::max(amax, std::fabs(v));
         }
+    // symmetry, in 32 x 32 tiles (the transposed reads of a tile stay in cache)
     const double tol = 1e-12 * amax;
-    for (size_t x = 0; x < q.size(); x++)
-        for (size_t y = 0; y < x; y++)
-            if (std::fabs(cov[(size_t)q[x] * d + q[y]] - cov[(size_t)q[y] * d + q[x]]) > tol)
-                return fail(TOR_EINVAL, "cov is not symmetric at (%d, %d)", q[x], q[y]);
+    const size_t nq = q.size();
+    for (size_t x0 = 0; x0 < nq; x0 += 32)
+        for (size_t y0 = 0; y0 <= x0; y0 += 32)
+            for (size_t x = x0; x < std::min(nq, x0 + 32); x++)
+                for (size_t y = y0; y < std::min(x, y0 + 32); y++)
+                    if (std::fabs(cov[(size_t)q[x] * d + q[y]] - cov[(size_t)q[y] * d + q[x]]) > tol)
+                        return fail(TOR_EINVAL, "cov is not symmetric at (%d, %d)", q[x], q[y]);
     return TOR_OK;
 }
 
@@ -795,7 +800,10 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
         // a group that fits half the memory budget (at least one query)
         size_t last = first, bytes = 0;
         while (last < rs.size()) {
-            size_t b = cond_words(rs[last]) * sizeof(dd) + 64;
+            const Reduced *rl = rs[last];
+            size_t b = cond_words(rl) * sizeof(dd) + 64;
+            if (ctx->cond_block > 1)  // the block's scaled pivot columns
+                b += 2 * (size_t)ctx->cond_block * (size_t)(2 * (rl->n + rl->k) + rl->D) * sizeof(dd);
             if (last > first && bytes + b > ctx->mem_budget / 2) break;
             bytes += b;
             last++;
@@ -821,36 +829,71 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
                 gtot += r->g.size();
             }
         }
-        // jobs of every step, in step order
+        // jobs of every step (or block of steps), in step order
+        const int CB = ctx->cond_block;
         std::vector<CondJob> jobs;
+        std::vector<CondBlockJob> bjobs;
         struct Step {
             size_t first;
             int count;
-            long long blocks;
+            long long blocks, blocks2;  // the launch's workgroups (blocked: panel, bulk)
             int rmax;
         };
         std::vector<Step> steps;
-        // device layout: the matrices, then [accumulators | step jobs | gather
-        // jobs | gather rows], the latter staged from the host in one copy
-        const size_t acc_off = align_up(tot * sizeof(dd), 256);
-        const size_t job_off = align_up(acc_off + nq * 3 * sizeof(double), 256);
-        for (int t = 0; t < kmax; t++) {
-            Step st{jobs.size(), 0, 0, 1};
+        // blocked: each query's scaled pivot columns of a block, 2 CB rows of
+        // ld = its row count, after the matrices
+        std::vector<size_t> voff(nq);
+        size_t vtot = 0;
+        if (CB > 1)
             for (size_t i = 0; i < nq; i++) {
-                const Reduced *r = rs[first + i];
-                if (r->k <= t) continue;
-                CondJob j{};
-                j.r = r->n + r->k - t;
-                j.d = r->D;
-                j.begin = st.blocks;
-                jobs.push_back(j);
-                st.blocks += std::max<long long>(1, (EN(j.r - 1, j.d) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
-                st.count++;
-                st.rmax = std::max(st.rmax, j.r);
+                voff[i] = tot + vtot;
+                vtot += 2 * (size_t)CB * (size_t)(2 * (rs[first + i]->n + rs[first + i]->k) + rs[first + i]->D);
             }
-            steps.push_back(st);
+        // device layout: the matrices (and columns), then [accumulators | step
+        // jobs | gather jobs | gather rows], the latter staged from the host in
+        // one copy
+        const size_t acc_off = align_up((tot + vtot) * sizeof(dd), 256);
+        const size_t job_off = align_up(acc_off + nq * 3 * sizeof(double), 256);
+        if (CB <= 1) {
+            for (int t = 0; t < kmax; t++) {
+                Step st{jobs.size(), 0, 0, 0, 1};
+                for (size_t i = 0; i < nq; i++) {
+                    const Reduced *r = rs[first + i];
+                    if (r->k <= t) continue;
+                    CondJob j{};
+                    j.r = r->n + r->k - t;
+                    j.d = r->D;
+                    j.begin = st.blocks;
+                    jobs.push_back(j);
+                    st.blocks += std::max<long long>(1, (EN(j.r - 1, j.d) + TOR_COND_CHUNK - 1) / TOR_COND_CHUNK);
+                    st.count++;
+                    st.rmax = std::max(st.rmax, j.r);
+                }
+                steps.push_back(st);
+            }
+        } else {
+            for (int t0 = 0; t0 < kmax; t0 += CB) {
+                Step st{bjobs.size(), 0, 0, 0, 1};
+                for (size_t i = 0; i < nq; i++) {
+                    const Reduced *r = rs[first + i];
+                    if (r->k <= t0) continue;
+                    CondBlockJob j{};
+                    j.r = r->n + r->k - t0;
+                    j.b = std::min(CB, r->k - t0);
+                    j.d = r->D;
+                    j.ld = 2 * (r->n + r->k) + r->D;
+                    j.begin_panel = st.blocks;
+                    j.begin_bulk = st.blocks2;
+                    bjobs.push_back(j);
+                    st.blocks += cond_panel_blocks(j.r, j.b, j.d);
+                    st.blocks2 += cond_bulk_blocks(j.r, j.b, j.d);
+                    st.count++;
+                }
+                steps.push_back(st);
+            }
         }
-        const size_t gjob_off = align_up(job_off + jobs.size() * sizeof(CondJob), 256);
+        const size_t job_bytes = CB <= 1 ? jobs.size() * sizeof(CondJob) : bjobs.size() * sizeof(CondBlockJob);
+        const size_t gjob_off = align_up(job_off + job_bytes, 256);
         const size_t gidx_off = align_up(gjob_off + gjobs.size() * sizeof(GatherJob), 256);
         const size_t total_bytes = gidx_off + gtot * sizeof(int);
         if (total_bytes > ctx->mem_budget)
@@ -862,15 +905,27 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
         double *dacc = (double *)(dbase + acc_off);
         // job pointers (device addresses)
         size_t ji = 0;
-        for (int t = 0; t < kmax; t++)
-            for (size_t i = 0; i < nq; i++) {
-                const Reduced *r = rs[first + i];
-                if (r->k <= t) continue;
-                jobs[ji].mat = dmat + off[i];
-                jobs[ji].acc = dacc + 3 * i;
-                jobs[ji].qout = nullptr;
-                ji++;
-            }
+        if (CB <= 1) {
+            for (int t = 0; t < kmax; t++)
+                for (size_t i = 0; i < nq; i++) {
+                    const Reduced *r = rs[first + i];
+                    if (r->k <= t) continue;
+                    jobs[ji].mat = dmat + off[i];
+                    jobs[ji].acc = dacc + 3 * i;
+                    jobs[ji].qout = nullptr;
+                    ji++;
+                }
+        } else {
+            for (int t0 = 0; t0 < kmax; t0 += CB)
+                for (size_t i = 0; i < nq; i++) {
+                    const Reduced *r = rs[first + i];
+                    if (r->k <= t0) continue;
+                    bjobs[ji].mat = dmat + off[i];
+                    bjobs[ji].V = dmat + voff[i];
+                    bjobs[ji].acc = dacc + 3 * i;
+                    ji++;
+                }
+        }
         // the staged tail: accumulators, step jobs, gather jobs and rows
         std::vector<unsigned char> &stage = ctx->host_stage;
         const size_t tail = total_bytes - acc_off;
@@ -880,7 +935,8 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
             const double a0[3] = {1.0, 0.0, 0.0};
             std::memcpy(at(acc_off) + i * 3 * sizeof(double), a0, sizeof a0);
         }
-        std::memcpy(at(job_off), jobs.data(), jobs.size() * sizeof(CondJob));
+        if (CB <= 1) std::memcpy(at(job_off), jobs.data(), job_bytes);
+        else std::memcpy(at(job_off), bjobs.data(), job_bytes);
         {
             size_t gi = 0, gw = 0;
             int *gidx = (int *)at(gidx_off);
@@ -904,9 +960,17 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
                                        rs[first + i]->packed.size() * sizeof(dd), hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(dbase + acc_off, stage.data(), tail, hipMemcpyHostToDevice, st));
         HIP_TRY(tor_launch_cond_gather((const GatherJob *)(dbase + gjob_off), (int)gjobs.size(), gentries, st));
-        const CondJob *djobs = (const CondJob *)(dbase + job_off);
-        for (const Step &sp : steps)
-            HIP_TRY(tor_launch_condition(djobs + sp.first, sp.count, sp.blocks, sp.rmax, st));
+        if (CB <= 1) {
+            const CondJob *djobs = (const CondJob *)(dbase + job_off);
+            for (const Step &sp : steps)
+                HIP_TRY(tor_launch_condition(djobs + sp.first, sp.count, sp.blocks, sp.rmax, st));
+        } else {
+            const CondBlockJob *djobs = (const CondBlockJob *)(dbase + job_off);
+            for (const Step &sp : steps) {
+                HIP_TRY(tor_launch_cond_panel(djobs + sp.first, sp.count, sp.blocks, st));
+                HIP_TRY(tor_launch_cond_bulk(djobs + sp.first, sp.count, sp.blocks2, st));
+            }
+        }
         // results: the leading block of each matrix and the accumulators
         std::vector<std::vector<dd>> lead(nq);
         for (size_t i = 0; i < nq; i++) {
@@ -919,7 +983,7 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
         std::vector<double> accs(3 * nq);
         HIP_TRY(hipMemcpyAsync(accs.data(), dacc, accs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        ctx->stats.condition_launches += (int64_t)steps.size();
+        ctx->stats.condition_launches += (int64_t)steps.size() * (CB <= 1 ? 1 : 2);
         for (size_t i = 0; i < nq; i++) {
             Reduced *r = rs[first + i];
             const dd *pk = lead[i].data();
@@ -1745,6 +1809,10 @@ tor_status tor_ctx_set_option(tor_ctx *c, tor_option opt, int64_t v) {
     case TOR_OPT_CHAIN_CLICKS:
         if (v < 1 || v > TOR_CHAIN_CLICKS) return fail(TOR_EINVAL, "chain click cap must be in 1..%d", TOR_CHAIN_CLICKS);
         c->chain_clicks = (int)v;
+        return TOR_OK;
+    case TOR_OPT_COND_BLOCK:
+        if (v < 1 || v > TOR_COND_BLOCK) return fail(TOR_EINVAL, "conditioning block must be in 1..%d", TOR_COND_BLOCK);
+        c->cond_block = (int)v;
         return TOR_OK;
     }
     return fail(TOR_EINVAL, "unknown option %d", (int)opt);

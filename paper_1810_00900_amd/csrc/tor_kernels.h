@@ -75,6 +75,33 @@ struct CondJob {
     int d;            // 1: displaced state, the packed matrix has the mean row first
 };
 
+// Blocked conditioning: b <= TOR_COND_BLOCK no-click modes of one query per
+// pair of launches.  The panel launch walks the b modes in order on the
+// pivot block and, per column x of the rest, records each step's two scaled
+// pivot columns V[(2t + w) ld + x]; the bulk launch then applies the b
+// rank-2 updates to every remaining entry in step order (the per-mode
+// kernel's operations, entry for entry).
+#define TOR_COND_BLOCK 16
+struct CondBlockJob {
+    dd *mat;                 // packed matrix, R = 2r + d rows before the block
+    dd *V;                   // [2b][ld]: the block's scaled pivot columns
+    double *acc;             // (p hi, p lo, log p), updated in step order
+    long long begin_panel;   // first workgroup of the panel launch for this job
+    long long begin_bulk;    // first workgroup of the bulk launch for this job
+    int r, b, d, ld;
+};
+hipError_t tor_launch_cond_panel(const CondBlockJob *jobs, int njobs, long long total_blocks, hipStream_t st);
+hipError_t tor_launch_cond_bulk(const CondBlockJob *jobs, int njobs, long long total_blocks, hipStream_t st);
+// workgroups of a job's panel (256 columns each) and bulk (32 x 32 tiles) launches
+__host__ __device__ inline long long cond_panel_blocks(int r, int b, int d) {
+    const long long rb = 2LL * (r - b) + d;
+    return rb > 0 ? (rb + 255) / 256 : 1;
+}
+__host__ __device__ inline long long cond_bulk_blocks(int r, int b, int d) {
+    const long long rb = 2LL * (r - b) + d, t = (rb + 31) / 32;
+    return t > 0 ? t * (t + 1) / 2 : 0;
+}
+
 #define TOR_COND_CHUNK 1024
 // largest matrix (modes) a conditioning step takes: its two scaled pivot
 // columns (2 * (2r - 2) double-doubles) must fit 64 KiB of LDS

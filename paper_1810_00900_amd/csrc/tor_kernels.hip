@@ -172,6 +172,182 @@ __global__ __launch_bounds__(256) void condition_kernel(const CondJob *__restric
     }
 }
 
+// ---------------------------------------------------------------- blocked conditioning
+
+template <class F>
+__device__ __forceinline__ int find_cond_job(const CondBlockJob *jobs, int njobs, long long t, F begin) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (begin(jobs[mid]) <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Panel of one block of b modes of a query (rows Rb .. R - 1, Rb = R - 2b).
+// Every workgroup of the job walks the block's b steps on the 2b x 2b pivot
+// block (and the mean column of a displaced query) in LDS, exactly as the
+// per-mode kernel conditions those entries, keeping each step's pivot and the
+// scaled pivot columns of the block's own rows; then each thread takes one
+// column x < Rb: its 2b panel entries in registers, the b steps applied in
+// order, each step's two scaled pivot columns at x written to V.  Rows are
+// counted from the end (k = R - 1 - row), so a step's pivot rows are
+// k = 2t, 2t + 1 and the rows it updates k > 2t + 1.
+template <int D>
+__device__ __forceinline__ void cond_panel(const CondBlockJob &job, long long wg) {
+    constexpr int B = TOR_COND_BLOCK, NB = 2 * B;
+    __shared__ dd blk[NB * (NB + 1) / 2];  // pivot block, packed by reversed row index
+    __shared__ dd mc[NB];                  // mean column (D = 1)
+    __shared__ Pivot<dd> piv[B];
+    __shared__ dd vd[B][2][NB];            // scaled pivot columns at the block's rows
+    const int b = job.b, nb = 2 * b, R = 2 * job.r + D, Rb = R - nb;
+    dd *M = job.mat;
+    const int tid = threadIdx.x;
+    // the block's steps on one wave (wave-level ordering, no workgroup
+    // barrier per step); the other waves wait for its pivots and columns
+    __shared__ unsigned short lk[NB * (NB + 1) / 2];  // packed index -> (l, k) of the block
+    if (tid < 64) {
+        for (int e = tid; e < NB * (NB + 1) / 2; e += 64) {
+            int l, k;
+            unpack(e, l, k);
+            lk[e] = (unsigned short)(l | (k << 8));
+        }
+        // entry (k, l) of the block (rows R - 1 - k, R - 1 - l, k <= l) at pidx(l, k)
+        for (int e = tid; e < nb * (nb + 1) / 2; e += 64) {
+            int l, k;
+            unpack(e, l, k);
+            blk[e] = M[pidx(R - 1 - k, R - 1 - l)];
+        }
+        if (D)
+            for (int k = tid; k < nb; k += 64) mc[k] = M[pidx(R - 1 - k, 0)];
+        wave_sync();
+        for (int t = 0; t < b; ++t) {
+            const int k1 = 2 * t, k0 = 2 * t + 1;  // rows R_t - 1 and R_t - 2 of this step
+            // block (k, l) with k <= l is row R - 1 - k, column R - 1 - l: the
+            // entry (row p0, column p0) is blk[pidx(k0, k0)], (p1, p0) is
+            // blk[pidx(k0, k1)] (row k1 = p1 > column k0 = p0 means k1 < k0)
+            const Pivot<dd> pv = make_pivot_v<dd, D>(blk[pidx(k0, k0)], blk[pidx(k0, k1)], blk[pidx(k1, k1)],
+                                                     D ? mc[k0] : blk[0], D ? mc[k1] : blk[0]);
+            for (int k = k0 + 1 + tid; k < nb; k += 64) {  // column c = R - 1 - k < p0
+                const dd m0 = blk[pidx(k, k0)];
+                vd[t][0][k] = dd_mul(m0, pv.s1);
+                vd[t][1][k] = dd_mul(sub_mul(blk[pidx(k, k1)], pv.l, m0), pv.s2);
+            }
+            if (tid == 0) piv[t] = pv;
+            wave_sync();
+            // the block's remaining entries and mean column, as the per-mode
+            // update: all loads of a lane's (at most 8) entries first
+            const int rem = nb - (k0 + 1), nrem = rem * (rem + 1) / 2;
+            constexpr int PER = (NB * (NB + 1) / 2 + 63) / 64;
+            dd x[PER], a1[PER], b1[PER], a2[PER], b2[PER];
+            int dst[PER];
+            // (past the last entry a lane reads entry 0, (k0 + 1, k0 + 1), and
+            // stores nothing; there is none in the last step)
+#pragma unroll
+            for (int u = 0; u < PER && nrem > 0; ++u) {
+                const int e = tid + 64 * u;
+                const bool ok = e < nrem;
+                const unsigned short w = lk[ok ? e : 0];
+                const int l = (w & 0xff) + k0 + 1, k = (w >> 8) + k0 + 1;  // k <= l
+                dst[u] = ok ? pidx(l, k) : -1;
+                x[u] = blk[pidx(l, k)];
+                a1[u] = vd[t][0][k];
+                b1[u] = vd[t][0][l];
+                a2[u] = vd[t][1][k];
+                b2[u] = vd[t][1][l];
+            }
+#pragma unroll
+            for (int u = 0; u < PER && nrem > 0; ++u) {
+                const dd y = dd_sub_dot2(x[u], a1[u], b1[u], a2[u], b2[u]);
+                if (dst[u] >= 0) blk[dst[u]] = y;
+            }
+            if (D) {
+                const dd w1 = dd_mul(mc[k0], pv.s1), w2 = dd_mul(sub_mul(mc[k1], pv.l, mc[k0]), pv.s2);
+                for (int k = k0 + 1 + tid; k < nb; k += 64)
+                    mc[k] = dd_sub_dot2(mc[k], vd[t][0][k], w1, vd[t][1][k], w2);
+            }
+            wave_sync();
+        }
+        if (wg == 0 && tid == 0)  // the per-mode kernel's accumulation, in step order
+            for (int t = 0; t < b; ++t) {
+                const dd q = piv[t].q;
+                const dd p = dd_mul(dd_make(job.acc[0], job.acc[1]), q);
+                job.acc[0] = p.hi;
+                job.acc[1] = p.lo;
+                job.acc[2] += log(q.hi) + log1p(q.lo / q.hi);
+            }
+    }
+    __syncthreads();
+    // column x of the rest: its panel entries (rows R - 1 - k) in registers
+    const long long x = wg * blockDim.x + tid;
+    if (x >= Rb) return;
+    dd P[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) P[k] = k < nb ? M[pidx(R - 1 - k, (int)x)] : dd_from(0.0);
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        if (t < b) {
+            const Pivot<dd> pv = piv[t];
+            const dd m0 = P[2 * t + 1];
+            const dd v1 = dd_mul(m0, pv.s1);
+            const dd v2 = dd_mul(sub_mul(P[2 * t], pv.l, m0), pv.s2);
+            job.V[(long long)(2 * t) * job.ld + x] = v1;
+            job.V[(long long)(2 * t + 1) * job.ld + x] = v2;
+#pragma unroll
+            for (int k = 2 * t + 2; k < NB; ++k)
+                if (k < nb) P[k] = dd_sub_dot2(P[k], vd[t][0][k], v1, vd[t][1][k], v2);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void cond_panel_kernel(const CondBlockJob *__restrict__ jobs, int njobs) {
+    const int j = find_cond_job(jobs, njobs, (long long)blockIdx.x,
+                                [](const CondBlockJob &q) { return q.begin_panel; });
+    const CondBlockJob job = jobs[j];
+    const long long wg = (long long)blockIdx.x - job.begin_panel;
+    if (job.d) cond_panel<1>(job, wg);
+    else cond_panel<0>(job, wg);
+}
+
+// The rest of the matrix (rows and columns below Rb) in 32 x 32 tiles of the
+// lower triangle: each entry takes the block's b rank-2 updates in step order
+// from the recorded columns (staged in LDS for the tile's rows and columns).
+__global__ __launch_bounds__(256) void cond_bulk_kernel(const CondBlockJob *__restrict__ jobs, int njobs) {
+    constexpr int B = TOR_COND_BLOCK;
+    __shared__ dd Vr[B][2][32], Vc[B][2][32];
+    const int j = find_cond_job(jobs, njobs, (long long)blockIdx.x,
+                                [](const CondBlockJob &q) { return q.begin_bulk; });
+    const CondBlockJob job = jobs[j];
+    const long long tt = (long long)blockIdx.x - job.begin_bulk;
+    const int b = job.b, Rb = 2 * (job.r - b) + job.d;
+    // tile (I, J), J <= I, numbered row by row
+    long long I = (long long)((sqrt(8.0 * (double)tt + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > tt) --I;
+    while ((I + 1) * (I + 2) / 2 <= tt) ++I;
+    const long long J = tt - I * (I + 1) / 2;
+    const int a0 = (int)(32 * I), c0 = (int)(32 * J);
+    for (int idx = threadIdx.x; idx < b * 64; idx += blockDim.x) {
+        const int t = idx >> 6, w = (idx >> 5) & 1, l = idx & 31;
+        const dd *v = job.V + (long long)(2 * t + w) * job.ld;
+        Vr[t][w][l] = a0 + l < Rb ? v[a0 + l] : dd_from(0.0);
+        Vc[t][w][l] = c0 + l < Rb ? v[c0 + l] : dd_from(0.0);
+    }
+    __syncthreads();
+    dd *M = job.mat;
+    const int cl = threadIdx.x & 31, c = c0 + cl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int al = (threadIdx.x >> 5) + 8 * q, a = a0 + al;
+        if (a < Rb && c <= a) {
+            const long long e = (long long)a * (a + 1) / 2 + c;
+            dd x = M[e];
+            for (int t = 0; t < b; ++t) x = dd_sub_dot2(x, Vr[t][0][al], Vc[t][0][cl], Vr[t][1][al], Vc[t][1][cl]);
+            M[e] = x;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- reduction
 
 // One reduction stage: block b of a job sums in[b*chunk, min((b+1)*chunk, count))
@@ -287,6 +463,22 @@ hipError_t tor_launch_condition(const CondJob *jobs, int njobs, long long total_
     const size_t lds = sizeof(dd) * 2 * (2 * (size_t)rmax - 1) + 16;  // 2 columns of 2 rmax - 1 rows (mean row)
     (void)hipGetLastError();  // report only this launch's error
     hipLaunchKernelGGL(tor::condition_kernel, dim3((unsigned)total_blocks), dim3(256), lds, st, jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t tor_launch_cond_panel(const CondBlockJob *jobs, int njobs, long long total_blocks, hipStream_t st) {
+    if (total_blocks < 1) return hipSuccess;
+    if (total_blocks > (1LL << 31) - 1) return hipErrorInvalidValue;
+    (void)hipGetLastError();  // report only this launch's error
+    hipLaunchKernelGGL(tor::cond_panel_kernel, dim3((unsigned)total_blocks), dim3(256), 0, st, jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t tor_launch_cond_bulk(const CondBlockJob *jobs, int njobs, long long total_blocks, hipStream_t st) {
+    if (total_blocks < 1) return hipSuccess;
+    if (total_blocks > (1LL << 31) - 1) return hipErrorInvalidValue;
+    (void)hipGetLastError();  // report only this launch's error
+    hipLaunchKernelGGL(tor::cond_bulk_kernel, dim3((unsigned)total_blocks), dim3(256), 0, st, jobs, njobs);
     return hipGetLastError();
 }
 

@@ -89,16 +89,25 @@ __device__ __forceinline__ Pivot<S> make_pivot(S al, S be, S ga) {
 // vacuum probability of the mode gains the overlap factor exp(-|w|^2 / 2) of
 // its (conditioned) mean, w = L^-1 mu_B = (v1(0), v2(0)): row 0 holds the
 // means, so w is the mean row's entry of the two scaled pivot columns.
+// The same from the entries themselves: al, be, ga of the pivot block and,
+// with a mean row, the block's mean entries m0, m1 (ignored without one).
 template <class S, int D>
-__device__ __forceinline__ Pivot<S> make_pivot_m(const S *M, int p0, int p1) {
-    Pivot<S> pv = make_pivot(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)]);
+__device__ __forceinline__ Pivot<S> make_pivot_v(S al, S be, S ga, S m0, S m1) {
+    Pivot<S> pv = make_pivot(al, be, ga);
     if constexpr (D != 0) {
-        const S m0 = M[pidx(p0, 0)];
         const S w1 = mul_s(m0, pv.s1);
-        const S w2 = mul_s(sub_mul(M[pidx(p1, 0)], pv.l, m0), pv.s2);
+        const S w2 = mul_s(sub_mul(m1, pv.l, m0), pv.s2);
         pv.q = mul_s(pv.q, exp_s(scale_s(add_s(mul_s(w1, w1), mul_s(w2, w2)), D > 0 ? -0.5 : 0.5)));
     }
     return pv;
+}
+
+template <class S, int D>
+__device__ __forceinline__ Pivot<S> make_pivot_m(const S *M, int p0, int p1) {
+    if constexpr (D != 0)
+        return make_pivot_v<S, D>(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)], M[pidx(p0, 0)], M[pidx(p1, 0)]);
+    else
+        return make_pivot_v<S, D>(M[pidx(p0, p0)], M[pidx(p1, p0)], M[pidx(p1, p1)], M[0], M[0]);
 }
 
 // Signed sums and path coefficients: double-double for the binary64 and

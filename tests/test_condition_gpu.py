@@ -6,8 +6,9 @@ one in-place Schur step per mode, batched over queries).
   pair, from the binary64 matrix entries) and the pair closed forms;
 * a Haar-random 200-mode state, full patterns (every mode observed) against
   the binary128 oracle, which conditions with one Cholesky of sigma_Q[N];
-* batches equal single calls bitwise; one conditioning launch per no-click
-  mode of the largest query.
+* batches equal single calls bitwise; the conditioning of blocks of up to 16
+  no-click modes per pair of launches equals one launch per mode bitwise
+  (zero-mean and displaced, full 800-mode patterns, partial blocks).
 """
 import itertools
 
@@ -101,7 +102,16 @@ def test_tmsv_pairs_800_modes_hundreds_of_no_clicks(ctx):
     assert abs(float((want - closed) / want)) < 1e-12
     ctx.reset_stats()
     r = ctx.probability(cov, pat, prec="dd")
-    assert ctx.stats()["condition_launches"] == 600
+    assert ctx.stats()["condition_launches"] == 2 * ((600 + 15) // 16)  # blocks of 16 modes, two launches each
+    ctx.set_option(tg.OPT_COND_BLOCK, 1)
+    try:
+        ctx.reset_stats()
+        r1 = ctx.probability(cov, pat, prec="dd")
+        assert ctx.stats()["condition_launches"] == 600  # one launch per mode
+    finally:
+        ctx.set_option(tg.OPT_COND_BLOCK, 16)
+    assert (r.p, r.p_lo, r.T, r.T_lo, r.abs_sum, r.log_pvac_n) == (r1.p, r1.p_lo, r1.T, r1.T_lo, r1.abs_sum,
+                                                                 r1.log_pvac_n)
     assert r.n_clicks == 20
     err = _rel(_mp_p(r), want)
     assert err <= 1e-10
@@ -156,3 +166,50 @@ def test_condition_too_many_observed_modes(ctx):
     with pytest.raises(tg.TorError) as e:
         ctx.probability(cov, pat, prec="dd")
     assert e.value.status == tg.TOR_ETOOBIG
+
+
+FIELDS = ("p", "p_lo", "log_p", "tor", "T", "T_lo", "abs_sum", "log_pvac_n", "n_clicks", "status")
+
+
+def _same(a, b):
+    for f in FIELDS:
+        x, y = getattr(a, f), getattr(b, f)
+        assert x == y or (x != x and y != y), (f, x, y)
+
+
+@pytest.mark.parametrize("block", [16, 5, 2])
+def test_blocked_conditioning_equals_per_mode(ctx, block):
+    """Each entry takes the same rank-2 updates in the same order, whatever the
+    block: results are bitwise those of one launch per mode."""
+    rng = np.random.default_rng(211)
+    cov800 = gi.state_m800(30)
+    cases = [(cov800, gi.full_pattern(800, gi.random_click_set(800, 20, rng)), None)]  # 780 no-click modes
+    m = 90
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.3, 0.9, m))
+    mean = gi.random_mean(m, rng)
+    for n, nz in ((6, m - 6), (0, m), (9, 7), (4, 16), (3, 17)):  # full patterns, and partial blocks
+        pat = -np.ones(m, np.int8)
+        idx = rng.permutation(m)
+        pat[idx[:n]] = 1
+        pat[idx[n:n + nz]] = 0
+        cases.append((cov, pat, None))
+        cases.append((cov, pat, mean))
+    want = []
+    ctx.set_option(tg.OPT_COND_BLOCK, 1)
+    try:
+        for c, p, mu in cases:
+            want.append(ctx.probability(c, p, prec="dd") if mu is None else
+                        ctx.probability_displaced(c, mu, p, prec="dd"))
+        ctx.set_option(tg.OPT_COND_BLOCK, block)
+        for (c, p, mu), w in zip(cases, want):
+            r = ctx.probability(c, p, prec="dd") if mu is None else ctx.probability_displaced(c, mu, p, prec="dd")
+            _same(r, w)
+        # a batch mixing block counts (queries of a state, conditioned together)
+        st = ctx.state(cov)
+        pats = np.stack([p for c, p, mu in cases[1:] if mu is None])
+        res, _ = ctx.batch(st, pats, prec="dd")
+        for r, w in zip(res, [w for (c, p, mu), w in zip(cases[1:], want[1:]) if mu is None]):
+            _same(r, w)
+        st.close()
+    finally:
+        ctx.set_option(tg.OPT_COND_BLOCK, 16)
