@@ -197,9 +197,15 @@ def per_n_rates(ctx, cov, prec, ns=(20, 24, 28, 32), full=False, mean=None):
             r = call(pat)
         dt = (time.perf_counter() - t) / reps
         st = ctx.stats()
-        out[str(n)] = {"subset_dets_per_s": 2.0 ** n / dt, "ms": dt * 1e3,
-                       "kernel_ms": (st["wave_ms"] + st["expand_ms"] + st["reduce_ms"]) / reps,
+        kms = (st["wave_ms"] + st["expand_ms"] + st["reduce_ms"]) / reps
+        out[str(n)] = {"subset_dets_per_s": 2.0 ** n / dt, "ms": dt * 1e3, "kernel_ms": kms,
                        "rel_err_bound": r.rel_err_bound}
+        if prec == "dd" and mean is None and not full:
+            # algorithmic flops of the whole tree (expand levels and wave tasks)
+            # over the whole call and over the kernels' time, against FP64 peak
+            f = tree_flops(n)
+            out[str(n)]["frac_call"] = f / dt / 1e12 / FP64_PEAK_TFLOPS
+            out[str(n)]["frac_kernels"] = f / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS if kms > 0 else None
         if full:
             out[str(n)]["no_click_modes"] = int((pat == 0).sum())
             out[str(n)]["condition_launches"] = st["condition_launches"] // reps
@@ -654,6 +660,18 @@ def main():
     }
     if args.variant != "zero-mean":
         out["metric"] = METRIC + f" ({args.variant} variant)"
+    if args.variant == "zero-mean" and prec == "dd":
+        # the metric covers n = 20..28: whole calls at n = 20 and 24 beside the
+        # headline (frac over the call and over its kernels, algorithmic flops)
+        pn = per_n_rates(ctx, cov, "dd", ns=(20, 24))
+        out["roofline_per_n"] = {k: {"subset_dets_per_s": v["subset_dets_per_s"], "ms_per_call": v["ms"],
+                                     "frac_call": v["frac_call"], "frac_kernels": v["frac_kernels"]}
+                                 for k, v in pn.items()}
+        kms = (st["wave_ms"] + st["expand_ms"] + st["reduce_ms"]) / args.steps
+        out["roofline_per_n"][str(n)] = {"subset_dets_per_s": value, "ms_per_call": ms_per_step,
+                                         "frac_call": tree_flops(n) * args.steps / wall / 1e12 / FP64_PEAK_TFLOPS,
+                                         "frac_kernels": tree_flops(n) / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+
     def step(name, fn, *a, **kw):  # one extra measurement, with a progress line on stderr
         t = time.perf_counter()
         out[name] = fn(*a, **kw)
