@@ -118,7 +118,14 @@ typedef struct {
     double subsets;       /* number of subset terms evaluated (2^n per sum) */
     int64_t condition_launches; /* launches of no-click conditioning (one per mode, or two per
                                    block of TOR_OPT_COND_BLOCK modes) */
+    int64_t fused_launches; /* single-launch subset sums (TOR_OPT_FUSED); each also counts as a
+                               wave launch and its time as wave_ms */
 } tor_stats;
+
+/* Most wave-tier tasks of a group of subset sums in the single-launch path
+ * (TOR_OPT_FUSED); larger groups take the launch chain, whose shared HBM
+ * levels then cost less than each unit's own walk from Sigma_C. */
+#define TOR_FUSED_MAX_TASKS 4096
 
 /* Options settable on a context (tor_ctx_set_option). */
 typedef enum {
@@ -133,11 +140,18 @@ typedef enum {
     TOR_OPT_CHAIN_CLICKS = 5, /* most clicks a chain without postselection may carry,
                               1..TOR_CHAIN_CLICKS (default 15; above 15 the sampler
                               kernel uses more LDS per chain) */
-    TOR_OPT_COND_BLOCK = 6   /* no-click modes conditioned per pair of launches, 1..16
+    TOR_OPT_COND_BLOCK = 6,  /* no-click modes conditioned per pair of launches, 1..16
                               (default 16; 1: one launch per mode).  Every value gives
                               bitwise the same result: each entry takes the same
                               rank-2 updates in the same order (Eq. MatrixUpdate
                               iterated over the no-click modes, Sec. II) */
+    TOR_OPT_FUSED = 7        /* 1 (default): a group of zero-mean subset sums whose trees have at
+                              most 22 modes and which has at most TOR_FUSED_MAX_TASKS wave-tier tasks runs in
+                              one launch (each workgroup rebuilds its unit's node from Sigma_C;
+                              block completion counters order the reduction); 0: always the
+                              launch chain (one expansion launch per HBM level, the wave tier,
+                              the reduction stages).  Both give bitwise the same results: the
+                              same nodes, tasks and summation order */
 } tor_option;
 
 /* Create a context on HIP device `device` (its own stream, default priority).

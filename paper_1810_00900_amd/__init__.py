@@ -26,14 +26,15 @@ TOR_ETOOBIG = -3
 TOR_ENOMEM = -4
 TOR_EDEVICE = -5
 TOR_EAGAIN = -6
+FUSED_MAX_TASKS = 4096  # tor.h TOR_FUSED_MAX_TASKS
 PS_SLOTS = 4096  # TOR_PS_SLOTS: request slots of the persistent loop's ring
 
 PREC_AUTO, PREC_F64, PREC_DD, PREC_QD = 0, 1, 2, 3
 _PREC = {"auto": PREC_AUTO, "f64": PREC_F64, "dd": PREC_DD, "qd": PREC_QD,
          PREC_AUTO: PREC_AUTO, PREC_F64: PREC_F64, PREC_DD: PREC_DD, PREC_QD: PREC_QD}
 
-OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET, OPT_ASYNC_POOL, OPT_CHAIN_CLICKS, OPT_COND_BLOCK = (
-    0, 1, 2, 3, 4, 5, 6)
+(OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET, OPT_ASYNC_POOL, OPT_CHAIN_CLICKS, OPT_COND_BLOCK,
+ OPT_FUSED) = (0, 1, 2, 3, 4, 5, 6, 7)
 
 _STATUS_NAMES = {0: "TOR_OK", 1: "TOR_WARN_PRECISION", -1: "TOR_EINVAL", -2: "TOR_ENOTPD",
                  -3: "TOR_ETOOBIG", -4: "TOR_ENOMEM", -5: "TOR_EDEVICE", -6: "TOR_EAGAIN"}
@@ -58,7 +59,8 @@ class _CStats(ctypes.Structure):
     _fields_ = [("wave_ms", ctypes.c_double), ("expand_ms", ctypes.c_double),
                 ("reduce_ms", ctypes.c_double), ("wave_launches", ctypes.c_int64),
                 ("expand_launches", ctypes.c_int64), ("reduce_launches", ctypes.c_int64),
-                ("subsets", ctypes.c_double), ("condition_launches", ctypes.c_int64)]
+                ("subsets", ctypes.c_double), ("condition_launches", ctypes.c_int64),
+                ("fused_launches", ctypes.c_int64)]
 
 
 class _CGbsStats(ctypes.Structure):

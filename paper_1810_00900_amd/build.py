@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libtorgbs.so")
 SOURCES = ["csrc/tor_api.hip", "csrc/tor_kernels.hip", "csrc/tor_kernels_disp.hip", "csrc/tor_kernels_info.hip",
            "csrc/tor_kernels_qd.hip",
            "csrc/gbs_sampler.hip", "csrc/tor_async.hip", "csrc/tor_invert.hip", "csrc/tor_gather.hip",
-           "csrc/tor_pserver.hip"]
+           "csrc/tor_pserver.hip", "csrc/tor_fused.hip"]
 
 # -ffp-contract=off: the double-double error-free transformations must not be
 # fused into FMAs by the compiler (explicit fma() calls are kept).

@@ -148,6 +148,10 @@ struct tor_ctx {
     size_t async_pool = (size_t)4 << 30;
     int chain_clicks = 15;  // click cap of chains without postselection
     int cond_block = TOR_COND_BLOCK;  // no-click modes per conditioning launch pair (1: one launch per mode)
+    bool fused = true;  // small zero-mean trees in one launch (tor_fused.hip)
+    DevBuf fctr;        // completion counters of the single-launch path (zero between launches)
+    unsigned char *pin_stage = nullptr;  // pinned upload buffer of the single-launch path
+    size_t pin_cap = 0;
     DevBuf kbuf, koff, hbuf, hoff, c_out, c_status, c_tp, c_tu, c_sub;
     Partial *host_res = nullptr;
     size_t host_res_cap = 0;
@@ -511,6 +515,161 @@ size_t sum_bytes(int n, int J, size_t es, int D = 0) {
            1024;
 }
 
+// Single-launch path (tor_fused.hip): every tree of the group is zero-mean
+// with at most TOR_FUSED_MAX_N modes and the group has at most
+// TOR_FUSED_MAX_TASKS wave-tier tasks.
+
+bool fused_fits(const tor_ctx *ctx, const std::vector<SumIn> &in, const std::vector<int> &idx, bool use_dd) {
+    if (!ctx->fused || idx.empty()) return false;
+    long long tasks = 0;
+    for (int q : idx) {
+        if (in[q].D != 0 || in[q].n < 1 || in[q].n > TOR_FUSED_MAX_N) return false;
+        tasks += 1LL << (in[q].n - task_modes_for(ctx, use_dd, in[q].n));
+    }
+    return tasks <= TOR_FUSED_MAX_TASKS;
+}
+
+// Depth-first levels of a unit: about 1024 units (one one-wave workgroup
+// each, a task deep) fill the device; the levels beyond are walked depth
+// first inside the units.
+int fused_levels(int G) { return std::max(0, std::min(TOR_FUSED_TMAX, G - 10)); }
+
+tor_status gpu_group_fused(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vector<int> &idx, bool use_dd,
+                           std::vector<SumOut> &out) {
+    const size_t es = use_dd ? sizeof(dd) : sizeof(double);
+    struct Plan {
+        int q, n, J, g, t;
+        long long tasks, nblk;
+        size_t root_off, part_off, ctr_off;
+    };
+    std::vector<Plan> P;
+    size_t roots = 0, parts = 0, ctrs = 0;
+    for (int q : idx) {
+        Plan p;
+        p.q = q;
+        p.n = in[q].n;
+        p.J = task_modes_for(ctx, use_dd, p.n);
+        const int G = p.n - p.J;
+        p.t = fused_levels(G);
+        p.g = G - p.t;
+        p.tasks = 1LL << G;
+        p.nblk = (p.tasks + TOR_REDUCE_CHUNK - 1) / TOR_REDUCE_CHUNK;
+        p.root_off = roots;
+        roots += (size_t)EN(p.n, 0);
+        p.part_off = parts;
+        parts += (size_t)(p.tasks + (p.nblk > 1 ? p.nblk : 0));
+        p.ctr_off = ctrs;
+        ctrs += (size_t)(1 + p.nblk);
+        P.push_back(p);
+    }
+    // one launch per task size, larger tasks first
+    std::vector<size_t> order(P.size());
+    for (size_t i = 0; i < P.size(); i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return P[a].J > P[b].J; });
+    struct Launch {
+        int J;
+        size_t first;
+        int count;
+        long long units;
+        long long stride;
+    };
+    std::vector<Launch> L;
+    long long ws_words = 0;
+    for (size_t k = 0; k < order.size(); k++) {
+        const Plan &p = P[order[k]];
+        if (L.empty() || L.back().J != p.J) L.push_back({p.J, k, 0, 0, 0});
+        Launch &l = L.back();
+        l.count++;
+        l.units += 1LL << p.g;
+        l.stride = std::max(l.stride, (long long)(1 + p.t) * EN(p.J + p.t, 0));
+    }
+    for (Launch &l : L) {
+        const long long grid = std::min<long long>(l.units, ctx->wave_grid);
+        ws_words = std::max(ws_words, grid * l.stride);
+    }
+    const size_t off_roots = align_up(P.size() * sizeof(FusedJob), 256);
+    const size_t up_bytes = off_roots + roots * es;
+    const size_t part_bytes = parts * sizeof(Partial);
+    if (up_bytes + part_bytes + (size_t)ws_words * es > ctx->mem_budget)
+        return fail(TOR_ENOMEM, "subset sums need %.2f GB of device memory (budget %.2f GB)",
+                    (up_bytes + part_bytes + (double)ws_words * es) / 1e9, ctx->mem_budget / 1e9);
+    const size_t ctr_cap = ctx->fctr.cap;
+    if (ctx->jobs.ensure(up_bytes) != hipSuccess || ctx->partA.ensure(part_bytes) != hipSuccess ||
+        ctx->pool.ensure((size_t)ws_words * es) != hipSuccess || ctx->fctr.ensure(ctrs * sizeof(unsigned)) != hipSuccess)
+        return fail(TOR_ENOMEM, "device allocation of %.2f MB failed", (up_bytes + part_bytes) / 1e6);
+    hipStream_t st = ctx->stream;
+    if (ctx->fctr.cap != ctr_cap)  // a new counter buffer starts at zero (the kernel leaves it so)
+        HIP_TRY(hipMemsetAsync(ctx->fctr.p, 0, ctx->fctr.cap, st));
+    if (ctx->pin_cap < up_bytes) {
+        if (ctx->pin_stage) (void)hipHostFree(ctx->pin_stage);
+        ctx->pin_stage = nullptr;
+        ctx->pin_cap = 0;
+        if (hipHostMalloc((void **)&ctx->pin_stage, up_bytes + up_bytes / 8, hipHostMallocDefault) != hipSuccess)
+            return fail(TOR_ENOMEM, "pinned allocation failed");
+        ctx->pin_cap = up_bytes + up_bytes / 8;
+    }
+    if (ctx->host_res_cap < P.size()) {
+        if (ctx->host_res) (void)hipHostFree(ctx->host_res);
+        ctx->host_res = nullptr;
+        ctx->host_res_cap = 0;
+        if (hipHostMalloc((void **)&ctx->host_res, sizeof(Partial) * P.size(), hipHostMallocDefault) != hipSuccess)
+            return fail(TOR_ENOMEM, "pinned allocation failed");
+        ctx->host_res_cap = P.size();
+    }
+    unsigned char *dj = (unsigned char *)ctx->jobs.p;
+    long long begin = 0;
+    int prevJ = -1;
+    for (size_t k = 0; k < order.size(); k++) {
+        const size_t i = order[k];
+        const Plan &p = P[i];
+        if (p.J != prevJ) begin = 0;  // unit indices are flat within a launch
+        prevJ = p.J;
+        FusedJob job;
+        job.root = dj + off_roots + p.root_off * es;
+        job.part = (Partial *)ctx->partA.p + p.part_off;
+        job.ctr = (unsigned *)ctx->fctr.p + p.ctr_off;
+        job.res = ctx->host_res + i;
+        job.begin = begin;
+        job.n = p.n;
+        job.g = p.g;
+        job.t = p.t;
+        std::memcpy(ctx->pin_stage + k * sizeof(FusedJob), &job, sizeof job);
+        begin += 1LL << p.g;
+        const std::vector<dd> &pk = *in[p.q].packed;
+        unsigned char *dst = ctx->pin_stage + off_roots + p.root_off * es;
+        if (use_dd) std::memcpy(dst, pk.data(), (size_t)EN(p.n, 0) * sizeof(dd));
+        else
+            for (long long e = 0; e < EN(p.n, 0); e++) ((double *)dst)[e] = pk[(size_t)e].hi + pk[(size_t)e].lo;
+    }
+    HIP_TRY(hipMemcpyAsync(dj, ctx->pin_stage, up_bytes, hipMemcpyHostToDevice, st));
+    if (ctx->timing) {
+        HIP_TRY(hipEventRecord(ctx->ev[0], st));
+        HIP_TRY(hipEventRecord(ctx->ev[1], st));
+    }
+    for (const Launch &l : L) {
+        const int grid = (int)std::min<long long>(l.units, ctx->wave_grid);
+        HIP_TRY(tor_launch_fused(use_dd, l.J, (const FusedJob *)dj + l.first, l.count, l.units, ctx->pool.p,
+                                 l.stride, grid, st));
+    }
+    if (ctx->timing) {
+        HIP_TRY(hipEventRecord(ctx->ev[2], st));
+        HIP_TRY(hipEventRecord(ctx->ev[3], st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ctx->timing) {
+        ctx->stats.wave_ms += elapsed(ctx->ev[1], ctx->ev[2]);
+    }
+    ctx->stats.wave_launches += (int64_t)L.size();
+    ctx->stats.fused_launches += (int64_t)L.size();
+    for (size_t i = 0; i < P.size(); i++) {
+        SumOut &o = out[P[i].q];
+        o.T = dd_make(ctx->host_res[i].t_hi, ctx->host_res[i].t_lo);
+        o.A = ctx->host_res[i].a;
+        ctx->stats.subsets += std::ldexp(1.0, P[i].n);
+    }
+    return TOR_OK;
+}
+
 // Evaluate a group of subset sums in shared launches.  The top n - J levels of
 // every tree are expanded in HBM (one launch per depth, all trees that reach it),
 // then one wave-tier launch per distinct J, then the per-tree reduction stages,
@@ -519,6 +678,7 @@ size_t sum_bytes(int n, int J, size_t es, int D = 0) {
 // has the same mean-row offset D.
 tor_status gpu_group(tor_ctx *ctx, const std::vector<SumIn> &in, const std::vector<int> &idx, bool use_dd,
                      std::vector<SumOut> &out) {
+    if (fused_fits(ctx, in, idx, use_dd)) return gpu_group_fused(ctx, in, idx, use_dd, out);
     const size_t es = use_dd ? sizeof(dd) : sizeof(double);
     const int D = idx.empty() ? 0 : in[idx[0]].D, mrows = MR(D);  // tree kind, mean rows
     struct Plan {
@@ -1773,7 +1933,9 @@ void tor_ctx_destroy(tor_ctx *c) {
     for (DevBuf *b : {&c->kbuf, &c->koff, &c->c_out, &c->c_status, &c->c_tp, &c->c_tu, &c->c_sub}) b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    c->fctr.release();
     if (c->host_res) (void)hipHostFree(c->host_res);
+    if (c->pin_stage) (void)hipHostFree(c->pin_stage);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     (void)hipGetLastError();  // leave no error for the next checked call
     delete c;
@@ -1813,6 +1975,10 @@ tor_status tor_ctx_set_option(tor_ctx *c, tor_option opt, int64_t v) {
     case TOR_OPT_COND_BLOCK:
         if (v < 1 || v > TOR_COND_BLOCK) return fail(TOR_EINVAL, "conditioning block must be in 1..%d", TOR_COND_BLOCK);
         c->cond_block = (int)v;
+        return TOR_OK;
+    case TOR_OPT_FUSED:
+        if (v != 0 && v != 1) return fail(TOR_EINVAL, "the single-launch switch must be 0 or 1");
+        c->fused = v != 0;
         return TOR_OK;
     }
     return fail(TOR_EINVAL, "unknown option %d", (int)opt);

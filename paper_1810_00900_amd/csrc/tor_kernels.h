@@ -55,6 +55,25 @@ struct ReduceJob {
 
 #define TOR_REDUCE_CHUNK 1024
 
+// Single-launch subset sum of a small zero-mean tree (tor_fused.hip): the tree
+// of n <= TOR_FUSED_MAX_N modes with J-mode wave-tier tasks is cut into 2^g
+// units of 2^t consecutive tasks (n = g + t + J, t <= TOR_FUSED_TMAX); flat
+// unit index `begin` is the tree's first (jobs sorted by begin).  part holds
+// 2^(g + t) task partials followed by the first reduction stage's block sums;
+// ctr holds 1 + (number of blocks) completion counters, zero before the
+// launch and zero again after it; res receives the tree's (T, A) and may be
+// host memory.
+#define TOR_FUSED_MAX_N 22
+#define TOR_FUSED_TMAX 4
+struct FusedJob {
+    const void *root;  // Sigma_C, packed lower, EN(n) scalars
+    Partial *part;
+    unsigned *ctr;
+    Partial *res;
+    long long begin;
+    int n, g, t;
+};
+
 // Job count and total work of a launch whose plan was made on the device
 // (stream-ordered batches): the kernels read them at entry when given a
 // non-null pointer, instead of their by-value arguments.
@@ -181,6 +200,10 @@ hipError_t tor_launch_expand(int is_dd, const ExpandJob *jobs, int njobs, int lo
 hipError_t tor_launch_reduce(const ReduceJob *jobs, int njobs, long long total_blocks, hipStream_t st,
                              const LaunchDims *dyn = nullptr);
 hipError_t tor_launch_gather(const Partial *const *src, int n, Partial *dst, hipStream_t st);
+// ws: grid * ws_stride scalars of per-workgroup scratch (ws_stride >= (1 + t) EN(J + t)
+// for every job); J in 1..11.
+hipError_t tor_launch_fused(int is_dd, int J, const FusedJob *jobs, int njobs, long long units, void *ws,
+                            long long ws_stride, int grid, hipStream_t st);
 hipError_t tor_launch_condition(const CondJob *jobs, int njobs, long long total_blocks, int rmax, hipStream_t st);
 
 // ---- quad-double term tier (one tree per launch sequence)
