@@ -145,13 +145,18 @@ typedef enum {
                               bitwise the same result: each entry takes the same
                               rank-2 updates in the same order (Eq. MatrixUpdate
                               iterated over the no-click modes, Sec. II) */
-    TOR_OPT_FUSED = 7        /* 1 (default): a group of zero-mean subset sums whose trees have at
+    TOR_OPT_FUSED = 7,       /* 1 (default): a group of zero-mean subset sums whose trees have at
                               most 22 modes and which has at most TOR_FUSED_MAX_TASKS wave-tier tasks runs in
                               one launch (each workgroup rebuilds its unit's node from Sigma_C;
                               block completion counters order the reduction); 0: always the
                               launch chain (one expansion launch per HBM level, the wave tier,
                               the reduction stages).  Both give bitwise the same results: the
                               same nodes, tasks and summation order */
+    TOR_OPT_CHAIN_PREC = 8   /* term precision of the chains of gbs_sample, gbs_trace and their
+                              displaced and step-traced forms: TOR_PREC_F64 (default; binary64
+                              K_j and subset terms, double-double sums) or TOR_PREC_DD
+                              (K_j as double-double words, double-double terms; about 3x the
+                              time).  The persistent loop's chains stay binary64 */
 } tor_option;
 
 /* Create a context on HIP device `device` (its own stream, default priority).
@@ -412,6 +417,22 @@ tor_status gbs_sample_displaced(tor_ctx *ctx, const double *cov, const double *m
 tor_status gbs_trace_displaced(tor_ctx *ctx, const double *cov, const double *mean, int32_t m, int32_t n_post,
                                uint64_t seed, int64_t chain_begin, int32_t nchains, double *p_click,
                                double *uniform, uint8_t *outcome, int8_t *status);
+
+/* gbs_trace (mean == NULL) or gbs_trace_displaced with two more per-step
+ * outputs (host, nchains x m, NaN where a step was not evaluated; either may be
+ * NULL): cancel_ratio receives max(A0 / |X0|, A1 / |X1|) of the step's split
+ * subset sum (X0, X1 the no-click and the all-observed sums whose ratio is
+ * P(no click), A0, A1 the sums of their terms' magnitudes; Sec. II), and
+ * err_bound an a-priori bound on the absolute error of the step's P(click):
+ * 16 ((k + 1) u + u_K) (A0 / |X0| + A1 / |X1|) X0 / X1 + 2^-52 (X0 / X1 +
+ * P(click)), k the clicks so far plus one, u the unit roundoff of the terms
+ * (2^-53, or 2^-104 with TOR_OPT_CHAIN_PREC = TOR_PREC_DD), u_K = 2m 2^-104
+ * for double-double K_j (0 for binary64 K_j, whose rounding the k + 1
+ * covers).  A coin u with |u - P(click)| above the bound is decided
+ * correctly.  Errors as for gbs_trace. */
+tor_status gbs_trace_steps(tor_ctx *ctx, const double *cov, const double *mean, int32_t m, int32_t n_post,
+                           uint64_t seed, int64_t chain_begin, int32_t nchains, double *p_click, double *uniform,
+                           uint8_t *outcome, int8_t *status, double *cancel_ratio, double *err_bound);
 
 /* The paper's benchmark mode (Sec. III, "Runtime"): one sample whose
  * outcomes are fixed in advance, measured mode by mode from the last mode down

@@ -34,7 +34,7 @@ _PREC = {"auto": PREC_AUTO, "f64": PREC_F64, "dd": PREC_DD, "qd": PREC_QD,
          PREC_AUTO: PREC_AUTO, PREC_F64: PREC_F64, PREC_DD: PREC_DD, PREC_QD: PREC_QD}
 
 (OPT_TIMING, OPT_TASK_MODES, OPT_WAVE_GRID, OPT_MEM_BUDGET, OPT_ASYNC_POOL, OPT_CHAIN_CLICKS, OPT_COND_BLOCK,
- OPT_FUSED) = (0, 1, 2, 3, 4, 5, 6, 7)
+ OPT_FUSED, OPT_CHAIN_PREC) = (0, 1, 2, 3, 4, 5, 6, 7, 8)
 
 _STATUS_NAMES = {0: "TOR_OK", 1: "TOR_WARN_PRECISION", -1: "TOR_EINVAL", -2: "TOR_ENOTPD",
                  -3: "TOR_ETOOBIG", -4: "TOR_ENOMEM", -5: "TOR_EDEVICE", -6: "TOR_EAGAIN"}
@@ -191,6 +191,8 @@ def lib():
                                   ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(_CGbsStats)], ctypes.c_int32),
         "gbs_trace_displaced": ([vp, dp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
                                  ctypes.c_int32, dp, dp, ctypes.POINTER(ctypes.c_uint8), i8p], ctypes.c_int32),
+        "gbs_trace_steps": ([vp, dp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
+                             ctypes.c_int32, dp, dp, ctypes.POINTER(ctypes.c_uint8), i8p, dp, dp], ctypes.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -368,9 +370,12 @@ class Context:
                                               int(seed) & (2**64 - 1), int(n_samples), op, ctypes.byref(st)))
         return out, {f: getattr(st, f) for f, _ in _CGbsStats._fields_}
 
-    def gbs_trace(self, cov, n_post: int, seed: int, chain_begin: int, nchains: int, mean=None):
+    def gbs_trace(self, cov, n_post: int, seed: int, chain_begin: int, nchains: int, mean=None,
+                  steps: bool = False):
         """Replay chains of gbs_sample (gbs_trace_displaced with a mean):
-        (p_click, uniform, outcome, status)."""
+        (p_click, uniform, outcome, status); with steps=True also the per-step
+        cancellation ratio and absolute error bound of p_click
+        (gbs_trace_steps)."""
         cov = _f64(cov)
         m = cov.shape[0] // 2
         pc = np.zeros((nchains, m))
@@ -378,6 +383,17 @@ class Context:
         oc = np.zeros((nchains, m), dtype=np.uint8)
         stt = np.zeros(nchains, dtype=np.int8)
         op = oc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        if steps:
+            rr = np.zeros((nchains, m))
+            bb = np.zeros((nchains, m))
+            if mean is not None:
+                mean = _f64(mean)
+                if mean.shape != (2 * m,):
+                    raise ValueError("mean must have 2m entries")
+            _check(lib().gbs_trace_steps(self._h, _dptr(cov), None if mean is None else _dptr(mean), m,
+                                         int(n_post), int(seed) & (2**64 - 1), int(chain_begin), int(nchains),
+                                         _dptr(pc), _dptr(un), op, _i8ptr(stt), _dptr(rr), _dptr(bb)))
+            return pc, un, oc, stt, rr, bb
         if mean is None:
             _check(lib().gbs_trace(self._h, _dptr(cov), m, int(n_post), int(seed) & (2**64 - 1), int(chain_begin),
                                    int(nchains), _dptr(pc), _dptr(un), op, _i8ptr(stt)))

@@ -62,6 +62,17 @@ hipError_t tor_launch_chains(const ChainParams &P, int grid_cap, hipStream_t st)
     if (g < 1) return hipSuccess;
     (void)hipGetLastError();  // report only this launch's error
     const bool small = P.cap + 1 <= TOR_CHAIN_MAX;
+    if (P.Klo) {  // double-double terms
+        if (P.H && small)
+            hipLaunchKernelGGL((tor::chain_kernel<dd, TOR_CHAIN_MAX, -1>), dim3((unsigned)g), dim3(64), 0, st, P);
+        else if (P.H)
+            hipLaunchKernelGGL((tor::chain_kernel<dd, TOR_CHAIN_MAX_BIG, -1>), dim3((unsigned)g), dim3(64), 0, st, P);
+        else if (small)
+            hipLaunchKernelGGL((tor::chain_kernel<dd, TOR_CHAIN_MAX, 0>), dim3((unsigned)g), dim3(64), 0, st, P);
+        else
+            hipLaunchKernelGGL((tor::chain_kernel<dd, TOR_CHAIN_MAX_BIG, 0>), dim3((unsigned)g), dim3(64), 0, st, P);
+        return hipGetLastError();
+    }
     if (P.H && small)
         hipLaunchKernelGGL((tor::chain_kernel<double, TOR_CHAIN_MAX, -1>), dim3((unsigned)g), dim3(64), 0, st, P);
     else if (P.H)

@@ -153,6 +153,8 @@ struct tor_ctx {
     unsigned char *pin_stage = nullptr;  // pinned upload buffer of the single-launch path
     size_t pin_cap = 0;
     DevBuf kbuf, koff, hbuf, hoff, c_out, c_status, c_tp, c_tu, c_sub;
+    DevBuf klobuf, hlobuf, c_tr, c_tb;  // double-double chain tables; per-step ratio and bound
+    int chain_prec = TOR_PREC_F64;      // term precision of gbs_sample / gbs_trace chains
     Partial *host_res = nullptr;
     size_t host_res_cap = 0;
     std::vector<unsigned char> host_jobs, host_stage;
@@ -1930,7 +1932,9 @@ void tor_ctx_destroy(tor_ctx *c) {
     c->cond.release();
     c->apool.release();
     c->abuf.release();
-    for (DevBuf *b : {&c->kbuf, &c->koff, &c->c_out, &c->c_status, &c->c_tp, &c->c_tu, &c->c_sub}) b->release();
+    for (DevBuf *b : {&c->kbuf, &c->koff, &c->hbuf, &c->hoff, &c->c_out, &c->c_status, &c->c_tp, &c->c_tu,
+                      &c->c_sub, &c->klobuf, &c->hlobuf, &c->c_tr, &c->c_tb})
+        b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     c->fctr.release();
@@ -1975,6 +1979,11 @@ tor_status tor_ctx_set_option(tor_ctx *c, tor_option opt, int64_t v) {
     case TOR_OPT_COND_BLOCK:
         if (v < 1 || v > TOR_COND_BLOCK) return fail(TOR_EINVAL, "conditioning block must be in 1..%d", TOR_COND_BLOCK);
         c->cond_block = (int)v;
+        return TOR_OK;
+    case TOR_OPT_CHAIN_PREC:
+        if (v != TOR_PREC_F64 && v != TOR_PREC_DD)
+            return fail(TOR_EINVAL, "chain term precision must be TOR_PREC_F64 or TOR_PREC_DD");
+        c->chain_prec = (int)v;
         return TOR_OK;
     case TOR_OPT_FUSED:
         if (v != 0 && v != 1) return fail(TOR_EINVAL, "the single-launch switch must be 0 or 1");
@@ -2535,7 +2544,8 @@ namespace {
 // M[t][a] M[t][b], accumulated row pair by row pair.  Rounded to binary64.
 tor_status build_k_tables(const double *cov, int m, std::vector<double> &K, std::vector<unsigned long long> &koff,
                           const double *mean = nullptr, std::vector<double> *H = nullptr,
-                          std::vector<unsigned long long> *hoff = nullptr) {
+                          std::vector<unsigned long long> *hoff = nullptr, std::vector<double> *Klo = nullptr,
+                          std::vector<double> *Hlo = nullptr) {
     const int d = 2 * m;
     std::vector<dd> L((size_t)d * d), rinv;
     for (int a = 0; a < d; a++)
@@ -2568,7 +2578,9 @@ tor_status build_k_tables(const double *cov, int m, std::vector<double> &K, std:
         hoff->assign(m + 1, 0);
         for (int j = 0; j < m; j++) (*hoff)[j + 1] = (*hoff)[j] + (unsigned long long)(2 * j + 2);
         H->assign((*hoff)[m], 0.0);
+        if (Hlo) Hlo->assign((*hoff)[m], 0.0);
     }
+    if (Klo) Klo->assign(koff[m], 0.0);
     std::vector<dd> acc((size_t)d * d, dd_from(0.0));
     for (int j = 0; j < m; j++) {
         const int D = 2 * j + 2;
@@ -2580,23 +2592,47 @@ tor_status build_k_tables(const double *cov, int m, std::vector<double> &K, std:
             if (mean)
                 for (int a = 0; a <= t; a++) hacc[a] = dd_add(hacc[a], dd_mul(Mi[(size_t)t * d + a], z[t]));
         }
+        // binary64 words: hi + lo rounded once; low words (double-double
+        // terms): the exact remainder, so that word + low word is the
+        // double-double value
         if (mean)
-            for (int a = 0; a < D; a++) (*H)[(*hoff)[j] + a] = hacc[a].hi + hacc[a].lo;
+            for (int a = 0; a < D; a++) {
+                double w, r;
+                two_sum(hacc[a].hi, hacc[a].lo, w, r);
+                (*H)[(*hoff)[j] + a] = w;
+                if (Hlo) (*Hlo)[(*hoff)[j] + a] = r;
+            }
         double *Kj = K.data() + koff[j];
+        double *Klj = Klo ? Klo->data() + koff[j] : nullptr;
         for (int a = 0; a < D; a++)
             for (int b = 0; b <= a; b++) {
                 dd v = acc[(size_t)a * d + b];
-                Kj[(size_t)a * D + b] = Kj[(size_t)b * D + a] = v.hi + v.lo;
+                double w, r;
+                two_sum(v.hi, v.lo, w, r);
+                Kj[(size_t)a * D + b] = Kj[(size_t)b * D + a] = w;
+                if (Klj) Klj[(size_t)a * D + b] = Klj[(size_t)b * D + a] = r;
             }
     }
     return TOR_OK;
 }
 
-tor_status upload_chain_tables(tor_ctx *ctx, const double *cov, int m, const double *mean = nullptr) {
-    std::vector<double> K, H;
+tor_status upload_chain_tables(tor_ctx *ctx, const double *cov, int m, const double *mean = nullptr,
+                               bool dd_terms = false) {
+    std::vector<double> K, H, Klo, Hlo;
     std::vector<unsigned long long> koff, hoff;
-    tor_status s = build_k_tables(cov, m, K, koff, mean, &H, &hoff);
+    tor_status s = build_k_tables(cov, m, K, koff, mean, &H, &hoff, dd_terms ? &Klo : nullptr,
+                                  dd_terms ? &Hlo : nullptr);
     if (s) return s;
+    if (dd_terms) {
+        if (ctx->klobuf.ensure(Klo.size() * sizeof(double)) != hipSuccess ||
+            (mean && ctx->hlobuf.ensure(Hlo.size() * sizeof(double)) != hipSuccess))
+            return fail(TOR_ENOMEM, "device allocation of the double-double K tables failed");
+        HIP_TRY(hipMemcpyAsync(ctx->klobuf.p, Klo.data(), Klo.size() * sizeof(double), hipMemcpyHostToDevice,
+                               ctx->stream));
+        if (mean)
+            HIP_TRY(hipMemcpyAsync(ctx->hlobuf.p, Hlo.data(), Hlo.size() * sizeof(double), hipMemcpyHostToDevice,
+                                   ctx->stream));
+    }
     if (mean) {
         if (ctx->hbuf.ensure(H.size() * sizeof(double)) != hipSuccess ||
             ctx->hoff.ensure(hoff.size() * sizeof(unsigned long long)) != hipSuccess)
@@ -2630,14 +2666,16 @@ tor_status check_sampler_args(const double *cov, int m, int n_post, const double
 }
 
 tor_status run_chains(tor_ctx *ctx, int m, int n_post, uint64_t seed, long long begin, int nchains, bool trace,
-                      bool displaced = false) {
+                      bool displaced = false, bool dd_terms = false, bool steps = false) {
     const size_t nm = (size_t)nchains * (size_t)m;
     if (ctx->c_out.ensure(nm) != hipSuccess || ctx->c_status.ensure((size_t)nchains) != hipSuccess ||
         ctx->c_sub.ensure((size_t)nchains * sizeof(double)) != hipSuccess ||
         (trace && (ctx->c_tp.ensure(nm * sizeof(double)) != hipSuccess ||
-                   ctx->c_tu.ensure(nm * sizeof(double)) != hipSuccess)))
+                   ctx->c_tu.ensure(nm * sizeof(double)) != hipSuccess)) ||
+        (steps && (ctx->c_tr.ensure(nm * sizeof(double)) != hipSuccess ||
+                   ctx->c_tb.ensure(nm * sizeof(double)) != hipSuccess)))
         return fail(TOR_ENOMEM, "device allocation for %d chains failed", nchains);
-    ChainParams P;
+    ChainParams P{};
     P.K = (const double *)ctx->kbuf.p;
     P.koff = (const unsigned long long *)ctx->koff.p;
     P.H = displaced ? (const double *)ctx->hbuf.p : nullptr;  // null selects the zero-mean kernels
@@ -2653,6 +2691,10 @@ tor_status run_chains(tor_ctx *ctx, int m, int n_post, uint64_t seed, long long 
     P.trace_p = trace ? (double *)ctx->c_tp.p : nullptr;
     P.trace_u = trace ? (double *)ctx->c_tu.p : nullptr;
     P.subsets = (double *)ctx->c_sub.p;
+    P.Klo = dd_terms ? (const double *)ctx->klobuf.p : nullptr;  // non-null selects double-double terms
+    P.Hlo = dd_terms && displaced ? (const double *)ctx->hlobuf.p : nullptr;
+    P.trace_r = steps ? (double *)ctx->c_tr.p : nullptr;
+    P.trace_b = steps ? (double *)ctx->c_tb.p : nullptr;
     HIP_TRY(tor_launch_chains(P, 256 * 8, ctx->stream));
     return TOR_OK;
 }
@@ -2865,7 +2907,8 @@ static tor_status sample_impl(tor_ctx *ctx, const double *cov, const double *mea
     if (s) return s;
     HIP_TRY(hipSetDevice(ctx->device));
     auto t0 = std::chrono::steady_clock::now();
-    s = upload_chain_tables(ctx, cov, m, mean);
+    const bool dd_terms = ctx->chain_prec == TOR_PREC_DD;
+    s = upload_chain_tables(ctx, cov, m, mean, dd_terms);
     if (s) return s;
     const int NB = 16384;
     std::vector<unsigned char> out((size_t)NB * m);
@@ -2876,7 +2919,7 @@ static tor_status sample_impl(tor_ctx *ctx, const double *cov, const double *mea
     int got = 0;
     while (got < n_samples) {
         if (begin >= (1LL << 31)) return fail(TOR_EAGAIN, "no %d accepted samples within 2^31 chains", n_samples);
-        s = run_chains(ctx, m, n_post, seed, begin, NB, false, mean != nullptr);
+        s = run_chains(ctx, m, n_post, seed, begin, NB, false, mean != nullptr, dd_terms);
         if (s) return s;
         HIP_TRY(hipMemcpyAsync(out.data(), ctx->c_out.p, out.size(), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipMemcpyAsync(st.data(), ctx->c_status.p, st.size(), hipMemcpyDeviceToHost, ctx->stream));
@@ -3045,18 +3088,24 @@ tor_status gbs_chain_fixed_displaced(tor_ctx *ctx, const double *cov, const doub
 // gbs_trace and its displaced form (mean != NULL)
 static tor_status trace_impl(tor_ctx *ctx, const double *cov, const double *mean, int32_t m, int32_t n_post,
                              uint64_t seed, int64_t chain_begin, int32_t nchains, double *p_click, double *uniform,
-                             uint8_t *outcome, int8_t *status) {
+                             uint8_t *outcome, int8_t *status, double *cancel_ratio = nullptr,
+                             double *err_bound = nullptr) {
     if (!ctx) return fail(TOR_EINVAL, "ctx is NULL");
     if (nchains < 0 || chain_begin < 0) return fail(TOR_EINVAL, "bad chain range");
     tor_status s = check_sampler_args(cov, m, n_post, mean, mean != nullptr);
     if (s) return s;
     if (nchains == 0) return TOR_OK;
     HIP_TRY(hipSetDevice(ctx->device));
-    s = upload_chain_tables(ctx, cov, m, mean);
+    const bool dd_terms = ctx->chain_prec == TOR_PREC_DD, steps = cancel_ratio || err_bound;
+    s = upload_chain_tables(ctx, cov, m, mean, dd_terms);
     if (s) return s;
-    s = run_chains(ctx, m, n_post, seed, chain_begin, nchains, true, mean != nullptr);
+    s = run_chains(ctx, m, n_post, seed, chain_begin, nchains, true, mean != nullptr, dd_terms, steps);
     if (s) return s;
     const size_t nm = (size_t)nchains * m;
+    if (cancel_ratio)
+        HIP_TRY(hipMemcpyAsync(cancel_ratio, ctx->c_tr.p, nm * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (err_bound)
+        HIP_TRY(hipMemcpyAsync(err_bound, ctx->c_tb.p, nm * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     if (p_click)
         HIP_TRY(hipMemcpyAsync(p_click, ctx->c_tp.p, nm * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     if (uniform)
@@ -3078,6 +3127,13 @@ tor_status gbs_trace_displaced(tor_ctx *ctx, const double *cov, const double *me
                                double *uniform, uint8_t *outcome, int8_t *status) {
     if (!mean) return fail(TOR_EINVAL, "mean is NULL");
     return trace_impl(ctx, cov, mean, m, n_post, seed, chain_begin, nchains, p_click, uniform, outcome, status);
+}
+
+tor_status gbs_trace_steps(tor_ctx *ctx, const double *cov, const double *mean, int32_t m, int32_t n_post,
+                           uint64_t seed, int64_t chain_begin, int32_t nchains, double *p_click, double *uniform,
+                           uint8_t *outcome, int8_t *status, double *cancel_ratio, double *err_bound) {
+    return trace_impl(ctx, cov, mean, m, n_post, seed, chain_begin, nchains, p_click, uniform, outcome, status,
+                      cancel_ratio, err_bound);
 }
 
 }  // extern "C"

@@ -45,18 +45,20 @@ __device__ __forceinline__ double philox_uniform(unsigned long long seed, long l
 }
 
 // Root split of a TL-mode tree for J <= 3 (one leaf): X0 = T(exclude last),
-// X1s = -q T(include last).
+// X1s = -q T(include last), and the sums of the terms' magnitudes A0, A1 of
+// the two halves.
 template <class S, int R, int D>
-__device__ __forceinline__ void leaf_split(const S *M, dd &X0, dd &X1s) {
+__device__ __forceinline__ void leaf_split(const S *M, dd &X0, dd &X1s, double &A0, double &A1) {
     if constexpr (R == 1) {
         S q;
         if constexpr (D == 0) q = rsqrt_s(det2(M[0], M[1], M[2]));
         else q = make_pivot_m<S, D>(M, 1, 2).q;
         X0 = dd_from(1.0);
         X1s = dd_neg(to_dd(q));
+        A0 = 1.0;
+        A1 = hi_of(q);
     } else {
         constexpr int p0 = 2 * R - 2 + MR(D), p1 = 2 * R - 1 + MR(D), RC = 2 * R - 2 + MR(D);
-        double A0;
         Leaf<S, R - 1, D>::run(M, X0, A0);
         Pivot<S> pv = make_pivot_m<S, D>(M, p0, p1);
         S v1[RC], v2[RC];
@@ -72,9 +74,10 @@ __device__ __forceinline__ void leaf_split(const S *M, dd &X0, dd &X1s) {
 #pragma unroll
             for (int b = 0; b <= a; ++b) Cm[pidx(a, b)] = sub_dot2(M[pidx(a, b)], v1[a], v1[b], v2[a], v2[b]);
         dd T1;
-        double A1;
-        Leaf<S, R - 1, D>::run(Cm, T1, A1);
+        double Ac;
+        Leaf<S, R - 1, D>::run(Cm, T1, Ac);
         X1s = dd_neg(coef_mul(T1, pv.q));
+        A1 = hi_of(pv.q) * Ac;
     }
 }
 
@@ -100,18 +103,21 @@ __device__ __forceinline__ S wave_schur_last(const S *in, int r, S *out, S *vt, 
 }
 
 template <class S, int J, int D> struct ChainStep {
-    // tree of the k = J modes already gathered into the wave LDS (k <= 9)
-    static __device__ __forceinline__ void run(unsigned char *raw, int lane, dd &X0, dd &X1s) {
+    // tree of the k = J modes already gathered into the wave LDS (k <= 9);
+    // this lane's shares of the two halves' sums and magnitude sums
+    static __device__ __forceinline__ void run(unsigned char *raw, int lane, dd &X0, dd &X1s, double &A0,
+                                               double &A1) {
         using C = WaveCfg<S, J, D>;
         WaveSmem<S, J, D> &sm = *reinterpret_cast<WaveSmem<S, J, D> *>(raw);
         if constexpr (C::TW == 0) {
             X0 = dd_from(0.0);
             X1s = dd_from(0.0);
+            A0 = A1 = 0.0;
             if (lane == 0) {
                 S M[EN(J, MR(D))];
 #pragma unroll
                 for (int e = 0; e < EN(J, MR(D)); ++e) M[e] = sm.mat[e];
-                leaf_split<S, J, D>(M, X0, X1s);
+                leaf_split<S, J, D>(M, X0, X1s, A0, A1);
             }
             wave_sync();
         } else {
@@ -120,6 +126,8 @@ template <class S, int J, int D> struct ChainStep {
             wave_tree<S, J, D>(sm, dd_from(1.0), 1.0, lane, T, A);
             X0 = (lane & 1) ? dd_from(0.0) : T;
             X1s = (lane & 1) ? T : dd_from(0.0);
+            A0 = (lane & 1) ? 0.0 : A;
+            A1 = (lane & 1) ? A : 0.0;
             wave_sync();
         }
     }
@@ -156,6 +164,7 @@ __device__ __forceinline__ void run_chain(const ChainParams &P, int ci, unsigned
         const int k = nc + 1;
         const int ld = 2 * j + 2;
         const double *Kj = P.K + P.koff[j];
+        const double *Klj = P.Klo ? P.Klo + P.koff[j] : nullptr;
         S *G = k <= 9 ? wmat : gbuf[0];
         for (int e = lane; e < EN(k, O); e += 64) {
             int a, b;
@@ -163,28 +172,31 @@ __device__ __forceinline__ void run_chain(const ChainParams &P, int ci, unsigned
             if (O && b == 0) {  // the mean column: h_j of the row's quadrature (0 at the corner)
                 const int aa = a - 1;
                 const int ma = (aa >> 1) < nc ? Cl[aa >> 1] : j;
-                G[e] = a == 0 ? from_pair<S>(0.0, 0.0) : from_pair<S>(P.H[P.hoff[j] + 2 * ma + (aa & 1)], 0.0);
+                const size_t he = P.hoff[j] + 2 * ma + (aa & 1);
+                G[e] = a == 0 ? from_pair<S>(0.0, 0.0) : from_pair<S>(P.H[he], P.Hlo ? P.Hlo[he] : 0.0);
                 continue;
             }
             a -= O;
             b -= O;
             const int ma = (a >> 1) < nc ? Cl[a >> 1] : j;
             const int mb = (b >> 1) < nc ? Cl[b >> 1] : j;
-            G[e] = (S)from_pair<S>(Kj[(2 * ma + (a & 1)) * ld + 2 * mb + (b & 1)], 0.0);
+            const size_t ke = (size_t)(2 * ma + (a & 1)) * ld + 2 * mb + (b & 1);
+            G[e] = (S)from_pair<S>(Kj[ke], Klj ? Klj[ke] : 0.0);
         }
         wave_sync();
         dd X0 = dd_from(0.0), X1s = dd_from(0.0);
+        double A0 = 0.0, A1 = 0.0;
         if (k <= 9) {
             switch (k) {
-            case 1: ChainStep<S, 1, D>::run(raw, lane, X0, X1s); break;
-            case 2: ChainStep<S, 2, D>::run(raw, lane, X0, X1s); break;
-            case 3: ChainStep<S, 3, D>::run(raw, lane, X0, X1s); break;
-            case 4: ChainStep<S, 4, D>::run(raw, lane, X0, X1s); break;
-            case 5: ChainStep<S, 5, D>::run(raw, lane, X0, X1s); break;
-            case 6: ChainStep<S, 6, D>::run(raw, lane, X0, X1s); break;
-            case 7: ChainStep<S, 7, D>::run(raw, lane, X0, X1s); break;
-            case 8: ChainStep<S, 8, D>::run(raw, lane, X0, X1s); break;
-            default: ChainStep<S, 9, D>::run(raw, lane, X0, X1s); break;
+            case 1: ChainStep<S, 1, D>::run(raw, lane, X0, X1s, A0, A1); break;
+            case 2: ChainStep<S, 2, D>::run(raw, lane, X0, X1s, A0, A1); break;
+            case 3: ChainStep<S, 3, D>::run(raw, lane, X0, X1s, A0, A1); break;
+            case 4: ChainStep<S, 4, D>::run(raw, lane, X0, X1s, A0, A1); break;
+            case 5: ChainStep<S, 5, D>::run(raw, lane, X0, X1s, A0, A1); break;
+            case 6: ChainStep<S, 6, D>::run(raw, lane, X0, X1s, A0, A1); break;
+            case 7: ChainStep<S, 7, D>::run(raw, lane, X0, X1s, A0, A1); break;
+            case 8: ChainStep<S, 8, D>::run(raw, lane, X0, X1s, A0, A1); break;
+            default: ChainStep<S, 9, D>::run(raw, lane, X0, X1s, A0, A1); break;
             }
         } else {
             // decisions on the top u = k - 9 modes (bit b: mode k-1-b; bit 0 is mode j)
@@ -210,18 +222,30 @@ __device__ __forceinline__ void run_chain(const ChainParams &P, int ci, unsigned
                 dd T;
                 double A;
                 wave_tree<S, 9, D>(sm, c, a, lane, T, A);
-                if (p & 1) X1s = dd_add(X1s, T);
-                else X0 = dd_add(X0, T);
+                if (p & 1) {
+                    X1s = dd_add(X1s, T);
+                    A1 += A;
+                } else {
+                    X0 = dd_add(X0, T);
+                    A0 += A;
+                }
                 wave_sync();
             }
         }
-        double dummy0 = 0.0, dummy1 = 0.0;
-        wave_reduce(X0, dummy0);
-        wave_reduce(X1s, dummy1);
+        wave_reduce(X0, A0);
+        wave_reduce(X1s, A1);
         nsub += (double)(1 << k);
-        // P(no click) = X0 / X1 with X1 = -X1s; all lanes hold the same sums
+        // P(no click) = X0 / X1 with X1 = -X1s; all lanes hold the same sums.
+        // Double-double terms: P(click) = (X1s + X0) / X1s, the difference
+        // taken before the rounding to binary64.
         const double x0 = X0.hi + X0.lo, x1 = -(X1s.hi + X1s.lo);
-        const double pclick = 1.0 - x0 / x1;
+        double pclick;
+        if constexpr (sizeof(S) > sizeof(double)) {
+            const dd num = dd_add(X1s, X0);
+            pclick = (num.hi + num.lo) / (X1s.hi + X1s.lo);
+        } else {
+            pclick = 1.0 - x0 / x1;
+        }
         const double uni = philox_uniform(P.seed, chain, j);
         const bool click = uni < pclick;
         if (lane == 0) {
@@ -229,6 +253,19 @@ __device__ __forceinline__ void run_chain(const ChainParams &P, int ci, unsigned
             P.outcome[o] = click ? 1 : 0;
             if (P.trace_p) P.trace_p[o] = pclick;
             if (P.trace_u) P.trace_u[o] = uni;
+            if (P.trace_r || P.trace_b) {
+                // each half's relative error is at most 16 (k + 1) u R_i (k
+                // Schur levels, the rounding of G's entries, R_i its
+                // cancellation ratio; binary64 G for binary64 terms, G to
+                // ~2m u_dd for double-double terms), so the ratio's is their
+                // sum; then the final quotient and difference in binary64
+                const double r0 = A0 / fabs(x0), r1 = A1 / fabs(x1), ratio = fabs(x0 / x1);
+                const double u = sizeof(S) > sizeof(double) ? 0x1.0p-104 : 0x1.0p-53;
+                const double uk = sizeof(S) > sizeof(double) ? 2.0 * P.m * 0x1.0p-104 : 0.0;
+                if (P.trace_r) P.trace_r[o] = r0 > r1 ? r0 : r1;
+                if (P.trace_b)
+                    P.trace_b[o] = 16.0 * ((k + 1) * u + uk) * (r0 + r1) * ratio + 0x1.0p-52 * (ratio + fabs(pclick));
+            }
             if (click) Cl[nc] = j;
         }
         wave_sync();
@@ -240,6 +277,8 @@ __device__ __forceinline__ void run_chain(const ChainParams &P, int ci, unsigned
         P.outcome[o] = 0;
         if (P.trace_p) P.trace_p[o] = __builtin_nan("");
         if (P.trace_u) P.trace_u[o] = __builtin_nan("");
+        if (P.trace_r) P.trace_r[o] = __builtin_nan("");
+        if (P.trace_b) P.trace_b[o] = __builtin_nan("");
     }
     if (lane == 0) {
         P.status[ci] = st;

@@ -253,6 +253,8 @@ struct ChainParams {
     const unsigned long long *koff;  // offset of K_j in K
     const double *H;                 // displaced states: h_j = K_j mu[0..2j+1], concatenated (else null)
     const unsigned long long *hoff;  // offset of h_j in H
+    const double *Klo;               // double-double terms: low words of K (and of H), else null
+    const double *Hlo;
     int m;
     int n_post;                      // < 0: no postselection
     int cap;                         // most clicks a chain may carry (<= TOR_CHAIN_MAX_BIG - 1)
@@ -264,6 +266,8 @@ struct ChainParams {
     double *trace_p;                 // optional nchains x m: P(click) (NaN where not evaluated)
     double *trace_u;                 // optional nchains x m: uniform draw
     double *subsets;                 // optional nchains: subset terms evaluated
+    double *trace_r;                 // optional nchains x m: cancellation ratio max(A0/|X0|, A1/|X1|)
+    double *trace_b;                 // optional nchains x m: bound on the absolute error of P(click)
 };
 
 hipError_t tor_launch_chains(const ChainParams &P, int grid_cap, hipStream_t st);

@@ -89,6 +89,6 @@ def test_binding_constants_match_header():
     assert tg.PS_SLOTS == int(consts["TOR_PS_SLOTS"])
     assert tg.FUSED_MAX_TASKS == int(consts["TOR_FUSED_MAX_TASKS"])
     opts = dict(re.findall(r"^\s+TOR_OPT_([A-Z_]+) = (\d+)", src, flags=re.M))
-    assert len(opts) == 8
+    assert len(opts) == 9
     for name, v in opts.items():
         assert getattr(tg, "OPT_" + name) == int(v), name
