@@ -329,69 +329,78 @@ def paper_worst_case(ctx, sizes=((10, 200), (12, 288), (14, 392), (16, 512), (18
     return out
 
 
-def dense_subgraph(ctx, n=200, p=0.5, clique=20, k=12, target_clicks=16.0, etas=(1.0, 0.5, 0.25),
-                   n_samples=500, seed=40, k20_samples=100):
+def dense_subgraph(ctx, n=200, p=0.5, clique=20, k=20, target_clicks=16.0, etas=(1.0, 0.5, 0.25),
+                   n_samples=500, seed=40, raw_chains=2000):
     """Dense-subgraph search with GBS (Sec. IV), synthetic graph: G(n, p) with
     a planted clique, encoded at the scale giving target_clicks mean clicks
-    without loss, then uniform loss eta.  Samples postselected on k clicks are
-    scored by the edge density of the clicked vertices and compared with
-    uniform random k-subsets (the baseline strategy)."""
+    without loss, then uniform loss eta.  At each eta: n_samples samples
+    postselected on k clicks (the search for the densest k-subgraph keeps the
+    densest sample so far) against uniform random k-subsets, how many clicked
+    vertices lie in the clique, raw (unpostselected) chains with the click
+    cap, and the single-vertex click probabilities inside and outside the
+    clique (exact marginals)."""
+    import math
     import numpy as np
     import gbs_inputs as gi
+    import paper_1810_00900_amd as tg
     A, cl = gi.planted_clique_graph(n, p, clique, seed)
-    clset = set(cl.tolist())
+    inside = np.zeros(n, bool)
+    inside[cl] = True
     single = -np.ones((n, n), np.int8)
     np.fill_diagonal(single, 1)
 
-    def mean_clicks(cov):
+    def marginals(cov):
         st = ctx.state(cov)
         res, _ = ctx.batch(st, single, prec="f64")
         st.close()
-        return float(sum(r.p for r in res))
+        return np.array([r.p for r in res])
 
     t = time.perf_counter()
-    c = gi.calibrate_scale(A, target_clicks, mean_clicks, iters=40)
+    c = gi.calibrate_scale(A, target_clicks, lambda cv: float(marginals(cv).sum()), iters=40)
     calib_s = time.perf_counter() - t
+    _, lam = gi.takagi_real_symmetric(A)
+    lam = np.sort(lam)[::-1]
+    nbar = np.sinh(np.arctanh(c * lam)) ** 2
     rng = np.random.default_rng([seed, 1])
-    uni = np.array([gi.subgraph_density(A, rng.choice(n, k, replace=False)) for _ in range(n_samples)])
     marks = [1, 10, 100, n_samples]
+    uni = [rng.choice(n, k, replace=False) for _ in range(n_samples)]
+    uni_d = np.array([gi.subgraph_density(A, u) for u in uni])
+    uni_o = np.array([inside[u].sum() for u in uni])
     out = {"graph": f"G({n},{p}) + planted {clique}-clique, seed {seed}", "k": k, "scale_c": c,
            "calibration_seconds": calib_s, "target_mean_clicks": target_clicks,
-           "uniform": {"mean_density": float(uni.mean()),
-                       "best_after": {str(x): float(uni[:x].max()) for x in marks}}}
+           "encoding": {"lambda_1": float(lam[0]), "lambda_2": float(lam[1]), "c_lambda_1": float(c * lam[0]),
+                        "mean_photons_total": float(nbar.sum()),
+                        "mean_photons_top_mode_share": float(nbar[0] / nbar.sum())},
+           "uniform": {"mean_density": float(uni_d.mean()),
+                       "best_after": {str(x): float(uni_d[:x].max()) for x in marks},
+                       "mean_in_clique": float(uni_o.mean()), "expected_in_clique": k * clique / n,
+                       "p_all_in_clique": 1.0 / math.comb(n, k) * math.comb(clique, k)}}
     for eta in etas:
         cov = gi.graph_covariance(A, c, eta)
-        mc = mean_clicks(cov)
-        samples, st = ctx.gbs_sample(cov, k, seed + int(100 * eta), n_samples)
+        pm = marginals(cov)
+        with tg.Context(0) as cs:
+            cs.set_option(tg.OPT_CHAIN_CLICKS, 20)
+            samples, st = cs.gbs_sample(cov, k, seed + int(100 * eta), n_samples)
+            raw, st2 = cs.gbs_sample(cov, -1, seed + 7, raw_chains)
         dens = np.array([gi.subgraph_density(A, np.nonzero(sm)[0]) for sm in samples])
-        inside = float(np.mean([set(np.nonzero(sm)[0].tolist()) <= clset for sm in samples]))
-        import paper_1810_00900_amd as tg
-        with tg.Context(0) as c20:               # unpostselected, chains of up to 20 clicks
-            c20.set_option(tg.OPT_CHAIN_CLICKS, 20)
-            raw, st2 = c20.gbs_sample(cov, -1, seed + 7, 2000)
+        ov = samples[:, inside].sum(axis=1)
         hist = np.bincount(raw.sum(axis=1), minlength=21).tolist()
-        out[f"eta={eta}"] = {"mean_clicks": mc, "samples": n_samples, "seconds": st["seconds"],
+        raw_in = raw[:, inside].sum()
+        out[f"eta={eta}"] = {"mean_clicks": float(pm.sum()), "samples": n_samples, "seconds": st["seconds"],
                              "samples_per_s": n_samples / st["seconds"],
                              "acceptance": st["chains_accepted"] / st["chains_started"],
                              "mean_density": float(dens.mean()),
                              "best_after": {str(x): float(dens[:x].max()) for x in marks},
-                             "fraction_inside_clique": inside,
-                             "click_histogram_unpostselected": hist,
-                             "unpostselected_chains_capped": st2["chains_capped"],
-                             "unpostselected_chains": st2["chains_started"]}
-    # the densest-20 search as specified (20-click samples), lossless only: with
-    # loss, 20 clicks become too rare to sample in bench time
-    if k20_samples:
-        cov = gi.graph_covariance(A, c, 1.0)
-        samples, st = ctx.gbs_sample(cov, clique, seed + 20, k20_samples)
-        dens = np.array([gi.subgraph_density(A, np.nonzero(sm)[0]) for sm in samples])
-        uni20 = np.array([gi.subgraph_density(A, rng.choice(n, clique, replace=False))
-                          for _ in range(k20_samples)])
-        out["k=20,eta=1.0"] = {"samples": k20_samples, "seconds": st["seconds"],
-                               "samples_per_s": k20_samples / st["seconds"],
-                               "acceptance": st["chains_accepted"] / st["chains_started"],
-                               "mean_density": float(dens.mean()), "best": float(dens.max()),
-                               "uniform_mean_density": float(uni20.mean()), "uniform_best": float(uni20.max())}
+                             "mean_in_clique": float(ov.mean()), "max_in_clique": int(ov.max()),
+                             "fraction_of_clicks_in_clique": float(ov.mean() / k),
+                             "samples_all_in_clique": int((ov == k).sum()),
+                             "click_prob_in_clique": float(pm[inside].mean()),
+                             "click_prob_outside": float(pm[~inside].mean()),
+                             "raw_click_histogram": hist,
+                             "raw_fraction_of_clicks_in_clique": float(raw_in / max(raw.sum(), 1)),
+                             "raw_chains_capped": st2["chains_capped"], "raw_chains": st2["chains_started"]}
+        print(f"dense subgraph eta={eta}: {n_samples} samples in {st['seconds']:.1f} s", file=sys.stderr,
+              flush=True)
     return out
 
 
