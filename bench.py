@@ -212,6 +212,27 @@ def per_n_rates(ctx, cov, prec, ns=(20, 24, 28, 32), full=False, mean=None):
     return out
 
 
+def batch_rate(ctx, cov, n, nq, reps=5, seed=60):
+    """Throughput of nq marginal n-click queries (distinct random click sets
+    on the state) in one tor_batch call, double-double terms: subset-dets/s
+    and the algorithmic FP64 fraction over the whole call."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    m = cov.shape[0] // 2
+    pats = np.full((nq, m), -1, np.int8)
+    for q in range(nq):
+        pats[q, rng.choice(m, n, replace=False)] = 1
+    st = ctx.state(cov)
+    ctx.batch(st, pats, prec="dd", tol=1e-8)
+    t = time.perf_counter()
+    for _ in range(reps):
+        ctx.batch(st, pats, prec="dd", tol=1e-8)
+    dt = (time.perf_counter() - t) / reps
+    st.close()
+    return {"queries": nq, "ms_per_call": dt * 1e3, "subset_dets_per_s": nq * 2.0 ** n / dt,
+            "frac_call": nq * tree_flops(n) / dt / 1e12 / FP64_PEAK_TFLOPS}
+
+
 def full_pattern_inverse(ctx, cov, ns=(20, 28), mean=None):
     """Full patterns (the per_n_full_pattern queries) on a state inverted once
     (tor_state_invert): the time of the inversion per precision, then each
@@ -676,6 +697,7 @@ def main():
         out["roofline_per_n"] = {k: {"subset_dets_per_s": v["subset_dets_per_s"], "ms_per_call": v["ms"],
                                      "frac_call": v["frac_call"], "frac_kernels": v["frac_kernels"]}
                                  for k, v in pn.items()}
+        out["roofline_per_n"]["20_batch64"] = batch_rate(ctx, cov, 20, 64)
         kms = (st["wave_ms"] + st["expand_ms"] + st["reduce_ms"]) / args.steps
         out["roofline_per_n"][str(n)] = {"subset_dets_per_s": value, "ms_per_call": ms_per_step,
                                          "frac_call": tree_flops(n) * args.steps / wall / 1e12 / FP64_PEAK_TFLOPS,
