@@ -425,20 +425,27 @@ def dense_subgraph(ctx, n=200, p=0.5, clique=20, k=20, target_clicks=16.0, etas=
     return out
 
 
-def sampler_bench(ctx, n_samples=1000, displaced=False):
+def sampler_bench(ctx, n_samples=1000, displaced=False, dd_terms=False):
     """The postselected sampling workload: m = 100, Haar U, r = 0.6, 12 clicks
-    (displaced: the same state with mean 0.3 N(0, 1) per quadrature, seed 52)."""
+    (displaced: the same state with mean 0.3 N(0, 1) per quadrature, seed 52;
+    dd_terms: double-double chain terms, TOR_OPT_CHAIN_PREC)."""
     import numpy as np
     import gbs_inputs as gi
+    import paper_1810_00900_amd as tg
     cov = gi.state_config2()
     mean = gi.random_mean(100, np.random.default_rng(52), 0.3) if displaced else None
-    samples, st = ctx.gbs_sample(cov, 12, 2, n_samples, mean=mean)
+    ctx.set_option(tg.OPT_CHAIN_PREC, tg.PREC_DD if dd_terms else tg.PREC_F64)
+    try:
+        samples, st = ctx.gbs_sample(cov, 12, 2, n_samples, mean=mean)
+    finally:
+        ctx.set_option(tg.OPT_CHAIN_PREC, tg.PREC_F64)
     assert (samples.sum(axis=1) == 12).all()
     return {"workload": "m=100, Haar U, r=0.6, postselected on 12 clicks, seed 2"
                         + (", displaced (mean 0.3 N(0,1), seed 52)" if displaced else ""),
             "samples": n_samples, "seconds": st["seconds"], "samples_per_s": n_samples / st["seconds"],
             "chains": st["chains_started"], "acceptance": st["chains_accepted"] / st["chains_started"],
-            "subset_dets_per_s": st["subsets"] / st["seconds"], "precision": "f64 terms, dd sums"}
+            "subset_dets_per_s": st["subsets"] / st["seconds"],
+            "precision": "dd terms and K_j words" if dd_terms else "f64 terms, dd sums"}
 
 
 def serving_bench(ctx, nq=10000, workers=2):
@@ -722,6 +729,7 @@ def main():
         step("per_n_displaced_qd_terms", per_n_rates, ctx, cov, "qd", ns=(20, 24), mean=mu)
         step("per_n_full_pattern_displaced_qd", per_n_rates, ctx, cov, "qd", ns=(20,), full=True, mean=mu)
         step("sampler", sampler_bench, ctx)
+        step("sampler_dd_terms", sampler_bench, ctx, dd_terms=True)
         step("sampler_displaced", sampler_bench, ctx, n_samples=200, displaced=True)
         step("paper_worst_case", paper_worst_case, ctx)
         step("paper_worst_case_qd", paper_worst_case, ctx, sizes=((16, 512), (18, 648), (20, 800)), prec="qd")
