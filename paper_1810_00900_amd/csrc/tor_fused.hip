@@ -141,18 +141,32 @@ __device__ __forceinline__ void fz_task(FzLds<S, J> &L, const S *node, dd c, dou
 // Sum of in[0 .. count), count <= TOR_REDUCE_CHUNK, in the order of one block
 // of the batched reduction: 256 strided sequential sums (four per lane), then
 // a fixed pairwise tree.
+// All of a lane's partials are loaded before the first addition (the block
+// is read once, in one round trip, right after the claim); the additions then
+// run in the block's order.
 template <class S, int J>
 __device__ __forceinline__ Partial fz_block_sum(const Partial *in, long long count, FzLds<S, J> &L, int lane) {
-    for (int v = lane; v < 256; v += 64) {
+    constexpr int PER = TOR_REDUCE_CHUNK / 256;  // partials per strided sum
+    Partial pp[4][PER];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const long long k = lane + 64 * w + 256 * i;
+            if (k < count) pp[w][i] = in[k];
+        }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
         dd T = dd_from(0.0);
         double A = 0.0;
-        for (long long k = v; k < count; k += 256) {
-            const Partial p = in[k];
-            T = dd_add(T, dd_make(p.t_hi, p.t_lo));
-            A += p.a;
-        }
-        L.red.T[v] = T;
-        L.red.A[v] = A;
+#pragma unroll
+        for (int i = 0; i < PER; ++i)
+            if (lane + 64 * w + 256 * i < count) {
+                T = dd_add(T, dd_make(pp[w][i].t_hi, pp[w][i].t_lo));
+                A += pp[w][i].a;
+            }
+        L.red.T[lane + 64 * w] = T;
+        L.red.A[lane + 64 * w] = A;
     }
     wave_sync();
     for (int s = 128; s > 0; s >>= 1) {
