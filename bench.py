@@ -440,12 +440,23 @@ def sampler_bench(ctx, n_samples=1000, displaced=False, dd_terms=False):
     finally:
         ctx.set_option(tg.OPT_CHAIN_PREC, tg.PREC_F64)
     assert (samples.sum(axis=1) == 12).all()
+    extra = {}
+    if dd_terms:
+        # the same chains with binary64 terms: a coin that falls within the
+        # binary64 error of P(click) sends its chain elsewhere; the two
+        # ordered sample lists are aligned (difflib) to count such chains
+        import difflib
+        f64s, st64 = ctx.gbs_sample(cov, 12, 2, n_samples, mean=mean)
+        a = [bytes(r) for r in samples]
+        b = [bytes(r) for r in f64s]
+        same = sum(m.size for m in difflib.SequenceMatcher(None, a, b, autojunk=False).get_matching_blocks())
+        extra = {"samples_not_in_f64_run": n_samples - same, "chains_f64_run": st64["chains_started"]}
     return {"workload": "m=100, Haar U, r=0.6, postselected on 12 clicks, seed 2"
                         + (", displaced (mean 0.3 N(0,1), seed 52)" if displaced else ""),
             "samples": n_samples, "seconds": st["seconds"], "samples_per_s": n_samples / st["seconds"],
             "chains": st["chains_started"], "acceptance": st["chains_accepted"] / st["chains_started"],
             "subset_dets_per_s": st["subsets"] / st["seconds"],
-            "precision": "dd terms and K_j words" if dd_terms else "f64 terms, dd sums"}
+            "precision": "dd terms and K_j words" if dd_terms else "f64 terms, dd sums", **extra}
 
 
 def serving_bench(ctx, nq=10000, workers=2):
