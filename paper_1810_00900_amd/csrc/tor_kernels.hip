@@ -279,24 +279,50 @@ __device__ __forceinline__ void cond_panel(const CondBlockJob &job, long long wg
             }
     }
     __syncthreads();
-    // column x of the rest: its panel entries (rows R - 1 - k) in registers
-    const long long x = wg * blockDim.x + tid;
-    if (x >= Rb) return;
-    dd P[NB];
+    // column x of the rest, TOR_COND_TPC threads per column: thread s of a
+    // column holds its panel entries k = PE s .. PE s + PE - 1 (rows
+    // R - 1 - k) in registers.  At step t the holder of the step's pivot rows
+    // (2t, 2t + 1) forms the two scaled pivot columns at x, writes them to V
+    // and passes them to the column's other threads (lane shuffles); every
+    // thread then applies the step to its entries below the pivot rows.  Each
+    // entry takes the same operations in the same order as with one thread
+    // per column.
+    constexpr int TPC = TOR_COND_TPC, PE = NB / TPC;
+    static_assert(NB % TPC == 0 && PE % 2 == 0, "a step's two pivot rows lie in one thread's entries");
+    const int s = tid % TPC, lane = tid & 63;
+    const long long x = wg * (blockDim.x / TPC) + tid / TPC;
+    const bool live = x < Rb;
+    dd P[PE];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) P[k] = k < nb ? M[pidx(R - 1 - k, (int)x)] : dd_from(0.0);
+    for (int i = 0; i < PE; ++i) {
+        const int k = PE * s + i;
+        P[i] = live && k < nb ? M[pidx(R - 1 - k, (int)x)] : dd_from(0.0);
+    }
 #pragma unroll
     for (int t = 0; t < B; ++t) {
         if (t < b) {
             const Pivot<dd> pv = piv[t];
-            const dd m0 = P[2 * t + 1];
-            const dd v1 = dd_mul(m0, pv.s1);
-            const dd v2 = dd_mul(sub_mul(P[2 * t], pv.l, m0), pv.s2);
-            job.V[(long long)(2 * t) * job.ld + x] = v1;
-            job.V[(long long)(2 * t + 1) * job.ld + x] = v2;
+            const int holder = (2 * t) / PE, i0 = (2 * t) % PE;
+            dd v1 = dd_from(0.0), v2 = dd_from(0.0);
+            if (s == holder) {
+                const dd m0 = P[i0 + 1];
+                v1 = dd_mul(m0, pv.s1);
+                v2 = dd_mul(sub_mul(P[i0], pv.l, m0), pv.s2);
+                if (live) {
+                    job.V[(long long)(2 * t) * job.ld + x] = v1;
+                    job.V[(long long)(2 * t + 1) * job.ld + x] = v2;
+                }
+            }
+            const int src = (lane & ~(TPC - 1)) | holder;
+            v1.hi = __shfl(v1.hi, src);
+            v1.lo = __shfl(v1.lo, src);
+            v2.hi = __shfl(v2.hi, src);
+            v2.lo = __shfl(v2.lo, src);
 #pragma unroll
-            for (int k = 2 * t + 2; k < NB; ++k)
-                if (k < nb) P[k] = dd_sub_dot2(P[k], vd[t][0][k], v1, vd[t][1][k], v2);
+            for (int i = 0; i < PE; ++i) {
+                const int k = PE * s + i;
+                if (k >= 2 * t + 2 && k < nb) P[i] = dd_sub_dot2(P[i], vd[t][0][k], v1, vd[t][1][k], v2);
+            }
         }
     }
 }
