@@ -139,6 +139,11 @@ void *scratch_of(int device, std::string *err) {
 
 }  // namespace
 
+// tor_probability gathers (C, N) on the device from one copy of the covariance
+// when the pattern observes at least half of the modes and has at least this
+// many no-click modes (host packing of the (C, N) matrix costs more than the copy).
+constexpr int kDeviceGatherNoClick = 64;
+
 struct tor_ctx {
     int device = 0;
     hipStream_t own_stream = nullptr;
@@ -149,6 +154,7 @@ struct tor_ctx {
     int chain_clicks = 15;  // click cap of chains without postselection
     int cond_block = TOR_COND_BLOCK;  // no-click modes per conditioning launch pair (1: one launch per mode)
     bool fused = true;  // small zero-mean trees in one launch (tor_fused.hip)
+    DevBuf cov_tmp;     // tor_probability: device copy of the caller's covariance for device-side gathers
     DevBuf fctr;        // completion counters of the single-launch path (zero between launches)
     unsigned char *pin_stage = nullptr;  // pinned upload buffer of the single-launch path
     size_t pin_cap = 0;
@@ -1938,6 +1944,7 @@ void tor_ctx_destroy(tor_ctx *c) {
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     c->fctr.release();
+    c->cov_tmp.release();
     if (c->host_res) (void)hipHostFree(c->host_res);
     if (c->pin_stage) (void)hipHostFree(c->pin_stage);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -2014,9 +2021,32 @@ tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int
     if (!out) return fail(TOR_EINVAL, "out is NULL");
     if (prec == TOR_PREC_QD) return probability_qd(ctx, cov, m, pattern, tol, out);
     Reduced red;
-    s = reduce_pattern(cov, m, pattern, red);
+    // A pattern that observes most modes, many of them without a click: the
+    // covariance goes to the device in one copy and the (C, N) matrix is
+    // gathered there, as for the queries of a state (the same words as the
+    // host packing), instead of being packed entry by entry on the host.
+    int observed = 0, noclick = 0;
+    for (int i = 0; i < m; i++) {
+        observed += pattern[i] != -1;
+        noclick += pattern[i] == 0;
+    }
+    tor_state tmp;
+    const bool on_device = noclick >= kDeviceGatherNoClick && 2 * observed >= m;
+    s = reduce_pattern(cov, m, pattern, red, on_device);
     if (s) return s;
+    if (on_device && red.cond) {
+        const size_t cov_bytes = 4 * (size_t)m * (size_t)m * sizeof(double);
+        if (ctx->cov_tmp.ensure(cov_bytes) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the covariance failed");
+        HIP_TRY(hipMemcpyAsync(ctx->cov_tmp.p, cov, cov_bytes, hipMemcpyHostToDevice, ctx->stream));
+        tmp.ctx = ctx;
+        tmp.device = ctx->device;
+        tmp.m = m;
+        tmp.dcov.p = ctx->cov_tmp.p;  // borrowed: tmp never releases it
+        tmp.dcov.cap = ctx->cov_tmp.cap;
+        red.st = &tmp;
+    }
     s = condition_on_gpu(ctx, {&red});
+    tmp.dcov.p = nullptr;
     if (s) return s;
     std::vector<Prepared> qs(1);
     s = prepare(red.sig, red.n, red.pvac, red.log_pvac, qs[0]);

@@ -158,6 +158,32 @@ def test_mixed_patterns_batch_equals_single(ctx):
         assert _rel(_mp_p(r), o.p + o.p_lo) <= 1e-10
 
 
+def test_single_call_device_gather_equals_host_packing(ctx):
+    """tor_probability gathers the (C, N) matrix on the device from one copy
+    of the covariance when the pattern observes at least half of the modes
+    with 64 or more no-click modes, and packs it on the host otherwise; both
+    give the words of a state's device gather, so single calls on either side
+    of the threshold equal the batched queries of a state bitwise."""
+    rng = np.random.default_rng(12)
+    m = 120
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.3, 0.9, m))
+    st = ctx.state(cov)
+    for k in (40, 63, 64, 100, 112):
+        idx = rng.permutation(m)
+        p = np.full(m, -1, np.int8)
+        p[idx[:8]] = 1
+        p[idx[8:8 + k]] = 0
+        print("single-call gather, no-click modes", k, flush=True)
+        a = ctx.probability(cov, p, prec="dd")
+        r = ctx.batch(st, p[None, :], prec="dd")[0][0]
+        assert (r.p, r.p_lo, r.abs_sum, r.log_pvac_n, r.rel_err_bound) == \
+            (a.p, a.p_lo, a.abs_sum, a.log_pvac_n, a.rel_err_bound), k
+        if k in (63, 64):
+            o = oracle.formS(cov, p)
+            assert _rel(_mp_p(a), o.p + o.p_lo) <= 1e-10
+    st.close()
+
+
 def test_condition_too_many_observed_modes(ctx):
     m = 1030
     cov = 0.5 * np.eye(2 * m)
