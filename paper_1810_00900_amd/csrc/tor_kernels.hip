@@ -204,80 +204,80 @@ __device__ __forceinline__ void cond_panel(const CondBlockJob &job, long long wg
     const int b = job.b, nb = 2 * b, R = 2 * job.r + D, Rb = R - nb;
     dd *M = job.mat;
     const int tid = threadIdx.x;
-    // the block's steps on one wave (wave-level ordering, no workgroup
-    // barrier per step); the other waves wait for its pivots and columns
+    // the block's steps, every thread of the workgroup taking a share of each
+    // step's entries (two workgroup barriers per step)
+    constexpr int NT = 256;  // threads per workgroup (the launch's block size)
     __shared__ unsigned short lk[NB * (NB + 1) / 2];  // packed index -> (l, k) of the block
-    if (tid < 64) {
-        for (int e = tid; e < NB * (NB + 1) / 2; e += 64) {
-            int l, k;
-            unpack(e, l, k);
-            lk[e] = (unsigned short)(l | (k << 8));
-        }
-        // entry (k, l) of the block (rows R - 1 - k, R - 1 - l, k <= l) at pidx(l, k)
-        for (int e = tid; e < nb * (nb + 1) / 2; e += 64) {
-            int l, k;
-            unpack(e, l, k);
-            blk[e] = M[pidx(R - 1 - k, R - 1 - l)];
-        }
-        if (D)
-            for (int k = tid; k < nb; k += 64) mc[k] = M[pidx(R - 1 - k, 0)];
-        wave_sync();
-        for (int t = 0; t < b; ++t) {
-            const int k1 = 2 * t, k0 = 2 * t + 1;  // rows R_t - 1 and R_t - 2 of this step
-            // block (k, l) with k <= l is row R - 1 - k, column R - 1 - l: the
-            // entry (row p0, column p0) is blk[pidx(k0, k0)], (p1, p0) is
-            // blk[pidx(k0, k1)] (row k1 = p1 > column k0 = p0 means k1 < k0)
-            const Pivot<dd> pv = make_pivot_v<dd, D>(blk[pidx(k0, k0)], blk[pidx(k0, k1)], blk[pidx(k1, k1)],
-                                                     D ? mc[k0] : blk[0], D ? mc[k1] : blk[0]);
-            for (int k = k0 + 1 + tid; k < nb; k += 64) {  // column c = R - 1 - k < p0
-                const dd m0 = blk[pidx(k, k0)];
-                vd[t][0][k] = dd_mul(m0, pv.s1);
-                vd[t][1][k] = dd_mul(sub_mul(blk[pidx(k, k1)], pv.l, m0), pv.s2);
-            }
-            if (tid == 0) piv[t] = pv;
-            wave_sync();
-            // the block's remaining entries and mean column, as the per-mode
-            // update: all loads of a lane's (at most 8) entries first
-            const int rem = nb - (k0 + 1), nrem = rem * (rem + 1) / 2;
-            constexpr int PER = (NB * (NB + 1) / 2 + 63) / 64;
-            dd x[PER], a1[PER], b1[PER], a2[PER], b2[PER];
-            int dst[PER];
-            // (past the last entry a lane reads entry 0, (k0 + 1, k0 + 1), and
-            // stores nothing; there is none in the last step)
-#pragma unroll
-            for (int u = 0; u < PER && nrem > 0; ++u) {
-                const int e = tid + 64 * u;
-                const bool ok = e < nrem;
-                const unsigned short w = lk[ok ? e : 0];
-                const int l = (w & 0xff) + k0 + 1, k = (w >> 8) + k0 + 1;  // k <= l
-                dst[u] = ok ? pidx(l, k) : -1;
-                x[u] = blk[pidx(l, k)];
-                a1[u] = vd[t][0][k];
-                b1[u] = vd[t][0][l];
-                a2[u] = vd[t][1][k];
-                b2[u] = vd[t][1][l];
-            }
-#pragma unroll
-            for (int u = 0; u < PER && nrem > 0; ++u) {
-                const dd y = dd_sub_dot2(x[u], a1[u], b1[u], a2[u], b2[u]);
-                if (dst[u] >= 0) blk[dst[u]] = y;
-            }
-            if (D) {
-                const dd w1 = dd_mul(mc[k0], pv.s1), w2 = dd_mul(sub_mul(mc[k1], pv.l, mc[k0]), pv.s2);
-                for (int k = k0 + 1 + tid; k < nb; k += 64)
-                    mc[k] = dd_sub_dot2(mc[k], vd[t][0][k], w1, vd[t][1][k], w2);
-            }
-            wave_sync();
-        }
-        if (wg == 0 && tid == 0)  // the per-mode kernel's accumulation, in step order
-            for (int t = 0; t < b; ++t) {
-                const dd q = piv[t].q;
-                const dd p = dd_mul(dd_make(job.acc[0], job.acc[1]), q);
-                job.acc[0] = p.hi;
-                job.acc[1] = p.lo;
-                job.acc[2] += log(q.hi) + log1p(q.lo / q.hi);
-            }
+    for (int e = tid; e < NB * (NB + 1) / 2; e += NT) {
+        int l, k;
+        unpack(e, l, k);
+        lk[e] = (unsigned short)(l | (k << 8));
     }
+    // entry (k, l) of the block (rows R - 1 - k, R - 1 - l, k <= l) at pidx(l, k)
+    for (int e = tid; e < nb * (nb + 1) / 2; e += NT) {
+        int l, k;
+        unpack(e, l, k);
+        blk[e] = M[pidx(R - 1 - k, R - 1 - l)];
+    }
+    if (D)
+        for (int k = tid; k < nb; k += NT) mc[k] = M[pidx(R - 1 - k, 0)];
+    __syncthreads();
+    for (int t = 0; t < b; ++t) {
+        const int k1 = 2 * t, k0 = 2 * t + 1;  // rows R_t - 1 and R_t - 2 of this step
+        // block (k, l) with k <= l is row R - 1 - k, column R - 1 - l: the
+        // entry (row p0, column p0) is blk[pidx(k0, k0)], (p1, p0) is
+        // blk[pidx(k0, k1)] (row k1 = p1 > column k0 = p0 means k1 < k0)
+        const Pivot<dd> pv = make_pivot_v<dd, D>(blk[pidx(k0, k0)], blk[pidx(k0, k1)], blk[pidx(k1, k1)],
+                                                 D ? mc[k0] : blk[0], D ? mc[k1] : blk[0]);
+        for (int k = k0 + 1 + tid; k < nb; k += NT) {  // column c = R - 1 - k < p0
+            const dd m0 = blk[pidx(k, k0)];
+            vd[t][0][k] = dd_mul(m0, pv.s1);
+            vd[t][1][k] = dd_mul(sub_mul(blk[pidx(k, k1)], pv.l, m0), pv.s2);
+        }
+        if (tid == 0) piv[t] = pv;
+        __syncthreads();
+        // the block's remaining entries and mean column, as the per-mode
+        // update: all loads of a thread's (at most 3) entries first
+        const int rem = nb - (k0 + 1), nrem = rem * (rem + 1) / 2;
+        constexpr int PER = (NB * (NB + 1) / 2 + NT - 1) / NT;
+        dd xe[PER], a1[PER], b1[PER], a2[PER], b2[PER];
+        int dst[PER];
+        // (past the last entry a thread reads entry 0, (k0 + 1, k0 + 1), and
+        // stores nothing; there is none in the last step)
+#pragma unroll
+        for (int u = 0; u < PER && nrem > 0; ++u) {
+            const int e = tid + NT * u;
+            const bool ok = e < nrem;
+            const unsigned short w = lk[ok ? e : 0];
+            const int l = (w & 0xff) + k0 + 1, k = (w >> 8) + k0 + 1;  // k <= l
+            dst[u] = ok ? pidx(l, k) : -1;
+            xe[u] = blk[pidx(l, k)];
+            a1[u] = vd[t][0][k];
+            b1[u] = vd[t][0][l];
+            a2[u] = vd[t][1][k];
+            b2[u] = vd[t][1][l];
+        }
+        // (each entry is read and written by its own thread only)
+#pragma unroll
+        for (int u = 0; u < PER && nrem > 0; ++u) {
+            const dd y = dd_sub_dot2(xe[u], a1[u], b1[u], a2[u], b2[u]);
+            if (dst[u] >= 0) blk[dst[u]] = y;
+        }
+        if (D) {
+            const dd w1 = dd_mul(mc[k0], pv.s1), w2 = dd_mul(sub_mul(mc[k1], pv.l, mc[k0]), pv.s2);
+            for (int k = k0 + 1 + tid; k < nb; k += NT)
+                mc[k] = dd_sub_dot2(mc[k], vd[t][0][k], w1, vd[t][1][k], w2);
+        }
+        __syncthreads();
+    }
+    if (wg == 0 && tid == 0)  // the per-mode kernel's accumulation, in step order
+        for (int t = 0; t < b; ++t) {
+            const dd q = piv[t].q;
+            const dd p = dd_mul(dd_make(job.acc[0], job.acc[1]), q);
+            job.acc[0] = p.hi;
+            job.acc[1] = p.lo;
+            job.acc[2] += log(q.hi) + log1p(q.lo / q.hi);
+        }
     __syncthreads();
     // column x of the rest, TOR_COND_TPC threads per column: thread s of a
     // column holds its panel entries k = PE s .. PE s + PE - 1 (rows
