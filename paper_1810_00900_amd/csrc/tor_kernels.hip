@@ -361,17 +361,31 @@ __global__ __launch_bounds__(256) void cond_bulk_kernel(const CondBlockJob *__re
     }
     __syncthreads();
     dd *M = job.mat;
+    // a thread's four entries share their column: the column's two values
+    // of a step are read once for all four, whose update chains interleave
+    // (each entry still takes the b updates in step order)
     const int cl = threadIdx.x & 31, c = c0 + cl;
+    dd xq[4];
+    long long eq[4];
+    bool okq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int al = (threadIdx.x >> 5) + 8 * q, a = a0 + al;
-        if (a < Rb && c <= a) {
-            const long long e = (long long)a * (a + 1) / 2 + c;
-            dd x = M[e];
-            for (int t = 0; t < b; ++t) x = dd_sub_dot2(x, Vr[t][0][al], Vc[t][0][cl], Vr[t][1][al], Vc[t][1][cl]);
-            M[e] = x;
+        const int a = a0 + (threadIdx.x >> 5) + 8 * q;
+        okq[q] = a < Rb && c <= a;
+        eq[q] = (long long)a * (a + 1) / 2 + c;
+        xq[q] = okq[q] ? M[eq[q]] : dd_from(0.0);
+    }
+    for (int t = 0; t < b; ++t) {
+        const dd c1 = Vc[t][0][cl], c2 = Vc[t][1][cl];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int al = (threadIdx.x >> 5) + 8 * q;
+            xq[q] = dd_sub_dot2(xq[q], Vr[t][0][al], c1, Vr[t][1][al], c2);
         }
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (okq[q]) M[eq[q]] = xq[q];
 }
 
 // ---------------------------------------------------------------- reduction
