@@ -155,6 +155,8 @@ struct tor_ctx {
     int cond_block = TOR_COND_BLOCK;  // no-click modes per conditioning launch pair (1: one launch per mode)
     bool fused = true;  // small zero-mean trees in one launch (tor_fused.hip)
     DevBuf cov_tmp;     // tor_probability: device copy of the caller's covariance for device-side gathers
+    DevBuf screen;      // its screen's words and the observed rows
+    unsigned long long *screen_host = nullptr;  // pinned copy of the screen's words
     DevBuf fctr;        // completion counters of the single-launch path (zero between launches)
     unsigned char *pin_stage = nullptr;  // pinned upload buffer of the single-launch path
     size_t pin_cap = 0;
@@ -1945,6 +1947,8 @@ void tor_ctx_destroy(tor_ctx *c) {
         if (e) (void)hipEventDestroy(e);
     c->fctr.release();
     c->cov_tmp.release();
+    c->screen.release();
+    if (c->screen_host) (void)hipHostFree(c->screen_host);
     if (c->host_res) (void)hipHostFree(c->host_res);
     if (c->pin_stage) (void)hipHostFree(c->pin_stage);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -2015,29 +2019,61 @@ tor_status tor_ctx_reset_stats(tor_ctx *c) {
 tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int8_t *pattern, tor_prec prec,
                            double tol, tor_result *out) {
     if (!ctx) return fail(TOR_EINVAL, "ctx is NULL");
-    tor_status s = validate_cov_block(cov, m, pattern);
-    if (s) return s;
+    // A pattern that observes most modes, many of them without a click: the
+    // covariance goes to the device in one copy and the (C, N) matrix is
+    // gathered there, as for the queries of a state (the same words as the
+    // host packing), instead of being packed entry by entry on the host; the
+    // finiteness and symmetry checks of the observed block then run on the
+    // device too (the host's scan, with its message, only when they fail).
+    bool on_device = false;
+    if (cov && pattern && m > 0 && m <= 100000 && prec != TOR_PREC_QD) {
+        int observed = 0, noclick = 0;
+        bool valid = true;
+        for (int i = 0; i < m && valid; i++) {
+            valid = pattern[i] >= -1 && pattern[i] <= 1;
+            observed += pattern[i] != -1;
+            noclick += pattern[i] == 0;
+        }
+        on_device = valid && noclick >= kDeviceGatherNoClick && 2 * observed >= m;
+    }
+    tor_status s;
+    if (!on_device) {
+        s = validate_cov_block(cov, m, pattern);
+        if (s) return s;
+    }
     HIP_TRY(hipSetDevice(ctx->device));
     if (!out) return fail(TOR_EINVAL, "out is NULL");
     if (prec == TOR_PREC_QD) return probability_qd(ctx, cov, m, pattern, tol, out);
     Reduced red;
-    // A pattern that observes most modes, many of them without a click: the
-    // covariance goes to the device in one copy and the (C, N) matrix is
-    // gathered there, as for the queries of a state (the same words as the
-    // host packing), instead of being packed entry by entry on the host.
-    int observed = 0, noclick = 0;
-    for (int i = 0; i < m; i++) {
-        observed += pattern[i] != -1;
-        noclick += pattern[i] == 0;
-    }
     tor_state tmp;
-    const bool on_device = noclick >= kDeviceGatherNoClick && 2 * observed >= m;
     s = reduce_pattern(cov, m, pattern, red, on_device);
-    if (s) return s;
-    if (on_device && red.cond) {
+    if (s) {
+        if (on_device) {  // a bad covariance is reported first, as on the host path
+            tor_status v = validate_cov_block(cov, m, pattern);
+            if (v) return v;
+        }
+        return s;
+    }
+    const bool screened = on_device && red.cond;
+    if (screened) {
         const size_t cov_bytes = 4 * (size_t)m * (size_t)m * sizeof(double);
-        if (ctx->cov_tmp.ensure(cov_bytes) != hipSuccess) return fail(TOR_ENOMEM, "device copy of the covariance failed");
-        HIP_TRY(hipMemcpyAsync(ctx->cov_tmp.p, cov, cov_bytes, hipMemcpyHostToDevice, ctx->stream));
+        const size_t g_bytes = red.g.size() * sizeof(int);
+        if (ctx->cov_tmp.ensure(cov_bytes) != hipSuccess || ctx->screen.ensure(g_bytes + 64) != hipSuccess)
+            return fail(TOR_ENOMEM, "device copy of the covariance failed");
+        if (!ctx->screen_host &&
+            hipHostMalloc((void **)&ctx->screen_host, 4 * sizeof(unsigned long long), hipHostMallocDefault) !=
+                hipSuccess) {
+            ctx->screen_host = nullptr;
+            return fail(TOR_ENOMEM, "pinned allocation failed");
+        }
+        hipStream_t st = ctx->stream;
+        unsigned long long *words = (unsigned long long *)ctx->screen.p;
+        int *dg = (int *)((unsigned char *)ctx->screen.p + 64);
+        HIP_TRY(hipMemcpyAsync(ctx->cov_tmp.p, cov, cov_bytes, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(dg, red.g.data(), g_bytes, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemsetAsync(words, 0, 4 * sizeof(unsigned long long), st));
+        HIP_TRY(tor_launch_cov_screen((const double *)ctx->cov_tmp.p, m, dg, (int)red.g.size(), words, st));
+        HIP_TRY(hipMemcpyAsync(ctx->screen_host, words, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         tmp.ctx = ctx;
         tmp.device = ctx->device;
         tmp.m = m;
@@ -2047,6 +2083,16 @@ tor_status tor_probability(tor_ctx *ctx, const double *cov, int32_t m, const int
     }
     s = condition_on_gpu(ctx, {&red});
     tmp.dcov.p = nullptr;
+    if (screened) {
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        double amax, asym;
+        std::memcpy(&amax, &ctx->screen_host[0], sizeof amax);
+        std::memcpy(&asym, &ctx->screen_host[2], sizeof asym);
+        if (ctx->screen_host[1] || asym > 1e-12 * amax) {
+            tor_status v = validate_cov_block(cov, m, pattern);  // the host's scan names the entry
+            if (v) return v;
+        }
+    }
     if (s) return s;
     std::vector<Prepared> qs(1);
     s = prepare(red.sig, red.n, red.pvac, red.log_pvac, qs[0]);

@@ -21,3 +21,11 @@ struct GatherJob {
 
 // jobs sorted by begin; total = sum of the jobs' entry counts.
 hipError_t tor_launch_cond_gather(const GatherJob *jobs, int njobs, long long total, hipStream_t st);
+
+// Screen of a caller's covariance over the rows and columns g[0..R) (global
+// quadrature indices): out[0] receives the bits of max |cov[a][b]|, out[1] is
+// set to 1 if an entry is not finite, out[2] receives the bits of
+// max |cov[a][b] - cov[b][a]| (a, b over g); out must hold zeros before.  The
+// caller compares out[2] with 1e-12 out[0], the host's symmetry test.
+hipError_t tor_launch_cov_screen(const double *cov, int m, const int *g, int R, unsigned long long *out,
+                                 hipStream_t st);

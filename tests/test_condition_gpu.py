@@ -184,6 +184,37 @@ def test_single_call_device_gather_equals_host_packing(ctx):
     st.close()
 
 
+def test_single_call_device_screen_errors(ctx):
+    """On the device-gather path of a single call the finiteness and symmetry
+    checks of the observed block run on the device: a non-finite or
+    asymmetric entry inside the block is reported as by the host scan
+    (TOR_EINVAL, naming the entry), one outside it is not read at all."""
+    rng = np.random.default_rng(13)
+    m = 120
+    cov = gi.gbs_covariance(gi.haar_unitary(m, rng), rng.uniform(0.3, 0.9, m))
+    idx = rng.permutation(m)
+    p = np.full(m, -1, np.int8)
+    p[idx[:8]] = 1
+    p[idx[8:108]] = 0
+    good = ctx.probability(cov, p, prec="dd")
+    a, b = 2 * int(idx[3]), 2 * int(idx[50]) + 1   # observed quadratures
+    u = 2 * int(idx[115])                          # an unobserved one
+    for what, val in (("not symmetric", None), ("non-finite", np.nan), ("non-finite", np.inf)):
+        bad = cov.copy()
+        if val is None:
+            bad[a, b] += 1e-6
+        else:
+            bad[a, b] = bad[b, a] = val
+        with pytest.raises(tg.TorError) as e:
+            ctx.probability(bad, p, prec="dd")
+        assert e.value.status == tg.TOR_EINVAL and what in str(e.value), str(e.value)
+    outside = cov.copy()
+    outside[u, a] += 1.0      # the row of an unobserved mode: asymmetric there,
+    outside[u, u] = np.nan    # and not finite
+    r = ctx.probability(outside, p, prec="dd")
+    assert (r.p, r.p_lo, r.abs_sum) == (good.p, good.p_lo, good.abs_sum)
+
+
 def test_condition_too_many_observed_modes(ctx):
     m = 1030
     cov = 0.5 * np.eye(2 * m)
