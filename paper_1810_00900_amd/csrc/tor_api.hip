@@ -144,6 +144,10 @@ void *scratch_of(int device, std::string *err) {
 // many no-click modes (host packing of the (C, N) matrix costs more than the copy).
 constexpr int kDeviceGatherNoClick = 64;
 
+// Panel workgroups per blocked-conditioning launch before a workgroup takes
+// several column groups (eight per CU).
+constexpr long long kPanelWorkgroups = 2048;
+
 struct tor_ctx {
     int device = 0;
     hipStream_t own_stream = nullptr;
@@ -1044,6 +1048,15 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
         } else {
             for (int t0 = 0; t0 < kmax; t0 += CB) {
                 Step st{bjobs.size(), 0, 0, 0, 1};
+                // every panel workgroup takes the block's steps before its
+                // columns: a launch of many queries gives each workgroup
+                // several column groups, so that about kPanelWorkgroups run
+                long long one = 0;
+                for (size_t i = 0; i < nq; i++) {
+                    const Reduced *r = rs[first + i];
+                    if (r->k > t0) one += cond_panel_blocks(r->n + r->k - t0, std::min(CB, r->k - t0), r->D, 1);
+                }
+                const int passes = (int)std::max(1LL, (one + kPanelWorkgroups - 1) / kPanelWorkgroups);
                 for (size_t i = 0; i < nq; i++) {
                     const Reduced *r = rs[first + i];
                     if (r->k <= t0) continue;
@@ -1052,10 +1065,11 @@ tor_status condition_on_gpu(tor_ctx *ctx, const std::vector<Reduced *> &all) {
                     j.b = std::min(CB, r->k - t0);
                     j.d = r->D;
                     j.ld = 2 * (r->n + r->k) + r->D;
+                    j.passes = passes;
                     j.begin_panel = st.blocks;
                     j.begin_bulk = st.blocks2;
                     bjobs.push_back(j);
-                    st.blocks += cond_panel_blocks(j.r, j.b, j.d);
+                    st.blocks += cond_panel_blocks(j.r, j.b, j.d, passes);
                     st.blocks2 += cond_bulk_blocks(j.r, j.b, j.d);
                     st.count++;
                 }

@@ -108,13 +108,14 @@ struct CondBlockJob {
     long long begin_panel;   // first workgroup of the panel launch for this job
     long long begin_bulk;    // first workgroup of the bulk launch for this job
     int r, b, d, ld;
+    int passes;              // panel: column groups per workgroup (its block steps serve all of them)
 };
 hipError_t tor_launch_cond_panel(const CondBlockJob *jobs, int njobs, long long total_blocks, hipStream_t st);
 hipError_t tor_launch_cond_bulk(const CondBlockJob *jobs, int njobs, long long total_blocks, hipStream_t st);
-// workgroups of a job's panel (256 / TOR_COND_TPC columns each) and bulk (32 x 32 tiles) launches
+// workgroups of a job's panel (passes x 256 / TOR_COND_TPC columns each) and bulk (32 x 32 tiles) launches
 #define TOR_COND_TPC 16 // panel kernel: threads per column (256 / TOR_COND_TPC columns per workgroup)
-__host__ __device__ inline long long cond_panel_blocks(int r, int b, int d) {
-    const long long rb = 2LL * (r - b) + d, per = 256 / TOR_COND_TPC;
+__host__ __device__ inline long long cond_panel_blocks(int r, int b, int d, int passes) {
+    const long long rb = 2LL * (r - b) + d, per = (long long)(256 / TOR_COND_TPC) * passes;
     return rb > 0 ? (rb + per - 1) / per : 1;
 }
 __host__ __device__ inline long long cond_bulk_blocks(int r, int b, int d) {

@@ -290,38 +290,40 @@ __device__ __forceinline__ void cond_panel(const CondBlockJob &job, long long wg
     constexpr int TPC = TOR_COND_TPC, PE = NB / TPC;
     static_assert(NB % TPC == 0 && PE % 2 == 0, "a step's two pivot rows lie in one thread's entries");
     const int s = tid % TPC, lane = tid & 63;
-    const long long x = wg * (blockDim.x / TPC) + tid / TPC;
-    const bool live = x < Rb;
-    dd P[PE];
+    for (int pass = 0; pass < job.passes; ++pass) {  // column groups of this workgroup
+        const long long x = (wg * job.passes + pass) * (blockDim.x / TPC) + tid / TPC;
+        const bool live = x < Rb;
+        dd P[PE];
 #pragma unroll
-    for (int i = 0; i < PE; ++i) {
-        const int k = PE * s + i;
-        P[i] = live && k < nb ? M[pidx(R - 1 - k, (int)x)] : dd_from(0.0);
-    }
+        for (int i = 0; i < PE; ++i) {
+            const int k = PE * s + i;
+            P[i] = live && k < nb ? M[pidx(R - 1 - k, (int)x)] : dd_from(0.0);
+        }
 #pragma unroll
-    for (int t = 0; t < B; ++t) {
-        if (t < b) {
-            const Pivot<dd> pv = piv[t];
-            const int holder = (2 * t) / PE, i0 = (2 * t) % PE;
-            dd v1 = dd_from(0.0), v2 = dd_from(0.0);
-            if (s == holder) {
-                const dd m0 = P[i0 + 1];
-                v1 = dd_mul(m0, pv.s1);
-                v2 = dd_mul(sub_mul(P[i0], pv.l, m0), pv.s2);
-                if (live) {
-                    job.V[(long long)(2 * t) * job.ld + x] = v1;
-                    job.V[(long long)(2 * t + 1) * job.ld + x] = v2;
+        for (int t = 0; t < B; ++t) {
+            if (t < b) {
+                const Pivot<dd> pv = piv[t];
+                const int holder = (2 * t) / PE, i0 = (2 * t) % PE;
+                dd v1 = dd_from(0.0), v2 = dd_from(0.0);
+                if (s == holder) {
+                    const dd m0 = P[i0 + 1];
+                    v1 = dd_mul(m0, pv.s1);
+                    v2 = dd_mul(sub_mul(P[i0], pv.l, m0), pv.s2);
+                    if (live) {
+                        job.V[(long long)(2 * t) * job.ld + x] = v1;
+                        job.V[(long long)(2 * t + 1) * job.ld + x] = v2;
+                    }
                 }
-            }
-            const int src = (lane & ~(TPC - 1)) | holder;
-            v1.hi = __shfl(v1.hi, src);
-            v1.lo = __shfl(v1.lo, src);
-            v2.hi = __shfl(v2.hi, src);
-            v2.lo = __shfl(v2.lo, src);
+                const int src = (lane & ~(TPC - 1)) | holder;
+                v1.hi = __shfl(v1.hi, src);
+                v1.lo = __shfl(v1.lo, src);
+                v2.hi = __shfl(v2.hi, src);
+                v2.lo = __shfl(v2.lo, src);
 #pragma unroll
-            for (int i = 0; i < PE; ++i) {
-                const int k = PE * s + i;
-                if (k >= 2 * t + 2 && k < nb) P[i] = dd_sub_dot2(P[i], vd[t][0][k], v1, vd[t][1][k], v2);
+                for (int i = 0; i < PE; ++i) {
+                    const int k = PE * s + i;
+                    if (k >= 2 * t + 2 && k < nb) P[i] = dd_sub_dot2(P[i], vd[t][0][k], v1, vd[t][1][k], v2);
+                }
             }
         }
     }
