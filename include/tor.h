@@ -155,8 +155,8 @@ typedef enum {
     TOR_OPT_CHAIN_PREC = 8   /* term precision of the chains of gbs_sample, gbs_trace and their
                               displaced and step-traced forms: TOR_PREC_F64 (default; binary64
                               K_j and subset terms, double-double sums) or TOR_PREC_DD
-                              (K_j as double-double words, double-double terms; about 3x the
-                              time).  The persistent loop's chains stay binary64 */
+                              (K_j as double-double words, double-double terms; about 2.2x
+                              the time).  The persistent loop's chains stay binary64 */
 } tor_option;
 
 /* Create a context on HIP device `device` (its own stream, default priority).

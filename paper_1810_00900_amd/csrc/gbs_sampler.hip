@@ -44,13 +44,20 @@ template <class S, int KMAX, int D>
 __global__ __launch_bounds__(64) void chain_kernel(ChainParams P) {
     constexpr int O = MR(D);  // mean rows
     __shared__ __align__(16) unsigned char raw[ChainLds<S, D>::wave_bytes];
-    __shared__ S gbuf[3][EN(KMAX, O)];
+    // G in its own buffer; its two Schur complements in the nine-mode tree's
+    // slot area (past the nine-mode matrix) when they fit, else beside G
+    constexpr int EK = EN(KMAX, O), E9 = EN(9, O), MAT = WaveCfg<S, 9, D>::MAT;
+    constexpr bool IN_SLOTS = E9 + 2 * EK <= MAT;
+    __shared__ S gbuf[IN_SLOTS ? 1 : 3][EK];
+    S *g12;
+    if constexpr (IN_SLOTS) g12 = reinterpret_cast<WaveSmem<S, 9, D> *>(raw)->mat + E9;
+    else g12 = gbuf[IN_SLOTS ? 0 : 1];  // gbuf[1], gbuf[2]
     __shared__ S vt[4 * KMAX];
     __shared__ int Cl[KMAX + 1];
     const int lane = threadIdx.x;
     wave_tree_init<D>(reinterpret_cast<WaveSmem<S, 9, D> *>(raw)->ab, lane);
     for (int ci = blockIdx.x; ci < P.nchains; ci += gridDim.x) {
-        run_chain<S, KMAX, D>(P, ci, raw, gbuf, vt, Cl, lane);
+        run_chain<S, KMAX, D>(P, ci, raw, gbuf[0], g12, vt, Cl, lane);
         wave_sync();
     }
 }

@@ -139,10 +139,14 @@ template <class S, int D> struct ChainLds {
 
 // Run chain P.chain_begin + ci to its end and write its outcomes (and the
 // optional trace) at row ci of P's outputs.  raw: LDS of
-// ChainLds<S, D>::wave_bytes; gbuf, vt, Cl: LDS for the top decisions of
-// trees with more than nine modes (KMAX modes at most).  All 64 lanes call it.
+// ChainLds<S, D>::wave_bytes; g0 (the step's matrix G) and g12 (two buffers
+// one after the other for its Schur complements, ping-pong), vt, Cl: LDS for
+// the top decisions of trees with more than nine modes (EN(KMAX) scalars per
+// buffer, KMAX modes at most; g12 may lie in raw's slot area past the
+// nine-mode matrix, which the nine-mode tree overwrites only after they are
+// read).  All 64 lanes call it.
 template <class S, int KMAX, int D>
-__device__ __forceinline__ void run_chain(const ChainParams &P, int ci, unsigned char *raw, S (*gbuf)[EN(KMAX, MR(D))],
+__device__ __forceinline__ void run_chain(const ChainParams &P, int ci, unsigned char *raw, S *g0, S *g12,
                                           S *vt, int *Cl, int lane) {
     constexpr int O = MR(D);  // mean rows
     // ab[] then mat[] sit at the same offsets in WaveSmem<S, J, D> for every J
@@ -165,7 +169,7 @@ __device__ __forceinline__ void run_chain(const ChainParams &P, int ci, unsigned
         const int ld = 2 * j + 2;
         const double *Kj = P.K + P.koff[j];
         const double *Klj = P.Klo ? P.Klo + P.koff[j] : nullptr;
-        S *G = k <= 9 ? wmat : gbuf[0];
+        S *G = k <= 9 ? wmat : g0;
         for (int e = lane; e < EN(k, O); e += 64) {
             int a, b;
             unpack(e, a, b);
@@ -203,13 +207,13 @@ __device__ __forceinline__ void run_chain(const ChainParams &P, int ci, unsigned
             const int u = k - 9;
             WaveSmem<S, 9, D> &sm = *reinterpret_cast<WaveSmem<S, 9, D> *>(raw);
             for (int p = 0; p < (1 << u); ++p) {
-                const S *cur = gbuf[0];
+                const S *cur = g0;
                 int r = k, nb = 1;
                 dd c = dd_from(1.0);
                 double a = 1.0;
                 for (int b = 0; b < u; ++b, --r) {
                     if ((p >> b) & 1) {
-                        S *o = gbuf[nb];
+                        S *o = g12 + (nb == 1 ? 0 : EN(KMAX, MR(D)));
                         S q = wave_schur_last<S, D>(cur, r, o, vt, lane);
                         c = dd_neg(coef_mul(c, q));
                         a *= hi_of(q);

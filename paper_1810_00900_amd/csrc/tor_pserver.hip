@@ -249,7 +249,7 @@ __device__ __attribute__((noinline)) void ps_prob_unit(const PsReq &R, long long
 // A sampling unit: one chain.  The two kinds of unit are kept out of line so
 // that their register allocations stay apart (each as in its own kernel).
 __device__ __attribute__((noinline)) void ps_chain_unit(const ChainParams &P, int ci, PsChainLds &L, int lane) {
-    run_chain<double, TOR_CHAIN_MAX, 0>(P, ci, L.raw, L.gbuf, L.vt, L.Cl, lane);
+    run_chain<double, TOR_CHAIN_MAX, 0>(P, ci, L.raw, L.gbuf[0], L.gbuf[1], L.vt, L.Cl, lane);  // gbuf[1], gbuf[2]
 }
 
 // Sum of the request's task partials in the batched path's order: stages of
