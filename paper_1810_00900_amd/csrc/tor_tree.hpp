@@ -257,6 +257,15 @@ template <class S, int J, int D = 0> struct WaveCfg {
 // smaller matrix is a prefix.
 __host__ __device__ constexpr int ab_n(int D) { return EN(8, D); }
 
+// Rank-2 updates a lane keeps in flight per chunk of a cooperative level:
+// double-double updates, whose dependency chains are the longest, take up to
+// 12 (a nine-mode tree's largest level in one chunk, within the register file
+// of one wave per SIMD); binary64 trees, at two waves per SIMD, take 8 (more
+// spills); quad-double terms 4.
+template <class S> struct ChunkW { static constexpr int value = 4; };
+template <> struct ChunkW<dd> { static constexpr int value = 12; };
+template <> struct ChunkW<double> { static constexpr int value = 8; };
+
 template <class S, int J, int K, int D = 0> struct WaveLevel {
     using C = WaveCfg<S, J, D>;
     using Acc = typename AccOf<S>::type;
@@ -296,7 +305,7 @@ template <class S, int J, int K, int D = 0> struct WaveLevel {
                 // phase 0), so the whole phase is one branch-free block.
                 {
                     constexpr int TOT = NK * EC, JJ = (TOT + 63) / 64;
-                    constexpr int NCH = (JJ + 3) / 4, CH = (JJ + NCH - 1) / NCH;
+                    constexpr int NCH = (JJ + ChunkW<S>::value - 1) / ChunkW<S>::value, CH = (JJ + NCH - 1) / NCH;
     #pragma unroll
                     for (int j0 = 0; j0 < JJ; j0 += CH) {
                         S x[CH], p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
@@ -350,7 +359,7 @@ template <class S, int J, int K, int D = 0> struct WaveLevel {
                     // again before the next level's phase 0; node 0 is in the first
                     // part), so the whole phase is one branch-free block.
                     constexpr int TOT = NKH * EC, JJ = (TOT + 63) / 64;
-                    constexpr int NCH = (JJ + 3) / 4, CH = (JJ + NCH - 1) / NCH;
+                    constexpr int NCH = (JJ + ChunkW<S>::value - 1) / ChunkW<S>::value, CH = (JJ + NCH - 1) / NCH;
     #pragma unroll
                     for (int j0 = 0; j0 < JJ; j0 += CH) {
                         S x[CH], p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
