@@ -273,71 +273,91 @@ template <class S, int J, int K, int D = 0> struct WaveLevel {
                                                Acc *coef, double *acoef, int lane) {
         if constexpr (K < C::TWC) {
             constexpr int r = J - K, R = 2 * r + MR(D), NK = 1 << K, RC = R - 2, EC = EN(r - 1, MR(D));
-            // phase 0: pivot of each node, coefficients and slots of the include children
-            if (lane < NK) {
-                const S *base = mat + loc[lane];
-                Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
-                piv[lane] = pv;
-                coef[NK + lane] = acc_neg(coef_mul(coef[lane], pv.q));
-                acoef[NK + lane] = acoef[lane] * hi_of(pv.q);
-                loc[NK + lane] = C::soff(K) + lane * EC;
-            }
-            wave_sync();
-            // phases 1 and 2: for all nodes at once, or (halves(K) = 2) for each
-            // half of the nodes in turn
             constexpr int NH = C::halves(K), NKH = NK / NH;
             if constexpr (NH == 1) {
-                // phase 1: the two scaled pivot columns of every node
-                for (int it = lane; it < NK * RC; it += 64) {
-                    int i = it / RC, c = it - i * RC;
-                    const S *base = mat + loc[i];
-                    Pivot<S> pv = piv[i];
-                    S m0 = base[pidx(R - 2, c)];
-                    vbuf[i * 2 * RC + c] = mul_s(m0, pv.s1);
-                    vbuf[i * 2 * RC + RC + c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
+                // phases 0 and 1: the 64 / NK lanes of each node form its pivot
+                // themselves (the same value in each) and then its two scaled
+                // columns, a few columns per lane; the node's first lane stores the
+                // include child's coefficients and slot.  Phase 2 updates, in each
+                // lane, entries of the lane's own node, so their packed indices and
+                // values are loaded here, while the pivot is formed.
+                static_assert(64 % NK == 0, "at most 64 nodes per level");
+                constexpr int LPN = 64 / NK, NCOL = (RC + LPN - 1) / LPN, NE = (EC + LPN - 1) / LPN;
+                const int i = lane / LPN, c0 = lane - i * LPN;
+                unsigned short w[NE];
+#pragma unroll
+                for (int u = 0; u < NE; ++u) w[u] = ab[c0 + LPN * u < EC ? c0 + LPN * u : EC - 1];
+                const S *base = mat + loc[i];
+                const Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
+                S m0[NCOL], m1[NCOL], x[NE];
+#pragma unroll
+                for (int j = 0; j < NCOL; ++j) {
+                    const int c = c0 + LPN * j < RC ? c0 + LPN * j : RC - 1;
+                    m0[j] = base[pidx(R - 2, c)];
+                    m1[j] = base[pidx(R - 1, c)];
+                }
+#pragma unroll
+                for (int u = 0; u < NE; ++u) x[u] = base[c0 + LPN * u < EC ? c0 + LPN * u : EC - 1];
+#pragma unroll
+                for (int j = 0; j < NCOL; ++j) {
+                    const int c = c0 + LPN * j;
+                    const S x1 = mul_s(m0[j], pv.s1);
+                    const S x2 = mul_s(sub_mul(m1[j], pv.l, m0[j]), pv.s2);
+                    if (c < RC) {
+                        vbuf[i * 2 * RC + c] = x1;
+                        vbuf[i * 2 * RC + RC + c] = x2;
+                    }
+                }
+                if (c0 == 0) {
+                    coef[NK + i] = acc_neg(coef_mul(coef[i], pv.q));
+                    acoef[NK + i] = acoef[i] * hi_of(pv.q);
+                    loc[NK + i] = C::soff(K) + i * EC;
                 }
                 wave_sync();
-                // phase 2: rank-2 updates into the include children's slots.  Each
-                // lane's entries are taken in chunks: all loads of a chunk first,
-                // then the independent updates (computed unconditionally so that
-                // their dependency chains interleave), then the stores.  A lane
-                // past the end stores into piv[] (dead until the next level's
-                // phase 0), so the whole phase is one branch-free block.
+                // phase 2: rank-2 updates of the lane's entries into the include
+                // child's slot, in chunks: the chunk's column values first, then
+                // the independent updates (so that their dependency chains
+                // interleave), then the stores.
                 {
-                    constexpr int TOT = NK * EC, JJ = (TOT + 63) / 64;
-                    constexpr int NCH = (JJ + ChunkW<S>::value - 1) / ChunkW<S>::value, CH = (JJ + NCH - 1) / NCH;
+                    const S *v = vbuf + i * 2 * RC;
+                    S *dst = mat + C::soff(K) + i * EC;
+                    constexpr int NCH = (NE + ChunkW<S>::value - 1) / ChunkW<S>::value, CH = (NE + NCH - 1) / NCH;
     #pragma unroll
-                    for (int j0 = 0; j0 < JJ; j0 += CH) {
-                        S x[CH], p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
-                        int dst[CH];
+                    for (int j0 = 0; j0 < NE; j0 += CH) {
+                        S p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
     #pragma unroll
                         for (int u = 0; u < CH; ++u) {
-                            const int it0 = lane + 64 * (j0 + u);
-                            const bool ok = (j0 + u < JJ) && it0 < TOT;
-                            const int it = ok ? it0 : 0;
-                            const int i = it / EC, e = it - i * EC;
-                            const unsigned short w = ab[e];
-                            const int a = w & 0xff, b = w >> 8;
-                            const S *base = mat + loc[i];
-                            const S *v = vbuf + i * 2 * RC;
-                            x[u] = base[e];
+                            const int uu = j0 + u < NE ? j0 + u : NE - 1;
+                            const int a = w[uu] & 0xff, b = w[uu] >> 8;
                             p1[u] = v[a];
                             q1[u] = v[b];
                             p2[u] = v[RC + a];
                             q2[u] = v[RC + b];
-                            dst[u] = ok ? C::soff(K) + i * EC + e : -1;
                         }
     #pragma unroll
-                        for (int u = 0; u < CH; ++u) r[u] = sub_dot2(x[u], p1[u], q1[u], p2[u], q2[u]);
+                        for (int u = 0; u < CH; ++u) {
+                            const int uu = j0 + u < NE ? j0 + u : NE - 1;
+                            r[u] = sub_dot2(x[uu], p1[u], q1[u], p2[u], q2[u]);
+                        }
     #pragma unroll
                         for (int u = 0; u < CH; ++u) {
-                            S *dp = dst[u] >= 0 ? mat + dst[u] : reinterpret_cast<S *>(piv);
-                            *dp = r[u];
+                            const int e = c0 + LPN * (j0 + u);
+                            if (j0 + u < NE && e < EC) dst[e] = r[u];
                         }
                     }
                 }
                 wave_sync();
             } else {
+                // phase 0: pivot of each node, coefficients and slots of the include children
+                if (lane < NK) {
+                    const S *base = mat + loc[lane];
+                    Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
+                    piv[lane] = pv;
+                    coef[NK + lane] = acc_neg(coef_mul(coef[lane], pv.q));
+                    acoef[NK + lane] = acoef[lane] * hi_of(pv.q);
+                    loc[NK + lane] = C::soff(K) + lane * EC;
+                }
+                wave_sync();
     #pragma unroll
                 for (int h = 0; h < NH; ++h) {
                     // phase 1: the two scaled pivot columns of every node of the part
