@@ -266,6 +266,19 @@ template <class S> struct ChunkW { static constexpr int value = 4; };
 template <> struct ChunkW<dd> { static constexpr int value = 12; };
 template <> struct ChunkW<double> { static constexpr int value = 8; };
 
+// LDS offset of node i of a J-mode tree after K cooperative levels: node 0 at
+// 0, node i >= 1 the include child formed at level k = floor(log2 i) from node
+// i - 2^k, in that level's slots (the same value the levels store in loc[]).
+template <class S, int J, int D, int K>
+__device__ __forceinline__ int node_loc(int i) {
+    using C = WaveCfg<S, J, D>;
+    int o = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (i >= (1 << k)) o = C::soff(k) + (i - (1 << k)) * EN(J - k - 1, MR(D));
+    return o;
+}
+
 template <class S, int J, int K, int D = 0> struct WaveLevel {
     using C = WaveCfg<S, J, D>;
     using Acc = typename AccOf<S>::type;
@@ -287,7 +300,7 @@ template <class S, int J, int K, int D = 0> struct WaveLevel {
                 unsigned short w[NE];
 #pragma unroll
                 for (int u = 0; u < NE; ++u) w[u] = ab[c0 + LPN * u < EC ? c0 + LPN * u : EC - 1];
-                const S *base = mat + loc[i];
+                const S *base = mat + node_loc<S, J, D, K>(i);
                 const Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
                 S m0[NCOL], m1[NCOL], x[NE];
 #pragma unroll
@@ -492,7 +505,7 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, typename AccOf<
             constexpr int R1 = C::TL + 1, p0 = 2 * R1 - 2 + MR(D), p1 = 2 * R1 - 1 + MR(D), RC = 2 * R1 - 2 + MR(D);
             const int i = lane & (C::NN - 1);
             const bool inc = lane >= C::NN;
-            const S *base = sm.mat + sm.loc[i];
+            const S *base = sm.mat + node_loc<S, J, D, C::TWC>(i);
             S M[EN(R1, MR(D))];
 #pragma unroll
             for (int e = 0; e < EN(R1, MR(D)); ++e) M[e] = base[e];
