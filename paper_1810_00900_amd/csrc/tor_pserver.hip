@@ -56,10 +56,15 @@ struct PsReduceLds {
     double sA[256];
 };
 
+// Byte offset of the prefix buffer in the shared LDS region: after the
+// packed-index table, room for 32 modes (E(32) double-doubles).
+constexpr int kPsPrefixOffset = 512;
+
 union PsLds {
     TopSmem<dd, 0, 2> top;  // largest probability task (11 modes); smaller tasks use its prefix
     PsChainLds chain;
     PsReduceLds red;
+    unsigned char prefix[kPsPrefixOffset + EN(TOR_MAX_N, 0) * sizeof(dd)];  // the walk's prefix matrix
 };
 
 using PsWaveDD = WaveSmem<dd, 9, 0>;
@@ -117,10 +122,6 @@ __device__ __forceinline__ void ps_gather(const PsReq &R, dd *out, int lane) {  
     }
     wave_sync();
 }
-
-// Byte offset of the prefix buffer in the shared LDS region: after the
-// packed-index table, room for 32 modes (E(32) double-doubles).
-constexpr int kPsPrefixOffset = 512;
 
 // Include child of the r-mode node m (LDS) in place (the expansion's update).
 __device__ __forceinline__ Pivot<dd> ps_schur_lds(dd *m, int r, dd *vt, int lane) {

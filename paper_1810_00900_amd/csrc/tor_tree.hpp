@@ -236,20 +236,9 @@ template <class S, int J, int D = 0> struct WaveCfg {
         return o;
     }
     static constexpr int MAT = soff(TWC);
-    // Levels whose pivot columns are formed for half of the nodes at a time:
-    // the levels with 8 or more nodes of displaced double-double trees, so
-    // that their working set fits four workgroups per CU.
-    static constexpr int halves(int k) { return (D != 0 && sizeof(S) > sizeof(double) && (1 << k) >= 8) ? 2 : 1; }
-    static constexpr int vmax() {
-        int m = 1;
-        for (int k = 0; k < TWC; ++k) {
-            int v = (1 << k) / halves(k) * 2 * (2 * (J - k) - 2 + MR(D));
-            if (v > m) m = v;
-        }
-        return m;
-    }
-    static constexpr int VMAX = vmax();
-    static constexpr int NPIV = NN / 2 > 0 ? NN / 2 : 1;
+    // Scaled pivot columns of node 0 at any level (the other nodes keep theirs
+    // in their own dead pivot rows)
+    static constexpr int VMAX = 2 * (2 * J - 2 + MR(D));
 };
 
 // (row, column) of packed index e, for every e < EN(8, D) (the largest child
@@ -268,7 +257,7 @@ template <> struct ChunkW<double> { static constexpr int value = 8; };
 
 // LDS offset of node i of a J-mode tree after K cooperative levels: node 0 at
 // 0, node i >= 1 the include child formed at level k = floor(log2 i) from node
-// i - 2^k, in that level's slots (the same value the levels store in loc[]).
+// i - 2^k, in that level's slots.
 template <class S, int J, int D, int K>
 __device__ __forceinline__ int node_loc(int i) {
     using C = WaveCfg<S, J, D>;
@@ -282,151 +271,87 @@ __device__ __forceinline__ int node_loc(int i) {
 template <class S, int J, int K, int D = 0> struct WaveLevel {
     using C = WaveCfg<S, J, D>;
     using Acc = typename AccOf<S>::type;
-    static __device__ __forceinline__ void run(const unsigned short *ab, S *mat, S *vbuf, Pivot<S> *piv, int *loc,
-                                               Acc *coef, double *acoef, int lane) {
+    static __device__ __forceinline__ void run(const unsigned short *ab, S *mat, S *vbuf, Acc *coef, double *acoef,
+                                               int lane) {
         if constexpr (K < C::TWC) {
             constexpr int r = J - K, R = 2 * r + MR(D), NK = 1 << K, RC = R - 2, EC = EN(r - 1, MR(D));
-            constexpr int NH = C::halves(K), NKH = NK / NH;
-            if constexpr (NH == 1) {
-                // phases 0 and 1: the 64 / NK lanes of each node form its pivot
-                // themselves (the same value in each) and then its two scaled
-                // columns, a few columns per lane; the node's first lane stores the
-                // include child's coefficients and slot.  Phase 2 updates, in each
-                // lane, entries of the lane's own node, so their packed indices and
-                // values are loaded here, while the pivot is formed.
-                static_assert(64 % NK == 0, "at most 64 nodes per level");
-                constexpr int LPN = 64 / NK, NCOL = (RC + LPN - 1) / LPN, NE = (EC + LPN - 1) / LPN;
-                const int i = lane / LPN, c0 = lane - i * LPN;
-                unsigned short w[NE];
+            // phases 0 and 1: the 64 / NK lanes of each node form its pivot
+            // themselves (the same value in each) and then its two scaled
+            // columns, a few columns per lane, into the node's own pivot rows,
+            // dead once read (node 0's rows, the caller's matrix, are kept: its
+            // columns go to vbuf); the node's first lane stores the include
+            // child's path coefficients.  Phase 2 updates, in each
+            // lane, entries of the lane's own node, so their packed indices and
+            // values are loaded here, while the pivot is formed.
+            static_assert(64 % NK == 0, "at most 64 nodes per level");
+            constexpr int LPN = 64 / NK, NCOL = (RC + LPN - 1) / LPN, NE = (EC + LPN - 1) / LPN;
+            const int i = lane / LPN, c0 = lane - i * LPN;
+            unsigned short w[NE];
 #pragma unroll
-                for (int u = 0; u < NE; ++u) w[u] = ab[c0 + LPN * u < EC ? c0 + LPN * u : EC - 1];
-                const S *base = mat + node_loc<S, J, D, K>(i);
-                const Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
-                S m0[NCOL], m1[NCOL], x[NE];
+            for (int u = 0; u < NE; ++u) w[u] = ab[c0 + LPN * u < EC ? c0 + LPN * u : EC - 1];
+            const int nl = node_loc<S, J, D, K>(i);
+            S *base = mat + nl;
+            // 2 RC <= 2 R - 1 entries: the two pivot rows hold both columns
+            S *vcol = mat + (i == 0 ? (int)(vbuf - mat) : nl + pidx(R - 2, 0));
+            const Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
+            S m0[NCOL], m1[NCOL], x[NE];
 #pragma unroll
-                for (int j = 0; j < NCOL; ++j) {
-                    const int c = c0 + LPN * j < RC ? c0 + LPN * j : RC - 1;
-                    m0[j] = base[pidx(R - 2, c)];
-                    m1[j] = base[pidx(R - 1, c)];
-                }
+            for (int j = 0; j < NCOL; ++j) {
+                const int c = c0 + LPN * j < RC ? c0 + LPN * j : RC - 1;
+                m0[j] = base[pidx(R - 2, c)];
+                m1[j] = base[pidx(R - 1, c)];
+            }
 #pragma unroll
-                for (int u = 0; u < NE; ++u) x[u] = base[c0 + LPN * u < EC ? c0 + LPN * u : EC - 1];
+            for (int u = 0; u < NE; ++u) x[u] = base[c0 + LPN * u < EC ? c0 + LPN * u : EC - 1];
 #pragma unroll
-                for (int j = 0; j < NCOL; ++j) {
-                    const int c = c0 + LPN * j;
-                    const S x1 = mul_s(m0[j], pv.s1);
-                    const S x2 = mul_s(sub_mul(m1[j], pv.l, m0[j]), pv.s2);
-                    if (c < RC) {
-                        vbuf[i * 2 * RC + c] = x1;
-                        vbuf[i * 2 * RC + RC + c] = x2;
-                    }
-                }
-                if (c0 == 0) {
-                    coef[NK + i] = acc_neg(coef_mul(coef[i], pv.q));
-                    acoef[NK + i] = acoef[i] * hi_of(pv.q);
-                    loc[NK + i] = C::soff(K) + i * EC;
-                }
-                wave_sync();
-                // phase 2: rank-2 updates of the lane's entries into the include
-                // child's slot, in chunks: the chunk's column values first, then
-                // the independent updates (so that their dependency chains
-                // interleave), then the stores.
-                {
-                    const S *v = vbuf + i * 2 * RC;
-                    S *dst = mat + C::soff(K) + i * EC;
-                    constexpr int NCH = (NE + ChunkW<S>::value - 1) / ChunkW<S>::value, CH = (NE + NCH - 1) / NCH;
-    #pragma unroll
-                    for (int j0 = 0; j0 < NE; j0 += CH) {
-                        S p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
-    #pragma unroll
-                        for (int u = 0; u < CH; ++u) {
-                            const int uu = j0 + u < NE ? j0 + u : NE - 1;
-                            const int a = w[uu] & 0xff, b = w[uu] >> 8;
-                            p1[u] = v[a];
-                            q1[u] = v[b];
-                            p2[u] = v[RC + a];
-                            q2[u] = v[RC + b];
-                        }
-    #pragma unroll
-                        for (int u = 0; u < CH; ++u) {
-                            const int uu = j0 + u < NE ? j0 + u : NE - 1;
-                            r[u] = sub_dot2(x[uu], p1[u], q1[u], p2[u], q2[u]);
-                        }
-    #pragma unroll
-                        for (int u = 0; u < CH; ++u) {
-                            const int e = c0 + LPN * (j0 + u);
-                            if (j0 + u < NE && e < EC) dst[e] = r[u];
-                        }
-                    }
-                }
-                wave_sync();
-            } else {
-                // phase 0: pivot of each node, coefficients and slots of the include children
-                if (lane < NK) {
-                    const S *base = mat + loc[lane];
-                    Pivot<S> pv = make_pivot_m<S, D>(base, R - 2, R - 1);
-                    piv[lane] = pv;
-                    coef[NK + lane] = acc_neg(coef_mul(coef[lane], pv.q));
-                    acoef[NK + lane] = acoef[lane] * hi_of(pv.q);
-                    loc[NK + lane] = C::soff(K) + lane * EC;
-                }
-                wave_sync();
-    #pragma unroll
-                for (int h = 0; h < NH; ++h) {
-                    // phase 1: the two scaled pivot columns of every node of the part
-                    for (int it = lane; it < NKH * RC; it += 64) {
-                        int il = it / RC, c = it - il * RC;
-                        const int i = h * NKH + il;
-                        const S *base = mat + loc[i];
-                        Pivot<S> pv = piv[i];
-                        S m0 = base[pidx(R - 2, c)];
-                        vbuf[il * 2 * RC + c] = mul_s(m0, pv.s1);
-                        vbuf[il * 2 * RC + RC + c] = mul_s(sub_mul(base[pidx(R - 1, c)], pv.l, m0), pv.s2);
-                    }
-                    wave_sync();
-                    // phase 2: rank-2 updates into the include children's slots.  Each
-                    // lane's entries are taken in chunks: all loads of a chunk first,
-                    // then the independent updates (computed unconditionally so that
-                    // their dependency chains interleave), then the stores.  A lane
-                    // past the end stores into piv[0] (its node's pivot is not read
-                    // again before the next level's phase 0; node 0 is in the first
-                    // part), so the whole phase is one branch-free block.
-                    constexpr int TOT = NKH * EC, JJ = (TOT + 63) / 64;
-                    constexpr int NCH = (JJ + ChunkW<S>::value - 1) / ChunkW<S>::value, CH = (JJ + NCH - 1) / NCH;
-    #pragma unroll
-                    for (int j0 = 0; j0 < JJ; j0 += CH) {
-                        S x[CH], p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
-                        int dst[CH];
-    #pragma unroll
-                        for (int u = 0; u < CH; ++u) {
-                            const int it0 = lane + 64 * (j0 + u);
-                            const bool ok = (j0 + u < JJ) && it0 < TOT;
-                            const int it = ok ? it0 : 0;
-                            const int il = it / EC, e = it - il * EC;
-                            const int i = h * NKH + il;
-                            const unsigned short w = ab[e];
-                            const int a = w & 0xff, b = w >> 8;
-                            const S *base = mat + loc[i];
-                            const S *v = vbuf + il * 2 * RC;
-                            x[u] = base[e];
-                            p1[u] = v[a];
-                            q1[u] = v[b];
-                            p2[u] = v[RC + a];
-                            q2[u] = v[RC + b];
-                            dst[u] = ok ? C::soff(K) + i * EC + e : -1;
-                        }
-    #pragma unroll
-                        for (int u = 0; u < CH; ++u) r[u] = sub_dot2(x[u], p1[u], q1[u], p2[u], q2[u]);
-    #pragma unroll
-                        for (int u = 0; u < CH; ++u) {
-                            S *dp = dst[u] >= 0 ? mat + dst[u] : reinterpret_cast<S *>(piv);
-                            *dp = r[u];
-                        }
-                    }
-                    wave_sync();
+            for (int j = 0; j < NCOL; ++j) {
+                const int c = c0 + LPN * j;
+                const S x1 = mul_s(m0[j], pv.s1);
+                const S x2 = mul_s(sub_mul(m1[j], pv.l, m0[j]), pv.s2);
+                if (c < RC) {
+                    vcol[c] = x1;
+                    vcol[RC + c] = x2;
                 }
             }
-            WaveLevel<S, J, K + 1, D>::run(ab, mat, vbuf, piv, loc, coef, acoef, lane);
+            if (c0 == 0) {
+                coef[NK + i] = acc_neg(coef_mul(coef[i], pv.q));
+                acoef[NK + i] = acoef[i] * hi_of(pv.q);
+            }
+            wave_sync();
+            // phase 2: rank-2 updates of the lane's entries into the include
+            // child's slot, in chunks: the chunk's column values first, then
+            // the independent updates (so that their dependency chains
+            // interleave), then the stores.
+            {
+                const S *v = vcol;
+                S *dst = mat + C::soff(K) + i * EC;
+                constexpr int NCH = (NE + ChunkW<S>::value - 1) / ChunkW<S>::value, CH = (NE + NCH - 1) / NCH;
+#pragma unroll
+                for (int j0 = 0; j0 < NE; j0 += CH) {
+                    S p1[CH], q1[CH], p2[CH], q2[CH], r[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        const int uu = j0 + u < NE ? j0 + u : NE - 1;
+                        const int a = w[uu] & 0xff, b = w[uu] >> 8;
+                        p1[u] = v[a];
+                        q1[u] = v[b];
+                        p2[u] = v[RC + a];
+                        q2[u] = v[RC + b];
+                    }
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        const int uu = j0 + u < NE ? j0 + u : NE - 1;
+                        r[u] = sub_dot2(x[uu], p1[u], q1[u], p2[u], q2[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        const int e = c0 + LPN * (j0 + u);
+                        if (j0 + u < NE && e < EC) dst[e] = r[u];
+                    }
+                }
+            }
+            wave_sync();
+            WaveLevel<S, J, K + 1, D>::run(ab, mat, vbuf, coef, acoef, lane);
         }
     }
 };
@@ -450,8 +375,6 @@ template <class S, int J, int D = 0> struct WaveSmem {
     unsigned short ab[ab_n(MR(D))];
     S mat[C::MAT];
     S vbuf[C::VMAX];
-    Pivot<S> piv[C::NPIV];
-    int loc[C::NN];
     typename AccOf<S>::type coef[C::NN];
     double acoef[C::NN];
 };
@@ -481,12 +404,11 @@ __device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, typename AccOf<
     using C = WaveCfg<S, J, D>;
     using Acc = typename AccOf<S>::type;
     if (lane == 0) {
-        sm.loc[0] = 0;
         sm.coef[0] = c;
         sm.acoef[0] = a;
     }
     wave_sync();
-    WaveLevel<S, J, 0, D>::run(sm.ab, sm.mat, sm.vbuf, sm.piv, sm.loc, sm.coef, sm.acoef, lane);
+    WaveLevel<S, J, 0, D>::run(sm.ab, sm.mat, sm.vbuf, sm.coef, sm.acoef, lane);
     T = acc_const<Acc>(0.0);
     A = 0.0;
     if constexpr (C::TW == 0) {

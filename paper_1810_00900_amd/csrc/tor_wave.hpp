@@ -18,14 +18,14 @@
 
 namespace tor {
 
-// Waves per SIMD the wave tier asks the register allocator for: two where two
-// workgroups' LDS fit a quarter of the CU's 160 KiB (one wave per workgroup),
-// so that a second wave can hide the first one's latency; else one.  The
+// Waves per SIMD the wave tier asks the register allocator for: two where five
+// or more one-wave workgroups fit the CU's 160 KiB of LDS, so that some SIMD
+// can hold a second wave to hide the first one's latency; else one.  The
 // double-double leaf with a mean row (one more packed row per node) does not
 // fit the 256 registers of two waves without spilling, so it asks for one.
 template <class S, int J, int D> struct WaveOcc {
     static constexpr int value = (D != 0 && sizeof(S) > sizeof(double)) ? 1
-                                 : sizeof(WaveSmem<S, J, D>) + 512 <= 20480 ? 2 : 1;
+                                 : (sizeof(WaveSmem<S, J, D>) + 1024) * 5 <= 163840 ? 2 : 1;
 };
 
 // One wave-tier task of J <= 9 modes: the node's matrix at root (global
