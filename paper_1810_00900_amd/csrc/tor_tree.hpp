@@ -397,7 +397,9 @@ __device__ __forceinline__ void wave_tree_init(unsigned short *ab, int lane) {
 // update in registers; else exclude, the same code with zero update vectors)
 // and finishes the TL-mode leaf in registers.  Returns this lane's share
 // (T, A) (zero for lanes >= NL).  Lane bit 0 is the decision on the node's last
-// mode (1 = included) when J > TL.  Must be called by all 64 lanes.
+// mode (1 = included) when J > TL.  The node's matrix is left as it was (the
+// levels write only the slot area beyond it, vbuf and the dead pivot rows of
+// the nodes in slots).  Must be called by all 64 lanes.
 template <class S, int J, int D = 0>
 __device__ __forceinline__ void wave_tree(WaveSmem<S, J, D> &sm, typename AccOf<S>::type c, double a, int lane,
                                           typename AccOf<S>::type &T, double &A) {
