@@ -248,9 +248,8 @@ __host__ __device__ constexpr int ab_n(int D) { return EN(8, D); }
 
 // Rank-2 updates a lane keeps in flight per chunk of a cooperative level:
 // double-double updates, whose dependency chains are the longest, take up to
-// 12 (a nine-mode tree's largest level in one chunk, within the register file
-// of one wave per SIMD); binary64 trees, at two waves per SIMD, take 8 (more
-// spills); quad-double terms 4.
+// 12 (a nine-mode tree's largest level, 9 per lane, in one chunk); binary64
+// trees take 8 (12 measured no faster); quad-double terms 4.
 template <class S> struct ChunkW { static constexpr int value = 4; };
 template <> struct ChunkW<dd> { static constexpr int value = 12; };
 template <> struct ChunkW<double> { static constexpr int value = 8; };
